@@ -1,0 +1,178 @@
+/*
+ * qmc.h -- C ABI of the batched JAGP (Jastrow x antisymmetrized geminal power)
+ * wave-function library for AMD Instinct MI355X (gfx950).
+ *
+ * What is computed (arXiv:2002.07401, TurboRVB review):
+ *   Psi(x)   = det(W) exp(J)                    (Wave functions section; eq:wfAGPs)
+ *   W[i][j]  = sum_{mu,nu} Lambda[mu][nu] psi_mu(r_i) psi_nu(r_j),
+ *              i an up electron, j a down electron          (agp_expansion)
+ *   psi_mu   = P_{l,m}(r - R_a) exp(-zeta_mu |r - R_a|^2)   (eq. gaussian)
+ *   J        = J1 + J2                    (onebody_J_hom, onebody_u, twobody_jastrow,
+ *                                          twobody_v)
+ *   e_L      = (H Psi)/Psi, H the all-electron Coulomb Hamiltonian in Hartree
+ *              units                       (local energy, Variational Monte Carlo section)
+ *   ratio    = Psi(x')/Psi(x) for x' differing from x by one electron; QMC cost is
+ *              set by e_L and by such ratios (Wave functions section, intro).
+ *
+ * Conventions shared by every call:
+ *   - Electrons 0..n_up-1 are spin up, n_up..N-1 spin down (AGP section ordering).
+ *   - Real solid harmonics P_{l,m}, unnormalised, component index m:
+ *       l=0: 1;  l=1: x, y, z;  l=2: xy, yz, zx, x^2-y^2, 2z^2-x^2-y^2.
+ *   - Arrays are row-major, FP64 unless stated.  "Device" pointers point to memory
+ *     of the GPU that is current when the call is made; the caller owns them.
+ *     Every call that takes a stream enqueues its work on that stream and
+ *     returns without waiting (create/destroy and qmc_walkers_read's host copy
+ *     excepted).
+ *   - A handle may be used by one host thread at a time; distinct handles are
+ *     independent.
+ *   - Errors: a negative qmc_status.  Argument and shape errors are detected
+ *     on the host before anything is enqueued, and qmc_last_error() returns a
+ *     thread-local message.  HIP launch errors surface as QMC_ERR_HIP.  Per-walker
+ *     numerical problems never fail a call; they are reported in status[w]:
+ *        0 ok, 1 singular geminal matrix (det = 0), 2 non-finite result.
+ */
+#ifndef QMC_JAGP_H
+#define QMC_JAGP_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QMC_ABI_VERSION 1
+
+typedef enum {
+  QMC_OK = 0,
+  QMC_ERR_ARG = -1,         /* null pointer, out-of-range index or enum        */
+  QMC_ERR_SHAPE = -2,       /* sizes the library cannot handle                 */
+  QMC_ERR_HIP = -3,         /* a HIP runtime call failed                       */
+  QMC_ERR_OOM = -4,         /* device allocation failed                        */
+  QMC_ERR_UNSUPPORTED = -5, /* a feature of the description is not built       */
+  QMC_ERR_STATE = -6        /* call order violated (e.g. accept before propose) */
+} qmc_status;
+
+/* Arithmetic of the geminal products (W build, move rows) and of the stored
+ * basis matrices.  LU, inverse, Sherman-Morrison updates and ratio
+ * accumulation are FP64 in every mode. */
+typedef enum {
+  QMC_FP64 = 0,    /* everything FP64                                           */
+  QMC_W_FP32 = 1   /* Phi, P = Phi Lambda and the W products in FP32 on MFMA
+                      with FP32 accumulation; FP64 LU/inverse/SM/ratios          */
+} qmc_precision;
+
+typedef struct qmc_system qmc_system;   /* opaque: nuclei, basis, Lambda, Jastrow */
+typedef struct qmc_walkers qmc_walkers; /* opaque: per-walker state for moves     */
+
+/* System description.  All pointers are HOST pointers; the arrays are copied
+ * to the device by qmc_system_create and may be freed afterwards. */
+typedef struct {
+  int32_t n_nuc;              /* number of nuclei A                              */
+  const double *R;            /* [A][3] nuclear positions (bohr)                 */
+  const double *Z;            /* [A] nuclear charges                             */
+  int32_t n_basis;            /* L                                               */
+  const int32_t *center;      /* [L] nucleus index of each basis function        */
+  const int32_t *l;           /* [L] angular momentum, 0..2                      */
+  const int32_t *m;           /* [L] component index (see above)                 */
+  const int32_t *radial;      /* [L] 0 Gaussian (only 0 is built)                */
+  const double *zeta;         /* [L] exponents                                   */
+  const double *lambda;       /* [L][L] pairing coefficients (general matrix;
+                                 symmetric for a spin singlet)                   */
+  int32_t n_up, n_dn;         /* electrons per spin; n_up == n_dn is built       */
+  int32_t j1_form;            /* 0 none, 1 u=(1-e^{-bs})/(2b), 2 u=s/(2(1+bs))   */
+  const double *j1_b;         /* [A] one-body b per nucleus                      */
+  int32_t j2_form;            /* 0 none, 1 Pade (b_para, b_anti),
+                                 2 Pade series (b,a1,a2,a3 parallel, then anti)  */
+  int32_t n_j2;               /* 2 for form 1, 8 for form 2                      */
+  const double *j2;           /* [n_j2]                                          */
+  int32_t precision;          /* qmc_precision                                   */
+  int32_t refresh_every;      /* recompute W^{-1} by LU every this many
+                                 attempted moves (>= 1)                          */
+} qmc_system_desc;
+
+/* Version of this header the library was built from (QMC_ABI_VERSION). */
+int32_t qmc_abi_version(void);
+
+/* Message of the last failed call on this host thread ("" if none). */
+const char *qmc_last_error(void);
+
+/* Copy a description to the current device.  Fails with QMC_ERR_UNSUPPORTED
+ * for Slater functions, l > 2, n_up != n_dn or a precision not built. */
+qmc_status qmc_system_create(const qmc_system_desc *desc, qmc_system **out);
+qmc_status qmc_system_destroy(qmc_system *sys);
+
+/* Allocate the device state of n_walkers walkers of sys (positions, basis
+ * matrix Phi, P = Phi Lambda, W, W^{-1} and move buffers).  The state is
+ * undefined until qmc_eval_batch has run. */
+qmc_status qmc_walkers_create(qmc_system *sys, int32_t n_walkers, qmc_walkers **out);
+qmc_status qmc_walkers_destroy(qmc_walkers *wk);
+
+/* Evaluate every walker from scratch at positions r and make that the walkers'
+ * state.  (Local energy definition, VMC section; eq:wfAGPs; agp_expansion.)
+ *   r      [Wk][N][3]  device, read
+ *   logabs [Wk]        device, write: log|Psi|
+ *   sign   [Wk]        device, write: sign(Psi) = sign(det W); 0 when singular
+ *   drift  [Wk][N][3]  device, write, may be NULL: grad_i log|Psi|
+ *   e_kin  [Wk]        device, write, may be NULL: -1/2 sum_i lap_i Psi / Psi
+ *   e_loc  [Wk]        device, write, may be NULL: e_kin + Coulomb potential
+ *   status [Wk]        device, write, may be NULL
+ * Resets the move counter used by refresh_every. */
+qmc_status qmc_eval_batch(qmc_system *sys, qmc_walkers *wk, const double *r,
+                          double *logabs, double *sign, double *drift,
+                          double *e_kin, double *e_loc, int32_t *status,
+                          hipStream_t stream);
+
+/* Propose moving electron `electron` of every walker to r_new[w] and return
+ * ratio[w] = Psi(x')/Psi(x) (signed).  The determinant factor comes from the
+ * new row (up electron) or column (down electron) of W contracted with the
+ * matching column/row of W^{-1} (one row or column of the geminal matrix
+ * changes when one electron moves, Wave functions section).
+ *   r_new     [Wk][3] device, read
+ *   ratio     [Wk]    device, write
+ *   drift_new [Wk][3] device, write, may be NULL: grad log|Psi| of the moved
+ *             electron at its new position
+ * A second propose replaces the first. */
+qmc_status qmc_propose_move(qmc_system *sys, qmc_walkers *wk, int32_t electron,
+                            const double *r_new, double *ratio, double *drift_new,
+                            hipStream_t stream);
+
+/* Accept (accept[w] != 0) or reject the pending proposal of `electron` for
+ * every walker: on accept, Sherman-Morrison rank-1 update of W^{-1} (FP64),
+ * new row/column of W, new basis row and position.  Every refresh_every
+ * attempted moves W^{-1} and log|det W| are recomputed by FP64 LU.
+ * QMC_ERR_STATE if no proposal of this electron is pending.
+ *   accept [Wk] device, read (uint8)
+ *   status [Wk] device, write, may be NULL (1 when a refresh finds det = 0) */
+qmc_status qmc_accept_move(qmc_system *sys, qmc_walkers *wk, int32_t electron,
+                           const uint8_t *accept, int32_t *status, hipStream_t stream);
+
+/* Run n_steps Metropolis single-electron steps (VMC section): step t moves
+ * electron (e_start + t) mod N of every walker by disp[t][w] and accepts iff
+ * unif[t][w] < ratio^2 (strict), all on the device.
+ *   disp         [n_steps][Wk][3] device, read
+ *   unif         [n_steps][Wk]    device, read
+ *   accept_count [Wk]             device, read-write, may be NULL: += accepted */
+qmc_status qmc_vmc_steps(qmc_system *sys, qmc_walkers *wk, int32_t e_start, int32_t n_steps,
+                         const double *disp, const double *unif, int32_t *accept_count,
+                         hipStream_t stream);
+
+/* Items of the walker state that qmc_walkers_read can copy out. */
+typedef enum {
+  QMC_STATE_R = 0,       /* [Wk][N][3]   FP64 positions                          */
+  QMC_STATE_LOGABS = 1,  /* [Wk]         FP64 log|Psi| tracked through moves     */
+  QMC_STATE_SIGN = 2,    /* [Wk]         FP64 sign(Psi)                          */
+  QMC_STATE_W = 3,       /* [Wk][n_up][n_dn] FP64 geminal matrix                 */
+  QMC_STATE_AINV = 4,    /* [Wk][n_dn][n_up] FP64 W^{-1}                         */
+  QMC_STATE_PHI = 5      /* [Wk][N][L]   FP64 basis values psi_mu(r_i)           */
+} qmc_state_item;
+
+/* Copy one item of the walker state into dst (device memory, the layout given
+ * above, FP64) on `stream`.  For inspection and checkpoints. */
+qmc_status qmc_walkers_read(qmc_walkers *wk, int32_t item, double *dst, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QMC_JAGP_H */

@@ -1,0 +1,198 @@
+"""ctypes binding of libqmc_jagp.so (include/qmc.h).
+
+Argument marshalling only: every step of the wave-function path runs in the
+HIP kernels of the library.  PyTorch supplies device memory and the stream.
+Importing this module does not load the library; the first use does, and it
+raises QMCError when the library is missing -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, Optional
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqmc_jagp.so")
+
+QMC_FP64 = 0
+QMC_W_FP32 = 1
+
+STATE_R, STATE_LOGABS, STATE_SIGN, STATE_W, STATE_AINV, STATE_PHI = range(6)
+
+STATUS_NAMES = {0: "OK", -1: "ERR_ARG", -2: "ERR_SHAPE", -3: "ERR_HIP", -4: "ERR_OOM",
+                -5: "ERR_UNSUPPORTED", -6: "ERR_STATE"}
+
+FUNCTIONS = (
+    "qmc_abi_version", "qmc_last_error", "qmc_system_create", "qmc_system_destroy",
+    "qmc_walkers_create", "qmc_walkers_destroy", "qmc_eval_batch", "qmc_propose_move",
+    "qmc_accept_move", "qmc_vmc_steps", "qmc_walkers_read",
+)
+
+
+class QMCError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class SystemDesc(ctypes.Structure):
+    _fields_ = [
+        ("n_nuc", ctypes.c_int32), ("R", ctypes.c_void_p), ("Z", ctypes.c_void_p),
+        ("n_basis", ctypes.c_int32), ("center", ctypes.c_void_p), ("l", ctypes.c_void_p),
+        ("m", ctypes.c_void_p), ("radial", ctypes.c_void_p), ("zeta", ctypes.c_void_p),
+        ("lambda_", ctypes.c_void_p), ("n_up", ctypes.c_int32), ("n_dn", ctypes.c_int32),
+        ("j1_form", ctypes.c_int32), ("j1_b", ctypes.c_void_p), ("j2_form", ctypes.c_int32),
+        ("n_j2", ctypes.c_int32), ("j2", ctypes.c_void_p), ("precision", ctypes.c_int32),
+        ("refresh_every", ctypes.c_int32),
+    ]
+
+
+_lib: Optional[ctypes.CDLL] = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load the library once; raise QMCError if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise QMCError(-5, f"{path} is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    vp, i32, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p
+    lib.qmc_abi_version.restype = i32
+    lib.qmc_last_error.restype = ctypes.c_char_p
+    for name in FUNCTIONS[2:]:
+        getattr(lib, name).restype = ctypes.c_int
+    lib.qmc_system_create.argtypes = [ctypes.POINTER(SystemDesc), ctypes.POINTER(vp)]
+    lib.qmc_system_destroy.argtypes = [vp]
+    lib.qmc_walkers_create.argtypes = [vp, i32, ctypes.POINTER(vp)]
+    lib.qmc_walkers_destroy.argtypes = [vp]
+    lib.qmc_eval_batch.argtypes = [vp, vp, dp, dp, dp, dp, dp, dp, vp, vp]
+    lib.qmc_propose_move.argtypes = [vp, vp, i32, dp, dp, dp, vp]
+    lib.qmc_accept_move.argtypes = [vp, vp, i32, vp, vp, vp]
+    lib.qmc_vmc_steps.argtypes = [vp, vp, i32, i32, dp, dp, vp, vp]
+    lib.qmc_walkers_read.argtypes = [vp, i32, dp, vp]
+    _lib = lib
+    return lib
+
+
+def _check(code):
+    if code != 0:
+        raise QMCError(code, load().qmc_last_error().decode())
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise QMCError(-1, "device tensor expected")
+    if not t.is_contiguous():
+        raise QMCError(-1, "contiguous tensor expected")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class JAGPSystem:
+    """A system on the current GPU, built from a workloads.System."""
+
+    def __init__(self, s, precision: int = QMC_FP64, refresh_every: Optional[int] = None):
+        lib = load()
+        self.s = s
+        keep = dict(
+            R=np.ascontiguousarray(s.R, np.float64), Z=np.ascontiguousarray(s.Z, np.float64),
+            center=np.ascontiguousarray(s.center, np.int32), l=np.ascontiguousarray(s.l, np.int32),
+            m=np.ascontiguousarray(s.m, np.int32), radial=np.ascontiguousarray(s.radial, np.int32),
+            zeta=np.ascontiguousarray(s.zeta, np.float64), lam=np.ascontiguousarray(s.lam, np.float64),
+            j1_b=np.ascontiguousarray(s.j1_b, np.float64), j2=np.ascontiguousarray(s.j2, np.float64))
+        p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        d = SystemDesc(
+            n_nuc=len(s.Z), R=p(keep["R"]), Z=p(keep["Z"]), n_basis=len(s.zeta),
+            center=p(keep["center"]), l=p(keep["l"]), m=p(keep["m"]), radial=p(keep["radial"]),
+            zeta=p(keep["zeta"]), lambda_=p(keep["lam"]), n_up=s.n_up, n_dn=s.n_dn,
+            j1_form=s.j1_form, j1_b=p(keep["j1_b"]), j2_form=s.j2_form, n_j2=len(s.j2),
+            j2=p(keep["j2"]), precision=precision,
+            refresh_every=s.refresh_every if refresh_every is None else refresh_every)
+        h = ctypes.c_void_p()
+        _check(lib.qmc_system_create(ctypes.byref(d), ctypes.byref(h)))
+        self.h = h
+        self.precision = precision
+        self.n_elec = s.n_up + s.n_dn
+        self.n_up, self.n_dn, self.L = s.n_up, s.n_dn, len(s.zeta)
+
+    def close(self):
+        if getattr(self, "h", None):
+            _check(load().qmc_system_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Walkers:
+    """Device state of n_walkers walkers of a JAGPSystem."""
+
+    def __init__(self, system: JAGPSystem, n_walkers: int):
+        self.sys = system
+        self.n = n_walkers
+        h = ctypes.c_void_p()
+        _check(load().qmc_walkers_create(system.h, n_walkers, ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            _check(load().qmc_walkers_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def eval_batch(self, r: torch.Tensor, drift=True, stream=None) -> Dict[str, torch.Tensor]:
+        dev = r.device
+        Wk, N = self.n, self.sys.n_elec
+        assert r.shape == (Wk, N, 3) and r.dtype == torch.float64
+        f = lambda *sh: torch.empty(*sh, dtype=torch.float64, device=dev)
+        out = dict(logabs=f(Wk), sign=f(Wk), drift=f(Wk, N, 3) if drift else None,
+                   e_kin=f(Wk), e_loc=f(Wk), status=torch.empty(Wk, dtype=torch.int32, device=dev))
+        _check(load().qmc_eval_batch(self.sys.h, self.h, _ptr(r), _ptr(out["logabs"]), _ptr(out["sign"]),
+                                     _ptr(out["drift"]), _ptr(out["e_kin"]), _ptr(out["e_loc"]),
+                                     _ptr(out["status"]), _stream(stream)))
+        return out
+
+    def propose(self, e: int, r_new: torch.Tensor, drift=False, stream=None):
+        ratio = torch.empty(self.n, dtype=torch.float64, device=r_new.device)
+        dn = torch.empty(self.n, 3, dtype=torch.float64, device=r_new.device) if drift else None
+        _check(load().qmc_propose_move(self.sys.h, self.h, e, _ptr(r_new), _ptr(ratio), _ptr(dn),
+                                       _stream(stream)))
+        return (ratio, dn) if drift else ratio
+
+    def accept(self, e: int, accept: torch.Tensor, status: Optional[torch.Tensor] = None, stream=None):
+        assert accept.dtype == torch.uint8
+        _check(load().qmc_accept_move(self.sys.h, self.h, e, _ptr(accept), _ptr(status), _stream(stream)))
+
+    def vmc_steps(self, e_start: int, disp: torch.Tensor, unif: torch.Tensor,
+                  accept_count: Optional[torch.Tensor] = None, stream=None):
+        n_steps = disp.shape[0]
+        assert disp.shape == (n_steps, self.n, 3) and unif.shape == (n_steps, self.n)
+        _check(load().qmc_vmc_steps(self.sys.h, self.h, e_start, n_steps, _ptr(disp), _ptr(unif),
+                                    _ptr(accept_count), _stream(stream)))
+
+    def read(self, item: int, stream=None) -> torch.Tensor:
+        Wk, N, nu, nd, L = self.n, self.sys.n_elec, self.sys.n_up, self.sys.n_dn, self.sys.L
+        shape = {STATE_R: (Wk, N, 3), STATE_LOGABS: (Wk,), STATE_SIGN: (Wk,), STATE_W: (Wk, nu, nd),
+                 STATE_AINV: (Wk, nd, nu), STATE_PHI: (Wk, N, L)}[item]
+        dst = torch.empty(shape, dtype=torch.float64, device="cuda")
+        _check(load().qmc_walkers_read(self.h, item, _ptr(dst), _stream(stream)))
+        return dst

@@ -1,0 +1,199 @@
+// From-scratch evaluation kernels: basis values, the per-electron determinant
+// derivatives, and the Jastrow / Coulomb / local-energy assembly.
+#include "internal.h"
+
+namespace qmc {
+
+// ---------------------------------------------------------------------------
+// Phi[w][i][mu] = psi_mu(r_i)  (eq. gaussian), zero for padding mu >= L.
+// One workgroup per electron row; consecutive threads write consecutive mu.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) basis_values_kernel(SysDev s, const double* __restrict__ r,
+                                                           T* __restrict__ phi) {
+  const long row = blockIdx.x;   // w * N + i
+  const double px = r[3 * row], py = r[3 * row + 1], pz = r[3 * row + 2];
+  T* out = phi + row * s.Lp;
+  for (int mu = threadIdx.x; mu < s.Lp; mu += blockDim.x)
+    out[mu] = (T)(mu < s.L ? basis_value(s, mu, px, py, pz) : 0.0);
+}
+
+hipError_t launch_basis_values(const SysDev& s, const WalkDev& w, hipStream_t st) {
+  const dim3 grid((unsigned)((long)w.Wk * s.N));
+  if (s.precision == QMC_W_FP32)
+    hipLaunchKernelGGL(basis_values_kernel<float>, grid, dim3(256), 0, st, s, w.r, (float*)w.phi);
+  else
+    hipLaunchKernelGGL(basis_values_kernel<double>, grid, dim3(256), 0, st, s, w.r, (double*)w.phi);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Row dots of the derivative rows with the cofactor vectors:
+//   D[w][i][0:3] = sum_mu grad psi_mu(r_i) Yt[w][i][mu]  = grad_i det / det
+//   D[w][i][3]   = sum_mu lap  psi_mu(r_i) Yt[w][i][mu]  = lap_i  det / det
+// Exact because W depends on r_i through one row (or column) only.  The basis
+// derivatives are recomputed here instead of being stored.  One wave per row.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) rowdot_kernel(SysDev s, int rows, const double* __restrict__ r,
+                                                     const double* __restrict__ Yt,
+                                                     double* __restrict__ D) {
+  const int lane = threadIdx.x & 63;
+  const long row = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= rows) return;
+  const double px = r[3 * row], py = r[3 * row + 1], pz = r[3 * row + 2];
+  const double* y = Yt + row * s.Lp;
+  double sx = 0.0, sy = 0.0, sz = 0.0, sl = 0.0;
+  for (int mu = lane; mu < s.L; mu += 64) {
+    double v, gx, gy, gz, lp;
+    basis_vgl(s, mu, px, py, pz, v, gx, gy, gz, lp);
+    const double yy = y[mu];
+    sx += gx * yy; sy += gy * yy; sz += gz * yy; sl += lp * yy;
+  }
+  sx = wave_sum(sx); sy = wave_sum(sy); sz = wave_sum(sz); sl = wave_sum(sl);
+  if (lane == 0) {
+    D[4 * row] = sx; D[4 * row + 1] = sy; D[4 * row + 2] = sz; D[4 * row + 3] = sl;
+  }
+}
+
+hipError_t launch_rowdots(const SysDev& s, const WalkDev& w, hipStream_t st) {
+  const int rows = w.Wk * s.N;
+  hipLaunchKernelGGL(rowdot_kernel, dim3((rows + 3) / 4), dim3(256), 0, st, s, rows, w.r, w.Yt, w.D);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Block-wide FP64 sum (fixed order, deterministic).
+// ---------------------------------------------------------------------------
+__device__ double block_sum(double v, double* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int k = 0; k < nw; ++k) t += red[k];
+  return t;
+}
+
+// ---------------------------------------------------------------------------
+// Jastrow J = J1 + J2 with per-electron gradient and Laplacian, the Coulomb
+// potential, and the assembly of log|Psi|, drift and local energy:
+//   drift_i = grad_i det/det + grad_i J
+//   e_kin   = -1/2 sum_i [ lap_i det/det + 2 grad_i det/det . grad_i J
+//                          + lap_i J + |grad_i J|^2 ]
+//   e_loc   = e_kin + V     (local energy, VMC section)
+// One workgroup per walker, threads over electrons.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+jastrow_assemble_kernel(SysDev s, WalkDev w, double* __restrict__ logabs_o, double* __restrict__ sign_o,
+                        double* __restrict__ drift_o, double* __restrict__ ekin_o,
+                        double* __restrict__ eloc_o, int32_t* __restrict__ status_o) {
+  __shared__ double red[16];
+  const int wk = blockIdx.x;
+  const double* r = w.r + (long)wk * s.N * 3;
+  double Jp = 0.0, Vp = 0.0, Kp = 0.0;
+  bool bad = false;
+  for (int i = threadIdx.x; i < s.N; i += blockDim.x) {
+    const double xi = r[3 * i], yi = r[3 * i + 1], zi = r[3 * i + 2];
+    double gx = 0.0, gy = 0.0, gz = 0.0, h = 0.0;
+    for (int a = 0; a < s.n_nuc; ++a) {
+      const double dx = xi - s.R[3 * a], dy = yi - s.R[3 * a + 1], dz = zi - s.R[3 * a + 2];
+      const double ria = sqrt(dx * dx + dy * dy + dz * dz);
+      Vp -= s.Z[a] / ria;
+      if (s.j1_form) {
+        double f, f1, f2;
+        j1_radial(s.j1_form, s.Z[a], s.j1_b[a], ria, f, f1, f2);
+        const double q = f1 / ria;
+        Jp += f;
+        gx += q * dx; gy += q * dy; gz += q * dz;
+        h += f2 + 2.0 * q;
+      }
+    }
+    const bool up_i = i < s.nu;
+    for (int j = 0; j < s.N; ++j) {
+      if (j == i) continue;
+      const double dx = xi - r[3 * j], dy = yi - r[3 * j + 1], dz = zi - r[3 * j + 2];
+      const double rij = sqrt(dx * dx + dy * dy + dz * dz);
+      Vp += 0.5 / rij;
+      if (s.j2_form) {
+        double v, v1, v2;
+        j2_radial(s.j2_form, s.j2, up_i == (j < s.nu), rij, v, v1, v2);
+        const double q = v1 / rij;
+        Jp += 0.5 * v;
+        gx += q * dx; gy += q * dy; gz += q * dz;
+        h += v2 + 2.0 * q;
+      }
+    }
+    const double* Di = w.D + ((long)wk * s.N + i) * 4;
+    const double ddx = Di[0], ddy = Di[1], ddz = Di[2], dl = Di[3];
+    Kp += dl + 2.0 * (ddx * gx + ddy * gy + ddz * gz) + h + gx * gx + gy * gy + gz * gz;
+    if (drift_o) {
+      double* o = drift_o + ((long)wk * s.N + i) * 3;
+      o[0] = ddx + gx; o[1] = ddy + gy; o[2] = ddz + gz;
+      bad |= !isfinite(o[0]) || !isfinite(o[1]) || !isfinite(o[2]);
+    }
+  }
+  // nucleus-nucleus repulsion
+  for (int p = threadIdx.x; p < s.n_nuc * s.n_nuc; p += blockDim.x) {
+    const int a = p / s.n_nuc, b = p % s.n_nuc;
+    if (b <= a) continue;
+    const double dx = s.R[3 * a] - s.R[3 * b], dy = s.R[3 * a + 1] - s.R[3 * b + 1],
+                 dz = s.R[3 * a + 2] - s.R[3 * b + 2];
+    Vp += s.Z[a] * s.Z[b] / sqrt(dx * dx + dy * dy + dz * dz);
+  }
+  const double J = block_sum(Jp, red);
+  const double V = block_sum(Vp, red + 4);
+  const double K = block_sum(Kp, red + 8);
+  __shared__ int bad_s;
+  if (threadIdx.x == 0) bad_s = 0;
+  __syncthreads();
+  if (bad) atomicOr(&bad_s, 1);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int sing = w.singular[wk];
+    const double ekin = -0.5 * K;
+    const double eloc = ekin + V;
+    const double la = sing ? -__builtin_inf() : w.logdet[wk] + J;
+    const double sg = w.detsign[wk];
+    int st = 0;
+    if (sing) st = 1;
+    else if (!isfinite(la) || !isfinite(eloc) || bad_s) st = 2;
+    w.logabs[wk] = la;
+    w.sign[wk] = sg;
+    w.J[wk] = J;
+    if (logabs_o) logabs_o[wk] = la;
+    if (sign_o) sign_o[wk] = sg;
+    if (ekin_o) ekin_o[wk] = ekin;
+    if (eloc_o) eloc_o[wk] = eloc;
+    if (status_o) status_o[wk] = st;
+  }
+}
+
+hipError_t launch_jastrow_assemble(const SysDev& s, const WalkDev& w, double* logabs, double* sign,
+                                   double* drift, double* e_kin, double* e_loc, int32_t* status,
+                                   hipStream_t st) {
+  hipLaunchKernelGGL(jastrow_assemble_kernel, dim3(w.Wk), dim3(256), 0, st, s, w, logabs, sign, drift,
+                     e_kin, e_loc, status);
+  return hipGetLastError();
+}
+
+// Copy the basis matrix out as FP64 (inspection).
+template <typename T>
+__global__ void export_phi_kernel(SysDev s, long rows, const T* __restrict__ phi, double* __restrict__ dst) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * s.L) return;
+  const long row = idx / s.L, mu = idx % s.L;
+  dst[idx] = (double)phi[row * s.Lp + mu];
+}
+
+hipError_t launch_export_phi(const SysDev& s, const WalkDev& w, double* dst, hipStream_t st) {
+  const long rows = (long)w.Wk * s.N;
+  const unsigned nb = (unsigned)((rows * s.L + 255) / 256);
+  if (s.precision == QMC_W_FP32)
+    hipLaunchKernelGGL(export_phi_kernel<float>, dim3(nb), dim3(256), 0, st, s, rows, (const float*)w.phi, dst);
+  else
+    hipLaunchKernelGGL(export_phi_kernel<double>, dim3(nb), dim3(256), 0, st, s, rows, (const double*)w.phi, dst);
+  return hipGetLastError();
+}
+
+}  // namespace qmc

@@ -1,0 +1,212 @@
+// Dense products of the geminal construction on the gfx950 matrix cores.
+//
+//   P_up = Phi_up Lambda        P_dn = Phi_dn Lambda^T          (agp_expansion)
+//   W    = P_up Phi_dn^T        (the geminal matrix, eq:wfAGPs)
+//   Yt_up = W^{-T} P_dn ... see launch_Y_build
+//
+// One templated kernel: C = op(A) op(B), row-major operands, 256 threads as a
+// 2x2 grid of waves, each wave owning (BM/2) x (BN/2) of the tile as 16x16
+// MFMA blocks.  K is staged through LDS in steps of 16.  Rows of A and C may be
+// "gathered": row m lives at (m / grp) * gs + (m % grp) * ld, which lets the
+// up (or down) rows of every walker form one tall matrix that multiplies the
+// shared Lambda.
+#include "internal.h"
+
+namespace qmc {
+
+typedef double dx4 __attribute__((ext_vector_type(4)));
+typedef float fx4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Mfma;
+// Output row of accumulator register r in lane `lane` (column is lane % 16):
+// the FP64 instruction interleaves rows across registers, the FP32 one blocks them.
+template <> struct Mfma<double> {
+  typedef dx4 acc_t;
+  static __device__ __forceinline__ acc_t run(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * r + (lane >> 4); }
+};
+template <> struct Mfma<float> {
+  typedef fx4 acc_t;
+  static __device__ __forceinline__ acc_t run(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+// TA: A stored [K][M] (op(A) = A^T); TB: B stored [N][K] (op(B) = B^T).
+// TI: operand type, TO: output type.
+template <int BM, int BN, bool TA, bool TB, typename TI, typename TO>
+__global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
+  constexpr int BK = 16;
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int FM = WM / 16, FN = WN / 16;
+  static_assert(FM >= 1 && FN >= 1, "tile too small");
+  __shared__ TI As[BK][BM + 1];
+  __shared__ TI Bs[BK][BN + 1];
+  typedef typename Mfma<TI>::acc_t acc_t;
+
+  const long bz = blockIdx.z;
+  const TI* __restrict__ A = (const TI*)g.A + bz * g.a_bs;
+  const TI* __restrict__ B = (const TI*)g.B + bz * g.b_bs;
+  TO* __restrict__ C = (TO*)g.C + bz * g.c_bs;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+
+  acc_t acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+      for (int r = 0; r < 4; ++r) acc[i][j][r] = 0;
+
+  for (int k0 = 0; k0 < g.K; k0 += BK) {
+    for (int idx = tid; idx < BM * BK; idx += 256) {
+      int mm, kk;
+      if (TA) { kk = idx / BM; mm = idx % BM; } else { mm = idx / BK; kk = idx % BK; }
+      const int gm = m0 + mm, gk = k0 + kk;
+      TI v = 0;
+      if (gm < g.M && gk < g.K) {
+        const long off = TA ? (long)gk * g.lda + gm
+                            : (long)(gm / g.a_grp) * g.a_gs + (long)(gm % g.a_grp) * g.lda + gk;
+        v = A[off];
+      }
+      As[kk][mm] = v;
+    }
+    for (int idx = tid; idx < BN * BK; idx += 256) {
+      int nn, kk;
+      if (TB) { nn = idx / BK; kk = idx % BK; } else { kk = idx / BN; nn = idx % BN; }
+      const int gn = n0 + nn, gk = k0 + kk;
+      TI v = 0;
+      if (gn < g.N && gk < g.K) v = TB ? B[(long)gn * g.ldb + gk] : B[(long)gk * g.ldb + gn];
+      Bs[kk][nn] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      TI a[FM], b[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) a[i] = As[kk + (lane >> 4)][wm * WM + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < FN; ++j) b[j] = Bs[kk + (lane >> 4)][wn * WN + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = Mfma<TI>::run(a[i], b[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+  // 16x16 block layout: lane holds column lane%16 and the rows given by Mfma::row
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gm = m0 + wm * WM + i * 16 + Mfma<TI>::row(lane, r);
+        const int gn = n0 + wn * WN + j * 16 + (lane & 15);
+        if (gm < g.M && gn < g.N)
+          C[(long)(gm / g.c_grp) * g.c_gs + (long)(gm % g.c_grp) * g.ldc + gn] = (TO)acc[i][j][r];
+      }
+}
+
+template <int BM, int BN, bool TA, bool TB, typename TI, typename TO>
+static hipError_t run_gemm(const GemmArgs& g, hipStream_t st) {
+  if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
+  dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, g.batch);
+  hipLaunchKernelGGL((gemm_kernel<BM, BN, TA, TB, TI, TO>), grid, dim3(256), 0, st, g);
+  return hipGetLastError();
+}
+
+static GemmArgs plain(int M, int N, int K) {
+  GemmArgs g{};
+  g.M = M; g.N = N; g.K = K;
+  g.a_grp = 1 << 30; g.a_gs = 0;
+  g.c_grp = 1 << 30; g.c_gs = 0;
+  g.batch = 1;
+  return g;
+}
+
+template <typename T>
+static hipError_t P_build_t(const SysDev& s, const WalkDev& w, int halves, hipStream_t st,
+                            const T* lam, const T* lamT) {
+  const long rowst = (long)s.N * s.Lp;
+  const T* phi = (const T*)w.phi;
+  T* P = (T*)w.P;
+  hipError_t e = hipSuccess;
+  if (halves & 1) {   // P_up = Phi_up Lambda  (rows 0..nu-1 of every walker)
+    GemmArgs g = plain(w.Wk * s.nu, s.Lp, s.Lp);
+    g.A = phi; g.lda = s.Lp; g.a_grp = s.nu; g.a_gs = rowst;
+    g.B = lam; g.ldb = s.Lp;
+    g.C = P; g.ldc = s.Lp; g.c_grp = s.nu; g.c_gs = rowst;
+    e = run_gemm<64, 64, false, false, T, T>(g, st);
+    if (e != hipSuccess) return e;
+  }
+  if (halves & 2) {   // P_dn = Phi_dn Lambda^T (rows nu..N-1)
+    GemmArgs g = plain(w.Wk * s.nd, s.Lp, s.Lp);
+    g.A = phi + (long)s.nu * s.Lp; g.lda = s.Lp; g.a_grp = s.nd; g.a_gs = rowst;
+    g.B = lamT; g.ldb = s.Lp;
+    g.C = P + (long)s.nu * s.Lp; g.ldc = s.Lp; g.c_grp = s.nd; g.c_gs = rowst;
+    e = run_gemm<64, 64, false, false, T, T>(g, st);
+  }
+  return e;
+}
+
+hipError_t launch_P_build(const SysDev& s, const WalkDev& w, int halves, hipStream_t st) {
+  if (s.precision == QMC_W_FP32) return P_build_t<float>(s, w, halves, st, s.lam32, s.lamT32);
+  return P_build_t<double>(s, w, halves, st, s.lam, s.lamT);
+}
+
+// W[w] = P_up[w] Phi_dn[w]^T  ->  W[i][j] = sum_nu (Phi_up Lambda)[i][nu] psi_nu(r_j)
+template <typename T>
+static hipError_t W_build_t(const SysDev& s, const WalkDev& w, hipStream_t st) {
+  const long rowst = (long)s.N * s.Lp;
+  GemmArgs g = plain(s.nu, s.nd, s.Lp);
+  g.A = (const T*)w.P; g.lda = s.Lp; g.a_bs = rowst;
+  g.B = (const T*)w.phi + (long)s.nu * s.Lp; g.ldb = s.Lp; g.b_bs = rowst;
+  g.C = w.W; g.ldc = s.nd; g.c_bs = (long)s.nu * s.nd;
+  g.batch = w.Wk;
+  return run_gemm<32, 32, false, true, T, double>(g, st);
+}
+
+hipError_t launch_W_build(const SysDev& s, const WalkDev& w, hipStream_t st) {
+  if (s.precision == QMC_W_FP32) return W_build_t<float>(s, w, st);
+  return W_build_t<double>(s, w, st);
+}
+
+// Cofactor vectors of the local-energy derivatives:
+//   Yt_up[i][mu] = sum_j A[j][i] P_dn[j][mu]   (= (Lambda Phi_dn^T W^{-1})[mu][i])
+//   Yt_dn[j][nu] = sum_i A[j][i] P_up[i][nu]   (= (W^{-1} Phi_up Lambda)[j][nu])
+// so that grad_i det/det = grad psi(r_i) . Yt[i] for every electron i.
+// FP64 path only: A (FP64) times P (FP64).
+hipError_t launch_Y_build(const SysDev& s, const WalkDev& w, hipStream_t st) {
+  const long rowst = (long)s.N * s.Lp;
+  hipError_t e;
+  if (s.precision == QMC_W_FP32) {
+    // P is FP32: promote on the fly by running the FP64 kernel on an FP64 copy
+    // is avoided; instead the FP32 rows are read by the mixed kernel below.
+    return hipErrorNotSupported;
+  }
+  {
+    GemmArgs g = plain(s.nu, s.Lp, s.nd);
+    g.A = w.A; g.lda = s.nu; g.a_bs = (long)s.nd * s.nu;
+    g.B = (const double*)w.P + (long)s.nu * s.Lp; g.ldb = s.Lp; g.b_bs = rowst;
+    g.C = w.Yt; g.ldc = s.Lp; g.c_bs = rowst;
+    g.batch = w.Wk;
+    e = run_gemm<32, 64, true, false, double, double>(g, st);
+    if (e != hipSuccess) return e;
+  }
+  {
+    GemmArgs g = plain(s.nd, s.Lp, s.nu);
+    g.A = w.A; g.lda = s.nu; g.a_bs = (long)s.nd * s.nu;
+    g.B = (const double*)w.P; g.ldb = s.Lp; g.b_bs = rowst;
+    g.C = w.Yt + (long)s.nu * s.Lp; g.ldc = s.Lp; g.c_bs = rowst;
+    g.batch = w.Wk;
+    e = run_gemm<32, 64, false, false, double, double>(g, st);
+  }
+  return e;
+}
+
+}  // namespace qmc

@@ -1,0 +1,222 @@
+// Internal declarations of the gfx950 JAGP library: device data of a system
+// and of a walker batch, device helpers for the basis and Jastrow terms, and
+// the kernel launchers the C ABI layer calls.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <stdint.h>
+
+#include "../../include/qmc.h"
+
+namespace qmc {
+
+// ---------------------------------------------------------------------------
+// sizes
+// ---------------------------------------------------------------------------
+constexpr int kMaxNuc = 4096;
+constexpr int kLuMaxN = 128;      // LDS-resident Gauss-Jordan inverse limit
+
+inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+// Device-resident description of one system.
+struct SysDev {
+  int n_nuc, L, Lp, nu, nd, N;
+  int j1_form, j2_form;
+  double j2[8];
+  int precision, refresh_every;
+  double* R;        // [A][3]
+  double* Z;        // [A]
+  double* j1_b;     // [A]
+  int* center;      // [L]
+  int* kind;        // [L]  0 s | 1..3 p(x,y,z) | 4..8 d(xy,yz,zx,x2-y2,2z2-x2-y2)
+  double* zeta;     // [L]
+  double* lam;      // [Lp][Lp]  Lambda, zero padded
+  double* lamT;     // [Lp][Lp]  Lambda^T
+  float* lam32;     // [Lp][Lp]  FP32 copies (precision QMC_W_FP32)
+  float* lamT32;
+};
+
+// Device state of a batch of walkers.
+struct WalkDev {
+  int Wk;
+  double* r;        // [Wk][N][3]
+  void* phi;        // [Wk][N][Lp]  basis values (double or float)
+  void* P;          // [Wk][N][Lp]  rows i<nu: Phi_up Lambda ; rows i>=nu: Phi_dn Lambda^T
+  double* W;        // [Wk][nu][nd]
+  double* A;        // [Wk][nd][nu]  W^{-1}
+  double* Yt;       // [Wk][N][Lp]  eval workspace: Yt_up = A^T P_dn, Yt_dn = A P_up
+  double* D;        // [Wk][N][4]   grad det/det (3), lap det/det
+  double* logdet;   // [Wk]
+  double* detsign;  // [Wk]
+  int* singular;    // [Wk]
+  double* logabs;   // [Wk] log|Psi| tracked through moves
+  double* sign;     // [Wk]
+  double* J;        // [Wk] Jastrow exponent tracked through moves
+  // pending proposal
+  double* psi_new;  // [Wk][Lp] basis values at r'
+  double* w_new;    // [Wk][nmax] new row (up) or column (down) of W
+  double* rdet;     // [Wk]
+  double* dJ;       // [Wk]
+  double* r_new;    // [Wk][3]
+  double* ratio;    // [Wk] scratch for the device Metropolis loop
+  uint8_t* acc;     // [Wk]
+};
+
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+
+// Angular factor P and its gradient for an unnormalised real solid harmonic.
+__device__ __forceinline__ void angular(int kind, double x, double y, double z,
+                                        double& P, double& Px, double& Py, double& Pz) {
+  switch (kind) {
+    case 0: P = 1.0;     Px = 0.0;      Py = 0.0;      Pz = 0.0;     break;
+    case 1: P = x;       Px = 1.0;      Py = 0.0;      Pz = 0.0;     break;
+    case 2: P = y;       Px = 0.0;      Py = 1.0;      Pz = 0.0;     break;
+    case 3: P = z;       Px = 0.0;      Py = 0.0;      Pz = 1.0;     break;
+    case 4: P = x * y;   Px = y;        Py = x;        Pz = 0.0;     break;
+    case 5: P = y * z;   Px = 0.0;      Py = z;        Pz = y;       break;
+    case 6: P = z * x;   Px = z;        Py = 0.0;      Pz = x;       break;
+    case 7: P = x * x - y * y;  Px = 2.0 * x;  Py = -2.0 * y;  Pz = 0.0;  break;
+    default: P = 2.0 * z * z - x * x - y * y;  Px = -2.0 * x;  Py = -2.0 * y;  Pz = 4.0 * z;  break;
+  }
+}
+
+__device__ __forceinline__ int kind_l(int kind) { return kind == 0 ? 0 : (kind < 4 ? 1 : 2); }
+
+__device__ __forceinline__ double angular_value(int kind, double x, double y, double z) {
+  switch (kind) {
+    case 0: return 1.0;
+    case 1: return x;
+    case 2: return y;
+    case 3: return z;
+    case 4: return x * y;
+    case 5: return y * z;
+    case 6: return z * x;
+    case 7: return x * x - y * y;
+    default: return 2.0 * z * z - x * x - y * y;
+  }
+}
+
+// Gaussian function mu at point (px,py,pz): value only.
+__device__ __forceinline__ double basis_value(const SysDev& s, int mu, double px, double py, double pz) {
+  const int c = s.center[mu];
+  const double x = px - s.R[3 * c], y = py - s.R[3 * c + 1], z = pz - s.R[3 * c + 2];
+  const double r2 = x * x + y * y + z * z;
+  return angular_value(s.kind[mu], x, y, z) * exp(-s.zeta[mu] * r2);
+}
+
+// Value, gradient and Laplacian.  The angular factors are harmonic and
+// homogeneous of degree l, so lap(P e^{-zeta r^2}) = (4 zeta^2 r^2 - (4l+6) zeta) P e.
+__device__ __forceinline__ void basis_vgl(const SysDev& s, int mu, double px, double py, double pz,
+                                          double& v, double& gx, double& gy, double& gz, double& lap) {
+  const int c = s.center[mu];
+  const double x = px - s.R[3 * c], y = py - s.R[3 * c + 1], z = pz - s.R[3 * c + 2];
+  const double r2 = x * x + y * y + z * z;
+  const double zt = s.zeta[mu];
+  const int k = s.kind[mu];
+  double P, Px, Py, Pz;
+  angular(k, x, y, z, P, Px, Py, Pz);
+  const double e = exp(-zt * r2);
+  const double t = -2.0 * zt * P;
+  v = P * e;
+  gx = (Px + t * x) * e;
+  gy = (Py + t * y) * e;
+  gz = (Pz + t * z) * e;
+  lap = (4.0 * zt * zt * r2 - (4.0 * kind_l(k) + 6.0) * zt) * v;
+}
+
+// One-body term f(r) = -(2Z)^{3/4} u((2Z)^{1/4} r) and its radial derivatives.
+__device__ __forceinline__ void j1_radial(int form, double Z, double b, double r,
+                                          double& f, double& f1, double& f2) {
+  const double q = sqrt(sqrt(2.0 * Z));     // (2Z)^{1/4}
+  const double s = q * r;
+  double u, u1, u2;
+  if (form == 1) {
+    const double e = exp(-b * s);
+    u = -expm1(-b * s) / (2.0 * b);
+    u1 = 0.5 * e;
+    u2 = -0.5 * b * e;
+  } else {
+    const double den = 1.0 / (1.0 + b * s);
+    u = 0.5 * s * den;
+    u1 = 0.5 * den * den;
+    u2 = -b * den * den * den;
+  }
+  const double q3 = q * q * q;
+  f = -q3 * u;
+  f1 = -q3 * q * u1;
+  f2 = -q3 * q * q * u2;
+}
+
+// Two-body term v(r) and its radial derivatives; same = parallel spins.
+// form 1: v = c r/(1+b r); form 2: v = c t + a1 t^2 + a2 t^3 + a3 t^4, t = r/(1+b r).
+__device__ __forceinline__ void j2_radial(int form, const double* p, bool same, double r,
+                                          double& v, double& v1, double& v2) {
+  const double c = same ? 0.25 : 0.5;
+  double b, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  if (form == 1) {
+    b = same ? p[0] : p[1];
+  } else {
+    const int o = same ? 0 : 4;
+    b = p[o]; a1 = p[o + 1]; a2 = p[o + 2]; a3 = p[o + 3];
+  }
+  const double den = 1.0 / (1.0 + b * r);
+  const double t = r * den;
+  const double dt = den * den;
+  const double d2t = -2.0 * b * den * den * den;
+  // g(t) = c t + a1 t^2 + a2 t^3 + a3 t^4
+  const double g = t * (c + t * (a1 + t * (a2 + t * a3)));
+  const double g1 = c + t * (2.0 * a1 + t * (3.0 * a2 + t * 4.0 * a3));
+  const double g2 = 2.0 * a1 + t * (6.0 * a2 + t * 12.0 * a3);
+  v = g;
+  v1 = g1 * dt;
+  v2 = g2 * dt * dt + g1 * d2t;
+}
+
+// ---------------------------------------------------------------------------
+// wave-level reductions (64 lanes)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// launchers (all asynchronous on `st`)
+// ---------------------------------------------------------------------------
+hipError_t launch_basis_values(const SysDev& s, const WalkDev& w, hipStream_t st);
+hipError_t launch_P_build(const SysDev& s, const WalkDev& w, int halves, hipStream_t st);
+hipError_t launch_W_build(const SysDev& s, const WalkDev& w, hipStream_t st);
+hipError_t launch_Y_build(const SysDev& s, const WalkDev& w, hipStream_t st);
+hipError_t launch_lu_inverse(const SysDev& s, const WalkDev& w, hipStream_t st);
+hipError_t launch_rowdots(const SysDev& s, const WalkDev& w, hipStream_t st);
+hipError_t launch_jastrow_assemble(const SysDev& s, const WalkDev& w, double* logabs, double* sign,
+                                   double* drift, double* e_kin, double* e_loc, int32_t* status,
+                                   hipStream_t st);
+hipError_t launch_propose(const SysDev& s, const WalkDev& w, int e, const double* r_new,
+                          const double* disp, double* ratio, double* drift_new, hipStream_t st);
+hipError_t launch_metropolis_accept(const SysDev& s, const WalkDev& w, int e, const double* unif,
+                                    int32_t* accept_count, hipStream_t st);
+hipError_t launch_accept(const SysDev& s, const WalkDev& w, int e, const uint8_t* acc,
+                         hipStream_t st);
+hipError_t launch_refresh_finish(const SysDev& s, const WalkDev& w, int32_t* status, hipStream_t st);
+hipError_t launch_export_phi(const SysDev& s, const WalkDev& w, double* dst, hipStream_t st);
+
+// FP64 MFMA GEMM, exposed for the launchers above.
+struct GemmArgs {
+  int M, N, K;
+  const void* A; long lda; long a_bs; int a_grp; long a_gs;
+  const void* B; long ldb; long b_bs;
+  void* C; long ldc; long c_bs; int c_grp; long c_gs;
+  int batch;
+};
+
+}  // namespace qmc

@@ -1,0 +1,325 @@
+// Host side of the C ABI declared in include/qmc.h: validation, device
+// allocation of system and walker state, and the launch sequences of the
+// evaluation, move and Metropolis calls.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace qmc;
+
+namespace {
+thread_local std::string g_err;
+
+qmc_status fail(qmc_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+qmc_status hip_fail(hipError_t e, const char* where) {
+  g_err = std::string(where) + ": " + hipGetErrorString(e);
+  return QMC_ERR_HIP;
+}
+
+#define HIP_TRY(expr, where)                          \
+  do {                                                \
+    hipError_t _e = (expr);                           \
+    if (_e != hipSuccess) return hip_fail(_e, where); \
+  } while (0)
+
+template <typename T>
+hipError_t dalloc(T** p, size_t count) {
+  return hipMalloc((void**)p, count * sizeof(T) + 256);
+}
+}  // namespace
+
+struct qmc_system {
+  SysDev d{};
+  int device = 0;
+  std::vector<void*> allocs;
+  ~qmc_system() {
+    for (void* p : allocs) (void)hipFree(p);
+  }
+};
+
+struct qmc_walkers {
+  qmc_system* sys = nullptr;
+  WalkDev d{};
+  std::vector<void*> allocs;
+  int pending_e = -1;
+  long attempts = 0;
+  bool evaluated = false;
+  bool P_up_valid = false, P_dn_valid = false;
+  ~qmc_walkers() {
+    for (void* p : allocs) (void)hipFree(p);
+  }
+};
+
+extern "C" int32_t qmc_abi_version(void) { return QMC_ABI_VERSION; }
+
+extern "C" const char* qmc_last_error(void) { return g_err.c_str(); }
+
+extern "C" qmc_status qmc_system_create(const qmc_system_desc* desc, qmc_system** out) {
+  if (!desc || !out) return fail(QMC_ERR_ARG, "null argument");
+  *out = nullptr;
+  const qmc_system_desc& q = *desc;
+  if (q.n_nuc <= 0 || q.n_nuc > kMaxNuc || !q.R || !q.Z) return fail(QMC_ERR_ARG, "bad nuclei");
+  if (q.n_basis <= 0 || !q.center || !q.l || !q.m || !q.zeta || !q.lambda)
+    return fail(QMC_ERR_ARG, "bad basis");
+  if (q.n_up <= 0 || q.n_dn < 0) return fail(QMC_ERR_ARG, "bad electron counts");
+  if (q.n_up != q.n_dn) return fail(QMC_ERR_UNSUPPORTED, "only n_up == n_dn is built");
+  if (q.n_up > kLuMaxN) return fail(QMC_ERR_UNSUPPORTED, "n_up > 128 needs the blocked LU");
+  if (q.precision != QMC_FP64 && q.precision != QMC_W_FP32)
+    return fail(QMC_ERR_UNSUPPORTED, "precision not built");
+  if (q.refresh_every < 1) return fail(QMC_ERR_ARG, "refresh_every must be >= 1");
+  if (q.j1_form < 0 || q.j1_form > 2 || (q.j1_form && !q.j1_b)) return fail(QMC_ERR_ARG, "bad j1");
+  if (q.j2_form < 0 || q.j2_form > 2) return fail(QMC_ERR_ARG, "bad j2 form");
+  if (q.j2_form == 1 && (q.n_j2 != 2 || !q.j2)) return fail(QMC_ERR_ARG, "j2 form 1 needs 2 params");
+  if (q.j2_form == 2 && (q.n_j2 != 8 || !q.j2)) return fail(QMC_ERR_ARG, "j2 form 2 needs 8 params");
+  const int L = q.n_basis;
+  std::vector<int> kind(L);
+  for (int mu = 0; mu < L; ++mu) {
+    if (q.radial && q.radial[mu] != 0) return fail(QMC_ERR_UNSUPPORTED, "only Gaussian functions are built");
+    if (q.center[mu] < 0 || q.center[mu] >= q.n_nuc) return fail(QMC_ERR_ARG, "basis center out of range");
+    const int l = q.l[mu], m = q.m[mu];
+    if (l < 0 || l > 2) return fail(QMC_ERR_UNSUPPORTED, "l > 2 not built");
+    if (m < 0 || m >= 2 * l + 1) return fail(QMC_ERR_ARG, "component index out of range");
+    kind[mu] = (l == 0) ? 0 : (l == 1 ? 1 + m : 4 + m);
+  }
+  auto* s = new qmc_system();
+  SysDev& d = s->d;
+  if (hipGetDevice(&s->device) != hipSuccess) s->device = 0;
+  d.n_nuc = q.n_nuc; d.L = L; d.Lp = round_up(L, 32);
+  d.nu = q.n_up; d.nd = q.n_dn; d.N = q.n_up + q.n_dn;
+  d.j1_form = q.j1_form; d.j2_form = q.j2_form;
+  for (int k = 0; k < 8; ++k) d.j2[k] = (q.j2 && k < q.n_j2) ? q.j2[k] : 0.0;
+  d.precision = q.precision; d.refresh_every = q.refresh_every;
+  const int Lp = d.Lp, A = q.n_nuc;
+  std::vector<double> lam((size_t)Lp * Lp, 0.0), lamT((size_t)Lp * Lp, 0.0);
+  for (int i = 0; i < L; ++i)
+    for (int j = 0; j < L; ++j) {
+      lam[(size_t)i * Lp + j] = q.lambda[(size_t)i * L + j];
+      lamT[(size_t)j * Lp + i] = q.lambda[(size_t)i * L + j];
+    }
+  std::vector<double> j1b(A, 1.0);
+  if (q.j1_form) for (int a = 0; a < A; ++a) j1b[a] = q.j1_b[a];
+  auto up = [&](void** dst, const void* src, size_t bytes) -> hipError_t {
+    hipError_t e = hipMalloc(dst, bytes + 256);
+    if (e != hipSuccess) return e;
+    s->allocs.push_back(*dst);
+    return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+  };
+  hipError_t e = hipSuccess;
+  if (!e) e = up((void**)&d.R, q.R, sizeof(double) * 3 * A);
+  if (!e) e = up((void**)&d.Z, q.Z, sizeof(double) * A);
+  if (!e) e = up((void**)&d.j1_b, j1b.data(), sizeof(double) * A);
+  if (!e) e = up((void**)&d.center, q.center, sizeof(int) * L);
+  if (!e) e = up((void**)&d.kind, kind.data(), sizeof(int) * L);
+  if (!e) e = up((void**)&d.zeta, q.zeta, sizeof(double) * L);
+  if (!e) e = up((void**)&d.lam, lam.data(), sizeof(double) * lam.size());
+  if (!e) e = up((void**)&d.lamT, lamT.data(), sizeof(double) * lamT.size());
+  if (!e && q.precision == QMC_W_FP32) {
+    std::vector<float> l32(lam.begin(), lam.end()), lT32(lamT.begin(), lamT.end());
+    e = up((void**)&d.lam32, l32.data(), sizeof(float) * l32.size());
+    if (!e) e = up((void**)&d.lamT32, lT32.data(), sizeof(float) * lT32.size());
+  }
+  if (e != hipSuccess) {
+    delete s;
+    return e == hipErrorOutOfMemory ? fail(QMC_ERR_OOM, "device allocation failed") : hip_fail(e, "system_create");
+  }
+  *out = s;
+  return QMC_OK;
+}
+
+extern "C" qmc_status qmc_system_destroy(qmc_system* sys) {
+  if (!sys) return fail(QMC_ERR_ARG, "null system");
+  (void)hipDeviceSynchronize();
+  delete sys;
+  return QMC_OK;
+}
+
+extern "C" qmc_status qmc_walkers_create(qmc_system* sys, int32_t n_walkers, qmc_walkers** out) {
+  if (!sys || !out) return fail(QMC_ERR_ARG, "null argument");
+  if (n_walkers <= 0) return fail(QMC_ERR_ARG, "n_walkers must be positive");
+  *out = nullptr;
+  const SysDev& s = sys->d;
+  auto* wk = new qmc_walkers();
+  wk->sys = sys;
+  WalkDev& d = wk->d;
+  d.Wk = n_walkers;
+  const size_t Wk = n_walkers, N = s.N, Lp = s.Lp;
+  const size_t nmax = s.nu > s.nd ? s.nu : s.nd;
+  const size_t esz = s.precision == QMC_W_FP32 ? sizeof(float) : sizeof(double);
+  hipError_t e = hipSuccess;
+  auto al = [&](void** p, size_t bytes) {
+    if (e != hipSuccess) return;
+    e = hipMalloc(p, bytes + 256);
+    if (e == hipSuccess) {
+      wk->allocs.push_back(*p);
+      e = hipMemset(*p, 0, bytes + 256);
+    }
+  };
+  al((void**)&d.r, sizeof(double) * Wk * N * 3);
+  al(&d.phi, esz * Wk * N * Lp);
+  al(&d.P, esz * Wk * N * Lp);
+  al((void**)&d.W, sizeof(double) * Wk * s.nu * s.nd);
+  al((void**)&d.A, sizeof(double) * Wk * s.nd * s.nu);
+  al((void**)&d.Yt, sizeof(double) * Wk * N * Lp);
+  al((void**)&d.D, sizeof(double) * Wk * N * 4);
+  al((void**)&d.logdet, sizeof(double) * Wk);
+  al((void**)&d.detsign, sizeof(double) * Wk);
+  al((void**)&d.singular, sizeof(int) * Wk);
+  al((void**)&d.logabs, sizeof(double) * Wk);
+  al((void**)&d.sign, sizeof(double) * Wk);
+  al((void**)&d.J, sizeof(double) * Wk);
+  al((void**)&d.psi_new, sizeof(double) * Wk * Lp);
+  al((void**)&d.w_new, sizeof(double) * Wk * nmax);
+  al((void**)&d.rdet, sizeof(double) * Wk);
+  al((void**)&d.dJ, sizeof(double) * Wk);
+  al((void**)&d.r_new, sizeof(double) * Wk * 3);
+  al((void**)&d.ratio, sizeof(double) * Wk);
+  al((void**)&d.acc, sizeof(uint8_t) * Wk);
+  if (e != hipSuccess) {
+    delete wk;
+    return e == hipErrorOutOfMemory ? fail(QMC_ERR_OOM, "device allocation failed") : hip_fail(e, "walkers_create");
+  }
+  *out = wk;
+  return QMC_OK;
+}
+
+extern "C" qmc_status qmc_walkers_destroy(qmc_walkers* wk) {
+  if (!wk) return fail(QMC_ERR_ARG, "null walkers");
+  (void)hipDeviceSynchronize();
+  delete wk;
+  return QMC_OK;
+}
+
+static qmc_status check_pair(qmc_system* sys, qmc_walkers* wk) {
+  if (!sys || !wk) return fail(QMC_ERR_ARG, "null handle");
+  if (wk->sys != sys) return fail(QMC_ERR_ARG, "walkers belong to another system");
+  return QMC_OK;
+}
+
+extern "C" qmc_status qmc_eval_batch(qmc_system* sys, qmc_walkers* wk, const double* r, double* logabs,
+                                     double* sign, double* drift, double* e_kin, double* e_loc,
+                                     int32_t* status, hipStream_t stream) {
+  qmc_status c = check_pair(sys, wk);
+  if (c) return c;
+  if (!r) return fail(QMC_ERR_ARG, "null positions");
+  const SysDev& s = sys->d;
+  WalkDev& d = wk->d;
+  if (s.precision != QMC_FP64) return fail(QMC_ERR_UNSUPPORTED, "eval for this precision not built");
+  HIP_TRY(hipMemcpyAsync(d.r, r, sizeof(double) * d.Wk * s.N * 3, hipMemcpyDeviceToDevice, stream), "copy r");
+  HIP_TRY(launch_basis_values(s, d, stream), "basis");
+  HIP_TRY(launch_P_build(s, d, 3, stream), "P build");
+  HIP_TRY(launch_W_build(s, d, stream), "W build");
+  HIP_TRY(launch_lu_inverse(s, d, stream), "LU");
+  HIP_TRY(launch_Y_build(s, d, stream), "Y build");
+  HIP_TRY(launch_rowdots(s, d, stream), "row dots");
+  HIP_TRY(launch_jastrow_assemble(s, d, logabs, sign, drift, e_kin, e_loc, status, stream), "assemble");
+  wk->evaluated = true;
+  wk->P_up_valid = wk->P_dn_valid = true;
+  wk->attempts = 0;
+  wk->pending_e = -1;
+  return QMC_OK;
+}
+
+// P rows of the spin opposite to electron e must match the current basis rows.
+static qmc_status ensure_P(qmc_walkers* wk, int e, hipStream_t stream) {
+  const SysDev& s = wk->sys->d;
+  const bool up = e < s.nu;
+  if (up && !wk->P_dn_valid) {
+    HIP_TRY(launch_P_build(s, wk->d, 2, stream), "P_dn rebuild");
+    wk->P_dn_valid = true;
+  } else if (!up && !wk->P_up_valid) {
+    HIP_TRY(launch_P_build(s, wk->d, 1, stream), "P_up rebuild");
+    wk->P_up_valid = true;
+  }
+  return QMC_OK;
+}
+
+extern "C" qmc_status qmc_propose_move(qmc_system* sys, qmc_walkers* wk, int32_t electron,
+                                       const double* r_new, double* ratio, double* drift_new,
+                                       hipStream_t stream) {
+  qmc_status c = check_pair(sys, wk);
+  if (c) return c;
+  const SysDev& s = sys->d;
+  if (!wk->evaluated) return fail(QMC_ERR_STATE, "propose before eval_batch");
+  if (electron < 0 || electron >= s.N) return fail(QMC_ERR_ARG, "electron index out of range");
+  if (!r_new) return fail(QMC_ERR_ARG, "null r_new");
+  c = ensure_P(wk, electron, stream);
+  if (c) return c;
+  HIP_TRY(launch_propose(s, wk->d, electron, r_new, nullptr, ratio, drift_new, stream), "propose");
+  wk->pending_e = electron;
+  return QMC_OK;
+}
+
+static qmc_status after_accept(qmc_walkers* wk, int e, int32_t* status, hipStream_t stream) {
+  const SysDev& s = wk->sys->d;
+  if (e < s.nu) wk->P_up_valid = false; else wk->P_dn_valid = false;
+  wk->pending_e = -1;
+  wk->attempts += 1;
+  if (wk->attempts % s.refresh_every == 0) {
+    HIP_TRY(launch_lu_inverse(s, wk->d, stream), "refresh LU");
+    HIP_TRY(launch_refresh_finish(s, wk->d, status, stream), "refresh finish");
+  }
+  return QMC_OK;
+}
+
+extern "C" qmc_status qmc_accept_move(qmc_system* sys, qmc_walkers* wk, int32_t electron,
+                                      const uint8_t* accept, int32_t* status, hipStream_t stream) {
+  qmc_status c = check_pair(sys, wk);
+  if (c) return c;
+  if (!accept) return fail(QMC_ERR_ARG, "null accept");
+  if (wk->pending_e < 0 || wk->pending_e != electron)
+    return fail(QMC_ERR_STATE, "no pending proposal for this electron");
+  HIP_TRY(launch_accept(sys->d, wk->d, electron, accept, stream), "accept");
+  return after_accept(wk, electron, status, stream);
+}
+
+extern "C" qmc_status qmc_vmc_steps(qmc_system* sys, qmc_walkers* wk, int32_t e_start, int32_t n_steps,
+                                    const double* disp, const double* unif, int32_t* accept_count,
+                                    hipStream_t stream) {
+  qmc_status c = check_pair(sys, wk);
+  if (c) return c;
+  const SysDev& s = sys->d;
+  if (!wk->evaluated) return fail(QMC_ERR_STATE, "vmc_steps before eval_batch");
+  if (!disp || !unif) return fail(QMC_ERR_ARG, "null random arrays");
+  if (n_steps < 0 || e_start < 0) return fail(QMC_ERR_ARG, "negative step count or electron");
+  const long Wk = wk->d.Wk;
+  for (int t = 0; t < n_steps; ++t) {
+    const int e = (int)((e_start + (long)t) % s.N);
+    c = ensure_P(wk, e, stream);
+    if (c) return c;
+    HIP_TRY(launch_propose(s, wk->d, e, nullptr, disp + (long)t * Wk * 3, nullptr, nullptr, stream), "propose");
+    HIP_TRY(launch_metropolis_accept(s, wk->d, e, unif + (long)t * Wk, accept_count, stream), "metropolis");
+    c = after_accept(wk, e, nullptr, stream);
+    if (c) return c;
+  }
+  return QMC_OK;
+}
+
+extern "C" qmc_status qmc_walkers_read(qmc_walkers* wk, int32_t item, double* dst, hipStream_t stream) {
+  if (!wk || !dst) return fail(QMC_ERR_ARG, "null argument");
+  const SysDev& s = wk->sys->d;
+  const WalkDev& d = wk->d;
+  const size_t Wk = d.Wk;
+  const void* src = nullptr;
+  size_t bytes = 0;
+  switch (item) {
+    case QMC_STATE_R: src = d.r; bytes = sizeof(double) * Wk * s.N * 3; break;
+    case QMC_STATE_LOGABS: src = d.logabs; bytes = sizeof(double) * Wk; break;
+    case QMC_STATE_SIGN: src = d.sign; bytes = sizeof(double) * Wk; break;
+    case QMC_STATE_W: src = d.W; bytes = sizeof(double) * Wk * s.nu * s.nd; break;
+    case QMC_STATE_AINV: src = d.A; bytes = sizeof(double) * Wk * s.nd * s.nu; break;
+    case QMC_STATE_PHI:
+      HIP_TRY(launch_export_phi(s, d, dst, stream), "export phi");
+      return QMC_OK;
+    default: return fail(QMC_ERR_ARG, "unknown state item");
+  }
+  HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, stream), "read state");
+  return QMC_OK;
+}
