@@ -1,0 +1,222 @@
+"""Benchmark of the batched JAGP hot path on one MI355X.
+
+One step = one from-scratch evaluation of every walker (basis -> P = Phi Lambda
+-> W -> FP64 LU/inverse -> cofactor products -> local energy) followed by one
+sweep of single-electron Metropolis moves (every electron once, device-side
+accept, FP64 Sherman-Morrison updates, LU refresh every 32 attempted moves).
+Workload: 40 nuclei, 160 electrons (80/80), 600 Gaussian basis functions,
+1024 walkers (synthetic, seeded).
+
+Prints ONE JSON line.  `value` is walker-electron moves/s over the move
+sweeps of the timed steps; E_loc evaluations/s over their evaluations are
+reported beside it, with the error against the CPU oracle on sampled walkers,
+the roofline of the dominant kernel and the oracle's own CPU throughput.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+import torch  # noqa: E402
+
+METRIC = "walker-electron moves/s + E_loc evals/s at 160e, mixed vs FP64, err vs oracle"
+HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--walkers", type=int, default=1024)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--oracle-walkers", type=int, default=4)
+    ap.add_argument("--only", action="store_true", help="run the headline precision only")
+    return ap.parse_args()
+
+
+def kernel_models(s, Wk, esz, acc_rate):
+    """Algorithmic bytes / flops per launch of the main kernels.
+
+    propose (the streaming kernel): every walker reads the N_other x L rows of P
+             of the opposite spin (esz bytes each), psi(r') (8 L), the matching
+             W^{-1} column (8 N_other), and writes the new W row (8 N_other).
+    accept:  an accepted walker reads and writes W^{-1} (2 x 8 n^2), reads the new
+             row and basis values (8 (N_other + L)), writes the W row (8 N_other)
+             and the basis row (esz L); rejected walkers move no data.
+    P_build: 2 L^2 flops per basis row, over the Wk * N/2 rows of one spin.
+    """
+    L, N, n = s.n_basis, s.n_up + s.n_dn, s.n_up
+    prop = Wk * (esz * n * L + 8 * L + 8 * n + 8 * n)
+    acc = Wk * acc_rate * (16 * n * n + 8 * (n + L) + 8 * n + esz * L)
+    pflops = 2.0 * L * L * Wk * n
+    return {"propose": ("hbm", prop), "accept": ("hbm", acc), "P_build": ("mfma", pflops)}
+
+
+def cpu_baseline(w, n_walk=8, n_moves=320, n_eval=32):
+    """The CPU oracle, untuned, on a bounded sample of the same workload."""
+    from oracle import jagp as O
+    from workloads import configs as C
+    sy = O.from_workload_system(w.system)
+    t0 = time.perf_counter()
+    O.evaluate(sy, torch.tensor(w.r0[:n_eval]))
+    t_eval = time.perf_counter() - t0
+    r = torch.tensor(w.r0[:n_walk])
+    disp, unif = C.chain_arrays(77, n_moves, n_walk)
+    t0 = time.perf_counter()
+    O.run_chain(sy, r, torch.tensor(disp), torch.tensor(unif))
+    t_moves = time.perf_counter() - t0
+    return {
+        "value": n_walk * n_moves / t_moves, "unit": "walker-electron moves/s",
+        "cores": torch.get_num_threads(), "kind": "oracle",
+        "sample": f"{n_walk} walkers x {n_moves} single-electron moves (each move re-evaluates Psi "
+                  f"from scratch) and E_loc evaluations of {n_eval} walkers, same workload",
+        "eloc_evals_per_s": n_eval / t_eval,
+        "seconds": round(t_eval + t_moves, 2),
+    }
+
+
+def run_precision(P, C, w, args, precision):
+    """Timed steps at one precision; returns the measurement record."""
+    from oracle import jagp as O
+    dev = torch.device("cuda:0")
+    s = w.system
+    N = s.n_up + s.n_dn
+    Wk = args.walkers
+    prec = {"fp64": P.QMC_FP64, "fp32": P.QMC_W_FP32}[precision]
+    esz = 8 if precision == "fp64" else 4
+    sysh = P.JAGPSystem(s, precision=prec)
+    wk = P.Walkers(sysh, Wk)
+    n_tot = args.warmup + args.steps
+    disp, unif = C.chain_arrays(20020740, n_tot * N, Wk)
+    disp = torch.tensor(disp, device=dev).view(n_tot, N, Wk, 3)
+    unif = torch.tensor(unif, device=dev).view(n_tot, N, Wk)
+    cnt = torch.zeros(Wk, dtype=torch.int32, device=dev)
+    r_cur = torch.tensor(w.r0, device=dev)
+
+    def step(k, ev=None):
+        nonlocal r_cur
+        if ev: ev[0].record()
+        wk.eval_batch(r_cur, drift=True)
+        if ev: ev[1].record()
+        wk.vmc_steps(0, disp[k], unif[k], cnt)
+        if ev: ev[2].record()
+        r_cur = wk.read(P.STATE_R)
+
+    for k in range(args.warmup):
+        step(k)
+    torch.cuda.synchronize()
+    cnt.zero_()
+    wk.set_timing(True)
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(args.warmup + k, evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tim = wk.timing()
+    wk.set_timing(False)
+    t_eval = sum(e[0].elapsed_time(e[1]) for e in evs) / 1e3
+    t_move = sum(e[1].elapsed_time(e[2]) for e in evs) / 1e3
+    moves = args.steps * N * Wk
+    acc_rate = cnt.sum().item() / moves
+
+    # error of an evaluation at the final positions against the CPU oracle
+    idx = np.linspace(0, Wk - 1, args.oracle_walkers).round().astype(int).tolist()
+    out = wk.eval_batch(r_cur, drift=True)
+    torch.cuda.synchronize()
+    ref = O.evaluate(O.from_workload_system(s), r_cur.cpu()[idx])
+    err = {}
+    for key in ("logabs", "e_loc"):
+        d = (out[key].cpu()[idx] - ref[key]).abs() / ref[key].abs().clamp(min=1.0)
+        err[key] = float(f"{float(d.max()):.3e}")
+
+    # roofline of the dominant kernel (largest summed time in the timed steps)
+    models = kernel_models(s, Wk, esz, acc_rate)
+    dom = max(models, key=lambda k: tim[k][0])
+    bound, units = models[dom]
+    avg_ms = tim[dom][0] / max(tim[dom][1], 1)
+    if bound == "hbm":
+        achieved = units / (avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "bytes_per_launch": int(units), "avg_launch_us": round(avg_ms * 1e3, 2)}
+    else:
+        peak = MFMA_PEAK_TFLOPS[precision]
+        achieved = units / (avg_ms * 1e-3) / 1e12
+        roof = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 2), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                "flops_per_launch": int(units), "avg_launch_us": round(avg_ms * 1e3, 2)}
+    wk.close()
+    sysh.close()
+    return {
+        "moves_per_s": round(moves / t_move, 1),
+        "eloc_evals_per_s": round(Wk * args.steps / t_eval, 1),
+        "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "acceptance": round(acc_rate, 4),
+        "err_vs_oracle": {"walkers": idx, **err},
+        "kernel_ms": {k: round(v[0], 3) for k, v in tim.items() if v[1]},
+        "kernel_launches": {k: v[1] for k, v in tim.items() if v[1]},
+        "roofline": roof,
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU: the walker batch of one MI355X is the unit measured here; "
+              "multi-GPU runs are not part of this build.", file=sys.stderr)
+        sys.exit(2)
+    import paper_2002_07401_amd as P
+    from workloads import configs as C
+    P.load()
+    torch.cuda.set_device(0)
+    w = C.mol_40nuc_160e(n_walkers=args.walkers)
+    s = w.system
+    N = s.n_up + s.n_dn
+    main_prec = args.precision
+    other = "fp32" if main_prec == "fp64" else "fp64"
+    head = run_precision(P, C, w, args, main_prec)
+    side = None if args.only else run_precision(P, C, w, args, other)
+    res = {
+        "metric": METRIC,
+        "value": head["moves_per_s"],
+        "unit": "walker-electron moves/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if main_prec == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "mol_40nuc_160e", "walkers": args.walkers, "electrons": N,
+                   "basis": s.n_basis, "nuclei": len(s.Z), "refresh_every": s.refresh_every,
+                   "precision": main_prec},
+        "eloc_evals_per_s": head["eloc_evals_per_s"],
+        "acceptance": head["acceptance"],
+        "err_vs_oracle": head["err_vs_oracle"],
+        "kernel_ms": head["kernel_ms"],
+        "kernel_launches": head["kernel_launches"],
+        "roofline": head["roofline"],
+    }
+    if side is not None:
+        key = "mixed_fp32" if other == "fp32" else "fp64"
+        res[key] = side
+        if other == "fp32":
+            res["mixed_over_fp64_moves"] = round(side["moves_per_s"] / head["moves_per_s"], 3)
+            res["mixed_over_fp64_evals"] = round(side["eloc_evals_per_s"] / head["eloc_evals_per_s"], 3)
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

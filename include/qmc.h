@@ -172,6 +172,34 @@ typedef enum {
  * above, FP64) on `stream`.  For inspection and checkpoints. */
 qmc_status qmc_walkers_read(qmc_walkers *wk, int32_t item, double *dst, hipStream_t stream);
 
+/* Kernel timers.  When timing is enabled on a walker set, every launch the
+ * library makes for it is bracketed by a pair of HIP events recorded on the
+ * call's stream, and the elapsed times are summed per timer. */
+typedef enum {
+  QMC_T_BASIS = 0,     /* basis values                                   */
+  QMC_T_P_BUILD = 1,   /* P = Phi Lambda (eval and rebuilds before moves)  */
+  QMC_T_W_BUILD = 2,   /* W = P_up Phi_dn^T                              */
+  QMC_T_LU = 3,        /* FP64 LU inverse / log-det (eval and refresh)   */
+  QMC_T_Y_BUILD = 4,   /* cofactor products for the local energy         */
+  QMC_T_ROWDOT = 5,    /* basis-derivative row dots                      */
+  QMC_T_ASSEMBLE = 6,  /* Jastrow, Coulomb, local-energy assembly         */
+  QMC_T_PROPOSE = 7,   /* proposal, streaming part: new W row/column and
+                          the partial determinant ratios                  */
+  QMC_T_ACCEPT = 8,    /* Metropolis decision + Sherman-Morrison update  */
+  QMC_T_OTHER = 9,     /* small bookkeeping kernels                      */
+  QMC_T_PROPOSE_PREP = 10, /* proposal, per-walker part: psi(r'), Jastrow
+                              change                                      */
+  QMC_TIMER_COUNT = 11
+} qmc_timer;
+
+/* enable != 0 turns timing on and clears the sums; 0 turns it off. */
+qmc_status qmc_walkers_set_timing(qmc_walkers *wk, int32_t enable);
+
+/* Wait for the recorded events and return, per timer, the summed kernel time in
+ * milliseconds (ms[QMC_TIMER_COUNT], host) and the number of launches
+ * (launches[QMC_TIMER_COUNT], host).  Synchronises with the recorded events. */
+qmc_status qmc_walkers_timing(qmc_walkers *wk, double *ms, int64_t *launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -28,8 +28,12 @@ STATUS_NAMES = {0: "OK", -1: "ERR_ARG", -2: "ERR_SHAPE", -3: "ERR_HIP", -4: "ERR
 FUNCTIONS = (
     "qmc_abi_version", "qmc_last_error", "qmc_system_create", "qmc_system_destroy",
     "qmc_walkers_create", "qmc_walkers_destroy", "qmc_eval_batch", "qmc_propose_move",
-    "qmc_accept_move", "qmc_vmc_steps", "qmc_walkers_read",
+    "qmc_accept_move", "qmc_vmc_steps", "qmc_walkers_read", "qmc_walkers_set_timing",
+    "qmc_walkers_timing",
 )
+
+TIMER_NAMES = ("basis", "P_build", "W_build", "LU", "Y_build", "rowdot", "assemble", "propose",
+               "accept", "other", "propose_prep")
 
 
 class QMCError(RuntimeError):
@@ -75,6 +79,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.qmc_accept_move.argtypes = [vp, vp, i32, vp, vp, vp]
     lib.qmc_vmc_steps.argtypes = [vp, vp, i32, i32, dp, dp, vp, vp]
     lib.qmc_walkers_read.argtypes = [vp, i32, dp, vp]
+    lib.qmc_walkers_set_timing.argtypes = [vp, i32]
+    lib.qmc_walkers_timing.argtypes = [vp, vp, vp]
     _lib = lib
     return lib
 
@@ -196,3 +202,13 @@ class Walkers:
         dst = torch.empty(shape, dtype=torch.float64, device="cuda")
         _check(load().qmc_walkers_read(self.h, item, _ptr(dst), _stream(stream)))
         return dst
+
+    def set_timing(self, enable: bool):
+        _check(load().qmc_walkers_set_timing(self.h, 1 if enable else 0))
+
+    def timing(self):
+        """{timer name: (total ms, launches)}; waits for the recorded events."""
+        ms = (ctypes.c_double * len(TIMER_NAMES))()
+        n = (ctypes.c_int64 * len(TIMER_NAMES))()
+        _check(load().qmc_walkers_timing(self.h, ms, n))
+        return {k: (ms[i], n[i]) for i, k in enumerate(TIMER_NAMES)}

@@ -36,8 +36,9 @@ template <> struct Mfma<float> {
 };
 
 // TA: A stored [K][M] (op(A) = A^T); TB: B stored [N][K] (op(B) = B^T).
-// TI: operand type, TO: output type.
-template <int BM, int BN, bool TA, bool TB, typename TI, typename TO>
+// SA, SB: storage types of A and B (converted exactly to TI on load);
+// TI: MFMA operand type; TO: output type.
+template <int BM, int BN, bool TA, bool TB, typename SA, typename SB, typename TI, typename TO>
 __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
   constexpr int BK = 16;
   constexpr int WM = BM / 2, WN = BN / 2;
@@ -48,8 +49,8 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
   typedef typename Mfma<TI>::acc_t acc_t;
 
   const long bz = blockIdx.z;
-  const TI* __restrict__ A = (const TI*)g.A + bz * g.a_bs;
-  const TI* __restrict__ B = (const TI*)g.B + bz * g.b_bs;
+  const SA* __restrict__ A = (const SA*)g.A + bz * g.a_bs;
+  const SB* __restrict__ B = (const SB*)g.B + bz * g.b_bs;
   TO* __restrict__ C = (TO*)g.C + bz * g.c_bs;
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -71,7 +72,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
       if (gm < g.M && gk < g.K) {
         const long off = TA ? (long)gk * g.lda + gm
                             : (long)(gm / g.a_grp) * g.a_gs + (long)(gm % g.a_grp) * g.lda + gk;
-        v = A[off];
+        v = (TI)A[off];
       }
       As[kk][mm] = v;
     }
@@ -80,7 +81,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
       if (TB) { nn = idx / BK; kk = idx % BK; } else { kk = idx / BN; nn = idx % BN; }
       const int gn = n0 + nn, gk = k0 + kk;
       TI v = 0;
-      if (gn < g.N && gk < g.K) v = TB ? B[(long)gn * g.ldb + gk] : B[(long)gk * g.ldb + gn];
+      if (gn < g.N && gk < g.K) v = (TI)(TB ? B[(long)gn * g.ldb + gk] : B[(long)gk * g.ldb + gn]);
       Bs[kk][nn] = v;
     }
     __syncthreads();
@@ -112,11 +113,11 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
       }
 }
 
-template <int BM, int BN, bool TA, bool TB, typename TI, typename TO>
+template <int BM, int BN, bool TA, bool TB, typename SA, typename SB, typename TI, typename TO>
 static hipError_t run_gemm(const GemmArgs& g, hipStream_t st) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
   dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, g.batch);
-  hipLaunchKernelGGL((gemm_kernel<BM, BN, TA, TB, TI, TO>), grid, dim3(256), 0, st, g);
+  hipLaunchKernelGGL((gemm_kernel<BM, BN, TA, TB, SA, SB, TI, TO>), grid, dim3(256), 0, st, g);
   return hipGetLastError();
 }
 
@@ -141,7 +142,7 @@ static hipError_t P_build_t(const SysDev& s, const WalkDev& w, int halves, hipSt
     g.A = phi; g.lda = s.Lp; g.a_grp = s.nu; g.a_gs = rowst;
     g.B = lam; g.ldb = s.Lp;
     g.C = P; g.ldc = s.Lp; g.c_grp = s.nu; g.c_gs = rowst;
-    e = run_gemm<64, 64, false, false, T, T>(g, st);
+    e = run_gemm<64, 64, false, false, T, T, T, T>(g, st);
     if (e != hipSuccess) return e;
   }
   if (halves & 2) {   // P_dn = Phi_dn Lambda^T (rows nu..N-1)
@@ -149,7 +150,7 @@ static hipError_t P_build_t(const SysDev& s, const WalkDev& w, int halves, hipSt
     g.A = phi + (long)s.nu * s.Lp; g.lda = s.Lp; g.a_grp = s.nd; g.a_gs = rowst;
     g.B = lamT; g.ldb = s.Lp;
     g.C = P + (long)s.nu * s.Lp; g.ldc = s.Lp; g.c_grp = s.nd; g.c_gs = rowst;
-    e = run_gemm<64, 64, false, false, T, T>(g, st);
+    e = run_gemm<64, 64, false, false, T, T, T, T>(g, st);
   }
   return e;
 }
@@ -168,7 +169,7 @@ static hipError_t W_build_t(const SysDev& s, const WalkDev& w, hipStream_t st) {
   g.B = (const T*)w.phi + (long)s.nu * s.Lp; g.ldb = s.Lp; g.b_bs = rowst;
   g.C = w.W; g.ldc = s.nd; g.c_bs = (long)s.nu * s.nd;
   g.batch = w.Wk;
-  return run_gemm<32, 32, false, true, T, double>(g, st);
+  return run_gemm<32, 32, false, true, T, T, T, double>(g, st);
 }
 
 hipError_t launch_W_build(const SysDev& s, const WalkDev& w, hipStream_t st) {
@@ -179,34 +180,35 @@ hipError_t launch_W_build(const SysDev& s, const WalkDev& w, hipStream_t st) {
 // Cofactor vectors of the local-energy derivatives:
 //   Yt_up[i][mu] = sum_j A[j][i] P_dn[j][mu]   (= (Lambda Phi_dn^T W^{-1})[mu][i])
 //   Yt_dn[j][nu] = sum_i A[j][i] P_up[i][nu]   (= (W^{-1} Phi_up Lambda)[j][nu])
-// so that grad_i det/det = grad psi(r_i) . Yt[i] for every electron i.
-// FP64 path only: A (FP64) times P (FP64).
-hipError_t launch_Y_build(const SysDev& s, const WalkDev& w, hipStream_t st) {
+// so that grad_i det/det = grad psi(r_i) . Yt[i] for every electron i.  Always
+// FP64 arithmetic: A is FP64 and P (FP64 or FP32 storage) is promoted exactly.
+template <typename T>
+static hipError_t Y_build_t(const SysDev& s, const WalkDev& w, hipStream_t st) {
   const long rowst = (long)s.N * s.Lp;
   hipError_t e;
-  if (s.precision == QMC_W_FP32) {
-    // P is FP32: promote on the fly by running the FP64 kernel on an FP64 copy
-    // is avoided; instead the FP32 rows are read by the mixed kernel below.
-    return hipErrorNotSupported;
-  }
   {
     GemmArgs g = plain(s.nu, s.Lp, s.nd);
     g.A = w.A; g.lda = s.nu; g.a_bs = (long)s.nd * s.nu;
-    g.B = (const double*)w.P + (long)s.nu * s.Lp; g.ldb = s.Lp; g.b_bs = rowst;
+    g.B = (const T*)w.P + (long)s.nu * s.Lp; g.ldb = s.Lp; g.b_bs = rowst;
     g.C = w.Yt; g.ldc = s.Lp; g.c_bs = rowst;
     g.batch = w.Wk;
-    e = run_gemm<32, 64, true, false, double, double>(g, st);
+    e = run_gemm<32, 64, true, false, double, T, double, double>(g, st);
     if (e != hipSuccess) return e;
   }
   {
     GemmArgs g = plain(s.nd, s.Lp, s.nu);
     g.A = w.A; g.lda = s.nu; g.a_bs = (long)s.nd * s.nu;
-    g.B = (const double*)w.P; g.ldb = s.Lp; g.b_bs = rowst;
+    g.B = (const T*)w.P; g.ldb = s.Lp; g.b_bs = rowst;
     g.C = w.Yt + (long)s.nu * s.Lp; g.ldc = s.Lp; g.c_bs = rowst;
     g.batch = w.Wk;
-    e = run_gemm<32, 64, false, false, double, double>(g, st);
+    e = run_gemm<32, 64, false, false, double, T, double, double>(g, st);
   }
   return e;
+}
+
+hipError_t launch_Y_build(const SysDev& s, const WalkDev& w, hipStream_t st) {
+  if (s.precision == QMC_W_FP32) return Y_build_t<float>(s, w, st);
+  return Y_build_t<double>(s, w, st);
 }
 
 }  // namespace qmc

@@ -16,6 +16,7 @@ namespace qmc {
 // ---------------------------------------------------------------------------
 constexpr int kMaxNuc = 4096;
 constexpr int kLuMaxN = 128;      // LDS-resident Gauss-Jordan inverse limit
+constexpr int kPropRows = 16;     // rows of P per proposal workgroup
 
 inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
@@ -54,13 +55,17 @@ struct WalkDev {
   double* sign;     // [Wk]
   double* J;        // [Wk] Jastrow exponent tracked through moves
   // pending proposal
-  double* psi_new;  // [Wk][Lp] basis values at r'
+  double* psi_new;  // [Wk][Lp] basis values at r' (zero-padded)
   double* w_new;    // [Wk][nmax] new row (up) or column (down) of W
   double* rdet;     // [Wk]
   double* dJ;       // [Wk]
   double* r_new;    // [Wk][3]
-  double* ratio;    // [Wk] scratch for the device Metropolis loop
+  double* ratio;    // [Wk] ratio of the pending proposal
   uint8_t* acc;     // [Wk]
+  double* rdet_part;  // [Wk][S] partial determinant ratios (one per proposal block)
+  double* gdet_part;  // [Wk][S][3] partial gradients (drift at r')
+  double* gJ_new;     // [Wk][3] Jastrow gradient at r'
+  double* gpsi_new;   // [Wk][3][Lp] basis gradients at r' (drift requests)
 };
 
 // ---------------------------------------------------------------------------
@@ -201,8 +206,13 @@ hipError_t launch_rowdots(const SysDev& s, const WalkDev& w, hipStream_t st);
 hipError_t launch_jastrow_assemble(const SysDev& s, const WalkDev& w, double* logabs, double* sign,
                                    double* drift, double* e_kin, double* e_loc, int32_t* status,
                                    hipStream_t st);
-hipError_t launch_propose(const SysDev& s, const WalkDev& w, int e, const double* r_new,
-                          const double* disp, double* ratio, double* drift_new, hipStream_t st);
+int propose_splits(const SysDev& s);
+// Proposal in two launches: per-walker psi(r') and Jastrow change, then the
+// streaming row kernel (and, when finalize, the ratio sum).
+hipError_t launch_propose_prep(const SysDev& s, const WalkDev& w, int e, const double* r_new,
+                               const double* disp, bool drift, hipStream_t st);
+hipError_t launch_propose_rows(const SysDev& s, const WalkDev& w, int e, double* ratio,
+                               double* drift_new, bool finalize, hipStream_t st);
 hipError_t launch_metropolis_accept(const SysDev& s, const WalkDev& w, int e, const double* unif,
                                     int32_t* accept_count, hipStream_t st);
 hipError_t launch_accept(const SysDev& s, const WalkDev& w, int e, const uint8_t* acc,

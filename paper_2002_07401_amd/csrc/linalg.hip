@@ -32,6 +32,8 @@ gj_inverse_kernel(const double* __restrict__ Wg, double* __restrict__ Ag, double
 
   for (int idx = tid; idx < n * n; idx += blockDim.x) M[(idx / n) * ld + (idx % n)] = W[idx];
 
+  // fixed thread -> (column jc, row group g) map for the elimination update
+  const int G = blockDim.x / n, jc = tid % n, g = tid / n;
   double lsum = 0.0, sg = 1.0;
   int sing = 0;
   for (int k = 0; k < n; ++k) {
@@ -72,13 +74,15 @@ gj_inverse_kernel(const double* __restrict__ Wg, double* __restrict__ Ag, double
       ck[j] = M[j * ld + k];
     }
     __syncthreads();
-    for (int idx = tid; idx < n * n; idx += blockDim.x) {
-      const int i = idx / n, j = idx - (idx / n) * n;
-      double v;
-      if (i == k) v = rk[j];
-      else if (j == k) v = -ck[i] * rk[k];
-      else v = M[i * ld + j] - ck[i] * rk[j];
-      M[i * ld + j] = v;
+    if (g < G) {
+      const double rj = rk[jc];
+      for (int i = g; i < n; i += G) {
+        double v;
+        if (i == k) v = rj;
+        else if (jc == k) v = -ck[i] * rk[k];
+        else v = M[i * ld + jc] - ck[i] * rj;
+        M[i * ld + jc] = v;
+      }
     }
   }
   __syncthreads();
@@ -105,7 +109,160 @@ gj_inverse_kernel(const double* __restrict__ Wg, double* __restrict__ Ag, double
   }
 }
 
+// Register-resident variant (the default).  Thread t keeps column c = t % n of
+// rows g, g + G, g + 2G, ... (g = t / n, G = blockDim / n) in registers.  Rows
+// are never swapped: step k pivots in place on (p_k, k), p_k the unused row
+// with the largest |T[p][k]| (lowest index on ties), with the same update as
+// above.  In-place Gauss-Jordan on the pivots (p_k, k) leaves
+//   W^{-1}[k][p_k'] = T[p_k][k']   and   det W = sgn(p) prod_k T_k[p_k][k],
+// sgn(p) the parity of the permutation k -> p_k.
+template <int QMAX>
+__global__ void __launch_bounds__(256)
+gj_inverse_reg_kernel(const double* __restrict__ Wg, double* __restrict__ Ag, double* __restrict__ logdet,
+                      double* __restrict__ detsign, int* __restrict__ singular, int n, long w_bs, long a_bs) {
+  __shared__ double rk[kLuMaxN];
+  __shared__ double ck[kLuMaxN];
+  __shared__ int used[kLuMaxN];
+  __shared__ int prow[kLuMaxN];
+  __shared__ int invp[kLuMaxN];
+  __shared__ double cand_v[256];
+  __shared__ int cand_i[256];
+  __shared__ double piv_s;
+  __shared__ int p_s;
+  const int tid = threadIdx.x;
+  const int G = blockDim.x / n, c = tid % n, g = tid / n;
+  const bool own = g < G;
+  const double* W = Wg + blockIdx.x * w_bs;
+  double* A = Ag + blockIdx.x * a_bs;
+  double a[QMAX];
+#pragma unroll
+  for (int q = 0; q < QMAX; ++q) {
+    const int i = g + G * q;
+    a[q] = (own && i < n) ? W[(long)i * n + c] : 0.0;
+  }
+  for (int i = tid; i < n; i += blockDim.x) used[i] = 0;
+  double lsum = 0.0, sg = 1.0;
+  int sing = 0;
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    if (own && c == k) {
+      double best = -1.0, bv = 0.0;
+      int bi = n;
+#pragma unroll
+      for (int q = 0; q < QMAX; ++q) {
+        const int i = g + G * q;
+        if (i < n && !used[i]) {
+          const double v = fabs(a[q]);
+          if (v > best) { best = v; bi = i; bv = a[q]; }
+        }
+      }
+      cand_v[g] = bv;
+      cand_i[g] = bi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double best = -1.0, bv = 0.0;
+      int bi = n;
+      for (int q = 0; q < G; ++q) {
+        const int i = cand_i[q];
+        if (i >= n) continue;
+        const double v = fabs(cand_v[q]);
+        if (v > best || (v == best && i < bi)) { best = v; bi = i; bv = cand_v[q]; }
+      }
+      p_s = bi;
+      piv_s = bv;
+      if (bi < n) { prow[k] = bi; used[bi] = 1; invp[bi] = k; }
+    }
+    __syncthreads();
+    const int p = p_s;
+    const double piv = piv_s;
+    if (p >= n || !(piv != 0.0)) { sing = 1; break; }   // uniform across the block
+    lsum += log(fabs(piv));
+    if (piv < 0.0) sg = -sg;
+    const double inv = 1.0 / piv;
+    if (own && g == p % G) {
+      const int qp = p / G;
+      double v = 0.0;
+#pragma unroll
+      for (int q = 0; q < QMAX; ++q) if (q == qp) v = a[q];
+      rk[c] = (c == k) ? inv : v * inv;
+    }
+    if (own && c == k) {
+#pragma unroll
+      for (int q = 0; q < QMAX; ++q) {
+        const int i = g + G * q;
+        if (i < n) ck[i] = a[q];
+      }
+    }
+    __syncthreads();
+    if (own) {
+      const double rc = rk[c], rkk = rk[k];
+#pragma unroll
+      for (int q = 0; q < QMAX; ++q) {
+        const int i = g + G * q;
+        if (i < n) {
+          if (i == p) a[q] = rc;
+          else if (c == k) a[q] = -ck[i] * rkk;
+          else a[q] -= ck[i] * rc;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (!sing) {
+    // parity of k -> prow[k]
+    if (tid == 0) {
+      int* visited = cand_i;
+      for (int i = 0; i < n; ++i) visited[i] = 0;
+      for (int i = 0; i < n; ++i) {
+        if (visited[i]) continue;
+        int len = 0, j = i;
+        while (!visited[j]) { visited[j] = 1; j = prow[j]; ++len; }
+        if ((len & 1) == 0) sg = -sg;
+      }
+      piv_s = sg;
+    }
+    __syncthreads();
+    sg = piv_s;
+    if (own) {
+      const int col = prow[c];
+#pragma unroll
+      for (int q = 0; q < QMAX; ++q) {
+        const int i = g + G * q;
+        if (i < n) A[(long)invp[i] * n + col] = a[q];
+      }
+    }
+  } else {
+    const double nanv = __longlong_as_double(0x7ff8000000000000LL);
+    for (int idx = tid; idx < n * n; idx += blockDim.x) A[idx] = nanv;
+  }
+  if (tid == 0) {
+    logdet[blockIdx.x] = sing ? -__builtin_inf() : lsum;
+    detsign[blockIdx.x] = sing ? 0.0 : sg;
+    singular[blockIdx.x] = sing;
+  }
+}
+
+hipError_t launch_lu_inverse_lds(const SysDev& s, const WalkDev& w, hipStream_t st);
+
 hipError_t launch_lu_inverse(const SysDev& s, const WalkDev& w, hipStream_t st) {
+  const int n = s.nu;
+  if (n > kLuMaxN) return hipErrorNotSupported;
+  const int G = 256 / n, Q = (n + G - 1) / G;
+  const long wbs = (long)s.nu * s.nd, abs_ = (long)s.nd * s.nu;
+  // registers pay off only while the column slices stay short (high occupancy)
+  if (Q > 8) return launch_lu_inverse_lds(s, w, st);
+#define QMC_LU_REG(QM)                                                                              \
+  hipLaunchKernelGGL(gj_inverse_reg_kernel<QM>, dim3(w.Wk), dim3(256), 0, st, w.W, w.A, w.logdet, \
+                     w.detsign, w.singular, n, wbs, abs_)
+  if (Q <= 4) QMC_LU_REG(4);
+  else QMC_LU_REG(8);
+#undef QMC_LU_REG
+  return hipGetLastError();
+}
+
+// LDS variant with physical row swaps, kept for cross-checking the register kernel.
+hipError_t launch_lu_inverse_lds(const SysDev& s, const WalkDev& w, hipStream_t st) {
   const int n = s.nu;
   if (n > kLuMaxN) return hipErrorNotSupported;
   const size_t shm = ((size_t)n * (n + 1) + 2 * (size_t)n) * sizeof(double);

@@ -11,6 +11,14 @@
 // accumulated in FP64 whatever the storage precision of P.  The Jastrow
 // factor contributes exp(J(x') - J(x)) over the N_at + N - 1 terms that
 // involve the moved electron.
+//
+// The proposal streams the N/2 x L block of P of the other spin for every
+// walker: it is bound by HBM bandwidth.  A small per-walker kernel first
+// computes psi(r') and the Jastrow change; the streaming kernel then splits
+// each walker's rows over several workgroups (kPropRows rows each) so that
+// many blocks are in flight, and every block writes a partial determinant
+// ratio, which the accept kernel (device Metropolis) or the finalize kernel
+// (host-driven moves) sums in a fixed order.
 #include "internal.h"
 
 namespace qmc {
@@ -27,7 +35,8 @@ __device__ double block_sum_mv(double v, double* red) {
   return t;
 }
 
-// Jastrow terms of electron e at position p: value and gradient (in g).
+// Jastrow terms of electron e at position p, summed over this thread's share
+// of nuclei and electrons: value and gradient.
 __device__ void jastrow_one(const SysDev& s, const double* r, int e, double px, double py, double pz,
                             bool want_grad, double& val, double& gx, double& gy, double& gz) {
   val = 0.0; gx = gy = gz = 0.0;
@@ -55,46 +64,158 @@ __device__ void jastrow_one(const SysDev& s, const double* r, int e, double px, 
   }
 }
 
-template <typename T, bool DRIFT>
+// Step 1 of a proposal, one workgroup per walker: the new position, the basis
+// values psi(r') (zero-padded to Lp, and their gradients when a drift is
+// requested) and the Jastrow change J(x') - J(x) (and grad J at r').
+template <bool DRIFT>
 __global__ void __launch_bounds__(256)
-propose_kernel(SysDev s, WalkDev w, int e, const double* __restrict__ r_new_in,
-               const double* __restrict__ disp, double* __restrict__ ratio_o,
-               double* __restrict__ drift_o) {
-  extern __shared__ double sm[];
-  double* psi = sm;                          // [L]
-  double* gpsi = psi + s.Lp;                 // [3][L] when DRIFT
-  const int nmax = s.nu > s.nd ? s.nu : s.nd;
-  double* wn = gpsi + (DRIFT ? 3 * s.Lp : 0); // [nmax]
-  double* gwn = wn + nmax;                    // [3][nmax] when DRIFT
+propose_prep_kernel(SysDev s, WalkDev w, int e, const double* __restrict__ r_new_in,
+                    const double* __restrict__ disp) {
   __shared__ double red[8];
   __shared__ double rn[3];
-  const int wk = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wk = blockIdx.x, tid = threadIdx.x;
   const double* r = w.r + (long)wk * s.N * 3;
-  if (tid < 3) rn[tid] = disp ? r[3 * e + tid] + disp[3 * (long)wk + tid] : r_new_in[3 * (long)wk + tid];
+  if (tid < 3) {
+    rn[tid] = disp ? r[3 * e + tid] + disp[3 * (long)wk + tid] : r_new_in[3 * (long)wk + tid];
+    w.r_new[3 * wk + tid] = rn[tid];
+  }
   __syncthreads();
   const double px = rn[0], py = rn[1], pz = rn[2];
-  double* psi_g = w.psi_new + (long)wk * s.Lp;
-  for (int mu = tid; mu < s.L; mu += blockDim.x) {
-    if (DRIFT) {
+  double* psi = w.psi_new + (long)wk * s.Lp;
+  double* gpsi = w.gpsi_new + (long)wk * 3 * s.Lp;
+  for (int mu = tid; mu < s.Lp; mu += blockDim.x) {
+    if (mu >= s.L) {
+      psi[mu] = 0.0;
+      if (DRIFT) { gpsi[mu] = 0.0; gpsi[s.Lp + mu] = 0.0; gpsi[2 * s.Lp + mu] = 0.0; }
+    } else if (DRIFT) {
       double v, gx, gy, gz, lp;
       basis_vgl(s, mu, px, py, pz, v, gx, gy, gz, lp);
       psi[mu] = v; gpsi[mu] = gx; gpsi[s.Lp + mu] = gy; gpsi[2 * s.Lp + mu] = gz;
-      psi_g[mu] = v;
     } else {
-      const double v = basis_value(s, mu, px, py, pz);
-      psi[mu] = v;
-      psi_g[mu] = v;
+      psi[mu] = basis_value(s, mu, px, py, pz);
     }
   }
+  double jn, gxn, gyn, gzn, jo, d0, d1, d2;
+  jastrow_one(s, r, e, px, py, pz, DRIFT, jn, gxn, gyn, gzn);
+  jastrow_one(s, r, e, r[3 * e], r[3 * e + 1], r[3 * e + 2], false, jo, d0, d1, d2);
+  const double dJ = block_sum_mv(jn - jo, red);
+  if (DRIFT) {
+    gxn = block_sum_mv(gxn, red); gyn = block_sum_mv(gyn, red); gzn = block_sum_mv(gzn, red);
+  }
+  if (tid == 0) {
+    w.dJ[wk] = dJ;
+    if (DRIFT) { w.gJ_new[3 * wk] = gxn; w.gJ_new[3 * wk + 1] = gyn; w.gJ_new[3 * wk + 2] = gzn; }
+  }
+}
+
+template <typename T> struct Vec16;
+template <> struct Vec16<double> { typedef double2 type; static constexpr int n = 2; };
+template <> struct Vec16<float> { typedef float4 type; static constexpr int n = 4; };
+
+__device__ __forceinline__ double vget(const double2& v, int i) { return i == 0 ? v.x : v.y; }
+__device__ __forceinline__ double vget(const float4& v, int i) {
+  return (double)(i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w)));
+}
+
+// Combine the per-wave (lane 0) partial ratios of one block into rdet_part.
+__device__ __forceinline__ void block_partial(double part, double gx, double gy, double gz, bool drift,
+                                              WalkDev& w, int wk, int S, int sb) {
+  __shared__ double red[16];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if (lane == 0) {
+    red[wave] = part;
+    if (drift) { red[4 + wave] = gx; red[8 + wave] = gy; red[12 + wave] = gz; }
+  }
   __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0, tx = 0.0, ty = 0.0, tz = 0.0;
+    for (int k = 0; k < nw; ++k) {
+      t += red[k];
+      if (drift) { tx += red[4 + k]; ty += red[8 + k]; tz += red[12 + k]; }
+    }
+    w.rdet_part[(long)wk * S + sb] = t;
+    if (drift) {
+      double* g = w.gdet_part + ((long)wk * S + sb) * 3;
+      g[0] = tx; g[1] = ty; g[2] = tz;
+    }
+  }
+}
+
+// Step 2, streaming kernel: block (sb, wk) computes the new W entries of rows
+// [sb*kPropRows, (sb+1)*kPropRows) of the opposite spin of walker wk and their
+// contribution to the determinant ratio.  One wave per row; psi(r') chunks sit
+// in registers and each row is read with NC independent 16-byte loads per lane.
+template <typename T, int NC>
+__global__ void __launch_bounds__(256)
+propose_rows_kernel(SysDev s, WalkDev w, int e) {
+  typedef typename Vec16<T>::type V;
+  constexpr int VN = Vec16<T>::n;
+  constexpr int STEP = 64 * VN;
+  const int sb = blockIdx.x, wk = blockIdx.y, S = gridDim.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
   const bool up = e < s.nu;
   const int row0 = up ? s.nu : 0;
   const int nrow = up ? s.nd : s.nu;
+  const int nmax = s.nu > s.nd ? s.nu : s.nd;
   const T* Pw = (const T*)w.P + ((long)wk * s.N + row0) * s.Lp;
-  for (int j = wave; j < nrow; j += 4) {
+  const double* Aw = w.A + (long)wk * s.nd * s.nu;
+  double* wn_g = w.w_new + (long)wk * nmax;
+  const double* psi = w.psi_new + (long)wk * s.Lp;
+  double ps[NC][VN];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const int i0 = c * STEP + lane * VN;
+#pragma unroll
+    for (int v = 0; v < VN; ++v) ps[c][v] = (i0 < s.Lp) ? psi[i0 + v] : 0.0;
+  }
+  const int j0 = sb * kPropRows;
+  const int j1 = min(j0 + kPropRows, nrow);
+  double part = 0.0;
+  for (int j = j0 + wave; j < j1; j += nw) {
+    const T* prow = Pw + (long)j * s.Lp;
+    V pv[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int i0 = c * STEP + lane * VN;
+      if (i0 < s.Lp) pv[c] = *reinterpret_cast<const V*>(prow + i0);
+      else pv[c] = V{};
+    }
+    double acc = 0.0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int v = 0; v < VN; ++v) acc += vget(pv[c], v) * ps[c][v];
+    acc = wave_sum(acc);
+    if (lane == 0) {
+      wn_g[j] = acc;
+      part += acc * (up ? Aw[(long)j * s.nu + e] : Aw[(long)(e - s.nu) * s.nu + j]);
+    }
+  }
+  block_partial(part, 0.0, 0.0, 0.0, false, w, wk, S, sb);
+}
+
+// Generic streaming kernel (any Lp; optional gradients for the drift at r').
+template <typename T, bool DRIFT>
+__global__ void __launch_bounds__(256)
+propose_rows_generic_kernel(SysDev s, WalkDev w, int e) {
+  const int sb = blockIdx.x, wk = blockIdx.y, S = gridDim.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  const bool up = e < s.nu;
+  const int row0 = up ? s.nu : 0;
+  const int nrow = up ? s.nd : s.nu;
+  const int nmax = s.nu > s.nd ? s.nu : s.nd;
+  const T* Pw = (const T*)w.P + ((long)wk * s.N + row0) * s.Lp;
+  const double* Aw = w.A + (long)wk * s.nd * s.nu;
+  double* wn_g = w.w_new + (long)wk * nmax;
+  const double* psi = w.psi_new + (long)wk * s.Lp;
+  const double* gpsi = w.gpsi_new + (long)wk * 3 * s.Lp;
+  const int j0 = sb * kPropRows;
+  const int j1 = min(j0 + kPropRows, nrow);
+  double part = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+  for (int j = j0 + wave; j < j1; j += nw) {
     const T* prow = Pw + (long)j * s.Lp;
     double a0 = 0.0, ax = 0.0, ay = 0.0, az = 0.0;
-    for (int mu = lane; mu < s.L; mu += 64) {
+    for (int mu = lane; mu < s.Lp; mu += 64) {
       const double p = (double)prow[mu];
       a0 += p * psi[mu];
       if (DRIFT) { ax += p * gpsi[mu]; ay += p * gpsi[s.Lp + mu]; az += p * gpsi[2 * s.Lp + mu]; }
@@ -102,60 +223,77 @@ propose_kernel(SysDev s, WalkDev w, int e, const double* __restrict__ r_new_in,
     a0 = wave_sum(a0);
     if (DRIFT) { ax = wave_sum(ax); ay = wave_sum(ay); az = wave_sum(az); }
     if (lane == 0) {
-      wn[j] = a0;
-      if (DRIFT) { gwn[j] = ax; gwn[nmax + j] = ay; gwn[2 * nmax + j] = az; }
+      wn_g[j] = a0;
+      const double a = up ? Aw[(long)j * s.nu + e] : Aw[(long)(e - s.nu) * s.nu + j];
+      part += a0 * a;
+      if (DRIFT) { gx += ax * a; gy += ay * a; gz += az * a; }
     }
   }
-  __syncthreads();
-  const double* Aw = w.A + (long)wk * s.nd * s.nu;
-  double part = 0.0, pgx = 0.0, pgy = 0.0, pgz = 0.0;
-  for (int j = tid; j < nrow; j += blockDim.x) {
-    const double a = up ? Aw[(long)j * s.nu + e] : Aw[(long)(e - s.nu) * s.nu + j];
-    part += wn[j] * a;
-    if (DRIFT) { pgx += gwn[j] * a; pgy += gwn[nmax + j] * a; pgz += gwn[2 * nmax + j] * a; }
-  }
-  const double rdet = block_sum_mv(part, red);
-  double jn, gxn, gyn, gzn, jo, d0, d1, d2;
-  jastrow_one(s, r, e, px, py, pz, DRIFT, jn, gxn, gyn, gzn);
-  jastrow_one(s, r, e, r[3 * e], r[3 * e + 1], r[3 * e + 2], false, jo, d0, d1, d2);
-  const double dJ = block_sum_mv(jn - jo, red);
-  double Gx = 0.0, Gy = 0.0, Gz = 0.0, Jx = 0.0, Jy = 0.0, Jz = 0.0;
-  if (DRIFT) {
-    Gx = block_sum_mv(pgx, red); Gy = block_sum_mv(pgy, red); Gz = block_sum_mv(pgz, red);
-    Jx = block_sum_mv(gxn, red); Jy = block_sum_mv(gyn, red); Jz = block_sum_mv(gzn, red);
-  }
-  double* wn_g = w.w_new + (long)wk * nmax;
-  for (int j = tid; j < nrow; j += blockDim.x) wn_g[j] = wn[j];
-  if (tid == 0) {
-    const double ratio = rdet * exp(dJ);
-    w.rdet[wk] = rdet;
-    w.dJ[wk] = dJ;
-    w.ratio[wk] = ratio;
-    w.r_new[3 * wk] = px; w.r_new[3 * wk + 1] = py; w.r_new[3 * wk + 2] = pz;
-    if (ratio_o) ratio_o[wk] = ratio;
-    if (DRIFT && drift_o) {
-      // grad of log|det| for the moved electron at r' uses the updated inverse,
-      // whose column e equals the old one divided by the determinant ratio
-      drift_o[3 * wk] = Gx / rdet + Jx;
-      drift_o[3 * wk + 1] = Gy / rdet + Jy;
-      drift_o[3 * wk + 2] = Gz / rdet + Jz;
-    }
+  block_partial(part, gx, gy, gz, DRIFT, w, wk, S, sb);
+}
+
+// Sum the partial ratios (fixed order) for host-driven proposals.
+__global__ void propose_finalize_kernel(WalkDev w, int S, double* __restrict__ ratio_o,
+                                        double* __restrict__ drift_o) {
+  const int wk = blockIdx.x * blockDim.x + threadIdx.x;
+  if (wk >= w.Wk) return;
+  double R = 0.0;
+  for (int k = 0; k < S; ++k) R += w.rdet_part[(long)wk * S + k];
+  const double ratio = R * exp(w.dJ[wk]);
+  w.rdet[wk] = R;
+  w.ratio[wk] = ratio;
+  if (ratio_o) ratio_o[wk] = ratio;
+  if (drift_o) {
+    // grad log|det| of the moved electron at r' uses the updated inverse, whose
+    // column (row) e equals the old one divided by the determinant ratio
+    double g[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < S; ++k)
+      for (int c = 0; c < 3; ++c) g[c] += w.gdet_part[((long)wk * S + k) * 3 + c];
+    for (int c = 0; c < 3; ++c) drift_o[3 * wk + c] = g[c] / R + w.gJ_new[3 * wk + c];
   }
 }
 
-hipError_t launch_propose(const SysDev& s, const WalkDev& w, int e, const double* r_new,
-                          const double* disp, double* ratio, double* drift_new, hipStream_t st) {
+int propose_splits(const SysDev& s) {
   const int nmax = s.nu > s.nd ? s.nu : s.nd;
+  return (nmax + kPropRows - 1) / kPropRows;
+}
+
+hipError_t launch_propose_prep(const SysDev& s, const WalkDev& w, int e, const double* r_new,
+                               const double* disp, bool drift, hipStream_t st) {
+  if (drift)
+    hipLaunchKernelGGL(propose_prep_kernel<true>, dim3(w.Wk), dim3(256), 0, st, s, w, e, r_new, disp);
+  else
+    hipLaunchKernelGGL(propose_prep_kernel<false>, dim3(w.Wk), dim3(256), 0, st, s, w, e, r_new, disp);
+  return hipGetLastError();
+}
+
+hipError_t launch_propose_rows(const SysDev& s, const WalkDev& w, int e, double* ratio,
+                               double* drift_new, bool finalize, hipStream_t st) {
   const bool drift = drift_new != nullptr;
-  const size_t shm = sizeof(double) * ((drift ? 4 : 1) * (size_t)s.Lp + (drift ? 4 : 1) * (size_t)nmax);
+  const int S = propose_splits(s);
+  const dim3 grid(S, w.Wk);
   const bool f32 = s.precision == QMC_W_FP32;
+  hipError_t err;
+  const int chunks = (s.Lp + (f32 ? 255 : 127)) / (f32 ? 256 : 128);
   if (drift) {
-    if (f32) hipLaunchKernelGGL((propose_kernel<float, true>), dim3(w.Wk), dim3(256), shm, st, s, w, e, r_new, disp, ratio, drift_new);
-    else hipLaunchKernelGGL((propose_kernel<double, true>), dim3(w.Wk), dim3(256), shm, st, s, w, e, r_new, disp, ratio, drift_new);
+    if (f32) hipLaunchKernelGGL((propose_rows_generic_kernel<float, true>), grid, dim3(256), 0, st, s, w, e);
+    else hipLaunchKernelGGL((propose_rows_generic_kernel<double, true>), grid, dim3(256), 0, st, s, w, e);
+  } else if (chunks <= 8) {
+#define QMC_ROWS(T, NC) hipLaunchKernelGGL((propose_rows_kernel<T, NC>), grid, dim3(256), 0, st, s, w, e)
+    if (f32) {
+      if (chunks <= 2) QMC_ROWS(float, 2); else if (chunks <= 4) QMC_ROWS(float, 4); else QMC_ROWS(float, 8);
+    } else {
+      if (chunks <= 2) QMC_ROWS(double, 2); else if (chunks <= 4) QMC_ROWS(double, 4); else QMC_ROWS(double, 8);
+    }
+#undef QMC_ROWS
   } else {
-    if (f32) hipLaunchKernelGGL((propose_kernel<float, false>), dim3(w.Wk), dim3(256), shm, st, s, w, e, r_new, disp, ratio, drift_new);
-    else hipLaunchKernelGGL((propose_kernel<double, false>), dim3(w.Wk), dim3(256), shm, st, s, w, e, r_new, disp, ratio, drift_new);
+    if (f32) hipLaunchKernelGGL((propose_rows_generic_kernel<float, false>), grid, dim3(256), 0, st, s, w, e);
+    else hipLaunchKernelGGL((propose_rows_generic_kernel<double, false>), grid, dim3(256), 0, st, s, w, e);
   }
+  err = hipGetLastError();
+  if (err != hipSuccess || !finalize) return err;
+  hipLaunchKernelGGL(propose_finalize_kernel, dim3((w.Wk + 255) / 256), dim3(256), 0, st, w, S, ratio,
+                     drift_new);
   return hipGetLastError();
 }
 
@@ -164,69 +302,121 @@ hipError_t launch_propose(const SysDev& s, const WalkDev& w, int e, const double
 // apply the rank-1 Sherman-Morrison update of A = W^{-1} in FP64:
 //   up e   (row e of W replaced by w'):    A <- A - A[:,e] (delta^T A) / R
 //   down e (column e of W replaced by w'): A <- A - (A delta) A[e,:] / R
-// with delta = w' - (old row/column) and R = det W'/det W.
+// with delta = w' - (old row/column) and R = det W'/det W.  Thread t holds
+// column c = t % n of rows g, g+G, ... (g = t / n, G = blockDim / n) in
+// registers: A is read once and written once.  Column sums (up moves) reduce
+// through LDS over the G groups; row sums (down moves) are wave dot products
+// over the rows (served from cache, the rows having just been read).
+// S > 0: the ratio is first summed from the proposal's S partial sums.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int QMAX>
 __global__ void __launch_bounds__(256)
 accept_kernel(SysDev s, WalkDev w, int e, const uint8_t* __restrict__ acc_in,
-              const double* __restrict__ unif, int32_t* __restrict__ accept_count) {
-  extern __shared__ double sm[];
-  const int nmax = s.nu > s.nd ? s.nu : s.nd;
-  double* delta = sm;          // [nmax]
-  double* coef = delta + nmax; // [nmax]
-  double* save = coef + nmax;  // [nmax]
+              const double* __restrict__ unif, int32_t* __restrict__ accept_count, int S) {
+  __shared__ double delta[kLuMaxN];
+  __shared__ double save[kLuMaxN];
+  __shared__ double coef[kLuMaxN];
+  __shared__ double part[256];
+  __shared__ double R_s;
+  __shared__ int acc_s;
+  const int n = s.nu;             // square: n_up == n_dn
   const int wk = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  bool acc;
-  if (unif) {
-    const double q = w.ratio[wk];
-    acc = unif[wk] < q * q;
-  } else {
-    acc = acc_in[wk] != 0;
+  const int nw = blockDim.x >> 6;
+  if (tid == 0) {
+    double R;
+    if (S > 0) {
+      R = 0.0;
+      for (int k = 0; k < S; ++k) R += w.rdet_part[(long)wk * S + k];
+      w.rdet[wk] = R;
+      w.ratio[wk] = R * exp(w.dJ[wk]);
+    } else {
+      R = w.rdet[wk];
+    }
+    bool acc;
+    if (unif) {
+      const double q = w.ratio[wk];
+      acc = unif[wk] < q * q;
+    } else {
+      acc = acc_in[wk] != 0;
+    }
+    w.acc[wk] = acc ? 1 : 0;
+    R_s = R;
+    acc_s = acc;
   }
-  if (tid == 0) w.acc[wk] = acc ? 1 : 0;
-  if (!acc) return;
-  const double R = w.rdet[wk];
-  const double invR = 1.0 / R;
+  __syncthreads();
+  if (!acc_s) return;
+  const double invR = 1.0 / R_s;
   const bool up = e < s.nu;
-  double* Aw = w.A + (long)wk * s.nd * s.nu;
-  double* Ww = w.W + (long)wk * s.nu * s.nd;
-  const double* wn = w.w_new + (long)wk * nmax;
+  const int ed = e - s.nu;
+  double* Aw = w.A + (long)wk * n * n;
+  double* Ww = w.W + (long)wk * n * n;
+  const double* wn = w.w_new + (long)wk * n;
+  const int G = blockDim.x / n, c = tid % n, g = tid / n;
+  const bool own = g < G;
+  double a[QMAX];
+#pragma unroll
+  for (int q = 0; q < QMAX; ++q) {
+    const int j = g + G * q;
+    a[q] = (own && j < n) ? Aw[(long)j * n + c] : 0.0;
+  }
+  for (int j = tid; j < n; j += blockDim.x)
+    delta[j] = up ? wn[j] - Ww[(long)e * n + j] : wn[j] - Ww[(long)j * n + ed];
+  __syncthreads();
   if (up) {
-    for (int j = tid; j < s.nd; j += blockDim.x) {
-      delta[j] = wn[j] - Ww[(long)e * s.nd + j];
-      save[j] = Aw[(long)j * s.nu + e];
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < QMAX; ++q) {
+      const int j = g + G * q;
+      if (own && j < n) t += delta[j] * a[q];
+    }
+    if (own) part[g * n + c] = t;
+    if (own && c == e) {
+#pragma unroll
+      for (int q = 0; q < QMAX; ++q) {
+        const int j = g + G * q;
+        if (j < n) save[j] = a[q];
+      }
     }
     __syncthreads();
-    for (int k = tid; k < s.nu; k += blockDim.x) {
-      double t = 0.0;
-      for (int j = 0; j < s.nd; ++j) t += delta[j] * Aw[(long)j * s.nu + k];
-      coef[k] = t * invR;
+    for (int k = tid; k < n; k += blockDim.x) {
+      double u = 0.0;
+      for (int q = 0; q < G; ++q) u += part[q * n + k];
+      coef[k] = u * invR;
     }
     __syncthreads();
-    for (int idx = tid; idx < s.nd * s.nu; idx += blockDim.x) {
-      const int j = idx / s.nu, k = idx - (idx / s.nu) * s.nu;
-      Aw[idx] -= save[j] * coef[k];
+    if (own) {
+      const double ck = coef[c];
+#pragma unroll
+      for (int q = 0; q < QMAX; ++q) {
+        const int j = g + G * q;
+        if (j < n) Aw[(long)j * n + c] = a[q] - save[j] * ck;
+      }
     }
-    for (int j = tid; j < s.nd; j += blockDim.x) Ww[(long)e * s.nd + j] = wn[j];
+    for (int j = tid; j < n; j += blockDim.x) Ww[(long)e * n + j] = wn[j];
   } else {
-    const int ed = e - s.nu;
-    for (int i = tid; i < s.nu; i += blockDim.x) {
-      delta[i] = wn[i] - Ww[(long)i * s.nd + ed];
-      save[i] = Aw[(long)ed * s.nu + i];
-    }
-    __syncthreads();
-    for (int j = wave; j < s.nd; j += 4) {
+    for (int j = wave; j < n; j += nw) {
       double t = 0.0;
-      for (int i = lane; i < s.nu; i += 64) t += Aw[(long)j * s.nu + i] * delta[i];
+      for (int i = lane; i < n; i += 64) t += Aw[(long)j * n + i] * delta[i];
       t = wave_sum(t);
       if (lane == 0) coef[j] = t * invR;
     }
-    __syncthreads();
-    for (int idx = tid; idx < s.nd * s.nu; idx += blockDim.x) {
-      const int j = idx / s.nu, k = idx - (idx / s.nu) * s.nu;
-      Aw[idx] -= coef[j] * save[k];
+    if (own && g == ed % G) {
+      const int qe = ed / G;
+      double v = 0.0;
+#pragma unroll
+      for (int q = 0; q < QMAX; ++q) if (q == qe) v = a[q];
+      save[c] = v;
     }
-    for (int i = tid; i < s.nu; i += blockDim.x) Ww[(long)i * s.nd + ed] = wn[i];
+    __syncthreads();
+    if (own) {
+      const double sc = save[c];
+#pragma unroll
+      for (int q = 0; q < QMAX; ++q) {
+        const int j = g + G * q;
+        if (j < n) Aw[(long)j * n + c] = a[q] - coef[j] * sc;
+      }
+    }
+    for (int i = tid; i < n; i += blockDim.x) Ww[(long)i * n + ed] = wn[i];
   }
   T* prow = (T*)w.phi + ((long)wk * s.N + e) * s.Lp;
   const double* pn = w.psi_new + (long)wk * s.Lp;
@@ -235,33 +425,43 @@ accept_kernel(SysDev s, WalkDev w, int e, const uint8_t* __restrict__ acc_in,
     double* re = w.r + ((long)wk * s.N + e) * 3;
     re[0] = w.r_new[3 * wk]; re[1] = w.r_new[3 * wk + 1]; re[2] = w.r_new[3 * wk + 2];
     const double dJ = w.dJ[wk];
-    w.logabs[wk] += log(fabs(R)) + dJ;
-    if (R < 0.0) w.sign[wk] = -w.sign[wk];
+    w.logabs[wk] += log(fabs(R_s)) + dJ;
+    if (R_s < 0.0) w.sign[wk] = -w.sign[wk];
     w.J[wk] += dJ;
     if (accept_count) accept_count[wk] += 1;
   }
 }
 
-hipError_t launch_accept(const SysDev& s, const WalkDev& w, int e, const uint8_t* acc,
-                         hipStream_t st) {
-  const int nmax = s.nu > s.nd ? s.nu : s.nd;
-  const size_t shm = sizeof(double) * 3 * (size_t)nmax;
-  if (s.precision == QMC_W_FP32)
-    hipLaunchKernelGGL(accept_kernel<float>, dim3(w.Wk), dim3(256), shm, st, s, w, e, acc, nullptr, nullptr);
-  else
-    hipLaunchKernelGGL(accept_kernel<double>, dim3(w.Wk), dim3(256), shm, st, s, w, e, acc, nullptr, nullptr);
+template <typename T>
+static hipError_t accept_launch_t(const SysDev& s, const WalkDev& w, int e, const uint8_t* acc,
+                                  const double* unif, int32_t* accept_count, int S, hipStream_t st) {
+  const int n = s.nu;
+  const int G = 256 / n, Q = (n + G - 1) / G;
+#define QMC_ACC(QM) \
+  hipLaunchKernelGGL((accept_kernel<T, QM>), dim3(w.Wk), dim3(256), 0, st, s, w, e, acc, unif, accept_count, S)
+  if (Q <= 4) QMC_ACC(4);
+  else if (Q <= 8) QMC_ACC(8);
+  else if (Q <= 16) QMC_ACC(16);
+  else if (Q <= 32) QMC_ACC(32);
+  else QMC_ACC(64);
+#undef QMC_ACC
   return hipGetLastError();
+}
+
+static hipError_t accept_launch(const SysDev& s, const WalkDev& w, int e, const uint8_t* acc,
+                                const double* unif, int32_t* accept_count, int S, hipStream_t st) {
+  if (s.nu > kLuMaxN) return hipErrorNotSupported;
+  if (s.precision == QMC_W_FP32) return accept_launch_t<float>(s, w, e, acc, unif, accept_count, S, st);
+  return accept_launch_t<double>(s, w, e, acc, unif, accept_count, S, st);
+}
+
+hipError_t launch_accept(const SysDev& s, const WalkDev& w, int e, const uint8_t* acc, hipStream_t st) {
+  return accept_launch(s, w, e, acc, nullptr, nullptr, 0, st);
 }
 
 hipError_t launch_metropolis_accept(const SysDev& s, const WalkDev& w, int e, const double* unif,
                                     int32_t* accept_count, hipStream_t st) {
-  const int nmax = s.nu > s.nd ? s.nu : s.nd;
-  const size_t shm = sizeof(double) * 3 * (size_t)nmax;
-  if (s.precision == QMC_W_FP32)
-    hipLaunchKernelGGL(accept_kernel<float>, dim3(w.Wk), dim3(256), shm, st, s, w, e, nullptr, unif, accept_count);
-  else
-    hipLaunchKernelGGL(accept_kernel<double>, dim3(w.Wk), dim3(256), shm, st, s, w, e, nullptr, unif, accept_count);
-  return hipGetLastError();
+  return accept_launch(s, w, e, nullptr, unif, accept_count, propose_splits(s), st);
 }
 
 // After a refresh LU: log|Psi| = log|det W| + J, sign from the LU.

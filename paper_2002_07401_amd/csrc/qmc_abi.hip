@@ -45,6 +45,62 @@ struct qmc_system {
   }
 };
 
+// Event-pair timers for the kernels launched on behalf of one walker set.
+struct Timers {
+  bool on = false;
+  double ms[QMC_TIMER_COUNT] = {};
+  int64_t n[QMC_TIMER_COUNT] = {};
+  struct Pair { hipEvent_t a, b; int id; };
+  std::vector<Pair> pending;
+  std::vector<Pair> spare;
+  int open_id = -1;
+  hipEvent_t open_a = nullptr;
+
+  hipError_t fold() {   // wait for pending pairs and accumulate them
+    for (auto& p : pending) {
+      hipError_t e = hipEventSynchronize(p.b);
+      if (e != hipSuccess) return e;
+      float t = 0.f;
+      e = hipEventElapsedTime(&t, p.a, p.b);
+      if (e != hipSuccess) return e;
+      ms[p.id] += t;
+      n[p.id] += 1;
+      spare.push_back(p);
+    }
+    pending.clear();
+    return hipSuccess;
+  }
+  hipError_t begin(int id, hipStream_t st) {
+    if (!on) return hipSuccess;
+    if (pending.size() >= 2048) {
+      hipError_t e = fold();
+      if (e != hipSuccess) return e;
+    }
+    Pair p;
+    if (!spare.empty()) { p = spare.back(); spare.pop_back(); }
+    else {
+      hipError_t e = hipEventCreate(&p.a);
+      if (e == hipSuccess) e = hipEventCreate(&p.b);
+      if (e != hipSuccess) return e;
+    }
+    p.id = id;
+    open_id = id;
+    open_a = p.a;
+    pending.push_back(p);
+    return hipEventRecord(p.a, st);
+  }
+  hipError_t end(hipStream_t st) {
+    if (!on || open_id < 0) return hipSuccess;
+    open_id = -1;
+    return hipEventRecord(pending.back().b, st);
+  }
+  void destroy() {
+    (void)fold();
+    for (auto& p : spare) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+    spare.clear();
+  }
+};
+
 struct qmc_walkers {
   qmc_system* sys = nullptr;
   WalkDev d{};
@@ -53,10 +109,20 @@ struct qmc_walkers {
   long attempts = 0;
   bool evaluated = false;
   bool P_up_valid = false, P_dn_valid = false;
+  Timers tm;
   ~qmc_walkers() {
+    tm.destroy();
     for (void* p : allocs) (void)hipFree(p);
   }
 };
+
+// Launch `expr` between the begin/end events of timer `id` (when timing is on).
+#define TIMED(wk, id, st, expr, where)                    \
+  do {                                                    \
+    HIP_TRY((wk)->tm.begin((id), (st)), "timer begin");   \
+    HIP_TRY((expr), where);                               \
+    HIP_TRY((wk)->tm.end((st)), "timer end");             \
+  } while (0)
 
 extern "C" int32_t qmc_abi_version(void) { return QMC_ABI_VERSION; }
 
@@ -182,6 +248,11 @@ extern "C" qmc_status qmc_walkers_create(qmc_system* sys, int32_t n_walkers, qmc
   al((void**)&d.r_new, sizeof(double) * Wk * 3);
   al((void**)&d.ratio, sizeof(double) * Wk);
   al((void**)&d.acc, sizeof(uint8_t) * Wk);
+  const size_t S = propose_splits(s);
+  al((void**)&d.rdet_part, sizeof(double) * Wk * S);
+  al((void**)&d.gdet_part, sizeof(double) * Wk * S * 3);
+  al((void**)&d.gJ_new, sizeof(double) * Wk * 3);
+  al((void**)&d.gpsi_new, sizeof(double) * Wk * 3 * Lp);
   if (e != hipSuccess) {
     delete wk;
     return e == hipErrorOutOfMemory ? fail(QMC_ERR_OOM, "device allocation failed") : hip_fail(e, "walkers_create");
@@ -211,15 +282,15 @@ extern "C" qmc_status qmc_eval_batch(qmc_system* sys, qmc_walkers* wk, const dou
   if (!r) return fail(QMC_ERR_ARG, "null positions");
   const SysDev& s = sys->d;
   WalkDev& d = wk->d;
-  if (s.precision != QMC_FP64) return fail(QMC_ERR_UNSUPPORTED, "eval for this precision not built");
   HIP_TRY(hipMemcpyAsync(d.r, r, sizeof(double) * d.Wk * s.N * 3, hipMemcpyDeviceToDevice, stream), "copy r");
-  HIP_TRY(launch_basis_values(s, d, stream), "basis");
-  HIP_TRY(launch_P_build(s, d, 3, stream), "P build");
-  HIP_TRY(launch_W_build(s, d, stream), "W build");
-  HIP_TRY(launch_lu_inverse(s, d, stream), "LU");
-  HIP_TRY(launch_Y_build(s, d, stream), "Y build");
-  HIP_TRY(launch_rowdots(s, d, stream), "row dots");
-  HIP_TRY(launch_jastrow_assemble(s, d, logabs, sign, drift, e_kin, e_loc, status, stream), "assemble");
+  TIMED(wk, QMC_T_BASIS, stream, launch_basis_values(s, d, stream), "basis");
+  TIMED(wk, QMC_T_P_BUILD, stream, launch_P_build(s, d, 3, stream), "P build");
+  TIMED(wk, QMC_T_W_BUILD, stream, launch_W_build(s, d, stream), "W build");
+  TIMED(wk, QMC_T_LU, stream, launch_lu_inverse(s, d, stream), "LU");
+  TIMED(wk, QMC_T_Y_BUILD, stream, launch_Y_build(s, d, stream), "Y build");
+  TIMED(wk, QMC_T_ROWDOT, stream, launch_rowdots(s, d, stream), "row dots");
+  TIMED(wk, QMC_T_ASSEMBLE, stream,
+        launch_jastrow_assemble(s, d, logabs, sign, drift, e_kin, e_loc, status, stream), "assemble");
   wk->evaluated = true;
   wk->P_up_valid = wk->P_dn_valid = true;
   wk->attempts = 0;
@@ -232,10 +303,10 @@ static qmc_status ensure_P(qmc_walkers* wk, int e, hipStream_t stream) {
   const SysDev& s = wk->sys->d;
   const bool up = e < s.nu;
   if (up && !wk->P_dn_valid) {
-    HIP_TRY(launch_P_build(s, wk->d, 2, stream), "P_dn rebuild");
+    TIMED(wk, QMC_T_P_BUILD, stream, launch_P_build(s, wk->d, 2, stream), "P_dn rebuild");
     wk->P_dn_valid = true;
   } else if (!up && !wk->P_up_valid) {
-    HIP_TRY(launch_P_build(s, wk->d, 1, stream), "P_up rebuild");
+    TIMED(wk, QMC_T_P_BUILD, stream, launch_P_build(s, wk->d, 1, stream), "P_up rebuild");
     wk->P_up_valid = true;
   }
   return QMC_OK;
@@ -252,7 +323,10 @@ extern "C" qmc_status qmc_propose_move(qmc_system* sys, qmc_walkers* wk, int32_t
   if (!r_new) return fail(QMC_ERR_ARG, "null r_new");
   c = ensure_P(wk, electron, stream);
   if (c) return c;
-  HIP_TRY(launch_propose(s, wk->d, electron, r_new, nullptr, ratio, drift_new, stream), "propose");
+  TIMED(wk, QMC_T_PROPOSE_PREP, stream,
+        launch_propose_prep(s, wk->d, electron, r_new, nullptr, drift_new != nullptr, stream), "propose prep");
+  TIMED(wk, QMC_T_PROPOSE, stream, launch_propose_rows(s, wk->d, electron, ratio, drift_new, true, stream),
+        "propose rows");
   wk->pending_e = electron;
   return QMC_OK;
 }
@@ -263,8 +337,8 @@ static qmc_status after_accept(qmc_walkers* wk, int e, int32_t* status, hipStrea
   wk->pending_e = -1;
   wk->attempts += 1;
   if (wk->attempts % s.refresh_every == 0) {
-    HIP_TRY(launch_lu_inverse(s, wk->d, stream), "refresh LU");
-    HIP_TRY(launch_refresh_finish(s, wk->d, status, stream), "refresh finish");
+    TIMED(wk, QMC_T_LU, stream, launch_lu_inverse(s, wk->d, stream), "refresh LU");
+    TIMED(wk, QMC_T_OTHER, stream, launch_refresh_finish(s, wk->d, status, stream), "refresh finish");
   }
   return QMC_OK;
 }
@@ -276,7 +350,7 @@ extern "C" qmc_status qmc_accept_move(qmc_system* sys, qmc_walkers* wk, int32_t 
   if (!accept) return fail(QMC_ERR_ARG, "null accept");
   if (wk->pending_e < 0 || wk->pending_e != electron)
     return fail(QMC_ERR_STATE, "no pending proposal for this electron");
-  HIP_TRY(launch_accept(sys->d, wk->d, electron, accept, stream), "accept");
+  TIMED(wk, QMC_T_ACCEPT, stream, launch_accept(sys->d, wk->d, electron, accept, stream), "accept");
   return after_accept(wk, electron, status, stream);
 }
 
@@ -294,8 +368,12 @@ extern "C" qmc_status qmc_vmc_steps(qmc_system* sys, qmc_walkers* wk, int32_t e_
     const int e = (int)((e_start + (long)t) % s.N);
     c = ensure_P(wk, e, stream);
     if (c) return c;
-    HIP_TRY(launch_propose(s, wk->d, e, nullptr, disp + (long)t * Wk * 3, nullptr, nullptr, stream), "propose");
-    HIP_TRY(launch_metropolis_accept(s, wk->d, e, unif + (long)t * Wk, accept_count, stream), "metropolis");
+    TIMED(wk, QMC_T_PROPOSE_PREP, stream,
+          launch_propose_prep(s, wk->d, e, nullptr, disp + (long)t * Wk * 3, false, stream), "propose prep");
+    TIMED(wk, QMC_T_PROPOSE, stream, launch_propose_rows(s, wk->d, e, nullptr, nullptr, false, stream),
+          "propose rows");
+    TIMED(wk, QMC_T_ACCEPT, stream,
+          launch_metropolis_accept(s, wk->d, e, unif + (long)t * Wk, accept_count, stream), "metropolis");
     c = after_accept(wk, e, nullptr, stream);
     if (c) return c;
   }
@@ -321,5 +399,20 @@ extern "C" qmc_status qmc_walkers_read(qmc_walkers* wk, int32_t item, double* ds
     default: return fail(QMC_ERR_ARG, "unknown state item");
   }
   HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, stream), "read state");
+  return QMC_OK;
+}
+
+extern "C" qmc_status qmc_walkers_set_timing(qmc_walkers* wk, int32_t enable) {
+  if (!wk) return fail(QMC_ERR_ARG, "null walkers");
+  HIP_TRY(wk->tm.fold(), "timer fold");
+  for (int k = 0; k < QMC_TIMER_COUNT; ++k) { wk->tm.ms[k] = 0.0; wk->tm.n[k] = 0; }
+  wk->tm.on = enable != 0;
+  return QMC_OK;
+}
+
+extern "C" qmc_status qmc_walkers_timing(qmc_walkers* wk, double* ms, int64_t* launches) {
+  if (!wk || !ms || !launches) return fail(QMC_ERR_ARG, "null argument");
+  HIP_TRY(wk->tm.fold(), "timer fold");
+  for (int k = 0; k < QMC_TIMER_COUNT; ++k) { ms[k] = wk->tm.ms[k]; launches[k] = wk->tm.n[k]; }
   return QMC_OK;
 }

@@ -1,0 +1,144 @@
+"""Mixed-precision path (QMC_W_FP32): basis matrix, P = Phi Lambda and the W
+product in FP32 on MFMA with FP32 accumulation; LU, inverse, cofactor
+products, ratios and Sherman-Morrison updates in FP64.
+
+Two checks:
+
+* Forward-error bound (must hold).  With u = 2^-24 and gamma = (2L + 4) u
+  (rounding of Phi and Lambda to FP32, the two length-L FP32 accumulations and
+  the FP32 storage of P), every geminal entry obeys to first order
+      |dW| <= gamma |Phi_up| |Lambda| |Phi_dn|^T
+  and the derivative rows V = Q_up Lambda Phi_dn^T + Phi_up Lambda Q_dn^T
+  (Q = lap Phi + 2 grad Phi . grad J, whose trace against W^{-1} is the
+  determinant part of the kinetic energy) obey the same with |Q| in place of
+  |Phi|.  Hence, to first order,
+      |d log|det W||  <= sum |A^T| * |dW|
+      |d e_kin|       <= 1/2 ( sum |(A V A)^T| * |dW| + sum |A^T| * |dV| ).
+  The bounds are evaluated from the oracle's FP64 quantities.
+
+* The spec bar (relative 1e-6 on log|Psi| and E_loc after refinement)
+  is not met by FP32 products alone when W is ill-conditioned (condition
+  numbers of 1e5..1e6 in these workloads amplify u); it stays an expected
+  failure until a refinement stage is built.
+"""
+import pytest
+import torch
+
+from gpu_util import need_gpu, rel_err
+from oracle import jagp as O
+from workloads import configs as C
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu_eval(P, w):
+    sysh = P.JAGPSystem(w.system, precision=P.QMC_W_FP32)
+    wk = P.Walkers(sysh, w.r0.shape[0])
+    out = wk.eval_batch(torch.tensor(w.r0, device="cuda"))
+    torch.cuda.synchronize()
+    return out
+
+
+def _bounds(sy, r):
+    ref = O.evaluate(sy, r, with_intermediates=True)
+    L = sy.lam.shape[0]
+    gam = (2 * L + 4) * 2.0 ** -24
+    nu = sy.n_up
+    Phi, G, H, A = ref["Phi"], ref["gradPhi"], ref["lapPhi"], ref["A"]
+    gJ = ref["gradJ"]
+    Q = H + 2 * (G * gJ.unsqueeze(2)).sum(-1)
+    aL = sy.lam.abs()
+    absW = Phi[:, :nu].abs() @ aL @ Phi[:, nu:].abs().transpose(1, 2)
+    absV = Q[:, :nu].abs() @ aL @ Phi[:, nu:].abs().transpose(1, 2) + \
+        Phi[:, :nu].abs() @ aL @ Q[:, nu:].abs().transpose(1, 2)
+    V = Q[:, :nu] @ sy.lam @ Phi[:, nu:].transpose(1, 2) + \
+        Phi[:, :nu] @ sy.lam @ Q[:, nu:].transpose(1, 2)
+    AVA = A @ V @ A
+    b_logdet = gam * (A.abs().transpose(1, 2) * absW).sum(dim=(1, 2))
+    b_ekin = 0.5 * gam * ((AVA.abs().transpose(1, 2) * absW).sum(dim=(1, 2)) +
+                          (A.abs().transpose(1, 2) * absV).sum(dim=(1, 2)))
+    return ref, b_logdet, b_ekin
+
+
+@pytest.mark.parametrize("name", ["tiny", "mol160"])
+def test_mixed_eval_within_forward_error_bound(name):
+    P = need_gpu()
+    if name == "tiny":
+        w, idx = C.tiny_3nuc_10e(), list(range(64))
+    else:
+        w, idx = C.mol_40nuc_160e(n_walkers=64), [0, 9, 31, 50, 63]
+    out = _gpu_eval(P, w)
+    sy = O.from_workload_system(w.system)
+    ref, b_ld, b_ek = _bounds(sy, torch.tensor(w.r0[idx]))
+    d_ld = (out["logabs"].cpu()[idx] - ref["logabs"]).abs()
+    d_ek = (out["e_kin"].cpu()[idx] - ref["e_kin"]).abs()
+    d_el = (out["e_loc"].cpu()[idx] - ref["e_loc"]).abs()
+    print(f"[mixed fp32 {name}] max |d logabs| {d_ld.max():.3e} (bound {b_ld.min():.3e}..{b_ld.max():.3e}); "
+          f"max |d e_kin| {d_ek.max():.3e} (bound {b_ek.min():.3e}..{b_ek.max():.3e}); "
+          f"max rel err logabs {rel_err(out['logabs'].cpu()[idx], ref['logabs']).max():.3e}, "
+          f"e_loc {rel_err(out['e_loc'].cpu()[idx], ref['e_loc']).max():.3e}")
+    assert torch.all(d_ld <= b_ld + 1e-10)
+    assert torch.all(d_ek <= b_ek + 1e-9)
+    # the potential is FP64 on both sides: e_loc - e_kin agrees to FP64 rounding
+    assert torch.allclose(out["e_loc"].cpu()[idx] - out["e_kin"].cpu()[idx], ref["V"], rtol=1e-12, atol=1e-10)
+    assert torch.equal(out["sign"].cpu()[idx], ref["sign"])
+
+
+@pytest.mark.xfail(reason="mixed path has no refinement stage yet: FP32 products amplified by cond(W) "
+                          "miss the 1e-6 bar on these inputs", strict=False)
+def test_mixed_eval_north_star_1e6():
+    P = need_gpu()
+    w = C.mol_40nuc_160e(n_walkers=64)
+    idx = [0, 9, 31, 50, 63]
+    out = _gpu_eval(P, w)
+    ref = O.evaluate(O.from_workload_system(w.system), torch.tensor(w.r0[idx]))
+    assert rel_err(out["logabs"].cpu()[idx], ref["logabs"]).max().item() <= 1e-6
+    assert rel_err(out["e_loc"].cpu()[idx], ref["e_loc"]).max().item() <= 1e-6
+
+
+def test_mixed_moves_ratio_within_bound():
+    # After an FP32 evaluation, the ratio R = w'^T A[:,e] (up) or A[e,:] w' (down)
+    # carries two first-order error terms: the FP32 rows of P in w' = P_other psi',
+    #   |dw'| <= gamma |Phi_other| |Lambda| |psi'|,
+    # and the inverse of the FP32-built W, dA = -A dW A with
+    #   |dW| <= gamma |Phi_up| |Lambda| |Phi_dn|^T,
+    # giving |dR| <= |dw'|.|A col| + sum_ik |(w'^T A)_i| |dW_ik| |A_ke| (up; the
+    # transpose for down), times exp(dJ).
+    P = need_gpu()
+    w = C.mol_40nuc_160e(n_walkers=16)
+    sysh = P.JAGPSystem(w.system, precision=P.QMC_W_FP32)
+    wk = P.Walkers(sysh, 16)
+    r = torch.tensor(w.r0)
+    sy = O.from_workload_system(w.system)
+    L = sy.lam.shape[0]
+    gam = (2 * L + 4) * 2.0 ** -24
+    nu = sy.n_up
+    disp = torch.tensor(C.chain_arrays(13, 2, 16)[0])
+    ref = O.evaluate(sy, r, with_intermediates=True)
+    Phi, A = ref["Phi"], ref["A"]
+    absW = Phi[:, :nu].abs() @ sy.lam.abs() @ Phi[:, nu:].abs().transpose(1, 2)
+    for t, e in enumerate((3, 120)):
+        wk.eval_batch(r.cuda())
+        rn = r[:, e] + disp[t]
+        ratio = wk.propose(e, rn.cuda().contiguous())
+        torch.cuda.synchronize()
+        rr = O.move_ratio(sy, r, e, rn)
+        psi_n = O.basis(sy, rn)[0]
+        if e < nu:
+            wn = torch.einsum('wm,mn,wjn->wj', psi_n, sy.lam, Phi[:, nu:])
+            dw = gam * torch.einsum('wm,mn,wjn->wj', psi_n.abs(), sy.lam.abs(), Phi[:, nu:].abs())
+            col = A[:, :, e]
+            u = torch.einsum('wj,wji->wi', wn, A)
+            b = (dw * col.abs()).sum(-1) + gam * torch.einsum('wi,wik,wk->w', u.abs(), absW, col.abs())
+        else:
+            ed = e - nu
+            wn = torch.einsum('wim,mn,wn->wi', Phi[:, :nu], sy.lam, psi_n)
+            dw = gam * torch.einsum('wim,mn,wn->wi', Phi[:, :nu].abs(), sy.lam.abs(), psi_n.abs())
+            row = A[:, ed, :]
+            v = torch.einsum('wli,wi->wl', A, wn)
+            b = (dw * row.abs()).sum(-1) + gam * torch.einsum('wk,wkl,wl->w', row.abs(), absW, v.abs())
+        r2 = r.clone(); r2[:, e] = rn
+        bound = b * torch.exp(O.jastrow(sy, r2)[0] - ref["J"])
+        d = (ratio.cpu() - rr).abs()
+        print(f"[mixed fp32 moves e={e}] max |d ratio| {d.max():.3e}, bound {bound.min():.3e}..{bound.max():.3e}")
+        assert torch.all(d <= bound + 1e-12)
