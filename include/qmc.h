@@ -158,6 +158,32 @@ qmc_status qmc_vmc_steps(qmc_system *sys, qmc_walkers *wk, int32_t e_start, int3
                          const double *disp, const double *unif, int32_t *accept_count,
                          hipStream_t stream);
 
+/* Outputs of qmc_forces (device pointers; any may be NULL to skip it).
+ * n_jas = n_nuc (one-body b per nucleus) + n_j2 (two-body parameters). */
+typedef struct {
+  double *dR;       /* [A][3] summed over walkers, or [Wk][A][3] per walker      */
+  double *dzeta;    /* [L] or [Wk][L]                                            */
+  double *dlambda;  /* [L][L] or [Wk][L][L]: d/dLambda[mu][nu], every entry
+                       independent (the caller applies any symmetry constraint) */
+  double *djas;     /* [n_jas] or [Wk][n_jas]                                    */
+  double *dr;       /* [Wk][N][3] (always per walker)                            */
+} qmc_grads;
+
+/* Adjoint of the evaluation (Derivatives of energy section: logarithmic
+ * derivatives O_k of the wave function and derivatives of the local energy,
+ * all obtained by one reverse pass).  For every walker w it differentiates
+ *     F_w = gbar_logpsi[w] * log|Psi_w| + gbar_eloc[w] * e_L,w
+ * with respect to the nuclear positions, basis exponents, pairing matrix,
+ * Jastrow parameters and electron positions.  per_walker = 0 sums the
+ * parameter gradients over walkers (a vector-Jacobian product); 1 returns
+ * them per walker.  r [Wk][N][3] device; gbar_* [Wk] device, NULL means 0.
+ * Re-evaluates the walkers at r (their state becomes that of qmc_eval_batch).
+ * FP64 systems with N <= 256 electrons and <= 256 nuclei.  The first call on
+ * a walker set allocates its workspace. */
+qmc_status qmc_forces(qmc_system *sys, qmc_walkers *wk, const double *r, int32_t per_walker,
+                      const double *gbar_logpsi, const double *gbar_eloc, const qmc_grads *out,
+                      hipStream_t stream);
+
 /* Items of the walker state that qmc_walkers_read can copy out. */
 typedef enum {
   QMC_STATE_R = 0,       /* [Wk][N][3]   FP64 positions                          */

@@ -29,7 +29,7 @@ FUNCTIONS = (
     "qmc_abi_version", "qmc_last_error", "qmc_system_create", "qmc_system_destroy",
     "qmc_walkers_create", "qmc_walkers_destroy", "qmc_eval_batch", "qmc_propose_move",
     "qmc_accept_move", "qmc_vmc_steps", "qmc_walkers_read", "qmc_walkers_set_timing",
-    "qmc_walkers_timing",
+    "qmc_walkers_timing", "qmc_forces",
 )
 
 TIMER_NAMES = ("basis", "P_build", "W_build", "LU", "Y_build", "rowdot", "assemble", "propose",
@@ -40,6 +40,11 @@ class QMCError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
         self.code = code
+
+
+class Grads(ctypes.Structure):
+    _fields_ = [("dR", ctypes.c_void_p), ("dzeta", ctypes.c_void_p), ("dlambda", ctypes.c_void_p),
+                ("djas", ctypes.c_void_p), ("dr", ctypes.c_void_p)]
 
 
 class SystemDesc(ctypes.Structure):
@@ -81,6 +86,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.qmc_walkers_read.argtypes = [vp, i32, dp, vp]
     lib.qmc_walkers_set_timing.argtypes = [vp, i32]
     lib.qmc_walkers_timing.argtypes = [vp, vp, vp]
+    lib.qmc_forces.argtypes = [vp, vp, dp, i32, dp, dp, ctypes.POINTER(Grads), vp]
     _lib = lib
     return lib
 
@@ -131,6 +137,8 @@ class JAGPSystem:
         self.precision = precision
         self.n_elec = s.n_up + s.n_dn
         self.n_up, self.n_dn, self.L = s.n_up, s.n_dn, len(s.zeta)
+        self.n_nuc = len(s.Z)
+        self.n_jas = len(s.Z) + len(s.j2)
 
     def close(self):
         if getattr(self, "h", None):
@@ -212,3 +220,20 @@ class Walkers:
         n = (ctypes.c_int64 * len(TIMER_NAMES))()
         _check(load().qmc_walkers_timing(self.h, ms, n))
         return {k: (ms[i], n[i]) for i, k in enumerate(TIMER_NAMES)}
+
+    def forces(self, r: torch.Tensor, gbar_logpsi: Optional[torch.Tensor], gbar_eloc: Optional[torch.Tensor],
+               per_walker: bool = False, stream=None) -> Dict[str, torch.Tensor]:
+        """Gradients of sum_w (gbar_logpsi[w] log|Psi_w| + gbar_eloc[w] e_L,w) (per_walker=False)
+        or of each walker's term separately (per_walker=True)."""
+        S = self.sys
+        Wk, N, A, L, nj = self.n, S.n_elec, S.n_nuc, S.L, S.n_jas
+        f = lambda *sh: torch.empty(*sh, dtype=torch.float64, device=r.device)
+        if per_walker:
+            out = dict(R=f(Wk, A, 3), zeta=f(Wk, L), lam=f(Wk, L, L), jas=f(Wk, nj), r=f(Wk, N, 3))
+        else:
+            out = dict(R=f(A, 3), zeta=f(L), lam=f(L, L), jas=f(nj), r=f(Wk, N, 3))
+        g = Grads(dR=_ptr(out["R"]), dzeta=_ptr(out["zeta"]), dlambda=_ptr(out["lam"]),
+                  djas=_ptr(out["jas"]), dr=_ptr(out["r"]))
+        _check(load().qmc_forces(S.h, self.h, _ptr(r), 1 if per_walker else 0, _ptr(gbar_logpsi),
+                                 _ptr(gbar_eloc), ctypes.byref(g), _stream(stream)))
+        return out

@@ -1,0 +1,535 @@
+// Hand-written reverse pass (adjoint) of the whole evaluation: gradients of
+//   F_w = a_w log|Psi_w| + b_w e_L,w
+// with respect to nuclear positions R, basis exponents zeta, the pairing
+// matrix Lambda (all L^2 entries, unconstrained), the Jastrow parameters and
+// the electron positions r.  (Derivatives of energy section: O_k = d ln Psi /
+// d alpha_k and the local-energy derivatives needed for forces; the adjoint
+// gives all of them at a small multiple of the cost of one evaluation.)
+//
+// Forward quantities per walker (FP64): Phi, W = Phi_U Lambda Phi_D^T,
+// A = W^{-1}, P = [Phi_U Lambda ; Phi_D Lambda^T], Yt = [A^T P_D ; A P_U],
+// Jastrow gradient g_i and Laplacian h_i, drift.  With
+//   Q = lap Phi + 2 grad Phi . g          (per electron row)
+//   V = Q_U Lambda Phi_D^T + Phi_U Lambda Q_D^T,
+// the determinant part of the kinetic sum is tr(A V) and
+//   e_kin = -1/2 [ tr(A V) + sum_i (h_i + |g_i|^2) ].
+// Reverse pass:
+//   G_W = a A^T + b/2 (A V A)^T       (d F / d W)
+//   G_V = -b/2 A^T                      (d F / d V)
+//   X_U = G_W Phi_D + G_V Q_D,  X_D = G_W^T Phi_U + G_V^T Q_U,  Z_U = G_V Phi_D
+//   dF/dPhi_U = X_U Lambda^T,  dF/dPhi_D = X_D Lambda
+//   dF/dLambda = Phi_U^T X_U + Q_U^T Z_U
+//   dF/dQ = -b/2 Yt,  so dF/dlap Phi = -b/2 Yt and dF/dgrad Phi = -b Yt g
+//   dF/dg_i = -b drift_i,  dF/dh_i = -b/2,  dF/dJ = a,  dF/dV_coulomb = b
+// then through the basis functions (values, gradients, Hessians, gradient of
+// the Laplacian, exponent derivatives) and the radial Jastrow terms.
+#include <vector>
+
+#include "internal.h"
+
+namespace qmc {
+
+// ---------------------------------------------------------------------------
+// forward-mode dual numbers for the radial Jastrow functions
+// ---------------------------------------------------------------------------
+struct Dl {
+  double v, d;
+};
+__device__ __forceinline__ Dl operator+(Dl a, Dl b) { return {a.v + b.v, a.d + b.d}; }
+__device__ __forceinline__ Dl operator-(Dl a, Dl b) { return {a.v - b.v, a.d - b.d}; }
+__device__ __forceinline__ Dl operator-(Dl a) { return {-a.v, -a.d}; }
+__device__ __forceinline__ Dl operator*(Dl a, Dl b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
+__device__ __forceinline__ Dl operator/(Dl a, Dl b) { return {a.v / b.v, (a.d * b.v - a.v * b.d) / (b.v * b.v)}; }
+__device__ __forceinline__ Dl operator+(double a, Dl b) { return {a + b.v, b.d}; }
+__device__ __forceinline__ Dl operator*(double a, Dl b) { return {a * b.v, a * b.d}; }
+__device__ __forceinline__ Dl operator*(Dl a, double b) { return {a.v * b, a.d * b}; }
+__device__ __forceinline__ Dl operator/(double a, Dl b) { return {a / b.v, -a * b.d / (b.v * b.v)}; }
+__device__ __forceinline__ Dl dexp(Dl a) { const double e = exp(a.v); return {e, e * a.d}; }
+__device__ __forceinline__ Dl dexpm1(Dl a) { return {expm1(a.v), exp(a.v) * a.d}; }
+__device__ __forceinline__ double dexp(double a) { return exp(a); }
+__device__ __forceinline__ double dexpm1(double a) { return expm1(a); }
+
+template <class S>
+__device__ void j1_radial_t(int form, double Z, S b, S r, S& f, S& f1, S& f2) {
+  const double q = sqrt(sqrt(2.0 * Z));
+  const S s = q * r;
+  S u, u1, u2;
+  if (form == 1) {
+    const S e = dexp(-(b * s));
+    u = -dexpm1(-(b * s)) / (2.0 * b);
+    u1 = 0.5 * e;
+    u2 = -0.5 * (b * e);
+  } else {
+    const S den = 1.0 / (1.0 + b * s);
+    u = 0.5 * (s * den);
+    u1 = 0.5 * (den * den);
+    u2 = -(b * den * den * den);
+  }
+  const double q3 = q * q * q;
+  f = -q3 * u;
+  f1 = -(q3 * q) * u1;
+  f2 = -(q3 * q * q) * u2;
+}
+
+// two-body: c t + a1 t^2 + a2 t^3 + a3 t^4 with t = r/(1+b r); c = 1/4 or 1/2
+template <class S>
+__device__ void j2_radial_t(double c, S b, S a1, S a2, S a3, S r, S& v, S& v1, S& v2) {
+  const S den = 1.0 / (1.0 + b * r);
+  const S t = r * den;
+  const S dt = den * den;
+  const S d2t = -2.0 * (b * den * den * den);
+  const S g = t * (c + t * (a1 + t * (a2 + t * a3)));
+  const S g1 = c + t * (2.0 * a1 + t * (3.0 * a2 + t * (4.0 * a3)));
+  const S g2 = 2.0 * a1 + t * (6.0 * a2 + t * (12.0 * a3));
+  v = g;
+  v1 = g1 * dt;
+  v2 = g2 * dt * dt + g1 * d2t;
+}
+
+__device__ __forceinline__ Dl cst(double x) { return {x, 0.0}; }
+__device__ __forceinline__ Dl var(double x) { return {x, 1.0}; }
+
+// Parameters (b, a1, a2, a3) of the two-body channel of a pair.
+__device__ __forceinline__ void j2_params(const SysDev& s, bool same, double p[4]) {
+  if (s.j2_form == 1) {
+    p[0] = same ? s.j2[0] : s.j2[1]; p[1] = p[2] = p[3] = 0.0;
+  } else {
+    const int o = same ? 0 : 4;
+    p[0] = s.j2[o]; p[1] = s.j2[o + 1]; p[2] = s.j2[o + 2]; p[3] = s.j2[o + 3];
+  }
+}
+
+// Gradient, w.r.t. the displacement d (|d| = r), of the pair term
+//   T = cv f(r) + gb . d f'(r)/r + ch (f''(r) + 2 f'(r)/r)
+// given f', f'', f''' at r.
+__device__ __forceinline__ void pair_term_grad(double cv, double ch, const double gb[3], const double d[3],
+                                               double r, double f1, double f2, double f3, double out[3]) {
+  const double ir = 1.0 / r;
+  const double gd = gb[0] * d[0] + gb[1] * d[1] + gb[2] * d[2];
+  const double radial = cv * f1 + ch * (f3 + 2.0 * f2 * ir - 2.0 * f1 * ir * ir);
+  const double k = (f2 * ir - f1 * ir * ir) * ir * gd;
+  for (int c = 0; c < 3; ++c) out[c] = radial * d[c] * ir + gb[c] * f1 * ir + k * d[c];
+}
+
+// ---------------------------------------------------------------------------
+// 1. stacked basis rows: SU = [Phi_U ; Q_U], SD = [Phi_D ; Q_D] per walker,
+//    Q = lap Phi + 2 grad Phi . g_i  (one workgroup per electron row)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) stack_basis_kernel(SysDev s, WalkDev w, double* __restrict__ SU,
+                                                          double* __restrict__ SD) {
+  const long row = blockIdx.x;           // wk * N + i
+  const int wk = (int)(row / s.N), i = (int)(row % s.N);
+  const double px = w.r[3 * row], py = w.r[3 * row + 1], pz = w.r[3 * row + 2];
+  const double* g = w.gJ + 4 * row;
+  const double gx = g[0], gy = g[1], gz = g[2];
+  const int n = s.nu;
+  double *dphi, *dq;
+  if (i < s.nu) {
+    dphi = SU + ((long)wk * 2 * n + i) * s.Lp;
+    dq = SU + ((long)wk * 2 * n + n + i) * s.Lp;
+  } else {
+    dphi = SD + ((long)wk * 2 * n + (i - s.nu)) * s.Lp;
+    dq = SD + ((long)wk * 2 * n + n + (i - s.nu)) * s.Lp;
+  }
+  for (int mu = threadIdx.x; mu < s.Lp; mu += blockDim.x) {
+    double v = 0.0, q = 0.0;
+    if (mu < s.L) {
+      double bx, by, bz, lp;
+      basis_vgl(s, mu, px, py, pz, v, bx, by, bz, lp);
+      q = lp + 2.0 * (bx * gx + by * gy + bz * gz);
+    }
+    dphi[mu] = v;
+    dq[mu] = q;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 2. G_W = a A^T + b/2 M^T (M = A V A), G_V = -b/2 A^T, stored as
+//    GG  = [G_W | G_V]  (n x 2n)  and  GGt = [G_W ; G_V]  (2n x n)
+// ---------------------------------------------------------------------------
+__global__ void gw_kernel(int n, int Wk, const double* __restrict__ A, const double* __restrict__ M,
+                          const double* __restrict__ ga, const double* __restrict__ gb,
+                          double* __restrict__ GG, double* __restrict__ GGt) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)Wk * n * n) return;
+  const int wk = (int)(idx / ((long)n * n));
+  const int rem = (int)(idx % ((long)n * n));
+  const int i = rem / n, j = rem % n;       // G[i][j], i up, j down
+  const double a = ga ? ga[wk] : 0.0, b = gb ? gb[wk] : 0.0;
+  const double Aji = A[(long)wk * n * n + (long)j * n + i];
+  const double Mji = M[(long)wk * n * n + (long)j * n + i];
+  const double gw = a * Aji + 0.5 * b * Mji;
+  const double gv = -0.5 * b * Aji;
+  double* gg = GG + (long)wk * 2 * n * n;
+  gg[(long)i * 2 * n + j] = gw;
+  gg[(long)i * 2 * n + n + j] = gv;
+  double* gt = GGt + (long)wk * 2 * n * n;
+  gt[(long)i * n + j] = gw;
+  gt[(long)(n + i) * n + j] = gv;
+}
+
+// ---------------------------------------------------------------------------
+// 3. basis backward, one workgroup per walker; threads own basis functions mu
+//    and loop over electrons.  For each (i, mu):
+//      pb = dF/dPhi, qb = dF/dQ = -b/2 Yt, gbar = 2 qb g_i, hbar = qb
+//      t  = pb grad psi + Hess psi . gbar + hbar grad(lap psi)      (= dF/dr_i)
+//      zeta_bar_mu += pb d_zeta psi + gbar . d_zeta grad psi + hbar d_zeta lap psi
+//    dF/dR_center(mu) -= t.  Per-electron sums of t reduce per wave (fixed order).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void hess_P(int kind, double H[6]) {   // xx yy zz xy yz zx
+  for (int k = 0; k < 6; ++k) H[k] = 0.0;
+  switch (kind) {
+    case 4: H[3] = 1.0; break;
+    case 5: H[4] = 1.0; break;
+    case 6: H[5] = 1.0; break;
+    case 7: H[0] = 2.0; H[1] = -2.0; break;
+    case 8: H[0] = -2.0; H[1] = -2.0; H[2] = 4.0; break;
+    default: break;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+basis_backward_kernel(SysDev s, WalkDev w, const double* __restrict__ phibar, const double* __restrict__ gb,
+                      double* __restrict__ dr, double* __restrict__ Rbar_w, double* __restrict__ zbar_w,
+                      double* __restrict__ tmu) {
+  __shared__ double rpart[4][kLuMaxN * 2][3];
+  const int wk = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const double b = gb ? gb[wk] : 0.0;
+  const double* r = w.r + (long)wk * s.N * 3;
+  const double* Yt = w.Yt + (long)wk * s.N * s.Lp;
+  const double* PB = phibar + (long)wk * s.N * s.Lp;
+  const double* gJ = w.gJ + (long)wk * s.N * 4;
+  double* tm = tmu + (long)wk * s.L * 3;
+  const int nmu = (s.L + blockDim.x - 1) / blockDim.x;
+  for (int k = 0; k < nmu; ++k) {
+    const int mu = tid + k * blockDim.x;
+    const bool act = mu < s.L;
+    int c = 0, kind = 0;
+    double zt = 0.0, Rx = 0.0, Ry = 0.0, Rz = 0.0, HP[6];
+    if (act) {
+      c = s.center[mu]; kind = s.kind[mu]; zt = s.zeta[mu];
+      Rx = s.R[3 * c]; Ry = s.R[3 * c + 1]; Rz = s.R[3 * c + 2];
+    }
+    hess_P(kind, HP);
+    const double lq = 4.0 * kind_l(kind) + 6.0;
+    double zacc = 0.0, tx = 0.0, ty = 0.0, tz = 0.0;
+    for (int i = 0; i < s.N; ++i) {
+      double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+      if (act) {
+        const double pb = PB[(long)i * s.Lp + mu];
+        const double qb = -0.5 * b * Yt[(long)i * s.Lp + mu];
+        const double gbx = 2.0 * qb * gJ[4 * i], gby = 2.0 * qb * gJ[4 * i + 1], gbz = 2.0 * qb * gJ[4 * i + 2];
+        const double hb = qb;
+        const double d[3] = {r[3 * i] - Rx, r[3 * i + 1] - Ry, r[3 * i + 2] - Rz};
+        const double sq = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        double P, Pg[3];
+        angular(kind, d[0], d[1], d[2], P, Pg[0], Pg[1], Pg[2]);
+        const double e = exp(-zt * sq);
+        const double psi = P * e;
+        double gpsi[3];
+        for (int a = 0; a < 3; ++a) gpsi[a] = (Pg[a] - 2.0 * zt * d[a] * P) * e;
+        // Hessian of psi
+        const int ia[6] = {0, 1, 2, 0, 1, 2}, ib[6] = {0, 1, 2, 1, 2, 0};
+        double Hs[3][3];
+        for (int q = 0; q < 6; ++q) {
+          const int a = ia[q], bb = ib[q];
+          const double v = (HP[q] - 2.0 * zt * (d[a] * Pg[bb] + d[bb] * Pg[a]) -
+                            (a == bb ? 2.0 * zt * P : 0.0) + 4.0 * zt * zt * d[a] * d[bb] * P) * e;
+          Hs[a][bb] = v; Hs[bb][a] = v;
+        }
+        const double cl = 4.0 * zt * zt * sq - lq * zt;   // lap psi = cl psi
+        double glap[3];
+        for (int a = 0; a < 3; ++a) glap[a] = 8.0 * zt * zt * d[a] * psi + cl * gpsi[a];
+        const double gbv[3] = {gbx, gby, gbz};
+        t0 = pb * gpsi[0] + Hs[0][0] * gbv[0] + Hs[0][1] * gbv[1] + Hs[0][2] * gbv[2] + hb * glap[0];
+        t1 = pb * gpsi[1] + Hs[1][0] * gbv[0] + Hs[1][1] * gbv[1] + Hs[1][2] * gbv[2] + hb * glap[1];
+        t2 = pb * gpsi[2] + Hs[2][0] * gbv[0] + Hs[2][1] * gbv[1] + Hs[2][2] * gbv[2] + hb * glap[2];
+        // exponent derivatives
+        const double zpsi = -sq * psi;
+        double zg = 0.0;
+        for (int a = 0; a < 3; ++a) zg += gbv[a] * (-2.0 * d[a] * P * e - sq * gpsi[a]);
+        const double zlap = (8.0 * zt * sq - lq) * psi - sq * cl * psi;
+        zacc += pb * zpsi + zg + hb * zlap;
+        tx += t0; ty += t1; tz += t2;
+      }
+      const double s0 = wave_sum(t0), s1 = wave_sum(t1), s2 = wave_sum(t2);
+      if (lane == 0) {
+        if (k == 0) { rpart[wave][i][0] = s0; rpart[wave][i][1] = s1; rpart[wave][i][2] = s2; }
+        else { rpart[wave][i][0] += s0; rpart[wave][i][1] += s1; rpart[wave][i][2] += s2; }
+      }
+    }
+    if (act) {
+      zbar_w[(long)wk * s.L + mu] = zacc;
+      tm[3 * mu] = tx; tm[3 * mu + 1] = ty; tm[3 * mu + 2] = tz;
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < s.N; i += blockDim.x) {
+    for (int c = 0; c < 3; ++c) {
+      double t = 0.0;
+      for (int q = 0; q < 4; ++q) t += rpart[q][i][c];
+      dr[((long)wk * s.N + i) * 3 + c] = t;
+    }
+  }
+  // nuclear positions: dF/dR_a = - sum over the functions centred on a (CSR order)
+  for (int a = tid; a < s.n_nuc; a += blockDim.x) {
+    double t[3] = {0.0, 0.0, 0.0};
+    for (int k = s.cptr[a]; k < s.cptr[a + 1]; ++k) {
+      const int mu = s.cmu[k];
+      for (int c = 0; c < 3; ++c) t[c] += tm[3 * mu + c];
+    }
+    for (int c = 0; c < 3; ++c) Rbar_w[((long)wk * s.n_nuc + a) * 3 + c] = -t[c];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 4. Jastrow and Coulomb backward, one workgroup per walker, thread i = electron i.
+//    Pair terms of F: a_w J + sum_i gbar_i . grad_i J - b_w/2 sum_i lap_i J + b_w V,
+//    gbar_i = -b_w drift_i.  Accumulates into dr, Rbar_w and writes jbar_w.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+jastrow_backward_kernel(SysDev s, WalkDev w, const double* __restrict__ ga, const double* __restrict__ gbw,
+                        double* __restrict__ dr, double* __restrict__ Rbar_w, double* __restrict__ jbar_w) {
+  __shared__ double rbin[4][kMaxNucBack][4];   // per wave: dR (3) and d b_a
+  __shared__ double red[4][8];
+  const int wk = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const double av = ga ? ga[wk] : 0.0, bv = gbw ? gbw[wk] : 0.0;
+  const double* r = w.r + (long)wk * s.N * 3;
+  const double* drift = w.drift + (long)wk * s.N * 3;
+  const int i = tid;
+  const bool act = i < s.N;
+  double xi[3] = {0.0, 0.0, 0.0}, gi[3] = {0.0, 0.0, 0.0};
+  if (act) {
+    for (int c = 0; c < 3; ++c) { xi[c] = r[3 * i + c]; gi[c] = -bv * drift[3 * i + c]; }
+  }
+  double rb[3] = {0.0, 0.0, 0.0};
+  // one-body terms and electron-nucleus attraction, nucleus by nucleus
+  for (int a = 0; a < s.n_nuc; ++a) {
+    double cR[3] = {0.0, 0.0, 0.0}, cb = 0.0;
+    if (act) {
+      const double d[3] = {xi[0] - s.R[3 * a], xi[1] - s.R[3 * a + 1], xi[2] - s.R[3 * a + 2]};
+      const double ria = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      const double Z = s.Z[a];
+      double t[3] = {0.0, 0.0, 0.0};
+      if (s.j1_form) {
+        Dl f, f1, f2;
+        j1_radial_t<Dl>(s.j1_form, Z, cst(s.j1_b[a]), var(ria), f, f1, f2);
+        pair_term_grad(av, -0.5 * bv, gi, d, ria, f1.v, f2.v, f2.d, t);
+        Dl pf, pf1, pf2;
+        j1_radial_t<Dl>(s.j1_form, Z, var(s.j1_b[a]), cst(ria), pf, pf1, pf2);
+        const double gd = (gi[0] * d[0] + gi[1] * d[1] + gi[2] * d[2]) / ria;
+        cb = av * pf.d + gd * pf1.d - 0.5 * bv * (pf2.d + 2.0 * pf1.d / ria);
+      }
+      // b_w * (-Z / r_ia): d/dr_i = b Z d / r^3
+      const double ir3 = 1.0 / (ria * ria * ria);
+      for (int c = 0; c < 3; ++c) t[c] += bv * Z * d[c] * ir3;
+      for (int c = 0; c < 3; ++c) { rb[c] += t[c]; cR[c] = -t[c]; }
+    }
+    const double s0 = wave_sum(cR[0]), s1 = wave_sum(cR[1]), s2 = wave_sum(cR[2]), s3 = wave_sum(cb);
+    if (lane == 0 && a < kMaxNucBack) {
+      rbin[wave][a][0] = s0; rbin[wave][a][1] = s1; rbin[wave][a][2] = s2; rbin[wave][a][3] = s3;
+    }
+  }
+  // two-body terms and electron-electron repulsion
+  double th[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // jas slots after the one-body b's
+  if (act) {
+    for (int j = 0; j < s.N; ++j) {
+      if (j == i) continue;
+      const double d[3] = {xi[0] - r[3 * j], xi[1] - r[3 * j + 1], xi[2] - r[3 * j + 2]};
+      const double rij = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      const double ir3 = 1.0 / (rij * rij * rij);
+      for (int c = 0; c < 3; ++c) rb[c] += -bv * d[c] * ir3;    // b_w * 1/r_ij
+      if (!s.j2_form) continue;
+      const bool same = (i < s.nu) == (j < s.nu);
+      double p[4];
+      j2_params(s, same, p);
+      const double cc = same ? 0.25 : 0.5;
+      double dg[3];
+      for (int c = 0; c < 3; ++c) dg[c] = gi[c] + bv * drift[3 * j + c];    // gbar_i - gbar_j
+      Dl v, v1, v2;
+      j2_radial_t<Dl>(cc, cst(p[0]), cst(p[1]), cst(p[2]), cst(p[3]), var(rij), v, v1, v2);
+      double t[3];
+      pair_term_grad(av, -bv, dg, d, rij, v1.v, v2.v, v2.d, t);
+      for (int c = 0; c < 3; ++c) rb[c] += t[c];
+      const double gd = (dg[0] * d[0] + dg[1] * d[1] + dg[2] * d[2]) / rij;
+      const int np = s.j2_form == 1 ? 1 : 4;
+      const int slot0 = s.j2_form == 1 ? (same ? 0 : 1) : (same ? 0 : 4);
+      for (int k = 0; k < np; ++k) {
+        Dl q[4] = {cst(p[0]), cst(p[1]), cst(p[2]), cst(p[3])};
+        q[k].d = 1.0;
+        Dl pv, pv1, pv2;
+        j2_radial_t<Dl>(cc, q[0], q[1], q[2], q[3], cst(rij), pv, pv1, pv2);
+        // each pair is visited from both electrons: half weight
+        th[slot0 + k] += 0.5 * (av * pv.d + gd * pv1.d - bv * (pv2.d + 2.0 * pv1.d / rij));
+      }
+    }
+    for (int c = 0; c < 3; ++c) dr[((long)wk * s.N + i) * 3 + c] += rb[c];
+  }
+  for (int k = 0; k < 8; ++k) {
+    const double t = wave_sum(th[k]);
+    if (lane == 0) red[wave][k] = t;
+  }
+  __syncthreads();
+  const int n2 = s.j2_form == 1 ? 2 : (s.j2_form == 2 ? 8 : 0);
+  const int nj = s.n_nuc + n2;
+  double* jb = jbar_w + (long)wk * nj;
+  for (int a = tid; a < s.n_nuc; a += blockDim.x) {
+    double t[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int q = 0; q < 4; ++q)
+      for (int c = 0; c < 4; ++c) t[c] += rbin[q][a][c];
+    // nucleus-nucleus repulsion b_w Z_a Z_b / R_ab
+    for (int bb = 0; bb < s.n_nuc; ++bb) {
+      if (bb == a) continue;
+      const double d[3] = {s.R[3 * a] - s.R[3 * bb], s.R[3 * a + 1] - s.R[3 * bb + 1],
+                           s.R[3 * a + 2] - s.R[3 * bb + 2]};
+      const double R2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+      const double k3 = -bv * s.Z[a] * s.Z[bb] / (R2 * sqrt(R2));
+      for (int c = 0; c < 3; ++c) t[c] += k3 * d[c];
+    }
+    for (int c = 0; c < 3; ++c) Rbar_w[((long)wk * s.n_nuc + a) * 3 + c] += t[c];
+    jb[a] = s.j1_form ? t[3] : 0.0;
+  }
+  if (tid < n2) {
+    double t = 0.0;
+    for (int q = 0; q < 4; ++q) t += red[q][tid];
+    jb[s.n_nuc + tid] = t;
+  }
+}
+
+// Sum per-walker (or per-chunk) rows: out[k] = sum_w in[w][k], fixed order.
+__global__ void sum_rows_kernel(const double* __restrict__ in, long n_rows, long len, double* __restrict__ out) {
+  const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= len) return;
+  double t = 0.0;
+  for (long w = 0; w < n_rows; ++w) t += in[w * len + k];
+  out[k] = t;
+}
+
+static hipError_t sum_rows(const double* in, long n_rows, long len, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(sum_rows_kernel, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, in, n_rows, len, out);
+  return hipGetLastError();
+}
+
+#define HT(x)                              \
+  do {                                     \
+    hipError_t _e = (x);                   \
+    if (_e != hipSuccess) return _e;       \
+  } while (0)
+
+// The reverse pass.  The forward state (Phi rows are recomputed here; P, A,
+// Yt, gJ, drift come from the evaluation that the caller ran just before).
+hipError_t launch_forces(const SysDev& s, const WalkDev& w, const AdjWork& aw, const double* ga,
+                         const double* gb, int per_walker, double* dR, double* dzeta, double* dlambda,
+                         double* djas, double* dr, hipStream_t st) {
+  const int n = s.nu, Wk = w.Wk, Lp = s.Lp, L = s.L, N = s.N;
+  const long rowst = (long)N * Lp, stk = 2L * n * Lp;
+  // 1. stacked rows [Phi_U; Q_U], [Phi_D; Q_D]
+  hipLaunchKernelGGL(stack_basis_kernel, dim3((unsigned)((long)Wk * N)), dim3(256), 0, st, s, w, aw.SU, aw.SD);
+  HT(hipGetLastError());
+  // 2. V = Q_U P_D^T + P_U Q_D^T   (n x n per walker)
+  {
+    GemmArgs g = gemm_args(n, n, Lp);
+    g.A = aw.SU + (long)n * Lp; g.lda = Lp; g.a_bs = stk;
+    g.B = (const double*)w.P + (long)n * Lp; g.ldb = Lp; g.b_bs = rowst;
+    g.C = aw.VQ; g.ldc = n; g.c_bs = (long)n * n; g.batch = Wk;
+    HT(gemm_f64(g, false, true, false, st));
+    g.A = w.P; g.a_bs = rowst;
+    g.B = aw.SD + (long)n * Lp; g.b_bs = stk;
+    g.accumulate = 1;
+    HT(gemm_f64(g, false, true, false, st));
+  }
+  // 3. M = A V A
+  {
+    GemmArgs g = gemm_args(n, n, n);
+    g.A = w.A; g.lda = n; g.a_bs = (long)n * n;
+    g.B = aw.VQ; g.ldb = n; g.b_bs = (long)n * n;
+    g.C = aw.T1; g.ldc = n; g.c_bs = (long)n * n; g.batch = Wk;
+    HT(gemm_f64(g, false, false, false, st));
+    g.A = aw.T1; g.B = w.A; g.C = aw.M;
+    HT(gemm_f64(g, false, false, false, st));
+  }
+  // 4. G_W, G_V
+  {
+    const long tot = (long)Wk * n * n;
+    hipLaunchKernelGGL(gw_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n, Wk, w.A, aw.M, ga, gb,
+                       aw.GG, aw.GGt);
+    HT(hipGetLastError());
+  }
+  // 5. X_U = [G_W | G_V] [Phi_D; Q_D],  Z_U = G_V Phi_D,  X_D = [G_W; G_V]^T [Phi_U; Q_U]
+  {
+    GemmArgs g = gemm_args(n, Lp, 2 * n);
+    g.A = aw.GG; g.lda = 2 * n; g.a_bs = 2L * n * n;
+    g.B = aw.SD; g.ldb = Lp; g.b_bs = stk;
+    g.C = aw.XZ; g.ldc = Lp; g.c_bs = stk; g.batch = Wk;
+    HT(gemm_f64(g, false, false, false, st));
+    GemmArgs z = gemm_args(n, Lp, n);
+    z.A = aw.GG + n; z.lda = 2 * n; z.a_bs = 2L * n * n;
+    z.B = aw.SD; z.ldb = Lp; z.b_bs = stk;
+    z.C = aw.XZ + (long)n * Lp; z.ldc = Lp; z.c_bs = stk; z.batch = Wk;
+    HT(gemm_f64(z, false, false, false, st));
+    GemmArgs x = gemm_args(n, Lp, 2 * n);
+    x.A = aw.GGt; x.lda = n; x.a_bs = 2L * n * n;
+    x.B = aw.SU; x.ldb = Lp; x.b_bs = stk;
+    x.C = aw.XD; x.ldc = Lp; x.c_bs = (long)n * Lp; x.batch = Wk;
+    HT(gemm_f64(x, true, false, false, st));
+  }
+  // 6. dF/dPhi: rows of the up spin X_U Lambda^T, of the down spin X_D Lambda
+  {
+    GemmArgs g = gemm_args(Wk * n, Lp, Lp);
+    g.A = aw.XZ; g.lda = Lp; g.a_grp = n; g.a_gs = stk;
+    g.B = s.lamT; g.ldb = Lp;
+    g.C = aw.PB; g.ldc = Lp; g.c_grp = n; g.c_gs = rowst;
+    HT(gemm_f64(g, false, false, true, st));
+    GemmArgs h = gemm_args(Wk * n, Lp, Lp);
+    h.A = aw.XD; h.lda = Lp;
+    h.B = s.lam; h.ldb = Lp;
+    h.C = aw.PB + (long)n * Lp; h.ldc = Lp; h.c_grp = n; h.c_gs = rowst;
+    HT(gemm_f64(h, false, false, true, st));
+  }
+  // 7. dF/dLambda = [Phi_U; Q_U]^T [X_U; Z_U]
+  if (dlambda) {
+    if (per_walker) {
+      GemmArgs g = gemm_args(L, L, 2 * n);
+      g.A = aw.SU; g.lda = Lp; g.a_bs = stk;
+      g.B = aw.XZ; g.ldb = Lp; g.b_bs = stk;
+      g.C = dlambda; g.ldc = L; g.c_bs = (long)L * L; g.batch = Wk;
+      HT(gemm_f64(g, true, false, true, st));
+    } else {
+      const int cw = aw.chunk_walkers, nfull = Wk / cw, rest = Wk % cw;
+      GemmArgs g = gemm_args(L, L, 2 * n * cw);
+      g.A = aw.SU; g.lda = Lp; g.a_bs = stk * cw;
+      g.B = aw.XZ; g.ldb = Lp; g.b_bs = stk * cw;
+      g.C = aw.lam_part; g.ldc = L; g.c_bs = (long)L * L; g.batch = nfull;
+      if (nfull) HT(gemm_f64(g, true, false, true, st));
+      if (rest) {
+        GemmArgs h = g;
+        h.K = 2 * n * rest;
+        h.A = aw.SU + stk * cw * nfull; h.B = aw.XZ + stk * cw * nfull;
+        h.C = aw.lam_part + (long)nfull * L * L; h.batch = 1;
+        HT(gemm_f64(h, true, false, true, st));
+      }
+      HT(sum_rows(aw.lam_part, nfull + (rest ? 1 : 0), (long)L * L, dlambda, st));
+    }
+  }
+  // 8. basis and Jastrow/Coulomb backward
+  double* drw = dr ? dr : aw.dr;
+  hipLaunchKernelGGL(basis_backward_kernel, dim3(Wk), dim3(256), 0, st, s, w, aw.PB, gb, drw, aw.Rbar,
+                     aw.zbar, aw.tmu);
+  HT(hipGetLastError());
+  hipLaunchKernelGGL(jastrow_backward_kernel, dim3(Wk), dim3(256), 0, st, s, w, ga, gb, drw, aw.Rbar, aw.jbar);
+  HT(hipGetLastError());
+  // 9. outputs
+  const int nj = s.n_nuc + (s.j2_form == 1 ? 2 : (s.j2_form == 2 ? 8 : 0));
+  if (per_walker) {
+    if (dR) HT(hipMemcpyAsync(dR, aw.Rbar, sizeof(double) * Wk * s.n_nuc * 3, hipMemcpyDeviceToDevice, st));
+    if (dzeta) HT(hipMemcpyAsync(dzeta, aw.zbar, sizeof(double) * Wk * L, hipMemcpyDeviceToDevice, st));
+    if (djas) HT(hipMemcpyAsync(djas, aw.jbar, sizeof(double) * Wk * nj, hipMemcpyDeviceToDevice, st));
+  } else {
+    if (dR) HT(sum_rows(aw.Rbar, Wk, (long)s.n_nuc * 3, dR, st));
+    if (dzeta) HT(sum_rows(aw.zbar, Wk, L, dzeta, st));
+    if (djas) HT(sum_rows(aw.jbar, Wk, nj, djas, st));
+  }
+  return hipSuccess;
+}
+
+}  // namespace qmc

@@ -127,6 +127,10 @@ jastrow_assemble_kernel(SysDev s, WalkDev w, double* __restrict__ logabs_o, doub
     const double* Di = w.D + ((long)wk * s.N + i) * 4;
     const double ddx = Di[0], ddy = Di[1], ddz = Di[2], dl = Di[3];
     Kp += dl + 2.0 * (ddx * gx + ddy * gy + ddz * gz) + h + gx * gx + gy * gy + gz * gz;
+    double* gj = w.gJ + ((long)wk * s.N + i) * 4;
+    gj[0] = gx; gj[1] = gy; gj[2] = gz; gj[3] = h;
+    double* dd = w.drift + ((long)wk * s.N + i) * 3;
+    dd[0] = ddx + gx; dd[1] = ddy + gy; dd[2] = ddz + gz;
     if (drift_o) {
       double* o = drift_o + ((long)wk * s.N + i) * 3;
       o[0] = ddx + gx; o[1] = ddy + gy; o[2] = ddz + gz;

@@ -108,8 +108,10 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
       for (int r = 0; r < 4; ++r) {
         const int gm = m0 + wm * WM + i * 16 + Mfma<TI>::row(lane, r);
         const int gn = n0 + wn * WN + j * 16 + (lane & 15);
-        if (gm < g.M && gn < g.N)
-          C[(long)(gm / g.c_grp) * g.c_gs + (long)(gm % g.c_grp) * g.ldc + gn] = (TO)acc[i][j][r];
+        if (gm < g.M && gn < g.N) {
+          TO* cp = C + (long)(gm / g.c_grp) * g.c_gs + (long)(gm % g.c_grp) * g.ldc + gn;
+          *cp = g.accumulate ? (TO)(*cp + (TO)acc[i][j][r]) : (TO)acc[i][j][r];
+        }
       }
 }
 
@@ -121,13 +123,26 @@ static hipError_t run_gemm(const GemmArgs& g, hipStream_t st) {
   return hipGetLastError();
 }
 
-static GemmArgs plain(int M, int N, int K) {
+GemmArgs gemm_args(int M, int N, int K) {
   GemmArgs g{};
   g.M = M; g.N = N; g.K = K;
   g.a_grp = 1 << 30; g.a_gs = 0;
   g.c_grp = 1 << 30; g.c_gs = 0;
   g.batch = 1;
   return g;
+}
+
+static GemmArgs plain(int M, int N, int K) { return gemm_args(M, N, K); }
+
+hipError_t gemm_f64(const GemmArgs& g, bool ta, bool tb, bool big, hipStream_t st) {
+#define QMC_G(BM, BN, TA_, TB_) run_gemm<BM, BN, TA_, TB_, double, double, double, double>(g, st)
+  if (big) {
+    if (ta) return tb ? QMC_G(64, 64, true, true) : QMC_G(64, 64, true, false);
+    return tb ? QMC_G(64, 64, false, true) : QMC_G(64, 64, false, false);
+  }
+  if (ta) return tb ? QMC_G(32, 32, true, true) : QMC_G(32, 32, true, false);
+  return tb ? QMC_G(32, 32, false, true) : QMC_G(32, 32, false, false);
+#undef QMC_G
 }
 
 template <typename T>

@@ -17,6 +17,7 @@ namespace qmc {
 constexpr int kMaxNuc = 4096;
 constexpr int kLuMaxN = 128;      // LDS-resident Gauss-Jordan inverse limit
 constexpr int kPropRows = 16;     // rows of P per proposal workgroup
+constexpr int kMaxNucBack = 256;  // nuclei handled by the Jastrow backward kernel
 
 inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
@@ -36,6 +37,8 @@ struct SysDev {
   double* lamT;     // [Lp][Lp]  Lambda^T
   float* lam32;     // [Lp][Lp]  FP32 copies (precision QMC_W_FP32)
   float* lamT32;
+  int* cptr;        // [A+1] basis functions of nucleus a: cmu[cptr[a] .. cptr[a+1])
+  int* cmu;         // [L]
 };
 
 // Device state of a batch of walkers.
@@ -66,7 +69,34 @@ struct WalkDev {
   double* gdet_part;  // [Wk][S][3] partial gradients (drift at r')
   double* gJ_new;     // [Wk][3] Jastrow gradient at r'
   double* gpsi_new;   // [Wk][3][Lp] basis gradients at r' (drift requests)
+  double* gJ;         // [Wk][N][4] Jastrow gradient (3) and Laplacian per electron
+  double* drift;      // [Wk][N][3] grad_i log|Psi| of the last evaluation
 };
+
+// Workspace of the reverse pass (allocated on the first qmc_forces call).
+struct AdjWork {
+  double* SU;       // [Wk][2n][Lp]  [Phi_U ; Q_U]
+  double* SD;       // [Wk][2n][Lp]  [Phi_D ; Q_D]
+  double* VQ;       // [Wk][n][n]
+  double* T1;       // [Wk][n][n]
+  double* M;        // [Wk][n][n]
+  double* GG;       // [Wk][n][2n]   [G_W | G_V]
+  double* GGt;      // [Wk][2n][n]   [G_W ; G_V]
+  double* XZ;       // [Wk][2n][Lp]  [X_U ; Z_U]
+  double* XD;       // [Wk][n][Lp]
+  double* PB;       // [Wk][N][Lp]   dF/dPhi
+  double* tmu;      // [Wk][L][3]
+  double* Rbar;     // [Wk][A][3]
+  double* zbar;     // [Wk][L]
+  double* jbar;     // [Wk][A + n_j2]
+  double* dr;       // [Wk][N][3]    used when the caller passes no dr
+  double* lam_part; // [chunks][L][L]
+  int chunk_walkers;
+  int chunks;
+};
+hipError_t launch_forces(const SysDev& s, const WalkDev& w, const AdjWork& aw, const double* ga,
+                         const double* gb, int per_walker, double* dR, double* dzeta, double* dlambda,
+                         double* djas, double* dr, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // device helpers
@@ -227,6 +257,12 @@ struct GemmArgs {
   const void* B; long ldb; long b_bs;
   void* C; long ldc; long c_bs; int c_grp; long c_gs;
   int batch;
+  int accumulate;   // 1: C += op(A) op(B); 0: C = op(A) op(B)
 };
+
+// Plain (ungathered) argument block for an M x N x K product.
+GemmArgs gemm_args(int M, int N, int K);
+// FP64 products on MFMA; big = 64x64 tiles (else 32x32).
+hipError_t gemm_f64(const GemmArgs& g, bool ta, bool tb, bool big, hipStream_t st);
 
 }  // namespace qmc

@@ -110,6 +110,8 @@ struct qmc_walkers {
   bool evaluated = false;
   bool P_up_valid = false, P_dn_valid = false;
   Timers tm;
+  AdjWork aw{};
+  bool aw_ready = false;
   ~qmc_walkers() {
     tm.destroy();
     for (void* p : allocs) (void)hipFree(p);
@@ -155,6 +157,13 @@ extern "C" qmc_status qmc_system_create(const qmc_system_desc* desc, qmc_system*
     if (m < 0 || m >= 2 * l + 1) return fail(QMC_ERR_ARG, "component index out of range");
     kind[mu] = (l == 0) ? 0 : (l == 1 ? 1 + m : 4 + m);
   }
+  std::vector<int> cptr(q.n_nuc + 1, 0), cmu(L);
+  for (int mu = 0; mu < L; ++mu) cptr[q.center[mu] + 1]++;
+  for (int a = 0; a < q.n_nuc; ++a) cptr[a + 1] += cptr[a];
+  {
+    std::vector<int> fill(cptr.begin(), cptr.end() - 1);
+    for (int mu = 0; mu < L; ++mu) cmu[fill[q.center[mu]]++] = mu;
+  }
   auto* s = new qmc_system();
   SysDev& d = s->d;
   if (hipGetDevice(&s->device) != hipSuccess) s->device = 0;
@@ -187,6 +196,8 @@ extern "C" qmc_status qmc_system_create(const qmc_system_desc* desc, qmc_system*
   if (!e) e = up((void**)&d.zeta, q.zeta, sizeof(double) * L);
   if (!e) e = up((void**)&d.lam, lam.data(), sizeof(double) * lam.size());
   if (!e) e = up((void**)&d.lamT, lamT.data(), sizeof(double) * lamT.size());
+  if (!e) e = up((void**)&d.cptr, cptr.data(), sizeof(int) * cptr.size());
+  if (!e) e = up((void**)&d.cmu, cmu.data(), sizeof(int) * cmu.size());
   if (!e && q.precision == QMC_W_FP32) {
     std::vector<float> l32(lam.begin(), lam.end()), lT32(lamT.begin(), lamT.end());
     e = up((void**)&d.lam32, l32.data(), sizeof(float) * l32.size());
@@ -253,6 +264,8 @@ extern "C" qmc_status qmc_walkers_create(qmc_system* sys, int32_t n_walkers, qmc
   al((void**)&d.gdet_part, sizeof(double) * Wk * S * 3);
   al((void**)&d.gJ_new, sizeof(double) * Wk * 3);
   al((void**)&d.gpsi_new, sizeof(double) * Wk * 3 * Lp);
+  al((void**)&d.gJ, sizeof(double) * Wk * N * 4);
+  al((void**)&d.drift, sizeof(double) * Wk * N * 3);
   if (e != hipSuccess) {
     delete wk;
     return e == hipErrorOutOfMemory ? fail(QMC_ERR_OOM, "device allocation failed") : hip_fail(e, "walkers_create");
@@ -414,5 +427,63 @@ extern "C" qmc_status qmc_walkers_timing(qmc_walkers* wk, double* ms, int64_t* l
   if (!wk || !ms || !launches) return fail(QMC_ERR_ARG, "null argument");
   HIP_TRY(wk->tm.fold(), "timer fold");
   for (int k = 0; k < QMC_TIMER_COUNT; ++k) { ms[k] = wk->tm.ms[k]; launches[k] = wk->tm.n[k]; }
+  return QMC_OK;
+}
+
+// Allocate the reverse-pass workspace of a walker set (first qmc_forces call).
+static hipError_t alloc_adjoint(qmc_walkers* wk) {
+  if (wk->aw_ready) return hipSuccess;
+  const SysDev& s = wk->sys->d;
+  const size_t Wk = wk->d.Wk, n = s.nu, Lp = s.Lp, L = s.L, N = s.N, A = s.n_nuc;
+  const size_t nj = A + (s.j2_form == 1 ? 2 : (s.j2_form == 2 ? 8 : 0));
+  AdjWork& a = wk->aw;
+  a.chunk_walkers = (int)((Wk + 63) / 64);
+  a.chunks = (int)((Wk + a.chunk_walkers - 1) / a.chunk_walkers);
+  hipError_t e = hipSuccess;
+  auto al = [&](double** p, size_t count) {
+    if (e != hipSuccess) return;
+    e = hipMalloc((void**)p, count * sizeof(double) + 256);
+    if (e == hipSuccess) {
+      wk->allocs.push_back(*p);
+      e = hipMemset(*p, 0, count * sizeof(double) + 256);
+    }
+  };
+  al(&a.SU, Wk * 2 * n * Lp);
+  al(&a.SD, Wk * 2 * n * Lp);
+  al(&a.VQ, Wk * n * n);
+  al(&a.T1, Wk * n * n);
+  al(&a.M, Wk * n * n);
+  al(&a.GG, Wk * 2 * n * n);
+  al(&a.GGt, Wk * 2 * n * n);
+  al(&a.XZ, Wk * 2 * n * Lp);
+  al(&a.XD, Wk * n * Lp);
+  al(&a.PB, Wk * N * Lp);
+  al(&a.tmu, Wk * L * 3);
+  al(&a.Rbar, Wk * A * 3);
+  al(&a.zbar, Wk * L);
+  al(&a.jbar, Wk * nj);
+  al(&a.dr, Wk * N * 3);
+  al(&a.lam_part, (size_t)a.chunks * L * L);
+  if (e == hipSuccess) wk->aw_ready = true;
+  return e;
+}
+
+extern "C" qmc_status qmc_forces(qmc_system* sys, qmc_walkers* wk, const double* r, int32_t per_walker,
+                                 const double* gbar_logpsi, const double* gbar_eloc, const qmc_grads* out,
+                                 hipStream_t stream) {
+  qmc_status c = check_pair(sys, wk);
+  if (c) return c;
+  if (!r || !out) return fail(QMC_ERR_ARG, "null positions or output block");
+  const SysDev& s = sys->d;
+  if (s.precision != QMC_FP64) return fail(QMC_ERR_UNSUPPORTED, "forces are built for the FP64 path");
+  if (s.N > 2 * kLuMaxN || s.n_nuc > kMaxNucBack)
+    return fail(QMC_ERR_UNSUPPORTED, "forces need N <= 256 electrons and <= 256 nuclei");
+  hipError_t e = alloc_adjoint(wk);
+  if (e != hipSuccess)
+    return e == hipErrorOutOfMemory ? fail(QMC_ERR_OOM, "adjoint workspace allocation failed") : hip_fail(e, "forces workspace");
+  c = qmc_eval_batch(sys, wk, r, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, stream);
+  if (c) return c;
+  HIP_TRY(launch_forces(s, wk->d, wk->aw, gbar_logpsi, gbar_eloc, per_walker, out->dR, out->dzeta,
+                        out->dlambda, out->djas, out->dr, stream), "forces");
   return QMC_OK;
 }
