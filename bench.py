@@ -171,6 +171,41 @@ def run_precision(P, C, w, args, precision):
     }
 
 
+def forces_leg(P, C, reps=5):
+    """Adjoint cost on the 80-electron workload: E_loc evaluation vs the full
+    reverse pass (gradients of log|Psi| and E_loc w.r.t. R, zeta, Lambda,
+    Jastrow and r), 512 walkers, FP64."""
+    dev = torch.device("cuda:0")
+    w = C.forces_20nuc_80e()
+    Wk = w.r0.shape[0]
+    sysh = P.JAGPSystem(w.system)
+    wk = P.Walkers(sysh, Wk)
+    r = torch.tensor(w.r0, device=dev)
+    gl = torch.ones(Wk, dtype=torch.float64, device=dev)
+    ge = torch.ones(Wk, dtype=torch.float64, device=dev)
+    wk.eval_batch(r)
+    wk.forces(r, gl, ge)
+    torch.cuda.synchronize()
+    te, tf = [], []
+    for _ in range(reps):
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record()
+        wk.eval_batch(r)
+        e1.record()
+        wk.forces(r, gl, ge)
+        e2.record()
+        torch.cuda.synchronize()
+        te.append(e0.elapsed_time(e1))
+        tf.append(e1.elapsed_time(e2))
+    te, tf = float(np.median(te)), float(np.median(tf))
+    wk.close()
+    sysh.close()
+    return {"workload": "forces_20nuc_80e", "walkers": Wk, "eval_ms": round(te, 3),
+            "forces_ms": round(tf, 3), "forces_over_eval": round(tf / te, 2),
+            "grad_evals_per_s": round(Wk / (tf * 1e-3), 1),
+            "note": "forces_ms includes its own re-evaluation; the paper quotes ~4x for energy+forces"}
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -213,6 +248,8 @@ def main():
         if other == "fp32":
             res["mixed_over_fp64_moves"] = round(side["moves_per_s"] / head["moves_per_s"], 3)
             res["mixed_over_fp64_evals"] = round(side["eloc_evals_per_s"] / head["eloc_evals_per_s"], 3)
+    if not args.only:
+        res["forces"] = forces_leg(P, C)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(res), flush=True)

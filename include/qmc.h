@@ -103,6 +103,16 @@ const char *qmc_last_error(void);
 qmc_status qmc_system_create(const qmc_system_desc *desc, qmc_system **out);
 qmc_status qmc_system_destroy(qmc_system *sys);
 
+/* Replace parameters of a system from DEVICE arrays (any may be NULL to keep
+ * the current values): R [A][3], zeta [L], lambda [L][L], jas [A + n_j2]
+ * (one-body b per nucleus, then the two-body parameters).  Work is enqueued on
+ * `stream`; when jas is given the call also waits for that copy (the two-body
+ * parameters live in the launch arguments).  Walker sets of this system must be
+ * re-evaluated (qmc_eval_batch) before further moves: proposals return
+ * QMC_ERR_STATE until then. */
+qmc_status qmc_system_set_params(qmc_system *sys, const double *R, const double *zeta,
+                                 const double *lambda, const double *jas, hipStream_t stream);
+
 /* Allocate the device state of n_walkers walkers of sys (positions, basis
  * matrix Phi, P = Phi Lambda, W, W^{-1} and move buffers).  The state is
  * undefined until qmc_eval_batch has run. */

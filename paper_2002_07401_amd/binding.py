@@ -29,7 +29,7 @@ FUNCTIONS = (
     "qmc_abi_version", "qmc_last_error", "qmc_system_create", "qmc_system_destroy",
     "qmc_walkers_create", "qmc_walkers_destroy", "qmc_eval_batch", "qmc_propose_move",
     "qmc_accept_move", "qmc_vmc_steps", "qmc_walkers_read", "qmc_walkers_set_timing",
-    "qmc_walkers_timing", "qmc_forces",
+    "qmc_walkers_timing", "qmc_forces", "qmc_system_set_params",
 )
 
 TIMER_NAMES = ("basis", "P_build", "W_build", "LU", "Y_build", "rowdot", "assemble", "propose",
@@ -87,6 +87,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.qmc_walkers_set_timing.argtypes = [vp, i32]
     lib.qmc_walkers_timing.argtypes = [vp, vp, vp]
     lib.qmc_forces.argtypes = [vp, vp, dp, i32, dp, dp, ctypes.POINTER(Grads), vp]
+    lib.qmc_system_set_params.argtypes = [vp, dp, dp, dp, dp, vp]
     _lib = lib
     return lib
 
@@ -139,6 +140,13 @@ class JAGPSystem:
         self.n_up, self.n_dn, self.L = s.n_up, s.n_dn, len(s.zeta)
         self.n_nuc = len(s.Z)
         self.n_jas = len(s.Z) + len(s.j2)
+
+    def set_params(self, R=None, zeta=None, lam=None, jas=None, stream=None):
+        """Replace parameters from device tensors (None keeps the current value)."""
+        c = lambda t: None if t is None else t.detach().contiguous()
+        R, zeta, lam, jas = c(R), c(zeta), c(lam), c(jas)
+        _check(load().qmc_system_set_params(self.h, _ptr(R), _ptr(zeta), _ptr(lam), _ptr(jas),
+                                            _stream(stream)))
 
     def close(self):
         if getattr(self, "h", None):
@@ -237,3 +245,29 @@ class Walkers:
         _check(load().qmc_forces(S.h, self.h, _ptr(r), 1 if per_walker else 0, _ptr(gbar_logpsi),
                                  _ptr(gbar_eloc), ctypes.byref(g), _stream(stream)))
         return out
+
+
+class JAGPFunction(torch.autograd.Function):
+    """(log|Psi|, E_loc) of every walker as a differentiable function of the
+    electron positions r [Wk,N,3], nuclear positions R [A,3], exponents zeta [L],
+    pairing matrix Lambda [L,L] and Jastrow vector [A + n_j2].  The backward
+    pass is the library's hand-written adjoint (qmc_forces, summed over walkers).
+    Call as JAGPFunction.apply(walkers, r, R, zeta, Lambda, jas)."""
+
+    @staticmethod
+    def forward(ctx, walkers, r, R, zeta, lam, jas):
+        walkers.sys.set_params(R, zeta, lam, jas)
+        out = walkers.eval_batch(r.detach().contiguous(), drift=False)
+        ctx.walkers = walkers
+        ctx.save_for_backward(r.detach(), R.detach(), zeta.detach(), lam.detach(), jas.detach())
+        return out["logabs"], out["e_loc"]
+
+    @staticmethod
+    def backward(ctx, g_logabs, g_eloc):
+        r, R, zeta, lam, jas = ctx.saved_tensors
+        wk = ctx.walkers
+        wk.sys.set_params(R, zeta, lam, jas)
+        gl = None if g_logabs is None else g_logabs.contiguous()
+        ge = None if g_eloc is None else g_eloc.contiguous()
+        g = wk.forces(r.contiguous(), gl, ge)
+        return None, g["r"], g["R"], g["zeta"], g["lam"], g["jas"]

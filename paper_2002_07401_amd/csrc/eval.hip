@@ -200,4 +200,25 @@ hipError_t launch_export_phi(const SysDev& s, const WalkDev& w, double* dst, hip
   return hipGetLastError();
 }
 
+// Scatter a dense [L][L] Lambda into the padded Lambda, its transpose and the
+// FP32 copies.
+__global__ void set_lambda_kernel(SysDev s, const double* __restrict__ lam) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)s.L * s.L) return;
+  const int i = (int)(idx / s.L), j = (int)(idx % s.L);
+  const double v = lam[idx];
+  s.lam[(long)i * s.Lp + j] = v;
+  s.lamT[(long)j * s.Lp + i] = v;
+  if (s.lam32) {
+    s.lam32[(long)i * s.Lp + j] = (float)v;
+    s.lamT32[(long)j * s.Lp + i] = (float)v;
+  }
+}
+
+hipError_t launch_set_lambda(const SysDev& s, const double* lam, hipStream_t st) {
+  const long tot = (long)s.L * s.L;
+  hipLaunchKernelGGL(set_lambda_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, s, lam);
+  return hipGetLastError();
+}
+
 }  // namespace qmc

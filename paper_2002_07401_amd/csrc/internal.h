@@ -249,6 +249,7 @@ hipError_t launch_accept(const SysDev& s, const WalkDev& w, int e, const uint8_t
                          hipStream_t st);
 hipError_t launch_refresh_finish(const SysDev& s, const WalkDev& w, int32_t* status, hipStream_t st);
 hipError_t launch_export_phi(const SysDev& s, const WalkDev& w, double* dst, hipStream_t st);
+hipError_t launch_set_lambda(const SysDev& s, const double* lam, hipStream_t st);
 
 // FP64 MFMA GEMM, exposed for the launchers above.
 struct GemmArgs {

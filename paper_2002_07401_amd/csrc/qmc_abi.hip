@@ -39,6 +39,7 @@ hipError_t dalloc(T** p, size_t count) {
 struct qmc_system {
   SysDev d{};
   int device = 0;
+  long generation = 0;   // bumped by qmc_system_set_params
   std::vector<void*> allocs;
   ~qmc_system() {
     for (void* p : allocs) (void)hipFree(p);
@@ -112,6 +113,7 @@ struct qmc_walkers {
   Timers tm;
   AdjWork aw{};
   bool aw_ready = false;
+  long generation = -1;  // system generation of the last evaluation
   ~qmc_walkers() {
     tm.destroy();
     for (void* p : allocs) (void)hipFree(p);
@@ -305,6 +307,7 @@ extern "C" qmc_status qmc_eval_batch(qmc_system* sys, qmc_walkers* wk, const dou
   TIMED(wk, QMC_T_ASSEMBLE, stream,
         launch_jastrow_assemble(s, d, logabs, sign, drift, e_kin, e_loc, status, stream), "assemble");
   wk->evaluated = true;
+  wk->generation = sys->generation;
   wk->P_up_valid = wk->P_dn_valid = true;
   wk->attempts = 0;
   wk->pending_e = -1;
@@ -332,6 +335,7 @@ extern "C" qmc_status qmc_propose_move(qmc_system* sys, qmc_walkers* wk, int32_t
   if (c) return c;
   const SysDev& s = sys->d;
   if (!wk->evaluated) return fail(QMC_ERR_STATE, "propose before eval_batch");
+  if (wk->generation != sys->generation) return fail(QMC_ERR_STATE, "parameters changed since the last eval_batch");
   if (electron < 0 || electron >= s.N) return fail(QMC_ERR_ARG, "electron index out of range");
   if (!r_new) return fail(QMC_ERR_ARG, "null r_new");
   c = ensure_P(wk, electron, stream);
@@ -374,6 +378,7 @@ extern "C" qmc_status qmc_vmc_steps(qmc_system* sys, qmc_walkers* wk, int32_t e_
   if (c) return c;
   const SysDev& s = sys->d;
   if (!wk->evaluated) return fail(QMC_ERR_STATE, "vmc_steps before eval_batch");
+  if (wk->generation != sys->generation) return fail(QMC_ERR_STATE, "parameters changed since the last eval_batch");
   if (!disp || !unif) return fail(QMC_ERR_ARG, "null random arrays");
   if (n_steps < 0 || e_start < 0) return fail(QMC_ERR_ARG, "negative step count or electron");
   const long Wk = wk->d.Wk;
@@ -485,5 +490,26 @@ extern "C" qmc_status qmc_forces(qmc_system* sys, qmc_walkers* wk, const double*
   if (c) return c;
   HIP_TRY(launch_forces(s, wk->d, wk->aw, gbar_logpsi, gbar_eloc, per_walker, out->dR, out->dzeta,
                         out->dlambda, out->djas, out->dr, stream), "forces");
+  return QMC_OK;
+}
+
+extern "C" qmc_status qmc_system_set_params(qmc_system* sys, const double* R, const double* zeta,
+                                            const double* lambda, const double* jas, hipStream_t stream) {
+  if (!sys) return fail(QMC_ERR_ARG, "null system");
+  SysDev& d = sys->d;
+  if (R) HIP_TRY(hipMemcpyAsync(d.R, R, sizeof(double) * 3 * d.n_nuc, hipMemcpyDeviceToDevice, stream), "set R");
+  if (zeta) HIP_TRY(hipMemcpyAsync(d.zeta, zeta, sizeof(double) * d.L, hipMemcpyDeviceToDevice, stream), "set zeta");
+  if (lambda) HIP_TRY(launch_set_lambda(d, lambda, stream), "set lambda");
+  if (jas) {
+    HIP_TRY(hipMemcpyAsync(d.j1_b, jas, sizeof(double) * d.n_nuc, hipMemcpyDeviceToDevice, stream), "set j1");
+    const int n2 = d.j2_form == 1 ? 2 : (d.j2_form == 2 ? 8 : 0);
+    if (n2) {
+      double h[8];
+      HIP_TRY(hipMemcpyAsync(h, jas + d.n_nuc, sizeof(double) * n2, hipMemcpyDeviceToHost, stream), "get j2");
+      HIP_TRY(hipStreamSynchronize(stream), "sync j2");
+      for (int k = 0; k < n2; ++k) d.j2[k] = h[k];
+    }
+  }
+  sys->generation += 1;
   return QMC_OK;
 }

@@ -98,3 +98,43 @@ def test_forces_positions_match_central_differences_of_gpu_eval():
         fd = (ep - em) / (2 * h)
         err = ((g[:, i, c] - fd).abs() / fd.abs().clamp(min=1.0)).max().item()
         assert err <= 1e-6, (i, c, err)
+
+
+def test_autograd_function_matches_oracle_and_parameter_differences():
+    P = need_gpu()
+    w = C.forces_20nuc_80e(n_walkers=4)
+    s = w.system
+    wk, sy, r = _setup(P, w, 4)
+    dev = "cuda"
+    R = torch.tensor(s.R, device=dev, requires_grad=True)
+    zeta = torch.tensor(s.zeta, device=dev, requires_grad=True)
+    lam = torch.tensor(s.lam, device=dev, requires_grad=True)
+    jas = torch.tensor(s.jastrow_params, device=dev, requires_grad=True)
+    rr = r.clone().to(dev).requires_grad_(True)
+    la, el = P.JAGPFunction.apply(wk, rr, R, zeta, lam, jas)
+    wts = torch.tensor([0.3, -1.0, 0.7, 0.2], dtype=torch.float64, device=dev)
+    loss = (wts * la).sum() + (wts.flip(0) * el).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    ref = O.forces_vjp(sy, r, wts.cpu(), wts.flip(0).cpu())
+    got = dict(R=R.grad, zeta=zeta.grad, lam=lam.grad, jas=jas.grad, r=rr.grad)
+    _cmp(got, ref, label="autograd")
+
+    # central differences of the GPU evaluation (h = 1e-5) through set_params
+    def F(R_=None, zeta_=None, lam_=None, jas_=None):
+        wk.sys.set_params(R_, zeta_, lam_, jas_)
+        out = wk.eval_batch(r.to(dev))
+        v = ((wts * out["logabs"]).sum() + (wts.flip(0) * out["e_loc"]).sum()).item()
+        wk.sys.set_params(R.detach(), zeta.detach(), lam.detach(), jas.detach())
+        return v
+
+    h = 1e-5
+    for name, base, ix in (("R", R, (3, 1)), ("zeta", zeta, (17,)), ("lam", lam, (5, 40)), ("jas", jas, (21,)),
+                           ("jas", jas, (24,))):
+        p = base.detach().clone(); p[ix] += h
+        fp = F(**{name + "_": p})
+        p = base.detach().clone(); p[ix] -= h
+        fm = F(**{name + "_": p})
+        fd = (fp - fm) / (2 * h)
+        g = got[name][ix].item()
+        assert abs(g - fd) <= 1e-6 * max(1.0, abs(fd)), (name, ix, g, fd)
