@@ -194,6 +194,43 @@ qmc_status qmc_forces(qmc_system *sys, qmc_walkers *wk, const double *r, int32_t
                       const double *gbar_logpsi, const double *gbar_eloc, const qmc_grads *out,
                       hipStream_t stream);
 
+/* Several systems moved together (uneven electron counts).  Every phase of a
+ * Metropolis step (proposal set-up, streaming rows, accept/update, periodic LU
+ * refresh) is one persistent launch over (system, walker[, row chunk]) work
+ * items ordered by decreasing cost; each member evolves exactly as it would
+ * with qmc_vmc_steps alone given the same random numbers.  Members must have
+ * the same precision and n_up == n_dn <= 128; at most 32 members.  The handles
+ * stay owned by the caller and must outlive the group. */
+typedef struct qmc_multi qmc_multi;
+qmc_status qmc_multi_create(int32_t n_members, qmc_system *const *systems, qmc_walkers *const *walkers,
+                            qmc_multi **out);
+qmc_status qmc_multi_destroy(qmc_multi *m);
+
+/* Time the streaming-rows launch for rows-per-work-item in {8, 16, 32} and
+ * persistent grid sizes {512 .. 4096} on the current walker state (read-only
+ * apart from proposal scratch) and keep the fastest; returns the choice in
+ * *rows and *grid (host, may be NULL).  Synchronises. */
+qmc_status qmc_multi_autotune(qmc_multi *m, int32_t *rows, int32_t *grid, hipStream_t stream);
+
+/* n_steps Metropolis steps of every walker of every member; member k moves
+ * electron (its move count) mod N_k at each step.  disp/unif: host arrays of
+ * n_members DEVICE pointers to [n_steps][Wk_k][3] and [n_steps][Wk_k]; when
+ * both are NULL the draws come from Philox4x32-10 (key = seed, counter = the
+ * member's move count, walker and member index; see qmc_philox_draws).
+ * use_graph != 0 (Philox draws only): the whole n_steps sequence is captured
+ * once into a HIP graph and replayed by later calls in the same phase (move
+ * counts modulo N_k and refresh_every, cached basis products).  Members must
+ * have been evaluated. */
+qmc_status qmc_multi_vmc_steps(qmc_multi *m, int32_t n_steps, const double *const *disp,
+                               const double *const *unif, uint64_t seed, double sigma, int32_t use_graph,
+                               hipStream_t stream);
+
+/* The draws the Philox mode of qmc_multi_vmc_steps uses for member `member`
+ * at move count `step`: disp [Wk][3] (Box-Muller normals times sigma) and
+ * unif [Wk] in [0, 1), device pointers. */
+qmc_status qmc_philox_draws(uint64_t seed, int32_t member, int32_t n_walkers, uint64_t step, double sigma,
+                            double *disp, double *unif, hipStream_t stream);
+
 /* Items of the walker state that qmc_walkers_read can copy out. */
 typedef enum {
   QMC_STATE_R = 0,       /* [Wk][N][3]   FP64 positions                          */

@@ -29,7 +29,8 @@ FUNCTIONS = (
     "qmc_abi_version", "qmc_last_error", "qmc_system_create", "qmc_system_destroy",
     "qmc_walkers_create", "qmc_walkers_destroy", "qmc_eval_batch", "qmc_propose_move",
     "qmc_accept_move", "qmc_vmc_steps", "qmc_walkers_read", "qmc_walkers_set_timing",
-    "qmc_walkers_timing", "qmc_forces", "qmc_system_set_params",
+    "qmc_walkers_timing", "qmc_forces", "qmc_system_set_params", "qmc_multi_create",
+    "qmc_multi_destroy", "qmc_multi_autotune", "qmc_multi_vmc_steps", "qmc_philox_draws",
 )
 
 TIMER_NAMES = ("basis", "P_build", "W_build", "LU", "Y_build", "rowdot", "assemble", "propose",
@@ -88,6 +89,12 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.qmc_walkers_timing.argtypes = [vp, vp, vp]
     lib.qmc_forces.argtypes = [vp, vp, dp, i32, dp, dp, ctypes.POINTER(Grads), vp]
     lib.qmc_system_set_params.argtypes = [vp, dp, dp, dp, dp, vp]
+    lib.qmc_multi_create.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp)]
+    lib.qmc_multi_destroy.argtypes = [vp]
+    lib.qmc_multi_autotune.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), vp]
+    lib.qmc_multi_vmc_steps.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_uint64,
+                                        ctypes.c_double, i32, vp]
+    lib.qmc_philox_draws.argtypes = [ctypes.c_uint64, i32, i32, ctypes.c_uint64, ctypes.c_double, dp, dp, vp]
     _lib = lib
     return lib
 
@@ -271,3 +278,52 @@ class JAGPFunction(torch.autograd.Function):
         ge = None if g_eloc is None else g_eloc.contiguous()
         g = wk.forces(r.contiguous(), gl, ge)
         return None, g["r"], g["R"], g["zeta"], g["lam"], g["jas"]
+
+
+def philox_draws(seed: int, member: int, n_walkers: int, step: int, sigma: float, stream=None):
+    """Device Philox4x32-10 draws of one step: (disp [Wk,3], unif [Wk])."""
+    disp = torch.empty(n_walkers, 3, dtype=torch.float64, device="cuda")
+    unif = torch.empty(n_walkers, dtype=torch.float64, device="cuda")
+    _check(load().qmc_philox_draws(seed, member, n_walkers, step, sigma, _ptr(disp), _ptr(unif), _stream(stream)))
+    return disp, unif
+
+
+class MultiSystem:
+    """Several (JAGPSystem, Walkers) pairs moved together by persistent launches."""
+
+    def __init__(self, walkers_list):
+        self.members = list(walkers_list)
+        n = len(self.members)
+        sh = (ctypes.c_void_p * n)(*[w.sys.h for w in self.members])
+        wh = (ctypes.c_void_p * n)(*[w.h for w in self.members])
+        h = ctypes.c_void_p()
+        _check(load().qmc_multi_create(n, sh, wh, ctypes.byref(h)))
+        self.h = h
+
+    def autotune(self, stream=None):
+        r = ctypes.c_int32()
+        g = ctypes.c_int32()
+        _check(load().qmc_multi_autotune(self.h, ctypes.byref(r), ctypes.byref(g), _stream(stream)))
+        return r.value, g.value
+
+    def vmc_steps(self, n_steps: int, disp=None, unif=None, seed: int = 0, sigma: float = 0.3,
+                  use_graph: bool = False, stream=None):
+        n = len(self.members)
+        if disp is not None:
+            dp = (ctypes.c_void_p * n)(*[_ptr(d).value for d in disp])
+            up = (ctypes.c_void_p * n)(*[_ptr(u).value for u in unif])
+        else:
+            dp = up = None
+        _check(load().qmc_multi_vmc_steps(self.h, n_steps, dp, up, seed, sigma, 1 if use_graph else 0,
+                                          _stream(stream)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            _check(load().qmc_multi_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -17,6 +17,7 @@ namespace qmc {
 constexpr int kMaxNuc = 4096;
 constexpr int kLuMaxN = 128;      // LDS-resident Gauss-Jordan inverse limit
 constexpr int kPropRows = 16;     // rows of P per proposal workgroup
+constexpr int kPropRowsMin = 8;   // smallest rows-per-workgroup the autotuner may pick
 constexpr int kMaxNucBack = 256;  // nuclei handled by the Jastrow backward kernel
 
 inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
@@ -94,6 +95,30 @@ struct AdjWork {
   int chunk_walkers;
   int chunks;
 };
+// Arguments of the persistent multi-system phase kernels.
+struct MultiArgs {
+  const SysDev* sysv;             // [members] device copies
+  const WalkDev* wkv;             // [members]
+  const long long* steps;         // [members] attempted moves so far (device)
+  const int* rows;                // [members] P rows per proposal work item
+  const double* const* disp;      // [members] explicit displacements [n_steps][Wk][3], or null
+  const double* const* unif;      // [members] explicit uniforms [n_steps][Wk], or null
+  int t;                          // step index within the call (explicit arrays)
+  unsigned long long seed;        // Philox key
+  double sigma;                   // displacement width
+};
+hipError_t launch_multi_prep(const MultiArgs& a, const int2* items, int n_items, int grid, hipStream_t st);
+hipError_t launch_multi_rows(const MultiArgs& a, bool f32, int nc, const int4* items, int n_items, int grid,
+                             hipStream_t st);
+hipError_t launch_multi_accept(const MultiArgs& a, bool f32, int qmax, const int2* items, int n_items, int grid,
+                               hipStream_t st);
+hipError_t launch_multi_advance(long long* steps, int n, hipStream_t st);
+hipError_t prepare_multi_lu(size_t shm);
+hipError_t launch_multi_lu(const SysDev* sysv, const WalkDev* wkv, const int2* items, int n_items,
+                           unsigned mask, size_t shm, int grid, hipStream_t st);
+hipError_t launch_philox_draws(unsigned long long seed, int member, int Wk, unsigned long long step, double sigma,
+                               double* disp, double* unif, hipStream_t st);
+
 hipError_t launch_forces(const SysDev& s, const WalkDev& w, const AdjWork& aw, const double* ga,
                          const double* gb, int per_walker, double* dR, double* dzeta, double* dlambda,
                          double* djas, double* dr, hipStream_t st);

@@ -16,10 +16,10 @@
 
 namespace qmc {
 
-__global__ void __launch_bounds__(256)
-gj_inverse_kernel(const double* __restrict__ Wg, double* __restrict__ Ag, double* __restrict__ logdet,
-                  double* __restrict__ detsign, int* __restrict__ singular, int n, long w_bs, long a_bs) {
-  extern __shared__ double smem[];
+// One matrix per workgroup: W (n x n) -> A = W^{-1}, log|det W| and sign in
+// *logdet, *detsign (singular: *singular = 1).  smem holds n (n+1) + 2n doubles.
+__device__ void gj_lds_body(const double* __restrict__ W, double* __restrict__ A, double* __restrict__ logdet,
+                            double* __restrict__ detsign, int* __restrict__ singular, int n, double* smem) {
   const int ld = n + 1;
   double* M = smem;                 // n x ld
   double* rk = M + (long)n * ld;    // scaled pivot row
@@ -27,8 +27,6 @@ gj_inverse_kernel(const double* __restrict__ Wg, double* __restrict__ Ag, double
   __shared__ int perm[kLuMaxN];
   __shared__ int piv_s;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const double* W = Wg + blockIdx.x * w_bs;
-  double* A = Ag + blockIdx.x * a_bs;
 
   for (int idx = tid; idx < n * n; idx += blockDim.x) M[(idx / n) * ld + (idx % n)] = W[idx];
 
@@ -103,10 +101,18 @@ gj_inverse_kernel(const double* __restrict__ Wg, double* __restrict__ Ag, double
   for (int idx = tid; idx < n * n; idx += blockDim.x)
     A[idx] = sing ? nanv : M[(idx / n) * ld + (idx % n)];
   if (tid == 0) {
-    logdet[blockIdx.x] = sing ? -__builtin_inf() : lsum;
-    detsign[blockIdx.x] = sing ? 0.0 : sg;
-    singular[blockIdx.x] = sing;
+    *logdet = sing ? -__builtin_inf() : lsum;
+    *detsign = sing ? 0.0 : sg;
+    *singular = sing;
   }
+}
+
+__global__ void __launch_bounds__(256)
+gj_inverse_kernel(const double* __restrict__ Wg, double* __restrict__ Ag, double* __restrict__ logdet,
+                  double* __restrict__ detsign, int* __restrict__ singular, int n, long w_bs, long a_bs) {
+  extern __shared__ double smem[];
+  const long b = blockIdx.x;
+  gj_lds_body(Wg + b * w_bs, Ag + b * a_bs, logdet + b, detsign + b, singular + b, n, smem);
 }
 
 // Register-resident variant (the default).  Thread t keeps column c = t % n of
@@ -117,9 +123,8 @@ gj_inverse_kernel(const double* __restrict__ Wg, double* __restrict__ Ag, double
 //   W^{-1}[k][p_k'] = T[p_k][k']   and   det W = sgn(p) prod_k T_k[p_k][k],
 // sgn(p) the parity of the permutation k -> p_k.
 template <int QMAX>
-__global__ void __launch_bounds__(256)
-gj_inverse_reg_kernel(const double* __restrict__ Wg, double* __restrict__ Ag, double* __restrict__ logdet,
-                      double* __restrict__ detsign, int* __restrict__ singular, int n, long w_bs, long a_bs) {
+__device__ void gj_reg_body(const double* __restrict__ W, double* __restrict__ A, double* __restrict__ logdet,
+                            double* __restrict__ detsign, int* __restrict__ singular, int n) {
   __shared__ double rk[kLuMaxN];
   __shared__ double ck[kLuMaxN];
   __shared__ int used[kLuMaxN];
@@ -132,8 +137,6 @@ gj_inverse_reg_kernel(const double* __restrict__ Wg, double* __restrict__ Ag, do
   const int tid = threadIdx.x;
   const int G = blockDim.x / n, c = tid % n, g = tid / n;
   const bool own = g < G;
-  const double* W = Wg + blockIdx.x * w_bs;
-  double* A = Ag + blockIdx.x * a_bs;
   double a[QMAX];
 #pragma unroll
   for (int q = 0; q < QMAX; ++q) {
@@ -237,10 +240,18 @@ gj_inverse_reg_kernel(const double* __restrict__ Wg, double* __restrict__ Ag, do
     for (int idx = tid; idx < n * n; idx += blockDim.x) A[idx] = nanv;
   }
   if (tid == 0) {
-    logdet[blockIdx.x] = sing ? -__builtin_inf() : lsum;
-    detsign[blockIdx.x] = sing ? 0.0 : sg;
-    singular[blockIdx.x] = sing;
+    *logdet = sing ? -__builtin_inf() : lsum;
+    *detsign = sing ? 0.0 : sg;
+    *singular = sing;
   }
+}
+
+template <int QMAX>
+__global__ void __launch_bounds__(256)
+gj_inverse_reg_kernel(const double* __restrict__ Wg, double* __restrict__ Ag, double* __restrict__ logdet,
+                      double* __restrict__ detsign, int* __restrict__ singular, int n, long w_bs, long a_bs) {
+  const long b = blockIdx.x;
+  gj_reg_body<QMAX>(Wg + b * w_bs, Ag + b * a_bs, logdet + b, detsign + b, singular + b, n);
 }
 
 hipError_t launch_lu_inverse_lds(const SysDev& s, const WalkDev& w, hipStream_t st);
@@ -273,6 +284,47 @@ hipError_t launch_lu_inverse_lds(const SysDev& s, const WalkDev& w, hipStream_t 
   }
   hipLaunchKernelGGL(gj_inverse_kernel, dim3(w.Wk), dim3(256), shm, st, w.W, w.A, w.logdet,
                      w.detsign, w.singular, n, (long)s.nu * s.nd, (long)s.nd * s.nu);
+  return hipGetLastError();
+}
+
+// Persistent refresh over (member, walker) items of several systems; members
+// not in `mask` are skipped.  The LU variant per member is the one the
+// one-system refresh uses, so the results are identical.
+__global__ void __launch_bounds__(256)
+multi_lu_kernel(const SysDev* __restrict__ sysv, const WalkDev* __restrict__ wkv, const int2* __restrict__ items,
+                int n_items, unsigned mask) {
+  extern __shared__ double smem[];
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    __syncthreads();
+    const int k = items[it].x, w = items[it].y;
+    if (!((mask >> k) & 1u)) continue;
+    const SysDev& s = sysv[k];
+    const WalkDev& wd = wkv[k];
+    const int n = s.nu;
+    const int G = 256 / n, Q = (n + G - 1) / G;
+    const double* W = wd.W + (long)w * n * n;
+    double* A = wd.A + (long)w * n * n;
+    if (Q <= 8) gj_reg_body<8>(W, A, wd.logdet + w, wd.detsign + w, wd.singular + w, n);
+    else gj_lds_body(W, A, wd.logdet + w, wd.detsign + w, wd.singular + w, n, smem);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const int sing = wd.singular[w];
+      wd.logabs[w] = sing ? -__builtin_inf() : wd.logdet[w] + wd.J[w];
+      wd.sign[w] = wd.detsign[w];
+    }
+  }
+}
+
+hipError_t prepare_multi_lu(size_t shm) {
+  if (shm <= 64 * 1024) return hipSuccess;
+  return hipFuncSetAttribute((const void*)multi_lu_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+}
+
+// (prepare_multi_lu must have been called for shm beforehand: this launch may be
+// inside a captured graph.)
+hipError_t launch_multi_lu(const SysDev* sysv, const WalkDev* wkv, const int2* items, int n_items,
+                           unsigned mask, size_t shm, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(multi_lu_kernel, dim3(grid), dim3(256), shm, st, sysv, wkv, items, n_items, mask);
   return hipGetLastError();
 }
 

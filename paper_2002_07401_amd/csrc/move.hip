@@ -19,217 +19,37 @@
 // many blocks are in flight, and every block writes a partial determinant
 // ratio, which the accept kernel (device Metropolis) or the finalize kernel
 // (host-driven moves) sums in a fixed order.
-#include "internal.h"
+#include "move_dev.h"
 
 namespace qmc {
 
-__device__ double block_sum_mv(double v, double* red) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  v = wave_sum(v);
-  __syncthreads();
-  if (lane == 0) red[wave] = v;
-  __syncthreads();
-  double t = 0.0;
-  for (int k = 0; k < nw; ++k) t += red[k];
-  __syncthreads();
-  return t;
-}
-
-// Jastrow terms of electron e at position p, summed over this thread's share
-// of nuclei and electrons: value and gradient.
-__device__ void jastrow_one(const SysDev& s, const double* r, int e, double px, double py, double pz,
-                            bool want_grad, double& val, double& gx, double& gy, double& gz) {
-  val = 0.0; gx = gy = gz = 0.0;
-  if (s.j1_form) {
-    for (int a = threadIdx.x; a < s.n_nuc; a += blockDim.x) {
-      const double dx = px - s.R[3 * a], dy = py - s.R[3 * a + 1], dz = pz - s.R[3 * a + 2];
-      const double ria = sqrt(dx * dx + dy * dy + dz * dz);
-      double f, f1, f2;
-      j1_radial(s.j1_form, s.Z[a], s.j1_b[a], ria, f, f1, f2);
-      val += f;
-      if (want_grad) { const double q = f1 / ria; gx += q * dx; gy += q * dy; gz += q * dz; }
-    }
-  }
-  if (s.j2_form) {
-    const bool up_e = e < s.nu;
-    for (int j = threadIdx.x; j < s.N; j += blockDim.x) {
-      if (j == e) continue;
-      const double dx = px - r[3 * j], dy = py - r[3 * j + 1], dz = pz - r[3 * j + 2];
-      const double rij = sqrt(dx * dx + dy * dy + dz * dz);
-      double v, v1, v2;
-      j2_radial(s.j2_form, s.j2, up_e == (j < s.nu), rij, v, v1, v2);
-      val += v;
-      if (want_grad) { const double q = v1 / rij; gx += q * dx; gy += q * dy; gz += q * dz; }
-    }
-  }
-}
-
-// Step 1 of a proposal, one workgroup per walker: the new position, the basis
-// values psi(r') (zero-padded to Lp, and their gradients when a drift is
-// requested) and the Jastrow change J(x') - J(x) (and grad J at r').
 template <bool DRIFT>
 __global__ void __launch_bounds__(256)
 propose_prep_kernel(SysDev s, WalkDev w, int e, const double* __restrict__ r_new_in,
                     const double* __restrict__ disp) {
-  __shared__ double red[8];
-  __shared__ double rn[3];
-  const int wk = blockIdx.x, tid = threadIdx.x;
-  const double* r = w.r + (long)wk * s.N * 3;
-  if (tid < 3) {
-    rn[tid] = disp ? r[3 * e + tid] + disp[3 * (long)wk + tid] : r_new_in[3 * (long)wk + tid];
-    w.r_new[3 * wk + tid] = rn[tid];
-  }
-  __syncthreads();
-  const double px = rn[0], py = rn[1], pz = rn[2];
-  double* psi = w.psi_new + (long)wk * s.Lp;
-  double* gpsi = w.gpsi_new + (long)wk * 3 * s.Lp;
-  for (int mu = tid; mu < s.Lp; mu += blockDim.x) {
-    if (mu >= s.L) {
-      psi[mu] = 0.0;
-      if (DRIFT) { gpsi[mu] = 0.0; gpsi[s.Lp + mu] = 0.0; gpsi[2 * s.Lp + mu] = 0.0; }
-    } else if (DRIFT) {
-      double v, gx, gy, gz, lp;
-      basis_vgl(s, mu, px, py, pz, v, gx, gy, gz, lp);
-      psi[mu] = v; gpsi[mu] = gx; gpsi[s.Lp + mu] = gy; gpsi[2 * s.Lp + mu] = gz;
-    } else {
-      psi[mu] = basis_value(s, mu, px, py, pz);
-    }
-  }
-  double jn, gxn, gyn, gzn, jo, d0, d1, d2;
-  jastrow_one(s, r, e, px, py, pz, DRIFT, jn, gxn, gyn, gzn);
-  jastrow_one(s, r, e, r[3 * e], r[3 * e + 1], r[3 * e + 2], false, jo, d0, d1, d2);
-  const double dJ = block_sum_mv(jn - jo, red);
-  if (DRIFT) {
-    gxn = block_sum_mv(gxn, red); gyn = block_sum_mv(gyn, red); gzn = block_sum_mv(gzn, red);
-  }
-  if (tid == 0) {
-    w.dJ[wk] = dJ;
-    if (DRIFT) { w.gJ_new[3 * wk] = gxn; w.gJ_new[3 * wk + 1] = gyn; w.gJ_new[3 * wk + 2] = gzn; }
-  }
+  const int wk = blockIdx.x;
+  prep_body<DRIFT>(s, w, wk, e, r_new_in ? r_new_in + 3 * (long)wk : nullptr,
+                   disp ? disp + 3 * (long)wk : nullptr);
 }
 
-template <typename T> struct Vec16;
-template <> struct Vec16<double> { typedef double2 type; static constexpr int n = 2; };
-template <> struct Vec16<float> { typedef float4 type; static constexpr int n = 4; };
-
-__device__ __forceinline__ double vget(const double2& v, int i) { return i == 0 ? v.x : v.y; }
-__device__ __forceinline__ double vget(const float4& v, int i) {
-  return (double)(i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w)));
-}
-
-// Combine the per-wave (lane 0) partial ratios of one block into rdet_part.
-__device__ __forceinline__ void block_partial(double part, double gx, double gy, double gz, bool drift,
-                                              WalkDev& w, int wk, int S, int sb) {
-  __shared__ double red[16];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  if (lane == 0) {
-    red[wave] = part;
-    if (drift) { red[4 + wave] = gx; red[8 + wave] = gy; red[12 + wave] = gz; }
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = 0.0, tx = 0.0, ty = 0.0, tz = 0.0;
-    for (int k = 0; k < nw; ++k) {
-      t += red[k];
-      if (drift) { tx += red[4 + k]; ty += red[8 + k]; tz += red[12 + k]; }
-    }
-    w.rdet_part[(long)wk * S + sb] = t;
-    if (drift) {
-      double* g = w.gdet_part + ((long)wk * S + sb) * 3;
-      g[0] = tx; g[1] = ty; g[2] = tz;
-    }
-  }
-}
-
-// Step 2, streaming kernel: block (sb, wk) computes the new W entries of rows
-// [sb*kPropRows, (sb+1)*kPropRows) of the opposite spin of walker wk and their
-// contribution to the determinant ratio.  One wave per row; psi(r') chunks sit
-// in registers and each row is read with NC independent 16-byte loads per lane.
+// grid (S, Wk): block (sb, wk) handles rows [sb*kPropRows, (sb+1)*kPropRows) of walker wk.
 template <typename T, int NC>
-__global__ void __launch_bounds__(256)
-propose_rows_kernel(SysDev s, WalkDev w, int e) {
-  typedef typename Vec16<T>::type V;
-  constexpr int VN = Vec16<T>::n;
-  constexpr int STEP = 64 * VN;
-  const int sb = blockIdx.x, wk = blockIdx.y, S = gridDim.x;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
-  const bool up = e < s.nu;
-  const int row0 = up ? s.nu : 0;
-  const int nrow = up ? s.nd : s.nu;
-  const int nmax = s.nu > s.nd ? s.nu : s.nd;
-  const T* Pw = (const T*)w.P + ((long)wk * s.N + row0) * s.Lp;
-  const double* Aw = w.A + (long)wk * s.nd * s.nu;
-  double* wn_g = w.w_new + (long)wk * nmax;
-  const double* psi = w.psi_new + (long)wk * s.Lp;
-  double ps[NC][VN];
-#pragma unroll
-  for (int c = 0; c < NC; ++c) {
-    const int i0 = c * STEP + lane * VN;
-#pragma unroll
-    for (int v = 0; v < VN; ++v) ps[c][v] = (i0 < s.Lp) ? psi[i0 + v] : 0.0;
-  }
-  const int j0 = sb * kPropRows;
-  const int j1 = min(j0 + kPropRows, nrow);
-  double part = 0.0;
-  for (int j = j0 + wave; j < j1; j += nw) {
-    const T* prow = Pw + (long)j * s.Lp;
-    V pv[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      const int i0 = c * STEP + lane * VN;
-      if (i0 < s.Lp) pv[c] = *reinterpret_cast<const V*>(prow + i0);
-      else pv[c] = V{};
-    }
-    double acc = 0.0;
-#pragma unroll
-    for (int c = 0; c < NC; ++c)
-#pragma unroll
-      for (int v = 0; v < VN; ++v) acc += vget(pv[c], v) * ps[c][v];
-    acc = wave_sum(acc);
-    if (lane == 0) {
-      wn_g[j] = acc;
-      part += acc * (up ? Aw[(long)j * s.nu + e] : Aw[(long)(e - s.nu) * s.nu + j]);
-    }
-  }
-  block_partial(part, 0.0, 0.0, 0.0, false, w, wk, S, sb);
+__global__ void __launch_bounds__(256) propose_rows_kernel(SysDev s, WalkDev w, int e) {
+  rows_body<T, NC>(s, w, blockIdx.y, blockIdx.x, gridDim.x, e, kPropRows);
 }
 
-// Generic streaming kernel (any Lp; optional gradients for the drift at r').
 template <typename T, bool DRIFT>
+__global__ void __launch_bounds__(256) propose_rows_generic_kernel(SysDev s, WalkDev w, int e) {
+  rows_generic_body<T, DRIFT>(s, w, blockIdx.y, blockIdx.x, gridDim.x, e, kPropRows);
+}
+
+template <typename T, int QMAX>
 __global__ void __launch_bounds__(256)
-propose_rows_generic_kernel(SysDev s, WalkDev w, int e) {
-  const int sb = blockIdx.x, wk = blockIdx.y, S = gridDim.x;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
-  const bool up = e < s.nu;
-  const int row0 = up ? s.nu : 0;
-  const int nrow = up ? s.nd : s.nu;
-  const int nmax = s.nu > s.nd ? s.nu : s.nd;
-  const T* Pw = (const T*)w.P + ((long)wk * s.N + row0) * s.Lp;
-  const double* Aw = w.A + (long)wk * s.nd * s.nu;
-  double* wn_g = w.w_new + (long)wk * nmax;
-  const double* psi = w.psi_new + (long)wk * s.Lp;
-  const double* gpsi = w.gpsi_new + (long)wk * 3 * s.Lp;
-  const int j0 = sb * kPropRows;
-  const int j1 = min(j0 + kPropRows, nrow);
-  double part = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
-  for (int j = j0 + wave; j < j1; j += nw) {
-    const T* prow = Pw + (long)j * s.Lp;
-    double a0 = 0.0, ax = 0.0, ay = 0.0, az = 0.0;
-    for (int mu = lane; mu < s.Lp; mu += 64) {
-      const double p = (double)prow[mu];
-      a0 += p * psi[mu];
-      if (DRIFT) { ax += p * gpsi[mu]; ay += p * gpsi[s.Lp + mu]; az += p * gpsi[2 * s.Lp + mu]; }
-    }
-    a0 = wave_sum(a0);
-    if (DRIFT) { ax = wave_sum(ax); ay = wave_sum(ay); az = wave_sum(az); }
-    if (lane == 0) {
-      wn_g[j] = a0;
-      const double a = up ? Aw[(long)j * s.nu + e] : Aw[(long)(e - s.nu) * s.nu + j];
-      part += a0 * a;
-      if (DRIFT) { gx += ax * a; gy += ay * a; gz += az * a; }
-    }
-  }
-  block_partial(part, gx, gy, gz, DRIFT, w, wk, S, sb);
+accept_kernel(SysDev s, WalkDev w, int e, const uint8_t* __restrict__ acc_in,
+              const double* __restrict__ unif, int32_t* __restrict__ accept_count, int S) {
+  const int wk = blockIdx.x;
+  accept_body<T, QMAX>(s, w, wk, e, unif ? 1 : 0, acc_in ? acc_in + wk : nullptr, unif ? unif[wk] : 0.0,
+                       accept_count ? accept_count + wk : nullptr, S);
 }
 
 // Sum the partial ratios (fixed order) for host-driven proposals.
@@ -295,141 +115,6 @@ hipError_t launch_propose_rows(const SysDev& s, const WalkDev& w, int e, double*
   hipLaunchKernelGGL(propose_finalize_kernel, dim3((w.Wk + 255) / 256), dim3(256), 0, st, w, S, ratio,
                      drift_new);
   return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// Accept: decide (device Metropolis, u < ratio^2, when unif is given) and
-// apply the rank-1 Sherman-Morrison update of A = W^{-1} in FP64:
-//   up e   (row e of W replaced by w'):    A <- A - A[:,e] (delta^T A) / R
-//   down e (column e of W replaced by w'): A <- A - (A delta) A[e,:] / R
-// with delta = w' - (old row/column) and R = det W'/det W.  Thread t holds
-// column c = t % n of rows g, g+G, ... (g = t / n, G = blockDim / n) in
-// registers: A is read once and written once.  Column sums (up moves) reduce
-// through LDS over the G groups; row sums (down moves) are wave dot products
-// over the rows (served from cache, the rows having just been read).
-// S > 0: the ratio is first summed from the proposal's S partial sums.
-// ---------------------------------------------------------------------------
-template <typename T, int QMAX>
-__global__ void __launch_bounds__(256)
-accept_kernel(SysDev s, WalkDev w, int e, const uint8_t* __restrict__ acc_in,
-              const double* __restrict__ unif, int32_t* __restrict__ accept_count, int S) {
-  __shared__ double delta[kLuMaxN];
-  __shared__ double save[kLuMaxN];
-  __shared__ double coef[kLuMaxN];
-  __shared__ double part[256];
-  __shared__ double R_s;
-  __shared__ int acc_s;
-  const int n = s.nu;             // square: n_up == n_dn
-  const int wk = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int nw = blockDim.x >> 6;
-  if (tid == 0) {
-    double R;
-    if (S > 0) {
-      R = 0.0;
-      for (int k = 0; k < S; ++k) R += w.rdet_part[(long)wk * S + k];
-      w.rdet[wk] = R;
-      w.ratio[wk] = R * exp(w.dJ[wk]);
-    } else {
-      R = w.rdet[wk];
-    }
-    bool acc;
-    if (unif) {
-      const double q = w.ratio[wk];
-      acc = unif[wk] < q * q;
-    } else {
-      acc = acc_in[wk] != 0;
-    }
-    w.acc[wk] = acc ? 1 : 0;
-    R_s = R;
-    acc_s = acc;
-  }
-  __syncthreads();
-  if (!acc_s) return;
-  const double invR = 1.0 / R_s;
-  const bool up = e < s.nu;
-  const int ed = e - s.nu;
-  double* Aw = w.A + (long)wk * n * n;
-  double* Ww = w.W + (long)wk * n * n;
-  const double* wn = w.w_new + (long)wk * n;
-  const int G = blockDim.x / n, c = tid % n, g = tid / n;
-  const bool own = g < G;
-  double a[QMAX];
-#pragma unroll
-  for (int q = 0; q < QMAX; ++q) {
-    const int j = g + G * q;
-    a[q] = (own && j < n) ? Aw[(long)j * n + c] : 0.0;
-  }
-  for (int j = tid; j < n; j += blockDim.x)
-    delta[j] = up ? wn[j] - Ww[(long)e * n + j] : wn[j] - Ww[(long)j * n + ed];
-  __syncthreads();
-  if (up) {
-    double t = 0.0;
-#pragma unroll
-    for (int q = 0; q < QMAX; ++q) {
-      const int j = g + G * q;
-      if (own && j < n) t += delta[j] * a[q];
-    }
-    if (own) part[g * n + c] = t;
-    if (own && c == e) {
-#pragma unroll
-      for (int q = 0; q < QMAX; ++q) {
-        const int j = g + G * q;
-        if (j < n) save[j] = a[q];
-      }
-    }
-    __syncthreads();
-    for (int k = tid; k < n; k += blockDim.x) {
-      double u = 0.0;
-      for (int q = 0; q < G; ++q) u += part[q * n + k];
-      coef[k] = u * invR;
-    }
-    __syncthreads();
-    if (own) {
-      const double ck = coef[c];
-#pragma unroll
-      for (int q = 0; q < QMAX; ++q) {
-        const int j = g + G * q;
-        if (j < n) Aw[(long)j * n + c] = a[q] - save[j] * ck;
-      }
-    }
-    for (int j = tid; j < n; j += blockDim.x) Ww[(long)e * n + j] = wn[j];
-  } else {
-    for (int j = wave; j < n; j += nw) {
-      double t = 0.0;
-      for (int i = lane; i < n; i += 64) t += Aw[(long)j * n + i] * delta[i];
-      t = wave_sum(t);
-      if (lane == 0) coef[j] = t * invR;
-    }
-    if (own && g == ed % G) {
-      const int qe = ed / G;
-      double v = 0.0;
-#pragma unroll
-      for (int q = 0; q < QMAX; ++q) if (q == qe) v = a[q];
-      save[c] = v;
-    }
-    __syncthreads();
-    if (own) {
-      const double sc = save[c];
-#pragma unroll
-      for (int q = 0; q < QMAX; ++q) {
-        const int j = g + G * q;
-        if (j < n) Aw[(long)j * n + c] = a[q] - coef[j] * sc;
-      }
-    }
-    for (int i = tid; i < n; i += blockDim.x) Ww[(long)i * n + ed] = wn[i];
-  }
-  T* prow = (T*)w.phi + ((long)wk * s.N + e) * s.Lp;
-  const double* pn = w.psi_new + (long)wk * s.Lp;
-  for (int mu = tid; mu < s.L; mu += blockDim.x) prow[mu] = (T)pn[mu];
-  if (tid == 0) {
-    double* re = w.r + ((long)wk * s.N + e) * 3;
-    re[0] = w.r_new[3 * wk]; re[1] = w.r_new[3 * wk + 1]; re[2] = w.r_new[3 * wk + 2];
-    const double dJ = w.dJ[wk];
-    w.logabs[wk] += log(fabs(R_s)) + dJ;
-    if (R_s < 0.0) w.sign[wk] = -w.sign[wk];
-    w.J[wk] += dJ;
-    if (accept_count) accept_count[wk] += 1;
-  }
 }
 
 template <typename T>

@@ -3,7 +3,10 @@
 // evaluation, move and Metropolis calls.
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
+#include <map>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -261,7 +264,7 @@ extern "C" qmc_status qmc_walkers_create(qmc_system* sys, int32_t n_walkers, qmc
   al((void**)&d.r_new, sizeof(double) * Wk * 3);
   al((void**)&d.ratio, sizeof(double) * Wk);
   al((void**)&d.acc, sizeof(uint8_t) * Wk);
-  const size_t S = propose_splits(s);
+  const size_t S = (nmax + kPropRowsMin - 1) / kPropRowsMin;
   al((void**)&d.rdet_part, sizeof(double) * Wk * S);
   al((void**)&d.gdet_part, sizeof(double) * Wk * S * 3);
   al((void**)&d.gJ_new, sizeof(double) * Wk * 3);
@@ -511,5 +514,321 @@ extern "C" qmc_status qmc_system_set_params(qmc_system* sys, const double* R, co
     }
   }
   sys->generation += 1;
+  return QMC_OK;
+}
+
+// ===========================================================================
+// multi-system groups
+// ===========================================================================
+struct qmc_multi {
+  int n = 0;
+  std::vector<qmc_system*> sys;
+  std::vector<qmc_walkers*> wk;
+  std::vector<SysDev> h_sys;
+  std::vector<WalkDev> h_wk;
+  std::vector<long long> h_steps;
+  std::vector<const double*> h_disp, h_unif;
+  std::vector<int> order;        // members by decreasing cost
+  std::vector<int> rows;         // rows per proposal item, per member
+  SysDev* d_sys = nullptr;
+  WalkDev* d_wk = nullptr;
+  long long* d_steps = nullptr;
+  int* d_rows = nullptr;
+  const double** d_disp = nullptr;
+  const double** d_unif = nullptr;
+  int2* d_items = nullptr;
+  int n_items = 0;
+  int4* d_rows_items = nullptr;
+  int n_rows_items = 0, rows_cap = 0;
+  int grid_rows = 2048, grid_items = 1024;
+  int nc = 1, qmax = 4;
+  size_t lu_shm = 0;
+  bool f32 = false;
+  hipStream_t own = nullptr;
+  hipEvent_t ev_a = nullptr, ev_b = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::string gkey;
+  std::vector<void*> allocs;
+  ~qmc_multi() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (ev_a) (void)hipEventDestroy(ev_a);
+    if (ev_b) (void)hipEventDestroy(ev_b);
+    if (own) { (void)hipStreamSynchronize(own); (void)hipStreamDestroy(own); }
+    for (void* p : allocs) (void)hipFree(p);
+  }
+};
+
+static hipError_t multi_build_rows(qmc_multi* m) {
+  std::vector<int4> items;
+  for (int k : m->order) {
+    const SysDev& s = m->h_sys[k];
+    const int S = (s.nu + m->rows[k] - 1) / m->rows[k];
+    for (int w = 0; w < m->h_wk[k].Wk; ++w)
+      for (int sb = 0; sb < S; ++sb) items.push_back(make_int4(k, w, sb, S));
+  }
+  if ((int)items.size() > m->rows_cap) {
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, sizeof(int4) * items.size());
+    if (e != hipSuccess) return e;
+    m->allocs.push_back(p);
+    m->d_rows_items = (int4*)p;
+    m->rows_cap = (int)items.size();
+  }
+  m->n_rows_items = (int)items.size();
+  hipError_t e = hipMemcpy(m->d_rows_items, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return e;
+  return hipMemcpy(m->d_rows, m->rows.data(), sizeof(int) * m->n, hipMemcpyHostToDevice);
+}
+
+extern "C" qmc_status qmc_multi_create(int32_t n_members, qmc_system* const* systems, qmc_walkers* const* walkers,
+                                       qmc_multi** out) {
+  if (!systems || !walkers || !out) return fail(QMC_ERR_ARG, "null argument");
+  if (n_members < 1 || n_members > 32) return fail(QMC_ERR_ARG, "1..32 members");
+  *out = nullptr;
+  auto* m = new qmc_multi();
+  m->n = n_members;
+  for (int k = 0; k < n_members; ++k) {
+    if (check_pair(systems[k], walkers[k])) { delete m; return QMC_ERR_ARG; }
+    const SysDev& s = systems[k]->d;
+    if (s.precision != systems[0]->d.precision) { delete m; return fail(QMC_ERR_ARG, "members differ in precision"); }
+    if (s.nu != s.nd || s.nu > kLuMaxN) { delete m; return fail(QMC_ERR_UNSUPPORTED, "members need n_up == n_dn <= 128"); }
+    m->sys.push_back(systems[k]);
+    m->wk.push_back(walkers[k]);
+    m->h_sys.push_back(s);
+    m->h_wk.push_back(walkers[k]->d);
+    m->rows.push_back(kPropRows);
+  }
+  m->f32 = systems[0]->d.precision == QMC_W_FP32;
+  m->order.resize(n_members);
+  std::iota(m->order.begin(), m->order.end(), 0);
+  std::stable_sort(m->order.begin(), m->order.end(), [&](int a, int b) {
+    const SysDev &x = m->h_sys[a], &y = m->h_sys[b];
+    return (long)x.L * x.nu > (long)y.L * y.nu;
+  });
+  const int vec = m->f32 ? 256 : 128;
+  std::vector<int2> items;
+  for (int k : m->order) {
+    const SysDev& s = m->h_sys[k];
+    m->nc = std::max(m->nc, (s.Lp + vec - 1) / vec);
+    const int G = 256 / s.nu, Q = (s.nu + G - 1) / G;
+    m->qmax = std::max(m->qmax, Q);
+    if (Q > 8) m->lu_shm = std::max(m->lu_shm, ((size_t)s.nu * (s.nu + 1) + 2 * (size_t)s.nu) * sizeof(double));
+    for (int w = 0; w < m->h_wk[k].Wk; ++w) items.push_back(make_int2(k, w));
+  }
+  if (m->nc > 8) { delete m; return fail(QMC_ERR_UNSUPPORTED, "members need L <= 1024 (FP64) or 2048 (FP32)"); }
+  m->n_items = (int)items.size();
+  m->grid_items = std::min(m->n_items, 2048);
+  hipError_t e = hipSuccess;
+  auto al = [&](void** p, size_t bytes) {
+    if (e != hipSuccess) return;
+    e = hipMalloc(p, bytes);
+    if (e == hipSuccess) m->allocs.push_back(*p);
+  };
+  al((void**)&m->d_sys, sizeof(SysDev) * n_members);
+  al((void**)&m->d_wk, sizeof(WalkDev) * n_members);
+  al((void**)&m->d_steps, sizeof(long long) * n_members);
+  al((void**)&m->d_rows, sizeof(int) * n_members);
+  al((void**)&m->d_disp, sizeof(double*) * n_members);
+  al((void**)&m->d_unif, sizeof(double*) * n_members);
+  al((void**)&m->d_items, sizeof(int2) * items.size());
+  if (!e) e = hipMemcpy(m->d_items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice);
+  if (!e) e = hipMemcpy(m->d_wk, m->h_wk.data(), sizeof(WalkDev) * n_members, hipMemcpyHostToDevice);
+  if (!e) e = multi_build_rows(m);
+  if (!e) e = prepare_multi_lu(m->lu_shm);
+  if (!e) e = hipStreamCreateWithFlags(&m->own, hipStreamNonBlocking);
+  if (!e) e = hipEventCreateWithFlags(&m->ev_a, hipEventDisableTiming);
+  if (!e) e = hipEventCreateWithFlags(&m->ev_b, hipEventDisableTiming);
+  m->grid_rows = std::min(m->n_rows_items, 2048);
+  if (e != hipSuccess) { delete m; return hip_fail(e, "multi_create"); }
+  *out = m;
+  return QMC_OK;
+}
+
+extern "C" qmc_status qmc_multi_destroy(qmc_multi* m) {
+  if (!m) return fail(QMC_ERR_ARG, "null group");
+  delete m;
+  return QMC_OK;
+}
+
+// Refresh the device copies of the member descriptors and move counters on
+// the group's stream (not part of any captured graph).
+static hipError_t multi_upload(qmc_multi* m) {
+  m->h_steps.resize(m->n);
+  for (int k = 0; k < m->n; ++k) {
+    m->h_sys[k] = m->sys[k]->d;
+    m->h_steps[k] = m->wk[k]->attempts;
+  }
+  hipError_t e = hipMemcpyAsync(m->d_sys, m->h_sys.data(), sizeof(SysDev) * m->n, hipMemcpyHostToDevice, m->own);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(m->d_steps, m->h_steps.data(), sizeof(long long) * m->n, hipMemcpyHostToDevice, m->own);
+  return e;
+}
+
+// Enqueue n_steps steps on the group's stream; P validity of the members is
+// simulated in up/dn (and returned), so a captured graph and a direct run
+// follow the same schedule.
+static hipError_t multi_enqueue(qmc_multi* m, int n_steps, bool explicit_draws, unsigned long long seed,
+                                double sigma, std::vector<char>& up_ok, std::vector<char>& dn_ok) {
+  MultiArgs a{m->d_sys, m->d_wk, m->d_steps, m->d_rows, explicit_draws ? m->d_disp : nullptr,
+              explicit_draws ? m->d_unif : nullptr, 0, seed, sigma};
+  for (int t = 0; t < n_steps; ++t) {
+    a.t = t;
+    unsigned mask = 0;
+    for (int k = 0; k < m->n; ++k) {
+      const SysDev& s = m->h_sys[k];
+      const long att = m->wk[k]->attempts + t;
+      const int e = (int)(att % s.N);
+      if (e < s.nu && !dn_ok[k]) {
+        hipError_t r = launch_P_build(s, m->h_wk[k], 2, m->own);
+        if (r != hipSuccess) return r;
+        dn_ok[k] = 1;
+      } else if (e >= s.nu && !up_ok[k]) {
+        hipError_t r = launch_P_build(s, m->h_wk[k], 1, m->own);
+        if (r != hipSuccess) return r;
+        up_ok[k] = 1;
+      }
+      if (e < s.nu) up_ok[k] = 0; else dn_ok[k] = 0;
+      if ((att + 1) % s.refresh_every == 0) mask |= 1u << k;
+    }
+    hipError_t r = launch_multi_prep(a, m->d_items, m->n_items, m->grid_items, m->own);
+    if (r == hipSuccess) r = launch_multi_rows(a, m->f32, m->nc, m->d_rows_items, m->n_rows_items, m->grid_rows, m->own);
+    if (r == hipSuccess) r = launch_multi_accept(a, m->f32, m->qmax, m->d_items, m->n_items, m->grid_items, m->own);
+    if (r == hipSuccess && mask)
+      r = launch_multi_lu(m->d_sys, m->d_wk, m->d_items, m->n_items, mask, m->lu_shm, m->grid_items, m->own);
+    if (r == hipSuccess) r = launch_multi_advance(m->d_steps, m->n, m->own);
+    if (r != hipSuccess) return r;
+  }
+  return hipSuccess;
+}
+
+extern "C" qmc_status qmc_multi_vmc_steps(qmc_multi* m, int32_t n_steps, const double* const* disp,
+                                          const double* const* unif, uint64_t seed, double sigma, int32_t use_graph,
+                                          hipStream_t stream) {
+  if (!m) return fail(QMC_ERR_ARG, "null group");
+  if (n_steps < 0) return fail(QMC_ERR_ARG, "negative step count");
+  if ((disp == nullptr) != (unif == nullptr)) return fail(QMC_ERR_ARG, "give both draw arrays or neither");
+  const bool expl = disp != nullptr;
+  if (expl && use_graph) return fail(QMC_ERR_ARG, "graphs are built for the Philox draws");
+  for (int k = 0; k < m->n; ++k) {
+    qmc_walkers* w = m->wk[k];
+    if (!w->evaluated) return fail(QMC_ERR_STATE, "member not evaluated");
+    if (w->generation != m->sys[k]->generation) return fail(QMC_ERR_STATE, "member parameters changed");
+    if (w->pending_e >= 0) return fail(QMC_ERR_STATE, "member has a pending proposal");
+    if (expl && (!disp[k] || !unif[k])) return fail(QMC_ERR_ARG, "null draw array");
+  }
+  if (n_steps == 0) return QMC_OK;
+  HIP_TRY(hipEventRecord(m->ev_a, stream), "event");
+  HIP_TRY(hipStreamWaitEvent(m->own, m->ev_a, 0), "wait");
+  HIP_TRY(multi_upload(m), "upload");
+  if (expl) {
+    m->h_disp.assign(disp, disp + m->n);
+    m->h_unif.assign(unif, unif + m->n);
+    HIP_TRY(hipMemcpyAsync(m->d_disp, m->h_disp.data(), sizeof(double*) * m->n, hipMemcpyHostToDevice, m->own), "ptrs");
+    HIP_TRY(hipMemcpyAsync(m->d_unif, m->h_unif.data(), sizeof(double*) * m->n, hipMemcpyHostToDevice, m->own), "ptrs");
+  }
+  std::vector<char> up_ok(m->n), dn_ok(m->n);
+  for (int k = 0; k < m->n; ++k) { up_ok[k] = m->wk[k]->P_up_valid; dn_ok[k] = m->wk[k]->P_dn_valid; }
+  if (use_graph) {
+    std::string key = std::to_string(n_steps) + ":" + std::to_string(seed) + ":" + std::to_string(sigma) + ":" +
+                      std::to_string(m->grid_rows);
+    for (int k = 0; k < m->n; ++k) {
+      const SysDev& s = m->h_sys[k];
+      // the per-step schedule (electron, refresh) repeats with period lcm(N, refresh_every)
+      const long period = (long)s.N / std::gcd((long)s.N, (long)s.refresh_every) * s.refresh_every;
+      key += ":" + std::to_string(m->wk[k]->attempts % period) + "," +
+             std::to_string((int)up_ok[k]) + std::to_string((int)dn_ok[k]) + "," + std::to_string(m->rows[k]);
+    }
+    std::vector<char> up2 = up_ok, dn2 = dn_ok;
+    if (!m->gexec || key != m->gkey) {
+      if (m->gexec) { (void)hipGraphExecDestroy(m->gexec); m->gexec = nullptr; }
+      hipGraph_t g = nullptr;
+      HIP_TRY(hipStreamBeginCapture(m->own, hipStreamCaptureModeThreadLocal), "begin capture");
+      hipError_t r = multi_enqueue(m, n_steps, false, seed, sigma, up2, dn2);
+      hipError_t r2 = hipStreamEndCapture(m->own, &g);
+      if (r != hipSuccess) { if (g) (void)hipGraphDestroy(g); return hip_fail(r, "capture"); }
+      HIP_TRY(r2, "end capture");
+      r = hipGraphInstantiate(&m->gexec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      HIP_TRY(r, "instantiate");
+      m->gkey = key;
+    } else {
+      // replay: the schedule is the captured one; advance the simulated flags the same way
+      std::vector<char> u3 = up_ok, d3 = dn_ok;
+      for (int t = 0; t < n_steps; ++t)
+        for (int k = 0; k < m->n; ++k) {
+          const SysDev& s = m->h_sys[k];
+          const int e = (int)((m->wk[k]->attempts + t) % s.N);
+          if (e < s.nu && !d3[k]) d3[k] = 1; else if (e >= s.nu && !u3[k]) u3[k] = 1;
+          if (e < s.nu) u3[k] = 0; else d3[k] = 0;
+        }
+      up2 = u3; dn2 = d3;
+    }
+    HIP_TRY(hipGraphLaunch(m->gexec, m->own), "graph launch");
+    up_ok = up2; dn_ok = dn2;
+  } else {
+    HIP_TRY(multi_enqueue(m, n_steps, expl, seed, sigma, up_ok, dn_ok), "multi steps");
+  }
+  for (int k = 0; k < m->n; ++k) {
+    m->wk[k]->attempts += n_steps;
+    m->wk[k]->P_up_valid = up_ok[k];
+    m->wk[k]->P_dn_valid = dn_ok[k];
+  }
+  HIP_TRY(hipEventRecord(m->ev_b, m->own), "event");
+  HIP_TRY(hipStreamWaitEvent(stream, m->ev_b, 0), "wait");
+  return QMC_OK;
+}
+
+extern "C" qmc_status qmc_multi_autotune(qmc_multi* m, int32_t* rows_out, int32_t* grid_out, hipStream_t stream) {
+  if (!m) return fail(QMC_ERR_ARG, "null group");
+  for (int k = 0; k < m->n; ++k)
+    if (!m->wk[k]->evaluated) return fail(QMC_ERR_STATE, "member not evaluated");
+  HIP_TRY(hipStreamSynchronize(stream), "sync");
+  HIP_TRY(multi_upload(m), "upload");
+  MultiArgs a{m->d_sys, m->d_wk, m->d_steps, m->d_rows, nullptr, nullptr, 0, 12345ULL, 0.3};
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0), "event");
+  HIP_TRY(hipEventCreate(&e1), "event");
+  const int cand_rows[3] = {8, 16, 32};
+  const int cand_grid[4] = {512, 1024, 2048, 4096};
+  float best = 1e30f;
+  int best_r = m->rows.empty() ? kPropRows : m->rows[0], best_g = m->grid_rows;
+  hipError_t err = hipSuccess;
+  for (int r : cand_rows) {
+    for (int k = 0; k < m->n; ++k) m->rows[k] = r;
+    err = multi_build_rows(m);
+    if (err != hipSuccess) break;
+    err = launch_multi_prep(a, m->d_items, m->n_items, m->grid_items, m->own);
+    if (err != hipSuccess) break;
+    for (int g : cand_grid) {
+      const int grid = std::min(g, m->n_rows_items);
+      err = launch_multi_rows(a, m->f32, m->nc, m->d_rows_items, m->n_rows_items, grid, m->own);
+      if (err == hipSuccess) err = hipEventRecord(e0, m->own);
+      for (int rep = 0; rep < 5 && err == hipSuccess; ++rep)
+        err = launch_multi_rows(a, m->f32, m->nc, m->d_rows_items, m->n_rows_items, grid, m->own);
+      if (err == hipSuccess) err = hipEventRecord(e1, m->own);
+      if (err == hipSuccess) err = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+      if (err != hipSuccess) break;
+      if (ms < best) { best = ms; best_r = r; best_g = grid; }
+    }
+    if (err != hipSuccess) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  HIP_TRY(err, "autotune");
+  for (int k = 0; k < m->n; ++k) m->rows[k] = best_r;
+  HIP_TRY(multi_build_rows(m), "rows table");
+  m->grid_rows = std::min(best_g, m->n_rows_items);
+  if (m->gexec) { (void)hipGraphExecDestroy(m->gexec); m->gexec = nullptr; }
+  if (rows_out) *rows_out = best_r;
+  if (grid_out) *grid_out = m->grid_rows;
+  return QMC_OK;
+}
+
+extern "C" qmc_status qmc_philox_draws(uint64_t seed, int32_t member, int32_t n_walkers, uint64_t step, double sigma,
+                                       double* disp, double* unif, hipStream_t stream) {
+  if (!disp || !unif || n_walkers <= 0 || member < 0) return fail(QMC_ERR_ARG, "bad argument");
+  HIP_TRY(launch_philox_draws(seed, member, n_walkers, step, sigma, disp, unif, stream), "philox");
   return QMC_OK;
 }
