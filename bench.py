@@ -206,6 +206,52 @@ def forces_leg(P, C, reps=5):
             "note": "forces_ms includes its own re-evaluation; the paper quotes ~4x for energy+forces"}
 
 
+def multi_leg(P, C, precision="fp32", replays=3):
+    """Eight systems with 16..256 electrons, 256 walkers each (2048 walkers),
+    moved together by the persistent multi-system launches: autotuned, one
+    graph of 768 steps (the schedule period of all members) replayed.  Beside
+    it the same members moved one system at a time with qmc_vmc_steps."""
+    dev = torch.device("cuda:0")
+    prec = {"fp64": P.QMC_FP64, "fp32": P.QMC_W_FP32}[precision]
+    members = []
+    for n in C.MULTI_SIZES:
+        w = C.multi_system(n)
+        sysh = P.JAGPSystem(w.system, precision=prec)
+        wk = P.Walkers(sysh, w.r0.shape[0])
+        wk.eval_batch(torch.tensor(w.r0, device=dev))
+        members.append((w, sysh, wk))
+    m = P.MultiSystem([wk for _, _, wk in members])
+    rows, grid = m.autotune()
+    period = 768
+    m.vmc_steps(period, seed=11, sigma=0.3, use_graph=True)      # capture + first replay
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(replays):
+        m.vmc_steps(period, seed=11, sigma=0.3, use_graph=True)
+    e1.record()
+    torch.cuda.synchronize()
+    t_multi = e0.elapsed_time(e1) / 1e3
+    n_walk = sum(w.r0.shape[0] for w, _, _ in members)
+    moves = replays * period * n_walk
+    # one system at a time, same number of steps, host-driven launches
+    steps = 96
+    draws = [C.chain_arrays(31 + k, steps, w.r0.shape[0]) for k, (w, _, _) in enumerate(members)]
+    draws = [(torch.tensor(d, device=dev), torch.tensor(u, device=dev)) for d, u in draws]
+    torch.cuda.synchronize()
+    e0.record()
+    for k, (_, _, wk) in enumerate(members):
+        wk.vmc_steps(0, draws[k][0], draws[k][1])
+    e1.record()
+    torch.cuda.synchronize()
+    t_seq = e0.elapsed_time(e1) / 1e3
+    m.close()
+    return {"workload": "multi_8sys_16to256e", "walkers": n_walk, "precision": precision,
+            "moves_per_s": round(moves / t_multi, 1), "graph_steps": period, "replays": replays,
+            "autotuned_rows_per_item": rows, "autotuned_grid": grid,
+            "one_system_at_a_time_moves_per_s": round(steps * n_walk / t_seq, 1)}
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -250,6 +296,7 @@ def main():
             res["mixed_over_fp64_evals"] = round(side["eloc_evals_per_s"] / head["eloc_evals_per_s"], 3)
     if not args.only:
         res["forces"] = forces_leg(P, C)
+        res["multi_system"] = multi_leg(P, C)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(res), flush=True)

@@ -184,7 +184,10 @@ static hipError_t W_build_t(const SysDev& s, const WalkDev& w, hipStream_t st) {
   g.B = (const T*)w.phi + (long)s.nu * s.Lp; g.ldb = s.Lp; g.b_bs = rowst;
   g.C = w.W; g.ldc = s.nd; g.c_bs = (long)s.nu * s.nd;
   g.batch = w.Wk;
-  return run_gemm<32, 32, false, true, T, T, T, double>(g, st);
+  // FP64 MFMA accumulation whatever the storage type of P and Phi (FP32 values
+  // promote exactly): the length-L sums of the geminal entries carry no FP32
+  // rounding.
+  return run_gemm<32, 32, false, true, T, T, double, double>(g, st);
 }
 
 hipError_t launch_W_build(const SysDev& s, const WalkDev& w, hipStream_t st) {

@@ -5,8 +5,9 @@ products, ratios and Sherman-Morrison updates in FP64.
 Two checks:
 
 * Forward-error bound (must hold).  With u = 2^-24 and gamma = (2L + 4) u
-  (rounding of Phi and Lambda to FP32, the two length-L FP32 accumulations and
-  the FP32 storage of P), every geminal entry obeys to first order
+  (rounding of Phi and Lambda to FP32, the length-L FP32 accumulation of P and
+  its FP32 storage; the W product itself accumulates in FP64 and is covered
+  with room to spare), every geminal entry obeys to first order
       |dW| <= gamma |Phi_up| |Lambda| |Phi_dn|^T
   and the derivative rows V = Q_up Lambda Phi_dn^T + Phi_up Lambda Q_dn^T
   (Q = lap Phi + 2 grad Phi . grad J, whose trace against W^{-1} is the
