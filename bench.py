@@ -28,7 +28,7 @@ import torch  # noqa: E402
 
 METRIC = "walker-electron moves/s + E_loc evals/s at 160e, mixed vs FP64, err vs oracle"
 HBM_PEAK_GBS = 8000.0
-MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
+MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "mixed": 157.3}
 
 
 def parse():
@@ -37,11 +37,64 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--walkers", type=int, default=1024)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed", "fp32"],
+                    help="fp64; mixed = FP32 move path with FP64-accurate evaluations; "
+                         "fp32 = FP32 move path and FP32-product evaluations")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--oracle-walkers", type=int, default=4)
     ap.add_argument("--only", action="store_true", help="run the headline precision only")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first run a plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
+
+
+# Sources of the streaming proposal kernel: a recorded counter measurement is
+# reported only while these files are unchanged.
+ROWS_SOURCES = ("paper_2002_07401_amd/csrc/move.hip", "paper_2002_07401_amd/csrc/move_dev.h",
+                "paper_2002_07401_amd/csrc/internal.h")
+
+
+def rows_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ROWS_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(precision, walkers):
+    """HBM bytes per launch of the proposal kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE passes, each scaled by the same counter
+    over a plain copy of known size), or None when the summary is missing, was
+    taken on another configuration, or the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", f"propose_rows_mol160e_{precision}_pmc.txt")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                rec[k.strip()] = v.strip()
+    if rec.get("source_sha256") != rows_source_hash() or rec.get("walkers") != str(walkers):
+        return None
+    try:
+        return int(float(rec["traffic_bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_probe(mib):
+    """A plain elementwise copy (read mib MiB, write mib MiB) for calibrating
+    the FETCH_SIZE / WRITE_SIZE counters."""
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    del src, dst
 
 
 def kernel_models(s, Wk, esz, acc_rate):
@@ -92,7 +145,7 @@ def run_precision(P, C, w, args, precision):
     s = w.system
     N = s.n_up + s.n_dn
     Wk = args.walkers
-    prec = {"fp64": P.QMC_FP64, "fp32": P.QMC_W_FP32}[precision]
+    prec = {"fp64": P.QMC_FP64, "mixed": P.QMC_MIXED, "fp32": P.QMC_W_FP32}[precision]
     esz = 8 if precision == "fp64" else 4
     sysh = P.JAGPSystem(s, precision=prec)
     wk = P.Walkers(sysh, Wk)
@@ -133,13 +186,14 @@ def run_precision(P, C, w, args, precision):
 
     # error of an evaluation at the final positions against the CPU oracle
     idx = np.linspace(0, Wk - 1, args.oracle_walkers).round().astype(int).tolist()
-    out = wk.eval_batch(r_cur, drift=True)
-    torch.cuda.synchronize()
-    ref = O.evaluate(O.from_workload_system(s), r_cur.cpu()[idx])
     err = {}
-    for key in ("logabs", "e_loc"):
-        d = (out[key].cpu()[idx] - ref[key]).abs() / ref[key].abs().clamp(min=1.0)
-        err[key] = float(f"{float(d.max()):.3e}")
+    if idx:
+        out = wk.eval_batch(r_cur, drift=True)
+        torch.cuda.synchronize()
+        ref = O.evaluate(O.from_workload_system(s), r_cur.cpu()[idx])
+        for key in ("logabs", "e_loc"):
+            d = (out[key].cpu()[idx] - ref[key]).abs() / ref[key].abs().clamp(min=1.0)
+            err[key] = float(f"{float(d.max()):.3e}")
 
     # roofline of the dominant kernel (largest summed time in the timed steps)
     models = kernel_models(s, Wk, esz, acc_rate)
@@ -149,7 +203,9 @@ def run_precision(P, C, w, args, precision):
     if bound == "hbm":
         achieved = units / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": (recorded_traffic("fp64" if precision == "fp64" else "fp32", Wk)
+                            if dom == "propose" else None),
                 "bytes_per_launch": int(units), "avg_launch_us": round(avg_ms * 1e3, 2)}
     else:
         peak = MFMA_PEAK_TFLOPS[precision]
@@ -262,13 +318,15 @@ def main():
     from workloads import configs as C
     P.load()
     torch.cuda.set_device(0)
+    if args.copy_probe_mib > 0:
+        copy_probe(args.copy_probe_mib)
     w = C.mol_40nuc_160e(n_walkers=args.walkers)
     s = w.system
     N = s.n_up + s.n_dn
     main_prec = args.precision
-    other = "fp32" if main_prec == "fp64" else "fp64"
+    others = [p for p in ("fp64", "mixed", "fp32") if p != main_prec]
     head = run_precision(P, C, w, args, main_prec)
-    side = None if args.only else run_precision(P, C, w, args, other)
+    sides = {} if args.only else {p: run_precision(P, C, w, args, p) for p in others}
     res = {
         "metric": METRIC,
         "value": head["moves_per_s"],
@@ -288,12 +346,12 @@ def main():
         "kernel_launches": head["kernel_launches"],
         "roofline": head["roofline"],
     }
-    if side is not None:
-        key = "mixed_fp32" if other == "fp32" else "fp64"
-        res[key] = side
-        if other == "fp32":
-            res["mixed_over_fp64_moves"] = round(side["moves_per_s"] / head["moves_per_s"], 3)
-            res["mixed_over_fp64_evals"] = round(side["eloc_evals_per_s"] / head["eloc_evals_per_s"], 3)
+    for p, rec in sides.items():
+        res[p] = rec
+    if main_prec == "fp64":
+        for p, rec in sides.items():
+            res[f"{p}_over_fp64_moves"] = round(rec["moves_per_s"] / head["moves_per_s"], 3)
+            res[f"{p}_over_fp64_evals"] = round(rec["eloc_evals_per_s"] / head["eloc_evals_per_s"], 3)
     if not args.only:
         res["forces"] = forces_leg(P, C)
         res["multi_system"] = multi_leg(P, C)

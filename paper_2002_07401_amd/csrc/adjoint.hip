@@ -207,8 +207,9 @@ basis_backward_kernel(SysDev s, WalkDev w, const double* __restrict__ phibar, co
     int c = 0, kind = 0;
     double zt = 0.0, Rx = 0.0, Ry = 0.0, Rz = 0.0, HP[6];
     if (act) {
-      c = s.center[mu]; kind = s.kind[mu]; zt = s.zeta[mu];
-      Rx = s.R[3 * c]; Ry = s.R[3 * c + 1]; Rz = s.R[3 * c + 2];
+      const double4 f = s.bfn[mu];
+      c = s.center[mu]; kind = s.kind[mu]; zt = f.w;
+      Rx = f.x; Ry = f.y; Rz = f.z;
     }
     hess_P(kind, HP);
     const double lq = 4.0 * kind_l(kind) + 6.0;

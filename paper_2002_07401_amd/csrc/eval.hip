@@ -20,10 +20,28 @@ __global__ void __launch_bounds__(256) basis_values_kernel(SysDev s, const doubl
 
 hipError_t launch_basis_values(const SysDev& s, const WalkDev& w, hipStream_t st) {
   const dim3 grid((unsigned)((long)w.Wk * s.N));
-  if (s.precision == QMC_W_FP32)
+  if (s.f32())
     hipLaunchKernelGGL(basis_values_kernel<float>, grid, dim3(256), 0, st, s, w.r, (float*)w.phi);
   else
     hipLaunchKernelGGL(basis_values_kernel<double>, grid, dim3(256), 0, st, s, w.r, (double*)w.phi);
+  return hipGetLastError();
+}
+
+// FP32 copies of FP64 arrays (padding included), 4 elements per thread.
+__global__ void __launch_bounds__(256) downcast_kernel(const double* __restrict__ src, float* __restrict__ dst,
+                                                       long n) {
+  const long i = 4 * ((long)blockIdx.x * blockDim.x + threadIdx.x);
+  if (i + 3 < n) {
+    const double4 v = *reinterpret_cast<const double4*>(src + i);
+    *reinterpret_cast<float4*>(dst + i) = make_float4((float)v.x, (float)v.y, (float)v.z, (float)v.w);
+  } else {
+    for (long k = i; k < n; ++k) dst[k] = (float)src[k];
+  }
+}
+
+hipError_t launch_downcast(const double* src, float* dst, long n, hipStream_t st) {
+  const long threads = (n + 3) / 4;
+  hipLaunchKernelGGL(downcast_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, src, dst, n);
   return hipGetLastError();
 }
 
@@ -193,7 +211,7 @@ __global__ void export_phi_kernel(SysDev s, long rows, const T* __restrict__ phi
 hipError_t launch_export_phi(const SysDev& s, const WalkDev& w, double* dst, hipStream_t st) {
   const long rows = (long)w.Wk * s.N;
   const unsigned nb = (unsigned)((rows * s.L + 255) / 256);
-  if (s.precision == QMC_W_FP32)
+  if (s.f32())
     hipLaunchKernelGGL(export_phi_kernel<float>, dim3(nb), dim3(256), 0, st, s, rows, (const float*)w.phi, dst);
   else
     hipLaunchKernelGGL(export_phi_kernel<double>, dim3(nb), dim3(256), 0, st, s, rows, (const double*)w.phi, dst);
@@ -213,6 +231,19 @@ __global__ void set_lambda_kernel(SysDev s, const double* __restrict__ lam) {
     s.lam32[(long)i * s.Lp + j] = (float)v;
     s.lamT32[(long)j * s.Lp + i] = (float)v;
   }
+}
+
+// bfn[mu] = (centre of mu, zeta_mu); rebuilt whenever R or zeta change.
+__global__ void pack_basis_kernel(SysDev s) {
+  const int mu = blockIdx.x * blockDim.x + threadIdx.x;
+  if (mu >= s.L) return;
+  const int c = s.center[mu];
+  s.bfn[mu] = make_double4(s.R[3 * c], s.R[3 * c + 1], s.R[3 * c + 2], s.zeta[mu]);
+}
+
+hipError_t launch_pack_basis(const SysDev& s, hipStream_t st) {
+  hipLaunchKernelGGL(pack_basis_kernel, dim3((s.L + 255) / 256), dim3(256), 0, st, s);
+  return hipGetLastError();
 }
 
 hipError_t launch_set_lambda(const SysDev& s, const double* lam, hipStream_t st) {

@@ -171,7 +171,7 @@ static hipError_t P_build_t(const SysDev& s, const WalkDev& w, int halves, hipSt
 }
 
 hipError_t launch_P_build(const SysDev& s, const WalkDev& w, int halves, hipStream_t st) {
-  if (s.precision == QMC_W_FP32) return P_build_t<float>(s, w, halves, st, s.lam32, s.lamT32);
+  if (s.f32()) return P_build_t<float>(s, w, halves, st, s.lam32, s.lamT32);
   return P_build_t<double>(s, w, halves, st, s.lam, s.lamT);
 }
 
@@ -191,7 +191,7 @@ static hipError_t W_build_t(const SysDev& s, const WalkDev& w, hipStream_t st) {
 }
 
 hipError_t launch_W_build(const SysDev& s, const WalkDev& w, hipStream_t st) {
-  if (s.precision == QMC_W_FP32) return W_build_t<float>(s, w, st);
+  if (s.f32()) return W_build_t<float>(s, w, st);
   return W_build_t<double>(s, w, st);
 }
 
@@ -225,7 +225,7 @@ static hipError_t Y_build_t(const SysDev& s, const WalkDev& w, hipStream_t st) {
 }
 
 hipError_t launch_Y_build(const SysDev& s, const WalkDev& w, hipStream_t st) {
-  if (s.precision == QMC_W_FP32) return Y_build_t<float>(s, w, st);
+  if (s.f32()) return Y_build_t<float>(s, w, st);
   return Y_build_t<double>(s, w, st);
 }
 

@@ -16,6 +16,7 @@ namespace qmc {
 // ---------------------------------------------------------------------------
 constexpr int kMaxNuc = 4096;
 constexpr int kLuMaxN = 128;      // LDS-resident Gauss-Jordan inverse limit
+constexpr int kLuRowMax = 96;     // register (row-per-thread) Gauss-Jordan limit
 constexpr int kPropRows = 16;     // rows of P per proposal workgroup
 constexpr int kPropRowsMin = 8;   // smallest rows-per-workgroup the autotuner may pick
 constexpr int kMaxNucBack = 256;  // nuclei handled by the Jastrow backward kernel
@@ -28,6 +29,8 @@ struct SysDev {
   int j1_form, j2_form;
   double j2[8];
   int precision, refresh_every;
+  // FP32 storage of Phi and P (the move path) in the two reduced-precision modes
+  __host__ __device__ bool f32() const { return precision != QMC_FP64; }
   double* R;        // [A][3]
   double* Z;        // [A]
   double* j1_b;     // [A]
@@ -40,6 +43,7 @@ struct SysDev {
   float* lamT32;
   int* cptr;        // [A+1] basis functions of nucleus a: cmu[cptr[a] .. cptr[a+1])
   int* cmu;         // [L]
+  double4* bfn;     // [L] packed (x, y, z) of the function's centre and its zeta
 };
 
 // Device state of a batch of walkers.
@@ -72,6 +76,8 @@ struct WalkDev {
   double* gpsi_new;   // [Wk][3][Lp] basis gradients at r' (drift requests)
   double* gJ;         // [Wk][N][4] Jastrow gradient (3) and Laplacian per electron
   double* drift;      // [Wk][N][3] grad_i log|Psi| of the last evaluation
+  double* phi64;      // [Wk][N][Lp] FP64 evaluation work arrays (QMC_MIXED only)
+  double* P64;        // [Wk][N][Lp]
 };
 
 // Workspace of the reverse pass (allocated on the first qmc_forces call).
@@ -113,9 +119,6 @@ hipError_t launch_multi_rows(const MultiArgs& a, bool f32, int nc, const int4* i
 hipError_t launch_multi_accept(const MultiArgs& a, bool f32, int qmax, const int2* items, int n_items, int grid,
                                hipStream_t st);
 hipError_t launch_multi_advance(long long* steps, int n, hipStream_t st);
-hipError_t prepare_multi_lu(size_t shm);
-hipError_t launch_multi_lu(const SysDev* sysv, const WalkDev* wkv, const int2* items, int n_items,
-                           unsigned mask, size_t shm, int grid, hipStream_t st);
 hipError_t launch_philox_draws(unsigned long long seed, int member, int Wk, unsigned long long step, double sigma,
                                double* disp, double* unif, hipStream_t st);
 
@@ -159,22 +162,23 @@ __device__ __forceinline__ double angular_value(int kind, double x, double y, do
   }
 }
 
-// Gaussian function mu at point (px,py,pz): value only.
+// Gaussian function mu at point (px,py,pz): value only.  The centre and the
+// exponent come from one packed record (one memory round trip).
 __device__ __forceinline__ double basis_value(const SysDev& s, int mu, double px, double py, double pz) {
-  const int c = s.center[mu];
-  const double x = px - s.R[3 * c], y = py - s.R[3 * c + 1], z = pz - s.R[3 * c + 2];
+  const double4 f = s.bfn[mu];
+  const double x = px - f.x, y = py - f.y, z = pz - f.z;
   const double r2 = x * x + y * y + z * z;
-  return angular_value(s.kind[mu], x, y, z) * exp(-s.zeta[mu] * r2);
+  return angular_value(s.kind[mu], x, y, z) * exp(-f.w * r2);
 }
 
 // Value, gradient and Laplacian.  The angular factors are harmonic and
 // homogeneous of degree l, so lap(P e^{-zeta r^2}) = (4 zeta^2 r^2 - (4l+6) zeta) P e.
 __device__ __forceinline__ void basis_vgl(const SysDev& s, int mu, double px, double py, double pz,
                                           double& v, double& gx, double& gy, double& gz, double& lap) {
-  const int c = s.center[mu];
-  const double x = px - s.R[3 * c], y = py - s.R[3 * c + 1], z = pz - s.R[3 * c + 2];
+  const double4 f = s.bfn[mu];
+  const double x = px - f.x, y = py - f.y, z = pz - f.z;
   const double r2 = x * x + y * y + z * z;
-  const double zt = s.zeta[mu];
+  const double zt = f.w;
   const int k = s.kind[mu];
   double P, Px, Py, Pz;
   angular(k, x, y, z, P, Px, Py, Pz);
@@ -253,9 +257,11 @@ __device__ __forceinline__ float wave_sum(float v) {
 // launchers (all asynchronous on `st`)
 // ---------------------------------------------------------------------------
 hipError_t launch_basis_values(const SysDev& s, const WalkDev& w, hipStream_t st);
+hipError_t launch_downcast(const double* src, float* dst, long n, hipStream_t st);
 hipError_t launch_P_build(const SysDev& s, const WalkDev& w, int halves, hipStream_t st);
 hipError_t launch_W_build(const SysDev& s, const WalkDev& w, hipStream_t st);
 hipError_t launch_Y_build(const SysDev& s, const WalkDev& w, hipStream_t st);
+hipError_t prepare_lu(int n);
 hipError_t launch_lu_inverse(const SysDev& s, const WalkDev& w, hipStream_t st);
 hipError_t launch_rowdots(const SysDev& s, const WalkDev& w, hipStream_t st);
 hipError_t launch_jastrow_assemble(const SysDev& s, const WalkDev& w, double* logabs, double* sign,
@@ -275,6 +281,7 @@ hipError_t launch_accept(const SysDev& s, const WalkDev& w, int e, const uint8_t
 hipError_t launch_refresh_finish(const SysDev& s, const WalkDev& w, int32_t* status, hipStream_t st);
 hipError_t launch_export_phi(const SysDev& s, const WalkDev& w, double* dst, hipStream_t st);
 hipError_t launch_set_lambda(const SysDev& s, const double* lam, hipStream_t st);
+hipError_t launch_pack_basis(const SysDev& s, hipStream_t st);
 
 // FP64 MFMA GEMM, exposed for the launchers above.
 struct GemmArgs {

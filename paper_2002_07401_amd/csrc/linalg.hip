@@ -6,9 +6,10 @@
 // behaves like 1/Pf, finite-variance reweighting subsection), which is why this
 // step stays in FP64 in every precision mode.
 //
-// Method: in-place Gauss-Jordan elimination with partial (row) pivoting, the
-// whole matrix resident in LDS (n <= 128), one workgroup per walker.  The pivot
-// is the largest |entry| of the column (lowest row on ties).
+// Method: in-place Gauss-Jordan elimination with partial (row) pivoting, one
+// workgroup per walker: rows in registers for n <= kLuRowMax, else the whole
+// matrix resident in LDS (n <= kLuMaxN).  The pivot is the largest |entry| of
+// the column.
 //   log|det| = sum_k log|pivot_k|,  sign = prod_k sign(pivot_k) * (-1)^{#swaps}
 // After elimination the row interchanges are undone as column interchanges in
 // reverse order, leaving W^{-1}.  A zero pivot marks the walker singular.
@@ -115,143 +116,153 @@ gj_inverse_kernel(const double* __restrict__ Wg, double* __restrict__ Ag, double
   gj_lds_body(Wg + b * w_bs, Ag + b * a_bs, logdet + b, detsign + b, singular + b, n, smem);
 }
 
-// Register-resident variant (the default).  Thread t keeps column c = t % n of
-// rows g, g + G, g + 2G, ... (g = t / n, G = blockDim / n) in registers.  Rows
-// are never swapped: step k pivots in place on (p_k, k), p_k the unused row
-// with the largest |T[p][k]| (lowest index on ties), with the same update as
-// above.  In-place Gauss-Jordan on the pivots (p_k, k) leaves
-//   W^{-1}[k][p_k'] = T[p_k][k']   and   det W = sgn(p) prod_k T_k[p_k][k],
-// sgn(p) the parity of the permutation k -> p_k.
-template <int QMAX>
-__device__ void gj_reg_body(const double* __restrict__ W, double* __restrict__ A, double* __restrict__ logdet,
-                            double* __restrict__ detsign, int* __restrict__ singular, int n) {
-  __shared__ double rk[kLuMaxN];
-  __shared__ double ck[kLuMaxN];
-  __shared__ int used[kLuMaxN];
-  __shared__ int prow[kLuMaxN];
-  __shared__ int invp[kLuMaxN];
-  __shared__ double cand_v[256];
-  __shared__ int cand_i[256];
-  __shared__ double piv_s;
-  __shared__ int p_s;
-  const int tid = threadIdx.x;
-  const int G = blockDim.x / n, c = tid % n, g = tid / n;
-  const bool own = g < G;
-  double a[QMAX];
+// Row-per-thread variant (the default for n <= kLuRowMax).  The matrix is
+// padded to NMAX = round_up(n, 8) with an identity block, which leaves the real
+// block's elimination unchanged (padding rows are zero in real columns, real
+// rows zero in padding columns).  Thread i keeps row i in registers as a
+// rotating window: before step k, a[j] holds column (k + j) mod NMAX, so the
+// pivot column is always a[0] and the update a[j] <- a[j+1] - g rk[j+1] shifts
+// by one; after NMAX steps the window is back in place.
+//
+// Rows are never swapped: step k pivots on (p_k, k), p_k the unused row with
+// the largest |T[p][k]| (compared on the top 44 mantissa bits, lowest row on
+// ties).  A pivot row is left unscaled (its column-k entry set to 1) and
+// divided by its own pivot once at the end; every later update is linear in
+// the row, so this equals scaling at the pivot step.  In-place Gauss-Jordan on
+// the pivots (p_k, k) leaves
+//   W^{-1}[k][p_k'] = T[p_k][k'],   det W = sgn(p) prod_k pivot_k,
+// sgn(p) the parity of k -> p_k.
+struct GjRowShared {
+  double rk[2][2][kLuRowMax];        // per parity, per wave: that wave's best row
+  unsigned long long key[2][2];      // per parity, per wave: its pivot key
+  int prow[kLuRowMax];
+  int kof[kLuRowMax];
+  double red_d[4];
+  int red_i[4];
+};
+
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
 #pragma unroll
-  for (int q = 0; q < QMAX; ++q) {
-    const int i = g + G * q;
-    a[q] = (own && i < n) ? W[(long)i * n + c] : 0.0;
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long u = __shfl_xor(v, o, 64);
+    v = u > v ? u : v;
   }
-  for (int i = tid; i < n; i += blockDim.x) used[i] = 0;
-  double lsum = 0.0, sg = 1.0;
-  int sing = 0;
-  __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    if (own && c == k) {
-      double best = -1.0, bv = 0.0;
-      int bi = n;
+  return v;
+}
+
+template <int NMAX>
+__device__ __forceinline__ void gj_row_body(const double* __restrict__ W, double* __restrict__ A, double* __restrict__ logdet,
+                            double* __restrict__ detsign, int* __restrict__ singular, int n, GjRowShared& sm) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nw = (min((int)blockDim.x, NMAX) + 63) >> 6;   // waves holding rows
+  const bool live = tid < NMAX, real = tid < n;
+  double a[NMAX];
+  if (real) {
+    const double* row = W + (long)tid * n;
+    if ((n & 1) == 0) {
 #pragma unroll
-      for (int q = 0; q < QMAX; ++q) {
-        const int i = g + G * q;
-        if (i < n && !used[i]) {
-          const double v = fabs(a[q]);
-          if (v > best) { best = v; bi = i; bv = a[q]; }
+      for (int j = 0; j < NMAX; j += 2) {
+        if (j < n) {
+          const double2 v = *reinterpret_cast<const double2*>(row + j);
+          a[j] = v.x; a[j + 1] = v.y;
+        } else {
+          a[j] = 0.0; a[j + 1] = 0.0;
         }
       }
-      cand_v[g] = bv;
-      cand_i[g] = bi;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      double best = -1.0, bv = 0.0;
-      int bi = n;
-      for (int q = 0; q < G; ++q) {
-        const int i = cand_i[q];
-        if (i >= n) continue;
-        const double v = fabs(cand_v[q]);
-        if (v > best || (v == best && i < bi)) { best = v; bi = i; bv = cand_v[q]; }
-      }
-      p_s = bi;
-      piv_s = bv;
-      if (bi < n) { prow[k] = bi; used[bi] = 1; invp[bi] = k; }
-    }
-    __syncthreads();
-    const int p = p_s;
-    const double piv = piv_s;
-    if (p >= n || !(piv != 0.0)) { sing = 1; break; }   // uniform across the block
-    lsum += log(fabs(piv));
-    if (piv < 0.0) sg = -sg;
-    const double inv = 1.0 / piv;
-    if (own && g == p % G) {
-      const int qp = p / G;
-      double v = 0.0;
+    } else {
 #pragma unroll
-      for (int q = 0; q < QMAX; ++q) if (q == qp) v = a[q];
-      rk[c] = (c == k) ? inv : v * inv;
-    }
-    if (own && c == k) {
-#pragma unroll
-      for (int q = 0; q < QMAX; ++q) {
-        const int i = g + G * q;
-        if (i < n) ck[i] = a[q];
-      }
-    }
-    __syncthreads();
-    if (own) {
-      const double rc = rk[c], rkk = rk[k];
-#pragma unroll
-      for (int q = 0; q < QMAX; ++q) {
-        const int i = g + G * q;
-        if (i < n) {
-          if (i == p) a[q] = rc;
-          else if (c == k) a[q] = -ck[i] * rkk;
-          else a[q] -= ck[i] * rc;
-        }
-      }
-    }
-    __syncthreads();
-  }
-  if (!sing) {
-    // parity of k -> prow[k]
-    if (tid == 0) {
-      int* visited = cand_i;
-      for (int i = 0; i < n; ++i) visited[i] = 0;
-      for (int i = 0; i < n; ++i) {
-        if (visited[i]) continue;
-        int len = 0, j = i;
-        while (!visited[j]) { visited[j] = 1; j = prow[j]; ++len; }
-        if ((len & 1) == 0) sg = -sg;
-      }
-      piv_s = sg;
-    }
-    __syncthreads();
-    sg = piv_s;
-    if (own) {
-      const int col = prow[c];
-#pragma unroll
-      for (int q = 0; q < QMAX; ++q) {
-        const int i = g + G * q;
-        if (i < n) A[(long)invp[i] * n + col] = a[q];
-      }
+      for (int j = 0; j < NMAX; ++j) a[j] = j < n ? row[j] : 0.0;
     }
   } else {
+#pragma unroll
+    for (int j = 0; j < NMAX; ++j) a[j] = (j == tid) ? 1.0 : 0.0;
+  }
+
+  bool used = !live;
+  double own_piv = 1.0;
+  int own_k = tid;
+  int sing = 0;
+  for (int k = 0; k < NMAX; ++k) {
+    const int b = k & 1;
+    const double f = a[0];
+    // Only real rows may pivot in the first n steps (whatever the values), so
+    // real rows take steps 0..n-1 and every store below stays inside A.
+    const bool elig = !used && (real || k >= n);
+    const unsigned long long key =
+        elig ? ((__double_as_longlong(fabs(f)) & ~0xFFull) | (unsigned long long)(255 - tid)) : 0ull;
+    const unsigned long long wk = wave_max_u64(key);
+    if (wave < nw) {
+      if (key == wk && wk != 0ull) {
+        double* dst = sm.rk[b][wave];
+#pragma unroll
+        for (int j = 0; j < NMAX; ++j) dst[j] = a[j];
+      }
+      if (lane == 0) sm.key[b][wave] = wk;
+    }
+    __syncthreads();
+    unsigned long long best = sm.key[b][0];
+    int ws = 0;
+    if (nw > 1 && sm.key[b][1] > best) { best = sm.key[b][1]; ws = 1; }
+    const double* rk = sm.rk[b][ws];
+    const double piv = rk[0];
+    if (!(piv != 0.0)) { sing = 1; break; }   // uniform across the block
+    const int p = 255 - (int)(best & 0xFFull);
+    const bool isp = tid == p;
+    if (isp) { used = true; own_piv = piv; own_k = k; sm.prow[k] = tid; }
+    const double g = isp ? 0.0 : f * (1.0 / piv);
+#pragma unroll
+    for (int j = 0; j < NMAX - 1; ++j) a[j] = fma(-g, rk[j + 1], a[j + 1]);
+    a[NMAX - 1] = isp ? 1.0 : -g;
+  }
+
+  if (sing) {
     const double nanv = __longlong_as_double(0x7ff8000000000000LL);
     for (int idx = tid; idx < n * n; idx += blockDim.x) A[idx] = nanv;
+    if (tid == 0) { *logdet = -__builtin_inf(); *detsign = 0.0; *singular = 1; }
+    return;
   }
+  if (live) sm.kof[tid] = own_k;
+  __syncthreads();
+  // log|det| = sum log|pivot|; sign from the pivots' signs and the parity of
+  // the pivot permutation (inversions among real rows; padding rows are
+  // pivoted last, in order).
+  double ls = real ? log(fabs(own_piv)) : 0.0;
+  int odd = 0;
+  if (real) {
+    odd = own_piv < 0.0;
+    for (int i2 = tid + 1; i2 < n; ++i2) odd += sm.kof[i2] < own_k;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    ls += __shfl_xor(ls, o, 64);
+    odd += __shfl_xor(odd, o, 64);
+  }
+  if (lane == 0 && wave < 4) { sm.red_d[wave] = ls; sm.red_i[wave] = odd; }
+  if (real) {
+    const double inv = 1.0 / own_piv;
+    double* out = A + (long)own_k * n;
+#pragma unroll
+    for (int j = 0; j < NMAX; ++j)
+      if (j < n) out[sm.prow[j]] = a[j] * inv;
+  }
+  __syncthreads();
   if (tid == 0) {
-    *logdet = sing ? -__builtin_inf() : lsum;
-    *detsign = sing ? 0.0 : sg;
-    *singular = sing;
+    double lsum = 0.0;
+    int par = 0;
+    for (int q = 0; q < nw; ++q) { lsum += sm.red_d[q]; par += sm.red_i[q]; }
+    *logdet = lsum;
+    *detsign = (par & 1) ? -1.0 : 1.0;
+    *singular = 0;
   }
 }
 
-template <int QMAX>
-__global__ void __launch_bounds__(256)
-gj_inverse_reg_kernel(const double* __restrict__ Wg, double* __restrict__ Ag, double* __restrict__ logdet,
+template <int NMAX>
+__global__ void __launch_bounds__(128)
+gj_inverse_row_kernel(const double* __restrict__ Wg, double* __restrict__ Ag, double* __restrict__ logdet,
                       double* __restrict__ detsign, int* __restrict__ singular, int n, long w_bs, long a_bs) {
+  __shared__ GjRowShared sm;
   const long b = blockIdx.x;
-  gj_reg_body<QMAX>(Wg + b * w_bs, Ag + b * a_bs, logdet + b, detsign + b, singular + b, n);
+  gj_row_body<NMAX>(Wg + b * w_bs, Ag + b * a_bs, logdet + b, detsign + b, singular + b, n, sm);
 }
 
 hipError_t launch_lu_inverse_lds(const SysDev& s, const WalkDev& w, hipStream_t st);
@@ -259,72 +270,39 @@ hipError_t launch_lu_inverse_lds(const SysDev& s, const WalkDev& w, hipStream_t 
 hipError_t launch_lu_inverse(const SysDev& s, const WalkDev& w, hipStream_t st) {
   const int n = s.nu;
   if (n > kLuMaxN) return hipErrorNotSupported;
-  const int G = 256 / n, Q = (n + G - 1) / G;
+  if (n > kLuRowMax) return launch_lu_inverse_lds(s, w, st);
   const long wbs = (long)s.nu * s.nd, abs_ = (long)s.nd * s.nu;
-  // registers pay off only while the column slices stay short (high occupancy)
-  if (Q > 8) return launch_lu_inverse_lds(s, w, st);
-#define QMC_LU_REG(QM)                                                                              \
-  hipLaunchKernelGGL(gj_inverse_reg_kernel<QM>, dim3(w.Wk), dim3(256), 0, st, w.W, w.A, w.logdet, \
-                     w.detsign, w.singular, n, wbs, abs_)
-  if (Q <= 4) QMC_LU_REG(4);
-  else QMC_LU_REG(8);
-#undef QMC_LU_REG
+  const dim3 blk(n > 64 ? 128 : 64);
+  switch ((n + 7) >> 3) {
+#define QMC_LU_ROW(C)                                                                                   \
+    case C:                                                                                             \
+      hipLaunchKernelGGL(gj_inverse_row_kernel<8 * C>, dim3(w.Wk), blk, 0, st, w.W, w.A, w.logdet,      \
+                         w.detsign, w.singular, n, wbs, abs_);                                          \
+      break;
+    QMC_LU_ROW(1) QMC_LU_ROW(2) QMC_LU_ROW(3) QMC_LU_ROW(4) QMC_LU_ROW(5) QMC_LU_ROW(6)
+    QMC_LU_ROW(7) QMC_LU_ROW(8) QMC_LU_ROW(9) QMC_LU_ROW(10) QMC_LU_ROW(11) QMC_LU_ROW(12)
+#undef QMC_LU_ROW
+    default: return hipErrorNotSupported;
+  }
   return hipGetLastError();
 }
 
-// LDS variant with physical row swaps, kept for cross-checking the register kernel.
+static size_t lu_lds_bytes(int n) { return ((size_t)n * (n + 1) + 2 * (size_t)n) * sizeof(double); }
+
+// Raises the LDS limit of the LDS variant for an n x n problem; called once at
+// system creation so that no launch (possibly under graph capture) needs it.
+hipError_t prepare_lu(int n) {
+  if (n <= kLuRowMax || lu_lds_bytes(n) <= 64 * 1024) return hipSuccess;
+  return hipFuncSetAttribute((const void*)gj_inverse_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)lu_lds_bytes(n));
+}
+
+// LDS variant with physical row swaps, for kLuRowMax < n <= kLuMaxN.
 hipError_t launch_lu_inverse_lds(const SysDev& s, const WalkDev& w, hipStream_t st) {
   const int n = s.nu;
   if (n > kLuMaxN) return hipErrorNotSupported;
-  const size_t shm = ((size_t)n * (n + 1) + 2 * (size_t)n) * sizeof(double);
-  if (shm > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)gj_inverse_kernel,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    if (e != hipSuccess) return e;
-  }
-  hipLaunchKernelGGL(gj_inverse_kernel, dim3(w.Wk), dim3(256), shm, st, w.W, w.A, w.logdet,
+  hipLaunchKernelGGL(gj_inverse_kernel, dim3(w.Wk), dim3(256), lu_lds_bytes(n), st, w.W, w.A, w.logdet,
                      w.detsign, w.singular, n, (long)s.nu * s.nd, (long)s.nd * s.nu);
-  return hipGetLastError();
-}
-
-// Persistent refresh over (member, walker) items of several systems; members
-// not in `mask` are skipped.  The LU variant per member is the one the
-// one-system refresh uses, so the results are identical.
-__global__ void __launch_bounds__(256)
-multi_lu_kernel(const SysDev* __restrict__ sysv, const WalkDev* __restrict__ wkv, const int2* __restrict__ items,
-                int n_items, unsigned mask) {
-  extern __shared__ double smem[];
-  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
-    __syncthreads();
-    const int k = items[it].x, w = items[it].y;
-    if (!((mask >> k) & 1u)) continue;
-    const SysDev& s = sysv[k];
-    const WalkDev& wd = wkv[k];
-    const int n = s.nu;
-    const int G = 256 / n, Q = (n + G - 1) / G;
-    const double* W = wd.W + (long)w * n * n;
-    double* A = wd.A + (long)w * n * n;
-    if (Q <= 8) gj_reg_body<8>(W, A, wd.logdet + w, wd.detsign + w, wd.singular + w, n);
-    else gj_lds_body(W, A, wd.logdet + w, wd.detsign + w, wd.singular + w, n, smem);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      const int sing = wd.singular[w];
-      wd.logabs[w] = sing ? -__builtin_inf() : wd.logdet[w] + wd.J[w];
-      wd.sign[w] = wd.detsign[w];
-    }
-  }
-}
-
-hipError_t prepare_multi_lu(size_t shm) {
-  if (shm <= 64 * 1024) return hipSuccess;
-  return hipFuncSetAttribute((const void*)multi_lu_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-}
-
-// (prepare_multi_lu must have been called for shm beforehand: this launch may be
-// inside a captured graph.)
-hipError_t launch_multi_lu(const SysDev* sysv, const WalkDev* wkv, const int2* items, int n_items,
-                           unsigned mask, size_t shm, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(multi_lu_kernel, dim3(grid), dim3(256), shm, st, sysv, wkv, items, n_items, mask);
   return hipGetLastError();
 }
 

@@ -92,7 +92,7 @@ hipError_t launch_propose_rows(const SysDev& s, const WalkDev& w, int e, double*
   const bool drift = drift_new != nullptr;
   const int S = propose_splits(s);
   const dim3 grid(S, w.Wk);
-  const bool f32 = s.precision == QMC_W_FP32;
+  const bool f32 = s.f32();
   hipError_t err;
   const int chunks = (s.Lp + (f32 ? 255 : 127)) / (f32 ? 256 : 128);
   if (drift) {
@@ -136,7 +136,7 @@ static hipError_t accept_launch_t(const SysDev& s, const WalkDev& w, int e, cons
 static hipError_t accept_launch(const SysDev& s, const WalkDev& w, int e, const uint8_t* acc,
                                 const double* unif, int32_t* accept_count, int S, hipStream_t st) {
   if (s.nu > kLuMaxN) return hipErrorNotSupported;
-  if (s.precision == QMC_W_FP32) return accept_launch_t<float>(s, w, e, acc, unif, accept_count, S, st);
+  if (s.f32()) return accept_launch_t<float>(s, w, e, acc, unif, accept_count, S, st);
   return accept_launch_t<double>(s, w, e, acc, unif, accept_count, S, st);
 }
 

@@ -145,7 +145,7 @@ extern "C" qmc_status qmc_system_create(const qmc_system_desc* desc, qmc_system*
   if (q.n_up <= 0 || q.n_dn < 0) return fail(QMC_ERR_ARG, "bad electron counts");
   if (q.n_up != q.n_dn) return fail(QMC_ERR_UNSUPPORTED, "only n_up == n_dn is built");
   if (q.n_up > kLuMaxN) return fail(QMC_ERR_UNSUPPORTED, "n_up > 128 needs the blocked LU");
-  if (q.precision != QMC_FP64 && q.precision != QMC_W_FP32)
+  if (q.precision != QMC_FP64 && q.precision != QMC_W_FP32 && q.precision != QMC_MIXED)
     return fail(QMC_ERR_UNSUPPORTED, "precision not built");
   if (q.refresh_every < 1) return fail(QMC_ERR_ARG, "refresh_every must be >= 1");
   if (q.j1_form < 0 || q.j1_form > 2 || (q.j1_form && !q.j1_b)) return fail(QMC_ERR_ARG, "bad j1");
@@ -203,11 +203,21 @@ extern "C" qmc_status qmc_system_create(const qmc_system_desc* desc, qmc_system*
   if (!e) e = up((void**)&d.lamT, lamT.data(), sizeof(double) * lamT.size());
   if (!e) e = up((void**)&d.cptr, cptr.data(), sizeof(int) * cptr.size());
   if (!e) e = up((void**)&d.cmu, cmu.data(), sizeof(int) * cmu.size());
-  if (!e && q.precision == QMC_W_FP32) {
+  if (!e) {
+    std::vector<double> bf(4 * (size_t)L);
+    for (int mu = 0; mu < L; ++mu) {
+      const int c = q.center[mu];
+      bf[4 * mu] = q.R[3 * c]; bf[4 * mu + 1] = q.R[3 * c + 1]; bf[4 * mu + 2] = q.R[3 * c + 2];
+      bf[4 * mu + 3] = q.zeta[mu];
+    }
+    e = up((void**)&d.bfn, bf.data(), sizeof(double) * bf.size());
+  }
+  if (!e && q.precision != QMC_FP64) {
     std::vector<float> l32(lam.begin(), lam.end()), lT32(lamT.begin(), lamT.end());
     e = up((void**)&d.lam32, l32.data(), sizeof(float) * l32.size());
     if (!e) e = up((void**)&d.lamT32, lT32.data(), sizeof(float) * lT32.size());
   }
+  if (!e) e = prepare_lu(d.nu);
   if (e != hipSuccess) {
     delete s;
     return e == hipErrorOutOfMemory ? fail(QMC_ERR_OOM, "device allocation failed") : hip_fail(e, "system_create");
@@ -234,7 +244,7 @@ extern "C" qmc_status qmc_walkers_create(qmc_system* sys, int32_t n_walkers, qmc
   d.Wk = n_walkers;
   const size_t Wk = n_walkers, N = s.N, Lp = s.Lp;
   const size_t nmax = s.nu > s.nd ? s.nu : s.nd;
-  const size_t esz = s.precision == QMC_W_FP32 ? sizeof(float) : sizeof(double);
+  const size_t esz = s.f32() ? sizeof(float) : sizeof(double);
   hipError_t e = hipSuccess;
   auto al = [&](void** p, size_t bytes) {
     if (e != hipSuccess) return;
@@ -271,6 +281,10 @@ extern "C" qmc_status qmc_walkers_create(qmc_system* sys, int32_t n_walkers, qmc
   al((void**)&d.gpsi_new, sizeof(double) * Wk * 3 * Lp);
   al((void**)&d.gJ, sizeof(double) * Wk * N * 4);
   al((void**)&d.drift, sizeof(double) * Wk * N * 3);
+  if (s.precision == QMC_MIXED) {
+    al((void**)&d.phi64, sizeof(double) * Wk * N * s.Lp);
+    al((void**)&d.P64, sizeof(double) * Wk * N * s.Lp);
+  }
   if (e != hipSuccess) {
     delete wk;
     return e == hipErrorOutOfMemory ? fail(QMC_ERR_OOM, "device allocation failed") : hip_fail(e, "walkers_create");
@@ -301,11 +315,26 @@ extern "C" qmc_status qmc_eval_batch(qmc_system* sys, qmc_walkers* wk, const dou
   const SysDev& s = sys->d;
   WalkDev& d = wk->d;
   HIP_TRY(hipMemcpyAsync(d.r, r, sizeof(double) * d.Wk * s.N * 3, hipMemcpyDeviceToDevice, stream), "copy r");
-  TIMED(wk, QMC_T_BASIS, stream, launch_basis_values(s, d, stream), "basis");
-  TIMED(wk, QMC_T_P_BUILD, stream, launch_P_build(s, d, 3, stream), "P build");
-  TIMED(wk, QMC_T_W_BUILD, stream, launch_W_build(s, d, stream), "W build");
-  TIMED(wk, QMC_T_LU, stream, launch_lu_inverse(s, d, stream), "LU");
-  TIMED(wk, QMC_T_Y_BUILD, stream, launch_Y_build(s, d, stream), "Y build");
+  // QMC_MIXED evaluates through the FP64 kernels on the FP64 work arrays, then
+  // stores the FP32 basis and P rows the moves stream.
+  const bool refine = s.precision == QMC_MIXED;
+  SysDev se = s;
+  WalkDev de = d;
+  if (refine) {
+    se.precision = QMC_FP64;
+    de.phi = d.phi64;
+    de.P = d.P64;
+  }
+  TIMED(wk, QMC_T_BASIS, stream, launch_basis_values(se, de, stream), "basis");
+  TIMED(wk, QMC_T_P_BUILD, stream, launch_P_build(se, de, 3, stream), "P build");
+  TIMED(wk, QMC_T_W_BUILD, stream, launch_W_build(se, de, stream), "W build");
+  TIMED(wk, QMC_T_LU, stream, launch_lu_inverse(se, de, stream), "LU");
+  TIMED(wk, QMC_T_Y_BUILD, stream, launch_Y_build(se, de, stream), "Y build");
+  if (refine) {
+    const long cnt = (long)d.Wk * s.N * s.Lp;
+    TIMED(wk, QMC_T_OTHER, stream, launch_downcast(d.phi64, (float*)d.phi, cnt, stream), "phi copy");
+    TIMED(wk, QMC_T_OTHER, stream, launch_downcast(d.P64, (float*)d.P, cnt, stream), "P copy");
+  }
   TIMED(wk, QMC_T_ROWDOT, stream, launch_rowdots(s, d, stream), "row dots");
   TIMED(wk, QMC_T_ASSEMBLE, stream,
         launch_jastrow_assemble(s, d, logabs, sign, drift, e_kin, e_loc, status, stream), "assemble");
@@ -503,6 +532,7 @@ extern "C" qmc_status qmc_system_set_params(qmc_system* sys, const double* R, co
   if (R) HIP_TRY(hipMemcpyAsync(d.R, R, sizeof(double) * 3 * d.n_nuc, hipMemcpyDeviceToDevice, stream), "set R");
   if (zeta) HIP_TRY(hipMemcpyAsync(d.zeta, zeta, sizeof(double) * d.L, hipMemcpyDeviceToDevice, stream), "set zeta");
   if (lambda) HIP_TRY(launch_set_lambda(d, lambda, stream), "set lambda");
+  if (R || zeta) HIP_TRY(launch_pack_basis(d, stream), "pack basis");
   if (jas) {
     HIP_TRY(hipMemcpyAsync(d.j1_b, jas, sizeof(double) * d.n_nuc, hipMemcpyDeviceToDevice, stream), "set j1");
     const int n2 = d.j2_form == 1 ? 2 : (d.j2_form == 2 ? 8 : 0);
@@ -542,7 +572,6 @@ struct qmc_multi {
   int n_rows_items = 0, rows_cap = 0;
   int grid_rows = 2048, grid_items = 1024;
   int nc = 1, qmax = 4;
-  size_t lu_shm = 0;
   bool f32 = false;
   hipStream_t own = nullptr;
   hipEvent_t ev_a = nullptr, ev_b = nullptr;
@@ -598,7 +627,7 @@ extern "C" qmc_status qmc_multi_create(int32_t n_members, qmc_system* const* sys
     m->h_wk.push_back(walkers[k]->d);
     m->rows.push_back(kPropRows);
   }
-  m->f32 = systems[0]->d.precision == QMC_W_FP32;
+  m->f32 = systems[0]->d.f32();
   m->order.resize(n_members);
   std::iota(m->order.begin(), m->order.end(), 0);
   std::stable_sort(m->order.begin(), m->order.end(), [&](int a, int b) {
@@ -612,7 +641,6 @@ extern "C" qmc_status qmc_multi_create(int32_t n_members, qmc_system* const* sys
     m->nc = std::max(m->nc, (s.Lp + vec - 1) / vec);
     const int G = 256 / s.nu, Q = (s.nu + G - 1) / G;
     m->qmax = std::max(m->qmax, Q);
-    if (Q > 8) m->lu_shm = std::max(m->lu_shm, ((size_t)s.nu * (s.nu + 1) + 2 * (size_t)s.nu) * sizeof(double));
     for (int w = 0; w < m->h_wk[k].Wk; ++w) items.push_back(make_int2(k, w));
   }
   if (m->nc > 8) { delete m; return fail(QMC_ERR_UNSUPPORTED, "members need L <= 1024 (FP64) or 2048 (FP32)"); }
@@ -634,7 +662,6 @@ extern "C" qmc_status qmc_multi_create(int32_t n_members, qmc_system* const* sys
   if (!e) e = hipMemcpy(m->d_items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice);
   if (!e) e = hipMemcpy(m->d_wk, m->h_wk.data(), sizeof(WalkDev) * n_members, hipMemcpyHostToDevice);
   if (!e) e = multi_build_rows(m);
-  if (!e) e = prepare_multi_lu(m->lu_shm);
   if (!e) e = hipStreamCreateWithFlags(&m->own, hipStreamNonBlocking);
   if (!e) e = hipEventCreateWithFlags(&m->ev_a, hipEventDisableTiming);
   if (!e) e = hipEventCreateWithFlags(&m->ev_b, hipEventDisableTiming);
@@ -693,8 +720,12 @@ static hipError_t multi_enqueue(qmc_multi* m, int n_steps, bool explicit_draws, 
     hipError_t r = launch_multi_prep(a, m->d_items, m->n_items, m->grid_items, m->own);
     if (r == hipSuccess) r = launch_multi_rows(a, m->f32, m->nc, m->d_rows_items, m->n_rows_items, m->grid_rows, m->own);
     if (r == hipSuccess) r = launch_multi_accept(a, m->f32, m->qmax, m->d_items, m->n_items, m->grid_items, m->own);
-    if (r == hipSuccess && mask)
-      r = launch_multi_lu(m->d_sys, m->d_wk, m->d_items, m->n_items, mask, m->lu_shm, m->grid_items, m->own);
+    // refresh: the one-system LU per member, so results match a lone run bitwise
+    for (int k = 0; k < m->n && r == hipSuccess; ++k) {
+      if (!((mask >> k) & 1u)) continue;
+      r = launch_lu_inverse(m->h_sys[k], m->h_wk[k], m->own);
+      if (r == hipSuccess) r = launch_refresh_finish(m->h_sys[k], m->h_wk[k], nullptr, m->own);
+    }
     if (r == hipSuccess) r = launch_multi_advance(m->d_steps, m->n, m->own);
     if (r != hipSuccess) return r;
   }
