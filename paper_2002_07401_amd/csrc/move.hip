@@ -43,13 +43,13 @@ __global__ void __launch_bounds__(256) propose_rows_generic_kernel(SysDev s, Wal
   rows_generic_body<T, DRIFT>(s, w, blockIdx.y, blockIdx.x, gridDim.x, e, kPropRows);
 }
 
-template <typename T, int QMAX>
+template <typename T, int QMAX, bool UP>
 __global__ void __launch_bounds__(256)
 accept_kernel(SysDev s, WalkDev w, int e, const uint8_t* __restrict__ acc_in,
               const double* __restrict__ unif, int32_t* __restrict__ accept_count, int S) {
   const int wk = blockIdx.x;
-  accept_body<T, QMAX>(s, w, wk, e, unif ? 1 : 0, acc_in ? acc_in + wk : nullptr, unif ? unif[wk] : 0.0,
-                       accept_count ? accept_count + wk : nullptr, S);
+  accept_body<T, QMAX, UP>(s, w, wk, e, unif ? 1 : 0, acc_in ? acc_in + wk : nullptr, unif ? unif[wk] : 0.0,
+                           accept_count ? accept_count + wk : nullptr, S);
 }
 
 // Sum the partial ratios (fixed order) for host-driven proposals.
@@ -99,11 +99,14 @@ hipError_t launch_propose_rows(const SysDev& s, const WalkDev& w, int e, double*
     if (f32) hipLaunchKernelGGL((propose_rows_generic_kernel<float, true>), grid, dim3(256), 0, st, s, w, e);
     else hipLaunchKernelGGL((propose_rows_generic_kernel<double, true>), grid, dim3(256), 0, st, s, w, e);
   } else if (chunks <= 8) {
-#define QMC_ROWS(T, NC) hipLaunchKernelGGL((propose_rows_kernel<T, NC>), grid, dim3(256), 0, st, s, w, e)
+#define QMC_ROWS(T, NC) \
+    case NC: hipLaunchKernelGGL((propose_rows_kernel<T, NC>), grid, dim3(256), 0, st, s, w, e); break;
     if (f32) {
-      if (chunks <= 2) QMC_ROWS(float, 2); else if (chunks <= 4) QMC_ROWS(float, 4); else QMC_ROWS(float, 8);
+      switch (chunks) { QMC_ROWS(float, 1) QMC_ROWS(float, 2) QMC_ROWS(float, 3) QMC_ROWS(float, 4)
+                        QMC_ROWS(float, 5) QMC_ROWS(float, 6) QMC_ROWS(float, 7) QMC_ROWS(float, 8) }
     } else {
-      if (chunks <= 2) QMC_ROWS(double, 2); else if (chunks <= 4) QMC_ROWS(double, 4); else QMC_ROWS(double, 8);
+      switch (chunks) { QMC_ROWS(double, 1) QMC_ROWS(double, 2) QMC_ROWS(double, 3) QMC_ROWS(double, 4)
+                        QMC_ROWS(double, 5) QMC_ROWS(double, 6) QMC_ROWS(double, 7) QMC_ROWS(double, 8) }
     }
 #undef QMC_ROWS
   } else {
@@ -122,13 +125,18 @@ static hipError_t accept_launch_t(const SysDev& s, const WalkDev& w, int e, cons
                                   const double* unif, int32_t* accept_count, int S, hipStream_t st) {
   const int n = s.nu;
   const int G = 256 / n, Q = (n + G - 1) / G;
-#define QMC_ACC(QM) \
-  hipLaunchKernelGGL((accept_kernel<T, QM>), dim3(w.Wk), dim3(256), 0, st, s, w, e, acc, unif, accept_count, S)
-  if (Q <= 4) QMC_ACC(4);
-  else if (Q <= 8) QMC_ACC(8);
-  else if (Q <= 16) QMC_ACC(16);
-  else if (Q <= 32) QMC_ACC(32);
-  else QMC_ACC(64);
+#define QMC_ACC(QM)                                                                                      \
+  if (e < s.nu)                                                                                          \
+    hipLaunchKernelGGL((accept_kernel<T, QM, true>), dim3(w.Wk), dim3(256), 0, st, s, w, e, acc, unif,     \
+                       accept_count, S);                                                                 \
+  else                                                                                                   \
+    hipLaunchKernelGGL((accept_kernel<T, QM, false>), dim3(w.Wk), dim3(256), 0, st, s, w, e, acc, unif,    \
+                       accept_count, S)
+  if (Q <= 4) { QMC_ACC(4); }
+  else if (Q <= 8) { QMC_ACC(8); }
+  else if (Q <= 16) { QMC_ACC(16); }
+  else if (Q <= 32) { QMC_ACC(32); }
+  else { QMC_ACC(64); }
 #undef QMC_ACC
   return hipGetLastError();
 }

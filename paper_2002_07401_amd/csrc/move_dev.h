@@ -128,9 +128,12 @@ __device__ __forceinline__ void block_partial(double part, double gx, double gy,
 
 // Step 2, streaming: the workgroup computes the new W entries of rows
 // [sb*R, (sb+1)*R) of the opposite spin of walker wk and their contribution to
-// the determinant ratio (partial sum sb of S).  One wave per row; psi(r') chunks
-// sit in registers and each row is read with NC independent 16-byte loads per
-// lane (chunks past Lp contribute exact zeros).
+// the determinant ratio (partial sum sb of S).  Wave v takes rows j0+v, j0+v+nw,
+// ... two at a time (both rows' loads in flight before either reduction);
+// psi(r') chunks sit in registers and each row is read with NC independent
+// 16-byte loads per lane (NC = ceil(Lp / (64 * 16 / sizeof(T))); chunks past Lp
+// contribute exact zeros).  The W^{-1} entries that weight the rows are loaded
+// once at the start, lane k holding the one of the wave's k-th row.
 template <typename T, int NC>
 __device__ void rows_body(const SysDev& s, const WalkDev& w, int wk, int sb, int S, int e, int R) {
   typedef typename Vec16<T>::type V;
@@ -145,6 +148,13 @@ __device__ void rows_body(const SysDev& s, const WalkDev& w, int wk, int sb, int
   const double* Aw = w.A + (long)wk * s.nd * s.nu;
   double* wn_g = w.w_new + (long)wk * nmax;
   const double* psi = w.psi_new + (long)wk * s.Lp;
+  const int j0 = sb * R;
+  const int j1 = min(j0 + R, nrow);
+  double a_own = 0.0;
+  {
+    const int j = j0 + wave + lane * nw;
+    if (j < j1) a_own = up ? Aw[(long)j * s.nu + e] : Aw[(long)(e - s.nu) * s.nu + j];
+  }
   double ps[NC][VN];
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
@@ -152,27 +162,38 @@ __device__ void rows_body(const SysDev& s, const WalkDev& w, int wk, int sb, int
 #pragma unroll
     for (int v = 0; v < VN; ++v) ps[c][v] = (i0 < s.Lp) ? psi[i0 + v] : 0.0;
   }
-  const int j0 = sb * R;
-  const int j1 = min(j0 + R, nrow);
   double part = 0.0;
-  for (int j = j0 + wave; j < j1; j += nw) {
-    const T* prow = Pw + (long)j * s.Lp;
-    V pv[NC];
+  int k = 0;
+  for (int j = j0 + wave; j < j1; j += 2 * nw, k += 2) {
+    const int jb = j + nw;
+    const bool two = jb < j1;   // uniform over the wave
+    const T* pa = Pw + (long)j * s.Lp;
+    const T* pb = two ? Pw + (long)jb * s.Lp : pa;   // never formed past the block
+    V va[NC], vb[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       const int i0 = c * STEP + lane * VN;
-      if (i0 < s.Lp) pv[c] = *reinterpret_cast<const V*>(prow + i0);
-      else pv[c] = V{};
+      va[c] = (i0 < s.Lp) ? *reinterpret_cast<const V*>(pa + i0) : V{};
+      vb[c] = (two && i0 < s.Lp) ? *reinterpret_cast<const V*>(pb + i0) : V{};
     }
-    double acc = 0.0;
+    double xa = 0.0, xb = 0.0;
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
-      for (int v = 0; v < VN; ++v) acc += vget(pv[c], v) * ps[c][v];
-    acc = wave_sum(acc);
+      for (int v = 0; v < VN; ++v) {
+        xa += vget(va[c], v) * ps[c][v];
+        xb += vget(vb[c], v) * ps[c][v];
+      }
+    xa = wave_sum(xa);
+    xb = wave_sum(xb);
+    const double aa = __shfl(a_own, k, 64), ab = __shfl(a_own, k + 1, 64);
     if (lane == 0) {
-      wn_g[j] = acc;
-      part += acc * (up ? Aw[(long)j * s.nu + e] : Aw[(long)(e - s.nu) * s.nu + j]);
+      wn_g[j] = xa;
+      part += xa * aa;
+      if (two) {
+        wn_g[jb] = xb;
+        part += xb * ab;
+      }
     }
   }
   block_partial(part, 0.0, 0.0, 0.0, false, w, wk, S, sb);
@@ -214,6 +235,31 @@ __device__ void rows_generic_body(const SysDev& s, const WalkDev& w, int wk, int
   block_partial(part, gx, gy, gz, DRIFT, w, wk, S, sb);
 }
 
+// Sums 16 per-lane values over the 64 lanes of a wave with 17 shuffles in six
+// dependent rounds: each of the first four rounds keeps half of the live values
+// and trades the other half with the partner lane.  Lanes 4m..4m+3 return the
+// total of x[m].
+#define QMC_MS_STAGE(H, O)                                      \
+  {                                                             \
+    const bool hi = (lane & (O)) != 0;                          \
+    _Pragma("unroll") for (int k = 0; k < (H); ++k) {           \
+      const double send = hi ? x[k] : x[k + (H)];               \
+      const double keep = hi ? x[k + (H)] : x[k];               \
+      x[k] = keep + __shfl_xor(send, (O), 64);                  \
+    }                                                           \
+  }
+__device__ __forceinline__ double wave_multi_sum16(double (&x)[16], int lane) {
+  QMC_MS_STAGE(8, 32)
+  QMC_MS_STAGE(4, 16)
+  QMC_MS_STAGE(2, 8)
+  QMC_MS_STAGE(1, 4)
+  double t = x[0];
+  t += __shfl_xor(t, 2, 64);
+  t += __shfl_xor(t, 1, 64);
+  return t;
+}
+#undef QMC_MS_STAGE
+
 // ---------------------------------------------------------------------------
 // Accept: decide (device Metropolis, u < ratio^2, when unif is given) and
 // apply the rank-1 Sherman-Morrison update of A = W^{-1} in FP64:
@@ -221,50 +267,44 @@ __device__ void rows_generic_body(const SysDev& s, const WalkDev& w, int wk, int
 //   down e (column e of W replaced by w'): A <- A - (A delta) A[e,:] / R
 // with delta = w' - (old row/column) and R = det W'/det W.  Thread t holds
 // column c = t % n of rows g, g+G, ... (g = t / n, G = blockDim / n) in
-// registers: A is read once and written once.  Column sums (up moves) reduce
-// through LDS over the G groups; row sums (down moves) are wave dot products
-// over the rows (served from cache, the rows having just been read).
+// registers: A is read once and written once.  Column sums (up moves) combine
+// the G groups' partials through LDS; row sums (down moves) are read row-wise
+// (served from cache, the rows having just been read) and reduced 16 rows per
+// wave at a time.  Every thread takes the acceptance decision itself from the
+// same values, so no barrier precedes the loads of A.
 // S > 0: the ratio is first summed from the proposal's S partial sums.
 // ---------------------------------------------------------------------------
 // acc_in: this walker's host decision (mode 0), or u: its uniform (mode 1).
 // cnt: this walker's accept counter (may be null).
-template <typename T, int QMAX>
+// UP = (e < n_up), fixed per instantiation so that each direction gets its own
+// register allocation.
+template <typename T, int QMAX, bool UP>
 __device__ void accept_body(const SysDev& s, const WalkDev& w, int wk, int e, int mode,
                             const uint8_t* __restrict__ acc_in, double u, int32_t* __restrict__ cnt, int S) {
   __shared__ double delta[kLuMaxN];
   __shared__ double save[kLuMaxN];
   __shared__ double coef[kLuMaxN];
   __shared__ double part[256];
-  __shared__ double R_s;
-  __shared__ int acc_s;
   const int n = s.nu;             // square: n_up == n_dn
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nw = blockDim.x >> 6;
-  if (tid == 0) {
-    double R;
-    if (S > 0) {
-      R = 0.0;
-      for (int k = 0; k < S; ++k) R += w.rdet_part[(long)wk * S + k];
-      w.rdet[wk] = R;
-      w.ratio[wk] = R * exp(w.dJ[wk]);
-    } else {
-      R = w.rdet[wk];
-    }
-    bool acc;
-    if (mode == 1) {
-      const double q = w.ratio[wk];
-      acc = u < q * q;
-    } else {
-      acc = acc_in[0] != 0;
-    }
-    w.acc[wk] = acc ? 1 : 0;
-    R_s = R;
-    acc_s = acc;
+  double R, ratio;
+  if (S > 0) {
+    R = 0.0;
+    for (int k = 0; k < S; ++k) R += w.rdet_part[(long)wk * S + k];
+    ratio = R * exp(w.dJ[wk]);
+  } else {
+    R = w.rdet[wk];
+    ratio = w.ratio[wk];
   }
-  __syncthreads();
-  if (!acc_s) return;
-  const double invR = 1.0 / R_s;
-  const bool up = e < s.nu;
+  const bool acc = (mode == 1) ? (u < ratio * ratio) : (acc_in[0] != 0);
+  if (tid == 0) {
+    if (S > 0) { w.rdet[wk] = R; w.ratio[wk] = ratio; }
+    w.acc[wk] = acc ? 1 : 0;
+  }
+  if (!acc) return;   // uniform over the block
+  const double invR = 1.0 / R;
+  constexpr bool up = UP;
   const int ed = e - s.nu;
   double* Aw = w.A + (long)wk * n * n;
   double* Ww = w.W + (long)wk * n * n;
@@ -272,15 +312,36 @@ __device__ void accept_body(const SysDev& s, const WalkDev& w, int wk, int e, in
   const int G = blockDim.x / n, c = tid % n, g = tid / n;
   const bool own = g < G;
   double a[QMAX];
+  // up moves: the column slices load while delta and the bookkeeping proceed;
+  // down moves load them after the row sums (cache hits, fewer live registers)
+  if constexpr (UP) {
 #pragma unroll
-  for (int q = 0; q < QMAX; ++q) {
-    const int j = g + G * q;
-    a[q] = (own && j < n) ? Aw[(long)j * n + c] : 0.0;
+    for (int q = 0; q < QMAX; ++q) {
+      const int j = g + G * q;
+      a[q] = (own && j < n) ? Aw[(long)j * n + c] : 0.0;
+    }
   }
   for (int j = tid; j < n; j += blockDim.x)
     delta[j] = up ? wn[j] - Ww[(long)e * n + j] : wn[j] - Ww[(long)j * n + ed];
+  // bookkeeping that does not depend on the update
+  {
+    T* prow = (T*)w.phi + ((long)wk * s.N + e) * s.Lp;
+    const double* pn = w.psi_new + (long)wk * s.Lp;
+    for (int mu = tid; mu < s.L; mu += blockDim.x) prow[mu] = (T)pn[mu];
+    if (tid == 0) {
+      double* re = w.r + ((long)wk * s.N + e) * 3;
+      re[0] = w.r_new[3 * wk]; re[1] = w.r_new[3 * wk + 1]; re[2] = w.r_new[3 * wk + 2];
+    }
+    if (tid == (blockDim.x > 64 ? 64 : 0)) {
+      const double dJ = w.dJ[wk];
+      w.logabs[wk] += log(fabs(R)) + dJ;
+      if (R < 0.0) w.sign[wk] = -w.sign[wk];
+      w.J[wk] += dJ;
+      if (cnt) cnt[0] += 1;
+    }
+  }
   __syncthreads();
-  if (up) {
+  if constexpr (UP) {
     double t = 0.0;
 #pragma unroll
     for (int q = 0; q < QMAX; ++q) {
@@ -296,14 +357,10 @@ __device__ void accept_body(const SysDev& s, const WalkDev& w, int wk, int e, in
       }
     }
     __syncthreads();
-    for (int k = tid; k < n; k += blockDim.x) {
-      double u = 0.0;
-      for (int q = 0; q < G; ++q) u += part[q * n + k];
-      coef[k] = u * invR;
-    }
-    __syncthreads();
     if (own) {
-      const double ck = coef[c];
+      double uc = 0.0;
+      for (int q = 0; q < G; ++q) uc += part[q * n + c];
+      const double ck = uc * invR;
 #pragma unroll
       for (int q = 0; q < QMAX; ++q) {
         const int j = g + G * q;
@@ -312,11 +369,25 @@ __device__ void accept_body(const SysDev& s, const WalkDev& w, int wk, int e, in
     }
     for (int j = tid; j < n; j += blockDim.x) Ww[(long)e * n + j] = wn[j];
   } else {
-    for (int j = wave; j < n; j += nw) {
-      double t = 0.0;
-      for (int i = lane; i < n; i += 64) t += Aw[(long)j * n + i] * delta[i];
-      t = wave_sum(t);
-      if (lane == 0) coef[j] = t * invR;
+    // rows j = wave + nw * m, 16 values of m per pass (n <= 32 nw)
+    for (int m0 = 0; wave + nw * m0 < n; m0 += 16) {
+      double x[16];
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        const int j = wave + nw * (m0 + m);
+        double t = 0.0;
+        if (j < n)
+          for (int i = lane; i < n; i += 64) t += Aw[(long)j * n + i] * delta[i];
+        x[m] = t;
+      }
+      const double tot = wave_multi_sum16(x, lane);
+      const int j = wave + nw * (m0 + (lane >> 2));
+      if ((lane & 3) == 0 && j < n) coef[j] = tot * invR;
+    }
+#pragma unroll
+    for (int q = 0; q < QMAX; ++q) {
+      const int j = g + G * q;
+      a[q] = (own && j < n) ? Aw[(long)j * n + c] : 0.0;
     }
     if (own && g == ed % G) {
       const int qe = ed / G;
@@ -335,18 +406,6 @@ __device__ void accept_body(const SysDev& s, const WalkDev& w, int wk, int e, in
       }
     }
     for (int i = tid; i < n; i += blockDim.x) Ww[(long)i * n + ed] = wn[i];
-  }
-  T* prow = (T*)w.phi + ((long)wk * s.N + e) * s.Lp;
-  const double* pn = w.psi_new + (long)wk * s.Lp;
-  for (int mu = tid; mu < s.L; mu += blockDim.x) prow[mu] = (T)pn[mu];
-  if (tid == 0) {
-    double* re = w.r + ((long)wk * s.N + e) * 3;
-    re[0] = w.r_new[3 * wk]; re[1] = w.r_new[3 * wk + 1]; re[2] = w.r_new[3 * wk + 2];
-    const double dJ = w.dJ[wk];
-    w.logabs[wk] += log(fabs(R_s)) + dJ;
-    if (R_s < 0.0) w.sign[wk] = -w.sign[wk];
-    w.J[wk] += dJ;
-    if (cnt) cnt[0] += 1;
   }
 }
 

@@ -122,7 +122,9 @@ __global__ void __launch_bounds__(256) multi_accept_kernel(MultiArgs a, const in
     double d[3], u;
     member_draw(a, k, w, wd.Wk, d, &u);
     const int nrow = e < s.nu ? s.nd : s.nu;
-    accept_body<T, QMAX>(s, wd, w, e, 1, nullptr, u, nullptr, (nrow + a.rows[k] - 1) / a.rows[k]);
+    const int S = (nrow + a.rows[k] - 1) / a.rows[k];
+    if (e < s.nu) accept_body<T, QMAX, true>(s, wd, w, e, 1, nullptr, u, nullptr, S);
+    else accept_body<T, QMAX, false>(s, wd, w, e, 1, nullptr, u, nullptr, S);
   }
 }
 
@@ -144,14 +146,16 @@ hipError_t launch_multi_prep(const MultiArgs& a, const int2* items, int n_items,
 
 hipError_t launch_multi_rows(const MultiArgs& a, bool f32, int nc, const int4* items, int n_items, int grid,
                              hipStream_t st) {
+#define QMC_MR(T, NC) case NC: return rows_launch<T, NC>(a, items, n_items, grid, st);
   if (f32) {
-    if (nc <= 2) return rows_launch<float, 2>(a, items, n_items, grid, st);
-    if (nc <= 4) return rows_launch<float, 4>(a, items, n_items, grid, st);
-    return rows_launch<float, 8>(a, items, n_items, grid, st);
+    switch (nc) { QMC_MR(float, 1) QMC_MR(float, 2) QMC_MR(float, 3) QMC_MR(float, 4)
+                  QMC_MR(float, 5) QMC_MR(float, 6) QMC_MR(float, 7) QMC_MR(float, 8) }
+  } else {
+    switch (nc) { QMC_MR(double, 1) QMC_MR(double, 2) QMC_MR(double, 3) QMC_MR(double, 4)
+                  QMC_MR(double, 5) QMC_MR(double, 6) QMC_MR(double, 7) QMC_MR(double, 8) }
   }
-  if (nc <= 2) return rows_launch<double, 2>(a, items, n_items, grid, st);
-  if (nc <= 4) return rows_launch<double, 4>(a, items, n_items, grid, st);
-  return rows_launch<double, 8>(a, items, n_items, grid, st);
+#undef QMC_MR
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_multi_accept(const MultiArgs& a, bool f32, int qmax, const int2* items, int n_items, int grid,
