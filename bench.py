@@ -308,6 +308,47 @@ def multi_leg(P, C, precision="fp32", replays=3):
             "one_system_at_a_time_moves_per_s": round(steps * n_walk / t_seq, 1)}
 
 
+def large_leg(P, C, steps=128, Wk=256):
+    """The 1024-electron workload (256 nuclei, L = 4096, Lambda banded at 8
+    bohr; n = 512 per spin, so the blocked Gauss-Jordan refresh and the
+    two-pass Sherman-Morrison update), 256 walkers, FP64: one evaluation and
+    `steps` Metropolis moves (refresh every 64); error of the evaluation against
+    the oracle on one walker."""
+    from oracle import jagp as O
+    dev = torch.device("cuda:0")
+    w = C.large_256nuc_1024e(n_walkers=Wk)
+    sysh = P.JAGPSystem(w.system)
+    wk = P.Walkers(sysh, Wk)
+    r = torch.tensor(w.r0, device=dev)
+    d, u = C.chain_arrays(41, steps, Wk)
+    d, u = torch.tensor(d, device=dev), torch.tensor(u, device=dev)
+    cnt = torch.zeros(Wk, dtype=torch.int32, device=dev)
+    wk.eval_batch(r)
+    torch.cuda.synchronize()
+    wk.set_timing(True)
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    e0.record()
+    out = wk.eval_batch(r, drift=True)
+    e1.record()
+    wk.vmc_steps(0, d, u, cnt)
+    e2.record()
+    torch.cuda.synchronize()
+    tim = wk.timing()
+    wk.set_timing(False)
+    t_eval, t_move = e0.elapsed_time(e1) / 1e3, e1.elapsed_time(e2) / 1e3
+    ref = O.evaluate(O.from_workload_system(w.system), torch.tensor(w.r0[:1]))
+    err = {k: float(f"{float(((out[k].cpu()[:1] - ref[k]).abs() / ref[k].abs().clamp(min=1.0)).max()):.3e}")
+           for k in ("logabs", "e_loc")}
+    wk.close()
+    sysh.close()
+    return {"workload": "large_256nuc_1024e", "walkers": Wk, "precision": "fp64",
+            "eloc_evals_per_s": round(Wk / t_eval, 1), "moves_per_s": round(steps * Wk / t_move, 1),
+            "acceptance": round(cnt.sum().item() / (steps * Wk), 4), "moves": steps,
+            "err_vs_oracle": {"walkers": [0], **err},
+            "kernel_ms": {k: round(v[0], 3) for k, v in tim.items() if v[1]},
+            "kernel_launches": {k: v[1] for k, v in tim.items() if v[1]}}
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -355,6 +396,7 @@ def main():
     if not args.only:
         res["forces"] = forces_leg(P, C)
         res["multi_system"] = multi_leg(P, C)
+        res["large"] = large_leg(P, C)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(res), flush=True)

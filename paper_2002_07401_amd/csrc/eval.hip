@@ -246,6 +246,33 @@ hipError_t launch_pack_basis(const SysDev& s, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Nonzero flags of the [kLamTileK x kLamTileN] tiles of Lambda and Lambda^T
+// (one block per tile pair); a banded Lambda lets the P products skip most tiles.
+__global__ void __launch_bounds__(256) lam_mask_kernel(SysDev s) {
+  const int nt = blockIdx.x, kt = blockIdx.y;
+  const int mask_ld = gridDim.x;
+  int nz = 0, nzT = 0;
+  for (int idx = threadIdx.x; idx < kLamTileK * kLamTileN; idx += blockDim.x) {
+    const int r = kt * kLamTileK + idx / kLamTileN, c = nt * kLamTileN + idx % kLamTileN;
+    if (r < s.Lp && c < s.Lp) {
+      nz |= s.lam[(long)r * s.Lp + c] != 0.0;
+      nzT |= s.lamT[(long)r * s.Lp + c] != 0.0;
+    }
+  }
+  nz = __syncthreads_or(nz);
+  nzT = __syncthreads_or(nzT);
+  if (threadIdx.x == 0) {
+    s.lam_mask[(long)kt * mask_ld + nt] = nz ? 1 : 0;
+    s.lamT_mask[(long)kt * mask_ld + nt] = nzT ? 1 : 0;
+  }
+}
+
+hipError_t launch_lam_mask(const SysDev& s, hipStream_t st) {
+  const dim3 grid((s.Lp + kLamTileN - 1) / kLamTileN, (s.Lp + kLamTileK - 1) / kLamTileK);
+  hipLaunchKernelGGL(lam_mask_kernel, grid, dim3(256), 0, st, s);
+  return hipGetLastError();
+}
+
 hipError_t launch_set_lambda(const SysDev& s, const double* lam, hipStream_t st) {
   const long tot = (long)s.L * s.L;
   hipLaunchKernelGGL(set_lambda_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, s, lam);

@@ -64,6 +64,9 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
       for (int r = 0; r < 4; ++r) acc[i][j][r] = 0;
 
   for (int k0 = 0; k0 < g.K; k0 += BK) {
+    if constexpr (BN == kLamTileN && BK == kLamTileK && !TB) {
+      if (g.kmask && !g.kmask[(long)(k0 / BK) * g.kmask_ld + n0 / BN]) continue;   // uniform per block
+    }
     for (int idx = tid; idx < BM * BK; idx += 256) {
       int mm, kk;
       if (TA) { kk = idx / BM; mm = idx % BM; } else { mm = idx / BK; kk = idx % BK; }
@@ -152,10 +155,12 @@ static hipError_t P_build_t(const SysDev& s, const WalkDev& w, int halves, hipSt
   const T* phi = (const T*)w.phi;
   T* P = (T*)w.P;
   hipError_t e = hipSuccess;
+  const int mask_ld = (s.Lp + kLamTileN - 1) / kLamTileN;
   if (halves & 1) {   // P_up = Phi_up Lambda  (rows 0..nu-1 of every walker)
     GemmArgs g = plain(w.Wk * s.nu, s.Lp, s.Lp);
     g.A = phi; g.lda = s.Lp; g.a_grp = s.nu; g.a_gs = rowst;
     g.B = lam; g.ldb = s.Lp;
+    g.kmask = s.lam_mask; g.kmask_ld = mask_ld;
     g.C = P; g.ldc = s.Lp; g.c_grp = s.nu; g.c_gs = rowst;
     e = run_gemm<64, 64, false, false, T, T, T, T>(g, st);
     if (e != hipSuccess) return e;
@@ -164,6 +169,7 @@ static hipError_t P_build_t(const SysDev& s, const WalkDev& w, int halves, hipSt
     GemmArgs g = plain(w.Wk * s.nd, s.Lp, s.Lp);
     g.A = phi + (long)s.nu * s.Lp; g.lda = s.Lp; g.a_grp = s.nd; g.a_gs = rowst;
     g.B = lamT; g.ldb = s.Lp;
+    g.kmask = s.lamT_mask; g.kmask_ld = mask_ld;
     g.C = P + (long)s.nu * s.Lp; g.ldc = s.Lp; g.c_grp = s.nd; g.c_gs = rowst;
     e = run_gemm<64, 64, false, false, T, T, T, T>(g, st);
   }

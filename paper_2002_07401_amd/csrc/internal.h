@@ -20,6 +20,10 @@ constexpr int kLuRowMax = 96;     // register (row-per-thread) Gauss-Jordan limi
 constexpr int kPropRows = 16;     // rows of P per proposal workgroup
 constexpr int kPropRowsMin = 8;   // smallest rows-per-workgroup the autotuner may pick
 constexpr int kMaxNucBack = 256;  // nuclei handled by the Jastrow backward kernel
+constexpr int kBigMaxN = 1024;    // blocked (global-memory) Gauss-Jordan limit for n > kLuMaxN
+constexpr int kGjPanel = 64;      // panel width of the blocked Gauss-Jordan
+constexpr int kLamTileK = 16;     // Lambda tile mask granularity: rows (GEMM K step) ...
+constexpr int kLamTileN = 64;     // ... and columns (GEMM N tile)
 
 inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
@@ -44,6 +48,11 @@ struct SysDev {
   int* cptr;        // [A+1] basis functions of nucleus a: cmu[cptr[a] .. cptr[a+1])
   int* cmu;         // [L]
   double4* bfn;     // [L] packed (x, y, z) of the function's centre and its zeta
+  // nonzero flags of the [kLamTileK x kLamTileN] tiles of Lambda and Lambda^T
+  // ([Lp/16][Lp/64]); the P products skip zero tiles (banded Lambda)
+  uint8_t* lam_mask;
+  uint8_t* lamT_mask;
+  int np;           // n rounded up to kGjPanel (blocked Gauss-Jordan, n > kLuMaxN)
 };
 
 // Device state of a batch of walkers.
@@ -78,6 +87,13 @@ struct WalkDev {
   double* drift;      // [Wk][N][3] grad_i log|Psi| of the last evaluation
   double* phi64;      // [Wk][N][Lp] FP64 evaluation work arrays (QMC_MIXED only)
   double* P64;        // [Wk][N][Lp]
+  // n > kLuMaxN only: blocked Gauss-Jordan and two-pass Sherman-Morrison work
+  double* T;          // [Wk][np][np] identity-padded working copy of W
+  double* Tsave;      // [Wk][kGjPanel][np] pivot rows of the current panel, before it
+  int* rowk;          // [Wk][np] step at which row i was pivoted (-1: not yet)
+  int* prow;          // [Wk][np] row pivoted at step k
+  double* pivv;       // [Wk][np] pivot value of step k
+  double* smv;        // [Wk][2][nu] coefficient and saved vectors of a rank-1 update
 };
 
 // Workspace of the reverse pass (allocated on the first qmc_forces call).
@@ -263,6 +279,7 @@ hipError_t launch_W_build(const SysDev& s, const WalkDev& w, hipStream_t st);
 hipError_t launch_Y_build(const SysDev& s, const WalkDev& w, hipStream_t st);
 hipError_t prepare_lu(int n);
 hipError_t launch_lu_inverse(const SysDev& s, const WalkDev& w, hipStream_t st);
+hipError_t launch_lam_mask(const SysDev& s, hipStream_t st);
 hipError_t launch_rowdots(const SysDev& s, const WalkDev& w, hipStream_t st);
 hipError_t launch_jastrow_assemble(const SysDev& s, const WalkDev& w, double* logabs, double* sign,
                                    double* drift, double* e_kin, double* e_loc, int32_t* status,
@@ -291,6 +308,10 @@ struct GemmArgs {
   void* C; long ldc; long c_bs; int c_grp; long c_gs;
   int batch;
   int accumulate;   // 1: C += op(A) op(B); 0: C = op(A) op(B)
+  // optional nonzero flags of B's [kLamTileK x kLamTileN] tiles ([K/16][kmask_ld]);
+  // honoured by the 64-column-tile kernels, which skip zero tiles
+  const uint8_t* kmask;
+  int kmask_ld;
 };
 
 // Plain (ungathered) argument block for an M x N x K product.

@@ -266,10 +266,11 @@ gj_inverse_row_kernel(const double* __restrict__ Wg, double* __restrict__ Ag, do
 }
 
 hipError_t launch_lu_inverse_lds(const SysDev& s, const WalkDev& w, hipStream_t st);
+static hipError_t launch_lu_inverse_big(const SysDev& s, const WalkDev& w, hipStream_t st);
 
 hipError_t launch_lu_inverse(const SysDev& s, const WalkDev& w, hipStream_t st) {
   const int n = s.nu;
-  if (n > kLuMaxN) return hipErrorNotSupported;
+  if (n > kLuMaxN) return launch_lu_inverse_big(s, w, st);
   if (n > kLuRowMax) return launch_lu_inverse_lds(s, w, st);
   const long wbs = (long)s.nu * s.nd, abs_ = (long)s.nd * s.nu;
   const dim3 blk(n > 64 ? 128 : 64);
@@ -287,12 +288,261 @@ hipError_t launch_lu_inverse(const SysDev& s, const WalkDev& w, hipStream_t st) 
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Blocked Gauss-Jordan for kLuMaxN < n <= kBigMaxN (matrix in global memory).
+//
+// T = [[W, 0], [0, I]] (np = n rounded up to 64; the identity block leaves the
+// real block's elimination unchanged, as in the register kernel).  Panels of NB
+// columns: the panel kernel runs NB in-place Gauss-Jordan steps restricted to
+// the panel columns (rows in registers, the rotating window of gj_row_body,
+// pivots chosen among rows not yet pivoted, real rows first), which equals
+// applying the steps' elimination matrix E to the panel; E differs from the
+// identity only in the columns of the panel's pivot rows P, and in-place
+// Gauss-Jordan leaves exactly those columns of E in the panel.  The update
+// kernel then applies E to every other column:
+//   T[:, O] <- D T[:, O] + T'[:, C] T_old[P, O]      (D zeroes the rows P),
+// a product with K = NB.  The finish kernel writes W^{-1}[k][p_k'] = T[p_k][k']
+// and log|det W| = sum log|pivot_k|, sign = sgn(p) prod sign(pivot_k).
+// ---------------------------------------------------------------------------
+__global__ void gj_big_init_kernel(const double* __restrict__ W, double* __restrict__ T, int* __restrict__ rowk,
+                                   int* __restrict__ singular, int n, int np) {
+  const long wk = blockIdx.y;
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < (long)np * np) {
+    const int i = (int)(idx / np), j = (int)(idx % np);
+    T[wk * np * np + idx] = (i < n && j < n) ? W[wk * n * n + (long)i * n + j] : (i == j ? 1.0 : 0.0);
+  }
+  if (idx < np) rowk[wk * np + idx] = -1;
+  if (idx == 0) singular[wk] = 0;
+}
+
+template <int NB>
+__global__ void __launch_bounds__(NB == 64 ? 512 : 1024)
+gj_panel_kernel(double* __restrict__ T, double* __restrict__ Tsave, int* __restrict__ rowk, int* __restrict__ prow,
+                double* __restrict__ pivv, int* __restrict__ singular, int n, int np, int c0) {
+  __shared__ double rk[2][16][NB];
+  __shared__ unsigned long long key_s[2][16];
+  __shared__ int pr_s[NB];
+  const long wk = blockIdx.x;
+  const int i = threadIdx.x, lane = i & 63, wave = i >> 6, nw = blockDim.x >> 6;
+  if (singular[wk]) return;   // the same value for the whole block
+  double* Tw = T + wk * np * np;
+  int* rkw = rowk + wk * np;
+  int my_k = rkw[i];
+  double a[NB];
+#pragma unroll
+  for (int j = 0; j < NB; j += 2) {
+    const double2 v = *reinterpret_cast<const double2*>(Tw + (long)i * np + c0 + j);
+    a[j] = v.x; a[j + 1] = v.y;
+  }
+  double own_piv = 1.0;
+  bool mine = false;
+  int sing = 0;
+  for (int kk = 0; kk < NB; ++kk) {
+    const int step = c0 + kk, b = kk & 1;
+    const double f = a[0];
+    const bool elig = my_k < 0 && (i < n || step >= n);
+    const unsigned long long key =
+        elig ? ((__double_as_longlong(fabs(f)) & ~0x7FFull) | (unsigned long long)(2047 - i)) : 0ull;   // > 0
+    const unsigned long long wmax = wave_max_u64(key);
+    if (key == wmax && wmax != 0ull) {
+#pragma unroll
+      for (int j = 0; j < NB; ++j) rk[b][wave][j] = a[j];
+    }
+    if (lane == 0) key_s[b][wave] = wmax;
+    __syncthreads();
+    unsigned long long best = key_s[b][0];
+    int ws = 0;
+    for (int q = 1; q < nw; ++q)
+      if (key_s[b][q] > best) { best = key_s[b][q]; ws = q; }
+    const double* rr = rk[b][ws];
+    const double piv = rr[0];
+    if (!(piv != 0.0)) { sing = 1; break; }   // uniform across the block
+    const int p = 2047 - (int)(best & 0x7FFull);
+    const bool isp = i == p;
+    if (isp) { my_k = step; own_piv = piv; mine = true; }
+    if (i == 0) {
+      pr_s[kk] = p;
+      prow[wk * np + step] = p;
+      pivv[wk * np + step] = piv;
+    }
+    const double g = isp ? 0.0 : f * (1.0 / piv);
+#pragma unroll
+    for (int j = 0; j < NB - 1; ++j) a[j] = fma(-g, rr[j + 1], a[j + 1]);
+    a[NB - 1] = isp ? 1.0 : -g;
+  }
+  if (sing) {
+    if (i == 0) singular[wk] = 1;
+    return;
+  }
+  if (mine) {
+    const double inv = 1.0 / own_piv;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) a[j] *= inv;
+  }
+#pragma unroll
+  for (int j = 0; j < NB; j += 2)
+    *reinterpret_cast<double2*>(Tw + (long)i * np + c0 + j) = make_double2(a[j], a[j + 1]);
+  rkw[i] = my_k;
+  __syncthreads();
+  // the panel's pivot rows outside the panel, before the update kernel changes them
+  double* Sw = Tsave + wk * NB * np;
+  for (int kk = 0; kk < NB; ++kk) {
+    const double* src = Tw + (long)pr_s[kk] * np;
+    for (int o = i; o < np; o += blockDim.x)
+      Sw[(long)kk * np + o] = (o >= c0 && o < c0 + NB) ? 0.0 : src[o];
+  }
+}
+
+// T[r][o] <- (rowk[r] in panel ? 0 : T[r][o]) + sum_kk T[r][c0+kk] Tsave[kk][o]
+// for o outside the panel; 64 x 64 tiles, 4 x 4 outputs per thread.
+template <int NB>
+__global__ void __launch_bounds__(256)
+gj_update_kernel(double* __restrict__ T, const double* __restrict__ Tsave, const int* __restrict__ rowk,
+                 const int* __restrict__ singular, int np, int c0) {
+  __shared__ double Fp[64][NB + 1];
+  __shared__ double Sv[NB][64 + 1];
+  __shared__ int zr[64];
+  const long wk = blockIdx.z;
+  const int o0 = blockIdx.x * 64, r0 = blockIdx.y * 64;
+  if (singular[wk]) return;
+  if (o0 >= c0 && o0 + 64 <= c0 + NB) return;   // tile inside the panel
+  double* Tw = T + wk * np * np;
+  const double* Sw = Tsave + wk * NB * np;
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  for (int idx = tid; idx < 64 * NB; idx += 256) {
+    const int r = idx / NB, kk = idx % NB;
+    Fp[r][kk] = Tw[(long)(r0 + r) * np + c0 + kk];
+  }
+  for (int idx = tid; idx < NB * 64; idx += 256) {
+    const int kk = idx / 64, o = idx % 64;
+    Sv[kk][o] = Sw[(long)kk * np + o0 + o];
+  }
+  if (tid < 64) {
+    const int k = rowk[wk * np + r0 + tid];
+    zr[tid] = (k >= c0 && k < c0 + NB) ? 1 : 0;
+  }
+  __syncthreads();
+  double acc[4][4];
+#pragma unroll
+  for (int ri = 0; ri < 4; ++ri)
+#pragma unroll
+    for (int cj = 0; cj < 4; ++cj) {
+      const int r = ty + 16 * ri, o = tx + 16 * cj;
+      acc[ri][cj] = zr[r] ? 0.0 : Tw[(long)(r0 + r) * np + o0 + o];
+    }
+#pragma unroll 8
+  for (int kk = 0; kk < NB; ++kk) {
+    double fr[4], sc[4];
+#pragma unroll
+    for (int ri = 0; ri < 4; ++ri) fr[ri] = Fp[ty + 16 * ri][kk];
+#pragma unroll
+    for (int cj = 0; cj < 4; ++cj) sc[cj] = Sv[kk][tx + 16 * cj];
+#pragma unroll
+    for (int ri = 0; ri < 4; ++ri)
+#pragma unroll
+      for (int cj = 0; cj < 4; ++cj) acc[ri][cj] = fma(fr[ri], sc[cj], acc[ri][cj]);
+  }
+#pragma unroll
+  for (int ri = 0; ri < 4; ++ri)
+#pragma unroll
+    for (int cj = 0; cj < 4; ++cj) {
+      const int r = ty + 16 * ri, o = o0 + tx + 16 * cj;
+      if (o < c0 || o >= c0 + NB) Tw[(long)(r0 + r) * np + o] = acc[ri][cj];
+    }
+}
+
+// A[k][m] = T[prow[k]][rowk[m]] for k, m < n (4 rows of A per block).
+__global__ void __launch_bounds__(256)
+gj_big_output_kernel(const double* __restrict__ T, const int* __restrict__ rowk, const int* __restrict__ prow,
+                     const int* __restrict__ singular, double* __restrict__ A, int n, int np) {
+  const long wk = blockIdx.y;
+  const int k = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (k >= n) return;
+  double* out = A + wk * n * n + (long)k * n;
+  const double nanv = __longlong_as_double(0x7ff8000000000000LL);
+  if (singular[wk]) {
+    for (int m = lane; m < n; m += 64) out[m] = nanv;
+    return;
+  }
+  const double* src = T + wk * np * np + (long)prow[wk * np + k] * np;
+  const int* rk = rowk + wk * np;
+  for (int m = lane; m < n; m += 64) out[m] = src[rk[m]];
+}
+
+// log|det W| = sum_k log|pivot_k|; sign = prod sign(pivot_k) * (-1)^{inversions of k -> p_k}.
+__global__ void __launch_bounds__(1024)
+gj_big_det_kernel(const int* __restrict__ rowk, const double* __restrict__ pivv, const int* __restrict__ singular,
+                  double* __restrict__ logdet, double* __restrict__ detsign, int n, int np) {
+  __shared__ double rd[16];
+  __shared__ int ri[16];
+  const long wk = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  if (singular[wk]) {
+    if (tid == 0) { logdet[wk] = -__builtin_inf(); detsign[wk] = 0.0; }
+    return;
+  }
+  const int* rk = rowk + wk * np;
+  double ls = 0.0;
+  int odd = 0;
+  for (int k = tid; k < n; k += blockDim.x) {
+    const double pv = pivv[wk * np + k];
+    ls += log(fabs(pv));
+    odd += pv < 0.0;
+  }
+  for (int i = tid; i < n; i += blockDim.x) {
+    const int ki = rk[i];
+    for (int i2 = i + 1; i2 < n; ++i2) odd += rk[i2] < ki;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    ls += __shfl_xor(ls, o, 64);
+    odd += __shfl_xor(odd, o, 64);
+  }
+  if (lane == 0) { rd[wave] = ls; ri[wave] = odd; }
+  __syncthreads();
+  if (tid == 0) {
+    double t = 0.0;
+    int par = 0;
+    for (int q = 0; q < nw; ++q) { t += rd[q]; par += ri[q]; }
+    logdet[wk] = t;
+    detsign[wk] = (par & 1) ? -1.0 : 1.0;
+  }
+}
+
+static hipError_t launch_lu_inverse_big(const SysDev& s, const WalkDev& w, hipStream_t st) {
+  const int n = s.nu, np = s.np;
+  if (n > kBigMaxN || np % 64 || !w.T) return hipErrorNotSupported;
+  const long nn = (long)np * np;
+  hipLaunchKernelGGL(gj_big_init_kernel, dim3((unsigned)((nn + 255) / 256), w.Wk), dim3(256), 0, st, w.W, w.T,
+                     w.rowk, w.singular, n, np);
+  const dim3 ug(np / 64, np / 64, w.Wk);
+  if (np <= 512) {
+    for (int c0 = 0; c0 < np; c0 += 64) {
+      hipLaunchKernelGGL(gj_panel_kernel<64>, dim3(w.Wk), dim3(np), 0, st, w.T, w.Tsave, w.rowk, w.prow, w.pivv,
+                         w.singular, n, np, c0);
+      hipLaunchKernelGGL(gj_update_kernel<64>, ug, dim3(256), 0, st, w.T, w.Tsave, w.rowk, w.singular, np, c0);
+    }
+  } else {
+    for (int c0 = 0; c0 < np; c0 += 32) {
+      hipLaunchKernelGGL(gj_panel_kernel<32>, dim3(w.Wk), dim3(np), 0, st, w.T, w.Tsave, w.rowk, w.prow, w.pivv,
+                         w.singular, n, np, c0);
+      hipLaunchKernelGGL(gj_update_kernel<32>, ug, dim3(256), 0, st, w.T, w.Tsave, w.rowk, w.singular, np, c0);
+    }
+  }
+  hipLaunchKernelGGL(gj_big_output_kernel, dim3((n + 3) / 4, w.Wk), dim3(256), 0, st, w.T, w.rowk, w.prow,
+                     w.singular, w.A, n, np);
+  hipLaunchKernelGGL(gj_big_det_kernel, dim3(w.Wk), dim3(1024), 0, st, w.rowk, w.pivv, w.singular, w.logdet,
+                     w.detsign, n, np);
+  return hipGetLastError();
+}
+
 static size_t lu_lds_bytes(int n) { return ((size_t)n * (n + 1) + 2 * (size_t)n) * sizeof(double); }
 
 // Raises the LDS limit of the LDS variant for an n x n problem; called once at
 // system creation so that no launch (possibly under graph capture) needs it.
 hipError_t prepare_lu(int n) {
-  if (n <= kLuRowMax || lu_lds_bytes(n) <= 64 * 1024) return hipSuccess;
+  if (n <= kLuRowMax || n > kLuMaxN || lu_lds_bytes(n) <= 64 * 1024) return hipSuccess;
   return hipFuncSetAttribute((const void*)gj_inverse_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)lu_lds_bytes(n));
 }

@@ -20,6 +20,7 @@
 // ratio, which the accept kernel (device Metropolis) or the finalize kernel
 // (host-driven moves) sums in a fixed order.
 #include "move_dev.h"
+#include <algorithm>
 
 namespace qmc {
 
@@ -141,9 +142,131 @@ static hipError_t accept_launch_t(const SysDev& s, const WalkDev& w, int e, cons
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Sherman-Morrison for kLuMaxN < n <= kBigMaxN, in two passes over A.
+// Pass 1 (grid (ceil(n/64), Wk)): decision, delta, and 64 entries per block of
+//   up:   coef[c] = (delta^T A)[c] / R,  save = A[:, e]   (block 0)
+//   down: coef[j] = (A delta)[j] / R,    save = A[e, :]   (block 0)
+// Pass 2: A -= save coef^T (up) or coef save^T (down), the W row/column, the
+// basis row and the bookkeeping (block 0).  Same arithmetic as accept_body.
+// ---------------------------------------------------------------------------
+template <bool UP>
+__global__ void __launch_bounds__(256)
+accept_big_coef_kernel(SysDev s, WalkDev w, int e, const uint8_t* __restrict__ acc_in,
+                       const double* __restrict__ unif, int S) {
+  __shared__ double delta[kBigMaxN];
+  __shared__ double part[4][64];
+  const int wk = blockIdx.y, x0 = blockIdx.x * 64;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double R, ratio;
+  if (S > 0) {
+    R = 0.0;
+    for (int k = 0; k < S; ++k) R += w.rdet_part[(long)wk * S + k];
+    ratio = R * exp(w.dJ[wk]);
+  } else {
+    R = w.rdet[wk];
+    ratio = w.ratio[wk];
+  }
+  const bool acc = unif ? (unif[wk] < ratio * ratio) : (acc_in[wk] != 0);
+  if (blockIdx.x == 0 && tid == 0) {
+    if (S > 0) { w.rdet[wk] = R; w.ratio[wk] = ratio; }
+    w.acc[wk] = acc ? 1 : 0;
+  }
+  if (!acc) return;
+  const int n = s.nu, ed = e - s.nu;
+  const double invR = 1.0 / R;
+  const double* Aw = w.A + (long)wk * n * n;
+  const double* Ww = w.W + (long)wk * n * n;
+  const double* wn = w.w_new + (long)wk * n;
+  double* coef = w.smv + (long)wk * 2 * n;
+  double* save = coef + n;
+  for (int j = tid; j < n; j += 256) delta[j] = UP ? wn[j] - Ww[(long)e * n + j] : wn[j] - Ww[(long)j * n + ed];
+  if (blockIdx.x == 0)
+    for (int j = tid; j < n; j += 256) save[j] = UP ? Aw[(long)j * n + e] : Aw[(long)ed * n + j];
+  __syncthreads();
+  if constexpr (UP) {
+    const int c = x0 + lane;
+    double t = 0.0;
+    if (c < n)
+      for (int j = wave; j < n; j += 4) t += delta[j] * Aw[(long)j * n + c];
+    part[wave][lane] = t;
+    __syncthreads();
+    if (tid < 64 && c < n) coef[c] = (part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane]) * invR;
+  } else {
+    double xv[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const int j = x0 + wave * 16 + m;
+      double t = 0.0;
+      if (j < n)
+        for (int i = lane; i < n; i += 64) t += Aw[(long)j * n + i] * delta[i];
+      xv[m] = t;
+    }
+    const double tot = wave_multi_sum16(xv, lane);
+    const int j = x0 + wave * 16 + (lane >> 2);
+    if ((lane & 3) == 0 && j < n) coef[j] = tot * invR;
+  }
+}
+
+template <typename T, bool UP>
+__global__ void __launch_bounds__(256)
+accept_big_update_kernel(SysDev s, WalkDev w, int e, int32_t* __restrict__ accept_count) {
+  const int wk = blockIdx.y;
+  if (!w.acc[wk]) return;
+  const int n = s.nu, ed = e - s.nu;
+  double* Aw = w.A + (long)wk * n * n;
+  const double* coef = w.smv + (long)wk * 2 * n;
+  const double* save = coef + n;
+  const long nn = (long)n * n;
+  for (long idx = (long)blockIdx.x * 256 + threadIdx.x; idx < nn; idx += (long)gridDim.x * 256) {
+    const int j = (int)(idx / n), c = (int)(idx % n);
+    Aw[idx] = UP ? Aw[idx] - save[j] * coef[c] : Aw[idx] - coef[j] * save[c];
+  }
+  if (blockIdx.x != 0) return;
+  const int tid = threadIdx.x;
+  double* Ww = w.W + (long)wk * n * n;
+  const double* wn = w.w_new + (long)wk * n;
+  for (int j = tid; j < n; j += 256) {
+    if (UP) Ww[(long)e * n + j] = wn[j];
+    else Ww[(long)j * n + ed] = wn[j];
+  }
+  T* prow = (T*)w.phi + ((long)wk * s.N + e) * s.Lp;
+  const double* pn = w.psi_new + (long)wk * s.Lp;
+  for (int mu = tid; mu < s.L; mu += 256) prow[mu] = (T)pn[mu];
+  if (tid == 0) {
+    const double R = w.rdet[wk];
+    double* re = w.r + ((long)wk * s.N + e) * 3;
+    re[0] = w.r_new[3 * wk]; re[1] = w.r_new[3 * wk + 1]; re[2] = w.r_new[3 * wk + 2];
+    const double dJ = w.dJ[wk];
+    w.logabs[wk] += log(fabs(R)) + dJ;
+    if (R < 0.0) w.sign[wk] = -w.sign[wk];
+    w.J[wk] += dJ;
+    if (accept_count) accept_count[wk] += 1;
+  }
+}
+
+template <typename T>
+static hipError_t accept_big_t(const SysDev& s, const WalkDev& w, int e, const uint8_t* acc, const double* unif,
+                               int32_t* accept_count, int S, hipStream_t st) {
+  const int n = s.nu;
+  if (n > kBigMaxN || !w.smv) return hipErrorNotSupported;
+  const dim3 g1((n + 63) / 64, w.Wk), g2((unsigned)std::min<long>(((long)n * n + 1023) / 1024, 256), w.Wk);
+  if (e < s.nu) {
+    hipLaunchKernelGGL(accept_big_coef_kernel<true>, g1, dim3(256), 0, st, s, w, e, acc, unif, S);
+    hipLaunchKernelGGL((accept_big_update_kernel<T, true>), g2, dim3(256), 0, st, s, w, e, accept_count);
+  } else {
+    hipLaunchKernelGGL(accept_big_coef_kernel<false>, g1, dim3(256), 0, st, s, w, e, acc, unif, S);
+    hipLaunchKernelGGL((accept_big_update_kernel<T, false>), g2, dim3(256), 0, st, s, w, e, accept_count);
+  }
+  return hipGetLastError();
+}
+
 static hipError_t accept_launch(const SysDev& s, const WalkDev& w, int e, const uint8_t* acc,
                                 const double* unif, int32_t* accept_count, int S, hipStream_t st) {
-  if (s.nu > kLuMaxN) return hipErrorNotSupported;
+  if (s.nu > kLuMaxN) {
+    if (s.f32()) return accept_big_t<float>(s, w, e, acc, unif, accept_count, S, st);
+    return accept_big_t<double>(s, w, e, acc, unif, accept_count, S, st);
+  }
   if (s.f32()) return accept_launch_t<float>(s, w, e, acc, unif, accept_count, S, st);
   return accept_launch_t<double>(s, w, e, acc, unif, accept_count, S, st);
 }

@@ -144,7 +144,7 @@ extern "C" qmc_status qmc_system_create(const qmc_system_desc* desc, qmc_system*
     return fail(QMC_ERR_ARG, "bad basis");
   if (q.n_up <= 0 || q.n_dn < 0) return fail(QMC_ERR_ARG, "bad electron counts");
   if (q.n_up != q.n_dn) return fail(QMC_ERR_UNSUPPORTED, "only n_up == n_dn is built");
-  if (q.n_up > kLuMaxN) return fail(QMC_ERR_UNSUPPORTED, "n_up > 128 needs the blocked LU");
+  if (q.n_up > kBigMaxN) return fail(QMC_ERR_UNSUPPORTED, "n_up > 1024 is not built");
   if (q.precision != QMC_FP64 && q.precision != QMC_W_FP32 && q.precision != QMC_MIXED)
     return fail(QMC_ERR_UNSUPPORTED, "precision not built");
   if (q.refresh_every < 1) return fail(QMC_ERR_ARG, "refresh_every must be >= 1");
@@ -177,6 +177,7 @@ extern "C" qmc_status qmc_system_create(const qmc_system_desc* desc, qmc_system*
   d.j1_form = q.j1_form; d.j2_form = q.j2_form;
   for (int k = 0; k < 8; ++k) d.j2[k] = (q.j2 && k < q.n_j2) ? q.j2[k] : 0.0;
   d.precision = q.precision; d.refresh_every = q.refresh_every;
+  d.np = round_up(d.nu, 64);
   const int Lp = d.Lp, A = q.n_nuc;
   std::vector<double> lam((size_t)Lp * Lp, 0.0), lamT((size_t)Lp * Lp, 0.0);
   for (int i = 0; i < L; ++i)
@@ -218,6 +219,14 @@ extern "C" qmc_status qmc_system_create(const qmc_system_desc* desc, qmc_system*
     if (!e) e = up((void**)&d.lamT32, lT32.data(), sizeof(float) * lT32.size());
   }
   if (!e) e = prepare_lu(d.nu);
+  if (!e) {
+    const size_t mb = (size_t)((Lp + kLamTileK - 1) / kLamTileK) * ((Lp + kLamTileN - 1) / kLamTileN);
+    std::vector<uint8_t> ones(mb, 1);
+    e = up((void**)&d.lam_mask, ones.data(), mb);
+    if (!e) e = up((void**)&d.lamT_mask, ones.data(), mb);
+    if (!e) e = launch_lam_mask(d, nullptr);
+    if (!e) e = hipStreamSynchronize(nullptr);
+  }
   if (e != hipSuccess) {
     delete s;
     return e == hipErrorOutOfMemory ? fail(QMC_ERR_OOM, "device allocation failed") : hip_fail(e, "system_create");
@@ -284,6 +293,15 @@ extern "C" qmc_status qmc_walkers_create(qmc_system* sys, int32_t n_walkers, qmc
   if (s.precision == QMC_MIXED) {
     al((void**)&d.phi64, sizeof(double) * Wk * N * s.Lp);
     al((void**)&d.P64, sizeof(double) * Wk * N * s.Lp);
+  }
+  if (s.nu > kLuMaxN) {
+    const size_t np = s.np;
+    al((void**)&d.T, sizeof(double) * Wk * np * np);
+    al((void**)&d.Tsave, sizeof(double) * Wk * kGjPanel * np);
+    al((void**)&d.rowk, sizeof(int) * Wk * np);
+    al((void**)&d.prow, sizeof(int) * Wk * np);
+    al((void**)&d.pivv, sizeof(double) * Wk * np);
+    al((void**)&d.smv, sizeof(double) * Wk * 2 * s.nu);
   }
   if (e != hipSuccess) {
     delete wk;
@@ -532,6 +550,7 @@ extern "C" qmc_status qmc_system_set_params(qmc_system* sys, const double* R, co
   if (R) HIP_TRY(hipMemcpyAsync(d.R, R, sizeof(double) * 3 * d.n_nuc, hipMemcpyDeviceToDevice, stream), "set R");
   if (zeta) HIP_TRY(hipMemcpyAsync(d.zeta, zeta, sizeof(double) * d.L, hipMemcpyDeviceToDevice, stream), "set zeta");
   if (lambda) HIP_TRY(launch_set_lambda(d, lambda, stream), "set lambda");
+  if (lambda) HIP_TRY(launch_lam_mask(d, stream), "lambda mask");
   if (R || zeta) HIP_TRY(launch_pack_basis(d, stream), "pack basis");
   if (jas) {
     HIP_TRY(hipMemcpyAsync(d.j1_b, jas, sizeof(double) * d.n_nuc, hipMemcpyDeviceToDevice, stream), "set j1");
