@@ -28,7 +28,7 @@ import torch  # noqa: E402
 
 METRIC = "walker-electron moves/s + E_loc evals/s at 160e, mixed vs FP64, err vs oracle"
 HBM_PEAK_GBS = 8000.0
-MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "mixed": 157.3}
+MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "mixed": 157.3, "bf16": 157.3}
 
 
 def parse():
@@ -37,9 +37,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--walkers", type=int, default=1024)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed", "fp32"],
-                    help="fp64; mixed = FP32 move path with FP64-accurate evaluations; "
-                         "fp32 = FP32 move path and FP32-product evaluations")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed", "bf16", "fp32"],
+                    help="fp64; mixed = FP32 move path with FP64-accurate evaluations; bf16 = the "
+                         "same with BF16 move rows; fp32 = FP32 move path and FP32-product evaluations")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--oracle-walkers", type=int, default=4)
     ap.add_argument("--only", action="store_true", help="run the headline precision only")
@@ -145,8 +145,8 @@ def run_precision(P, C, w, args, precision):
     s = w.system
     N = s.n_up + s.n_dn
     Wk = args.walkers
-    prec = {"fp64": P.QMC_FP64, "mixed": P.QMC_MIXED, "fp32": P.QMC_W_FP32}[precision]
-    esz = 8 if precision == "fp64" else 4
+    prec = {"fp64": P.QMC_FP64, "mixed": P.QMC_MIXED, "bf16": P.QMC_MIXED_BF16, "fp32": P.QMC_W_FP32}[precision]
+    esz = {"fp64": 8, "bf16": 2}.get(precision, 4)
     sysh = P.JAGPSystem(s, precision=prec)
     wk = P.Walkers(sysh, Wk)
     n_tot = args.warmup + args.steps
@@ -204,7 +204,7 @@ def run_precision(P, C, w, args, precision):
         achieved = units / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": (recorded_traffic("fp64" if precision == "fp64" else "fp32", Wk)
+                "traffic": (recorded_traffic({"fp64": "fp64", "bf16": "bf16"}.get(precision, "fp32"), Wk)
                             if dom == "propose" else None),
                 "bytes_per_launch": int(units), "avg_launch_us": round(avg_ms * 1e3, 2)}
     else:
@@ -365,7 +365,7 @@ def main():
     s = w.system
     N = s.n_up + s.n_dn
     main_prec = args.precision
-    others = [p for p in ("fp64", "mixed", "fp32") if p != main_prec]
+    others = [p for p in ("fp64", "mixed", "bf16", "fp32") if p != main_prec]
     head = run_precision(P, C, w, args, main_prec)
     sides = {} if args.only else {p: run_precision(P, C, w, args, p) for p in others}
     res = {

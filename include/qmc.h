@@ -61,11 +61,15 @@ typedef enum {
   QMC_FP64 = 0,    /* everything FP64                                           */
   QMC_W_FP32 = 1,  /* Phi, P = Phi Lambda and the W products in FP32 on MFMA
                       with FP32 accumulation; FP64 LU/inverse/SM/ratios          */
-  QMC_MIXED = 2    /* moves as QMC_W_FP32 (FP32 Phi and P rows streamed by the
+  QMC_MIXED = 2,   /* moves as QMC_W_FP32 (FP32 Phi and P rows streamed by the
                       proposals); every qmc_eval_batch builds Phi, P, W and the
                       cofactor products in FP64 (log|Psi|, E_loc and drift at
                       FP64 accuracy) and stores the FP32 copies the moves read.
                       Two extra [Wk][N][round_up(L,32)] FP64 work arrays.        */
+  QMC_MIXED_BF16 = 3 /* as QMC_MIXED with the moves' Phi and P rows stored in
+                      BF16 (half the streamed bytes of FP32; the P half rebuilds
+                      between evaluations run on MFMA from the BF16 rows with
+                      FP32 accumulation); ratios and updates FP64              */
 } qmc_precision;
 
 typedef struct qmc_system qmc_system;   /* opaque: nuclei, basis, Lambda, Jastrow */

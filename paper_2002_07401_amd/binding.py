@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libqmc_jagp.so")
 QMC_FP64 = 0
 QMC_W_FP32 = 1
 QMC_MIXED = 2
+QMC_MIXED_BF16 = 3
 
 STATE_R, STATE_LOGABS, STATE_SIGN, STATE_W, STATE_AINV, STATE_PHI = range(6)
 

@@ -20,28 +20,32 @@ __global__ void __launch_bounds__(256) basis_values_kernel(SysDev s, const doubl
 
 hipError_t launch_basis_values(const SysDev& s, const WalkDev& w, hipStream_t st) {
   const dim3 grid((unsigned)((long)w.Wk * s.N));
-  if (s.f32())
+  if (s.bf16())
+    hipLaunchKernelGGL(basis_values_kernel<bf16s>, grid, dim3(256), 0, st, s, w.r, (bf16s*)w.phi);
+  else if (s.f32())
     hipLaunchKernelGGL(basis_values_kernel<float>, grid, dim3(256), 0, st, s, w.r, (float*)w.phi);
   else
     hipLaunchKernelGGL(basis_values_kernel<double>, grid, dim3(256), 0, st, s, w.r, (double*)w.phi);
   return hipGetLastError();
 }
 
-// FP32 copies of FP64 arrays (padding included), 4 elements per thread.
-__global__ void __launch_bounds__(256) downcast_kernel(const double* __restrict__ src, float* __restrict__ dst,
-                                                       long n) {
+// FP32 or BF16 copies of FP64 arrays (padding included), 4 elements per thread.
+template <typename T>
+__global__ void __launch_bounds__(256) downcast_kernel(const double* __restrict__ src, T* __restrict__ dst, long n) {
   const long i = 4 * ((long)blockIdx.x * blockDim.x + threadIdx.x);
   if (i + 3 < n) {
     const double4 v = *reinterpret_cast<const double4*>(src + i);
-    *reinterpret_cast<float4*>(dst + i) = make_float4((float)v.x, (float)v.y, (float)v.z, (float)v.w);
+    dst[i] = (T)v.x; dst[i + 1] = (T)v.y; dst[i + 2] = (T)v.z; dst[i + 3] = (T)v.w;
   } else {
-    for (long k = i; k < n; ++k) dst[k] = (float)src[k];
+    for (long k = i; k < n; ++k) dst[k] = (T)src[k];
   }
 }
 
-hipError_t launch_downcast(const double* src, float* dst, long n, hipStream_t st) {
+hipError_t launch_downcast(const double* src, void* dst, bool to_bf16, long n, hipStream_t st) {
   const long threads = (n + 3) / 4;
-  hipLaunchKernelGGL(downcast_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, src, dst, n);
+  const dim3 grid((unsigned)((threads + 255) / 256));
+  if (to_bf16) hipLaunchKernelGGL(downcast_kernel<bf16s>, grid, dim3(256), 0, st, src, (bf16s*)dst, n);
+  else hipLaunchKernelGGL(downcast_kernel<float>, grid, dim3(256), 0, st, src, (float*)dst, n);
   return hipGetLastError();
 }
 
@@ -211,7 +215,9 @@ __global__ void export_phi_kernel(SysDev s, long rows, const T* __restrict__ phi
 hipError_t launch_export_phi(const SysDev& s, const WalkDev& w, double* dst, hipStream_t st) {
   const long rows = (long)w.Wk * s.N;
   const unsigned nb = (unsigned)((rows * s.L + 255) / 256);
-  if (s.f32())
+  if (s.bf16())
+    hipLaunchKernelGGL(export_phi_kernel<bf16s>, dim3(nb), dim3(256), 0, st, s, rows, (const bf16s*)w.phi, dst);
+  else if (s.f32())
     hipLaunchKernelGGL(export_phi_kernel<float>, dim3(nb), dim3(256), 0, st, s, rows, (const float*)w.phi, dst);
   else
     hipLaunchKernelGGL(export_phi_kernel<double>, dim3(nb), dim3(256), 0, st, s, rows, (const double*)w.phi, dst);

@@ -113,7 +113,8 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
         const int gn = n0 + wn * WN + j * 16 + (lane & 15);
         if (gm < g.M && gn < g.N) {
           TO* cp = C + (long)(gm / g.c_grp) * g.c_gs + (long)(gm % g.c_grp) * g.ldc + gn;
-          *cp = g.accumulate ? (TO)(*cp + (TO)acc[i][j][r]) : (TO)acc[i][j][r];
+          if constexpr (sizeof(TO) == 2) *cp = (TO)acc[i][j][r];   // BF16 output: never accumulated
+          else *cp = g.accumulate ? (TO)(*cp + (TO)acc[i][j][r]) : (TO)acc[i][j][r];
         }
       }
 }
@@ -148,9 +149,11 @@ hipError_t gemm_f64(const GemmArgs& g, bool ta, bool tb, bool big, hipStream_t s
 #undef QMC_G
 }
 
-template <typename T>
+// T: storage of Phi and P; TL: storage of Lambda and the MFMA operand type
+// (BF16 rows multiply the FP32 Lambda with FP32 accumulation).
+template <typename T, typename TL = T>
 static hipError_t P_build_t(const SysDev& s, const WalkDev& w, int halves, hipStream_t st,
-                            const T* lam, const T* lamT) {
+                            const TL* lam, const TL* lamT) {
   const long rowst = (long)s.N * s.Lp;
   const T* phi = (const T*)w.phi;
   T* P = (T*)w.P;
@@ -162,7 +165,7 @@ static hipError_t P_build_t(const SysDev& s, const WalkDev& w, int halves, hipSt
     g.B = lam; g.ldb = s.Lp;
     g.kmask = s.lam_mask; g.kmask_ld = mask_ld;
     g.C = P; g.ldc = s.Lp; g.c_grp = s.nu; g.c_gs = rowst;
-    e = run_gemm<64, 64, false, false, T, T, T, T>(g, st);
+    e = run_gemm<64, 64, false, false, T, TL, TL, T>(g, st);
     if (e != hipSuccess) return e;
   }
   if (halves & 2) {   // P_dn = Phi_dn Lambda^T (rows nu..N-1)
@@ -171,12 +174,13 @@ static hipError_t P_build_t(const SysDev& s, const WalkDev& w, int halves, hipSt
     g.B = lamT; g.ldb = s.Lp;
     g.kmask = s.lamT_mask; g.kmask_ld = mask_ld;
     g.C = P + (long)s.nu * s.Lp; g.ldc = s.Lp; g.c_grp = s.nd; g.c_gs = rowst;
-    e = run_gemm<64, 64, false, false, T, T, T, T>(g, st);
+    e = run_gemm<64, 64, false, false, T, TL, TL, T>(g, st);
   }
   return e;
 }
 
 hipError_t launch_P_build(const SysDev& s, const WalkDev& w, int halves, hipStream_t st) {
+  if (s.bf16()) return P_build_t<bf16s, float>(s, w, halves, st, s.lam32, s.lamT32);
   if (s.f32()) return P_build_t<float>(s, w, halves, st, s.lam32, s.lamT32);
   return P_build_t<double>(s, w, halves, st, s.lam, s.lamT);
 }
@@ -197,6 +201,7 @@ static hipError_t W_build_t(const SysDev& s, const WalkDev& w, hipStream_t st) {
 }
 
 hipError_t launch_W_build(const SysDev& s, const WalkDev& w, hipStream_t st) {
+  if (s.bf16()) return hipErrorNotSupported;   // BF16 systems evaluate in FP64
   if (s.f32()) return W_build_t<float>(s, w, st);
   return W_build_t<double>(s, w, st);
 }
@@ -231,6 +236,7 @@ static hipError_t Y_build_t(const SysDev& s, const WalkDev& w, hipStream_t st) {
 }
 
 hipError_t launch_Y_build(const SysDev& s, const WalkDev& w, hipStream_t st) {
+  if (s.bf16()) return hipErrorNotSupported;
   if (s.f32()) return Y_build_t<float>(s, w, st);
   return Y_build_t<double>(s, w, st);
 }

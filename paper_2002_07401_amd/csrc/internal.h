@@ -27,14 +27,42 @@ constexpr int kLamTileN = 64;     // ... and columns (GEMM N tile)
 
 inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
+// BF16 storage (the bit pattern).  Widening is exact; narrowing rounds to
+// nearest even through FP32 (NaN stays a quiet NaN).
+struct bf16s {
+  uint16_t x;
+  bf16s() = default;
+  __host__ __device__ static uint16_t narrow(float f) {
+    uint32_t u;
+    __builtin_memcpy(&u, &f, 4);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+  }
+  __host__ __device__ explicit bf16s(float f) : x(narrow(f)) {}
+  __host__ __device__ explicit bf16s(double d) : x(narrow((float)d)) {}
+  __host__ __device__ explicit operator float() const {
+    const uint32_t u = (uint32_t)x << 16;
+    float f;
+    __builtin_memcpy(&f, &u, 4);
+    return f;
+  }
+  __host__ __device__ explicit operator double() const { return (double)(float)*this; }
+};
+
 // Device-resident description of one system.
 struct SysDev {
   int n_nuc, L, Lp, nu, nd, N;
   int j1_form, j2_form;
   double j2[8];
   int precision, refresh_every;
-  // FP32 storage of Phi and P (the move path) in the two reduced-precision modes
+  // reduced-precision storage of Phi and P (the move path): FP32 in QMC_W_FP32
+  // and QMC_MIXED, BF16 in QMC_MIXED_BF16
   __host__ __device__ bool f32() const { return precision != QMC_FP64; }
+  __host__ __device__ bool bf16() const { return precision == QMC_MIXED_BF16; }
+  __host__ __device__ bool refined() const { return precision == QMC_MIXED || precision == QMC_MIXED_BF16; }
+  // 0: FP64, 1: FP32, 2: BF16 storage
+  __host__ __device__ int store() const { return precision == QMC_FP64 ? 0 : (bf16() ? 2 : 1); }
   double* R;        // [A][3]
   double* Z;        // [A]
   double* j1_b;     // [A]
@@ -130,9 +158,9 @@ struct MultiArgs {
   double sigma;                   // displacement width
 };
 hipError_t launch_multi_prep(const MultiArgs& a, const int2* items, int n_items, int grid, hipStream_t st);
-hipError_t launch_multi_rows(const MultiArgs& a, bool f32, int nc, const int4* items, int n_items, int grid,
+hipError_t launch_multi_rows(const MultiArgs& a, int store, int nc, const int4* items, int n_items, int grid,
                              hipStream_t st);
-hipError_t launch_multi_accept(const MultiArgs& a, bool f32, int qmax, const int2* items, int n_items, int grid,
+hipError_t launch_multi_accept(const MultiArgs& a, int store, int qmax, const int2* items, int n_items, int grid,
                                hipStream_t st);
 hipError_t launch_multi_advance(long long* steps, int n, hipStream_t st);
 hipError_t launch_philox_draws(unsigned long long seed, int member, int Wk, unsigned long long step, double sigma,
@@ -273,7 +301,7 @@ __device__ __forceinline__ float wave_sum(float v) {
 // launchers (all asynchronous on `st`)
 // ---------------------------------------------------------------------------
 hipError_t launch_basis_values(const SysDev& s, const WalkDev& w, hipStream_t st);
-hipError_t launch_downcast(const double* src, float* dst, long n, hipStream_t st);
+hipError_t launch_downcast(const double* src, void* dst, bool to_bf16, long n, hipStream_t st);
 hipError_t launch_P_build(const SysDev& s, const WalkDev& w, int halves, hipStream_t st);
 hipError_t launch_W_build(const SysDev& s, const WalkDev& w, hipStream_t st);
 hipError_t launch_Y_build(const SysDev& s, const WalkDev& w, hipStream_t st);

@@ -93,16 +93,23 @@ hipError_t launch_propose_rows(const SysDev& s, const WalkDev& w, int e, double*
   const bool drift = drift_new != nullptr;
   const int S = propose_splits(s);
   const dim3 grid(S, w.Wk);
-  const bool f32 = s.f32();
+  const int store = s.store();
   hipError_t err;
-  const int chunks = (s.Lp + (f32 ? 255 : 127)) / (f32 ? 256 : 128);
+  const int vn = store == 0 ? 2 : (store == 1 ? 4 : 8);   // elements per 16-byte load
+  const int chunks = (s.Lp + 64 * vn - 1) / (64 * vn);
+#define QMC_GEN(D)                                                                                         \
+  if (store == 2) hipLaunchKernelGGL((propose_rows_generic_kernel<bf16s, D>), grid, dim3(256), 0, st, s, w, e); \
+  else if (store == 1) hipLaunchKernelGGL((propose_rows_generic_kernel<float, D>), grid, dim3(256), 0, st, s, w, e); \
+  else hipLaunchKernelGGL((propose_rows_generic_kernel<double, D>), grid, dim3(256), 0, st, s, w, e);
   if (drift) {
-    if (f32) hipLaunchKernelGGL((propose_rows_generic_kernel<float, true>), grid, dim3(256), 0, st, s, w, e);
-    else hipLaunchKernelGGL((propose_rows_generic_kernel<double, true>), grid, dim3(256), 0, st, s, w, e);
+    QMC_GEN(true)
   } else if (chunks <= 8) {
 #define QMC_ROWS(T, NC) \
     case NC: hipLaunchKernelGGL((propose_rows_kernel<T, NC>), grid, dim3(256), 0, st, s, w, e); break;
-    if (f32) {
+    if (store == 2) {
+      switch (chunks) { QMC_ROWS(bf16s, 1) QMC_ROWS(bf16s, 2) QMC_ROWS(bf16s, 3) QMC_ROWS(bf16s, 4)
+                        QMC_ROWS(bf16s, 5) QMC_ROWS(bf16s, 6) QMC_ROWS(bf16s, 7) QMC_ROWS(bf16s, 8) }
+    } else if (store == 1) {
       switch (chunks) { QMC_ROWS(float, 1) QMC_ROWS(float, 2) QMC_ROWS(float, 3) QMC_ROWS(float, 4)
                         QMC_ROWS(float, 5) QMC_ROWS(float, 6) QMC_ROWS(float, 7) QMC_ROWS(float, 8) }
     } else {
@@ -111,9 +118,9 @@ hipError_t launch_propose_rows(const SysDev& s, const WalkDev& w, int e, double*
     }
 #undef QMC_ROWS
   } else {
-    if (f32) hipLaunchKernelGGL((propose_rows_generic_kernel<float, false>), grid, dim3(256), 0, st, s, w, e);
-    else hipLaunchKernelGGL((propose_rows_generic_kernel<double, false>), grid, dim3(256), 0, st, s, w, e);
+    QMC_GEN(false)
   }
+#undef QMC_GEN
   err = hipGetLastError();
   if (err != hipSuccess || !finalize) return err;
   hipLaunchKernelGGL(propose_finalize_kernel, dim3((w.Wk + 255) / 256), dim3(256), 0, st, w, S, ratio,
@@ -264,9 +271,11 @@ static hipError_t accept_big_t(const SysDev& s, const WalkDev& w, int e, const u
 static hipError_t accept_launch(const SysDev& s, const WalkDev& w, int e, const uint8_t* acc,
                                 const double* unif, int32_t* accept_count, int S, hipStream_t st) {
   if (s.nu > kLuMaxN) {
+    if (s.bf16()) return accept_big_t<bf16s>(s, w, e, acc, unif, accept_count, S, st);
     if (s.f32()) return accept_big_t<float>(s, w, e, acc, unif, accept_count, S, st);
     return accept_big_t<double>(s, w, e, acc, unif, accept_count, S, st);
   }
+  if (s.bf16()) return accept_launch_t<bf16s>(s, w, e, acc, unif, accept_count, S, st);
   if (s.f32()) return accept_launch_t<float>(s, w, e, acc, unif, accept_count, S, st);
   return accept_launch_t<double>(s, w, e, acc, unif, accept_count, S, st);
 }

@@ -96,10 +96,16 @@ __device__ void prep_body(const SysDev& s, const WalkDev& w, int wk, int e, cons
 template <typename T> struct Vec16;
 template <> struct Vec16<double> { typedef double2 type; static constexpr int n = 2; };
 template <> struct Vec16<float> { typedef float4 type; static constexpr int n = 4; };
+template <> struct Vec16<bf16s> { typedef uint4 type; static constexpr int n = 8; };
 
 __device__ __forceinline__ double vget(const double2& v, int i) { return i == 0 ? v.x : v.y; }
 __device__ __forceinline__ double vget(const float4& v, int i) {
   return (double)(i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w)));
+}
+// eight BF16 values: element i is half i % 2 of word i / 2 (exact widening)
+__device__ __forceinline__ double vget(const uint4& v, int i) {
+  const uint32_t w = (i >> 1) == 0 ? v.x : ((i >> 1) == 1 ? v.y : ((i >> 1) == 2 ? v.z : v.w));
+  return (double)__uint_as_float((i & 1) ? (w & 0xffff0000u) : (w << 16));
 }
 
 // Combine the per-wave (lane 0) partial ratios of one block into rdet_part.

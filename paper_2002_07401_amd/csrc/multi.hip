@@ -144,10 +144,13 @@ hipError_t launch_multi_prep(const MultiArgs& a, const int2* items, int n_items,
   return hipGetLastError();
 }
 
-hipError_t launch_multi_rows(const MultiArgs& a, bool f32, int nc, const int4* items, int n_items, int grid,
+hipError_t launch_multi_rows(const MultiArgs& a, int store, int nc, const int4* items, int n_items, int grid,
                              hipStream_t st) {
 #define QMC_MR(T, NC) case NC: return rows_launch<T, NC>(a, items, n_items, grid, st);
-  if (f32) {
+  if (store == 2) {
+    switch (nc) { QMC_MR(bf16s, 1) QMC_MR(bf16s, 2) QMC_MR(bf16s, 3) QMC_MR(bf16s, 4)
+                  QMC_MR(bf16s, 5) QMC_MR(bf16s, 6) QMC_MR(bf16s, 7) QMC_MR(bf16s, 8) }
+  } else if (store == 1) {
     switch (nc) { QMC_MR(float, 1) QMC_MR(float, 2) QMC_MR(float, 3) QMC_MR(float, 4)
                   QMC_MR(float, 5) QMC_MR(float, 6) QMC_MR(float, 7) QMC_MR(float, 8) }
   } else {
@@ -158,17 +161,17 @@ hipError_t launch_multi_rows(const MultiArgs& a, bool f32, int nc, const int4* i
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_multi_accept(const MultiArgs& a, bool f32, int qmax, const int2* items, int n_items, int grid,
+hipError_t launch_multi_accept(const MultiArgs& a, int store, int qmax, const int2* items, int n_items, int grid,
                                hipStream_t st) {
 #define QMC_MA(T, QM) \
   hipLaunchKernelGGL((multi_accept_kernel<T, QM>), dim3(grid), dim3(256), 0, st, a, items, n_items)
-  if (f32) {
-    if (qmax <= 4) QMC_MA(float, 4); else if (qmax <= 8) QMC_MA(float, 8); else if (qmax <= 16) QMC_MA(float, 16);
-    else if (qmax <= 32) QMC_MA(float, 32); else QMC_MA(float, 64);
-  } else {
-    if (qmax <= 4) QMC_MA(double, 4); else if (qmax <= 8) QMC_MA(double, 8); else if (qmax <= 16) QMC_MA(double, 16);
-    else if (qmax <= 32) QMC_MA(double, 32); else QMC_MA(double, 64);
-  }
+#define QMC_MA_ALL(T)                                                                                        \
+  if (qmax <= 4) QMC_MA(T, 4); else if (qmax <= 8) QMC_MA(T, 8); else if (qmax <= 16) QMC_MA(T, 16);      \
+  else if (qmax <= 32) QMC_MA(T, 32); else QMC_MA(T, 64);
+  if (store == 2) { QMC_MA_ALL(bf16s) }
+  else if (store == 1) { QMC_MA_ALL(float) }
+  else { QMC_MA_ALL(double) }
+#undef QMC_MA_ALL
 #undef QMC_MA
   return hipGetLastError();
 }

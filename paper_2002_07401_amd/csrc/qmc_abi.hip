@@ -145,7 +145,7 @@ extern "C" qmc_status qmc_system_create(const qmc_system_desc* desc, qmc_system*
   if (q.n_up <= 0 || q.n_dn < 0) return fail(QMC_ERR_ARG, "bad electron counts");
   if (q.n_up != q.n_dn) return fail(QMC_ERR_UNSUPPORTED, "only n_up == n_dn is built");
   if (q.n_up > kBigMaxN) return fail(QMC_ERR_UNSUPPORTED, "n_up > 1024 is not built");
-  if (q.precision != QMC_FP64 && q.precision != QMC_W_FP32 && q.precision != QMC_MIXED)
+  if (q.precision < QMC_FP64 || q.precision > QMC_MIXED_BF16)
     return fail(QMC_ERR_UNSUPPORTED, "precision not built");
   if (q.refresh_every < 1) return fail(QMC_ERR_ARG, "refresh_every must be >= 1");
   if (q.j1_form < 0 || q.j1_form > 2 || (q.j1_form && !q.j1_b)) return fail(QMC_ERR_ARG, "bad j1");
@@ -253,7 +253,7 @@ extern "C" qmc_status qmc_walkers_create(qmc_system* sys, int32_t n_walkers, qmc
   d.Wk = n_walkers;
   const size_t Wk = n_walkers, N = s.N, Lp = s.Lp;
   const size_t nmax = s.nu > s.nd ? s.nu : s.nd;
-  const size_t esz = s.f32() ? sizeof(float) : sizeof(double);
+  const size_t esz = s.bf16() ? sizeof(uint16_t) : (s.f32() ? sizeof(float) : sizeof(double));
   hipError_t e = hipSuccess;
   auto al = [&](void** p, size_t bytes) {
     if (e != hipSuccess) return;
@@ -290,7 +290,7 @@ extern "C" qmc_status qmc_walkers_create(qmc_system* sys, int32_t n_walkers, qmc
   al((void**)&d.gpsi_new, sizeof(double) * Wk * 3 * Lp);
   al((void**)&d.gJ, sizeof(double) * Wk * N * 4);
   al((void**)&d.drift, sizeof(double) * Wk * N * 3);
-  if (s.precision == QMC_MIXED) {
+  if (s.refined()) {
     al((void**)&d.phi64, sizeof(double) * Wk * N * s.Lp);
     al((void**)&d.P64, sizeof(double) * Wk * N * s.Lp);
   }
@@ -335,7 +335,7 @@ extern "C" qmc_status qmc_eval_batch(qmc_system* sys, qmc_walkers* wk, const dou
   HIP_TRY(hipMemcpyAsync(d.r, r, sizeof(double) * d.Wk * s.N * 3, hipMemcpyDeviceToDevice, stream), "copy r");
   // QMC_MIXED evaluates through the FP64 kernels on the FP64 work arrays, then
   // stores the FP32 basis and P rows the moves stream.
-  const bool refine = s.precision == QMC_MIXED;
+  const bool refine = s.refined();
   SysDev se = s;
   WalkDev de = d;
   if (refine) {
@@ -350,8 +350,8 @@ extern "C" qmc_status qmc_eval_batch(qmc_system* sys, qmc_walkers* wk, const dou
   TIMED(wk, QMC_T_Y_BUILD, stream, launch_Y_build(se, de, stream), "Y build");
   if (refine) {
     const long cnt = (long)d.Wk * s.N * s.Lp;
-    TIMED(wk, QMC_T_OTHER, stream, launch_downcast(d.phi64, (float*)d.phi, cnt, stream), "phi copy");
-    TIMED(wk, QMC_T_OTHER, stream, launch_downcast(d.P64, (float*)d.P, cnt, stream), "P copy");
+    TIMED(wk, QMC_T_OTHER, stream, launch_downcast(d.phi64, d.phi, s.bf16(), cnt, stream), "phi copy");
+    TIMED(wk, QMC_T_OTHER, stream, launch_downcast(d.P64, d.P, s.bf16(), cnt, stream), "P copy");
   }
   TIMED(wk, QMC_T_ROWDOT, stream, launch_rowdots(s, d, stream), "row dots");
   TIMED(wk, QMC_T_ASSEMBLE, stream,
@@ -591,7 +591,7 @@ struct qmc_multi {
   int n_rows_items = 0, rows_cap = 0;
   int grid_rows = 2048, grid_items = 1024;
   int nc = 1, qmax = 4;
-  bool f32 = false;
+  int store = 0;        // 0 FP64, 1 FP32, 2 BF16 rows
   hipStream_t own = nullptr;
   hipEvent_t ev_a = nullptr, ev_b = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -646,14 +646,14 @@ extern "C" qmc_status qmc_multi_create(int32_t n_members, qmc_system* const* sys
     m->h_wk.push_back(walkers[k]->d);
     m->rows.push_back(kPropRows);
   }
-  m->f32 = systems[0]->d.f32();
+  m->store = systems[0]->d.store();
   m->order.resize(n_members);
   std::iota(m->order.begin(), m->order.end(), 0);
   std::stable_sort(m->order.begin(), m->order.end(), [&](int a, int b) {
     const SysDev &x = m->h_sys[a], &y = m->h_sys[b];
     return (long)x.L * x.nu > (long)y.L * y.nu;
   });
-  const int vec = m->f32 ? 256 : 128;
+  const int vec = 64 * (m->store == 0 ? 2 : (m->store == 1 ? 4 : 8));
   std::vector<int2> items;
   for (int k : m->order) {
     const SysDev& s = m->h_sys[k];
@@ -737,8 +737,8 @@ static hipError_t multi_enqueue(qmc_multi* m, int n_steps, bool explicit_draws, 
       if ((att + 1) % s.refresh_every == 0) mask |= 1u << k;
     }
     hipError_t r = launch_multi_prep(a, m->d_items, m->n_items, m->grid_items, m->own);
-    if (r == hipSuccess) r = launch_multi_rows(a, m->f32, m->nc, m->d_rows_items, m->n_rows_items, m->grid_rows, m->own);
-    if (r == hipSuccess) r = launch_multi_accept(a, m->f32, m->qmax, m->d_items, m->n_items, m->grid_items, m->own);
+    if (r == hipSuccess) r = launch_multi_rows(a, m->store, m->nc, m->d_rows_items, m->n_rows_items, m->grid_rows, m->own);
+    if (r == hipSuccess) r = launch_multi_accept(a, m->store, m->qmax, m->d_items, m->n_items, m->grid_items, m->own);
     // refresh: the one-system LU per member, so results match a lone run bitwise
     for (int k = 0; k < m->n && r == hipSuccess; ++k) {
       if (!((mask >> k) & 1u)) continue;
@@ -851,10 +851,10 @@ extern "C" qmc_status qmc_multi_autotune(qmc_multi* m, int32_t* rows_out, int32_
     if (err != hipSuccess) break;
     for (int g : cand_grid) {
       const int grid = std::min(g, m->n_rows_items);
-      err = launch_multi_rows(a, m->f32, m->nc, m->d_rows_items, m->n_rows_items, grid, m->own);
+      err = launch_multi_rows(a, m->store, m->nc, m->d_rows_items, m->n_rows_items, grid, m->own);
       if (err == hipSuccess) err = hipEventRecord(e0, m->own);
       for (int rep = 0; rep < 5 && err == hipSuccess; ++rep)
-        err = launch_multi_rows(a, m->f32, m->nc, m->d_rows_items, m->n_rows_items, grid, m->own);
+        err = launch_multi_rows(a, m->store, m->nc, m->d_rows_items, m->n_rows_items, grid, m->own);
       if (err == hipSuccess) err = hipEventRecord(e1, m->own);
       if (err == hipSuccess) err = hipEventSynchronize(e1);
       float ms = 0.f;

@@ -86,29 +86,31 @@ def test_mixed_eval_within_forward_error_bound(name):
     assert torch.equal(out["sign"].cpu()[idx], ref["sign"])
 
 
+@pytest.mark.parametrize("mode", ["mixed", "mixed_bf16"])
 @pytest.mark.parametrize("name", ["tiny", "mol160"])
-def test_refined_mixed_eval_meets_1e6(name):
+def test_refined_mixed_eval_meets_1e6(name, mode):
     P = need_gpu()
     if name == "tiny":
         w, idx = C.tiny_3nuc_10e(), list(range(64))
     else:
         w, idx = C.mol_40nuc_160e(n_walkers=64), [0, 9, 31, 50, 63]
-    out = _gpu_eval(P, w, P.QMC_MIXED)
+    out = _gpu_eval(P, w, P.QMC_MIXED if mode == "mixed" else P.QMC_MIXED_BF16)
     ref = O.evaluate(O.from_workload_system(w.system), torch.tensor(w.r0[idx]))
     e_la = rel_err(out["logabs"].cpu()[idx], ref["logabs"]).max().item()
     e_el = rel_err(out["e_loc"].cpu()[idx], ref["e_loc"]).max().item()
     e_dr = ((out["drift"].cpu()[idx] - ref["drift"]).abs().max() / ref["drift"].abs().max()).item()
-    print(f"[mixed refined {name}] max rel err logabs {e_la:.3e}, e_loc {e_el:.3e}, drift {e_dr:.3e}")
+    print(f"[{mode} refined {name}] max rel err logabs {e_la:.3e}, e_loc {e_el:.3e}, drift {e_dr:.3e}")
     assert e_la <= 1e-6 and e_el <= 1e-6 and e_dr <= 1e-6
     assert torch.equal(out["sign"].cpu()[idx], ref["sign"])
 
 
-def test_refined_mixed_eval_after_moves():
-    # moves run on the FP32 copies; a later evaluation starts from scratch and
-    # is again FP64-accurate at the new positions
+@pytest.mark.parametrize("mode", ["mixed", "mixed_bf16"])
+def test_refined_mixed_eval_after_moves(mode):
+    # moves run on the reduced-precision copies (P halves rebuilt from them); a
+    # later evaluation starts from scratch and is again FP64-accurate
     P = need_gpu()
     w = C.mol_40nuc_160e(n_walkers=32)
-    sysh = P.JAGPSystem(w.system, precision=P.QMC_MIXED)
+    sysh = P.JAGPSystem(w.system, precision=P.QMC_MIXED if mode == "mixed" else P.QMC_MIXED_BF16)
     wk = P.Walkers(sysh, 32)
     wk.eval_batch(torch.tensor(w.r0, device="cuda"))
     d, u = C.chain_arrays(55, 200, 32)
@@ -124,23 +126,28 @@ def test_refined_mixed_eval_after_moves():
     assert rel_err(out["e_loc"].cpu()[idx], ref["e_loc"]).max().item() <= 1e-6
 
 
-@pytest.mark.parametrize("mode", ["w_fp32", "mixed"])
+@pytest.mark.parametrize("mode", ["w_fp32", "mixed", "mixed_bf16"])
 def test_mixed_moves_ratio_within_bound(mode):
-    # After an FP32 evaluation, the ratio R = w'^T A[:,e] (up) or A[e,:] w' (down)
-    # carries two first-order error terms: the FP32 rows of P in w' = P_other psi',
-    #   |dw'| <= gamma |Phi_other| |Lambda| |psi'|,
-    # and the inverse of the FP32-built W, dA = -A dW A with
+    # QMC_W_FP32: after an FP32 evaluation, the ratio R = w'^T A[:,e] (up) or
+    # A[e,:] w' (down) carries two first-order error terms: the FP32 rows of P in
+    # w' = P_other psi',  |dw'| <= gamma |Phi_other| |Lambda| |psi'|,  and the
+    # inverse of the FP32-built W, dA = -A dW A with
     #   |dW| <= gamma |Phi_up| |Lambda| |Phi_dn|^T,
     # giving |dR| <= |dw'|.|A col| + sum_ik |(w'^T A)_i| |dW_ik| |A_ke| (up; the
     # transpose for down), times exp(dJ).
+    # Refined modes: A is FP64-accurate and the stored rows are the FP64 P
+    # rounded once, |dP| <= u |P| (u = 2^-24 FP32, 2^-8 BF16), so
+    # |dR| <= u (|P_other| |psi'|) . |A col|, times exp(dJ).
     P = need_gpu()
+    prec = {"w_fp32": P.QMC_W_FP32, "mixed": P.QMC_MIXED, "mixed_bf16": P.QMC_MIXED_BF16}[mode]
     w = C.mol_40nuc_160e(n_walkers=16)
-    sysh = P.JAGPSystem(w.system, precision=P.QMC_W_FP32 if mode == "w_fp32" else P.QMC_MIXED)
+    sysh = P.JAGPSystem(w.system, precision=prec)
     wk = P.Walkers(sysh, 16)
     r = torch.tensor(w.r0)
     sy = O.from_workload_system(w.system)
     L = sy.lam.shape[0]
     gam = (2 * L + 4) * 2.0 ** -24
+    u = 2.0 ** -8 if mode == "mixed_bf16" else 2.0 ** -24
     nu = sy.n_up
     disp = torch.tensor(C.chain_arrays(13, 2, 16)[0])
     ref = O.evaluate(sy, r, with_intermediates=True)
@@ -154,20 +161,31 @@ def test_mixed_moves_ratio_within_bound(mode):
         rr = O.move_ratio(sy, r, e, rn)
         psi_n = O.basis(sy, rn)[0]
         if e < nu:
-            wn = torch.einsum('wm,mn,wjn->wj', psi_n, sy.lam, Phi[:, nu:])
-            dw = gam * torch.einsum('wm,mn,wjn->wj', psi_n.abs(), sy.lam.abs(), Phi[:, nu:].abs())
+            P_oth = Phi[:, nu:] @ sy.lam.T            # P_dn rows = Phi_dn Lambda^T
+            wn = torch.einsum('wjm,wm->wj', P_oth, psi_n)
             col = A[:, :, e]
-            u = torch.einsum('wj,wji->wi', wn, A)
-            b = (dw * col.abs()).sum(-1) + gam * torch.einsum('wi,wik,wk->w', u.abs(), absW, col.abs())
+            if mode == "w_fp32":
+                dw = gam * torch.einsum('wm,mn,wjn->wj', psi_n.abs(), sy.lam.abs(), Phi[:, nu:].abs())
+                v = torch.einsum('wj,wji->wi', wn, A)
+                b = (dw * col.abs()).sum(-1) + gam * torch.einsum('wi,wik,wk->w', v.abs(), absW, col.abs())
+            else:
+                dw = u * torch.einsum('wjm,wm->wj', P_oth.abs(), psi_n.abs())
+                b = (dw * col.abs()).sum(-1)
         else:
             ed = e - nu
-            wn = torch.einsum('wim,mn,wn->wi', Phi[:, :nu], sy.lam, psi_n)
-            dw = gam * torch.einsum('wim,mn,wn->wi', Phi[:, :nu].abs(), sy.lam.abs(), psi_n.abs())
+            P_oth = Phi[:, :nu] @ sy.lam               # P_up rows = Phi_up Lambda
+            wn = torch.einsum('wim,wm->wi', P_oth, psi_n)
             row = A[:, ed, :]
-            v = torch.einsum('wli,wi->wl', A, wn)
-            b = (dw * row.abs()).sum(-1) + gam * torch.einsum('wk,wkl,wl->w', row.abs(), absW, v.abs())
+            if mode == "w_fp32":
+                dw = gam * torch.einsum('wim,mn,wn->wi', Phi[:, :nu].abs(), sy.lam.abs(), psi_n.abs())
+                v = torch.einsum('wli,wi->wl', A, wn)
+                b = (dw * row.abs()).sum(-1) + gam * torch.einsum('wk,wkl,wl->w', row.abs(), absW, v.abs())
+            else:
+                dw = u * torch.einsum('wim,wm->wi', P_oth.abs(), psi_n.abs())
+                b = (dw * row.abs()).sum(-1)
         r2 = r.clone(); r2[:, e] = rn
         bound = b * torch.exp(O.jastrow(sy, r2)[0] - ref["J"])
         d = (ratio.cpu() - rr).abs()
-        print(f"[{mode} moves e={e}] max |d ratio| {d.max():.3e}, bound {bound.min():.3e}..{bound.max():.3e}")
-        assert torch.all(d <= bound + 1e-12)
+        print(f"[{mode} moves e={e}] max |d ratio| {d.max():.3e}, max rel {(d / rr.abs()).max():.3e}, "
+              f"bound {bound.min():.3e}..{bound.max():.3e}")
+        assert torch.all(d <= bound * (1 + 1e-6) + 1e-12)
