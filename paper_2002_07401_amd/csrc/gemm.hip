@@ -35,26 +35,95 @@ template <> struct Mfma<float> {
   static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
+// Logical block of a hardware block id.  Workgroups are dealt to the 8 XCDs in
+// turn; regrouping the ids gives each XCD one contiguous range of logical
+// blocks, so blocks that share operand tiles (the N tiles of one A tile, the
+// tiles of one walker's batched product) share that XCD's L2.  A bijection on
+// [0, total) whatever the dispatch order.
+__device__ __forceinline__ long xcd_remap(long id, long total) {
+  const long per = total / 8, rem = total % 8;
+  const long x = id % 8, slot = id / 8;
+  return (x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + slot;
+}
+
 // TA: A stored [K][M] (op(A) = A^T); TB: B stored [N][K] (op(B) = B^T).
 // SA, SB: storage types of A and B (converted exactly to TI on load);
-// TI: MFMA operand type; TO: output type.
-template <int BM, int BN, bool TA, bool TB, typename SA, typename SB, typename TI, typename TO>
-__global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
-  constexpr int BK = 16;
+// TI: MFMA operand type; TO: output type.  K advances in steps of BK; the
+// next step's operands are loaded into registers while the current step's
+// MFMAs run.  Products accumulate in k order (the result does not depend on
+// BK or on skipped all-zero tiles).
+template <int BM, int BN, bool TA, bool TB, typename SA, typename SB, typename TI, typename TO, int BK = 32>
+__global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g, int gx, int gy) {
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int FM = WM / 16, FN = WN / 16;
+  constexpr int EA = BM * BK / 256, EB = BN * BK / 256;
   static_assert(FM >= 1 && FN >= 1, "tile too small");
   __shared__ TI As[BK][BM + 1];
   __shared__ TI Bs[BK][BN + 1];
   typedef typename Mfma<TI>::acc_t acc_t;
 
-  const long bz = blockIdx.z;
+  const long L = xcd_remap(blockIdx.x, (long)gridDim.x);
+  const int bx = (int)(L % gx);
+  const long rest = L / gx;
+  const int by = (int)(rest % gy);
+  const long bz = rest / gy;
   const SA* __restrict__ A = (const SA*)g.A + bz * g.a_bs;
   const SB* __restrict__ B = (const SB*)g.B + bz * g.b_bs;
   TO* __restrict__ C = (TO*)g.C + bz * g.c_bs;
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int m0 = by * BM, n0 = bx * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
+
+  // staging coordinates of this thread's EA + EB elements, fixed over K
+  long aoff[EA], boff[EB];
+  int akk[EA], amm[EA], bkk[EB], bnn[EB];
+  bool aok[EA], bok[EB];
+#pragma unroll
+  for (int q = 0; q < EA; ++q) {
+    const int idx = tid + 256 * q;
+    int mm, kk;
+    if (TA) { kk = idx / BM; mm = idx % BM; } else { mm = idx / BK; kk = idx % BK; }
+    const int gm = m0 + mm;
+    akk[q] = kk; amm[q] = mm; aok[q] = gm < g.M;
+    aoff[q] = TA ? (long)kk * g.lda + gm
+                 : (long)(gm / g.a_grp) * g.a_gs + (long)(gm % g.a_grp) * g.lda + kk;
+  }
+#pragma unroll
+  for (int q = 0; q < EB; ++q) {
+    const int idx = tid + 256 * q;
+    int nn, kk;
+    if (TB) { nn = idx / BK; kk = idx % BK; } else { kk = idx / BN; nn = idx % BN; }
+    const int gn = n0 + nn;
+    bkk[q] = kk; bnn[q] = nn; bok[q] = gn < g.N;
+    boff[q] = TB ? (long)gn * g.ldb + kk : (long)kk * g.ldb + gn;
+  }
+  TI ra[EA], rb[EB];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < EA; ++q)
+      ra[q] = (aok[q] && k0 + akk[q] < g.K) ? (TI)A[aoff[q] + (TA ? (long)k0 * g.lda : (long)k0)] : (TI)0;
+#pragma unroll
+    for (int q = 0; q < EB; ++q)
+      rb[q] = (bok[q] && k0 + bkk[q] < g.K) ? (TI)B[boff[q] + (TB ? (long)k0 : (long)k0 * g.ldb)] : (TI)0;
+  };
+  // first K step at or after k whose B tile is not entirely zero (uniform per block)
+  auto next_k = [&](int k) -> int {
+    if constexpr (kLamTileN % BN == 0 && BK % kLamTileK == 0 && !TB) {
+      if (g.kmask) {
+        const int nt = n0 / kLamTileN;
+        while (k < g.K) {
+          const int t = k / kLamTileK;
+          bool nz = false;
+#pragma unroll
+          for (int h = 0; h < BK / kLamTileK; ++h)
+            nz |= (k + h * kLamTileK < g.K) && g.kmask[(long)(t + h) * g.kmask_ld + nt];
+          if (nz) break;
+          k += BK;
+        }
+      }
+    }
+    return k;
+  };
 
   acc_t acc[FM][FN];
 #pragma unroll
@@ -63,31 +132,16 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
     for (int j = 0; j < FN; ++j)
       for (int r = 0; r < 4; ++r) acc[i][j][r] = 0;
 
-  for (int k0 = 0; k0 < g.K; k0 += BK) {
-    if constexpr (BN == kLamTileN && BK == kLamTileK && !TB) {
-      if (g.kmask && !g.kmask[(long)(k0 / BK) * g.kmask_ld + n0 / BN]) continue;   // uniform per block
-    }
-    for (int idx = tid; idx < BM * BK; idx += 256) {
-      int mm, kk;
-      if (TA) { kk = idx / BM; mm = idx % BM; } else { mm = idx / BK; kk = idx % BK; }
-      const int gm = m0 + mm, gk = k0 + kk;
-      TI v = 0;
-      if (gm < g.M && gk < g.K) {
-        const long off = TA ? (long)gk * g.lda + gm
-                            : (long)(gm / g.a_grp) * g.a_gs + (long)(gm % g.a_grp) * g.lda + gk;
-        v = (TI)A[off];
-      }
-      As[kk][mm] = v;
-    }
-    for (int idx = tid; idx < BN * BK; idx += 256) {
-      int nn, kk;
-      if (TB) { nn = idx / BK; kk = idx % BK; } else { kk = idx / BN; nn = idx % BN; }
-      const int gn = n0 + nn, gk = k0 + kk;
-      TI v = 0;
-      if (gn < g.N && gk < g.K) v = (TI)(TB ? B[(long)gn * g.ldb + gk] : B[(long)gk * g.ldb + gn]);
-      Bs[kk][nn] = v;
-    }
+  int k0 = next_k(0);
+  if (k0 < g.K) load(k0);
+  while (k0 < g.K) {
+#pragma unroll
+    for (int q = 0; q < EA; ++q) As[akk[q]][amm[q]] = ra[q];
+#pragma unroll
+    for (int q = 0; q < EB; ++q) Bs[bkk[q]][bnn[q]] = rb[q];
     __syncthreads();
+    const int k1 = next_k(k0 + BK);
+    if (k1 < g.K) load(k1);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       TI a[FM], b[FN];
@@ -101,6 +155,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
         for (int j = 0; j < FN; ++j) acc[i][j] = Mfma<TI>::run(a[i], b[j], acc[i][j]);
     }
     __syncthreads();
+    k0 = k1;
   }
   // 16x16 block layout: lane holds column lane%16 and the rows given by Mfma::row
 #pragma unroll
@@ -119,11 +174,14 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
       }
 }
 
-template <int BM, int BN, bool TA, bool TB, typename SA, typename SB, typename TI, typename TO>
+template <int BM, int BN, bool TA, bool TB, typename SA, typename SB, typename TI, typename TO, int BK = 32>
 static hipError_t run_gemm(const GemmArgs& g, hipStream_t st) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
-  dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, g.batch);
-  hipLaunchKernelGGL((gemm_kernel<BM, BN, TA, TB, SA, SB, TI, TO>), grid, dim3(256), 0, st, g);
+  const int gx = (g.N + BN - 1) / BN, gy = (g.M + BM - 1) / BM;
+  const long total = (long)gx * gy * g.batch;
+  if (total > 0x7fffffffL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((gemm_kernel<BM, BN, TA, TB, SA, SB, TI, TO, BK>), dim3((unsigned)total), dim3(256), 0, st, g,
+                     gx, gy);
   return hipGetLastError();
 }
 
@@ -149,6 +207,15 @@ hipError_t gemm_f64(const GemmArgs& g, bool ta, bool tb, bool big, hipStream_t s
 #undef QMC_G
 }
 
+// Tile shapes from a sweep on MI355X (1024 walkers x 80 rows, L = 608): FP64
+// 64 x 32 with K steps of 16 (65 % of the FP64 matrix peak); FP32 / BF16 rows
+// 64 x 64 with K steps of 32.
+template <typename T, typename TL>
+static hipError_t P_gemm(const GemmArgs& g, hipStream_t st) {
+  if constexpr (sizeof(TL) == 8) return run_gemm<64, 32, false, false, T, TL, TL, T, 16>(g, st);
+  else return run_gemm<64, 64, false, false, T, TL, TL, T, 32>(g, st);
+}
+
 // T: storage of Phi and P; TL: storage of Lambda and the MFMA operand type
 // (BF16 rows multiply the FP32 Lambda with FP32 accumulation).
 template <typename T, typename TL = T>
@@ -165,7 +232,7 @@ static hipError_t P_build_t(const SysDev& s, const WalkDev& w, int halves, hipSt
     g.B = lam; g.ldb = s.Lp;
     g.kmask = s.lam_mask; g.kmask_ld = mask_ld;
     g.C = P; g.ldc = s.Lp; g.c_grp = s.nu; g.c_gs = rowst;
-    e = run_gemm<64, 64, false, false, T, TL, TL, T>(g, st);
+    e = P_gemm<T, TL>(g, st);
     if (e != hipSuccess) return e;
   }
   if (halves & 2) {   // P_dn = Phi_dn Lambda^T (rows nu..N-1)
@@ -174,7 +241,7 @@ static hipError_t P_build_t(const SysDev& s, const WalkDev& w, int halves, hipSt
     g.B = lamT; g.ldb = s.Lp;
     g.kmask = s.lamT_mask; g.kmask_ld = mask_ld;
     g.C = P + (long)s.nu * s.Lp; g.ldc = s.Lp; g.c_grp = s.nd; g.c_gs = rowst;
-    e = run_gemm<64, 64, false, false, T, TL, TL, T>(g, st);
+    e = P_gemm<T, TL>(g, st);
   }
   return e;
 }
@@ -221,7 +288,7 @@ static hipError_t Y_build_t(const SysDev& s, const WalkDev& w, hipStream_t st) {
     g.B = (const T*)w.P + (long)s.nu * s.Lp; g.ldb = s.Lp; g.b_bs = rowst;
     g.C = w.Yt; g.ldc = s.Lp; g.c_bs = rowst;
     g.batch = w.Wk;
-    e = run_gemm<32, 64, true, false, double, T, double, double>(g, st);
+    e = run_gemm<32, 64, true, false, double, T, double, double, 16>(g, st);
     if (e != hipSuccess) return e;
   }
   {
@@ -230,7 +297,7 @@ static hipError_t Y_build_t(const SysDev& s, const WalkDev& w, hipStream_t st) {
     g.B = (const T*)w.P; g.ldb = s.Lp; g.b_bs = rowst;
     g.C = w.Yt + (long)s.nu * s.Lp; g.ldc = s.Lp; g.c_bs = rowst;
     g.batch = w.Wk;
-    e = run_gemm<32, 64, false, false, double, T, double, double>(g, st);
+    e = run_gemm<32, 64, false, false, double, T, double, double, 16>(g, st);
   }
   return e;
 }
