@@ -264,11 +264,15 @@ __device__ __forceinline__ void j2_radial(int form, const double* p, bool same, 
                                           double& v, double& v1, double& v2) {
   const double c = same ? 0.25 : 0.5;
   double b, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  // constant indices only: p may point into a kernel argument, which a
+  // run-time index would copy to scratch memory
   if (form == 1) {
     b = same ? p[0] : p[1];
   } else {
-    const int o = same ? 0 : 4;
-    b = p[o]; a1 = p[o + 1]; a2 = p[o + 2]; a3 = p[o + 3];
+    b = same ? p[0] : p[4];
+    a1 = same ? p[1] : p[5];
+    a2 = same ? p[2] : p[6];
+    a3 = same ? p[3] : p[7];
   }
   const double den = 1.0 / (1.0 + b * r);
   const double t = r * den;

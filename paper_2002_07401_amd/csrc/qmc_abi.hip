@@ -591,6 +591,10 @@ struct qmc_multi {
   int n_rows_items = 0, rows_cap = 0;
   int grid_rows = 2048, grid_items = 1024;
   int nc = 1, qmax = 4;
+  // accept phase: one persistent launch per register class (slice length) so
+  // that small members do not run with the largest member's register budget
+  struct AccClass { int qm; int2* items; int n; int grid; };
+  std::vector<AccClass> acc;
   int store = 0;        // 0 FP64, 1 FP32, 2 BF16 rows
   hipStream_t own = nullptr;
   hipEvent_t ev_a = nullptr, ev_b = nullptr;
@@ -655,12 +659,17 @@ extern "C" qmc_status qmc_multi_create(int32_t n_members, qmc_system* const* sys
   });
   const int vec = 64 * (m->store == 0 ? 2 : (m->store == 1 ? 4 : 8));
   std::vector<int2> items;
+  std::vector<std::vector<int2>> cls(5);   // slice classes 4, 8, 16, 32, 64
   for (int k : m->order) {
     const SysDev& s = m->h_sys[k];
     m->nc = std::max(m->nc, (s.Lp + vec - 1) / vec);
     const int G = 256 / s.nu, Q = (s.nu + G - 1) / G;
     m->qmax = std::max(m->qmax, Q);
-    for (int w = 0; w < m->h_wk[k].Wk; ++w) items.push_back(make_int2(k, w));
+    const int c = Q <= 4 ? 0 : (Q <= 8 ? 1 : (Q <= 16 ? 2 : (Q <= 32 ? 3 : 4)));
+    for (int w = 0; w < m->h_wk[k].Wk; ++w) {
+      items.push_back(make_int2(k, w));
+      cls[c].push_back(make_int2(k, w));
+    }
   }
   if (m->nc > 8) { delete m; return fail(QMC_ERR_UNSUPPORTED, "members need L <= 1024 (FP64) or 2048 (FP32)"); }
   m->n_items = (int)items.size();
@@ -679,6 +688,13 @@ extern "C" qmc_status qmc_multi_create(int32_t n_members, qmc_system* const* sys
   al((void**)&m->d_unif, sizeof(double*) * n_members);
   al((void**)&m->d_items, sizeof(int2) * items.size());
   if (!e) e = hipMemcpy(m->d_items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice);
+  for (int c = 0; c < 5 && !e; ++c) {
+    if (cls[c].empty()) continue;
+    qmc_multi::AccClass ac{4 << c, nullptr, (int)cls[c].size(), std::min((int)cls[c].size(), 2048)};
+    al((void**)&ac.items, sizeof(int2) * cls[c].size());
+    if (!e) e = hipMemcpy(ac.items, cls[c].data(), sizeof(int2) * cls[c].size(), hipMemcpyHostToDevice);
+    m->acc.push_back(ac);
+  }
   if (!e) e = hipMemcpy(m->d_wk, m->h_wk.data(), sizeof(WalkDev) * n_members, hipMemcpyHostToDevice);
   if (!e) e = multi_build_rows(m);
   if (!e) e = hipStreamCreateWithFlags(&m->own, hipStreamNonBlocking);
@@ -738,7 +754,8 @@ static hipError_t multi_enqueue(qmc_multi* m, int n_steps, bool explicit_draws, 
     }
     hipError_t r = launch_multi_prep(a, m->d_items, m->n_items, m->grid_items, m->own);
     if (r == hipSuccess) r = launch_multi_rows(a, m->store, m->nc, m->d_rows_items, m->n_rows_items, m->grid_rows, m->own);
-    if (r == hipSuccess) r = launch_multi_accept(a, m->store, m->qmax, m->d_items, m->n_items, m->grid_items, m->own);
+    for (const auto& ac : m->acc)
+      if (r == hipSuccess) r = launch_multi_accept(a, m->store, ac.qm, ac.items, ac.n, ac.grid, m->own);
     // refresh: the one-system LU per member, so results match a lone run bitwise
     for (int k = 0; k < m->n && r == hipSuccess; ++k) {
       if (!((mask >> k) & 1u)) continue;
