@@ -15,12 +15,12 @@ namespace qmc {
 // sizes
 // ---------------------------------------------------------------------------
 constexpr int kMaxNuc = 4096;
-constexpr int kLuMaxN = 128;      // LDS-resident Gauss-Jordan inverse limit
+constexpr int kLuMaxN = 128;      // one-workgroup (register / LDS) Sherman-Morrison limit
 constexpr int kLuRowMax = 96;     // register (row-per-thread) Gauss-Jordan limit
 constexpr int kPropRows = 16;     // rows of P per proposal workgroup
 constexpr int kPropRowsMin = 8;   // smallest rows-per-workgroup the autotuner may pick
 constexpr int kMaxNucBack = 256;  // nuclei handled by the Jastrow backward kernel
-constexpr int kBigMaxN = 1024;    // blocked (global-memory) Gauss-Jordan limit for n > kLuMaxN
+constexpr int kBigMaxN = 1024;    // blocked Gauss-Jordan / two-pass update limit
 constexpr int kGjPanel = 64;      // panel width of the blocked Gauss-Jordan
 constexpr int kLamTileK = 16;     // Lambda tile mask granularity: rows (GEMM K step) ...
 constexpr int kLamTileN = 64;     // ... and columns (GEMM N tile)
@@ -80,7 +80,7 @@ struct SysDev {
   // ([Lp/16][Lp/64]); the P products skip zero tiles (banded Lambda)
   uint8_t* lam_mask;
   uint8_t* lamT_mask;
-  int np;           // n rounded up to kGjPanel (blocked Gauss-Jordan, n > kLuMaxN)
+  int np;           // n rounded up to 64 (blocked Gauss-Jordan, n > kLuRowMax)
 };
 
 // Device state of a batch of walkers.
@@ -115,7 +115,8 @@ struct WalkDev {
   double* drift;      // [Wk][N][3] grad_i log|Psi| of the last evaluation
   double* phi64;      // [Wk][N][Lp] FP64 evaluation work arrays (QMC_MIXED only)
   double* P64;        // [Wk][N][Lp]
-  // n > kLuMaxN only: blocked Gauss-Jordan and two-pass Sherman-Morrison work
+  // blocked Gauss-Jordan (n > kLuRowMax) and two-pass Sherman-Morrison
+  // (n > kLuMaxN) work arrays
   double* T;          // [Wk][np][np] identity-padded working copy of W
   double* Tsave;      // [Wk][kGjPanel][np] pivot rows of the current panel, before it
   int* rowk;          // [Wk][np] step at which row i was pivoted (-1: not yet)
@@ -309,7 +310,6 @@ hipError_t launch_downcast(const double* src, void* dst, bool to_bf16, long n, h
 hipError_t launch_P_build(const SysDev& s, const WalkDev& w, int halves, hipStream_t st);
 hipError_t launch_W_build(const SysDev& s, const WalkDev& w, hipStream_t st);
 hipError_t launch_Y_build(const SysDev& s, const WalkDev& w, hipStream_t st);
-hipError_t prepare_lu(int n);
 hipError_t launch_lu_inverse(const SysDev& s, const WalkDev& w, hipStream_t st);
 hipError_t launch_lam_mask(const SysDev& s, hipStream_t st);
 hipError_t launch_rowdots(const SysDev& s, const WalkDev& w, hipStream_t st);

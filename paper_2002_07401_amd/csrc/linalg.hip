@@ -6,115 +6,16 @@
 // behaves like 1/Pf, finite-variance reweighting subsection), which is why this
 // step stays in FP64 in every precision mode.
 //
-// Method: in-place Gauss-Jordan elimination with partial (row) pivoting, one
-// workgroup per walker: rows in registers for n <= kLuRowMax, else the whole
-// matrix resident in LDS (n <= kLuMaxN).  The pivot is the largest |entry| of
-// the column.
+// Method: in-place Gauss-Jordan elimination with partial (row) pivoting: one
+// workgroup per walker with the rows in registers for n <= kLuRowMax, else the
+// blocked elimination below (panels in registers, updates in global memory).
+// The pivot is the largest |entry| of the column.
 //   log|det| = sum_k log|pivot_k|,  sign = prod_k sign(pivot_k) * (-1)^{#swaps}
 // After elimination the row interchanges are undone as column interchanges in
 // reverse order, leaving W^{-1}.  A zero pivot marks the walker singular.
 #include "internal.h"
 
 namespace qmc {
-
-// One matrix per workgroup: W (n x n) -> A = W^{-1}, log|det W| and sign in
-// *logdet, *detsign (singular: *singular = 1).  smem holds n (n+1) + 2n doubles.
-__device__ void gj_lds_body(const double* __restrict__ W, double* __restrict__ A, double* __restrict__ logdet,
-                            double* __restrict__ detsign, int* __restrict__ singular, int n, double* smem) {
-  const int ld = n + 1;
-  double* M = smem;                 // n x ld
-  double* rk = M + (long)n * ld;    // scaled pivot row
-  double* ck = rk + n;              // pivot column before the step
-  __shared__ int perm[kLuMaxN];
-  __shared__ int piv_s;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-
-  for (int idx = tid; idx < n * n; idx += blockDim.x) M[(idx / n) * ld + (idx % n)] = W[idx];
-
-  // fixed thread -> (column jc, row group g) map for the elimination update
-  const int G = blockDim.x / n, jc = tid % n, g = tid / n;
-  double lsum = 0.0, sg = 1.0;
-  int sing = 0;
-  for (int k = 0; k < n; ++k) {
-    __syncthreads();
-    if (wave == 0) {
-      double best = -1.0;
-      int bi = n;
-      for (int i = k + lane; i < n; i += 64) {
-        const double v = fabs(M[i * ld + k]);
-        if (v > best) { best = v; bi = i; }
-      }
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        const double ob = __shfl_xor(best, o, 64);
-        const int oi = __shfl_xor(bi, o, 64);
-        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-      }
-      if (lane == 0) { piv_s = bi; perm[k] = bi; }
-    }
-    __syncthreads();
-    const int p = piv_s;
-    if (p != k) {
-      for (int j = tid; j < n; j += blockDim.x) {
-        const double t = M[k * ld + j];
-        M[k * ld + j] = M[p * ld + j];
-        M[p * ld + j] = t;
-      }
-      sg = -sg;
-    }
-    __syncthreads();
-    const double piv = M[k * ld + k];
-    if (!(piv != 0.0)) { sing = 1; break; }   // uniform across the block
-    lsum += log(fabs(piv));
-    if (piv < 0.0) sg = -sg;
-    const double inv = 1.0 / piv;
-    for (int j = tid; j < n; j += blockDim.x) {
-      rk[j] = (j == k) ? inv : M[k * ld + j] * inv;
-      ck[j] = M[j * ld + k];
-    }
-    __syncthreads();
-    if (g < G) {
-      const double rj = rk[jc];
-      for (int i = g; i < n; i += G) {
-        double v;
-        if (i == k) v = rj;
-        else if (jc == k) v = -ck[i] * rk[k];
-        else v = M[i * ld + jc] - ck[i] * rj;
-        M[i * ld + jc] = v;
-      }
-    }
-  }
-  __syncthreads();
-  if (!sing) {
-    for (int k = n - 1; k >= 0; --k) {
-      const int p = perm[k];
-      if (p != k) {
-        for (int i = tid; i < n; i += blockDim.x) {
-          const double t = M[i * ld + k];
-          M[i * ld + k] = M[i * ld + p];
-          M[i * ld + p] = t;
-        }
-      }
-      __syncthreads();
-    }
-  }
-  const double nanv = __longlong_as_double(0x7ff8000000000000LL);
-  for (int idx = tid; idx < n * n; idx += blockDim.x)
-    A[idx] = sing ? nanv : M[(idx / n) * ld + (idx % n)];
-  if (tid == 0) {
-    *logdet = sing ? -__builtin_inf() : lsum;
-    *detsign = sing ? 0.0 : sg;
-    *singular = sing;
-  }
-}
-
-__global__ void __launch_bounds__(256)
-gj_inverse_kernel(const double* __restrict__ Wg, double* __restrict__ Ag, double* __restrict__ logdet,
-                  double* __restrict__ detsign, int* __restrict__ singular, int n, long w_bs, long a_bs) {
-  extern __shared__ double smem[];
-  const long b = blockIdx.x;
-  gj_lds_body(Wg + b * w_bs, Ag + b * a_bs, logdet + b, detsign + b, singular + b, n, smem);
-}
 
 // Row-per-thread variant (the default for n <= kLuRowMax).  The matrix is
 // padded to NMAX = round_up(n, 8) with an identity block, which leaves the real
@@ -265,13 +166,11 @@ gj_inverse_row_kernel(const double* __restrict__ Wg, double* __restrict__ Ag, do
   gj_row_body<NMAX>(Wg + b * w_bs, Ag + b * a_bs, logdet + b, detsign + b, singular + b, n, sm);
 }
 
-hipError_t launch_lu_inverse_lds(const SysDev& s, const WalkDev& w, hipStream_t st);
 static hipError_t launch_lu_inverse_big(const SysDev& s, const WalkDev& w, hipStream_t st);
 
 hipError_t launch_lu_inverse(const SysDev& s, const WalkDev& w, hipStream_t st) {
   const int n = s.nu;
-  if (n > kLuMaxN) return launch_lu_inverse_big(s, w, st);
-  if (n > kLuRowMax) return launch_lu_inverse_lds(s, w, st);
+  if (n > kLuRowMax) return launch_lu_inverse_big(s, w, st);
   const long wbs = (long)s.nu * s.nd, abs_ = (long)s.nd * s.nu;
   const dim3 blk(n > 64 ? 128 : 64);
   switch ((n + 7) >> 3) {
@@ -289,7 +188,7 @@ hipError_t launch_lu_inverse(const SysDev& s, const WalkDev& w, hipStream_t st) 
 }
 
 // ---------------------------------------------------------------------------
-// Blocked Gauss-Jordan for kLuMaxN < n <= kBigMaxN (matrix in global memory).
+// Blocked Gauss-Jordan for kLuRowMax < n <= kBigMaxN (matrix in global memory).
 //
 // T = [[W, 0], [0, I]] (np = n rounded up to 64; the identity block leaves the
 // real block's elimination unchanged, as in the register kernel).  Panels of NB
@@ -534,25 +433,6 @@ static hipError_t launch_lu_inverse_big(const SysDev& s, const WalkDev& w, hipSt
                      w.singular, w.A, n, np);
   hipLaunchKernelGGL(gj_big_det_kernel, dim3(w.Wk), dim3(1024), 0, st, w.rowk, w.pivv, w.singular, w.logdet,
                      w.detsign, n, np);
-  return hipGetLastError();
-}
-
-static size_t lu_lds_bytes(int n) { return ((size_t)n * (n + 1) + 2 * (size_t)n) * sizeof(double); }
-
-// Raises the LDS limit of the LDS variant for an n x n problem; called once at
-// system creation so that no launch (possibly under graph capture) needs it.
-hipError_t prepare_lu(int n) {
-  if (n <= kLuRowMax || n > kLuMaxN || lu_lds_bytes(n) <= 64 * 1024) return hipSuccess;
-  return hipFuncSetAttribute((const void*)gj_inverse_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)lu_lds_bytes(n));
-}
-
-// LDS variant with physical row swaps, for kLuRowMax < n <= kLuMaxN.
-hipError_t launch_lu_inverse_lds(const SysDev& s, const WalkDev& w, hipStream_t st) {
-  const int n = s.nu;
-  if (n > kLuMaxN) return hipErrorNotSupported;
-  hipLaunchKernelGGL(gj_inverse_kernel, dim3(w.Wk), dim3(256), lu_lds_bytes(n), st, w.W, w.A, w.logdet,
-                     w.detsign, w.singular, n, (long)s.nu * s.nd, (long)s.nd * s.nu);
   return hipGetLastError();
 }
 

@@ -218,7 +218,6 @@ extern "C" qmc_status qmc_system_create(const qmc_system_desc* desc, qmc_system*
     e = up((void**)&d.lam32, l32.data(), sizeof(float) * l32.size());
     if (!e) e = up((void**)&d.lamT32, lT32.data(), sizeof(float) * lT32.size());
   }
-  if (!e) e = prepare_lu(d.nu);
   if (!e) {
     const size_t mb = (size_t)((Lp + kLamTileK - 1) / kLamTileK) * ((Lp + kLamTileN - 1) / kLamTileN);
     std::vector<uint8_t> ones(mb, 1);
@@ -294,15 +293,15 @@ extern "C" qmc_status qmc_walkers_create(qmc_system* sys, int32_t n_walkers, qmc
     al((void**)&d.phi64, sizeof(double) * Wk * N * s.Lp);
     al((void**)&d.P64, sizeof(double) * Wk * N * s.Lp);
   }
-  if (s.nu > kLuMaxN) {
+  if (s.nu > kLuRowMax) {
     const size_t np = s.np;
     al((void**)&d.T, sizeof(double) * Wk * np * np);
     al((void**)&d.Tsave, sizeof(double) * Wk * kGjPanel * np);
     al((void**)&d.rowk, sizeof(int) * Wk * np);
     al((void**)&d.prow, sizeof(int) * Wk * np);
     al((void**)&d.pivv, sizeof(double) * Wk * np);
-    al((void**)&d.smv, sizeof(double) * Wk * 2 * s.nu);
   }
+  if (s.nu > kLuMaxN) al((void**)&d.smv, sizeof(double) * Wk * 2 * s.nu);
   if (e != hipSuccess) {
     delete wk;
     return e == hipErrorOutOfMemory ? fail(QMC_ERR_OOM, "device allocation failed") : hip_fail(e, "walkers_create");

@@ -1,5 +1,5 @@
-"""Systems beyond the register and LDS inverses (n > 128): the blocked
-Gauss-Jordan refresh, the two-pass Sherman-Morrison update and, for the
+"""Systems beyond the register inverse (n > 96): the blocked Gauss-Jordan
+refresh, for n > 128 the two-pass Sherman-Morrison update and, for the
 1024-electron workload (256 nuclei, L = 4096, Lambda banded at 8 bohr), the P
 products that skip Lambda's zero tiles.
 
@@ -9,8 +9,8 @@ products that skip Lambda's zero tiles.
   determinants, and the updated inverse against the inverse of the updated W.
 * 70 Metropolis steps (one refresh at 64): the tracked log|Psi| and inverse
   equal those of a fresh evaluation at the final positions.
-* n = 150 (not a multiple of the 64-wide panel): identity padding of the blocked
-  elimination.
+* n = 112, 128, 150 (the blocked elimination runs for n > 96; 112 and 150 are
+  not multiples of the 64-wide panel): identity padding.
 * W = 0 is reported singular (status 1).
 """
 import dataclasses
@@ -59,9 +59,11 @@ def test_large_eval_matches_oracle(large):
     _check_eval(out, large, [0, 3])
 
 
-def test_n150_eval_and_refresh():
+@pytest.mark.parametrize("n_elec", [224, 256, 300])
+def test_blocked_eval_and_refresh(n_elec):
+    # n = 112, 128, 150: one or two padded 64-column panels
     P = need_gpu()
-    w = C.multi_system(300, n_walkers=8)
+    w = C.multi_system(n_elec, n_walkers=8)
     sysh, wk, out = _eval(P, w)
     _check_eval(out, w, [0, 7])
     d, u = C.chain_arrays(17, 40, 8)          # refresh every 32
