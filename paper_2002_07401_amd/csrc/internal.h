@@ -17,7 +17,6 @@ namespace qmc {
 constexpr int kMaxNuc = 4096;
 constexpr int kLuMaxN = 128;      // one-workgroup (register / LDS) Sherman-Morrison limit
 constexpr int kLuRowMax = 96;     // register (row-per-thread) Gauss-Jordan limit
-constexpr int kPropRows = 16;     // rows of P per proposal workgroup
 constexpr int kPropRowsMin = 8;   // smallest rows-per-workgroup the autotuner may pick
 constexpr int kMaxNucBack = 256;  // nuclei handled by the Jastrow backward kernel
 constexpr int kBigMaxN = 1024;    // blocked Gauss-Jordan / two-pass update limit
@@ -63,6 +62,9 @@ struct SysDev {
   __host__ __device__ bool refined() const { return precision == QMC_MIXED || precision == QMC_MIXED_BF16; }
   // 0: FP64, 1: FP32, 2: BF16 storage
   __host__ __device__ int store() const { return precision == QMC_FP64 ? 0 : (bf16() ? 2 : 1); }
+  // P rows per proposal workgroup (swept on MI355X: 8 for FP64 rows, 16 for
+  // the narrower FP32 / BF16 rows)
+  __host__ __device__ int prop_rows() const { return store() == 0 ? 8 : 16; }
   double* R;        // [A][3]
   double* Z;        // [A]
   double* j1_b;     // [A]

@@ -15,7 +15,7 @@
 // The proposal streams the N/2 x L block of P of the other spin for every
 // walker: it is bound by HBM bandwidth.  A small per-walker kernel first
 // computes psi(r') and the Jastrow change; the streaming kernel then splits
-// each walker's rows over several workgroups (kPropRows rows each) so that
+// each walker's rows over several workgroups (s.prop_rows() rows each) so that
 // many blocks are in flight, and every block writes a partial determinant
 // ratio, which the accept kernel (device Metropolis) or the finalize kernel
 // (host-driven moves) sums in a fixed order.
@@ -33,15 +33,15 @@ propose_prep_kernel(SysDev s, WalkDev w, int e, const double* __restrict__ r_new
                    disp ? disp + 3 * (long)wk : nullptr);
 }
 
-// grid (S, Wk): block (sb, wk) handles rows [sb*kPropRows, (sb+1)*kPropRows) of walker wk.
+// grid (S, Wk): block (sb, wk) handles rows [sb*R, (sb+1)*R) of walker wk, R = s.prop_rows().
 template <typename T, int NC>
 __global__ void __launch_bounds__(256) propose_rows_kernel(SysDev s, WalkDev w, int e) {
-  rows_body<T, NC>(s, w, blockIdx.y, blockIdx.x, gridDim.x, e, kPropRows);
+  rows_body<T, NC>(s, w, blockIdx.y, blockIdx.x, gridDim.x, e, s.prop_rows());
 }
 
 template <typename T, bool DRIFT>
 __global__ void __launch_bounds__(256) propose_rows_generic_kernel(SysDev s, WalkDev w, int e) {
-  rows_generic_body<T, DRIFT>(s, w, blockIdx.y, blockIdx.x, gridDim.x, e, kPropRows);
+  rows_generic_body<T, DRIFT>(s, w, blockIdx.y, blockIdx.x, gridDim.x, e, s.prop_rows());
 }
 
 template <typename T, int QMAX, bool UP>
@@ -76,7 +76,8 @@ __global__ void propose_finalize_kernel(WalkDev w, int S, double* __restrict__ r
 
 int propose_splits(const SysDev& s) {
   const int nmax = s.nu > s.nd ? s.nu : s.nd;
-  return (nmax + kPropRows - 1) / kPropRows;
+  const int R = s.prop_rows();
+  return (nmax + R - 1) / R;
 }
 
 hipError_t launch_propose_prep(const SysDev& s, const WalkDev& w, int e, const double* r_new,

@@ -647,7 +647,7 @@ extern "C" qmc_status qmc_multi_create(int32_t n_members, qmc_system* const* sys
     m->wk.push_back(walkers[k]);
     m->h_sys.push_back(s);
     m->h_wk.push_back(walkers[k]->d);
-    m->rows.push_back(kPropRows);
+    m->rows.push_back(s.prop_rows());
   }
   m->store = systems[0]->d.store();
   m->order.resize(n_members);
@@ -857,7 +857,7 @@ extern "C" qmc_status qmc_multi_autotune(qmc_multi* m, int32_t* rows_out, int32_
   const int cand_rows[3] = {8, 16, 32};
   const int cand_grid[4] = {512, 1024, 2048, 4096};
   float best = 1e30f;
-  int best_r = m->rows.empty() ? kPropRows : m->rows[0], best_g = m->grid_rows;
+  int best_r = m->rows.empty() ? 16 : m->rows[0], best_g = m->grid_rows;
   hipError_t err = hipSuccess;
   for (int r : cand_rows) {
     for (int k = 0; k < m->n; ++k) m->rows[k] = r;
