@@ -163,8 +163,8 @@ struct MultiArgs {
 hipError_t launch_multi_prep(const MultiArgs& a, const int2* items, int n_items, int grid, hipStream_t st);
 hipError_t launch_multi_rows(const MultiArgs& a, int store, int nc, const int4* items, int n_items, int grid,
                              hipStream_t st);
-hipError_t launch_multi_accept(const MultiArgs& a, int store, int qmax, const int2* items, int n_items, int grid,
-                               hipStream_t st);
+hipError_t launch_multi_accept(const MultiArgs& a, int store, int qmax, bool up, unsigned mask, const int2* items,
+                               int n_items, int grid, hipStream_t st);
 hipError_t launch_multi_advance(long long* steps, int n, hipStream_t st);
 hipError_t launch_philox_draws(unsigned long long seed, int member, int Wk, unsigned long long step, double sigma,
                                double* disp, double* unif, hipStream_t st);

@@ -592,7 +592,7 @@ struct qmc_multi {
   int nc = 1, qmax = 4;
   // accept phase: one persistent launch per register class (slice length) so
   // that small members do not run with the largest member's register budget
-  struct AccClass { int qm; int2* items; int n; int grid; };
+  struct AccClass { int qm; int2* items; int n; int grid; unsigned members; };
   std::vector<AccClass> acc;
   int store = 0;        // 0 FP64, 1 FP32, 2 BF16 rows
   hipStream_t own = nullptr;
@@ -689,7 +689,9 @@ extern "C" qmc_status qmc_multi_create(int32_t n_members, qmc_system* const* sys
   if (!e) e = hipMemcpy(m->d_items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice);
   for (int c = 0; c < 5 && !e; ++c) {
     if (cls[c].empty()) continue;
-    qmc_multi::AccClass ac{4 << c, nullptr, (int)cls[c].size(), std::min((int)cls[c].size(), 2048)};
+    unsigned members = 0;
+    for (const int2& it : cls[c]) members |= 1u << it.x;
+    qmc_multi::AccClass ac{4 << c, nullptr, (int)cls[c].size(), std::min((int)cls[c].size(), 2048), members};
     al((void**)&ac.items, sizeof(int2) * cls[c].size());
     if (!e) e = hipMemcpy(ac.items, cls[c].data(), sizeof(int2) * cls[c].size(), hipMemcpyHostToDevice);
     m->acc.push_back(ac);
@@ -734,11 +736,12 @@ static hipError_t multi_enqueue(qmc_multi* m, int n_steps, bool explicit_draws, 
               explicit_draws ? m->d_unif : nullptr, 0, seed, sigma};
   for (int t = 0; t < n_steps; ++t) {
     a.t = t;
-    unsigned mask = 0;
+    unsigned mask = 0, up_mask = 0;
     for (int k = 0; k < m->n; ++k) {
       const SysDev& s = m->h_sys[k];
       const long att = m->wk[k]->attempts + t;
       const int e = (int)(att % s.N);
+      if (e < s.nu) up_mask |= 1u << k;
       if (e < s.nu && !dn_ok[k]) {
         hipError_t r = launch_P_build(s, m->h_wk[k], 2, m->own);
         if (r != hipSuccess) return r;
@@ -753,8 +756,11 @@ static hipError_t multi_enqueue(qmc_multi* m, int n_steps, bool explicit_draws, 
     }
     hipError_t r = launch_multi_prep(a, m->d_items, m->n_items, m->grid_items, m->own);
     if (r == hipSuccess) r = launch_multi_rows(a, m->store, m->nc, m->d_rows_items, m->n_rows_items, m->grid_rows, m->own);
-    for (const auto& ac : m->acc)
-      if (r == hipSuccess) r = launch_multi_accept(a, m->store, ac.qm, ac.items, ac.n, ac.grid, m->own);
+    for (const auto& ac : m->acc) {
+      const unsigned mu = ac.members & up_mask, md = ac.members & ~up_mask;
+      if (r == hipSuccess && mu) r = launch_multi_accept(a, m->store, ac.qm, true, mu, ac.items, ac.n, ac.grid, m->own);
+      if (r == hipSuccess && md) r = launch_multi_accept(a, m->store, ac.qm, false, md, ac.items, ac.n, ac.grid, m->own);
+    }
     // refresh: the one-system LU per member, so results match a lone run bitwise
     for (int k = 0; k < m->n && r == hipSuccess; ++k) {
       if (!((mask >> k) & 1u)) continue;
