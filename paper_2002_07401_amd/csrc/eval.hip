@@ -187,6 +187,7 @@ jastrow_assemble_kernel(SysDev s, WalkDev w, double* __restrict__ logabs_o, doub
     w.logabs[wk] = la;
     w.sign[wk] = sg;
     w.J[wk] = J;
+    w.wm[wk] = 0;   // the fresh inverse has no delayed updates
     if (logabs_o) logabs_o[wk] = la;
     if (sign_o) sign_o[wk] = sg;
     if (ekin_o) ekin_o[wk] = ekin;

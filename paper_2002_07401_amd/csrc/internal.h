@@ -19,7 +19,8 @@ constexpr int kLuMaxN = 128;      // one-workgroup (register / LDS) Sherman-Morr
 constexpr int kLuRowMax = 96;     // register (row-per-thread) Gauss-Jordan limit
 constexpr int kPropRowsMin = 8;   // smallest rows-per-workgroup the autotuner may pick
 constexpr int kMaxNucBack = 256;  // nuclei handled by the Jastrow backward kernel
-constexpr int kBigMaxN = 1024;    // blocked Gauss-Jordan / two-pass update limit
+constexpr int kBigMaxN = 1024;    // blocked Gauss-Jordan limit
+constexpr int kWbMax = 64;        // capacity of the delayed-update buffer (moves between refreshes)
 constexpr int kGjPanel = 64;      // panel width of the blocked Gauss-Jordan
 constexpr int kLamTileK = 16;     // Lambda tile mask granularity: rows (GEMM K step) ...
 constexpr int kLamTileN = 64;     // ... and columns (GEMM N tile)
@@ -124,7 +125,18 @@ struct WalkDev {
   int* rowk;          // [Wk][np] step at which row i was pivoted (-1: not yet)
   int* prow;          // [Wk][np] row pivoted at step k
   double* pivv;       // [Wk][np] pivot value of step k
-  double* smv;        // [Wk][2][nu] coefficient and saved vectors of a rank-1 update
+  // Delayed updates since the last refresh (A0 = W^{-1} at the refresh):
+  //   W^{-1} = A0 - V S^{-1} (D^T A0)    (up moves: v_i = A0[:, e_i], d_i = row change)
+  //   W^{-1} = A0 - (A0 D) S^{-T} V^T    (down moves: v_i = A0[e_i, :], d_i = column change)
+  // with S_ij = d_i . v_j + [i == j] (m x m); one move direction per buffer.
+  int* wm;            // [Wk] stored updates m
+  double* wv;         // [Wk][kb][n] v_i
+  double* wd;         // [Wk][kb][n] d_i
+  double* wS;         // [Wk][kb][kb] S^{-1}
+  double* cvec;       // [Wk][n] current W^{-1} column e (up) or row e (down) of the pending proposal
+  double* v0;         // [Wk][n] A0's column / row e of the pending proposal
+  double* tz;         // [Wk][2][kb] t = D^T v0 and z = S^{-1} t of the pending proposal
+  int kb;             // buffer capacity (<= kWbMax)
 };
 
 // Workspace of the reverse pass (allocated on the first qmc_forces call).
@@ -163,8 +175,8 @@ struct MultiArgs {
 hipError_t launch_multi_prep(const MultiArgs& a, const int2* items, int n_items, int grid, hipStream_t st);
 hipError_t launch_multi_rows(const MultiArgs& a, int store, int nc, const int4* items, int n_items, int grid,
                              hipStream_t st);
-hipError_t launch_multi_accept(const MultiArgs& a, int store, int qmax, bool up, unsigned mask, const int2* items,
-                               int n_items, int grid, hipStream_t st);
+hipError_t launch_multi_accept(const MultiArgs& a, int store, const int2* items, int n_items, int grid,
+                               hipStream_t st);
 hipError_t launch_multi_advance(long long* steps, int n, hipStream_t st);
 hipError_t launch_philox_draws(unsigned long long seed, int member, int Wk, unsigned long long step, double sigma,
                                double* disp, double* unif, hipStream_t st);
@@ -330,6 +342,10 @@ hipError_t launch_metropolis_accept(const SysDev& s, const WalkDev& w, int e, co
 hipError_t launch_accept(const SysDev& s, const WalkDev& w, int e, const uint8_t* acc,
                          hipStream_t st);
 hipError_t launch_refresh_finish(const SysDev& s, const WalkDev& w, int32_t* status, hipStream_t st);
+hipError_t launch_materialize_inverse(const SysDev& s, const WalkDev& w, bool down, double* scratch, double* dst,
+                                      hipStream_t st);
+// moves that fit the delayed-update buffer between refreshes
+inline int wb_cap(const SysDev& s) { return s.refresh_every < kWbMax ? s.refresh_every : kWbMax; }
 hipError_t launch_export_phi(const SysDev& s, const WalkDev& w, double* dst, hipStream_t st);
 hipError_t launch_set_lambda(const SysDev& s, const double* lam, hipStream_t st);
 hipError_t launch_pack_basis(const SysDev& s, hipStream_t st);

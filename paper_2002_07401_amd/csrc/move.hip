@@ -44,13 +44,13 @@ __global__ void __launch_bounds__(256) propose_rows_generic_kernel(SysDev s, Wal
   rows_generic_body<T, DRIFT>(s, w, blockIdx.y, blockIdx.x, gridDim.x, e, s.prop_rows());
 }
 
-template <typename T, int QMAX, bool UP>
+template <typename T>
 __global__ void __launch_bounds__(256)
 accept_kernel(SysDev s, WalkDev w, int e, const uint8_t* __restrict__ acc_in,
               const double* __restrict__ unif, int32_t* __restrict__ accept_count, int S) {
   const int wk = blockIdx.x;
-  accept_body<T, QMAX, UP>(s, w, wk, e, unif ? 1 : 0, acc_in ? acc_in + wk : nullptr, unif ? unif[wk] : 0.0,
-                           accept_count ? accept_count + wk : nullptr, S);
+  accept_body<T>(s, w, wk, e, unif ? 1 : 0, acc_in ? acc_in + wk : nullptr, unif ? unif[wk] : 0.0,
+                 accept_count ? accept_count + wk : nullptr, S);
 }
 
 // Sum the partial ratios (fixed order) for host-driven proposals.
@@ -129,156 +129,14 @@ hipError_t launch_propose_rows(const SysDev& s, const WalkDev& w, int e, double*
   return hipGetLastError();
 }
 
-template <typename T>
-static hipError_t accept_launch_t(const SysDev& s, const WalkDev& w, int e, const uint8_t* acc,
-                                  const double* unif, int32_t* accept_count, int S, hipStream_t st) {
-  const int n = s.nu;
-  const int G = 256 / n, Q = (n + G - 1) / G;
-#define QMC_ACC(QM)                                                                                      \
-  if (e < s.nu)                                                                                          \
-    hipLaunchKernelGGL((accept_kernel<T, QM, true>), dim3(w.Wk), dim3(256), 0, st, s, w, e, acc, unif,     \
-                       accept_count, S);                                                                 \
-  else                                                                                                   \
-    hipLaunchKernelGGL((accept_kernel<T, QM, false>), dim3(w.Wk), dim3(256), 0, st, s, w, e, acc, unif,    \
-                       accept_count, S)
-  if (Q <= 4) { QMC_ACC(4); }
-  else if (Q <= 8) { QMC_ACC(8); }
-  else if (Q <= 16) { QMC_ACC(16); }
-  else if (Q <= 32) { QMC_ACC(32); }
-  else { QMC_ACC(64); }
-#undef QMC_ACC
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// Sherman-Morrison for kLuMaxN < n <= kBigMaxN, in two passes over A.
-// Pass 1 (grid (ceil(n/64), Wk)): decision, delta, and 64 entries per block of
-//   up:   coef[c] = (delta^T A)[c] / R,  save = A[:, e]   (block 0)
-//   down: coef[j] = (A delta)[j] / R,    save = A[e, :]   (block 0)
-// Pass 2: A -= save coef^T (up) or coef save^T (down), the W row/column, the
-// basis row and the bookkeeping (block 0).  Same arithmetic as accept_body.
-// ---------------------------------------------------------------------------
-template <bool UP>
-__global__ void __launch_bounds__(256)
-accept_big_coef_kernel(SysDev s, WalkDev w, int e, const uint8_t* __restrict__ acc_in,
-                       const double* __restrict__ unif, int S) {
-  __shared__ double delta[kBigMaxN];
-  __shared__ double part[4][64];
-  const int wk = blockIdx.y, x0 = blockIdx.x * 64;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  double R, ratio;
-  if (S > 0) {
-    R = 0.0;
-    for (int k = 0; k < S; ++k) R += w.rdet_part[(long)wk * S + k];
-    ratio = R * exp(w.dJ[wk]);
-  } else {
-    R = w.rdet[wk];
-    ratio = w.ratio[wk];
-  }
-  const bool acc = unif ? (unif[wk] < ratio * ratio) : (acc_in[wk] != 0);
-  if (blockIdx.x == 0 && tid == 0) {
-    if (S > 0) { w.rdet[wk] = R; w.ratio[wk] = ratio; }
-    w.acc[wk] = acc ? 1 : 0;
-  }
-  if (!acc) return;
-  const int n = s.nu, ed = e - s.nu;
-  const double invR = 1.0 / R;
-  const double* Aw = w.A + (long)wk * n * n;
-  const double* Ww = w.W + (long)wk * n * n;
-  const double* wn = w.w_new + (long)wk * n;
-  double* coef = w.smv + (long)wk * 2 * n;
-  double* save = coef + n;
-  for (int j = tid; j < n; j += 256) delta[j] = UP ? wn[j] - Ww[(long)e * n + j] : wn[j] - Ww[(long)j * n + ed];
-  if (blockIdx.x == 0)
-    for (int j = tid; j < n; j += 256) save[j] = UP ? Aw[(long)j * n + e] : Aw[(long)ed * n + j];
-  __syncthreads();
-  if constexpr (UP) {
-    const int c = x0 + lane;
-    double t = 0.0;
-    if (c < n)
-      for (int j = wave; j < n; j += 4) t += delta[j] * Aw[(long)j * n + c];
-    part[wave][lane] = t;
-    __syncthreads();
-    if (tid < 64 && c < n) coef[c] = (part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane]) * invR;
-  } else {
-    double xv[16];
-#pragma unroll
-    for (int m = 0; m < 16; ++m) {
-      const int j = x0 + wave * 16 + m;
-      double t = 0.0;
-      if (j < n)
-        for (int i = lane; i < n; i += 64) t += Aw[(long)j * n + i] * delta[i];
-      xv[m] = t;
-    }
-    const double tot = wave_multi_sum16(xv, lane);
-    const int j = x0 + wave * 16 + (lane >> 2);
-    if ((lane & 3) == 0 && j < n) coef[j] = tot * invR;
-  }
-}
-
-template <typename T, bool UP>
-__global__ void __launch_bounds__(256)
-accept_big_update_kernel(SysDev s, WalkDev w, int e, int32_t* __restrict__ accept_count) {
-  const int wk = blockIdx.y;
-  if (!w.acc[wk]) return;
-  const int n = s.nu, ed = e - s.nu;
-  double* Aw = w.A + (long)wk * n * n;
-  const double* coef = w.smv + (long)wk * 2 * n;
-  const double* save = coef + n;
-  const long nn = (long)n * n;
-  for (long idx = (long)blockIdx.x * 256 + threadIdx.x; idx < nn; idx += (long)gridDim.x * 256) {
-    const int j = (int)(idx / n), c = (int)(idx % n);
-    Aw[idx] = UP ? Aw[idx] - save[j] * coef[c] : Aw[idx] - coef[j] * save[c];
-  }
-  if (blockIdx.x != 0) return;
-  const int tid = threadIdx.x;
-  double* Ww = w.W + (long)wk * n * n;
-  const double* wn = w.w_new + (long)wk * n;
-  for (int j = tid; j < n; j += 256) {
-    if (UP) Ww[(long)e * n + j] = wn[j];
-    else Ww[(long)j * n + ed] = wn[j];
-  }
-  T* prow = (T*)w.phi + ((long)wk * s.N + e) * s.Lp;
-  const double* pn = w.psi_new + (long)wk * s.Lp;
-  for (int mu = tid; mu < s.L; mu += 256) prow[mu] = (T)pn[mu];
-  if (tid == 0) {
-    const double R = w.rdet[wk];
-    double* re = w.r + ((long)wk * s.N + e) * 3;
-    re[0] = w.r_new[3 * wk]; re[1] = w.r_new[3 * wk + 1]; re[2] = w.r_new[3 * wk + 2];
-    const double dJ = w.dJ[wk];
-    w.logabs[wk] += log(fabs(R)) + dJ;
-    if (R < 0.0) w.sign[wk] = -w.sign[wk];
-    w.J[wk] += dJ;
-    if (accept_count) accept_count[wk] += 1;
-  }
-}
-
-template <typename T>
-static hipError_t accept_big_t(const SysDev& s, const WalkDev& w, int e, const uint8_t* acc, const double* unif,
-                               int32_t* accept_count, int S, hipStream_t st) {
-  const int n = s.nu;
-  if (n > kBigMaxN || !w.smv) return hipErrorNotSupported;
-  const dim3 g1((n + 63) / 64, w.Wk), g2((unsigned)std::min<long>(((long)n * n + 1023) / 1024, 256), w.Wk);
-  if (e < s.nu) {
-    hipLaunchKernelGGL(accept_big_coef_kernel<true>, g1, dim3(256), 0, st, s, w, e, acc, unif, S);
-    hipLaunchKernelGGL((accept_big_update_kernel<T, true>), g2, dim3(256), 0, st, s, w, e, accept_count);
-  } else {
-    hipLaunchKernelGGL(accept_big_coef_kernel<false>, g1, dim3(256), 0, st, s, w, e, acc, unif, S);
-    hipLaunchKernelGGL((accept_big_update_kernel<T, false>), g2, dim3(256), 0, st, s, w, e, accept_count);
-  }
-  return hipGetLastError();
-}
-
 static hipError_t accept_launch(const SysDev& s, const WalkDev& w, int e, const uint8_t* acc,
                                 const double* unif, int32_t* accept_count, int S, hipStream_t st) {
-  if (s.nu > kLuMaxN) {
-    if (s.bf16()) return accept_big_t<bf16s>(s, w, e, acc, unif, accept_count, S, st);
-    if (s.f32()) return accept_big_t<float>(s, w, e, acc, unif, accept_count, S, st);
-    return accept_big_t<double>(s, w, e, acc, unif, accept_count, S, st);
-  }
-  if (s.bf16()) return accept_launch_t<bf16s>(s, w, e, acc, unif, accept_count, S, st);
-  if (s.f32()) return accept_launch_t<float>(s, w, e, acc, unif, accept_count, S, st);
-  return accept_launch_t<double>(s, w, e, acc, unif, accept_count, S, st);
+  if (s.nu > kBigMaxN || !w.wv) return hipErrorNotSupported;
+  const dim3 grid(w.Wk), blk(256);
+  if (s.bf16()) hipLaunchKernelGGL(accept_kernel<bf16s>, grid, blk, 0, st, s, w, e, acc, unif, accept_count, S);
+  else if (s.f32()) hipLaunchKernelGGL(accept_kernel<float>, grid, blk, 0, st, s, w, e, acc, unif, accept_count, S);
+  else hipLaunchKernelGGL(accept_kernel<double>, grid, blk, 0, st, s, w, e, acc, unif, accept_count, S);
+  return hipGetLastError();
 }
 
 hipError_t launch_accept(const SysDev& s, const WalkDev& w, int e, const uint8_t* acc, hipStream_t st) {
@@ -297,7 +155,52 @@ __global__ void refresh_finish_kernel(WalkDev w, int32_t* __restrict__ status) {
   const int sing = w.singular[wk];
   w.logabs[wk] = sing ? -__builtin_inf() : w.logdet[wk] + w.J[wk];
   w.sign[wk] = w.detsign[wk];
+  w.wm[wk] = 0;
   if (status) status[wk] = sing ? 1 : 0;
+}
+
+// W^{-1} of every walker from the refresh inverse A0 and the delayed updates
+// (state read-out).  up: A0 - V S^{-1} (D^T A0); down: A0 - (A0 D) S^{-T} V^T.
+// G = D^T A0 (up, [m][n]) or (A0 D)^T (down, [m][n]) goes through `scratch`.
+__global__ void __launch_bounds__(256)
+materialize_inverse_kernel(SysDev s, WalkDev w, int down, double* __restrict__ scratch, double* __restrict__ dst) {
+  const int wk = blockIdx.x, tid = threadIdx.x;
+  const int n = s.nu, kb = w.kb, m = w.wm[wk];
+  const double* A0 = w.A + (long)wk * n * n;
+  const double* D = w.wd + (long)wk * kb * n;
+  const double* V = w.wv + (long)wk * kb * n;
+  const double* Si = w.wS + (long)wk * kb * kb;
+  double* G = scratch + (long)wk * kb * n;
+  double* out = dst + (long)wk * n * n;
+  for (int idx = tid; idx < m * n; idx += blockDim.x) {
+    const int l = idx / n, j = idx % n;
+    double g = 0.0;
+    if (!down) for (int i = 0; i < n; ++i) g += D[(long)l * n + i] * A0[(long)i * n + j];
+    else for (int i = 0; i < n; ++i) g += A0[(long)j * n + i] * D[(long)l * n + i];
+    G[(long)l * n + j] = g;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < n * n; idx += blockDim.x) {
+    const int i = idx / n, j = idx % n;
+    double corr = 0.0;
+    for (int k = 0; k < m; ++k) {
+      double h = 0.0;
+      if (!down) {   // (V S^{-1} G)[i][j]
+        for (int l = 0; l < m; ++l) h += Si[k * kb + l] * G[(long)l * n + j];
+        corr += V[(long)k * n + i] * h;
+      } else {       // (G^T S^{-T} V)[i][j]
+        for (int l = 0; l < m; ++l) h += Si[l * kb + k] * V[(long)l * n + j];
+        corr += G[(long)k * n + i] * h;
+      }
+    }
+    out[idx] = A0[idx] - corr;
+  }
+}
+
+hipError_t launch_materialize_inverse(const SysDev& s, const WalkDev& w, bool down, double* scratch, double* dst,
+                                      hipStream_t st) {
+  hipLaunchKernelGGL(materialize_inverse_kernel, dim3(w.Wk), dim3(256), 0, st, s, w, down ? 1 : 0, scratch, dst);
+  return hipGetLastError();
 }
 
 hipError_t launch_refresh_finish(const SysDev& s, const WalkDev& w, int32_t* status, hipStream_t st) {

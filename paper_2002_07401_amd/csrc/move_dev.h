@@ -49,6 +49,58 @@ __device__ void jastrow_one(const SysDev& s, const double* r, int e, double px, 
   }
 }
 
+// The current inverse's column e (up move) or row e (down move) from the
+// refresh inverse A0 and the delayed updates (one workgroup per walker):
+//   v0 = A0[:, e] or A0[e, :],  t_i = d_i . v0,  z = S^{-1} t,  c = v0 - sum_i z_i v_i.
+// v0, t, z and c are kept for the accept step.
+__device__ void inverse_line_body(const SysDev& s, const WalkDev& w, int wk, int e) {
+  __shared__ double sv0[kBigMaxN];
+  __shared__ double st[kWbMax];
+  __shared__ double sz[kWbMax];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  const int n = s.nu, kb = w.kb;
+  const bool up = e < s.nu;
+  const int ie = up ? e : e - s.nu;
+  const double* A0 = w.A + (long)wk * n * n;
+  double* v0 = w.v0 + (long)wk * n;
+  double* cv = w.cvec + (long)wk * n;
+  const int m = w.wm[wk];
+  for (int j = tid; j < n; j += blockDim.x) {
+    const double v = up ? A0[(long)j * n + ie] : A0[(long)ie * n + j];
+    sv0[j] = v;
+    v0[j] = v;
+  }
+  __syncthreads();
+  if (m == 0) {
+    for (int j = tid; j < n; j += blockDim.x) cv[j] = sv0[j];
+    return;   // uniform
+  }
+  const double* D = w.wd + (long)wk * kb * n;
+  const double* V = w.wv + (long)wk * kb * n;
+  const double* Si = w.wS + (long)wk * kb * kb;
+  double* tz = w.tz + (long)wk * 2 * kb;
+  for (int i = wave; i < m; i += nw) {
+    double p = 0.0;
+    for (int j = lane; j < n; j += 64) p += D[(long)i * n + j] * sv0[j];
+    p = wave_sum(p);
+    if (lane == 0) st[i] = p;
+  }
+  __syncthreads();
+  for (int i = tid; i < m; i += blockDim.x) {
+    double z = 0.0;
+    for (int k = 0; k < m; ++k) z += Si[i * kb + k] * st[k];
+    sz[i] = z;
+    tz[i] = st[i];
+    tz[kb + i] = z;
+  }
+  __syncthreads();
+  for (int j = tid; j < n; j += blockDim.x) {
+    double c = sv0[j];
+    for (int i = 0; i < m; ++i) c -= sz[i] * V[(long)i * n + j];
+    cv[j] = c;
+  }
+}
+
 // Step 1 of a proposal, one workgroup per walker: the new position, the basis
 // values psi(r') (zero-padded to Lp, and their gradients when a drift is
 // requested) and the Jastrow change J(x') - J(x) (and grad J at r').
@@ -91,6 +143,7 @@ __device__ void prep_body(const SysDev& s, const WalkDev& w, int wk, int e, cons
     w.dJ[wk] = dJ;
     if (DRIFT) { w.gJ_new[3 * wk] = gxn; w.gJ_new[3 * wk + 1] = gyn; w.gJ_new[3 * wk + 2] = gzn; }
   }
+  inverse_line_body(s, w, wk, e);
 }
 
 template <typename T> struct Vec16;
@@ -138,8 +191,9 @@ __device__ __forceinline__ void block_partial(double part, double gx, double gy,
 // ... two at a time (both rows' loads in flight before either reduction);
 // psi(r') chunks sit in registers and each row is read with NC independent
 // 16-byte loads per lane (NC = ceil(Lp / (64 * 16 / sizeof(T))); chunks past Lp
-// contribute exact zeros).  The W^{-1} entries that weight the rows are loaded
-// once at the start, lane k holding the one of the wave's k-th row.
+// contribute exact zeros).  The entries of the current inverse's column (up) or
+// row (down) that weight the rows are loaded once at the start, lane k holding
+// the one of the wave's k-th row.
 template <typename T, int NC>
 __device__ void rows_body(const SysDev& s, const WalkDev& w, int wk, int sb, int S, int e, int R) {
   typedef typename Vec16<T>::type V;
@@ -151,7 +205,7 @@ __device__ void rows_body(const SysDev& s, const WalkDev& w, int wk, int sb, int
   const int nrow = up ? s.nd : s.nu;
   const int nmax = s.nu > s.nd ? s.nu : s.nd;
   const T* Pw = (const T*)w.P + ((long)wk * s.N + row0) * s.Lp;
-  const double* Aw = w.A + (long)wk * s.nd * s.nu;
+  const double* cv = w.cvec + (long)wk * s.nu;
   double* wn_g = w.w_new + (long)wk * nmax;
   const double* psi = w.psi_new + (long)wk * s.Lp;
   const int j0 = sb * R;
@@ -159,7 +213,7 @@ __device__ void rows_body(const SysDev& s, const WalkDev& w, int wk, int sb, int
   double a_own = 0.0;
   {
     const int j = j0 + wave + lane * nw;
-    if (j < j1) a_own = up ? Aw[(long)j * s.nu + e] : Aw[(long)(e - s.nu) * s.nu + j];
+    if (j < j1) a_own = cv[j];
   }
   double ps[NC][VN];
 #pragma unroll
@@ -214,7 +268,7 @@ __device__ void rows_generic_body(const SysDev& s, const WalkDev& w, int wk, int
   const int nrow = up ? s.nd : s.nu;
   const int nmax = s.nu > s.nd ? s.nu : s.nd;
   const T* Pw = (const T*)w.P + ((long)wk * s.N + row0) * s.Lp;
-  const double* Aw = w.A + (long)wk * s.nd * s.nu;
+  const double* cv = w.cvec + (long)wk * s.nu;
   double* wn_g = w.w_new + (long)wk * nmax;
   const double* psi = w.psi_new + (long)wk * s.Lp;
   const double* gpsi = w.gpsi_new + (long)wk * 3 * s.Lp;
@@ -233,7 +287,7 @@ __device__ void rows_generic_body(const SysDev& s, const WalkDev& w, int wk, int
     if (DRIFT) { ax = wave_sum(ax); ay = wave_sum(ay); az = wave_sum(az); }
     if (lane == 0) {
       wn_g[j] = a0;
-      const double a = up ? Aw[(long)j * s.nu + e] : Aw[(long)(e - s.nu) * s.nu + j];
+      const double a = cv[j];
       part += a0 * a;
       if (DRIFT) { gx += ax * a; gy += ay * a; gz += az * a; }
     }
@@ -241,59 +295,30 @@ __device__ void rows_generic_body(const SysDev& s, const WalkDev& w, int wk, int
   block_partial(part, gx, gy, gz, DRIFT, w, wk, S, sb);
 }
 
-// Sums 16 per-lane values over the 64 lanes of a wave with 17 shuffles in six
-// dependent rounds: each of the first four rounds keeps half of the live values
-// and trades the other half with the partner lane.  Lanes 4m..4m+3 return the
-// total of x[m].
-#define QMC_MS_STAGE(H, O)                                      \
-  {                                                             \
-    const bool hi = (lane & (O)) != 0;                          \
-    _Pragma("unroll") for (int k = 0; k < (H); ++k) {           \
-      const double send = hi ? x[k] : x[k + (H)];               \
-      const double keep = hi ? x[k + (H)] : x[k];               \
-      x[k] = keep + __shfl_xor(send, (O), 64);                  \
-    }                                                           \
-  }
-__device__ __forceinline__ double wave_multi_sum16(double (&x)[16], int lane) {
-  QMC_MS_STAGE(8, 32)
-  QMC_MS_STAGE(4, 16)
-  QMC_MS_STAGE(2, 8)
-  QMC_MS_STAGE(1, 4)
-  double t = x[0];
-  t += __shfl_xor(t, 2, 64);
-  t += __shfl_xor(t, 1, 64);
-  return t;
-}
-#undef QMC_MS_STAGE
-
 // ---------------------------------------------------------------------------
-// Accept: decide (device Metropolis, u < ratio^2, when unif is given) and
-// apply the rank-1 Sherman-Morrison update of A = W^{-1} in FP64:
-//   up e   (row e of W replaced by w'):    A <- A - A[:,e] (delta^T A) / R
-//   down e (column e of W replaced by w'): A <- A - (A delta) A[e,:] / R
-// with delta = w' - (old row/column) and R = det W'/det W.  Thread t holds
-// column c = t % n of rows g, g+G, ... (g = t / n, G = blockDim / n) in
-// registers: A is read once and written once.  Column sums (up moves) combine
-// the G groups' partials through LDS; row sums (down moves) are read row-wise
-// (served from cache, the rows having just been read) and reduced 16 rows per
-// wave at a time.  Every thread takes the acceptance decision itself from the
-// same values, so no barrier precedes the loads of A.
+// Accept: decide (device Metropolis, u < ratio^2, when u is given) and record
+// the accepted move as a delayed update (one workgroup per walker).  With
+// delta = w' - (old row / column of W), v0, t, z and c from the proposal:
+//   r_j = delta . v_j (j < m),  gamma = 1 + delta . v0 - r . z  (= 1 + delta . c,
+//   the determinant ratio),  y = S^{-T} r,
+//   S^{-1} <- [[S^{-1} + z y^T / gamma, -z / gamma], [-y^T / gamma, 1 / gamma]],
+//   v_m = v0, d_m = delta, m <- m + 1   (the bordered inverse of S).
+// The inverse itself is not touched; W's row / column, the basis row, the
+// position and the tracked log|Psi|, sign and Jastrow sum are.
 // S > 0: the ratio is first summed from the proposal's S partial sums.
 // ---------------------------------------------------------------------------
 // acc_in: this walker's host decision (mode 0), or u: its uniform (mode 1).
 // cnt: this walker's accept counter (may be null).
-// UP = (e < n_up), fixed per instantiation so that each direction gets its own
-// register allocation.
-template <typename T, int QMAX, bool UP>
+template <typename T>
 __device__ void accept_body(const SysDev& s, const WalkDev& w, int wk, int e, int mode,
                             const uint8_t* __restrict__ acc_in, double u, int32_t* __restrict__ cnt, int S) {
-  __shared__ double delta[kLuMaxN];
-  __shared__ double save[kLuMaxN];
-  __shared__ double coef[kLuMaxN];
-  __shared__ double part[256];
+  __shared__ double sd[kBigMaxN];
+  __shared__ double sr[kWbMax];
+  __shared__ double sy[kWbMax];
+  __shared__ double red[16];
+  __shared__ double gam_s;
   const int n = s.nu;             // square: n_up == n_dn
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int nw = blockDim.x >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
   double R, ratio;
   if (S > 0) {
     R = 0.0;
@@ -303,115 +328,84 @@ __device__ void accept_body(const SysDev& s, const WalkDev& w, int wk, int e, in
     R = w.rdet[wk];
     ratio = w.ratio[wk];
   }
-  const bool acc = (mode == 1) ? (u < ratio * ratio) : (acc_in[0] != 0);
+  const int kb = w.kb, m = w.wm[wk];
+  // a full buffer cannot occur (the host refreshes first); if it did, the move
+  // is rejected rather than written past the buffer
+  const bool acc = m < kb && ((mode == 1) ? (u < ratio * ratio) : (acc_in[0] != 0));
   if (tid == 0) {
     if (S > 0) { w.rdet[wk] = R; w.ratio[wk] = ratio; }
     w.acc[wk] = acc ? 1 : 0;
   }
   if (!acc) return;   // uniform over the block
-  const double invR = 1.0 / R;
-  constexpr bool up = UP;
-  const int ed = e - s.nu;
-  double* Aw = w.A + (long)wk * n * n;
+  const bool up = e < s.nu;
+  const int ie = up ? e : e - s.nu;
   double* Ww = w.W + (long)wk * n * n;
   const double* wn = w.w_new + (long)wk * n;
-  const int G = blockDim.x / n, c = tid % n, g = tid / n;
-  const bool own = g < G;
-  double a[QMAX];
-  // up moves: the column slices load while delta and the bookkeeping proceed;
-  // down moves load them after the row sums (cache hits, fewer live registers)
-  if constexpr (UP) {
-#pragma unroll
-    for (int q = 0; q < QMAX; ++q) {
-      const int j = g + G * q;
-      a[q] = (own && j < n) ? Aw[(long)j * n + c] : 0.0;
-    }
+  const double* v0 = w.v0 + (long)wk * n;
+  double* D = w.wd + (long)wk * kb * n;
+  double* V = w.wv + (long)wk * kb * n;
+  double* Si = w.wS + (long)wk * kb * kb;
+  const double* tz = w.tz + (long)wk * 2 * kb;
+  // delta, then W's row / column and the new buffer entries
+  double p0 = 0.0;
+  for (int j = tid; j < n; j += blockDim.x) {
+    const long off = up ? (long)ie * n + j : (long)j * n + ie;
+    const double d = wn[j] - Ww[off];
+    sd[j] = d;
+    p0 += d * v0[j];
+    D[(long)m * n + j] = d;
+    V[(long)m * n + j] = v0[j];
   }
-  for (int j = tid; j < n; j += blockDim.x)
-    delta[j] = up ? wn[j] - Ww[(long)e * n + j] : wn[j] - Ww[(long)j * n + ed];
-  // bookkeeping that does not depend on the update
-  {
-    T* prow = (T*)w.phi + ((long)wk * s.N + e) * s.Lp;
-    const double* pn = w.psi_new + (long)wk * s.Lp;
-    for (int mu = tid; mu < s.L; mu += blockDim.x) prow[mu] = (T)pn[mu];
-    if (tid == 0) {
-      double* re = w.r + ((long)wk * s.N + e) * 3;
-      re[0] = w.r_new[3 * wk]; re[1] = w.r_new[3 * wk + 1]; re[2] = w.r_new[3 * wk + 2];
-    }
-    if (tid == (blockDim.x > 64 ? 64 : 0)) {
-      const double dJ = w.dJ[wk];
-      w.logabs[wk] += log(fabs(R)) + dJ;
-      if (R < 0.0) w.sign[wk] = -w.sign[wk];
-      w.J[wk] += dJ;
-      if (cnt) cnt[0] += 1;
-    }
+  // delta . v0 (block sum in fixed order)
+  p0 = wave_sum(p0);
+  if (lane == 0) red[wave] = p0;
+  __syncthreads();
+  for (int i = wave; i < m; i += nw) {
+    double p = 0.0;
+    for (int j = lane; j < n; j += 64) p += sd[j] * V[(long)i * n + j];
+    p = wave_sum(p);
+    if (lane == 0) sr[i] = p;
   }
   __syncthreads();
-  if constexpr (UP) {
-    double t = 0.0;
-#pragma unroll
-    for (int q = 0; q < QMAX; ++q) {
-      const int j = g + G * q;
-      if (own && j < n) t += delta[j] * a[q];
-    }
-    if (own) part[g * n + c] = t;
-    if (own && c == e) {
-#pragma unroll
-      for (int q = 0; q < QMAX; ++q) {
-        const int j = g + G * q;
-        if (j < n) save[j] = a[q];
-      }
-    }
-    __syncthreads();
-    if (own) {
-      double uc = 0.0;
-      for (int q = 0; q < G; ++q) uc += part[q * n + c];
-      const double ck = uc * invR;
-#pragma unroll
-      for (int q = 0; q < QMAX; ++q) {
-        const int j = g + G * q;
-        if (j < n) Aw[(long)j * n + c] = a[q] - save[j] * ck;
-      }
-    }
-    for (int j = tid; j < n; j += blockDim.x) Ww[(long)e * n + j] = wn[j];
-  } else {
-    // rows j = wave + nw * m, 16 values of m per pass (n <= 32 nw)
-    for (int m0 = 0; wave + nw * m0 < n; m0 += 16) {
-      double x[16];
-#pragma unroll
-      for (int m = 0; m < 16; ++m) {
-        const int j = wave + nw * (m0 + m);
-        double t = 0.0;
-        if (j < n)
-          for (int i = lane; i < n; i += 64) t += Aw[(long)j * n + i] * delta[i];
-        x[m] = t;
-      }
-      const double tot = wave_multi_sum16(x, lane);
-      const int j = wave + nw * (m0 + (lane >> 2));
-      if ((lane & 3) == 0 && j < n) coef[j] = tot * invR;
-    }
-#pragma unroll
-    for (int q = 0; q < QMAX; ++q) {
-      const int j = g + G * q;
-      a[q] = (own && j < n) ? Aw[(long)j * n + c] : 0.0;
-    }
-    if (own && g == ed % G) {
-      const int qe = ed / G;
-      double v = 0.0;
-#pragma unroll
-      for (int q = 0; q < QMAX; ++q) if (q == qe) v = a[q];
-      save[c] = v;
-    }
-    __syncthreads();
-    if (own) {
-      const double sc = save[c];
-#pragma unroll
-      for (int q = 0; q < QMAX; ++q) {
-        const int j = g + G * q;
-        if (j < n) Aw[(long)j * n + c] = a[q] - coef[j] * sc;
-      }
-    }
-    for (int i = tid; i < n; i += blockDim.x) Ww[(long)i * n + ed] = wn[i];
+  if (tid == 0) {
+    double dv = 0.0;
+    for (int k = 0; k < nw; ++k) dv += red[k];
+    double rz = 0.0;
+    for (int i = 0; i < m; ++i) rz += sr[i] * tz[kb + i];
+    gam_s = 1.0 + dv - rz;
+  }
+  for (int k = tid; k < m; k += blockDim.x) {
+    double y = 0.0;
+    for (int i = 0; i < m; ++i) y += Si[i * kb + k] * sr[i];
+    sy[k] = y;
+  }
+  __syncthreads();
+  const double ig = 1.0 / gam_s;
+  for (int idx = tid; idx < (m + 1) * (m + 1); idx += blockDim.x) {
+    const int i = idx / (m + 1), k = idx % (m + 1);
+    double v;
+    if (i < m && k < m) v = Si[i * kb + k] + tz[kb + i] * sy[k] * ig;
+    else if (i < m) v = -tz[kb + i] * ig;
+    else if (k < m) v = -sy[k] * ig;
+    else v = ig;
+    Si[i * kb + k] = v;
+  }
+  for (int j = tid; j < n; j += blockDim.x) {
+    if (up) Ww[(long)ie * n + j] = wn[j];
+    else Ww[(long)j * n + ie] = wn[j];
+  }
+  T* prow = (T*)w.phi + ((long)wk * s.N + e) * s.Lp;
+  const double* pn = w.psi_new + (long)wk * s.Lp;
+  for (int mu = tid; mu < s.L; mu += blockDim.x) prow[mu] = (T)pn[mu];
+  if (tid == 0) {
+    w.wm[wk] = m + 1;
+    double* re = w.r + ((long)wk * s.N + e) * 3;
+    re[0] = w.r_new[3 * wk]; re[1] = w.r_new[3 * wk + 1]; re[2] = w.r_new[3 * wk + 2];
+    const double dJ = w.dJ[wk];
+    w.logabs[wk] += log(fabs(R)) + dJ;
+    if (R < 0.0) w.sign[wk] = -w.sign[wk];
+    w.J[wk] += dJ;
+    if (cnt) cnt[0] += 1;
   }
 }
 

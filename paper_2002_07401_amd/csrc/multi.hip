@@ -111,23 +111,18 @@ __global__ void __launch_bounds__(256) multi_rows_kernel(MultiArgs a, const int4
   }
 }
 
-// Members in `mask` only: each launch serves one move direction (the host
-// knows every member's electron), so up and down moves keep their own
-// register allocations as in the one-system kernels.
-template <typename T, int QMAX, bool UP>
-__global__ void __launch_bounds__(256) multi_accept_kernel(MultiArgs a, const int2* __restrict__ items, int n_items,
-                                                           unsigned mask) {
+template <typename T>
+__global__ void __launch_bounds__(256) multi_accept_kernel(MultiArgs a, const int2* __restrict__ items, int n_items) {
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
     __syncthreads();
     const int k = items[it].x, w = items[it].y;
-    if (!((mask >> k) & 1u)) continue;
     const SysDev& s = a.sysv[k];
     const WalkDev& wd = a.wkv[k];
     const int e = (int)(a.steps[k] % s.N);
     double d[3], u;
     member_draw(a, k, w, wd.Wk, d, &u);
-    const int nrow = UP ? s.nd : s.nu;
-    accept_body<T, QMAX, UP>(s, wd, w, e, 1, nullptr, u, nullptr, (nrow + a.rows[k] - 1) / a.rows[k]);
+    const int nrow = e < s.nu ? s.nd : s.nu;
+    accept_body<T>(s, wd, w, e, 1, nullptr, u, nullptr, (nrow + a.rows[k] - 1) / a.rows[k]);
   }
 }
 
@@ -164,19 +159,11 @@ hipError_t launch_multi_rows(const MultiArgs& a, int store, int nc, const int4* 
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_multi_accept(const MultiArgs& a, int store, int qmax, bool up, unsigned mask, const int2* items,
-                               int n_items, int grid, hipStream_t st) {
-#define QMC_MA(T, QM)                                                                                       \
-  if (up) hipLaunchKernelGGL((multi_accept_kernel<T, QM, true>), dim3(grid), dim3(256), 0, st, a, items, n_items, mask); \
-  else hipLaunchKernelGGL((multi_accept_kernel<T, QM, false>), dim3(grid), dim3(256), 0, st, a, items, n_items, mask)
-#define QMC_MA_ALL(T)                                                                                        \
-  if (qmax <= 4) { QMC_MA(T, 4); } else if (qmax <= 8) { QMC_MA(T, 8); } else if (qmax <= 16) { QMC_MA(T, 16); } \
-  else if (qmax <= 32) { QMC_MA(T, 32); } else { QMC_MA(T, 64); }
-  if (store == 2) { QMC_MA_ALL(bf16s) }
-  else if (store == 1) { QMC_MA_ALL(float) }
-  else { QMC_MA_ALL(double) }
-#undef QMC_MA_ALL
-#undef QMC_MA
+hipError_t launch_multi_accept(const MultiArgs& a, int store, const int2* items, int n_items, int grid,
+                               hipStream_t st) {
+  if (store == 2) hipLaunchKernelGGL(multi_accept_kernel<bf16s>, dim3(grid), dim3(256), 0, st, a, items, n_items);
+  else if (store == 1) hipLaunchKernelGGL(multi_accept_kernel<float>, dim3(grid), dim3(256), 0, st, a, items, n_items);
+  else hipLaunchKernelGGL(multi_accept_kernel<double>, dim3(grid), dim3(256), 0, st, a, items, n_items);
   return hipGetLastError();
 }
 

@@ -111,6 +111,9 @@ struct qmc_walkers {
   std::vector<void*> allocs;
   int pending_e = -1;
   long attempts = 0;
+  int since = 0;        // attempted moves since the last refresh
+  int buf_spin = -1;    // spin of the moves in the delayed-update buffer (-1: empty)
+  double* rd_scratch = nullptr;   // [Wk][kb][n] state read-out work
   bool evaluated = false;
   bool P_up_valid = false, P_dn_valid = false;
   Timers tm;
@@ -124,6 +127,15 @@ struct qmc_walkers {
 };
 
 // Launch `expr` between the begin/end events of timer `id` (when timing is on).
+// hipError_t-returning variant for helpers
+#define TIMED_E(wk, id, st, expr)                                   \
+  do {                                                              \
+    hipError_t te_ = (wk)->tm.begin((id), (st));                    \
+    if (te_ == hipSuccess) te_ = (expr);                            \
+    if (te_ == hipSuccess) te_ = (wk)->tm.end((st));                \
+    if (te_ != hipSuccess) return te_;                              \
+  } while (0)
+
 #define TIMED(wk, id, st, expr, where)                    \
   do {                                                    \
     HIP_TRY((wk)->tm.begin((id), (st)), "timer begin");   \
@@ -301,7 +313,18 @@ extern "C" qmc_status qmc_walkers_create(qmc_system* sys, int32_t n_walkers, qmc
     al((void**)&d.prow, sizeof(int) * Wk * np);
     al((void**)&d.pivv, sizeof(double) * Wk * np);
   }
-  if (s.nu > kLuMaxN) al((void**)&d.smv, sizeof(double) * Wk * 2 * s.nu);
+  d.kb = wb_cap(s);
+  {
+    const size_t n = s.nu, kb = d.kb;
+    al((void**)&d.wm, sizeof(int) * Wk);
+    al((void**)&d.wv, sizeof(double) * Wk * kb * n);
+    al((void**)&d.wd, sizeof(double) * Wk * kb * n);
+    al((void**)&d.wS, sizeof(double) * Wk * kb * kb);
+    al((void**)&d.cvec, sizeof(double) * Wk * n);
+    al((void**)&d.v0, sizeof(double) * Wk * n);
+    al((void**)&d.tz, sizeof(double) * Wk * 2 * kb);
+    al((void**)&wk->rd_scratch, sizeof(double) * Wk * kb * n);
+  }
   if (e != hipSuccess) {
     delete wk;
     return e == hipErrorOutOfMemory ? fail(QMC_ERR_OOM, "device allocation failed") : hip_fail(e, "walkers_create");
@@ -359,6 +382,8 @@ extern "C" qmc_status qmc_eval_batch(qmc_system* sys, qmc_walkers* wk, const dou
   wk->generation = sys->generation;
   wk->P_up_valid = wk->P_dn_valid = true;
   wk->attempts = 0;
+  wk->since = 0;
+  wk->buf_spin = -1;
   wk->pending_e = -1;
   return QMC_OK;
 }
@@ -377,6 +402,8 @@ static qmc_status ensure_P(qmc_walkers* wk, int e, hipStream_t stream) {
   return QMC_OK;
 }
 
+static qmc_status before_propose(qmc_walkers* wk, int e, hipStream_t stream);
+
 extern "C" qmc_status qmc_propose_move(qmc_system* sys, qmc_walkers* wk, int32_t electron,
                                        const double* r_new, double* ratio, double* drift_new,
                                        hipStream_t stream) {
@@ -387,6 +414,9 @@ extern "C" qmc_status qmc_propose_move(qmc_system* sys, qmc_walkers* wk, int32_t
   if (wk->generation != sys->generation) return fail(QMC_ERR_STATE, "parameters changed since the last eval_batch");
   if (electron < 0 || electron >= s.N) return fail(QMC_ERR_ARG, "electron index out of range");
   if (!r_new) return fail(QMC_ERR_ARG, "null r_new");
+  // (a pending proposal is simply replaced)
+  c = before_propose(wk, electron, stream);
+  if (c) return c;
   c = ensure_P(wk, electron, stream);
   if (c) return c;
   TIMED(wk, QMC_T_PROPOSE_PREP, stream,
@@ -397,15 +427,54 @@ extern "C" qmc_status qmc_propose_move(qmc_system* sys, qmc_walkers* wk, int32_t
   return QMC_OK;
 }
 
+// Refresh schedule (the same for one system and for a multi-system member):
+// the delayed-update buffer holds moves of one spin and at most wb_cap(s)
+// moves, so a proposal of the other spin refreshes first, and the move that
+// fills the buffer refreshes after its accept.  A refresh is the FP64 inverse
+// of the maintained W, which also resets log|Psi| and the sign.
+struct Sched {
+  long attempts;
+  int since, buf_spin;
+};
+static bool sched_before(const SysDev& s, Sched& q, int e) {   // true: refresh before proposing e
+  const int spin = e < s.nu ? 0 : 1;
+  const bool pre = q.since > 0 && spin != q.buf_spin;
+  if (pre) q.since = 0;
+  q.buf_spin = spin;
+  return pre;
+}
+static bool sched_after(const SysDev& s, Sched& q) {           // true: refresh after this accept
+  q.attempts += 1;
+  q.since += 1;
+  if (q.since < wb_cap(s)) return false;
+  q.since = 0;
+  return true;
+}
+
+static hipError_t refresh(const SysDev& s, qmc_walkers* wk, int32_t* status, hipStream_t stream) {
+  TIMED_E(wk, QMC_T_LU, stream, launch_lu_inverse(s, wk->d, stream));
+  TIMED_E(wk, QMC_T_OTHER, stream, launch_refresh_finish(s, wk->d, status, stream));
+  return hipSuccess;
+}
+
+static qmc_status before_propose(qmc_walkers* wk, int e, hipStream_t stream) {
+  const SysDev& s = wk->sys->d;
+  Sched q{wk->attempts, wk->since, wk->buf_spin};
+  if (sched_before(s, q, e)) HIP_TRY(refresh(s, wk, nullptr, stream), "spin-switch refresh");
+  wk->since = q.since;
+  wk->buf_spin = q.buf_spin;
+  return QMC_OK;
+}
+
 static qmc_status after_accept(qmc_walkers* wk, int e, int32_t* status, hipStream_t stream) {
   const SysDev& s = wk->sys->d;
   if (e < s.nu) wk->P_up_valid = false; else wk->P_dn_valid = false;
   wk->pending_e = -1;
-  wk->attempts += 1;
-  if (wk->attempts % s.refresh_every == 0) {
-    TIMED(wk, QMC_T_LU, stream, launch_lu_inverse(s, wk->d, stream), "refresh LU");
-    TIMED(wk, QMC_T_OTHER, stream, launch_refresh_finish(s, wk->d, status, stream), "refresh finish");
-  }
+  Sched q{wk->attempts, wk->since, wk->buf_spin};
+  const bool post = sched_after(s, q);
+  wk->attempts = q.attempts;
+  wk->since = q.since;
+  if (post) HIP_TRY(refresh(s, wk, status, stream), "refresh");
   return QMC_OK;
 }
 
@@ -433,6 +502,8 @@ extern "C" qmc_status qmc_vmc_steps(qmc_system* sys, qmc_walkers* wk, int32_t e_
   const long Wk = wk->d.Wk;
   for (int t = 0; t < n_steps; ++t) {
     const int e = (int)((e_start + (long)t) % s.N);
+    c = before_propose(wk, e, stream);
+    if (c) return c;
     c = ensure_P(wk, e, stream);
     if (c) return c;
     TIMED(wk, QMC_T_PROPOSE_PREP, stream,
@@ -459,7 +530,9 @@ extern "C" qmc_status qmc_walkers_read(qmc_walkers* wk, int32_t item, double* ds
     case QMC_STATE_LOGABS: src = d.logabs; bytes = sizeof(double) * Wk; break;
     case QMC_STATE_SIGN: src = d.sign; bytes = sizeof(double) * Wk; break;
     case QMC_STATE_W: src = d.W; bytes = sizeof(double) * Wk * s.nu * s.nd; break;
-    case QMC_STATE_AINV: src = d.A; bytes = sizeof(double) * Wk * s.nd * s.nu; break;
+    case QMC_STATE_AINV:   // A0 combined with the delayed updates
+      HIP_TRY(launch_materialize_inverse(s, d, wk->buf_spin == 1, wk->rd_scratch, dst, stream), "read inverse");
+      return QMC_OK;
     case QMC_STATE_PHI:
       HIP_TRY(launch_export_phi(s, d, dst, stream), "export phi");
       return QMC_OK;
@@ -589,11 +662,7 @@ struct qmc_multi {
   int4* d_rows_items = nullptr;
   int n_rows_items = 0, rows_cap = 0;
   int grid_rows = 2048, grid_items = 1024;
-  int nc = 1, qmax = 4;
-  // accept phase: one persistent launch per register class (slice length) so
-  // that small members do not run with the largest member's register budget
-  struct AccClass { int qm; int2* items; int n; int grid; unsigned members; };
-  std::vector<AccClass> acc;
+  int nc = 1;
   int store = 0;        // 0 FP64, 1 FP32, 2 BF16 rows
   hipStream_t own = nullptr;
   hipEvent_t ev_a = nullptr, ev_b = nullptr;
@@ -658,17 +727,10 @@ extern "C" qmc_status qmc_multi_create(int32_t n_members, qmc_system* const* sys
   });
   const int vec = 64 * (m->store == 0 ? 2 : (m->store == 1 ? 4 : 8));
   std::vector<int2> items;
-  std::vector<std::vector<int2>> cls(5);   // slice classes 4, 8, 16, 32, 64
   for (int k : m->order) {
     const SysDev& s = m->h_sys[k];
     m->nc = std::max(m->nc, (s.Lp + vec - 1) / vec);
-    const int G = 256 / s.nu, Q = (s.nu + G - 1) / G;
-    m->qmax = std::max(m->qmax, Q);
-    const int c = Q <= 4 ? 0 : (Q <= 8 ? 1 : (Q <= 16 ? 2 : (Q <= 32 ? 3 : 4)));
-    for (int w = 0; w < m->h_wk[k].Wk; ++w) {
-      items.push_back(make_int2(k, w));
-      cls[c].push_back(make_int2(k, w));
-    }
+    for (int w = 0; w < m->h_wk[k].Wk; ++w) items.push_back(make_int2(k, w));
   }
   if (m->nc > 8) { delete m; return fail(QMC_ERR_UNSUPPORTED, "members need L <= 1024 (FP64) or 2048 (FP32)"); }
   m->n_items = (int)items.size();
@@ -687,15 +749,6 @@ extern "C" qmc_status qmc_multi_create(int32_t n_members, qmc_system* const* sys
   al((void**)&m->d_unif, sizeof(double*) * n_members);
   al((void**)&m->d_items, sizeof(int2) * items.size());
   if (!e) e = hipMemcpy(m->d_items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice);
-  for (int c = 0; c < 5 && !e; ++c) {
-    if (cls[c].empty()) continue;
-    unsigned members = 0;
-    for (const int2& it : cls[c]) members |= 1u << it.x;
-    qmc_multi::AccClass ac{4 << c, nullptr, (int)cls[c].size(), std::min((int)cls[c].size(), 2048), members};
-    al((void**)&ac.items, sizeof(int2) * cls[c].size());
-    if (!e) e = hipMemcpy(ac.items, cls[c].data(), sizeof(int2) * cls[c].size(), hipMemcpyHostToDevice);
-    m->acc.push_back(ac);
-  }
   if (!e) e = hipMemcpy(m->d_wk, m->h_wk.data(), sizeof(WalkDev) * n_members, hipMemcpyHostToDevice);
   if (!e) e = multi_build_rows(m);
   if (!e) e = hipStreamCreateWithFlags(&m->own, hipStreamNonBlocking);
@@ -730,43 +783,59 @@ static hipError_t multi_upload(qmc_multi* m) {
 // Enqueue n_steps steps on the group's stream; P validity of the members is
 // simulated in up/dn (and returned), so a captured graph and a direct run
 // follow the same schedule.
+// Per-member schedule state carried through a call (and into the captured graph).
+struct MemberState {
+  Sched q;
+  char up_ok, dn_ok;   // P halves valid
+};
+
+// One member's host-side plan for its next step: electron, P half to rebuild
+// (0 none, 1 up, 2 down), refreshes before the proposal and after the accept.
+// The same rules as the one-system path (sched_before / ensure_P / sched_after).
+static void plan_member(const SysDev& s, MemberState& st, int& pbuild, bool& pre, bool& post) {
+  const int e = (int)(st.q.attempts % s.N);
+  pre = sched_before(s, st.q, e);
+  pbuild = 0;
+  if (e < s.nu && !st.dn_ok) { pbuild = 2; st.dn_ok = 1; }
+  else if (e >= s.nu && !st.up_ok) { pbuild = 1; st.up_ok = 1; }
+  if (e < s.nu) st.up_ok = 0; else st.dn_ok = 0;
+  post = sched_after(s, st.q);
+}
+
+static hipError_t multi_refresh(qmc_multi* m, unsigned mask) {
+  for (int k = 0; k < m->n; ++k) {
+    if (!((mask >> k) & 1u)) continue;
+    hipError_t r = launch_lu_inverse(m->h_sys[k], m->h_wk[k], m->own);
+    if (r == hipSuccess) r = launch_refresh_finish(m->h_sys[k], m->h_wk[k], nullptr, m->own);
+    if (r != hipSuccess) return r;
+  }
+  return hipSuccess;
+}
+
 static hipError_t multi_enqueue(qmc_multi* m, int n_steps, bool explicit_draws, unsigned long long seed,
-                                double sigma, std::vector<char>& up_ok, std::vector<char>& dn_ok) {
+                                double sigma, std::vector<MemberState>& st) {
   MultiArgs a{m->d_sys, m->d_wk, m->d_steps, m->d_rows, explicit_draws ? m->d_disp : nullptr,
               explicit_draws ? m->d_unif : nullptr, 0, seed, sigma};
   for (int t = 0; t < n_steps; ++t) {
     a.t = t;
-    unsigned mask = 0, up_mask = 0;
+    unsigned pre_mask = 0, post_mask = 0;
     for (int k = 0; k < m->n; ++k) {
-      const SysDev& s = m->h_sys[k];
-      const long att = m->wk[k]->attempts + t;
-      const int e = (int)(att % s.N);
-      if (e < s.nu) up_mask |= 1u << k;
-      if (e < s.nu && !dn_ok[k]) {
-        hipError_t r = launch_P_build(s, m->h_wk[k], 2, m->own);
+      int pb;
+      bool pre, post;
+      plan_member(m->h_sys[k], st[k], pb, pre, post);
+      if (pb) {
+        hipError_t r = launch_P_build(m->h_sys[k], m->h_wk[k], pb, m->own);
         if (r != hipSuccess) return r;
-        dn_ok[k] = 1;
-      } else if (e >= s.nu && !up_ok[k]) {
-        hipError_t r = launch_P_build(s, m->h_wk[k], 1, m->own);
-        if (r != hipSuccess) return r;
-        up_ok[k] = 1;
       }
-      if (e < s.nu) up_ok[k] = 0; else dn_ok[k] = 0;
-      if ((att + 1) % s.refresh_every == 0) mask |= 1u << k;
+      if (pre) pre_mask |= 1u << k;
+      if (post) post_mask |= 1u << k;
     }
-    hipError_t r = launch_multi_prep(a, m->d_items, m->n_items, m->grid_items, m->own);
+    // refreshes: the one-system LU per member, so results match a lone run bitwise
+    hipError_t r = multi_refresh(m, pre_mask);
+    if (r == hipSuccess) r = launch_multi_prep(a, m->d_items, m->n_items, m->grid_items, m->own);
     if (r == hipSuccess) r = launch_multi_rows(a, m->store, m->nc, m->d_rows_items, m->n_rows_items, m->grid_rows, m->own);
-    for (const auto& ac : m->acc) {
-      const unsigned mu = ac.members & up_mask, md = ac.members & ~up_mask;
-      if (r == hipSuccess && mu) r = launch_multi_accept(a, m->store, ac.qm, true, mu, ac.items, ac.n, ac.grid, m->own);
-      if (r == hipSuccess && md) r = launch_multi_accept(a, m->store, ac.qm, false, md, ac.items, ac.n, ac.grid, m->own);
-    }
-    // refresh: the one-system LU per member, so results match a lone run bitwise
-    for (int k = 0; k < m->n && r == hipSuccess; ++k) {
-      if (!((mask >> k) & 1u)) continue;
-      r = launch_lu_inverse(m->h_sys[k], m->h_wk[k], m->own);
-      if (r == hipSuccess) r = launch_refresh_finish(m->h_sys[k], m->h_wk[k], nullptr, m->own);
-    }
+    if (r == hipSuccess) r = launch_multi_accept(a, m->store, m->d_items, m->n_items, m->grid_items, m->own);
+    if (r == hipSuccess) r = multi_refresh(m, post_mask);
     if (r == hipSuccess) r = launch_multi_advance(m->d_steps, m->n, m->own);
     if (r != hipSuccess) return r;
   }
@@ -798,24 +867,28 @@ extern "C" qmc_status qmc_multi_vmc_steps(qmc_multi* m, int32_t n_steps, const d
     HIP_TRY(hipMemcpyAsync(m->d_disp, m->h_disp.data(), sizeof(double*) * m->n, hipMemcpyHostToDevice, m->own), "ptrs");
     HIP_TRY(hipMemcpyAsync(m->d_unif, m->h_unif.data(), sizeof(double*) * m->n, hipMemcpyHostToDevice, m->own), "ptrs");
   }
-  std::vector<char> up_ok(m->n), dn_ok(m->n);
-  for (int k = 0; k < m->n; ++k) { up_ok[k] = m->wk[k]->P_up_valid; dn_ok[k] = m->wk[k]->P_dn_valid; }
+  std::vector<MemberState> st(m->n);
+  for (int k = 0; k < m->n; ++k) {
+    const qmc_walkers* w = m->wk[k];
+    st[k] = MemberState{Sched{w->attempts, w->since, w->buf_spin}, (char)w->P_up_valid, (char)w->P_dn_valid};
+  }
   if (use_graph) {
+    // the captured schedule is determined by each member's electron phase,
+    // refresh state and valid P halves
     std::string key = std::to_string(n_steps) + ":" + std::to_string(seed) + ":" + std::to_string(sigma) + ":" +
                       std::to_string(m->grid_rows);
     for (int k = 0; k < m->n; ++k) {
       const SysDev& s = m->h_sys[k];
-      // the per-step schedule (electron, refresh) repeats with period lcm(N, refresh_every)
-      const long period = (long)s.N / std::gcd((long)s.N, (long)s.refresh_every) * s.refresh_every;
-      key += ":" + std::to_string(m->wk[k]->attempts % period) + "," +
-             std::to_string((int)up_ok[k]) + std::to_string((int)dn_ok[k]) + "," + std::to_string(m->rows[k]);
+      key += ":" + std::to_string(st[k].q.attempts % s.N) + "," + std::to_string(st[k].q.since) + "," +
+             std::to_string(st[k].q.buf_spin) + "," + std::to_string((int)st[k].up_ok) +
+             std::to_string((int)st[k].dn_ok) + "," + std::to_string(m->rows[k]);
     }
-    std::vector<char> up2 = up_ok, dn2 = dn_ok;
+    std::vector<MemberState> st2 = st;
     if (!m->gexec || key != m->gkey) {
       if (m->gexec) { (void)hipGraphExecDestroy(m->gexec); m->gexec = nullptr; }
       hipGraph_t g = nullptr;
       HIP_TRY(hipStreamBeginCapture(m->own, hipStreamCaptureModeThreadLocal), "begin capture");
-      hipError_t r = multi_enqueue(m, n_steps, false, seed, sigma, up2, dn2);
+      hipError_t r = multi_enqueue(m, n_steps, false, seed, sigma, st2);
       hipError_t r2 = hipStreamEndCapture(m->own, &g);
       if (r != hipSuccess) { if (g) (void)hipGraphDestroy(g); return hip_fail(r, "capture"); }
       HIP_TRY(r2, "end capture");
@@ -824,26 +897,26 @@ extern "C" qmc_status qmc_multi_vmc_steps(qmc_multi* m, int32_t n_steps, const d
       HIP_TRY(r, "instantiate");
       m->gkey = key;
     } else {
-      // replay: the schedule is the captured one; advance the simulated flags the same way
-      std::vector<char> u3 = up_ok, d3 = dn_ok;
+      // replay: the schedule is the captured one; advance the host state the same way
       for (int t = 0; t < n_steps; ++t)
         for (int k = 0; k < m->n; ++k) {
-          const SysDev& s = m->h_sys[k];
-          const int e = (int)((m->wk[k]->attempts + t) % s.N);
-          if (e < s.nu && !d3[k]) d3[k] = 1; else if (e >= s.nu && !u3[k]) u3[k] = 1;
-          if (e < s.nu) u3[k] = 0; else d3[k] = 0;
+          int pb;
+          bool pre, post;
+          plan_member(m->h_sys[k], st2[k], pb, pre, post);
         }
-      up2 = u3; dn2 = d3;
     }
     HIP_TRY(hipGraphLaunch(m->gexec, m->own), "graph launch");
-    up_ok = up2; dn_ok = dn2;
+    st = st2;
   } else {
-    HIP_TRY(multi_enqueue(m, n_steps, expl, seed, sigma, up_ok, dn_ok), "multi steps");
+    HIP_TRY(multi_enqueue(m, n_steps, expl, seed, sigma, st), "multi steps");
   }
   for (int k = 0; k < m->n; ++k) {
-    m->wk[k]->attempts += n_steps;
-    m->wk[k]->P_up_valid = up_ok[k];
-    m->wk[k]->P_dn_valid = dn_ok[k];
+    qmc_walkers* w = m->wk[k];
+    w->attempts = st[k].q.attempts;
+    w->since = st[k].q.since;
+    w->buf_spin = st[k].q.buf_spin;
+    w->P_up_valid = st[k].up_ok;
+    w->P_dn_valid = st[k].dn_ok;
   }
   HIP_TRY(hipEventRecord(m->ev_b, m->own), "event");
   HIP_TRY(hipStreamWaitEvent(stream, m->ev_b, 0), "wait");
