@@ -3,7 +3,8 @@
 One step = one from-scratch evaluation of every walker (basis -> P = Phi Lambda
 -> W -> FP64 LU/inverse -> cofactor products -> local energy) followed by one
 sweep of single-electron Metropolis moves (every electron once, device-side
-accept, FP64 Sherman-Morrison updates, LU refresh every 32 attempted moves).
+accept, FP64 delayed low-rank updates of W^{-1}, FP64 refresh after 32 moves of
+one spin and at each change of spin).
 Workload: 40 nuclei, 160 electrons (80/80), 600 Gaussian basis functions,
 1024 walkers (synthetic, seeded).
 
@@ -101,16 +102,26 @@ def kernel_models(s, Wk, esz, acc_rate):
     """Algorithmic bytes / flops per launch of the main kernels.
 
     propose (the streaming kernel): every walker reads the N_other x L rows of P
-             of the opposite spin (esz bytes each), psi(r') (8 L), the matching
-             W^{-1} column (8 N_other), and writes the new W row (8 N_other).
-    accept:  an accepted walker reads and writes W^{-1} (2 x 8 n^2), reads the new
-             row and basis values (8 (N_other + L)), writes the W row (8 N_other)
-             and the basis row (esz L); rejected walkers move no data.
+             of the opposite spin (esz bytes each), psi(r') (8 L), the current
+             W^{-1} column / row of the moved electron (8 N_other, assembled by the
+             set-up kernel), and writes the new W row (8 N_other).
+    accept:  an accepted walker with m buffered moves reads the new W row, the
+             old one, v0 and the m buffered vectors v_j (8 n (3 + m)), S^{-1} and
+             t, z (8 m^2 + 16 m), psi(r') (8 L); it writes d and v (16 n), the
+             bordered S^{-1} (8 (m+1)^2), the W row (8 n) and the basis row
+             (esz L); rejected walkers move no data.  m is averaged over a sweep:
+             the buffer restarts at every refresh (after min(refresh_every, 64)
+             moves of one spin and at each change of spin) and grows by the
+             acceptance rate per move.
     P_build: 2 L^2 flops per basis row, over the Wk * N/2 rows of one spin.
     """
     L, N, n = s.n_basis, s.n_up + s.n_dn, s.n_up
+    cap = min(s.refresh_every, 64)
+    cycles = [cap] * (n // cap) + ([n % cap] if n % cap else [])
+    m = acc_rate * sum(c * (c - 1) / 2 for c in cycles) / n
     prop = Wk * (esz * n * L + 8 * L + 8 * n + 8 * n)
-    acc = Wk * acc_rate * (16 * n * n + 8 * (n + L) + 8 * n + esz * L)
+    acc = Wk * acc_rate * (8 * n * (3 + m) + 8 * m * m + 16 * m + 8 * L
+                           + 16 * n + 8 * (m + 1) ** 2 + 8 * n + esz * L)
     pflops = 2.0 * L * L * Wk * n
     return {"propose": ("hbm", prop), "accept": ("hbm", acc), "P_build": ("mfma", pflops)}
 
@@ -310,9 +321,9 @@ def multi_leg(P, C, precision="fp32", replays=3):
 
 def large_leg(P, C, steps=128, Wk=256):
     """The 1024-electron workload (256 nuclei, L = 4096, Lambda banded at 8
-    bohr; n = 512 per spin, so the blocked Gauss-Jordan refresh and the
-    two-pass Sherman-Morrison update), 256 walkers, FP64: one evaluation and
-    `steps` Metropolis moves (refresh every 64); error of the evaluation against
+    bohr; n = 512 per spin, so the blocked Gauss-Jordan refresh), 256 walkers,
+    FP64: one evaluation and `steps` Metropolis moves (refresh after 64 moves
+    of one spin); error of the evaluation against
     the oracle on one walker."""
     from oracle import jagp as O
     dev = torch.device("cuda:0")

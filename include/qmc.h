@@ -55,8 +55,8 @@ typedef enum {
 } qmc_status;
 
 /* Arithmetic of the geminal products (W build, move rows) and of the stored
- * basis matrices.  LU, inverse, Sherman-Morrison updates and ratio
- * accumulation are FP64 in every mode. */
+ * basis matrices.  LU, inverse, inverse updates and ratio accumulation are
+ * FP64 in every mode. */
 typedef enum {
   QMC_FP64 = 0,    /* everything FP64                                           */
   QMC_W_FP32 = 1,  /* Phi, P = Phi Lambda and the W products in FP32 on MFMA
@@ -97,8 +97,9 @@ typedef struct {
   int32_t n_j2;               /* 2 for form 1, 8 for form 2                      */
   const double *j2;           /* [n_j2]                                          */
   int32_t precision;          /* qmc_precision                                   */
-  int32_t refresh_every;      /* recompute W^{-1} by LU every this many
-                                 attempted moves (>= 1)                          */
+  int32_t refresh_every;      /* recompute W^{-1} from W after this many
+                                 attempted moves of one spin (>= 1; at most 64
+                                 are buffered, see qmc_accept_move)              */
 } qmc_system_desc;
 
 /* Version of this header the library was built from (QMC_ABI_VERSION). */
@@ -158,9 +159,14 @@ qmc_status qmc_propose_move(qmc_system *sys, qmc_walkers *wk, int32_t electron,
                             hipStream_t stream);
 
 /* Accept (accept[w] != 0) or reject the pending proposal of `electron` for
- * every walker: on accept, Sherman-Morrison rank-1 update of W^{-1} (FP64),
- * new row/column of W, new basis row and position.  Every refresh_every
- * attempted moves W^{-1} and log|det W| are recomputed by FP64 LU.
+ * every walker: on accept, new row/column of W, new basis row and position,
+ * and a rank-1 update of W^{-1} (FP64) held in delayed form: the inverse of the
+ * last refresh A0 plus buffers V, D and S^{-1} of the moves since, with
+ * W^{-1} = A0 - V S^{-1} D^T A0 (up moves; transposed for down moves), equal
+ * to successive Sherman-Morrison updates (McDaniel et al., J. Chem. Phys. 147,
+ * 174107, 2017).  After min(refresh_every, 64) attempted moves of one spin,
+ * and before proposing an electron of the other spin while moves are
+ * buffered, W^{-1} and log|det W| are recomputed from W by FP64 elimination.
  * QMC_ERR_STATE if no proposal of this electron is pending.
  *   accept [Wk] device, read (uint8)
  *   status [Wk] device, write, may be NULL (1 when a refresh finds det = 0) */
@@ -246,7 +252,8 @@ typedef enum {
   QMC_STATE_LOGABS = 1,  /* [Wk]         FP64 log|Psi| tracked through moves     */
   QMC_STATE_SIGN = 2,    /* [Wk]         FP64 sign(Psi)                          */
   QMC_STATE_W = 3,       /* [Wk][n_up][n_dn] FP64 geminal matrix                 */
-  QMC_STATE_AINV = 4,    /* [Wk][n_dn][n_up] FP64 W^{-1}                         */
+  QMC_STATE_AINV = 4,    /* [Wk][n_dn][n_up] FP64 W^{-1} (assembled from the
+                            delayed form; uses the walkers' own work arrays)  */
   QMC_STATE_PHI = 5      /* [Wk][N][L]   FP64 basis values psi_mu(r_i)           */
 } qmc_state_item;
 
@@ -267,7 +274,7 @@ typedef enum {
   QMC_T_ASSEMBLE = 6,  /* Jastrow, Coulomb, local-energy assembly         */
   QMC_T_PROPOSE = 7,   /* proposal, streaming part: new W row/column and
                           the partial determinant ratios                  */
-  QMC_T_ACCEPT = 8,    /* Metropolis decision + Sherman-Morrison update  */
+  QMC_T_ACCEPT = 8,    /* Metropolis decision + delayed inverse update   */
   QMC_T_OTHER = 9,     /* small bookkeeping kernels                      */
   QMC_T_PROPOSE_PREP = 10, /* proposal, per-walker part: psi(r'), Jastrow
                               change                                      */

@@ -1,13 +1,13 @@
 """Systems beyond the register inverse (n > 96): the blocked Gauss-Jordan
-refresh, for n > 128 the two-pass Sherman-Morrison update and, for the
-1024-electron workload (256 nuclei, L = 4096, Lambda banded at 8 bohr), the P
-products that skip Lambda's zero tiles.
+refresh, delayed updates of n = 512 inverses and, for the 1024-electron
+workload (256 nuclei, L = 4096, Lambda banded at 8 bohr), the P products that
+skip Lambda's zero tiles.
 
 * Evaluation against the oracle at the FP64 bar (relative 1e-10 on log|Psi| and
   E_loc, 1e-8 on the drift).
 * Move ratios of an up and a down electron against the oracle's ratio of full
   determinants, and the updated inverse against the inverse of the updated W.
-* 70 Metropolis steps (one refresh at 64): the tracked log|Psi| and inverse
+* 70 Metropolis steps (a refresh after 64 moves of one spin): the tracked log|Psi| and inverse
   equal those of a fresh evaluation at the final positions.
 * n = 112, 128, 150 (the blocked elimination runs for n > 96; 112 and 150 are
   not multiples of the 64-wide panel): identity padding.

@@ -2,7 +2,7 @@
 
 QMC_W_FP32: basis matrix, P = Phi Lambda and the W products in FP32 on MFMA
 with FP32 accumulation; LU, inverse, cofactor products, ratios and
-Sherman-Morrison updates in FP64.  Checked against a forward-error bound (must
+inverse updates in FP64.  Checked against a forward-error bound (must
 hold).  With u = 2^-24 and gamma = (2L + 4) u (rounding of Phi and Lambda to
 FP32, the length-L FP32 accumulation of P and its FP32 storage; the W product
 itself accumulates in FP64 and is covered with room to spare), every geminal

@@ -90,10 +90,11 @@ def test_chain_tiny_1000_moves_matches_oracle():
 
 
 def test_chain_refresh_schedules():
-    # The refresh re-derives W^{-1} and log|det W| from W by LU; it never changes
-    # accept decisions here.  With refreshes every 1 or 32 moves the tracked
-    # log|Psi| meets the 1e-10 bar; with none in 200 moves the Sherman-Morrison
-    # drift is visible but bounded.
+    # The refresh re-derives W^{-1} and log|det W| from W by Gauss-Jordan; it
+    # never changes accept decisions here.  With refreshes every 1 or 32 moves
+    # the tracked log|Psi| meets the 1e-10 bar; with refresh_every = 1000 only
+    # the changes of spin refresh (every 5 moves here) and the accumulated
+    # log|R| is held to a looser bound.
     P = need_gpu()
     w = C.tiny_3nuc_10e(n_walkers=16, n_steps=200)
     disp = torch.tensor(w.disp)
