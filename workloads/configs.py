@@ -302,6 +302,21 @@ def chain_arrays(seed: int, n_steps: int, n_walkers: int, sigma: float = 0.3):
     return _chain_arrays(np.random.default_rng(seed), n_steps, n_walkers, sigma)
 
 
+# Lattice-regularised DMC settings of the synthetic runs: single grid with
+# hop length 0.2 bohr, and a double grid with 0.1 bohr hops within one
+# Thomas-Fermi length of a nucleus and 0.4 bohr hops elsewhere; fixed-node
+# gamma 0 and 0.5; projection time 0.05 Ha^-1 between branchings.
+LRDMC_SINGLE = dict(a=0.2, a_valence=0.0, tf_scale=1.0, gamma=0.0)
+LRDMC_DOUBLE = dict(a=0.1, a_valence=0.4, tf_scale=1.0, gamma=0.5)
+LRDMC_TAU = 0.05
+
+
+def lrdmc_draws(seed: int, n_steps: int, n_walkers: int):
+    """Uniforms in [0, 1) [n_steps, Wk, 2] for the continuous-time LRDMC step
+    (time spent in the configuration, then the hop)."""
+    return np.random.default_rng(seed).random((n_steps, n_walkers, 2))
+
+
 def random_positions(seed: int, sysd: System, n_walkers: int, spread=1.0):
     """Fresh walker positions for sysd drawn like the initial ones."""
     rng = np.random.default_rng(seed)
