@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define QMC_ABI_VERSION 1
+#define QMC_ABI_VERSION 2
 
 typedef enum {
   QMC_OK = 0,
@@ -246,6 +246,80 @@ qmc_status qmc_multi_vmc_steps(qmc_multi *m, int32_t n_steps, const double *cons
 qmc_status qmc_philox_draws(uint64_t seed, int32_t member, int32_t n_walkers, uint64_t step, double sigma,
                             double *disp, double *unif, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Lattice-regularised diffusion Monte Carlo (Lattice regularized Monte Carlo
+ * section), with Psi as the guiding function.
+ *
+ * The lattice kinetic term connects a configuration x with the 6N
+ * configurations x' in which one electron i hops by +-a_i along x, y or z, with
+ * matrix element -1/(2 a_i^2).  The potential becomes V^a = V +
+ * 1/2 sum_i (Delta^a_i - Delta_i) Psi / Psi (lrdmc_potential).  The fixed-node
+ * Hamiltonian H^{FN,gamma} adds (1 + gamma) V_sf to the diagonal, V_sf being
+ * the sum over hops with Psi(x')/Psi(x) < 0 of |ratio| / (2 a_i^2), and
+ * multiplies those hops' elements by -gamma.  The importance-sampled
+ * fixed-node Green's function has off-diagonal elements
+ * G_{x',x} = ratio / (2 a_i^2) (ratio > 0) or gamma |ratio| / (2 a_i^2)
+ * (ratio < 0) (is-green-function); their sum is the rate of leaving x.
+ * Hop order (ratios, hop indices): electron-major, then +x, -x, +y, -y, +z, -z.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  double a;          /* hop length in bohr (> 0); with a double grid, the
+                        length near nuclei                                    */
+  double a_valence;  /* > 0: double grid (a reading of the section's double-
+                        grid scheme): electrons farther than tf_scale Thomas-
+                        Fermi lengths 0.8853 Z^{-1/3} bohr from every nucleus
+                        hop by a_valence; <= 0: a everywhere                  */
+  double tf_scale;   /* see a_valence (> 0 when a double grid is used)       */
+  double gamma;      /* fixed-node spin-flip parameter (>= 0)                 */
+} qmc_lrdmc_params;
+
+/* Per-walker terms written by qmc_lrdmc_hops ([Wk][QMC_LR_NTERMS]). */
+typedef enum {
+  QMC_LR_ELOC = 0,      /* e_L(x) of the last evaluation; equal to the fixed-
+                           node lattice local energy sum_x' H^FN_{x',x} Psi(x')/
+                           Psi(x) for every gamma (lrdmc_mod_local_energy)   */
+  QMC_LR_EKIN = 1,      /* E_kin of the last evaluation                       */
+  QMC_LR_LAP_A = 2,     /* sum_i Delta^{a_i}_i Psi / Psi                      */
+  QMC_LR_VA_SHIFT = 3,  /* V^a - V                                            */
+  QMC_LR_VSF = 4,       /* spin-flip term V_sf                                */
+  QMC_LR_ESCAPE = 5,    /* sum of the off-diagonal Green's function elements  */
+  QMC_LR_HFN_DIAG = 6,  /* H^{FN,gamma}_{x,x}; the discrete-time diagonal
+                           element is lambda minus this, and the column sum
+                           b_x = lambda - e_L (lrdmc_mod_weight)              */
+  QMC_LR_NTERMS = 7
+} qmc_lrdmc_term;
+
+/* Ratios of the 6N lattice hops of every walker and the terms above.  The
+ * determinant ratio of a hop of electron i is psi(r')^T y_i with the cofactor
+ * row y_i of the last qmc_eval_batch (one row or column of W changes), times
+ * exp of the Jastrow change; no inverse is updated.  Needs qmc_eval_batch since
+ * the last move of these walkers (QMC_ERR_STATE otherwise); the values of
+ * walkers whose status was not 0 are undefined.
+ *   params  host pointer
+ *   ratios  [Wk][N][6] device, write, may be NULL: Psi(x')/Psi(x)
+ *   terms   [Wk][QMC_LR_NTERMS] device, write, may be NULL
+ * The walker set keeps both for qmc_lrdmc_advance. */
+qmc_status qmc_lrdmc_hops(qmc_system *sys, qmc_walkers *wk, const qmc_lrdmc_params *params,
+                          double *ratios, double *terms, hipStream_t stream);
+
+/* One continuous-time step of every walker from the last qmc_lrdmc_hops
+ * (treatment of diagonal moves in the Lattice regularized Monte Carlo
+ * section).  A walker with tau_left <= 0 or a singular last evaluation is left
+ * as it is.  Otherwise it stays in x for tau_xi = -log(1 - xi[w][0]) / escape;
+ * if tau_xi >= tau_left its weight is multiplied by exp(-tau_left e_L) and
+ * tau_left becomes 0 (no hop); else the weight is multiplied by
+ * exp(-tau_xi e_L), tau_left decreases by tau_xi and the walker makes the first
+ * hop in hop order whose running sum of Green's function elements exceeds
+ * xi[w][1] * escape.  The walkers' own state is not changed: evaluate r_next
+ * (qmc_eval_batch) before the next step.
+ *   xi       [Wk][2]    device, read: uniforms in [0, 1)
+ *   weight   [Wk]       device, read-write
+ *   tau_left [Wk]       device, read-write: projection time left
+ *   r_next   [Wk][N][3] device, write: positions after the step
+ *   hop      [Wk]       device, write, may be NULL: 6 i + direction, or -1 */
+qmc_status qmc_lrdmc_advance(qmc_system *sys, qmc_walkers *wk, const double *xi, double *weight,
+                             double *tau_left, double *r_next, int32_t *hop, hipStream_t stream);
+
 /* Items of the walker state that qmc_walkers_read can copy out. */
 typedef enum {
   QMC_STATE_R = 0,       /* [Wk][N][3]   FP64 positions                          */
@@ -278,7 +352,9 @@ typedef enum {
   QMC_T_OTHER = 9,     /* small bookkeeping kernels                      */
   QMC_T_PROPOSE_PREP = 10, /* proposal, per-walker part: psi(r'), Jastrow
                               change                                      */
-  QMC_TIMER_COUNT = 11
+  QMC_T_LRDMC_HOPS = 11,   /* lattice hop ratios and Green's function terms */
+  QMC_T_LRDMC_STEP = 12,   /* continuous-time lattice step                  */
+  QMC_TIMER_COUNT = 13
 } qmc_timer;
 
 /* enable != 0 turns timing on and clears the sums; 0 turns it off. */

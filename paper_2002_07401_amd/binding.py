@@ -33,10 +33,14 @@ FUNCTIONS = (
     "qmc_accept_move", "qmc_vmc_steps", "qmc_walkers_read", "qmc_walkers_set_timing",
     "qmc_walkers_timing", "qmc_forces", "qmc_system_set_params", "qmc_multi_create",
     "qmc_multi_destroy", "qmc_multi_autotune", "qmc_multi_vmc_steps", "qmc_philox_draws",
+    "qmc_lrdmc_hops", "qmc_lrdmc_advance",
 )
 
 TIMER_NAMES = ("basis", "P_build", "W_build", "LU", "Y_build", "rowdot", "assemble", "propose",
-               "accept", "other", "propose_prep")
+               "accept", "other", "propose_prep", "lrdmc_hops", "lrdmc_step")
+
+# per-walker terms of qmc_lrdmc_hops
+LR_TERMS = ("e_loc", "e_kin", "lap_a", "va_shift", "v_sf", "escape", "hfn_diag")
 
 
 class QMCError(RuntimeError):
@@ -48,6 +52,11 @@ class QMCError(RuntimeError):
 class Grads(ctypes.Structure):
     _fields_ = [("dR", ctypes.c_void_p), ("dzeta", ctypes.c_void_p), ("dlambda", ctypes.c_void_p),
                 ("djas", ctypes.c_void_p), ("dr", ctypes.c_void_p)]
+
+
+class LrdmcParams(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_double), ("a_valence", ctypes.c_double), ("tf_scale", ctypes.c_double),
+                ("gamma", ctypes.c_double)]
 
 
 class SystemDesc(ctypes.Structure):
@@ -97,6 +106,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.qmc_multi_vmc_steps.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_uint64,
                                         ctypes.c_double, i32, vp]
     lib.qmc_philox_draws.argtypes = [ctypes.c_uint64, i32, i32, ctypes.c_uint64, ctypes.c_double, dp, dp, vp]
+    lib.qmc_lrdmc_hops.argtypes = [vp, vp, ctypes.POINTER(LrdmcParams), dp, dp, vp]
+    lib.qmc_lrdmc_advance.argtypes = [vp, vp, dp, dp, dp, dp, vp, vp]
     _lib = lib
     return lib
 
@@ -254,6 +265,33 @@ class Walkers:
         _check(load().qmc_forces(S.h, self.h, _ptr(r), 1 if per_walker else 0, _ptr(gbar_logpsi),
                                  _ptr(gbar_eloc), ctypes.byref(g), _stream(stream)))
         return out
+
+    def lrdmc_hops(self, a: float, a_valence: float = 0.0, tf_scale: float = 1.0, gamma: float = 0.0,
+                   ratios: bool = True, stream=None) -> Dict[str, torch.Tensor]:
+        """Lattice hop ratios [Wk, N, 6] (if requested) and the per-walker terms,
+        as a dict keyed by LR_TERMS plus 'ratios' and 'terms' [Wk, 7]."""
+        Wk, N = self.n, self.sys.n_elec
+        f = lambda *sh: torch.empty(*sh, dtype=torch.float64, device="cuda")
+        rt = f(Wk, N, 6) if ratios else None
+        terms = f(Wk, len(LR_TERMS))
+        prm = LrdmcParams(a=a, a_valence=a_valence, tf_scale=tf_scale, gamma=gamma)
+        _check(load().qmc_lrdmc_hops(self.sys.h, self.h, ctypes.byref(prm), _ptr(rt), _ptr(terms),
+                                     _stream(stream)))
+        out = {k: terms[:, i] for i, k in enumerate(LR_TERMS)}
+        out["terms"] = terms
+        out["ratios"] = rt
+        return out
+
+    def lrdmc_advance(self, xi: torch.Tensor, weight: torch.Tensor, tau_left: torch.Tensor, stream=None):
+        """Continuous-time lattice step; weight and tau_left are updated in
+        place.  Returns (r_next [Wk, N, 3], hop [Wk])."""
+        Wk, N = self.n, self.sys.n_elec
+        assert xi.shape == (Wk, 2) and weight.shape == (Wk,) and tau_left.shape == (Wk,)
+        r_next = torch.empty(Wk, N, 3, dtype=torch.float64, device="cuda")
+        hop = torch.empty(Wk, dtype=torch.int32, device="cuda")
+        _check(load().qmc_lrdmc_advance(self.sys.h, self.h, _ptr(xi), _ptr(weight), _ptr(tau_left),
+                                        _ptr(r_next), _ptr(hop), _stream(stream)))
+        return r_next, hop
 
 
 class JAGPFunction(torch.autograd.Function):

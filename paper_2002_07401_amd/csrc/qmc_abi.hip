@@ -10,7 +10,7 @@
 #include <string>
 #include <vector>
 
-#include "internal.h"
+#include "lrdmc.h"
 
 using namespace qmc;
 
@@ -116,6 +116,11 @@ struct qmc_walkers {
   double* rd_scratch = nullptr;   // [Wk][kb][n] state read-out work
   bool evaluated = false;
   bool P_up_valid = false, P_dn_valid = false;
+  // lattice-regularised DMC: the cofactor rows Yt hold for the positions of
+  // the last evaluation until a move; hops computed for them (lr_ready)
+  LrdmcDev lr{};
+  LrdmcParams lr_p{};
+  bool yt_valid = false, lr_ready = false;
   Timers tm;
   AdjWork aw{};
   bool aw_ready = false;
@@ -325,6 +330,11 @@ extern "C" qmc_status qmc_walkers_create(qmc_system* sys, int32_t n_walkers, qmc
     al((void**)&d.tz, sizeof(double) * Wk * 2 * kb);
     al((void**)&wk->rd_scratch, sizeof(double) * Wk * kb * n);
   }
+  al((void**)&wk->lr.ratio, sizeof(double) * Wk * N * kHops);
+  al((void**)&wk->lr.ah, sizeof(double) * Wk * N);
+  al((void**)&wk->lr.terms, sizeof(double) * Wk * kLrTerms);
+  al((void**)&wk->lr.ekin, sizeof(double) * Wk);
+  al((void**)&wk->lr.eloc, sizeof(double) * Wk);
   if (e != hipSuccess) {
     delete wk;
     return e == hipErrorOutOfMemory ? fail(QMC_ERR_OOM, "device allocation failed") : hip_fail(e, "walkers_create");
@@ -376,9 +386,16 @@ extern "C" qmc_status qmc_eval_batch(qmc_system* sys, qmc_walkers* wk, const dou
     TIMED(wk, QMC_T_OTHER, stream, launch_downcast(d.P64, d.P, s.bf16(), cnt, stream), "P copy");
   }
   TIMED(wk, QMC_T_ROWDOT, stream, launch_rowdots(s, d, stream), "row dots");
+  // E_kin and E_loc stay with the walkers (the LRDMC step reads them)
   TIMED(wk, QMC_T_ASSEMBLE, stream,
-        launch_jastrow_assemble(s, d, logabs, sign, drift, e_kin, e_loc, status, stream), "assemble");
+        launch_jastrow_assemble(s, d, logabs, sign, drift, wk->lr.ekin, wk->lr.eloc, status, stream), "assemble");
+  if (e_kin)
+    HIP_TRY(hipMemcpyAsync(e_kin, wk->lr.ekin, sizeof(double) * d.Wk, hipMemcpyDeviceToDevice, stream), "e_kin");
+  if (e_loc)
+    HIP_TRY(hipMemcpyAsync(e_loc, wk->lr.eloc, sizeof(double) * d.Wk, hipMemcpyDeviceToDevice, stream), "e_loc");
   wk->evaluated = true;
+  wk->yt_valid = true;
+  wk->lr_ready = false;
   wk->generation = sys->generation;
   wk->P_up_valid = wk->P_dn_valid = true;
   wk->attempts = 0;
@@ -459,6 +476,7 @@ static hipError_t refresh(const SysDev& s, qmc_walkers* wk, int32_t* status, hip
 
 static qmc_status before_propose(qmc_walkers* wk, int e, hipStream_t stream) {
   const SysDev& s = wk->sys->d;
+  wk->yt_valid = wk->lr_ready = false;
   Sched q{wk->attempts, wk->since, wk->buf_spin};
   if (sched_before(s, q, e)) HIP_TRY(refresh(s, wk, nullptr, stream), "spin-switch refresh");
   wk->since = q.since;
@@ -612,6 +630,52 @@ extern "C" qmc_status qmc_forces(qmc_system* sys, qmc_walkers* wk, const double*
   if (c) return c;
   HIP_TRY(launch_forces(s, wk->d, wk->aw, gbar_logpsi, gbar_eloc, per_walker, out->dR, out->dzeta,
                         out->dlambda, out->djas, out->dr, stream), "forces");
+  return QMC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// lattice-regularised diffusion Monte Carlo
+// ---------------------------------------------------------------------------
+
+extern "C" qmc_status qmc_lrdmc_hops(qmc_system* sys, qmc_walkers* wk, const qmc_lrdmc_params* params,
+                                     double* ratios, double* terms, hipStream_t stream) {
+  qmc_status c = check_pair(sys, wk);
+  if (c) return c;
+  if (!params) return fail(QMC_ERR_ARG, "null parameters");
+  const qmc_lrdmc_params& q = *params;
+  if (!(q.a > 0.0) || !std::isfinite(q.a)) return fail(QMC_ERR_ARG, "hop length a must be positive");
+  const bool dbl = q.a_valence > 0.0;
+  if (dbl && (!std::isfinite(q.a_valence) || !(q.tf_scale > 0.0) || !std::isfinite(q.tf_scale)))
+    return fail(QMC_ERR_ARG, "double grid needs a finite a_valence and a positive tf_scale");
+  if (!(q.gamma >= 0.0) || !std::isfinite(q.gamma)) return fail(QMC_ERR_ARG, "gamma must be >= 0");
+  if (!wk->evaluated || !wk->yt_valid)
+    return fail(QMC_ERR_STATE, "lattice hops need an evaluation since the last move");
+  if (wk->generation != sys->generation) return fail(QMC_ERR_STATE, "parameters changed since the last eval_batch");
+  const SysDev& s = sys->d;
+  const WalkDev& d = wk->d;
+  const LrdmcParams p{q.a, dbl ? q.a_valence : 0.0, q.tf_scale, q.gamma};
+  TIMED(wk, QMC_T_LRDMC_HOPS, stream, launch_lrdmc_hops(s, d, wk->lr, p, stream), "lattice hops");
+  if (ratios)
+    HIP_TRY(hipMemcpyAsync(ratios, wk->lr.ratio, sizeof(double) * d.Wk * s.N * kHops, hipMemcpyDeviceToDevice,
+                           stream), "copy ratios");
+  if (terms)
+    HIP_TRY(hipMemcpyAsync(terms, wk->lr.terms, sizeof(double) * d.Wk * kLrTerms, hipMemcpyDeviceToDevice,
+                           stream), "copy terms");
+  wk->lr_p = p;
+  wk->lr_ready = true;
+  return QMC_OK;
+}
+
+extern "C" qmc_status qmc_lrdmc_advance(qmc_system* sys, qmc_walkers* wk, const double* xi, double* weight,
+                                        double* tau_left, double* r_next, int32_t* hop, hipStream_t stream) {
+  qmc_status c = check_pair(sys, wk);
+  if (c) return c;
+  if (!xi || !weight || !tau_left || !r_next) return fail(QMC_ERR_ARG, "null argument");
+  if (!wk->lr_ready || !wk->yt_valid) return fail(QMC_ERR_STATE, "qmc_lrdmc_hops has not run for these positions");
+  if (wk->generation != sys->generation) return fail(QMC_ERR_STATE, "parameters changed since the last eval_batch");
+  TIMED(wk, QMC_T_LRDMC_STEP, stream,
+        launch_lrdmc_advance(sys->d, wk->d, wk->lr, wk->lr_p, xi, weight, tau_left, r_next, hop, stream),
+        "lattice step");
   return QMC_OK;
 }
 
@@ -858,6 +922,7 @@ extern "C" qmc_status qmc_multi_vmc_steps(qmc_multi* m, int32_t n_steps, const d
     if (expl && (!disp[k] || !unif[k])) return fail(QMC_ERR_ARG, "null draw array");
   }
   if (n_steps == 0) return QMC_OK;
+  for (int k = 0; k < m->n; ++k) m->wk[k]->yt_valid = m->wk[k]->lr_ready = false;
   HIP_TRY(hipEventRecord(m->ev_a, stream), "event");
   HIP_TRY(hipStreamWaitEvent(m->own, m->ev_a, 0), "wait");
   HIP_TRY(multi_upload(m), "upload");
