@@ -319,6 +319,75 @@ def multi_leg(P, C, precision="fp32", replays=3):
             "one_system_at_a_time_moves_per_s": round(steps * n_walk / t_seq, 1)}
 
 
+def lrdmc_leg(P, C, iters=10):
+    """Lattice-regularised DMC on the 160-electron workload, 1024 walkers,
+    FP64, double grid (0.1 / 0.4 bohr hops, fixed-node gamma 0.5): `iters`
+    iterations of evaluation -> 6N hop ratios and Green's function terms ->
+    continuous-time step.  Error of sampled hop ratios (walker 0, electrons 0
+    and 80) against the oracle's full re-evaluations."""
+    from oracle import jagp as O
+    from oracle import lrdmc as L
+    dev = torch.device("cuda:0")
+    w = C.mol_40nuc_160e()
+    s = w.system
+    Wk, N, Lb = w.r0.shape[0], s.n_up + s.n_dn, s.n_basis
+    prm = C.LRDMC_DOUBLE
+    sysh = P.JAGPSystem(s)
+    wk = P.Walkers(sysh, Wk)
+    r0 = torch.tensor(w.r0, device=dev)
+    xi = torch.tensor(C.lrdmc_draws(17, iters + 1, Wk), device=dev)
+    weight = torch.ones(Wk, dtype=torch.float64, device=dev)
+    tau = torch.empty(Wk, dtype=torch.float64, device=dev)
+    # warm-up iteration, then the sampled error at the starting positions
+    wk.eval_batch(r0)
+    g = wk.lrdmc_hops(**prm)
+    torch.cuda.synchronize()
+    sy = O.from_workload_system(s)
+    rc = r0[:1].cpu()
+    a_i = L.mesh(sy, rc, prm["a"], prm["a_valence"], prm["tf_scale"])
+    err = 0.0
+    for e in (0, s.n_up):
+        for k, (sg, ax) in enumerate(L.DIRS):
+            rn = rc[:, e].clone()
+            rn[0, ax] += sg * a_i[0, e]
+            ref = O.move_ratio(sy, rc, e, rn)[0]
+            err = max(err, float((g["ratios"][0, e, k].cpu() - ref).abs() / max(abs(float(ref)), 1.0)))
+    r = r0
+    wk.set_timing(True)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(iters)]
+    hops = 0
+    cnt = torch.zeros((), dtype=torch.int64, device=dev)
+    for t in range(iters):
+        tau.fill_(C.LRDMC_TAU)
+        ev[t][0].record()
+        wk.eval_batch(r, drift=False)
+        ev[t][1].record()
+        wk.lrdmc_hops(**prm, ratios=False)
+        ev[t][2].record()
+        r, hop = wk.lrdmc_advance(xi[t], weight, tau)
+        ev[t][3].record()
+        cnt += (hop >= 0).sum()
+    torch.cuda.synchronize()
+    tim = wk.timing()
+    wk.set_timing(False)
+    hops = int(cnt.item())
+    t_eval = sum(e[0].elapsed_time(e[1]) for e in ev) / 1e3
+    t_hops = sum(e[1].elapsed_time(e[2]) for e in ev) / 1e3
+    t_adv = sum(e[2].elapsed_time(e[3]) for e in ev) / 1e3
+    t_all = sum(e[0].elapsed_time(e[3]) for e in ev) / 1e3
+    wk.close()
+    sysh.close()
+    return {"workload": "mol_40nuc_160e", "walkers": Wk, "precision": "fp64",
+            "grid": f"double ({prm['a']} / {prm['a_valence']} bohr)", "gamma": prm["gamma"],
+            "iterations": iters, "lrdmc_steps_per_s": round(iters * Wk / t_all, 1),
+            "hop_ratios_per_s": round(iters * Wk * 6 * N / t_hops, 1),
+            "hop_basis_values_per_s": round(iters * Wk * 6 * N * Lb / t_hops, 1),
+            "eval_ms": round(1e3 * t_eval / iters, 3), "hops_ms": round(1e3 * t_hops / iters, 3),
+            "advance_ms": round(1e3 * t_adv / iters, 3), "hops_made": hops,
+            "kernel_ms": {k: round(tim[k][0] / iters, 3) for k in ("lrdmc_hops", "lrdmc_step")},
+            "ratio_err_vs_oracle": float(f"{err:.3e}")}
+
+
 def large_leg(P, C, steps=128, Wk=256):
     """The 1024-electron workload (256 nuclei, L = 4096, Lambda banded at 8
     bohr; n = 512 per spin, so the blocked Gauss-Jordan refresh), 256 walkers,
@@ -408,6 +477,7 @@ def main():
         res["forces"] = forces_leg(P, C)
         res["multi_system"] = multi_leg(P, C)
         res["large"] = large_leg(P, C)
+        res["lrdmc"] = lrdmc_leg(P, C)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(res), flush=True)
