@@ -19,6 +19,7 @@ constexpr int kLuMaxN = 128;      // one-workgroup (register / LDS) Sherman-Morr
 constexpr int kLuRowMax = 96;     // register (row-per-thread) Gauss-Jordan limit
 constexpr int kPropRowsMin = 8;   // smallest rows-per-workgroup the autotuner may pick
 constexpr int kMaxNucBack = 256;  // nuclei handled by the Jastrow backward kernel
+constexpr int kFuseMaxLp = 1024;   // accept fused with the next set-up: psi(r') staged in LDS
 constexpr int kBigMaxN = 1024;    // blocked Gauss-Jordan limit
 constexpr int kWbMax = 64;        // capacity of the delayed-update buffer (moves between refreshes)
 constexpr int kGjPanel = 64;      // panel width of the blocked Gauss-Jordan
@@ -339,6 +340,10 @@ hipError_t launch_propose_rows(const SysDev& s, const WalkDev& w, int e, double*
                                double* drift_new, bool finalize, hipStream_t st);
 hipError_t launch_metropolis_accept(const SysDev& s, const WalkDev& w, int e, const double* unif,
                                     int32_t* accept_count, hipStream_t st);
+// Metropolis accept of e fused with the set-up of the next proposal (electron
+// e2, displacements disp2 [Wk][3]); needs s.Lp <= kFuseMaxLp.
+hipError_t launch_metropolis_accept_prep(const SysDev& s, const WalkDev& w, int e, const double* unif,
+                                         int32_t* accept_count, int e2, const double* disp2, hipStream_t st);
 hipError_t launch_accept(const SysDev& s, const WalkDev& w, int e, const uint8_t* acc,
                          hipStream_t st);
 hipError_t launch_refresh_finish(const SysDev& s, const WalkDev& w, int32_t* status, hipStream_t st);

@@ -33,15 +33,35 @@ propose_prep_kernel(SysDev s, WalkDev w, int e, const double* __restrict__ r_new
                    disp ? disp + 3 * (long)wk : nullptr);
 }
 
-// grid (S, Wk): block (sb, wk) handles rows [sb*R, (sb+1)*R) of walker wk, R = s.prop_rows().
+// 1-D grid of S * Wk blocks; block (wk, sb) handles rows [sb*R, (sb+1)*R) of
+// walker wk, R = s.prop_rows().  Workgroups are handed to the eight XCDs in
+// turn (block b to XCD b mod 8), each with its own L2: when Wk is a multiple of
+// 8 the S blocks of one walker are given ids with one residue mod 8, so psi(r')
+// and the inverse column they all read come from HBM once per walker, not once
+// per XCD.
+__device__ __forceinline__ void rows_block(int b, int S, int Wk, int& wk, int& sb) {
+  if ((Wk & 7) == 0) {
+    const int q = b >> 3;
+    wk = (b & 7) + 8 * (q / S);
+    sb = q % S;
+  } else {
+    wk = b / S;
+    sb = b % S;
+  }
+}
+
 template <typename T, int NC>
-__global__ void __launch_bounds__(256) propose_rows_kernel(SysDev s, WalkDev w, int e) {
-  rows_body<T, NC>(s, w, blockIdx.y, blockIdx.x, gridDim.x, e, s.prop_rows());
+__global__ void __launch_bounds__(256) propose_rows_kernel(SysDev s, WalkDev w, int e, int S) {
+  int wk, sb;
+  rows_block(blockIdx.x, S, w.Wk, wk, sb);
+  rows_body<T, NC>(s, w, wk, sb, S, e, s.prop_rows());
 }
 
 template <typename T, bool DRIFT>
-__global__ void __launch_bounds__(256) propose_rows_generic_kernel(SysDev s, WalkDev w, int e) {
-  rows_generic_body<T, DRIFT>(s, w, blockIdx.y, blockIdx.x, gridDim.x, e, s.prop_rows());
+__global__ void __launch_bounds__(256) propose_rows_generic_kernel(SysDev s, WalkDev w, int e, int S) {
+  int wk, sb;
+  rows_block(blockIdx.x, S, w.Wk, wk, sb);
+  rows_generic_body<T, DRIFT>(s, w, wk, sb, S, e, s.prop_rows());
 }
 
 template <typename T>
@@ -51,6 +71,15 @@ accept_kernel(SysDev s, WalkDev w, int e, const uint8_t* __restrict__ acc_in,
   const int wk = blockIdx.x;
   accept_body<T>(s, w, wk, e, unif ? 1 : 0, acc_in ? acc_in + wk : nullptr, unif ? unif[wk] : 0.0,
                  accept_count ? accept_count + wk : nullptr, S);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+accept_prep_kernel(SysDev s, WalkDev w, int e, const double* __restrict__ unif, int32_t* __restrict__ accept_count,
+                   int S, int e2, const double* __restrict__ disp2) {
+  const int wk = blockIdx.x;
+  accept_prep_body<T>(s, w, wk, e, unif[wk], accept_count ? accept_count + wk : nullptr, S, e2,
+                      disp2 + 3 * (long)wk);
 }
 
 // Sum the partial ratios (fixed order) for host-driven proposals.
@@ -93,20 +122,20 @@ hipError_t launch_propose_rows(const SysDev& s, const WalkDev& w, int e, double*
                                double* drift_new, bool finalize, hipStream_t st) {
   const bool drift = drift_new != nullptr;
   const int S = propose_splits(s);
-  const dim3 grid(S, w.Wk);
+  const dim3 grid((unsigned)(S * w.Wk));
   const int store = s.store();
   hipError_t err;
   const int vn = store == 0 ? 2 : (store == 1 ? 4 : 8);   // elements per 16-byte load
   const int chunks = (s.Lp + 64 * vn - 1) / (64 * vn);
 #define QMC_GEN(D)                                                                                         \
-  if (store == 2) hipLaunchKernelGGL((propose_rows_generic_kernel<bf16s, D>), grid, dim3(256), 0, st, s, w, e); \
-  else if (store == 1) hipLaunchKernelGGL((propose_rows_generic_kernel<float, D>), grid, dim3(256), 0, st, s, w, e); \
-  else hipLaunchKernelGGL((propose_rows_generic_kernel<double, D>), grid, dim3(256), 0, st, s, w, e);
+  if (store == 2) hipLaunchKernelGGL((propose_rows_generic_kernel<bf16s, D>), grid, dim3(256), 0, st, s, w, e, S); \
+  else if (store == 1) hipLaunchKernelGGL((propose_rows_generic_kernel<float, D>), grid, dim3(256), 0, st, s, w, e, S); \
+  else hipLaunchKernelGGL((propose_rows_generic_kernel<double, D>), grid, dim3(256), 0, st, s, w, e, S);
   if (drift) {
     QMC_GEN(true)
   } else if (chunks <= 8) {
 #define QMC_ROWS(T, NC) \
-    case NC: hipLaunchKernelGGL((propose_rows_kernel<T, NC>), grid, dim3(256), 0, st, s, w, e); break;
+    case NC: hipLaunchKernelGGL((propose_rows_kernel<T, NC>), grid, dim3(256), 0, st, s, w, e, S); break;
     if (store == 2) {
       switch (chunks) { QMC_ROWS(bf16s, 1) QMC_ROWS(bf16s, 2) QMC_ROWS(bf16s, 3) QMC_ROWS(bf16s, 4)
                         QMC_ROWS(bf16s, 5) QMC_ROWS(bf16s, 6) QMC_ROWS(bf16s, 7) QMC_ROWS(bf16s, 8) }
@@ -146,6 +175,20 @@ hipError_t launch_accept(const SysDev& s, const WalkDev& w, int e, const uint8_t
 hipError_t launch_metropolis_accept(const SysDev& s, const WalkDev& w, int e, const double* unif,
                                     int32_t* accept_count, hipStream_t st) {
   return accept_launch(s, w, e, nullptr, unif, accept_count, propose_splits(s), st);
+}
+
+hipError_t launch_metropolis_accept_prep(const SysDev& s, const WalkDev& w, int e, const double* unif,
+                                         int32_t* accept_count, int e2, const double* disp2, hipStream_t st) {
+  if (s.nu > kBigMaxN || !w.wv || s.Lp > kFuseMaxLp || e2 == e) return hipErrorNotSupported;
+  const int S = propose_splits(s);
+  const dim3 grid(w.Wk), blk(256);
+  if (s.bf16())
+    hipLaunchKernelGGL(accept_prep_kernel<bf16s>, grid, blk, 0, st, s, w, e, unif, accept_count, S, e2, disp2);
+  else if (s.f32())
+    hipLaunchKernelGGL(accept_prep_kernel<float>, grid, blk, 0, st, s, w, e, unif, accept_count, S, e2, disp2);
+  else
+    hipLaunchKernelGGL(accept_prep_kernel<double>, grid, blk, 0, st, s, w, e, unif, accept_count, S, e2, disp2);
+  return hipGetLastError();
 }
 
 // After a refresh LU: log|Psi| = log|det W| + J, sign from the LU.

@@ -307,18 +307,16 @@ __device__ void rows_generic_body(const SysDev& s, const WalkDev& w, int wk, int
 // position and the tracked log|Psi|, sign and Jastrow sum are.
 // S > 0: the ratio is first summed from the proposal's S partial sums.
 // ---------------------------------------------------------------------------
+template <typename T>
+__device__ void accept_apply(const SysDev& s, const WalkDev& w, int wk, int e, double R, int m,
+                             int32_t* __restrict__ cnt);
+
 // acc_in: this walker's host decision (mode 0), or u: its uniform (mode 1).
 // cnt: this walker's accept counter (may be null).
 template <typename T>
 __device__ void accept_body(const SysDev& s, const WalkDev& w, int wk, int e, int mode,
                             const uint8_t* __restrict__ acc_in, double u, int32_t* __restrict__ cnt, int S) {
-  __shared__ double sd[kBigMaxN];
-  __shared__ double sr[kWbMax];
-  __shared__ double sy[kWbMax];
-  __shared__ double red[16];
-  __shared__ double gam_s;
-  const int n = s.nu;             // square: n_up == n_dn
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  const int tid = threadIdx.x;
   double R, ratio;
   if (S > 0) {
     R = 0.0;
@@ -336,7 +334,20 @@ __device__ void accept_body(const SysDev& s, const WalkDev& w, int wk, int e, in
     if (S > 0) { w.rdet[wk] = R; w.ratio[wk] = ratio; }
     w.acc[wk] = acc ? 1 : 0;
   }
-  if (!acc) return;   // uniform over the block
+  if (acc) accept_apply<T>(s, w, wk, e, R, m, cnt);   // uniform over the block
+}
+
+template <typename T>
+__device__ void accept_apply(const SysDev& s, const WalkDev& w, int wk, int e, double R, int m,
+                             int32_t* __restrict__ cnt) {
+  __shared__ double sd[kBigMaxN];
+  __shared__ double sr[kWbMax];
+  __shared__ double sy[kWbMax];
+  __shared__ double red[16];
+  __shared__ double gam_s;
+  const int n = s.nu;             // square: n_up == n_dn
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  const int kb = w.kb;
   const bool up = e < s.nu;
   const int ie = up ? e : e - s.nu;
   double* Ww = w.W + (long)wk * n * n;
@@ -407,6 +418,38 @@ __device__ void accept_body(const SysDev& s, const WalkDev& w, int wk, int e, in
     w.J[wk] += dJ;
     if (cnt) cnt[0] += 1;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Metropolis accept of electron e fused with the set-up of the next proposal
+// (electron e2 != e, displacement disp2), one workgroup per walker.  The basis
+// values at r' = r[e2] + disp2 do not depend on the accept (it changes only
+// r[e]); they are computed first, into LDS, so that their arithmetic overlaps
+// the accept's memory round trips.  After a barrier (the accept has consumed
+// psi_new, r_new, dJ, v0 and z) the set-up continues exactly as prep_body:
+// psi_new, r_new, the Jastrow change with the updated positions and the
+// current inverse's column / row of e2 from the updated buffer.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ void accept_prep_body(const SysDev& s, const WalkDev& w, int wk, int e, double u,
+                                 int32_t* __restrict__ cnt, int S, int e2, const double* __restrict__ disp2) {
+  __shared__ double sps[kFuseMaxLp];
+  __shared__ double red[8];
+  const int tid = threadIdx.x;
+  const double* r = w.r + (long)wk * s.N * 3;
+  const double px = r[3 * e2] + disp2[0], py = r[3 * e2 + 1] + disp2[1], pz = r[3 * e2 + 2] + disp2[2];
+  for (int mu = tid; mu < s.L; mu += blockDim.x) sps[mu] = basis_value(s, mu, px, py, pz);
+  accept_body<T>(s, w, wk, e, 1, nullptr, u, cnt, S);
+  __syncthreads();
+  double* psi = w.psi_new + (long)wk * s.Lp;
+  for (int mu = tid; mu < s.Lp; mu += blockDim.x) psi[mu] = mu < s.L ? sps[mu] : 0.0;
+  if (tid < 3) w.r_new[3 * wk + tid] = tid == 0 ? px : (tid == 1 ? py : pz);
+  double jn, gxn, gyn, gzn, jo, d0, d1, d2;
+  jastrow_one(s, r, e2, px, py, pz, false, jn, gxn, gyn, gzn);
+  jastrow_one(s, r, e2, r[3 * e2], r[3 * e2 + 1], r[3 * e2 + 2], false, jo, d0, d1, d2);
+  const double dJ = block_sum_mv(jn - jo, red);
+  if (tid == 0) w.dJ[wk] = dJ;
+  inverse_line_body(s, w, wk, e2);
 }
 
 }  // namespace qmc

@@ -507,6 +507,20 @@ extern "C" qmc_status qmc_accept_move(qmc_system* sys, qmc_walkers* wk, int32_t 
   return after_accept(wk, electron, status, stream);
 }
 
+// The accept of e can run fused with the set-up of the next proposal e2 when
+// neither a refresh (after the accept, or before proposing e2) nor a P rebuild
+// (for e2) falls between them, and psi(r') fits the kernel's LDS stage.
+static bool fusable(const qmc_walkers* wk, int e, int e2) {
+  const SysDev& s = wk->sys->d;
+  if (s.Lp > kFuseMaxLp || s.nu > kBigMaxN || !wk->d.wv || e2 == e) return false;
+  Sched q{wk->attempts, wk->since, wk->buf_spin};
+  if (sched_after(s, q)) return false;
+  if (sched_before(s, q, e2)) return false;
+  bool up_ok = wk->P_up_valid, dn_ok = wk->P_dn_valid;
+  if (e < s.nu) up_ok = false; else dn_ok = false;
+  return e2 < s.nu ? dn_ok : up_ok;
+}
+
 extern "C" qmc_status qmc_vmc_steps(qmc_system* sys, qmc_walkers* wk, int32_t e_start, int32_t n_steps,
                                     const double* disp, const double* unif, int32_t* accept_count,
                                     hipStream_t stream) {
@@ -518,20 +532,40 @@ extern "C" qmc_status qmc_vmc_steps(qmc_system* sys, qmc_walkers* wk, int32_t e_
   if (!disp || !unif) return fail(QMC_ERR_ARG, "null random arrays");
   if (n_steps < 0 || e_start < 0) return fail(QMC_ERR_ARG, "negative step count or electron");
   const long Wk = wk->d.Wk;
+  bool prepped = false;   // the set-up of step t ran in step t-1's fused accept
   for (int t = 0; t < n_steps; ++t) {
     const int e = (int)((e_start + (long)t) % s.N);
-    c = before_propose(wk, e, stream);
-    if (c) return c;
-    c = ensure_P(wk, e, stream);
-    if (c) return c;
-    TIMED(wk, QMC_T_PROPOSE_PREP, stream,
-          launch_propose_prep(s, wk->d, e, nullptr, disp + (long)t * Wk * 3, false, stream), "propose prep");
+    if (!prepped) {
+      c = before_propose(wk, e, stream);
+      if (c) return c;
+      c = ensure_P(wk, e, stream);
+      if (c) return c;
+      TIMED(wk, QMC_T_PROPOSE_PREP, stream,
+            launch_propose_prep(s, wk->d, e, nullptr, disp + (long)t * Wk * 3, false, stream), "propose prep");
+    }
     TIMED(wk, QMC_T_PROPOSE, stream, launch_propose_rows(s, wk->d, e, nullptr, nullptr, false, stream),
           "propose rows");
-    TIMED(wk, QMC_T_ACCEPT, stream,
-          launch_metropolis_accept(s, wk->d, e, unif + (long)t * Wk, accept_count, stream), "metropolis");
-    c = after_accept(wk, e, nullptr, stream);
-    if (c) return c;
+    const int e2 = (int)((e_start + (long)t + 1) % s.N);
+    prepped = t + 1 < n_steps && fusable(wk, e, e2);
+    if (prepped) {
+      // no refresh and no P rebuild fall between the two: the bookkeeping of
+      // after_accept, before_propose and ensure_P below launches nothing
+      TIMED(wk, QMC_T_ACCEPT, stream,
+            launch_metropolis_accept_prep(s, wk->d, e, unif + (long)t * Wk, accept_count, e2,
+                                          disp + (long)(t + 1) * Wk * 3, stream),
+            "metropolis + next set-up");
+      c = after_accept(wk, e, nullptr, stream);
+      if (c) return c;
+      c = before_propose(wk, e2, stream);
+      if (c) return c;
+      c = ensure_P(wk, e2, stream);
+      if (c) return c;
+    } else {
+      TIMED(wk, QMC_T_ACCEPT, stream,
+            launch_metropolis_accept(s, wk->d, e, unif + (long)t * Wk, accept_count, stream), "metropolis");
+      c = after_accept(wk, e, nullptr, stream);
+      if (c) return c;
+    }
   }
   return QMC_OK;
 }
