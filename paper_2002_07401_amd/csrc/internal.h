@@ -18,6 +18,11 @@ constexpr int kMaxNuc = 4096;
 constexpr int kLuMaxN = 128;      // one-workgroup (register / LDS) Sherman-Morrison limit
 constexpr int kLuRowMax = 96;     // register (row-per-thread) Gauss-Jordan limit
 constexpr int kPropRowsMin = 8;   // smallest rows-per-workgroup the autotuner may pick
+// P rows per proposal workgroup (swept on MI355X: 8 for FP64 rows, 16 for the
+// narrower FP32 / BF16 rows); rdet_part holds ceil(n / kPropRowsMin) partial
+// sums per walker, so no choice may go below kPropRowsMin
+constexpr int kPropRowsF64 = 8, kPropRowsNarrow = 16;
+static_assert(kPropRowsF64 >= kPropRowsMin && kPropRowsNarrow >= kPropRowsMin, "partial-sum buffer too small");
 constexpr int kMaxNucBack = 256;  // nuclei handled by the Jastrow backward kernel
 constexpr int kFuseMaxLp = 1024;   // accept fused with the next set-up: psi(r') staged in LDS
 constexpr int kBigMaxN = 1024;    // blocked Gauss-Jordan limit
@@ -64,9 +69,7 @@ struct SysDev {
   __host__ __device__ bool refined() const { return precision == QMC_MIXED || precision == QMC_MIXED_BF16; }
   // 0: FP64, 1: FP32, 2: BF16 storage
   __host__ __device__ int store() const { return precision == QMC_FP64 ? 0 : (bf16() ? 2 : 1); }
-  // P rows per proposal workgroup (swept on MI355X: 8 for FP64 rows, 16 for
-  // the narrower FP32 / BF16 rows)
-  __host__ __device__ int prop_rows() const { return store() == 0 ? 8 : 16; }
+  __host__ __device__ int prop_rows() const { return store() == 0 ? kPropRowsF64 : kPropRowsNarrow; }
   double* R;        // [A][3]
   double* Z;        // [A]
   double* j1_b;     // [A]

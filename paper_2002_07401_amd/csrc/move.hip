@@ -121,6 +121,7 @@ hipError_t launch_propose_prep(const SysDev& s, const WalkDev& w, int e, const d
 hipError_t launch_propose_rows(const SysDev& s, const WalkDev& w, int e, double* ratio,
                                double* drift_new, bool finalize, hipStream_t st) {
   const bool drift = drift_new != nullptr;
+  if (s.prop_rows() < kPropRowsMin) return hipErrorInvalidValue;   // rdet_part would overflow
   const int S = propose_splits(s);
   const dim3 grid((unsigned)(S * w.Wk));
   const int store = s.store();

@@ -126,3 +126,33 @@ def test_chain_molecule_160e_one_sweep():
     assert torch.equal(rg, rf)
     assert rel_err(la, O.evaluate(sy, rf)["logabs"]).max().item() <= 1e-10
     assert accs.float().mean().item() > 0.05
+
+
+def test_device_sweep_equals_host_driven_moves():
+    # qmc_vmc_steps runs most accepts fused with the next proposal's set-up;
+    # the host-driven propose / accept calls run every kernel separately.  Same
+    # arithmetic in the same order: positions, log|Psi|, W and W^{-1} agree
+    # bitwise over 100 steps (refreshes at 32 moves of one spin and at the
+    # change of spin, P rebuilds).
+    P = need_gpu()
+    w = C.mol_40nuc_160e(n_walkers=16)
+    _, wk_a, sy, r = _setup(P, w)
+    _, wk_b, _, _ = _setup(P, w)
+    n = 100
+    e0 = 30
+    disp, unif = C.chain_arrays(41, n, 16)
+    disp, unif = torch.tensor(disp, device="cuda"), torch.tensor(unif, device="cuda")
+    cnt = torch.zeros(16, dtype=torch.int32, device="cuda")
+    wk_a.vmc_steps(e0, disp, unif, cnt)
+    N = w.system.n_up + w.system.n_dn
+    for t in range(n):
+        e = (e0 + t) % N
+        rcur = wk_b.read(P.STATE_R)
+        ratio = wk_b.propose(e, (rcur[:, e] + disp[t]).contiguous())
+        wk_b.accept(e, (unif[t] < ratio * ratio).to(torch.uint8))
+    torch.cuda.synchronize()
+    for item in (P.STATE_R, P.STATE_LOGABS, P.STATE_SIGN, P.STATE_W, P.STATE_AINV):
+        a, b = wk_a.read(item), wk_b.read(item)
+        torch.cuda.synchronize()
+        assert torch.equal(a.cpu(), b.cpu()), item
+    assert 0 < int(cnt.sum()) < 16 * n
