@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define QMC_ABI_VERSION 2
+#define QMC_ABI_VERSION 3
 
 typedef enum {
   QMC_OK = 0,
@@ -357,8 +357,14 @@ typedef enum {
   QMC_TIMER_COUNT = 13
 } qmc_timer;
 
-/* enable != 0 turns timing on and clears the sums; 0 turns it off. */
+/* enable != 0 turns every timer on and clears the sums; 0 turns timing off. */
 qmc_status qmc_walkers_set_timing(qmc_walkers *wk, int32_t enable);
+
+/* Turn on only the timers whose bit is set (bit k: timer k of qmc_timer) and
+ * clear the sums; 0 turns timing off.  Each timed launch adds two event
+ * records to its stream, so a measurement of throughput can time only the
+ * kernels it needs. */
+qmc_status qmc_walkers_set_timing_mask(qmc_walkers *wk, uint32_t mask);
 
 /* Wait for the recorded events and return, per timer, the summed kernel time in
  * milliseconds (ms[QMC_TIMER_COUNT], host) and the number of launches

@@ -33,7 +33,7 @@ FUNCTIONS = (
     "qmc_accept_move", "qmc_vmc_steps", "qmc_walkers_read", "qmc_walkers_set_timing",
     "qmc_walkers_timing", "qmc_forces", "qmc_system_set_params", "qmc_multi_create",
     "qmc_multi_destroy", "qmc_multi_autotune", "qmc_multi_vmc_steps", "qmc_philox_draws",
-    "qmc_lrdmc_hops", "qmc_lrdmc_advance",
+    "qmc_lrdmc_hops", "qmc_lrdmc_advance", "qmc_walkers_set_timing_mask",
 )
 
 TIMER_NAMES = ("basis", "P_build", "W_build", "LU", "Y_build", "rowdot", "assemble", "propose",
@@ -97,6 +97,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.qmc_vmc_steps.argtypes = [vp, vp, i32, i32, dp, dp, vp, vp]
     lib.qmc_walkers_read.argtypes = [vp, i32, dp, vp]
     lib.qmc_walkers_set_timing.argtypes = [vp, i32]
+    lib.qmc_walkers_set_timing_mask.argtypes = [vp, ctypes.c_uint32]
     lib.qmc_walkers_timing.argtypes = [vp, vp, vp]
     lib.qmc_forces.argtypes = [vp, vp, dp, i32, dp, dp, ctypes.POINTER(Grads), vp]
     lib.qmc_system_set_params.argtypes = [vp, dp, dp, dp, dp, vp]
@@ -239,8 +240,17 @@ class Walkers:
         _check(load().qmc_walkers_read(self.h, item, _ptr(dst), _stream(stream)))
         return dst
 
-    def set_timing(self, enable: bool):
-        _check(load().qmc_walkers_set_timing(self.h, 1 if enable else 0))
+    def set_timing(self, enable: bool, timers=None):
+        """Turn the kernel timers on (all, or only the named ones) or off."""
+        if not enable:
+            _check(load().qmc_walkers_set_timing(self.h, 0))
+        elif timers is None:
+            _check(load().qmc_walkers_set_timing(self.h, 1))
+        else:
+            mask = 0
+            for name in timers:
+                mask |= 1 << TIMER_NAMES.index(name)
+            _check(load().qmc_walkers_set_timing_mask(self.h, mask))
 
     def timing(self):
         """{timer name: (total ms, launches)}; waits for the recorded events."""

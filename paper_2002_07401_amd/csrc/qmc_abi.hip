@@ -52,6 +52,7 @@ struct qmc_system {
 // Event-pair timers for the kernels launched on behalf of one walker set.
 struct Timers {
   bool on = false;
+  uint32_t mask = 0;   // timers that record (bit k: timer k)
   double ms[QMC_TIMER_COUNT] = {};
   int64_t n[QMC_TIMER_COUNT] = {};
   struct Pair { hipEvent_t a, b; int id; };
@@ -75,8 +76,8 @@ struct Timers {
     return hipSuccess;
   }
   hipError_t begin(int id, hipStream_t st) {
-    if (!on) return hipSuccess;
-    if (pending.size() >= 2048) {
+    if (!on || !((mask >> id) & 1u)) return hipSuccess;
+    if (pending.size() >= 8192) {
       hipError_t e = fold();
       if (e != hipSuccess) return e;
     }
@@ -594,12 +595,17 @@ extern "C" qmc_status qmc_walkers_read(qmc_walkers* wk, int32_t item, double* ds
   return QMC_OK;
 }
 
-extern "C" qmc_status qmc_walkers_set_timing(qmc_walkers* wk, int32_t enable) {
+extern "C" qmc_status qmc_walkers_set_timing_mask(qmc_walkers* wk, uint32_t mask) {
   if (!wk) return fail(QMC_ERR_ARG, "null walkers");
   HIP_TRY(wk->tm.fold(), "timer fold");
   for (int k = 0; k < QMC_TIMER_COUNT; ++k) { wk->tm.ms[k] = 0.0; wk->tm.n[k] = 0; }
-  wk->tm.on = enable != 0;
+  wk->tm.mask = mask & ((1u << QMC_TIMER_COUNT) - 1u);
+  wk->tm.on = wk->tm.mask != 0;
   return QMC_OK;
+}
+
+extern "C" qmc_status qmc_walkers_set_timing(qmc_walkers* wk, int32_t enable) {
+  return qmc_walkers_set_timing_mask(wk, enable ? ~0u : 0u);
 }
 
 extern "C" qmc_status qmc_walkers_timing(qmc_walkers* wk, double* ms, int64_t* launches) {
