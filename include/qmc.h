@@ -85,7 +85,8 @@ typedef struct {
   const int32_t *center;      /* [L] nucleus index of each basis function        */
   const int32_t *l;           /* [L] angular momentum, 0..2                      */
   const int32_t *m;           /* [L] component index (see above)                 */
-  const int32_t *radial;      /* [L] 0 Gaussian (only 0 is built)                */
+  const int32_t *radial;      /* [L] 0 Gaussian e^{-zeta r^2} (eq. gaussian),
+                                 1 Slater e^{-zeta r} (eq. slater)                */
   const double *zeta;         /* [L] exponents                                   */
   const double *lambda;       /* [L][L] pairing coefficients (general matrix;
                                  symmetric for a spin singlet)                   */
@@ -109,7 +110,7 @@ int32_t qmc_abi_version(void);
 const char *qmc_last_error(void);
 
 /* Copy a description to the current device.  Fails with QMC_ERR_UNSUPPORTED
- * for Slater functions, l > 2, n_up != n_dn or a precision not built. */
+ * for l > 2, n_up != n_dn or a precision not built. */
 qmc_status qmc_system_create(const qmc_system_desc *desc, qmc_system **out);
 qmc_status qmc_system_destroy(qmc_system *sys);
 

@@ -211,8 +211,7 @@ basis_backward_kernel(SysDev s, WalkDev w, const double* __restrict__ phibar, co
       c = s.center[mu]; kind = s.kind[mu]; zt = f.w;
       Rx = f.x; Ry = f.y; Rz = f.z;
     }
-    hess_P(kind, HP);
-    const double lq = 4.0 * kind_l(kind) + 6.0;
+    hess_P(kind_ang(kind), HP);
     double zacc = 0.0, tx = 0.0, ty = 0.0, tz = 0.0;
     for (int i = 0; i < s.N; ++i) {
       double t0 = 0.0, t1 = 0.0, t2 = 0.0;
@@ -224,32 +223,33 @@ basis_backward_kernel(SysDev s, WalkDev w, const double* __restrict__ phibar, co
         const double d[3] = {r[3 * i] - Rx, r[3 * i + 1] - Ry, r[3 * i + 2] - Rz};
         const double sq = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
         double P, Pg[3];
-        angular(kind, d[0], d[1], d[2], P, Pg[0], Pg[1], Pg[2]);
-        const double e = exp(-zt * sq);
+        angular(kind_ang(kind), d[0], d[1], d[2], P, Pg[0], Pg[1], Pg[2]);
+        const Radial rd = radial_all(kind, zt, sq);
+        const double e = rd.e;
         const double psi = P * e;
         double gpsi[3];
-        for (int a = 0; a < 3; ++a) gpsi[a] = (Pg[a] - 2.0 * zt * d[a] * P) * e;
+        for (int a = 0; a < 3; ++a) gpsi[a] = (Pg[a] + rd.h1 * d[a] * P) * e;
         // Hessian of psi
         const int ia[6] = {0, 1, 2, 0, 1, 2}, ib[6] = {0, 1, 2, 1, 2, 0};
         double Hs[3][3];
         for (int q = 0; q < 6; ++q) {
           const int a = ia[q], bb = ib[q];
-          const double v = (HP[q] - 2.0 * zt * (d[a] * Pg[bb] + d[bb] * Pg[a]) -
-                            (a == bb ? 2.0 * zt * P : 0.0) + 4.0 * zt * zt * d[a] * d[bb] * P) * e;
+          const double v = (HP[q] + rd.h1 * (d[a] * Pg[bb] + d[bb] * Pg[a]) +
+                            (a == bb ? rd.h1 * P : 0.0) + rd.h2 * d[a] * d[bb] * P) * e;
           Hs[a][bb] = v; Hs[bb][a] = v;
         }
-        const double cl = 4.0 * zt * zt * sq - lq * zt;   // lap psi = cl psi
+        const double cl = rd.cl;   // lap psi = cl psi
         double glap[3];
-        for (int a = 0; a < 3; ++a) glap[a] = 8.0 * zt * zt * d[a] * psi + cl * gpsi[a];
+        for (int a = 0; a < 3; ++a) glap[a] = rd.gl * d[a] * psi + cl * gpsi[a];
         const double gbv[3] = {gbx, gby, gbz};
         t0 = pb * gpsi[0] + Hs[0][0] * gbv[0] + Hs[0][1] * gbv[1] + Hs[0][2] * gbv[2] + hb * glap[0];
         t1 = pb * gpsi[1] + Hs[1][0] * gbv[0] + Hs[1][1] * gbv[1] + Hs[1][2] * gbv[2] + hb * glap[1];
         t2 = pb * gpsi[2] + Hs[2][0] * gbv[0] + Hs[2][1] * gbv[1] + Hs[2][2] * gbv[2] + hb * glap[2];
         // exponent derivatives
-        const double zpsi = -sq * psi;
+        const double zpsi = -rd.zp * psi;
         double zg = 0.0;
-        for (int a = 0; a < 3; ++a) zg += gbv[a] * (-2.0 * d[a] * P * e - sq * gpsi[a]);
-        const double zlap = (8.0 * zt * sq - lq) * psi - sq * cl * psi;
+        for (int a = 0; a < 3; ++a) zg += gbv[a] * (-rd.zq * d[a] * psi - rd.zp * gpsi[a]);
+        const double zlap = rd.dcl * psi - rd.zp * cl * psi;
         zacc += pb * zpsi + zg + hb * zlap;
         tx += t0; ty += t1; tz += t2;
       }

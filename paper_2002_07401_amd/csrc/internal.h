@@ -74,7 +74,8 @@ struct SysDev {
   double* Z;        // [A]
   double* j1_b;     // [A]
   int* center;      // [L]
-  int* kind;        // [L]  0 s | 1..3 p(x,y,z) | 4..8 d(xy,yz,zx,x2-y2,2z2-x2-y2)
+  int* kind;        // [L]  0 s | 1..3 p(x,y,z) | 4..8 d(xy,yz,zx,x2-y2,2z2-x2-y2), plus
+                    //      kSlaterBit for a Slater radial factor e^{-zeta r}
   double* zeta;     // [L]
   double* lam;      // [Lp][Lp]  Lambda, zero padded
   double* lamT;     // [Lp][Lp]  Lambda^T
@@ -211,6 +212,57 @@ __device__ __forceinline__ void angular(int kind, double x, double y, double z,
 
 __device__ __forceinline__ int kind_l(int kind) { return kind == 0 ? 0 : (kind < 4 ? 1 : 2); }
 
+// Radial factors (eq. gaussian: e^{-zeta r^2}; eq. slater: e^{-zeta r}).  The
+// basis function is psi = P(d) e(r), P an unnormalised real solid harmonic of
+// degree l (harmonic and homogeneous), d the displacement from the centre.
+// With h = e(r) and its radial derivatives, every derivative the path needs
+// is P, grad P, Hess P and these coefficients (q = r^2):
+//   grad psi   = e (grad P + h1 P d)                      h1 = h'/(r h)
+//   Hess psi   = e (Hess P + h1 (d grad P^T + grad P d^T) + P (h2 d d^T + h1 I))
+//                                                         h2 = (h''/r^2 - h'/r^3)/h
+//   lap psi    = cl psi                                   cl = (h'' + 2(l+1) h'/r)/h
+//   grad lap   = cl grad psi + gl psi d                   gl = cl'/r
+//   dpsi/dzeta = -zp psi,  d grad psi/dzeta = -(zp grad psi + zq psi d),
+//   d lap psi/dzeta = (dcl - zp cl) psi                   zp = r^2 or r, zq = 2 or 1/r, dcl = dcl/dzeta
+// Gaussian: h1 = -2 zeta, h2 = 4 zeta^2, cl = 4 zeta^2 q - (4l+6) zeta, gl = 8 zeta^2.
+// Slater:   h1 = -zeta/r, h2 = zeta^2/r^2 + zeta/r^3, cl = zeta^2 - 2 zeta (l+1)/r,
+//           gl = 2 zeta (l+1)/r^3.
+constexpr int kSlaterBit = 16;
+__device__ __forceinline__ int kind_ang(int kind) { return kind & (kSlaterBit - 1); }
+
+__device__ __forceinline__ double radial_e(int kind, double zt, double q) {
+  return (kind & kSlaterBit) ? exp(-zt * sqrt(q)) : exp(-zt * q);
+}
+
+struct Radial { double e, h1, h2, cl, gl, zp, zq, dcl; };
+
+__device__ __forceinline__ Radial radial_all(int kind, double zt, double q) {
+  const double l = (double)kind_l(kind_ang(kind));
+  Radial o;
+  if (kind & kSlaterBit) {
+    const double r = sqrt(q), ir = 1.0 / r;
+    o.e = exp(-zt * r);
+    o.h1 = -zt * ir;
+    o.h2 = zt * zt * ir * ir + zt * ir * ir * ir;
+    o.cl = zt * zt - 2.0 * zt * (l + 1.0) * ir;
+    o.gl = 2.0 * zt * (l + 1.0) * ir * ir * ir;
+    o.zp = r;
+    o.zq = ir;
+    o.dcl = 2.0 * zt - 2.0 * (l + 1.0) * ir;
+  } else {
+    const double lq = 4.0 * l + 6.0;
+    o.e = exp(-zt * q);
+    o.h1 = -2.0 * zt;
+    o.h2 = 4.0 * zt * zt;
+    o.cl = 4.0 * zt * zt * q - lq * zt;
+    o.gl = 8.0 * zt * zt;
+    o.zp = q;
+    o.zq = 2.0;
+    o.dcl = 8.0 * zt * q - lq;
+  }
+  return o;
+}
+
 __device__ __forceinline__ double angular_value(int kind, double x, double y, double z) {
   switch (kind) {
     case 0: return 1.0;
@@ -225,33 +277,32 @@ __device__ __forceinline__ double angular_value(int kind, double x, double y, do
   }
 }
 
-// Gaussian function mu at point (px,py,pz): value only.  The centre and the
+// Basis function mu at point (px,py,pz): value only.  The centre and the
 // exponent come from one packed record (one memory round trip).
 __device__ __forceinline__ double basis_value(const SysDev& s, int mu, double px, double py, double pz) {
   const double4 f = s.bfn[mu];
   const double x = px - f.x, y = py - f.y, z = pz - f.z;
   const double r2 = x * x + y * y + z * z;
-  return angular_value(s.kind[mu], x, y, z) * exp(-f.w * r2);
+  const int k = s.kind[mu];
+  return angular_value(kind_ang(k), x, y, z) * radial_e(k, f.w, r2);
 }
 
-// Value, gradient and Laplacian.  The angular factors are harmonic and
-// homogeneous of degree l, so lap(P e^{-zeta r^2}) = (4 zeta^2 r^2 - (4l+6) zeta) P e.
+// Value, gradient and Laplacian (see Radial).
 __device__ __forceinline__ void basis_vgl(const SysDev& s, int mu, double px, double py, double pz,
                                           double& v, double& gx, double& gy, double& gz, double& lap) {
   const double4 f = s.bfn[mu];
   const double x = px - f.x, y = py - f.y, z = pz - f.z;
   const double r2 = x * x + y * y + z * z;
-  const double zt = f.w;
   const int k = s.kind[mu];
   double P, Px, Py, Pz;
-  angular(k, x, y, z, P, Px, Py, Pz);
-  const double e = exp(-zt * r2);
-  const double t = -2.0 * zt * P;
-  v = P * e;
-  gx = (Px + t * x) * e;
-  gy = (Py + t * y) * e;
-  gz = (Pz + t * z) * e;
-  lap = (4.0 * zt * zt * r2 - (4.0 * kind_l(k) + 6.0) * zt) * v;
+  angular(kind_ang(k), x, y, z, P, Px, Py, Pz);
+  const Radial rd = radial_all(k, f.w, r2);
+  const double t = rd.h1 * P;
+  v = P * rd.e;
+  gx = (Px + t * x) * rd.e;
+  gy = (Py + t * y) * rd.e;
+  gz = (Pz + t * z) * rd.e;
+  lap = rd.cl * v;
 }
 
 // One-body term f(r) = -(2Z)^{3/4} u((2Z)^{1/4} r) and its radial derivatives.

@@ -75,7 +75,7 @@ __global__ __launch_bounds__(256) void lrdmc_ratio_kernel(SysDev s, WalkDev w, L
 #pragma unroll
     for (int k = 0; k < kHops; ++k) {
       const double dx = px[k] - f.x, dy = py[k] - f.y, dz = pz[k] - f.z;
-      c[k] += angular_value(kind, dx, dy, dz) * exp(-f.w * (dx * dx + dy * dy + dz * dz)) * y_mu;
+      c[k] += angular_value(kind_ang(kind), dx, dy, dz) * radial_e(kind, f.w, dx * dx + dy * dy + dz * dz) * y_mu;
     }
   }
 

@@ -173,12 +173,12 @@ extern "C" qmc_status qmc_system_create(const qmc_system_desc* desc, qmc_system*
   const int L = q.n_basis;
   std::vector<int> kind(L);
   for (int mu = 0; mu < L; ++mu) {
-    if (q.radial && q.radial[mu] != 0) return fail(QMC_ERR_UNSUPPORTED, "only Gaussian functions are built");
+    if (q.radial && q.radial[mu] != 0 && q.radial[mu] != 1) return fail(QMC_ERR_ARG, "radial must be 0 or 1");
     if (q.center[mu] < 0 || q.center[mu] >= q.n_nuc) return fail(QMC_ERR_ARG, "basis center out of range");
     const int l = q.l[mu], m = q.m[mu];
     if (l < 0 || l > 2) return fail(QMC_ERR_UNSUPPORTED, "l > 2 not built");
     if (m < 0 || m >= 2 * l + 1) return fail(QMC_ERR_ARG, "component index out of range");
-    kind[mu] = (l == 0) ? 0 : (l == 1 ? 1 + m : 4 + m);
+    kind[mu] = ((l == 0) ? 0 : (l == 1 ? 1 + m : 4 + m)) | ((q.radial && q.radial[mu] == 1) ? kSlaterBit : 0);
   }
   std::vector<int> cptr(q.n_nuc + 1, 0), cmu(L);
   for (int mu = 0; mu < L; ++mu) cptr[q.center[mu] + 1]++;

@@ -496,3 +496,24 @@ def test_translation_sum_rule():
         tot = g["R"].sum(0) + g["r"].sum(dim=(0, 1))
         scale = g["R"].abs().max().item()
         assert tot.abs().max().item() < 1e-9 * max(1.0, scale)
+
+
+def test_basis_slater_finite_differences():
+    # Slater s, p and d functions (eq. slater): gradients against central
+    # differences of the values, Laplacians against Richardson second differences
+    s, sy = make_system([[0.2, -0.1, 0.3]], [1.0], [(0, 0), (0, 1), (0, 2)], 1, 1, radial=1)
+    pts = torch.tensor(np.random.default_rng(4).normal(size=(20, 3)), dtype=DT)
+    psi, grad, lap = O.basis(sy, pts)
+    h = 1e-5
+    for ax in range(3):
+        e = torch.zeros(3, dtype=DT); e[ax] = h
+        fd = (O.basis(sy, pts + e)[0] - O.basis(sy, pts - e)[0]) / (2 * h)
+        assert torch.allclose(grad[..., ax], fd, rtol=1e-6, atol=1e-9)
+    def lap_fd(hh):
+        tot = 0
+        for ax in range(3):
+            e = torch.zeros(3, dtype=DT); e[ax] = hh
+            tot = tot + (O.basis(sy, pts + e)[0] - 2 * psi + O.basis(sy, pts - e)[0]) / hh ** 2
+        return tot
+    fd2 = (4 * lap_fd(5e-4) - lap_fd(1e-3)) / 3
+    assert torch.allclose(lap, fd2, rtol=1e-5, atol=1e-6)

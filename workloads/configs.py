@@ -193,6 +193,37 @@ def tiny_3nuc_10e(n_walkers=64, n_steps=1000, seed_offset=1) -> Workload:
     return Workload(sysd, r0, disp, unif, 0.3)
 
 
+def slater_4nuc_20e(n_walkers=32, n_steps=200, seed_offset=5) -> Workload:
+    """Mixed Slater / Gaussian basis (eq. slater, eq. gaussian): 4 nuclei
+    (Z = 2, 4, 6, 8) in an 8-bohr cube, 20 electrons (10 up / 10 down), per
+    atom 2 Slater s + 1 Gaussian s + 1 Slater p + 1 Gaussian p + 1 Slater d
+    shells (14 functions, L = 56); Slater zeta log-uniform in [0.5, 5], Gaussian
+    zeta log-uniform in [0.1, 10]; Lambda symmetric N(0,1)/56; Pade one- and
+    two-body Jastrow with b = 1."""
+    rng = np.random.default_rng(SEED_BASE + seed_offset)
+    Z = np.array([2.0, 4.0, 6.0, 8.0])
+    R = _place_nuclei(rng, 4, 8.0)
+    shells = [(0, 1), (0, 1), (0, 0), (1, 1), (1, 0), (2, 1)]   # (l, radial)
+    center, l, m, zeta, radial = [], [], [], [], []
+    for a in range(4):
+        for ll, rad in shells:
+            z = float(_log_uniform(rng, 0.5, 5.0, 1)[0] if rad else _log_uniform(rng, 0.1, 10.0, 1)[0])
+            for mm in range(N_COMP[ll]):
+                center.append(a); l.append(ll); m.append(mm); zeta.append(z); radial.append(rad)
+    L = len(center)
+    lam = _sym_gaussian(rng, L, 1.0 / L)
+    sysd = System(
+        name="slater_4nuc_20e", R=R, Z=Z,
+        center=np.array(center, np.int32), l=np.array(l, np.int32),
+        m=np.array(m, np.int32), zeta=np.array(zeta, np.float64),
+        radial=np.array(radial, np.int32), lam=lam, n_up=10, n_dn=10,
+        unpaired=np.zeros((L, 0)), j1_form=2, j1_b=np.ones(4),
+        j2_form=1, j2=np.array([1.0, 1.0]), refresh_every=32)
+    r0 = _initial_positions(rng, R, Z, 10, 10, n_walkers)
+    disp, unif = _chain_arrays(rng, n_steps, n_walkers, 0.3)
+    return Workload(sysd, r0, disp, unif, 0.3)
+
+
 def mol_40nuc_160e(n_walkers=1024, n_steps=0, seed_offset=2) -> Workload:
     """40 nuclei (20 H, 10 C, 10 O) in a 20-bohr cube (min separation 1 bohr),
     160 electrons (80/80), per atom 4 s + 2 p + 1 d shells (15 functions,
@@ -333,6 +364,7 @@ def with_walkers(w: Workload, n_walkers: int) -> Workload:
 
 WORKLOADS = {
     "tiny_3nuc_10e": tiny_3nuc_10e,
+    "slater_4nuc_20e": slater_4nuc_20e,
     "mol_40nuc_160e": mol_40nuc_160e,
     "forces_20nuc_80e": forces_20nuc_80e,
     "large_256nuc_1024e": large_256nuc_1024e,
