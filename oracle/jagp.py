@@ -59,10 +59,23 @@ class OSystem:
     j1_b: torch.Tensor     # [A]
     j2_form: int
     j2: torch.Tensor       # [n_j2]
+    # Jastrow basis chi and the coefficients of onebody_J_inh / threebody_jastrow
+    # (LJ = 0: absent)
+    jb_center: Optional[torch.Tensor] = None   # [LJ] long
+    jb_l: Optional[torch.Tensor] = None
+    jb_m: Optional[torch.Tensor] = None
+    jb_radial: Optional[torch.Tensor] = None
+    jb_zeta: Optional[torch.Tensor] = None     # [LJ]
+    j1_inh: Optional[torch.Tensor] = None      # [2, LJ] up, down
+    j3: Optional[torch.Tensor] = None          # [3, LJ, LJ] up-up, down-down, up-down
 
     @property
     def n_elec(self):
         return self.n_up + self.n_dn
+
+    @property
+    def n_jbasis(self):
+        return 0 if self.jb_zeta is None else int(self.jb_zeta.shape[0])
 
 
 def from_workload_system(s) -> OSystem:
@@ -72,7 +85,10 @@ def from_workload_system(s) -> OSystem:
         m=_t(s.m, torch.long), zeta=_t(s.zeta), radial=_t(s.radial, torch.long),
         lam=_t(s.lam), unpaired=_t(s.unpaired).reshape(len(s.zeta), -1),
         n_up=int(s.n_up), n_dn=int(s.n_dn), j1_form=int(s.j1_form), j1_b=_t(s.j1_b),
-        j2_form=int(s.j2_form), j2=_t(s.j2))
+        j2_form=int(s.j2_form), j2=_t(s.j2),
+        **({} if getattr(s, "jb_zeta", None) is None else dict(
+            jb_center=_t(s.jb_center, torch.long), jb_l=_t(s.jb_l, torch.long), jb_m=_t(s.jb_m, torch.long),
+            jb_radial=_t(s.jb_radial, torch.long), jb_zeta=_t(s.jb_zeta), j1_inh=_t(s.j1_inh), j3=_t(s.j3))))
 
 
 # ---------------------------------------------------------------------------
@@ -216,6 +232,9 @@ def jastrow(sy: OSystem, r, R=None, j1_b=None, j2=None):
         J = J + f.sum(dim=(1, 2))
         g = g + (f1 / ria).unsqueeze(-1).mul(d).sum(2)
         h = h + (f2 + 2.0 * f1 / ria).sum(2)
+    if sy.n_jbasis:
+        Jx, gx, hx = _jastrow_basis_terms(sy, r, R)
+        J, g, h = J + Jx, g + gx, h + hx
     if sy.j2_form and N > 1:
         d = r.unsqueeze(2) - r.unsqueeze(1)                   # [Wk, N, N, 3]
         eye = torch.eye(N, dtype=torch.bool)
@@ -227,6 +246,57 @@ def jastrow(sy: OSystem, r, R=None, j1_b=None, j2=None):
         J = J + 0.5 * (v * off).sum(dim=(1, 2))
         g = g + ((v1 / rij) * off).unsqueeze(-1).mul(d).sum(2)
         h = h + ((v2 + 2.0 * v1 / rij) * off).sum(2)
+    return J, g, h
+
+
+class _JBasisView:
+    """The Jastrow basis dressed as a system for basis()."""
+    def __init__(self, sy: OSystem, R):
+        self.R, self.center, self.l, self.m = R, sy.jb_center, sy.jb_l, sy.jb_m
+        self.zeta, self.radial = sy.jb_zeta, sy.jb_radial
+
+
+def _jastrow_basis_terms(sy: OSystem, r, R=None):
+    """J1 inhomogeneous and J3/4 (onebody_J_inh, threebody_jastrow) with
+    per-electron gradients and Laplacians.
+
+      J1inh = sum_i m_{s_i} . chi(r_i)
+      J3/4  = sum_{i<j} chi(r_i)^T M^{s_i s_j} chi(r_j)
+    Up electrons come first, so a pair i < j of unlike spins is (up, down) and
+    uses M^{ud}; same-spin matrices are symmetric (the pair term must not
+    depend on the order of two same-spin electrons), M^{du} = (M^{ud})^T.
+    The pair sum is written out over all pairs; electron i's term is linear
+    in chi(r_i), so grad_i and lap_i act on chi(r_i) alone.
+    """
+    R = sy.R if R is None else R
+    chi, gchi, lchi = basis(_JBasisView(sy, R), r)          # [Wk, N, LJ], [.., 3], [..]
+    Wk, N, LJ = chi.shape
+    nu = sy.n_up
+    up = torch.arange(N) < nu
+    m = torch.where(up.view(1, N, 1), sy.j1_inh[0].view(1, 1, LJ), sy.j1_inh[1].view(1, 1, LJ))
+    J = (m * chi).sum(dim=(1, 2))
+    g = torch.einsum('wikx,wik->wix', gchi, m.expand(Wk, N, LJ))
+    h = (lchi * m).sum(-1)
+    # Mt[i, j]: the matrix that multiplies chi(r_j) in electron i's pair term
+    Muu, Mdd, Mud = sy.j3[0], sy.j3[1], sy.j3[2]
+    Mt = torch.empty(N, N, LJ, LJ, dtype=DT)
+    for i in range(N):
+        for j in range(N):
+            if up[i] and up[j]:
+                Mt[i, j] = Muu
+            elif not up[i] and not up[j]:
+                Mt[i, j] = Mdd
+            elif up[i]:
+                Mt[i, j] = Mud
+            else:
+                Mt[i, j] = Mud.T
+    B = torch.einsum('ijkl,wjl->wijk', Mt, chi)               # [Wk, i, j, LJ]: Mt[i,j] chi_j
+    off = (~torch.eye(N, dtype=torch.bool)).to(DT).view(1, N, N, 1)
+    K = (B * off).sum(2)                                      # [Wk, N, LJ]
+    iu = torch.triu_indices(N, N, 1)
+    J = J + (chi[:, iu[0]] * B[:, iu[0], iu[1]]).sum(dim=(1, 2))
+    g = g + torch.einsum('wikx,wik->wix', gchi, K)
+    h = h + (lchi * K).sum(-1)
     return J, g, h
 
 

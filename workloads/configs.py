@@ -55,6 +55,18 @@ class System:
     j2: np.ndarray           # [n_j2] float64
     refresh_every: int = 32
     band_cutoff: float = 0.0  # 0 means dense Lambda
+    # Jastrow basis chi (onebody_J_inh, threebody_jastrow); absent when jb_zeta is None
+    jb_center: Optional[np.ndarray] = None   # [LJ] int32
+    jb_l: Optional[np.ndarray] = None        # [LJ] int32
+    jb_m: Optional[np.ndarray] = None        # [LJ] int32
+    jb_radial: Optional[np.ndarray] = None   # [LJ] int32
+    jb_zeta: Optional[np.ndarray] = None     # [LJ] float64
+    j1_inh: Optional[np.ndarray] = None      # [2, LJ] coefficients of chi for up / down electrons
+    j3: Optional[np.ndarray] = None          # [3, LJ, LJ] up-up, down-down (symmetric), up-down
+
+    @property
+    def n_jbasis(self) -> int:
+        return 0 if self.jb_zeta is None else int(self.jb_zeta.shape[0])
 
     @property
     def n_elec(self) -> int:
@@ -224,6 +236,56 @@ def slater_4nuc_20e(n_walkers=32, n_steps=200, seed_offset=5) -> Workload:
     return Workload(sysd, r0, disp, unif, 0.3)
 
 
+def add_jastrow_basis(sysd: System, rng, shells=((0, 0), (0, 0), (1, 0)), zrange=(0.2, 3.0),
+                      scale_1=0.1, scale_3=0.05) -> System:
+    """A copy of sysd with a Jastrow basis of the given (l, radial) shells on
+    every nucleus (zeta log-uniform in zrange, one per shell), one-body
+    inhomogeneous coefficients N(0, scale_1^2) per spin, and three/four-body
+    matrices: up-up and down-down symmetric N(0, scale_3^2) (upper triangle
+    mirrored), up-down N(0, scale_3^2)."""
+    center, l, m, radial, zeta = [], [], [], [], []
+    for a in range(len(sysd.Z)):
+        for ll, rad in shells:
+            z = float(_log_uniform(rng, zrange[0], zrange[1], 1)[0])
+            for mm in range(N_COMP[ll]):
+                center.append(a); l.append(ll); m.append(mm); radial.append(rad); zeta.append(z)
+    LJ = len(center)
+    j3 = np.stack([_sym_gaussian(rng, LJ, scale_3), _sym_gaussian(rng, LJ, scale_3),
+                   rng.standard_normal((LJ, LJ)) * scale_3])
+    return replace(sysd, name=sysd.name + "_j3", jb_center=np.array(center, np.int32),
+                   jb_l=np.array(l, np.int32), jb_m=np.array(m, np.int32),
+                   jb_radial=np.array(radial, np.int32), jb_zeta=np.array(zeta, np.float64),
+                   j1_inh=rng.standard_normal((2, LJ)) * scale_1, j3=j3)
+
+
+def jas3_4nuc_20e(n_walkers=32, n_steps=200, seed_offset=6) -> Workload:
+    """The geometry and Gaussian geminal basis of a 4-nucleus, 20-electron
+    system (Z = 2, 4, 6, 8, 8-bohr cube, per atom 3 s + 1 p + 1 d Gaussian
+    shells, L = 44, Lambda symmetric N(0,1)/44, Pade J1 and J2 with b = 1) with
+    a Jastrow basis of 2 s + 1 p Gaussian shells per atom (LJ = 20), J1
+    inhomogeneous and J3/4 terms (onebody_J_inh, threebody_jastrow)."""
+    rng = np.random.default_rng(SEED_BASE + seed_offset)
+    Z = np.array([2.0, 4.0, 6.0, 8.0])
+    R = _place_nuclei(rng, 4, 8.0)
+    center, l, m = [], [], []
+    zeta = []
+    for a in range(4):
+        for ll in (0, 0, 0, 1, 2):
+            z = float(_log_uniform(rng, 0.1, 10.0, 1)[0])
+            for mm in range(N_COMP[ll]):
+                center.append(a); l.append(ll); m.append(mm); zeta.append(z)
+    L = len(center)
+    sysd = System(
+        name="jas3_4nuc_20e", R=R, Z=Z, center=np.array(center, np.int32), l=np.array(l, np.int32),
+        m=np.array(m, np.int32), zeta=np.array(zeta, np.float64), radial=np.zeros(L, np.int32),
+        lam=_sym_gaussian(rng, L, 1.0 / L), n_up=10, n_dn=10, unpaired=np.zeros((L, 0)),
+        j1_form=2, j1_b=np.ones(4), j2_form=1, j2=np.array([1.0, 1.0]), refresh_every=32)
+    sysd = add_jastrow_basis(sysd, rng)
+    r0 = _initial_positions(rng, R, Z, 10, 10, n_walkers)
+    disp, unif = _chain_arrays(rng, n_steps, n_walkers, 0.3)
+    return Workload(sysd, r0, disp, unif, 0.3)
+
+
 def mol_40nuc_160e(n_walkers=1024, n_steps=0, seed_offset=2) -> Workload:
     """40 nuclei (20 H, 10 C, 10 O) in a 20-bohr cube (min separation 1 bohr),
     160 electrons (80/80), per atom 4 s + 2 p + 1 d shells (15 functions,
@@ -365,6 +427,7 @@ def with_walkers(w: Workload, n_walkers: int) -> Workload:
 WORKLOADS = {
     "tiny_3nuc_10e": tiny_3nuc_10e,
     "slater_4nuc_20e": slater_4nuc_20e,
+    "jas3_4nuc_20e": jas3_4nuc_20e,
     "mol_40nuc_160e": mol_40nuc_160e,
     "forces_20nuc_80e": forces_20nuc_80e,
     "large_256nuc_1024e": large_256nuc_1024e,
