@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define QMC_ABI_VERSION 3
+#define QMC_ABI_VERSION 4
 
 typedef enum {
   QMC_OK = 0,
@@ -101,6 +101,23 @@ typedef struct {
   int32_t refresh_every;      /* recompute W^{-1} from W after this many
                                  attempted moves of one spin (>= 1; at most 64
                                  are buffered, see qmc_accept_move)              */
+  /* Jastrow basis chi_k (same function kinds as the geminal basis) for the
+   * one-body inhomogeneous and three/four-body terms (onebody_J_inh,
+   * threebody_jastrow):
+   *   J1inh = sum_i sum_k j1_inh[s_i][k] chi_k(r_i)
+   *   J3/4  = sum_{i<j} sum_{k,l} chi_k(r_i) M^{s_i s_j}[k][l] chi_l(r_j)
+   * Up electrons come first, so unlike-spin pairs i < j use M^{ud}; the
+   * same-spin matrices must be symmetric.  n_jbasis = 0: no such terms.
+   * Not supported with them: qmc_forces, qmc_multi_*, moving nuclei
+   * through qmc_system_set_params. */
+  int32_t n_jbasis;           /* LJ <= 1024                                      */
+  const int32_t *jb_center;   /* [LJ] nucleus index                              */
+  const int32_t *jb_l;        /* [LJ] 0..2                                       */
+  const int32_t *jb_m;        /* [LJ] component index                            */
+  const int32_t *jb_radial;   /* [LJ] 0 Gaussian, 1 Slater (may be NULL: all 0)  */
+  const double *jb_zeta;      /* [LJ]                                            */
+  const double *j1_inh;       /* [2][LJ] coefficients for up, then down electrons */
+  const double *j3;           /* [3][LJ][LJ] M^{uu}, M^{dd} (symmetric), M^{ud}   */
 } qmc_system_desc;
 
 /* Version of this header the library was built from (QMC_ABI_VERSION). */

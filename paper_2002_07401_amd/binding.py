@@ -68,6 +68,9 @@ class SystemDesc(ctypes.Structure):
         ("j1_form", ctypes.c_int32), ("j1_b", ctypes.c_void_p), ("j2_form", ctypes.c_int32),
         ("n_j2", ctypes.c_int32), ("j2", ctypes.c_void_p), ("precision", ctypes.c_int32),
         ("refresh_every", ctypes.c_int32),
+        ("n_jbasis", ctypes.c_int32), ("jb_center", ctypes.c_void_p), ("jb_l", ctypes.c_void_p),
+        ("jb_m", ctypes.c_void_p), ("jb_radial", ctypes.c_void_p), ("jb_zeta", ctypes.c_void_p),
+        ("j1_inh", ctypes.c_void_p), ("j3", ctypes.c_void_p),
     ]
 
 
@@ -145,6 +148,14 @@ class JAGPSystem:
             m=np.ascontiguousarray(s.m, np.int32), radial=np.ascontiguousarray(s.radial, np.int32),
             zeta=np.ascontiguousarray(s.zeta, np.float64), lam=np.ascontiguousarray(s.lam, np.float64),
             j1_b=np.ascontiguousarray(s.j1_b, np.float64), j2=np.ascontiguousarray(s.j2, np.float64))
+        LJ = 0 if getattr(s, "jb_zeta", None) is None else len(s.jb_zeta)
+        if LJ:
+            keep.update(jb_center=np.ascontiguousarray(s.jb_center, np.int32),
+                        jb_l=np.ascontiguousarray(s.jb_l, np.int32), jb_m=np.ascontiguousarray(s.jb_m, np.int32),
+                        jb_radial=np.ascontiguousarray(s.jb_radial, np.int32),
+                        jb_zeta=np.ascontiguousarray(s.jb_zeta, np.float64),
+                        j1_inh=np.ascontiguousarray(s.j1_inh, np.float64),
+                        j3=np.ascontiguousarray(s.j3, np.float64))
         p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
         d = SystemDesc(
             n_nuc=len(s.Z), R=p(keep["R"]), Z=p(keep["Z"]), n_basis=len(s.zeta),
@@ -152,7 +163,11 @@ class JAGPSystem:
             zeta=p(keep["zeta"]), lambda_=p(keep["lam"]), n_up=s.n_up, n_dn=s.n_dn,
             j1_form=s.j1_form, j1_b=p(keep["j1_b"]), j2_form=s.j2_form, n_j2=len(s.j2),
             j2=p(keep["j2"]), precision=precision,
-            refresh_every=s.refresh_every if refresh_every is None else refresh_every)
+            refresh_every=s.refresh_every if refresh_every is None else refresh_every,
+            n_jbasis=LJ,
+            **({} if not LJ else dict(jb_center=p(keep["jb_center"]), jb_l=p(keep["jb_l"]), jb_m=p(keep["jb_m"]),
+                                      jb_radial=p(keep["jb_radial"]), jb_zeta=p(keep["jb_zeta"]),
+                                      j1_inh=p(keep["j1_inh"]), j3=p(keep["j3"]))))
         h = ctypes.c_void_p()
         _check(lib.qmc_system_create(ctypes.byref(d), ctypes.byref(h)))
         self.h = h

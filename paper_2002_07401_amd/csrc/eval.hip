@@ -146,6 +146,12 @@ jastrow_assemble_kernel(SysDev s, WalkDev w, double* __restrict__ logabs_o, doub
         h += v2 + 2.0 * q;
       }
     }
+    if (s.LJ) {   // Jastrow-basis terms (one-body inhomogeneous, three/four-body)
+      const double* e3 = w.j3e + ((long)wk * s.N + i) * 5;
+      Jp += e3[0];
+      gx += e3[1]; gy += e3[2]; gz += e3[3];
+      h += e3[4];
+    }
     const double* Di = w.D + ((long)wk * s.N + i) * 4;
     const double ddx = Di[0], ddy = Di[1], ddz = Di[2], dl = Di[3];
     Kp += dl + 2.0 * (ddx * gx + ddy * gy + ddz * gz) + h + gx * gx + gy * gy + gz * gz;

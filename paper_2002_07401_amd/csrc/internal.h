@@ -25,6 +25,7 @@ constexpr int kPropRowsF64 = 8, kPropRowsNarrow = 16;
 static_assert(kPropRowsF64 >= kPropRowsMin && kPropRowsNarrow >= kPropRowsMin, "partial-sum buffer too small");
 constexpr int kMaxNucBack = 256;  // nuclei handled by the Jastrow backward kernel
 constexpr int kFuseMaxLp = 1024;   // accept fused with the next set-up: psi(r') staged in LDS
+constexpr int kMaxLJ = 1024;       // Jastrow basis functions (J1 inhomogeneous, J3/4)
 constexpr int kBigMaxN = 1024;    // blocked Gauss-Jordan limit
 constexpr int kWbMax = 64;        // capacity of the delayed-update buffer (moves between refreshes)
 constexpr int kGjPanel = 64;      // panel width of the blocked Gauss-Jordan
@@ -89,6 +90,12 @@ struct SysDev {
   uint8_t* lam_mask;
   uint8_t* lamT_mask;
   int np;           // n rounded up to 64 (blocked Gauss-Jordan, n > kLuRowMax)
+  // Jastrow basis chi (onebody_J_inh, threebody_jastrow); LJ = 0: absent
+  int LJ;
+  double4* jbfn;    // [LJ] centre and zeta
+  int* jkind;       // [LJ] as kind
+  double* jm;       // [2][LJ] one-body inhomogeneous coefficients, up then down
+  double* M3;       // [2LJ][2LJ] [[M_uu, M_ud], [M_ud^T, M_dd]] (symmetric)
 };
 
 // Device state of a batch of walkers.
@@ -142,6 +149,15 @@ struct WalkDev {
   double* v0;         // [Wk][n] A0's column / row e of the pending proposal
   double* tz;         // [Wk][2][kb] t = D^T v0 and z = S^{-1} t of the pending proposal
   int kb;             // buffer capacity (<= kWbMax)
+  // Jastrow-basis state (LJ > 0): chi(r_i), h_i = M^{ss} chi(r_i) over the
+  // electron's own spin block, G_s = sum of M^{s s'} chi(r_j) over all j of
+  // spin s' (i.e. [G_u; G_d] = M3 [X_u; X_d], X_s = sum_{j in s} chi(r_j)),
+  // chi at the pending proposal's r', and per-electron evaluation terms
+  double* chi;        // [Wk][N][LJ]
+  double* hv;         // [Wk][N][LJ]
+  double* G3;         // [Wk][2][LJ]
+  double* chi_new;    // [Wk][LJ]
+  double* j3e;        // [Wk][N][5] value part, gradient (3), Laplacian
 };
 
 // Workspace of the reverse pass (allocated on the first qmc_forces call).
@@ -277,23 +293,29 @@ __device__ __forceinline__ double angular_value(int kind, double x, double y, do
   }
 }
 
-// Basis function mu at point (px,py,pz): value only.  The centre and the
-// exponent come from one packed record (one memory round trip).
-__device__ __forceinline__ double basis_value(const SysDev& s, int mu, double px, double py, double pz) {
-  const double4 f = s.bfn[mu];
+// Function mu of a basis table (packed centre + zeta, kind) at point
+// (px,py,pz): value only.  One packed record per function (one round trip).
+__device__ __forceinline__ double basis_value_tab(const double4* __restrict__ bfn, const int* __restrict__ kinds,
+                                                  int mu, double px, double py, double pz) {
+  const double4 f = bfn[mu];
   const double x = px - f.x, y = py - f.y, z = pz - f.z;
   const double r2 = x * x + y * y + z * z;
-  const int k = s.kind[mu];
+  const int k = kinds[mu];
   return angular_value(kind_ang(k), x, y, z) * radial_e(k, f.w, r2);
 }
 
+__device__ __forceinline__ double basis_value(const SysDev& s, int mu, double px, double py, double pz) {
+  return basis_value_tab(s.bfn, s.kind, mu, px, py, pz);
+}
+
 // Value, gradient and Laplacian (see Radial).
-__device__ __forceinline__ void basis_vgl(const SysDev& s, int mu, double px, double py, double pz,
-                                          double& v, double& gx, double& gy, double& gz, double& lap) {
-  const double4 f = s.bfn[mu];
+__device__ __forceinline__ void basis_vgl_tab(const double4* __restrict__ bfn, const int* __restrict__ kinds, int mu,
+                                              double px, double py, double pz, double& v, double& gx, double& gy,
+                                              double& gz, double& lap) {
+  const double4 f = bfn[mu];
   const double x = px - f.x, y = py - f.y, z = pz - f.z;
   const double r2 = x * x + y * y + z * z;
-  const int k = s.kind[mu];
+  const int k = kinds[mu];
   double P, Px, Py, Pz;
   angular(kind_ang(k), x, y, z, P, Px, Py, Pz);
   const Radial rd = radial_all(k, f.w, r2);
@@ -303,6 +325,11 @@ __device__ __forceinline__ void basis_vgl(const SysDev& s, int mu, double px, do
   gy = (Py + t * y) * rd.e;
   gz = (Pz + t * z) * rd.e;
   lap = rd.cl * v;
+}
+
+__device__ __forceinline__ void basis_vgl(const SysDev& s, int mu, double px, double py, double pz,
+                                          double& v, double& gx, double& gy, double& gz, double& lap) {
+  basis_vgl_tab(s.bfn, s.kind, mu, px, py, pz, v, gx, gy, gz, lap);
 }
 
 // One-body term f(r) = -(2Z)^{3/4} u((2Z)^{1/4} r) and its radial derivatives.
@@ -382,6 +409,8 @@ hipError_t launch_Y_build(const SysDev& s, const WalkDev& w, hipStream_t st);
 hipError_t launch_lu_inverse(const SysDev& s, const WalkDev& w, hipStream_t st);
 hipError_t launch_lam_mask(const SysDev& s, hipStream_t st);
 hipError_t launch_rowdots(const SysDev& s, const WalkDev& w, hipStream_t st);
+// Jastrow-basis terms of an evaluation (LJ > 0): chi, X -> G, h, per-electron terms
+hipError_t launch_jastrow3_eval(const SysDev& s, const WalkDev& w, hipStream_t st);
 hipError_t launch_jastrow_assemble(const SysDev& s, const WalkDev& w, double* logabs, double* sign,
                                    double* drift, double* e_kin, double* e_loc, int32_t* status,
                                    hipStream_t st);

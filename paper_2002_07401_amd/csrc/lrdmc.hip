@@ -118,6 +118,18 @@ __global__ __launch_bounds__(256) void lrdmc_ratio_kernel(SysDev s, WalkDev w, L
       }
     }
   }
+  if (s.LJ) {   // Jastrow-basis change (chi(r'_k) - chi(r_i)) . (G_s - h_i + m_s)
+    const int LJ = s.LJ, sp = i < s.nu ? 0 : 1;
+    const double* ci = w.chi + ((long)wk * s.N + i) * LJ;
+    const double* hi = w.hv + ((long)wk * s.N + i) * LJ;
+    const double* G = w.G3 + ((long)wk * 2 + sp) * LJ;
+    const double* m = s.jm + (long)sp * LJ;
+    for (int q = lane; q < LJ; q += 64) {
+      const double g = G[q] - hi[q] + m[q], c0 = ci[q];
+#pragma unroll
+      for (int k = 0; k < kHops; ++k) dj[k] += (basis_value_tab(s.jbfn, s.jkind, q, px[k], py[k], pz[k]) - c0) * g;
+    }
+  }
 #pragma unroll
   for (int k = 0; k < kHops; ++k) {
     c[k] = wave_sum(c[k]);

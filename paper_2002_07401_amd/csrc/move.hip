@@ -180,7 +180,7 @@ hipError_t launch_metropolis_accept(const SysDev& s, const WalkDev& w, int e, co
 
 hipError_t launch_metropolis_accept_prep(const SysDev& s, const WalkDev& w, int e, const double* unif,
                                          int32_t* accept_count, int e2, const double* disp2, hipStream_t st) {
-  if (s.nu > kBigMaxN || !w.wv || s.Lp > kFuseMaxLp || e2 == e) return hipErrorNotSupported;
+  if (s.nu > kBigMaxN || !w.wv || s.Lp > kFuseMaxLp || e2 == e || s.LJ > 0) return hipErrorNotSupported;
   const int S = propose_splits(s);
   const dim3 grid(w.Wk), blk(256);
   if (s.bf16())

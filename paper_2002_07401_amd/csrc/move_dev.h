@@ -135,7 +135,31 @@ __device__ void prep_body(const SysDev& s, const WalkDev& w, int wk, int e, cons
   double jn, gxn, gyn, gzn, jo, d0, d1, d2;
   jastrow_one(s, r, e, px, py, pz, DRIFT, jn, gxn, gyn, gzn);
   jastrow_one(s, r, e, r[3 * e], r[3 * e + 1], r[3 * e + 2], false, jo, d0, d1, d2);
-  const double dJ = block_sum_mv(jn - jo, red);
+  double dj = jn - jo;
+  if (s.LJ) {
+    // chi(r') and (chi(r') - chi(r_e)) . (G_s - h_e + m_s); drift requests add
+    // grad chi(r') . (G_s - h_e + m_s)
+    const int sp = e < s.nu ? 0 : 1, LJ = s.LJ;
+    const double* ce = w.chi + ((long)wk * s.N + e) * LJ;
+    const double* he = w.hv + ((long)wk * s.N + e) * LJ;
+    const double* G = w.G3 + ((long)wk * 2 + sp) * LJ;
+    const double* m = s.jm + (long)sp * LJ;
+    double* cn = w.chi_new + (long)wk * LJ;
+    for (int k = tid; k < LJ; k += blockDim.x) {
+      const double g = G[k] - he[k] + m[k];
+      double v;
+      if (DRIFT) {
+        double vx, vy, vz, vl;
+        basis_vgl_tab(s.jbfn, s.jkind, k, px, py, pz, v, vx, vy, vz, vl);
+        gxn += vx * g; gyn += vy * g; gzn += vz * g;
+      } else {
+        v = basis_value_tab(s.jbfn, s.jkind, k, px, py, pz);
+      }
+      cn[k] = v;
+      dj += (v - ce[k]) * g;
+    }
+  }
+  const double dJ = block_sum_mv(dj, red);
   if (DRIFT) {
     gxn = block_sum_mv(gxn, red); gyn = block_sum_mv(gyn, red); gzn = block_sum_mv(gzn, red);
   }
@@ -328,6 +352,33 @@ template <typename T>
 __device__ void accept_apply(const SysDev& s, const WalkDev& w, int wk, int e, double R, int m,
                              int32_t* __restrict__ cnt);
 
+// Jastrow-basis state after electron e (spin s) moved: with dchi = chi(r') - chi(r_e),
+// [G_u; G_d] += M3[:, s block] dchi, h_e = M^{ss} chi(r'), chi_e = chi(r').
+// Called by every thread of the workgroup (block-uniform).
+__device__ void jastrow3_accept(const SysDev& s, const WalkDev& w, int wk, int e) {
+  const int LJ = s.LJ, sp = e < s.nu ? 0 : 1;
+  double* ce = w.chi + ((long)wk * s.N + e) * LJ;
+  const double* cn = w.chi_new + (long)wk * LJ;
+  double* G = w.G3 + (long)wk * 2 * LJ;
+  double* he = w.hv + ((long)wk * s.N + e) * LJ;
+  for (int o = threadIdx.x; o < 3 * LJ; o += blockDim.x) {
+    if (o < 2 * LJ) {
+      const double* row = s.M3 + (long)o * 2 * LJ + (long)sp * LJ;
+      double g = 0.0;
+      for (int k = 0; k < LJ; ++k) g += row[k] * (cn[k] - ce[k]);
+      G[o] += g;
+    } else {
+      const int j = o - 2 * LJ;
+      const double* row = s.M3 + ((long)sp * LJ + j) * 2 * LJ + (long)sp * LJ;
+      double h = 0.0;
+      for (int k = 0; k < LJ; ++k) h += row[k] * cn[k];
+      he[j] = h;
+    }
+  }
+  __syncthreads();   // every read of chi_e is done
+  for (int k = threadIdx.x; k < LJ; k += blockDim.x) ce[k] = cn[k];
+}
+
 // acc_in: this walker's host decision (mode 0), or u: its uniform (mode 1).
 // cnt: this walker's accept counter (may be null).
 template <typename T>
@@ -425,6 +476,7 @@ __device__ void accept_apply(const SysDev& s, const WalkDev& w, int wk, int e, d
   T* prow = (T*)w.phi + ((long)wk * s.N + e) * s.Lp;
   const double* pn = w.psi_new + (long)wk * s.Lp;
   for (int mu = tid; mu < s.L; mu += blockDim.x) prow[mu] = (T)pn[mu];
+  if (s.LJ) jastrow3_accept(s, w, wk, e);
   if (tid == 0) {
     w.wm[wk] = m + 1;
     double* re = w.r + ((long)wk * s.N + e) * 3;

@@ -196,6 +196,42 @@ extern "C" qmc_status qmc_system_create(const qmc_system_desc* desc, qmc_system*
   for (int k = 0; k < 8; ++k) d.j2[k] = (q.j2 && k < q.n_j2) ? q.j2[k] : 0.0;
   d.precision = q.precision; d.refresh_every = q.refresh_every;
   d.np = round_up(d.nu, 64);
+  // Jastrow basis (onebody_J_inh, threebody_jastrow)
+  const int LJ = q.n_jbasis;
+  if (LJ < 0 || LJ > kMaxLJ) return fail(QMC_ERR_UNSUPPORTED, "Jastrow basis of more than 1024 functions");
+  std::vector<double> jb4(4 * (size_t)LJ), M3((size_t)4 * LJ * LJ), jm(2 * (size_t)LJ);
+  std::vector<int> jkind(LJ);
+  if (LJ > 0) {
+    if (!q.jb_center || !q.jb_l || !q.jb_m || !q.jb_zeta || !q.j1_inh || !q.j3)
+      return fail(QMC_ERR_ARG, "Jastrow basis arrays missing");
+    for (int k = 0; k < LJ; ++k) {
+      const int c = q.jb_center[k], l = q.jb_l[k], m = q.jb_m[k], rad = q.jb_radial ? q.jb_radial[k] : 0;
+      if (c < 0 || c >= q.n_nuc) return fail(QMC_ERR_ARG, "Jastrow basis center out of range");
+      if (l < 0 || l > 2) return fail(QMC_ERR_UNSUPPORTED, "Jastrow basis l > 2 not built");
+      if (m < 0 || m >= 2 * l + 1) return fail(QMC_ERR_ARG, "Jastrow basis component out of range");
+      if (rad != 0 && rad != 1) return fail(QMC_ERR_ARG, "Jastrow basis radial must be 0 or 1");
+      jkind[k] = ((l == 0) ? 0 : (l == 1 ? 1 + m : 4 + m)) | (rad ? kSlaterBit : 0);
+      jb4[4 * k] = q.R[3 * c]; jb4[4 * k + 1] = q.R[3 * c + 1]; jb4[4 * k + 2] = q.R[3 * c + 2];
+      jb4[4 * k + 3] = q.jb_zeta[k];
+    }
+    const double* Muu = q.j3;
+    const double* Mdd = q.j3 + (size_t)LJ * LJ;
+    const double* Mud = q.j3 + 2 * (size_t)LJ * LJ;
+    double mx = 0.0;
+    for (size_t k = 0; k < 2 * (size_t)LJ * LJ; ++k) mx = std::max(mx, std::fabs(q.j3[k]));
+    for (int a = 0; a < LJ; ++a)
+      for (int b = 0; b < LJ; ++b) {
+        if (std::fabs(Muu[a * LJ + b] - Muu[b * LJ + a]) > 1e-12 * mx ||
+            std::fabs(Mdd[a * LJ + b] - Mdd[b * LJ + a]) > 1e-12 * mx)
+          return fail(QMC_ERR_ARG, "same-spin three/four-body matrices must be symmetric");
+        const size_t n2 = 2 * (size_t)LJ;
+        M3[a * n2 + b] = Muu[a * LJ + b];
+        M3[(LJ + a) * n2 + LJ + b] = Mdd[a * LJ + b];
+        M3[a * n2 + LJ + b] = Mud[a * LJ + b];
+        M3[(LJ + b) * n2 + a] = Mud[a * LJ + b];
+      }
+    for (int k = 0; k < 2 * LJ; ++k) jm[k] = q.j1_inh[k];
+  }
   const int Lp = d.Lp, A = q.n_nuc;
   std::vector<double> lam((size_t)Lp * Lp, 0.0), lamT((size_t)Lp * Lp, 0.0);
   for (int i = 0; i < L; ++i)
@@ -222,6 +258,13 @@ extern "C" qmc_status qmc_system_create(const qmc_system_desc* desc, qmc_system*
   if (!e) e = up((void**)&d.lamT, lamT.data(), sizeof(double) * lamT.size());
   if (!e) e = up((void**)&d.cptr, cptr.data(), sizeof(int) * cptr.size());
   if (!e) e = up((void**)&d.cmu, cmu.data(), sizeof(int) * cmu.size());
+  d.LJ = LJ;
+  if (!e && LJ > 0) {
+    e = up((void**)&d.jbfn, jb4.data(), sizeof(double) * jb4.size());
+    if (!e) e = up((void**)&d.jkind, jkind.data(), sizeof(int) * jkind.size());
+    if (!e) e = up((void**)&d.jm, jm.data(), sizeof(double) * jm.size());
+    if (!e) e = up((void**)&d.M3, M3.data(), sizeof(double) * M3.size());
+  }
   if (!e) {
     std::vector<double> bf(4 * (size_t)L);
     for (int mu = 0; mu < L; ++mu) {
@@ -331,6 +374,14 @@ extern "C" qmc_status qmc_walkers_create(qmc_system* sys, int32_t n_walkers, qmc
     al((void**)&d.tz, sizeof(double) * Wk * 2 * kb);
     al((void**)&wk->rd_scratch, sizeof(double) * Wk * kb * n);
   }
+  if (s.LJ > 0) {
+    const size_t LJ = s.LJ;
+    al((void**)&d.chi, sizeof(double) * Wk * N * LJ);
+    al((void**)&d.hv, sizeof(double) * Wk * N * LJ);
+    al((void**)&d.G3, sizeof(double) * Wk * 2 * LJ);
+    al((void**)&d.chi_new, sizeof(double) * Wk * LJ);
+    al((void**)&d.j3e, sizeof(double) * Wk * N * 5);
+  }
   al((void**)&wk->lr.ratio, sizeof(double) * Wk * N * kHops);
   al((void**)&wk->lr.ah, sizeof(double) * Wk * N);
   al((void**)&wk->lr.terms, sizeof(double) * Wk * kLrTerms);
@@ -387,6 +438,7 @@ extern "C" qmc_status qmc_eval_batch(qmc_system* sys, qmc_walkers* wk, const dou
     TIMED(wk, QMC_T_OTHER, stream, launch_downcast(d.P64, d.P, s.bf16(), cnt, stream), "P copy");
   }
   TIMED(wk, QMC_T_ROWDOT, stream, launch_rowdots(s, d, stream), "row dots");
+  if (s.LJ) TIMED(wk, QMC_T_ASSEMBLE, stream, launch_jastrow3_eval(s, d, stream), "Jastrow basis terms");
   // E_kin and E_loc stay with the walkers (the LRDMC step reads them)
   TIMED(wk, QMC_T_ASSEMBLE, stream,
         launch_jastrow_assemble(s, d, logabs, sign, drift, wk->lr.ekin, wk->lr.eloc, status, stream), "assemble");
@@ -513,7 +565,7 @@ extern "C" qmc_status qmc_accept_move(qmc_system* sys, qmc_walkers* wk, int32_t 
 // (for e2) falls between them, and psi(r') fits the kernel's LDS stage.
 static bool fusable(const qmc_walkers* wk, int e, int e2) {
   const SysDev& s = wk->sys->d;
-  if (s.Lp > kFuseMaxLp || s.nu > kBigMaxN || !wk->d.wv || e2 == e) return false;
+  if (s.Lp > kFuseMaxLp || s.nu > kBigMaxN || !wk->d.wv || e2 == e || s.LJ > 0) return false;
   Sched q{wk->attempts, wk->since, wk->buf_spin};
   if (sched_after(s, q)) return false;
   if (sched_before(s, q, e2)) return false;
@@ -661,6 +713,7 @@ extern "C" qmc_status qmc_forces(qmc_system* sys, qmc_walkers* wk, const double*
   if (!r || !out) return fail(QMC_ERR_ARG, "null positions or output block");
   const SysDev& s = sys->d;
   if (s.precision != QMC_FP64) return fail(QMC_ERR_UNSUPPORTED, "forces are built for the FP64 path");
+  if (s.LJ > 0) return fail(QMC_ERR_UNSUPPORTED, "forces with a Jastrow basis are not built");
   if (s.N > 2 * kLuMaxN || s.n_nuc > kMaxNucBack)
     return fail(QMC_ERR_UNSUPPORTED, "forces need N <= 256 electrons and <= 256 nuclei");
   hipError_t e = alloc_adjoint(wk);
@@ -723,6 +776,7 @@ extern "C" qmc_status qmc_system_set_params(qmc_system* sys, const double* R, co
                                             const double* lambda, const double* jas, hipStream_t stream) {
   if (!sys) return fail(QMC_ERR_ARG, "null system");
   SysDev& d = sys->d;
+  if (R && d.LJ > 0) return fail(QMC_ERR_UNSUPPORTED, "moving nuclei with a Jastrow basis is not built");
   if (R) HIP_TRY(hipMemcpyAsync(d.R, R, sizeof(double) * 3 * d.n_nuc, hipMemcpyDeviceToDevice, stream), "set R");
   if (zeta) HIP_TRY(hipMemcpyAsync(d.zeta, zeta, sizeof(double) * d.L, hipMemcpyDeviceToDevice, stream), "set zeta");
   if (lambda) HIP_TRY(launch_set_lambda(d, lambda, stream), "set lambda");
@@ -816,6 +870,7 @@ extern "C" qmc_status qmc_multi_create(int32_t n_members, qmc_system* const* sys
     const SysDev& s = systems[k]->d;
     if (s.precision != systems[0]->d.precision) { delete m; return fail(QMC_ERR_ARG, "members differ in precision"); }
     if (s.nu != s.nd || s.nu > kLuMaxN) { delete m; return fail(QMC_ERR_UNSUPPORTED, "members need n_up == n_dn <= 128"); }
+    if (s.LJ > 0) { delete m; return fail(QMC_ERR_UNSUPPORTED, "members with a Jastrow basis are not built"); }
     m->sys.push_back(systems[k]);
     m->wk.push_back(walkers[k]);
     m->h_sys.push_back(s);
