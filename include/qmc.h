@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define QMC_ABI_VERSION 4
+#define QMC_ABI_VERSION 5
 
 typedef enum {
   QMC_OK = 0,
@@ -226,6 +226,59 @@ typedef struct {
 qmc_status qmc_forces(qmc_system *sys, qmc_walkers *wk, const double *r, int32_t per_walker,
                       const double *gbar_logpsi, const double *gbar_eloc, const qmc_grads *out,
                       hipStream_t stream);
+
+/* Space-warp total derivatives (Atomic forces section: correlated sampling
+ * with the space-warp coordinate transformation).  With
+ * omega_a(r) = kappa_a(r) / sum_b kappa_b(r), kappa_a(r) = |r - R_a|^-4, for
+ * every walker w and nucleus a
+ *     out[w][a] = dR[w][a] + sum_i omega_a(r_i) dr[w][i]
+ *                 (+ 1/2 sum_i grad omega_a(r_i)   when jacobian != 0)
+ * i.e. the derivative of a per-walker quantity when the electrons move with
+ * the nuclei; jacobian != 0 gives that of log(J^1/2 |Psi|) from the partials
+ * of log|Psi|.  dR and dr are qmc_forces' per-walker partials (of e_L or of
+ * log|Psi|).  All pointers device, FP64, row-major:
+ *   r   [n_walkers][N][3], dR [n_walkers][A][3], dr [n_walkers][N][3],
+ *   out [n_walkers][A][3] (written; may not alias the inputs).
+ * N <= 1024.  An electron on a nucleus gives a non-finite result. */
+qmc_status qmc_swct(qmc_system *sys, int32_t n_walkers, const double *r, const double *dR, const double *dr,
+                    int32_t jacobian, double *out, hipStream_t stream);
+
+/* Finite-variance reweighting factor (Atomic forces section): for every
+ * walker, from the geminal matrix W and its inverse of the last evaluation,
+ *     R = (S sum_ij (W^-1)_ij^2)^-theta,   S = min_i sum_j W_ij^2,
+ *     weight = (R / max(R, eps))^2,
+ * the weight that turns averages over the modified sampling back into
+ * averages over |Psi|^2 (R is a distance-to-node measure: small near the
+ * node).  Needs qmc_eval_batch (or qmc_forces) since the last accepted move
+ * (QMC_ERR_STATE otherwise).  theta > 0, eps >= 0.
+ *   R      [Wk] device, written
+ *   weight [Wk] device, written, may be NULL */
+qmc_status qmc_reweight(qmc_system *sys, qmc_walkers *wk, double theta, double eps, double *R, double *weight,
+                        hipStream_t stream);
+
+/* Bytes of device workspace qmc_sr_step needs (0 for non-positive sizes). */
+size_t qmc_sr_workspace_size(int32_t n_samples, int64_t n_params);
+
+/* Stochastic-reconfiguration step (Stochastic reconfiguration section).  From
+ * the logarithmic derivatives O [n_samples][n_params] (row-major, device) and
+ * local energies e_loc [n_samples] of the samples, with optional weights
+ * [n_samples] (NULL: all 1; averages are sum w x / sum w):
+ *     Obar = <O>,  S_kl = <(O_k - Obar_k)(O_l - Obar_l)>,
+ *     f_k  = -2 <e_L (O_k - Obar_k)>,
+ * solves (S + eps diag(S)) delta = f by conjugate gradients preconditioned by
+ * the diagonal of S + eps diag(S), without forming S
+ * (each iteration streams O twice), stopping when |r| <= tol |f| or after
+ * max_iter iterations; the parameter change is dt * delta for a time step dt
+ * the caller chooses.  Every sum is taken in a fixed order, so the result is
+ * the same on every run.
+ *   delta    [n_params] device, written
+ *   force    [n_params] device, written, may be NULL
+ *   residual [1] device, written, may be NULL: |r| / |f| at exit
+ *   work     device, work_bytes >= qmc_sr_workspace_size(n_samples, n_params)
+ * The weights must be positive with a positive sum; with max_iter = 0 delta is 0. */
+qmc_status qmc_sr_step(int32_t n_samples, int64_t n_params, const double *O, const double *e_loc,
+                       const double *weights, double eps, int32_t max_iter, double tol, double *delta,
+                       double *force, double *residual, void *work, size_t work_bytes, hipStream_t stream);
 
 /* Several systems moved together (uneven electron counts).  Every phase of a
  * Metropolis step (proposal set-up, streaming rows, accept/update, periodic LU

@@ -4,4 +4,5 @@ The compute lives in libqmc_jagp.so (see include/qmc.h); `binding` marshals
 torch device tensors into its calls.
 """
 from .binding import (JAGPSystem, Walkers, QMCError, JAGPFunction, MultiSystem, philox_draws, QMC_FP64, QMC_W_FP32, QMC_MIXED, QMC_MIXED_BF16, load,  # noqa: F401
-                      STATE_R, STATE_LOGABS, STATE_SIGN, STATE_W, STATE_AINV, STATE_PHI, LR_TERMS)
+                      STATE_R, STATE_LOGABS, STATE_SIGN, STATE_W, STATE_AINV, STATE_PHI, LR_TERMS,
+                      swct, reweight, sr_step)

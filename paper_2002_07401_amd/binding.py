@@ -33,7 +33,8 @@ FUNCTIONS = (
     "qmc_accept_move", "qmc_vmc_steps", "qmc_walkers_read", "qmc_walkers_set_timing",
     "qmc_walkers_timing", "qmc_forces", "qmc_system_set_params", "qmc_multi_create",
     "qmc_multi_destroy", "qmc_multi_autotune", "qmc_multi_vmc_steps", "qmc_philox_draws",
-    "qmc_lrdmc_hops", "qmc_lrdmc_advance", "qmc_walkers_set_timing_mask",
+    "qmc_lrdmc_hops", "qmc_lrdmc_advance", "qmc_walkers_set_timing_mask", "qmc_swct", "qmc_reweight",
+    "qmc_sr_workspace_size", "qmc_sr_step",
 )
 
 TIMER_NAMES = ("basis", "P_build", "W_build", "LU", "Y_build", "rowdot", "assemble", "propose",
@@ -112,6 +113,12 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.qmc_philox_draws.argtypes = [ctypes.c_uint64, i32, i32, ctypes.c_uint64, ctypes.c_double, dp, dp, vp]
     lib.qmc_lrdmc_hops.argtypes = [vp, vp, ctypes.POINTER(LrdmcParams), dp, dp, vp]
     lib.qmc_lrdmc_advance.argtypes = [vp, vp, dp, dp, dp, dp, vp, vp]
+    lib.qmc_swct.argtypes = [vp, i32, dp, dp, dp, i32, dp, vp]
+    lib.qmc_reweight.argtypes = [vp, vp, ctypes.c_double, ctypes.c_double, dp, dp, vp]
+    lib.qmc_sr_workspace_size.restype = ctypes.c_size_t
+    lib.qmc_sr_workspace_size.argtypes = [i32, ctypes.c_int64]
+    lib.qmc_sr_step.argtypes = [i32, ctypes.c_int64, dp, dp, dp, ctypes.c_double, i32, ctypes.c_double, dp, dp,
+                                dp, vp, ctypes.c_size_t, vp]
     _lib = lib
     return lib
 
@@ -317,6 +324,47 @@ class Walkers:
         _check(load().qmc_lrdmc_advance(self.sys.h, self.h, _ptr(xi), _ptr(weight), _ptr(tau_left),
                                         _ptr(r_next), _ptr(hop), _stream(stream)))
         return r_next, hop
+
+
+def swct(system: JAGPSystem, r: torch.Tensor, dR: torch.Tensor, dr: torch.Tensor, jacobian: bool = False,
+         stream=None) -> torch.Tensor:
+    """Space-warp total derivatives [Wk, A, 3] from the per-walker partials
+    dR [Wk, A, 3] and dr [Wk, N, 3] at the positions r [Wk, N, 3]."""
+    Wk = r.shape[0]
+    A, N = system.n_nuc, system.n_elec
+    assert r.shape == (Wk, N, 3) and dR.shape == (Wk, A, 3) and dr.shape == (Wk, N, 3)
+    out = torch.empty(Wk, A, 3, dtype=torch.float64, device=r.device)
+    _check(load().qmc_swct(system.h, Wk, _ptr(r), _ptr(dR.contiguous()), _ptr(dr.contiguous()),
+                           1 if jacobian else 0, _ptr(out), _stream(stream)))
+    return out
+
+
+def reweight(walkers: Walkers, theta: float, eps: float, stream=None):
+    """Reweighting factor R [Wk] and weight [Wk] of the last evaluation."""
+    R = torch.empty(walkers.n, dtype=torch.float64, device="cuda")
+    w = torch.empty(walkers.n, dtype=torch.float64, device="cuda")
+    _check(load().qmc_reweight(walkers.sys.h, walkers.h, theta, eps, _ptr(R), _ptr(w), _stream(stream)))
+    return R, w
+
+
+def sr_step(O: torch.Tensor, e_loc: torch.Tensor, eps: float, weights: Optional[torch.Tensor] = None,
+            max_iter: int = 200, tol: float = 1e-12, work: Optional[torch.Tensor] = None, stream=None):
+    """Stochastic-reconfiguration step on the device: (delta [P], f [P],
+    relative residual [1]) from O [M, P] and e_loc [M]."""
+    M, P = O.shape
+    assert e_loc.shape == (M,) and (weights is None or weights.shape == (M,))
+    lib = load()
+    nb = lib.qmc_sr_workspace_size(M, P)
+    if work is None or work.numel() * work.element_size() < nb:
+        work = torch.empty((nb + 7) // 8, dtype=torch.float64, device=O.device)
+    delta = torch.empty(P, dtype=torch.float64, device=O.device)
+    f = torch.empty(P, dtype=torch.float64, device=O.device)
+    res = torch.empty(1, dtype=torch.float64, device=O.device)
+    _check(lib.qmc_sr_step(M, P, _ptr(O.contiguous()), _ptr(e_loc.contiguous()),
+                           _ptr(None if weights is None else weights.contiguous()), eps, max_iter, tol,
+                           _ptr(delta), _ptr(f), _ptr(res), _ptr(work), work.numel() * work.element_size(),
+                           _stream(stream)))
+    return delta, f, res
 
 
 class JAGPFunction(torch.autograd.Function):

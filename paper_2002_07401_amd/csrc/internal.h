@@ -411,6 +411,15 @@ hipError_t launch_lam_mask(const SysDev& s, hipStream_t st);
 hipError_t launch_rowdots(const SysDev& s, const WalkDev& w, hipStream_t st);
 // Jastrow-basis terms of an evaluation (LJ > 0): chi, X -> G, h, per-electron terms
 hipError_t launch_jastrow3_eval(const SysDev& s, const WalkDev& w, hipStream_t st);
+// Estimators (space warp, reweighting factor, stochastic reconfiguration)
+hipError_t launch_swct(const SysDev& s, int Wk, const double* r, const double* dR, const double* dr, int jac,
+                       double* out, hipStream_t st);
+hipError_t launch_reweight(const SysDev& s, const WalkDev& w, double theta, double eps, double* R, double* weight,
+                           hipStream_t st);
+size_t sr_workspace_doubles(int M, long P);
+hipError_t launch_sr_step(int M, long P, const double* O, const double* el, const double* wts, double eps,
+                          int max_iter, double tol, double* delta, double* force, double* resid, double* work,
+                          hipStream_t st);
 hipError_t launch_jastrow_assemble(const SysDev& s, const WalkDev& w, double* logabs, double* sign,
                                    double* drift, double* e_kin, double* e_loc, int32_t* status,
                                    hipStream_t st);

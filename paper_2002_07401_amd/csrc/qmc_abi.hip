@@ -772,6 +772,49 @@ extern "C" qmc_status qmc_lrdmc_advance(qmc_system* sys, qmc_walkers* wk, const 
   return QMC_OK;
 }
 
+// ---------------------------------------------------------------------------
+// estimators
+// ---------------------------------------------------------------------------
+
+extern "C" qmc_status qmc_swct(qmc_system* sys, int32_t n_walkers, const double* r, const double* dR,
+                               const double* dr, int32_t jacobian, double* out, hipStream_t stream) {
+  if (!sys || !r || !dR || !dr || !out) return fail(QMC_ERR_ARG, "null argument");
+  if (n_walkers <= 0) return fail(QMC_ERR_ARG, "n_walkers must be positive");
+  if (sys->d.N > 1024) return fail(QMC_ERR_UNSUPPORTED, "space warp built for N <= 1024");
+  HIP_TRY(launch_swct(sys->d, n_walkers, r, dR, dr, jacobian ? 1 : 0, out, stream), "space warp");
+  return QMC_OK;
+}
+
+extern "C" qmc_status qmc_reweight(qmc_system* sys, qmc_walkers* wk, double theta, double eps, double* R,
+                                   double* weight, hipStream_t stream) {
+  qmc_status c = check_pair(sys, wk);
+  if (c) return c;
+  if (!R) return fail(QMC_ERR_ARG, "null output");
+  if (!(theta > 0.0) || !(eps >= 0.0)) return fail(QMC_ERR_ARG, "theta > 0 and eps >= 0 required");
+  if (!wk->evaluated || !wk->yt_valid)
+    return fail(QMC_ERR_STATE, "the reweighting factor needs an evaluation since the last move");
+  HIP_TRY(launch_reweight(sys->d, wk->d, theta, eps, R, weight, stream), "reweight");
+  return QMC_OK;
+}
+
+extern "C" size_t qmc_sr_workspace_size(int32_t n_samples, int64_t n_params) {
+  if (n_samples <= 0 || n_params <= 0) return 0;
+  return sizeof(double) * sr_workspace_doubles(n_samples, (long)n_params);
+}
+
+extern "C" qmc_status qmc_sr_step(int32_t n_samples, int64_t n_params, const double* O, const double* e_loc,
+                                  const double* weights, double eps, int32_t max_iter, double tol, double* delta,
+                                  double* force, double* residual, void* work, size_t work_bytes,
+                                  hipStream_t stream) {
+  if (!O || !e_loc || !delta || !work) return fail(QMC_ERR_ARG, "null argument");
+  if (n_samples <= 0 || n_params <= 0 || max_iter < 0) return fail(QMC_ERR_ARG, "bad sizes");
+  if (!(eps >= 0.0) || !(tol >= 0.0)) return fail(QMC_ERR_ARG, "eps and tol must be >= 0");
+  if (work_bytes < qmc_sr_workspace_size(n_samples, n_params)) return fail(QMC_ERR_ARG, "workspace too small");
+  HIP_TRY(launch_sr_step(n_samples, (long)n_params, O, e_loc, weights, eps, max_iter, tol, delta, force, residual,
+                         (double*)work, stream), "SR step");
+  return QMC_OK;
+}
+
 extern "C" qmc_status qmc_system_set_params(qmc_system* sys, const double* R, const double* zeta,
                                             const double* lambda, const double* jas, hipStream_t stream) {
   if (!sys) return fail(QMC_ERR_ARG, "null system");
