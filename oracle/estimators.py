@@ -54,7 +54,7 @@ def swct_total(sy: O.OSystem, r, dR, dr, jacobian=False):
 
 def reweight(sy: O.OSystem, r, theta, eps):
     """R [Wk] and weight [Wk] from the geminal matrix of the configuration."""
-    Phi, _, _ = O.basis(sy, r)
+    Phi, _, _ = O.agp_basis(sy, r)
     W = O.geminal(sy, Phi)
     A = torch.linalg.inv(W)
     S = (W * W).sum(-1).min(-1).values

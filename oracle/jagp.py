@@ -14,6 +14,9 @@ over independent walkers:
     (agp_expansion, Lambda being the coefficient matrix A of that equation)
   * psi_mu = |r - R|^l e^{-zeta |r-R|^2} x (real solid harmonic), or the Slater
     form with e^{-zeta |r-R|} (eq. gaussian / eq. slater)
+  * optionally contracted orbitals phi_c = sum_mu C[mu, c] psi_mu in place of
+    psi in f_S and the unpaired columns (Contraction of the primitive atomic
+    basis section)
   * J = J1 + J2 with the homogeneous one-body term (onebody_J_hom), the
     bounded function u (onebody_u, plus a Pade variant) and the spin-dependent
     two-body term (twobody_jastrow, twobody_v, plus a Pade-series variant)
@@ -68,6 +71,11 @@ class OSystem:
     jb_zeta: Optional[torch.Tensor] = None     # [LJ]
     j1_inh: Optional[torch.Tensor] = None      # [2, LJ] up, down
     j3: Optional[torch.Tensor] = None          # [3, LJ, LJ] up-up, down-down, up-down
+    # contraction of the primitive basis (Contraction of the primitive atomic
+    # basis section): the geminal's orbitals are phi_c = sum_mu C[mu, c] psi_mu;
+    # center .. zeta then describe the primitives and lam / unpaired the
+    # contracted functions (None: lam / unpaired act on the primitives)
+    contraction: Optional[torch.Tensor] = None  # [L_primitive, L]
 
     @property
     def n_elec(self):
@@ -83,12 +91,13 @@ def from_workload_system(s) -> OSystem:
     return OSystem(
         R=_t(s.R), Z=_t(s.Z), center=_t(s.center, torch.long), l=_t(s.l, torch.long),
         m=_t(s.m, torch.long), zeta=_t(s.zeta), radial=_t(s.radial, torch.long),
-        lam=_t(s.lam), unpaired=_t(s.unpaired).reshape(len(s.zeta), -1),
+        lam=_t(s.lam), unpaired=_t(s.unpaired).reshape(len(s.lam), -1),
         n_up=int(s.n_up), n_dn=int(s.n_dn), j1_form=int(s.j1_form), j1_b=_t(s.j1_b),
         j2_form=int(s.j2_form), j2=_t(s.j2),
         **({} if getattr(s, "jb_zeta", None) is None else dict(
             jb_center=_t(s.jb_center, torch.long), jb_l=_t(s.jb_l, torch.long), jb_m=_t(s.jb_m, torch.long),
-            jb_radial=_t(s.jb_radial, torch.long), jb_zeta=_t(s.jb_zeta), j1_inh=_t(s.j1_inh), j3=_t(s.j3))))
+            jb_radial=_t(s.jb_radial, torch.long), jb_zeta=_t(s.jb_zeta), j1_inh=_t(s.j1_inh), j3=_t(s.j3))),
+        **({} if getattr(s, "contraction", None) is None else dict(contraction=_t(s.contraction))))
 
 
 # ---------------------------------------------------------------------------
@@ -158,6 +167,17 @@ def basis(sy: OSystem, r, R=None, zeta=None):
     grad = gP * e.unsqueeze(-1) + P.unsqueeze(-1) * ge
     lap = lP * e + 2.0 * (gP * ge).sum(-1) + P * le
     return psi, grad, lap
+
+
+def agp_basis(sy: OSystem, r, R=None, zeta=None):
+    """The orbitals the geminal is built from: the primitive basis, or its
+    contraction phi_c = sum_mu C[mu, c] psi_mu (values, gradients and
+    Laplacians are linear in psi, so each is contracted the same way)."""
+    psi, grad, lap = basis(sy, r, R, zeta)
+    C = sy.contraction
+    if C is None:
+        return psi, grad, lap
+    return psi @ C, torch.einsum('...mx,mc->...cx', grad, C), lap @ C
 
 
 # ---------------------------------------------------------------------------
@@ -336,7 +356,7 @@ def geminal(sy: OSystem, Phi, lam=None):
 
 def log_psi(sy: OSystem, r, R=None, zeta=None, lam=None, j1_b=None, j2=None):
     """log|Psi| [Wk] and sign(Psi) [Wk] (sign of the determinant)."""
-    Phi, _, _ = basis(sy, r, R, zeta)
+    Phi, _, _ = agp_basis(sy, r, R, zeta)
     W = geminal(sy, Phi, lam)
     sign, logdet = torch.linalg.slogdet(W)
     J, _, _ = jastrow(sy, r, R, j1_b, j2)
@@ -356,7 +376,7 @@ def evaluate(sy: OSystem, r, R=None, zeta=None, lam=None, j1_b=None, j2=None,
     """
     lam = sy.lam if lam is None else lam
     nu, nd = sy.n_up, sy.n_dn
-    Phi, G, H = basis(sy, r, R, zeta)
+    Phi, G, H = agp_basis(sy, r, R, zeta)
     W = geminal(sy, Phi, lam)
     sign, logdet = torch.linalg.slogdet(W)
     singular = sign == 0

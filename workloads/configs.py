@@ -63,6 +63,9 @@ class System:
     jb_zeta: Optional[np.ndarray] = None     # [LJ] float64
     j1_inh: Optional[np.ndarray] = None      # [2, LJ] coefficients of chi for up / down electrons
     j3: Optional[np.ndarray] = None          # [3, LJ, LJ] up-up, down-down (symmetric), up-down
+    # contraction of the primitive basis: center .. radial describe the
+    # primitives, lam / unpaired act on phi_c = sum_mu C[mu, c] psi_mu
+    contraction: Optional[np.ndarray] = None  # [L_primitive, L] float64
 
     @property
     def n_jbasis(self) -> int:
@@ -281,6 +284,41 @@ def jas3_4nuc_20e(n_walkers=32, n_steps=200, seed_offset=6) -> Workload:
         lam=_sym_gaussian(rng, L, 1.0 / L), n_up=10, n_dn=10, unpaired=np.zeros((L, 0)),
         j1_form=2, j1_b=np.ones(4), j2_form=1, j2=np.array([1.0, 1.0]), refresh_every=32)
     sysd = add_jastrow_basis(sysd, rng)
+    r0 = _initial_positions(rng, R, Z, 10, 10, n_walkers)
+    disp, unif = _chain_arrays(rng, n_steps, n_walkers, 0.3)
+    return Workload(sysd, r0, disp, unif, 0.3)
+
+
+def contracted_4nuc_20e(n_walkers=32, n_steps=200, seed_offset=7) -> Workload:
+    """A contracted (hybrid) basis (Contraction of the primitive atomic basis
+    section): 4 nuclei (Z = 2, 4, 6, 8) in an 8-bohr cube, 20 electrons
+    (10 up / 10 down); per atom 15 primitives (3 Gaussian s, 1 Slater s,
+    2 Gaussian p, 1 Gaussian d shells; Gaussian zeta log-uniform in [0.1, 10],
+    Slater in [0.5, 5]) and 7 contracted orbitals, each a combination of all of
+    its atom's primitives with N(0, 1/16) coefficients (60 primitives, L = 28);
+    Lambda symmetric N(0,1)/28; Pade J1 and J2 with b = 1."""
+    rng = np.random.default_rng(SEED_BASE + seed_offset)
+    Z = np.array([2.0, 4.0, 6.0, 8.0])
+    R = _place_nuclei(rng, 4, 8.0)
+    shells = [(0, 0), (0, 0), (0, 0), (0, 1), (1, 0), (1, 0), (2, 0)]   # (l, radial)
+    center, l, m, zeta, radial = [], [], [], [], []
+    for a in range(4):
+        for ll, rad in shells:
+            z = float(_log_uniform(rng, 0.5, 5.0, 1)[0] if rad else _log_uniform(rng, 0.1, 10.0, 1)[0])
+            for mm in range(N_COMP[ll]):
+                center.append(a); l.append(ll); m.append(mm); zeta.append(z); radial.append(rad)
+    Lq, n_con = len(center), 7
+    center = np.array(center, np.int32)
+    C = np.zeros((Lq, 4 * n_con))
+    for a in range(4):
+        prim = np.nonzero(center == a)[0]
+        C[np.ix_(prim, np.arange(a * n_con, (a + 1) * n_con))] = rng.standard_normal((len(prim), n_con)) / 4.0
+    L = C.shape[1]
+    sysd = System(
+        name="contracted_4nuc_20e", R=R, Z=Z, center=center, l=np.array(l, np.int32),
+        m=np.array(m, np.int32), zeta=np.array(zeta, np.float64), radial=np.array(radial, np.int32),
+        lam=_sym_gaussian(rng, L, 1.0 / L), n_up=10, n_dn=10, unpaired=np.zeros((L, 0)),
+        j1_form=2, j1_b=np.ones(4), j2_form=1, j2=np.array([1.0, 1.0]), refresh_every=32, contraction=C)
     r0 = _initial_positions(rng, R, Z, 10, 10, n_walkers)
     disp, unif = _chain_arrays(rng, n_steps, n_walkers, 0.3)
     return Workload(sysd, r0, disp, unif, 0.3)
