@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define QMC_ABI_VERSION 5
+#define QMC_ABI_VERSION 6
 
 typedef enum {
   QMC_OK = 0,
@@ -118,6 +118,17 @@ typedef struct {
   const double *jb_zeta;      /* [LJ]                                            */
   const double *j1_inh;       /* [2][LJ] coefficients for up, then down electrons */
   const double *j3;           /* [3][LJ][LJ] M^{uu}, M^{dd} (symmetric), M^{ud}   */
+  /* Contracted orbitals (Contraction of the primitive atomic basis section):
+   * with n_contracted = Lc > 0 the L basis functions above are primitives and
+   * the geminal is built from phi_c = sum_t con_coef[t] psi_{con_idx[t]} over
+   * t in [con_ptr[c], con_ptr[c+1]), c < Lc; lambda is then [Lc][Lc] and every
+   * [L] of the calls below that refers to orbitals (Phi rows) reads Lc.
+   * L <= 2048 primitives.  Not supported with it: qmc_forces, qmc_multi_*,
+   * exponents or nuclei changed through qmc_system_set_params. */
+  int32_t n_contracted;       /* Lc (0: the basis functions are the orbitals)    */
+  const int32_t *con_ptr;     /* [Lc + 1], con_ptr[0] = 0, non-decreasing        */
+  const int32_t *con_idx;     /* [con_ptr[Lc]] primitive index, 0 .. L-1         */
+  const double *con_coef;     /* [con_ptr[Lc]] coefficients                      */
 } qmc_system_desc;
 
 /* Version of this header the library was built from (QMC_ABI_VERSION). */

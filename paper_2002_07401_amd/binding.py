@@ -72,6 +72,8 @@ class SystemDesc(ctypes.Structure):
         ("n_jbasis", ctypes.c_int32), ("jb_center", ctypes.c_void_p), ("jb_l", ctypes.c_void_p),
         ("jb_m", ctypes.c_void_p), ("jb_radial", ctypes.c_void_p), ("jb_zeta", ctypes.c_void_p),
         ("j1_inh", ctypes.c_void_p), ("j3", ctypes.c_void_p),
+        ("n_contracted", ctypes.c_int32), ("con_ptr", ctypes.c_void_p), ("con_idx", ctypes.c_void_p),
+        ("con_coef", ctypes.c_void_p),
     ]
 
 
@@ -163,6 +165,15 @@ class JAGPSystem:
                         jb_zeta=np.ascontiguousarray(s.jb_zeta, np.float64),
                         j1_inh=np.ascontiguousarray(s.j1_inh, np.float64),
                         j3=np.ascontiguousarray(s.j3, np.float64))
+        Cm = getattr(s, "contraction", None)
+        if Cm is not None:
+            # CSR of the contraction by orbital: the nonzero C[mu][c] of each column c
+            Cm = np.asarray(Cm, np.float64)
+            cols = [np.nonzero(Cm[:, c])[0] for c in range(Cm.shape[1])]
+            keep.update(con_ptr=np.concatenate([[0], np.cumsum([len(x) for x in cols])]).astype(np.int32),
+                        con_idx=np.ascontiguousarray(np.concatenate(cols), np.int32),
+                        con_coef=np.ascontiguousarray(np.concatenate([Cm[x, c] for c, x in enumerate(cols)]),
+                                                      np.float64))
         p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
         d = SystemDesc(
             n_nuc=len(s.Z), R=p(keep["R"]), Z=p(keep["Z"]), n_basis=len(s.zeta),
@@ -174,13 +185,15 @@ class JAGPSystem:
             n_jbasis=LJ,
             **({} if not LJ else dict(jb_center=p(keep["jb_center"]), jb_l=p(keep["jb_l"]), jb_m=p(keep["jb_m"]),
                                       jb_radial=p(keep["jb_radial"]), jb_zeta=p(keep["jb_zeta"]),
-                                      j1_inh=p(keep["j1_inh"]), j3=p(keep["j3"]))))
+                                      j1_inh=p(keep["j1_inh"]), j3=p(keep["j3"]))),
+            **({} if Cm is None else dict(n_contracted=Cm.shape[1], con_ptr=p(keep["con_ptr"]),
+                                          con_idx=p(keep["con_idx"]), con_coef=p(keep["con_coef"]))))
         h = ctypes.c_void_p()
         _check(lib.qmc_system_create(ctypes.byref(d), ctypes.byref(h)))
         self.h = h
         self.precision = precision
         self.n_elec = s.n_up + s.n_dn
-        self.n_up, self.n_dn, self.L = s.n_up, s.n_dn, len(s.zeta)
+        self.n_up, self.n_dn, self.L = s.n_up, s.n_dn, len(s.lam)
         self.n_nuc = len(s.Z)
         self.n_jas = len(s.Z) + len(s.j2)
 

@@ -18,8 +18,37 @@ __global__ void __launch_bounds__(256) basis_values_kernel(SysDev s, const doubl
     out[mu] = (T)(mu < s.L ? basis_value(s, mu, px, py, pz) : 0.0);
 }
 
+// Contracted orbitals: the row's primitive values are staged in LDS, then
+// phi_c = sum_t C_t psi_{idx_t} (a contraction mixes primitives of one row only).
+template <typename T>
+__global__ void __launch_bounds__(256) contracted_values_kernel(SysDev s, const double* __restrict__ r,
+                                                                T* __restrict__ phi) {
+  __shared__ double q[kMaxLq];
+  const long row = blockIdx.x;   // w * N + i
+  const double px = r[3 * row], py = r[3 * row + 1], pz = r[3 * row + 2];
+  for (int mu = threadIdx.x; mu < s.Lq; mu += blockDim.x) q[mu] = basis_value(s, mu, px, py, pz);
+  __syncthreads();
+  T* out = phi + row * s.Lp;
+  for (int c = threadIdx.x; c < s.Lp; c += blockDim.x) {
+    double v = 0.0;
+    if (c < s.L)
+      for (int k = s.con_ptr[c]; k < s.con_ptr[c + 1]; ++k) v += s.con_coef[k] * q[s.con_idx[k]];
+    out[c] = (T)v;
+  }
+}
+
 hipError_t launch_basis_values(const SysDev& s, const WalkDev& w, hipStream_t st) {
   const dim3 grid((unsigned)((long)w.Wk * s.N));
+  if (s.Lq > 0) {
+    if (s.Lq > kMaxLq) return hipErrorNotSupported;
+    if (s.bf16())
+      hipLaunchKernelGGL(contracted_values_kernel<bf16s>, grid, dim3(256), 0, st, s, w.r, (bf16s*)w.phi);
+    else if (s.f32())
+      hipLaunchKernelGGL(contracted_values_kernel<float>, grid, dim3(256), 0, st, s, w.r, (float*)w.phi);
+    else
+      hipLaunchKernelGGL(contracted_values_kernel<double>, grid, dim3(256), 0, st, s, w.r, (double*)w.phi);
+    return hipGetLastError();
+  }
   if (s.bf16())
     hipLaunchKernelGGL(basis_values_kernel<bf16s>, grid, dim3(256), 0, st, s, w.r, (bf16s*)w.phi);
   else if (s.f32())
@@ -65,10 +94,12 @@ __global__ void __launch_bounds__(256) rowdot_kernel(SysDev s, int rows, const d
   const double px = r[3 * row], py = r[3 * row + 1], pz = r[3 * row + 2];
   const double* y = Yt + row * s.Lp;
   double sx = 0.0, sy = 0.0, sz = 0.0, sl = 0.0;
-  for (int mu = lane; mu < s.L; mu += 64) {
+  // contracted orbitals: sum_c y_c D phi_c = sum_mu (sum_c C[mu][c] y_c) D psi_mu
+  const int nb = s.nprim();
+  for (int mu = lane; mu < nb; mu += 64) {
     double v, gx, gy, gz, lp;
     basis_vgl(s, mu, px, py, pz, v, gx, gy, gz, lp);
-    const double yy = y[mu];
+    const double yy = s.Lq ? prim_weight(s, mu, y) : y[mu];
     sx += gx * yy; sy += gy * yy; sz += gz * yy; sl += lp * yy;
   }
   sx = wave_sum(sx); sy = wave_sum(sy); sz = wave_sum(sz); sl = wave_sum(sl);

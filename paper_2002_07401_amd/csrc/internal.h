@@ -26,6 +26,7 @@ static_assert(kPropRowsF64 >= kPropRowsMin && kPropRowsNarrow >= kPropRowsMin, "
 constexpr int kMaxNucBack = 256;  // nuclei handled by the Jastrow backward kernel
 constexpr int kFuseMaxLp = 1024;   // accept fused with the next set-up: psi(r') staged in LDS
 constexpr int kMaxLJ = 1024;       // Jastrow basis functions (J1 inhomogeneous, J3/4)
+constexpr int kMaxLq = 2048;       // primitives of a contracted basis (LDS stage of the basis kernel)
 constexpr int kBigMaxN = 1024;    // blocked Gauss-Jordan limit
 constexpr int kWbMax = 64;        // capacity of the delayed-update buffer (moves between refreshes)
 constexpr int kGjPanel = 64;      // panel width of the blocked Gauss-Jordan
@@ -96,6 +97,19 @@ struct SysDev {
   int* jkind;       // [LJ] as kind
   double* jm;       // [2][LJ] one-body inhomogeneous coefficients, up then down
   double* M3;       // [2LJ][2LJ] [[M_uu, M_ud], [M_ud^T, M_dd]] (symmetric)
+  // Contracted orbitals (Lq > 0): center, kind, zeta and bfn then describe Lq
+  // primitives and orbital c < L is sum_t con_coef[t] psi_{con_idx[t]},
+  // t in [con_ptr[c], con_ptr[c+1]); pri_* hold the same matrix by primitive
+  // (orbitals c with coefficient pri_coef[t] = C[mu][c] for t in
+  // [pri_ptr[mu], pri_ptr[mu+1])), so that sum_c C[mu][c] y_c is one short loop.
+  int Lq;
+  int* con_ptr;      // [L+1]
+  int* con_idx;      // [nnz]
+  double* con_coef;  // [nnz]
+  int* pri_ptr;      // [Lq+1]
+  int* pri_idx;      // [nnz]
+  double* pri_coef;  // [nnz]
+  __host__ __device__ int nprim() const { return Lq ? Lq : L; }
 };
 
 // Device state of a batch of walkers.
@@ -158,6 +172,7 @@ struct WalkDev {
   double* G3;         // [Wk][2][LJ]
   double* chi_new;    // [Wk][LJ]
   double* j3e;        // [Wk][N][5] value part, gradient (3), Laplacian
+  double* qbuf;       // [Wk][4][Lq] primitive values (and gradients) at r' (contracted orbitals)
 };
 
 // Workspace of the reverse pass (allocated on the first qmc_forces call).
@@ -330,6 +345,14 @@ __device__ __forceinline__ void basis_vgl_tab(const double4* __restrict__ bfn, c
 __device__ __forceinline__ void basis_vgl(const SysDev& s, int mu, double px, double py, double pz,
                                           double& v, double& gx, double& gy, double& gz, double& lap) {
   basis_vgl_tab(s.bfn, s.kind, mu, px, py, pz, v, gx, gy, gz, lap);
+}
+
+// sum_c C[mu][c] y[c] over the orbitals that contain primitive mu: the
+// coefficient of psi_mu in sum_c y_c phi_c (contracted orbitals only).
+__device__ __forceinline__ double prim_weight(const SysDev& s, int mu, const double* __restrict__ y) {
+  double t = 0.0;
+  for (int k = s.pri_ptr[mu]; k < s.pri_ptr[mu + 1]; ++k) t += s.pri_coef[k] * y[s.pri_idx[k]];
+  return t;
 }
 
 // One-body term f(r) = -(2Z)^{3/4} u((2Z)^{1/4} r) and its radial derivatives.

@@ -68,10 +68,12 @@ __global__ __launch_bounds__(256) void lrdmc_ratio_kernel(SysDev s, WalkDev w, L
   // determinant ratios psi(r'_k) . Yt[i]
   double c[kHops] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   const double* Y = w.Yt + ((long)wk * s.N + i) * s.Lp;
-  for (int mu = lane; mu < s.L; mu += 64) {
+  // contracted orbitals: sum_c y_c phi_c(r') = sum_mu (sum_c C[mu][c] y_c) psi_mu(r')
+  const int nb = s.nprim();
+  for (int mu = lane; mu < nb; mu += 64) {
     const double4 f = s.bfn[mu];
     const int kind = s.kind[mu];
-    const double y_mu = Y[mu];
+    const double y_mu = s.Lq ? prim_weight(s, mu, Y) : Y[mu];
 #pragma unroll
     for (int k = 0; k < kHops; ++k) {
       const double dx = px[k] - f.x, dy = py[k] - f.y, dz = pz[k] - f.z;

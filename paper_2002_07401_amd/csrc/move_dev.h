@@ -120,6 +120,34 @@ __device__ void prep_body(const SysDev& s, const WalkDev& w, int wk, int e, cons
   const double px = rn[0], py = rn[1], pz = rn[2];
   double* psi = w.psi_new + (long)wk * s.Lp;
   double* gpsi = w.gpsi_new + (long)wk * 3 * s.Lp;
+  if (s.Lq) {
+    // contracted orbitals: primitives at r' (values, gradients on request)
+    // into this walker's slice of qbuf, then phi_c = sum_t C_t psi_{idx_t}
+    const int Lq = s.Lq;
+    double* qb = w.qbuf + (long)wk * 4 * Lq;
+    for (int mu = tid; mu < Lq; mu += blockDim.x) {
+      if (DRIFT) {
+        double v, gx, gy, gz, lp;
+        basis_vgl(s, mu, px, py, pz, v, gx, gy, gz, lp);
+        qb[mu] = v; qb[Lq + mu] = gx; qb[2 * Lq + mu] = gy; qb[3 * Lq + mu] = gz;
+      } else {
+        qb[mu] = basis_value(s, mu, px, py, pz);
+      }
+    }
+    __syncthreads();
+    for (int c = tid; c < s.Lp; c += blockDim.x) {
+      double v = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+      if (c < s.L)
+        for (int k = s.con_ptr[c]; k < s.con_ptr[c + 1]; ++k) {
+          const double cf = s.con_coef[k];
+          const int mu = s.con_idx[k];
+          v += cf * qb[mu];
+          if (DRIFT) { gx += cf * qb[Lq + mu]; gy += cf * qb[2 * Lq + mu]; gz += cf * qb[3 * Lq + mu]; }
+        }
+      psi[c] = v;
+      if (DRIFT) { gpsi[c] = gx; gpsi[s.Lp + c] = gy; gpsi[2 * s.Lp + c] = gz; }
+    }
+  } else
   for (int mu = tid; mu < s.Lp; mu += blockDim.x) {
     if (mu >= s.L) {
       psi[mu] = 0.0;

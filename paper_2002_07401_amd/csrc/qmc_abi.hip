@@ -170,9 +170,22 @@ extern "C" qmc_status qmc_system_create(const qmc_system_desc* desc, qmc_system*
   if (q.j2_form < 0 || q.j2_form > 2) return fail(QMC_ERR_ARG, "bad j2 form");
   if (q.j2_form == 1 && (q.n_j2 != 2 || !q.j2)) return fail(QMC_ERR_ARG, "j2 form 1 needs 2 params");
   if (q.j2_form == 2 && (q.n_j2 != 8 || !q.j2)) return fail(QMC_ERR_ARG, "j2 form 2 needs 8 params");
-  const int L = q.n_basis;
-  std::vector<int> kind(L);
-  for (int mu = 0; mu < L; ++mu) {
+  const int Lb = q.n_basis;                       // basis functions (primitives when contracted)
+  const int Lc = q.n_contracted;
+  if (Lc < 0) return fail(QMC_ERR_ARG, "n_contracted must be >= 0");
+  if (Lc > 0) {
+    if (!q.con_ptr || !q.con_idx || !q.con_coef) return fail(QMC_ERR_ARG, "contraction arrays missing");
+    if (Lb > kMaxLq) return fail(QMC_ERR_UNSUPPORTED, "contracted basis of more than 2048 primitives");
+    if (q.con_ptr[0] != 0) return fail(QMC_ERR_ARG, "con_ptr[0] must be 0");
+    if (q.con_ptr[Lc] <= 0) return fail(QMC_ERR_ARG, "contraction without coefficients");
+    for (int c = 0; c < Lc; ++c)
+      if (q.con_ptr[c + 1] < q.con_ptr[c]) return fail(QMC_ERR_ARG, "con_ptr must be non-decreasing");
+    for (int k = 0; k < q.con_ptr[Lc]; ++k)
+      if (q.con_idx[k] < 0 || q.con_idx[k] >= Lb) return fail(QMC_ERR_ARG, "con_idx out of range");
+  }
+  const int L = Lc > 0 ? Lc : Lb;                 // orbitals of the geminal
+  std::vector<int> kind(Lb);
+  for (int mu = 0; mu < Lb; ++mu) {
     if (q.radial && q.radial[mu] != 0 && q.radial[mu] != 1) return fail(QMC_ERR_ARG, "radial must be 0 or 1");
     if (q.center[mu] < 0 || q.center[mu] >= q.n_nuc) return fail(QMC_ERR_ARG, "basis center out of range");
     const int l = q.l[mu], m = q.m[mu];
@@ -180,12 +193,12 @@ extern "C" qmc_status qmc_system_create(const qmc_system_desc* desc, qmc_system*
     if (m < 0 || m >= 2 * l + 1) return fail(QMC_ERR_ARG, "component index out of range");
     kind[mu] = ((l == 0) ? 0 : (l == 1 ? 1 + m : 4 + m)) | ((q.radial && q.radial[mu] == 1) ? kSlaterBit : 0);
   }
-  std::vector<int> cptr(q.n_nuc + 1, 0), cmu(L);
-  for (int mu = 0; mu < L; ++mu) cptr[q.center[mu] + 1]++;
+  std::vector<int> cptr(q.n_nuc + 1, 0), cmu(Lb);
+  for (int mu = 0; mu < Lb; ++mu) cptr[q.center[mu] + 1]++;
   for (int a = 0; a < q.n_nuc; ++a) cptr[a + 1] += cptr[a];
   {
     std::vector<int> fill(cptr.begin(), cptr.end() - 1);
-    for (int mu = 0; mu < L; ++mu) cmu[fill[q.center[mu]]++] = mu;
+    for (int mu = 0; mu < Lb; ++mu) cmu[fill[q.center[mu]]++] = mu;
   }
   auto* s = new qmc_system();
   SysDev& d = s->d;
@@ -251,9 +264,9 @@ extern "C" qmc_status qmc_system_create(const qmc_system_desc* desc, qmc_system*
   if (!e) e = up((void**)&d.R, q.R, sizeof(double) * 3 * A);
   if (!e) e = up((void**)&d.Z, q.Z, sizeof(double) * A);
   if (!e) e = up((void**)&d.j1_b, j1b.data(), sizeof(double) * A);
-  if (!e) e = up((void**)&d.center, q.center, sizeof(int) * L);
-  if (!e) e = up((void**)&d.kind, kind.data(), sizeof(int) * L);
-  if (!e) e = up((void**)&d.zeta, q.zeta, sizeof(double) * L);
+  if (!e) e = up((void**)&d.center, q.center, sizeof(int) * Lb);
+  if (!e) e = up((void**)&d.kind, kind.data(), sizeof(int) * Lb);
+  if (!e) e = up((void**)&d.zeta, q.zeta, sizeof(double) * Lb);
   if (!e) e = up((void**)&d.lam, lam.data(), sizeof(double) * lam.size());
   if (!e) e = up((void**)&d.lamT, lamT.data(), sizeof(double) * lamT.size());
   if (!e) e = up((void**)&d.cptr, cptr.data(), sizeof(int) * cptr.size());
@@ -265,9 +278,31 @@ extern "C" qmc_status qmc_system_create(const qmc_system_desc* desc, qmc_system*
     if (!e) e = up((void**)&d.jm, jm.data(), sizeof(double) * jm.size());
     if (!e) e = up((void**)&d.M3, M3.data(), sizeof(double) * M3.size());
   }
+  d.Lq = Lc > 0 ? Lb : 0;
+  if (!e && Lc > 0) {
+    const int nnz = q.con_ptr[Lc];
+    // the same matrix by primitive: pri_* (counting sort of the entries by primitive)
+    std::vector<int> pptr(Lb + 1, 0), pidx(nnz);
+    std::vector<double> pcoef(nnz);
+    for (int k = 0; k < nnz; ++k) pptr[q.con_idx[k] + 1]++;
+    for (int mu = 0; mu < Lb; ++mu) pptr[mu + 1] += pptr[mu];
+    std::vector<int> fill(pptr.begin(), pptr.end() - 1);
+    for (int c = 0; c < Lc; ++c)
+      for (int k = q.con_ptr[c]; k < q.con_ptr[c + 1]; ++k) {
+        const int at = fill[q.con_idx[k]]++;
+        pidx[at] = c;
+        pcoef[at] = q.con_coef[k];
+      }
+    e = up((void**)&d.con_ptr, q.con_ptr, sizeof(int) * (Lc + 1));
+    if (!e) e = up((void**)&d.con_idx, q.con_idx, sizeof(int) * nnz);
+    if (!e) e = up((void**)&d.con_coef, q.con_coef, sizeof(double) * nnz);
+    if (!e) e = up((void**)&d.pri_ptr, pptr.data(), sizeof(int) * (Lb + 1));
+    if (!e) e = up((void**)&d.pri_idx, pidx.data(), sizeof(int) * nnz);
+    if (!e) e = up((void**)&d.pri_coef, pcoef.data(), sizeof(double) * nnz);
+  }
   if (!e) {
-    std::vector<double> bf(4 * (size_t)L);
-    for (int mu = 0; mu < L; ++mu) {
+    std::vector<double> bf(4 * (size_t)Lb);
+    for (int mu = 0; mu < Lb; ++mu) {
       const int c = q.center[mu];
       bf[4 * mu] = q.R[3 * c]; bf[4 * mu + 1] = q.R[3 * c + 1]; bf[4 * mu + 2] = q.R[3 * c + 2];
       bf[4 * mu + 3] = q.zeta[mu];
@@ -382,6 +417,7 @@ extern "C" qmc_status qmc_walkers_create(qmc_system* sys, int32_t n_walkers, qmc
     al((void**)&d.chi_new, sizeof(double) * Wk * LJ);
     al((void**)&d.j3e, sizeof(double) * Wk * N * 5);
   }
+  if (s.Lq > 0) al((void**)&d.qbuf, sizeof(double) * Wk * 4 * s.Lq);
   al((void**)&wk->lr.ratio, sizeof(double) * Wk * N * kHops);
   al((void**)&wk->lr.ah, sizeof(double) * Wk * N);
   al((void**)&wk->lr.terms, sizeof(double) * Wk * kLrTerms);
@@ -565,7 +601,7 @@ extern "C" qmc_status qmc_accept_move(qmc_system* sys, qmc_walkers* wk, int32_t 
 // (for e2) falls between them, and psi(r') fits the kernel's LDS stage.
 static bool fusable(const qmc_walkers* wk, int e, int e2) {
   const SysDev& s = wk->sys->d;
-  if (s.Lp > kFuseMaxLp || s.nu > kBigMaxN || !wk->d.wv || e2 == e || s.LJ > 0) return false;
+  if (s.Lp > kFuseMaxLp || s.nu > kBigMaxN || !wk->d.wv || e2 == e || s.LJ > 0 || s.Lq > 0) return false;
   Sched q{wk->attempts, wk->since, wk->buf_spin};
   if (sched_after(s, q)) return false;
   if (sched_before(s, q, e2)) return false;
@@ -714,6 +750,7 @@ extern "C" qmc_status qmc_forces(qmc_system* sys, qmc_walkers* wk, const double*
   const SysDev& s = sys->d;
   if (s.precision != QMC_FP64) return fail(QMC_ERR_UNSUPPORTED, "forces are built for the FP64 path");
   if (s.LJ > 0) return fail(QMC_ERR_UNSUPPORTED, "forces with a Jastrow basis are not built");
+  if (s.Lq > 0) return fail(QMC_ERR_UNSUPPORTED, "forces with contracted orbitals are not built");
   if (s.N > 2 * kLuMaxN || s.n_nuc > kMaxNucBack)
     return fail(QMC_ERR_UNSUPPORTED, "forces need N <= 256 electrons and <= 256 nuclei");
   hipError_t e = alloc_adjoint(wk);
@@ -820,6 +857,8 @@ extern "C" qmc_status qmc_system_set_params(qmc_system* sys, const double* R, co
   if (!sys) return fail(QMC_ERR_ARG, "null system");
   SysDev& d = sys->d;
   if (R && d.LJ > 0) return fail(QMC_ERR_UNSUPPORTED, "moving nuclei with a Jastrow basis is not built");
+  if ((R || zeta) && d.Lq > 0)
+    return fail(QMC_ERR_UNSUPPORTED, "changing primitives of a contracted basis is not built");
   if (R) HIP_TRY(hipMemcpyAsync(d.R, R, sizeof(double) * 3 * d.n_nuc, hipMemcpyDeviceToDevice, stream), "set R");
   if (zeta) HIP_TRY(hipMemcpyAsync(d.zeta, zeta, sizeof(double) * d.L, hipMemcpyDeviceToDevice, stream), "set zeta");
   if (lambda) HIP_TRY(launch_set_lambda(d, lambda, stream), "set lambda");
@@ -914,6 +953,7 @@ extern "C" qmc_status qmc_multi_create(int32_t n_members, qmc_system* const* sys
     if (s.precision != systems[0]->d.precision) { delete m; return fail(QMC_ERR_ARG, "members differ in precision"); }
     if (s.nu != s.nd || s.nu > kLuMaxN) { delete m; return fail(QMC_ERR_UNSUPPORTED, "members need n_up == n_dn <= 128"); }
     if (s.LJ > 0) { delete m; return fail(QMC_ERR_UNSUPPORTED, "members with a Jastrow basis are not built"); }
+    if (s.Lq > 0) { delete m; return fail(QMC_ERR_UNSUPPORTED, "members with contracted orbitals are not built"); }
     m->sys.push_back(systems[k]);
     m->wk.push_back(walkers[k]);
     m->h_sys.push_back(s);
