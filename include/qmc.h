@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define QMC_ABI_VERSION 6
+#define QMC_ABI_VERSION 7
 
 typedef enum {
   QMC_OK = 0,
@@ -90,7 +90,8 @@ typedef struct {
   const double *zeta;         /* [L] exponents                                   */
   const double *lambda;       /* [L][L] pairing coefficients (general matrix;
                                  symmetric for a spin singlet)                   */
-  int32_t n_up, n_dn;         /* electrons per spin; n_up == n_dn is built       */
+  int32_t n_up, n_dn;         /* electrons per spin, n_up >= n_dn (label the
+                                 majority spin "up")                             */
   int32_t j1_form;            /* 0 none, 1 u=(1-e^{-bs})/(2b), 2 u=s/(2(1+bs))   */
   const double *j1_b;         /* [A] one-body b per nucleus                      */
   int32_t j2_form;            /* 0 none, 1 Pade (b_para, b_anti),
@@ -129,6 +130,11 @@ typedef struct {
   const int32_t *con_ptr;     /* [Lc + 1], con_ptr[0] = 0, non-decreasing        */
   const int32_t *con_idx;     /* [con_ptr[Lc]] primitive index, 0 .. L-1         */
   const double *con_coef;     /* [con_ptr[Lc]] coefficients                      */
+  /* Unpaired orbitals (eq:wfAGPunpaired): with k = n_up - n_dn > 0 the geminal
+   * matrix is n_up x n_up, columns n_dn + l holding sum_mu unpaired[mu][l]
+   * phi_mu(r_i) (phi the orbitals: the basis functions, or the contracted
+   * orbitals).  Not supported with it: qmc_forces, qmc_multi_*. */
+  const double *unpaired;     /* [L or Lc][k]; may be NULL when k = 0            */
 } qmc_system_desc;
 
 /* Version of this header the library was built from (QMC_ABI_VERSION). */
@@ -138,7 +144,7 @@ int32_t qmc_abi_version(void);
 const char *qmc_last_error(void);
 
 /* Copy a description to the current device.  Fails with QMC_ERR_UNSUPPORTED
- * for l > 2, n_up != n_dn or a precision not built. */
+ * for l > 2, n_up < n_dn or a precision not built. */
 qmc_status qmc_system_create(const qmc_system_desc *desc, qmc_system **out);
 qmc_status qmc_system_destroy(qmc_system *sys);
 

@@ -73,7 +73,7 @@ class SystemDesc(ctypes.Structure):
         ("jb_m", ctypes.c_void_p), ("jb_radial", ctypes.c_void_p), ("jb_zeta", ctypes.c_void_p),
         ("j1_inh", ctypes.c_void_p), ("j3", ctypes.c_void_p),
         ("n_contracted", ctypes.c_int32), ("con_ptr", ctypes.c_void_p), ("con_idx", ctypes.c_void_p),
-        ("con_coef", ctypes.c_void_p),
+        ("con_coef", ctypes.c_void_p), ("unpaired", ctypes.c_void_p),
     ]
 
 
@@ -156,7 +156,8 @@ class JAGPSystem:
             center=np.ascontiguousarray(s.center, np.int32), l=np.ascontiguousarray(s.l, np.int32),
             m=np.ascontiguousarray(s.m, np.int32), radial=np.ascontiguousarray(s.radial, np.int32),
             zeta=np.ascontiguousarray(s.zeta, np.float64), lam=np.ascontiguousarray(s.lam, np.float64),
-            j1_b=np.ascontiguousarray(s.j1_b, np.float64), j2=np.ascontiguousarray(s.j2, np.float64))
+            j1_b=np.ascontiguousarray(s.j1_b, np.float64), j2=np.ascontiguousarray(s.j2, np.float64),
+            unpaired=np.ascontiguousarray(np.asarray(s.unpaired, np.float64).reshape(len(s.lam), -1)))
         LJ = 0 if getattr(s, "jb_zeta", None) is None else len(s.jb_zeta)
         if LJ:
             keep.update(jb_center=np.ascontiguousarray(s.jb_center, np.int32),
@@ -182,7 +183,7 @@ class JAGPSystem:
             j1_form=s.j1_form, j1_b=p(keep["j1_b"]), j2_form=s.j2_form, n_j2=len(s.j2),
             j2=p(keep["j2"]), precision=precision,
             refresh_every=s.refresh_every if refresh_every is None else refresh_every,
-            n_jbasis=LJ,
+            n_jbasis=LJ, unpaired=p(keep["unpaired"]) if s.n_up > s.n_dn else None,
             **({} if not LJ else dict(jb_center=p(keep["jb_center"]), jb_l=p(keep["jb_l"]), jb_m=p(keep["jb_m"]),
                                       jb_radial=p(keep["jb_radial"]), jb_zeta=p(keep["jb_zeta"]),
                                       j1_inh=p(keep["j1_inh"]), j3=p(keep["j3"]))),
@@ -269,8 +270,8 @@ class Walkers:
 
     def read(self, item: int, stream=None) -> torch.Tensor:
         Wk, N, nu, nd, L = self.n, self.sys.n_elec, self.sys.n_up, self.sys.n_dn, self.sys.L
-        shape = {STATE_R: (Wk, N, 3), STATE_LOGABS: (Wk,), STATE_SIGN: (Wk,), STATE_W: (Wk, nu, nd),
-                 STATE_AINV: (Wk, nd, nu), STATE_PHI: (Wk, N, L)}[item]
+        shape = {STATE_R: (Wk, N, 3), STATE_LOGABS: (Wk,), STATE_SIGN: (Wk,), STATE_W: (Wk, nu, nu),
+                 STATE_AINV: (Wk, nu, nu), STATE_PHI: (Wk, N, L)}[item]
         dst = torch.empty(shape, dtype=torch.float64, device="cuda")
         _check(load().qmc_walkers_read(self.h, item, _ptr(dst), _stream(stream)))
         return dst

@@ -252,25 +252,34 @@ hipError_t launch_P_build(const SysDev& s, const WalkDev& w, int halves, hipStre
   return P_build_t<double>(s, w, halves, st, s.lam, s.lamT);
 }
 
-// W[w] = P_up[w] Phi_dn[w]^T  ->  W[i][j] = sum_nu (Phi_up Lambda)[i][nu] psi_nu(r_j)
+// W[w] = P_up[w] Phi_dn[w]^T  ->  W[i][j] = sum_nu (Phi_up Lambda)[i][nu] psi_nu(r_j),
+// and with unpaired orbitals (eq:wfAGPunpaired) the last nk columns
+// W[i][n_dn + l] = psi(r_i) . U[:, l] = (Phi_up Uph^T)[i][l].  W is n_up x n_up.
 template <typename T>
-static hipError_t W_build_t(const SysDev& s, const WalkDev& w, hipStream_t st) {
-  const long rowst = (long)s.N * s.Lp;
+static hipError_t W_build_t(const SysDev& s, const WalkDev& w, const T* Uph, hipStream_t st) {
+  const long rowst = (long)s.N * s.Lp, n = s.nu;
   GemmArgs g = plain(s.nu, s.nd, s.Lp);
   g.A = (const T*)w.P; g.lda = s.Lp; g.a_bs = rowst;
   g.B = (const T*)w.phi + (long)s.nu * s.Lp; g.ldb = s.Lp; g.b_bs = rowst;
-  g.C = w.W; g.ldc = s.nd; g.c_bs = (long)s.nu * s.nd;
+  g.C = w.W; g.ldc = n; g.c_bs = n * n;
   g.batch = w.Wk;
   // FP64 MFMA accumulation whatever the storage type of P and Phi (FP32 values
   // promote exactly): the length-L sums of the geminal entries carry no FP32
   // rounding.
-  return run_gemm<32, 32, false, true, T, T, double, double>(g, st);
+  hipError_t e = run_gemm<32, 32, false, true, T, T, double, double>(g, st);
+  if (e != hipSuccess || s.nk == 0) return e;
+  GemmArgs u = plain(s.nu, s.nk, s.Lp);
+  u.A = (const T*)w.phi; u.lda = s.Lp; u.a_bs = rowst;
+  u.B = Uph; u.ldb = s.Lp; u.b_bs = 0;
+  u.C = w.W + s.nd; u.ldc = n; u.c_bs = n * n;
+  u.batch = w.Wk;
+  return run_gemm<32, 32, false, true, T, T, double, double>(u, st);
 }
 
 hipError_t launch_W_build(const SysDev& s, const WalkDev& w, hipStream_t st) {
   if (s.bf16()) return hipErrorNotSupported;   // BF16 systems evaluate in FP64
-  if (s.f32()) return W_build_t<float>(s, w, st);
-  return W_build_t<double>(s, w, st);
+  if (s.f32()) return W_build_t<float>(s, w, s.Uph32, st);
+  return W_build_t<double>(s, w, s.Uph, st);
 }
 
 // Cofactor vectors of the local-energy derivatives:
@@ -278,22 +287,34 @@ hipError_t launch_W_build(const SysDev& s, const WalkDev& w, hipStream_t st) {
 //   Yt_dn[j][nu] = sum_i A[j][i] P_up[i][nu]   (= (W^{-1} Phi_up Lambda)[j][nu])
 // so that grad_i det/det = grad psi(r_i) . Yt[i] for every electron i.  Always
 // FP64 arithmetic: A is FP64 and P (FP64 or FP32 storage) is promoted exactly.
+// With unpaired orbitals the up electrons' vectors also collect the unpaired
+// columns: Yt_up[i] += sum_l A[n_dn + l][i] U[:, l].
 template <typename T>
-static hipError_t Y_build_t(const SysDev& s, const WalkDev& w, hipStream_t st) {
-  const long rowst = (long)s.N * s.Lp;
+static hipError_t Y_build_t(const SysDev& s, const WalkDev& w, const T* Uph, hipStream_t st) {
+  const long rowst = (long)s.N * s.Lp, n = s.nu;
   hipError_t e;
   {
     GemmArgs g = plain(s.nu, s.Lp, s.nd);
-    g.A = w.A; g.lda = s.nu; g.a_bs = (long)s.nd * s.nu;
+    g.A = w.A; g.lda = n; g.a_bs = n * n;
     g.B = (const T*)w.P + (long)s.nu * s.Lp; g.ldb = s.Lp; g.b_bs = rowst;
     g.C = w.Yt; g.ldc = s.Lp; g.c_bs = rowst;
     g.batch = w.Wk;
     e = run_gemm<32, 64, true, false, double, T, double, double, 16>(g, st);
     if (e != hipSuccess) return e;
   }
+  if (s.nk > 0) {
+    GemmArgs g = plain(s.nu, s.Lp, s.nk);
+    g.A = w.A + (long)s.nd * n; g.lda = n; g.a_bs = n * n;
+    g.B = Uph; g.ldb = s.Lp; g.b_bs = 0;
+    g.C = w.Yt; g.ldc = s.Lp; g.c_bs = rowst;
+    g.batch = w.Wk;
+    g.accumulate = 1;
+    e = run_gemm<32, 64, true, false, double, T, double, double, 16>(g, st);
+    if (e != hipSuccess) return e;
+  }
   {
     GemmArgs g = plain(s.nd, s.Lp, s.nu);
-    g.A = w.A; g.lda = s.nu; g.a_bs = (long)s.nd * s.nu;
+    g.A = w.A; g.lda = n; g.a_bs = n * n;
     g.B = (const T*)w.P; g.ldb = s.Lp; g.b_bs = rowst;
     g.C = w.Yt + (long)s.nu * s.Lp; g.ldc = s.Lp; g.c_bs = rowst;
     g.batch = w.Wk;
@@ -304,8 +325,8 @@ static hipError_t Y_build_t(const SysDev& s, const WalkDev& w, hipStream_t st) {
 
 hipError_t launch_Y_build(const SysDev& s, const WalkDev& w, hipStream_t st) {
   if (s.bf16()) return hipErrorNotSupported;
-  if (s.f32()) return Y_build_t<float>(s, w, st);
-  return Y_build_t<double>(s, w, st);
+  if (s.f32()) return Y_build_t<float>(s, w, s.Uph32, st);
+  return Y_build_t<double>(s, w, s.Uph, st);
 }
 
 }  // namespace qmc

@@ -110,6 +110,14 @@ struct SysDev {
   int* pri_idx;      // [nnz]
   double* pri_coef;  // [nnz]
   __host__ __device__ int nprim() const { return Lq ? Lq : L; }
+  // Unpaired orbitals (nk = n_up - n_dn > 0): W is n_up x n_up, its columns
+  // n_dn .. n_up-1 hold psi(r_i) . U[:, l].  Row l of Uph is U[:, l] (zero
+  // padded to Lp), the fixed "P row" of column n_dn + l; UphS is the copy in the
+  // move rows' storage type (Uph, Uph32 or a BF16 copy).
+  int nk;
+  double* Uph;       // [nk][Lp]
+  float* Uph32;      // [nk][Lp] (reduced-precision storage)
+  const void* UphS;  // [nk][Lp]
 };
 
 // Device state of a batch of walkers.
@@ -118,8 +126,8 @@ struct WalkDev {
   double* r;        // [Wk][N][3]
   void* phi;        // [Wk][N][Lp]  basis values (double or float)
   void* P;          // [Wk][N][Lp]  rows i<nu: Phi_up Lambda ; rows i>=nu: Phi_dn Lambda^T
-  double* W;        // [Wk][nu][nd]
-  double* A;        // [Wk][nd][nu]  W^{-1}
+  double* W;        // [Wk][nu][nu]  columns: n_dn paired, then nk unpaired
+  double* A;        // [Wk][nu][nu]  W^{-1}
   double* Yt;       // [Wk][N][Lp]  eval workspace: Yt_up = A^T P_dn, Yt_dn = A P_up
   double* D;        // [Wk][N][4]   grad det/det (3), lap det/det
   double* logdet;   // [Wk]

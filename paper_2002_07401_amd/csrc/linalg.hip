@@ -171,7 +171,7 @@ static hipError_t launch_lu_inverse_big(const SysDev& s, const WalkDev& w, hipSt
 hipError_t launch_lu_inverse(const SysDev& s, const WalkDev& w, hipStream_t st) {
   const int n = s.nu;
   if (n > kLuRowMax) return launch_lu_inverse_big(s, w, st);
-  const long wbs = (long)s.nu * s.nd, abs_ = (long)s.nd * s.nu;
+  const long wbs = (long)s.nu * s.nu, abs_ = wbs;   // W is n_up x n_up
   const dim3 blk(n > 64 ? 128 : 64);
   switch ((n + 7) >> 3) {
 #define QMC_LU_ROW(C)                                                                                   \

@@ -266,11 +266,14 @@ __device__ void rows_body(const SysDev& s, const WalkDev& w, int wk, int sb, int
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
   const bool up = e < s.nu;
   const int row0 = up ? s.nu : 0;
-  const int nrow = up ? s.nd : s.nu;
-  const int nmax = s.nu > s.nd ? s.nu : s.nd;
+  const int nrow = s.nu;   // W is n_up x n_up: a row has n_dn paired and nk unpaired columns
   const T* Pw = (const T*)w.P + ((long)wk * s.N + row0) * s.Lp;
+  // row j of the streamed side: walker rows, then (up moves) the unpaired orbitals
+  auto rowp = [&](int j) -> const T* {
+    return (up && j >= s.nd) ? (const T*)s.UphS + (long)(j - s.nd) * s.Lp : Pw + (long)j * s.Lp;
+  };
   const double* cv = w.cvec + (long)wk * s.nu;
-  double* wn_g = w.w_new + (long)wk * nmax;
+  double* wn_g = w.w_new + (long)wk * s.nu;
   const double* psi = w.psi_new + (long)wk * s.Lp;
   const int j0 = sb * R;
   const int j1 = min(j0 + R, nrow);
@@ -291,8 +294,8 @@ __device__ void rows_body(const SysDev& s, const WalkDev& w, int wk, int sb, int
   for (int j = j0 + wave; j < j1; j += 2 * nw, k += 2) {
     const int jb = j + nw;
     const bool two = jb < j1;   // uniform over the wave
-    const T* pa = Pw + (long)j * s.Lp;
-    const T* pb = two ? Pw + (long)jb * s.Lp : pa;   // never formed past the block
+    const T* pa = rowp(j);
+    const T* pb = two ? rowp(jb) : pa;   // never formed past the block
     V va[NC], vb[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
@@ -334,18 +337,17 @@ __device__ void rows_generic_body(const SysDev& s, const WalkDev& w, int wk, int
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
   const bool up = e < s.nu;
   const int row0 = up ? s.nu : 0;
-  const int nrow = up ? s.nd : s.nu;
-  const int nmax = s.nu > s.nd ? s.nu : s.nd;
+  const int nrow = s.nu;   // W is n_up x n_up (see rows_body)
   const T* Pw = (const T*)w.P + ((long)wk * s.N + row0) * s.Lp;
   const double* cv = w.cvec + (long)wk * s.nu;
-  double* wn_g = w.w_new + (long)wk * nmax;
+  double* wn_g = w.w_new + (long)wk * s.nu;
   const double* psi = w.psi_new + (long)wk * s.Lp;
   const double* gpsi = w.gpsi_new + (long)wk * 3 * s.Lp;
   const int j0 = sb * R;
   const int j1 = min(j0 + R, nrow);
   double part = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
   for (int j = j0 + wave; j < j1; j += nw) {
-    const T* prow = Pw + (long)j * s.Lp;
+    const T* prow = (up && j >= s.nd) ? (const T*)s.UphS + (long)(j - s.nd) * s.Lp : Pw + (long)j * s.Lp;
     double a0 = 0.0, ax = 0.0, ay = 0.0, az = 0.0;
     for (int mu = lane; mu < s.Lp; mu += 64) {
       const double p = (double)prow[mu];
@@ -441,7 +443,7 @@ __device__ void accept_apply(const SysDev& s, const WalkDev& w, int wk, int e, d
   __shared__ double sy[kWbMax];
   __shared__ double red[16];
   __shared__ double gam_s;
-  const int n = s.nu;             // square: n_up == n_dn
+  const int n = s.nu;             // W is n_up x n_up
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
   const int kb = w.kb;
   const bool up = e < s.nu;

@@ -161,7 +161,8 @@ extern "C" qmc_status qmc_system_create(const qmc_system_desc* desc, qmc_system*
   if (q.n_basis <= 0 || !q.center || !q.l || !q.m || !q.zeta || !q.lambda)
     return fail(QMC_ERR_ARG, "bad basis");
   if (q.n_up <= 0 || q.n_dn < 0) return fail(QMC_ERR_ARG, "bad electron counts");
-  if (q.n_up != q.n_dn) return fail(QMC_ERR_UNSUPPORTED, "only n_up == n_dn is built");
+  if (q.n_up < q.n_dn) return fail(QMC_ERR_UNSUPPORTED, "n_up < n_dn: label the majority spin up");
+  if (q.n_up > q.n_dn && !q.unpaired) return fail(QMC_ERR_ARG, "n_up > n_dn needs the unpaired orbitals");
   if (q.n_up > kBigMaxN) return fail(QMC_ERR_UNSUPPORTED, "n_up > 1024 is not built");
   if (q.precision < QMC_FP64 || q.precision > QMC_MIXED_BF16)
     return fail(QMC_ERR_UNSUPPORTED, "precision not built");
@@ -204,7 +205,7 @@ extern "C" qmc_status qmc_system_create(const qmc_system_desc* desc, qmc_system*
   SysDev& d = s->d;
   if (hipGetDevice(&s->device) != hipSuccess) s->device = 0;
   d.n_nuc = q.n_nuc; d.L = L; d.Lp = round_up(L, 32);
-  d.nu = q.n_up; d.nd = q.n_dn; d.N = q.n_up + q.n_dn;
+  d.nu = q.n_up; d.nd = q.n_dn; d.N = q.n_up + q.n_dn; d.nk = q.n_up - q.n_dn;
   d.j1_form = q.j1_form; d.j2_form = q.j2_form;
   for (int k = 0; k < 8; ++k) d.j2[k] = (q.j2 && k < q.n_j2) ? q.j2[k] : 0.0;
   d.precision = q.precision; d.refresh_every = q.refresh_every;
@@ -309,6 +310,33 @@ extern "C" qmc_status qmc_system_create(const qmc_system_desc* desc, qmc_system*
     }
     e = up((void**)&d.bfn, bf.data(), sizeof(double) * bf.size());
   }
+  if (!e && d.nk > 0) {
+    // unpaired orbital l as a fixed row: Uph[l][mu] = unpaired[mu][l]
+    std::vector<double> uph((size_t)d.nk * Lp, 0.0);
+    for (int l = 0; l < d.nk; ++l)
+      for (int mu = 0; mu < L; ++mu) uph[(size_t)l * Lp + mu] = q.unpaired[(size_t)mu * d.nk + l];
+    e = up((void**)&d.Uph, uph.data(), sizeof(double) * uph.size());
+    if (!e && q.precision != QMC_FP64) {
+      std::vector<float> u32(uph.begin(), uph.end());
+      e = up((void**)&d.Uph32, u32.data(), sizeof(float) * u32.size());
+    }
+    if (!e) {
+      if (q.precision == QMC_FP64) {
+        d.UphS = d.Uph;
+      } else if (q.precision == QMC_MIXED_BF16) {
+        void* u16 = nullptr;
+        e = hipMalloc(&u16, sizeof(uint16_t) * uph.size() + 256);
+        if (!e) {
+          s->allocs.push_back(u16);
+          e = launch_downcast(d.Uph, u16, true, (long)uph.size(), nullptr);
+          if (!e) e = hipStreamSynchronize(nullptr);
+        }
+        d.UphS = u16;
+      } else {
+        d.UphS = d.Uph32;
+      }
+    }
+  }
   if (!e && q.precision != QMC_FP64) {
     std::vector<float> l32(lam.begin(), lam.end()), lT32(lamT.begin(), lamT.end());
     e = up((void**)&d.lam32, l32.data(), sizeof(float) * l32.size());
@@ -361,8 +389,8 @@ extern "C" qmc_status qmc_walkers_create(qmc_system* sys, int32_t n_walkers, qmc
   al((void**)&d.r, sizeof(double) * Wk * N * 3);
   al(&d.phi, esz * Wk * N * Lp);
   al(&d.P, esz * Wk * N * Lp);
-  al((void**)&d.W, sizeof(double) * Wk * s.nu * s.nd);
-  al((void**)&d.A, sizeof(double) * Wk * s.nd * s.nu);
+  al((void**)&d.W, sizeof(double) * Wk * s.nu * s.nu);
+  al((void**)&d.A, sizeof(double) * Wk * s.nu * s.nu);
   al((void**)&d.Yt, sizeof(double) * Wk * N * Lp);
   al((void**)&d.D, sizeof(double) * Wk * N * 4);
   al((void**)&d.logdet, sizeof(double) * Wk);
@@ -670,7 +698,7 @@ extern "C" qmc_status qmc_walkers_read(qmc_walkers* wk, int32_t item, double* ds
     case QMC_STATE_R: src = d.r; bytes = sizeof(double) * Wk * s.N * 3; break;
     case QMC_STATE_LOGABS: src = d.logabs; bytes = sizeof(double) * Wk; break;
     case QMC_STATE_SIGN: src = d.sign; bytes = sizeof(double) * Wk; break;
-    case QMC_STATE_W: src = d.W; bytes = sizeof(double) * Wk * s.nu * s.nd; break;
+    case QMC_STATE_W: src = d.W; bytes = sizeof(double) * Wk * s.nu * s.nu; break;
     case QMC_STATE_AINV:   // A0 combined with the delayed updates
       HIP_TRY(launch_materialize_inverse(s, d, wk->buf_spin == 1, wk->rd_scratch, dst, stream), "read inverse");
       return QMC_OK;
@@ -751,6 +779,7 @@ extern "C" qmc_status qmc_forces(qmc_system* sys, qmc_walkers* wk, const double*
   if (s.precision != QMC_FP64) return fail(QMC_ERR_UNSUPPORTED, "forces are built for the FP64 path");
   if (s.LJ > 0) return fail(QMC_ERR_UNSUPPORTED, "forces with a Jastrow basis are not built");
   if (s.Lq > 0) return fail(QMC_ERR_UNSUPPORTED, "forces with contracted orbitals are not built");
+  if (s.nk > 0) return fail(QMC_ERR_UNSUPPORTED, "forces with unpaired orbitals are not built");
   if (s.N > 2 * kLuMaxN || s.n_nuc > kMaxNucBack)
     return fail(QMC_ERR_UNSUPPORTED, "forces need N <= 256 electrons and <= 256 nuclei");
   hipError_t e = alloc_adjoint(wk);

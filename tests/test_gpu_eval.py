@@ -130,9 +130,9 @@ def test_argument_errors():
     w = C.tiny_3nuc_10e(n_walkers=2)
     import dataclasses
     with pytest.raises(P.QMCError) as ei:
-        P.JAGPSystem(dataclasses.replace(w.system, n_up=6, n_dn=4,
-                                         unpaired=np.zeros((24, 2))))
-    assert ei.value.code == -5
+        P.JAGPSystem(dataclasses.replace(w.system, n_up=4, n_dn=6,
+                                         unpaired=np.zeros((24, 0))))
+    assert ei.value.code == -5   # the majority spin must be labelled up
     sysh = P.JAGPSystem(w.system)
     wk = P.Walkers(sysh, 2)
     with pytest.raises(P.QMCError) as ei:

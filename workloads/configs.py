@@ -157,11 +157,16 @@ def _electron_counts(Z, n_elec):
 
 def _initial_positions(rng, R, Z, n_up, n_dn, n_walkers, spread=1.0):
     """Electrons at R_a + N(0, spread^2); spins alternate over the per-nucleus
-    list, then up electrons are put first."""
+    list (the electrons past 2 n_dn are up), then up electrons are put first."""
     counts = _electron_counts(Z, n_up + n_dn)
     owner = np.repeat(np.arange(len(Z)), counts)
-    up_idx = owner[0::2]
-    dn_idx = owner[1::2]
+    if n_up == n_dn:
+        up_idx = owner[0::2]
+        dn_idx = owner[1::2]
+    else:
+        pair = owner[:2 * n_dn]
+        up_idx = np.concatenate([pair[0::2], owner[2 * n_dn:]])
+        dn_idx = pair[1::2]
     assert len(up_idx) == n_up and len(dn_idx) == n_dn, (len(up_idx), len(dn_idx))
     order = np.concatenate([up_idx, dn_idx])
     r0 = R[order][None, :, :] + spread * rng.standard_normal((n_walkers, len(order), 3))
@@ -320,6 +325,33 @@ def contracted_4nuc_20e(n_walkers=32, n_steps=200, seed_offset=7) -> Workload:
         lam=_sym_gaussian(rng, L, 1.0 / L), n_up=10, n_dn=10, unpaired=np.zeros((L, 0)),
         j1_form=2, j1_b=np.ones(4), j2_form=1, j2=np.array([1.0, 1.0]), refresh_every=32, contraction=C)
     r0 = _initial_positions(rng, R, Z, 10, 10, n_walkers)
+    disp, unif = _chain_arrays(rng, n_steps, n_walkers, 0.3)
+    return Workload(sysd, r0, disp, unif, 0.3)
+
+
+def polarized_4nuc_20e(n_walkers=32, n_steps=200, seed_offset=8) -> Workload:
+    """A spin-polarized geminal with unpaired orbitals (eq:wfAGPunpaired):
+    4 nuclei (Z = 2, 4, 6, 8) in an 8-bohr cube, 20 electrons, 11 up / 9 down
+    (two unpaired orbitals); per atom 3 s + 1 p + 1 d Gaussian shells (L = 44,
+    zeta log-uniform in [0.1, 10]); Lambda symmetric N(0,1)/44; unpaired
+    coefficients N(0, 1/44); Pade J1 and J2 with b = 1."""
+    rng = np.random.default_rng(SEED_BASE + seed_offset)
+    Z = np.array([2.0, 4.0, 6.0, 8.0])
+    R = _place_nuclei(rng, 4, 8.0)
+    center, l, m, zeta = [], [], [], []
+    for a in range(4):
+        for ll in (0, 0, 0, 1, 2):
+            z = float(_log_uniform(rng, 0.1, 10.0, 1)[0])
+            for mm in range(N_COMP[ll]):
+                center.append(a); l.append(ll); m.append(mm); zeta.append(z)
+    L = len(center)
+    sysd = System(
+        name="polarized_4nuc_20e", R=R, Z=Z, center=np.array(center, np.int32), l=np.array(l, np.int32),
+        m=np.array(m, np.int32), zeta=np.array(zeta, np.float64), radial=np.zeros(L, np.int32),
+        lam=_sym_gaussian(rng, L, 1.0 / L), n_up=11, n_dn=9,
+        unpaired=rng.standard_normal((L, 2)) / np.sqrt(L),
+        j1_form=2, j1_b=np.ones(4), j2_form=1, j2=np.array([1.0, 1.0]), refresh_every=32)
+    r0 = _initial_positions(rng, R, Z, 11, 9, n_walkers)
     disp, unif = _chain_arrays(rng, n_steps, n_walkers, 0.3)
     return Workload(sysd, r0, disp, unif, 0.3)
 
