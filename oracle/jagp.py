@@ -76,6 +76,13 @@ class OSystem:
     # center .. zeta then describe the primitives and lam / unpaired the
     # contracted functions (None: lam / unpaired act on the primitives)
     contraction: Optional[torch.Tensor] = None  # [L_primitive, L]
+    # Pfaffian pairing (pairing = 1): lam is A^{ud}, pf_uu / pf_dd the
+    # skew-symmetric same-spin blocks, unpaired / unpaired_dn the unpaired
+    # orbitals of up / down electrons (k = unpaired.shape[1], N + k even)
+    pairing: int = 0
+    pf_uu: Optional[torch.Tensor] = None       # [L, L]
+    pf_dd: Optional[torch.Tensor] = None       # [L, L]
+    unpaired_dn: Optional[torch.Tensor] = None  # [L, k]
 
     @property
     def n_elec(self):
@@ -97,7 +104,10 @@ def from_workload_system(s) -> OSystem:
         **({} if getattr(s, "jb_zeta", None) is None else dict(
             jb_center=_t(s.jb_center, torch.long), jb_l=_t(s.jb_l, torch.long), jb_m=_t(s.jb_m, torch.long),
             jb_radial=_t(s.jb_radial, torch.long), jb_zeta=_t(s.jb_zeta), j1_inh=_t(s.j1_inh), j3=_t(s.j3))),
-        **({} if getattr(s, "contraction", None) is None else dict(contraction=_t(s.contraction))))
+        **({} if getattr(s, "contraction", None) is None else dict(contraction=_t(s.contraction))),
+        **({} if not getattr(s, "pairing", 0) else dict(
+            pairing=int(s.pairing), pf_uu=_t(s.pf_uu), pf_dd=_t(s.pf_dd),
+            unpaired_dn=_t(s.unpaired_dn).reshape(len(s.lam), -1))))
 
 
 # ---------------------------------------------------------------------------
@@ -356,6 +366,9 @@ def geminal(sy: OSystem, Phi, lam=None):
 
 def log_psi(sy: OSystem, r, R=None, zeta=None, lam=None, j1_b=None, j2=None):
     """log|Psi| [Wk] and sign(Psi) [Wk] (sign of the determinant)."""
+    if sy.pairing:
+        from oracle import pfaffian
+        return pfaffian.log_psi(sy, r, R, zeta, lam, j1_b, j2)
     Phi, _, _ = agp_basis(sy, r, R, zeta)
     W = geminal(sy, Phi, lam)
     sign, logdet = torch.linalg.slogdet(W)
@@ -374,6 +387,9 @@ def evaluate(sy: OSystem, r, R=None, zeta=None, lam=None, j1_b=None, j2=None,
     and lap Psi / Psi = lap det/det + 2 grad det/det . grad J + lap J + |grad J|^2.
     status: 0 ok, 1 singular (det = 0), 2 non-finite result.
     """
+    if sy.pairing:
+        from oracle import pfaffian
+        return pfaffian.evaluate(sy, r, with_intermediates)
     lam = sy.lam if lam is None else lam
     nu, nd = sy.n_up, sy.n_dn
     Phi, G, H = agp_basis(sy, r, R, zeta)

@@ -66,6 +66,13 @@ class System:
     # contraction of the primitive basis: center .. radial describe the
     # primitives, lam / unpaired act on phi_c = sum_mu C[mu, c] psi_mu
     contraction: Optional[np.ndarray] = None  # [L_primitive, L] float64
+    # Pfaffian pairing (pairing = 1, eq:g): lam is the unlike-spin block A^{ud},
+    # pf_uu / pf_dd the skew-symmetric same-spin blocks, unpaired / unpaired_dn
+    # the unpaired orbitals of up / down electrons (k columns, N + k even)
+    pairing: int = 0
+    pf_uu: Optional[np.ndarray] = None       # [L, L]
+    pf_dd: Optional[np.ndarray] = None       # [L, L]
+    unpaired_dn: Optional[np.ndarray] = None  # [L, k]
 
     @property
     def n_jbasis(self) -> int:
@@ -351,6 +358,42 @@ def polarized_4nuc_20e(n_walkers=32, n_steps=200, seed_offset=8) -> Workload:
         lam=_sym_gaussian(rng, L, 1.0 / L), n_up=11, n_dn=9,
         unpaired=rng.standard_normal((L, 2)) / np.sqrt(L),
         j1_form=2, j1_b=np.ones(4), j2_form=1, j2=np.array([1.0, 1.0]), refresh_every=32)
+    r0 = _initial_positions(rng, R, Z, 11, 9, n_walkers)
+    disp, unif = _chain_arrays(rng, n_steps, n_walkers, 0.3)
+    return Workload(sysd, r0, disp, unif, 0.3)
+
+
+def _skew_gaussian(rng, L, scale):
+    u = rng.standard_normal((L, L)) * scale
+    return np.triu(u, 1) - np.triu(u, 1).T
+
+
+def pfaffian_4nuc_20e(n_walkers=32, n_steps=200, seed_offset=9) -> Workload:
+    """A Pfaffian wave function with all four pairing components (eq:g):
+    4 nuclei (Z = 2, 4, 6, 8) in an 8-bohr cube, 20 electrons, 11 up / 9 down
+    with k = 2 unpaired orbitals per spin (G~ is 22 x 22); per atom
+    3 s + 1 p + 1 d Gaussian shells (L = 44, zeta log-uniform in [0.1, 10]);
+    A^{ud} = singlet (symmetric N(0,1)/44) + triplet-zero part (skew N(0, 0.3^2)/44);
+    A^{uu}, A^{dd} skew N(0, 0.5^2)/44; unpaired coefficients N(0, 1/44) for
+    each spin; Pade J1 and J2 with b = 1."""
+    rng = np.random.default_rng(SEED_BASE + seed_offset)
+    Z = np.array([2.0, 4.0, 6.0, 8.0])
+    R = _place_nuclei(rng, 4, 8.0)
+    center, l, m, zeta = [], [], [], []
+    for a in range(4):
+        for ll in (0, 0, 0, 1, 2):
+            z = float(_log_uniform(rng, 0.1, 10.0, 1)[0])
+            for mm in range(N_COMP[ll]):
+                center.append(a); l.append(ll); m.append(mm); zeta.append(z)
+    L = len(center)
+    aud = _sym_gaussian(rng, L, 1.0 / L) + _skew_gaussian(rng, L, 0.3 / L)
+    sysd = System(
+        name="pfaffian_4nuc_20e", R=R, Z=Z, center=np.array(center, np.int32), l=np.array(l, np.int32),
+        m=np.array(m, np.int32), zeta=np.array(zeta, np.float64), radial=np.zeros(L, np.int32),
+        lam=aud, n_up=11, n_dn=9, unpaired=rng.standard_normal((L, 2)) / np.sqrt(L),
+        j1_form=2, j1_b=np.ones(4), j2_form=1, j2=np.array([1.0, 1.0]), refresh_every=32,
+        pairing=1, pf_uu=_skew_gaussian(rng, L, 0.5 / L), pf_dd=_skew_gaussian(rng, L, 0.5 / L),
+        unpaired_dn=rng.standard_normal((L, 2)) / np.sqrt(L))
     r0 = _initial_positions(rng, R, Z, 11, 9, n_walkers)
     disp, unif = _chain_arrays(rng, n_steps, n_walkers, 0.3)
     return Workload(sysd, r0, disp, unif, 0.3)
