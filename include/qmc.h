@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define QMC_ABI_VERSION 7
+#define QMC_ABI_VERSION 8
 
 typedef enum {
   QMC_OK = 0,
@@ -135,6 +135,21 @@ typedef struct {
    * phi_mu(r_i) (phi the orbitals: the basis functions, or the contracted
    * orbitals).  Not supported with it: qmc_forces, qmc_multi_*. */
   const double *unpaired;     /* [L or Lc][k]; may be NULL when k = 0            */
+  /* Pfaffian pairing (Pfaffian wave function section), pairing = 1: Psi =
+   * Pf(G~) exp J with G~_ij = phi(r_i)^T A^{s_i s_j} phi(r_j) (eq:g,
+   * agp_expansion), A^{ud} = lambda (singlet plus triplet-zero part, any
+   * matrix), A^{du} = -lambda^T, A^{uu} = pf_uu and A^{dd} = pf_dd
+   * skew-symmetric; pf_k unpaired orbitals as fictitious electrons
+   * (eq:pfodd): G~_{i, N+l} = phi(r_i) . U^{s_i}[:, l] with U^u = unpaired
+   * and U^d = pf_unpaired_dn.  N + pf_k must be even and at most 96; FP64
+   * precision only; n_up < n_dn is allowed.  Not supported with it:
+   * qmc_forces, qmc_multi_*, qmc_reweight, qmc_system_set_params, a Jastrow
+   * basis, contracted orbitals, drifts from qmc_propose_move. */
+  int32_t pairing;            /* 0 AGP determinant, 1 Pfaffian                   */
+  const double *pf_uu;        /* [L][L] skew-symmetric                           */
+  const double *pf_dd;        /* [L][L] skew-symmetric                           */
+  int32_t pf_k;               /* unpaired orbitals of the Pfaffian               */
+  const double *pf_unpaired_dn; /* [L][pf_k]                                     */
 } qmc_system_desc;
 
 /* Version of this header the library was built from (QMC_ABI_VERSION). */

@@ -74,6 +74,8 @@ class SystemDesc(ctypes.Structure):
         ("j1_inh", ctypes.c_void_p), ("j3", ctypes.c_void_p),
         ("n_contracted", ctypes.c_int32), ("con_ptr", ctypes.c_void_p), ("con_idx", ctypes.c_void_p),
         ("con_coef", ctypes.c_void_p), ("unpaired", ctypes.c_void_p),
+        ("pairing", ctypes.c_int32), ("pf_uu", ctypes.c_void_p), ("pf_dd", ctypes.c_void_p),
+        ("pf_k", ctypes.c_int32), ("pf_unpaired_dn", ctypes.c_void_p),
     ]
 
 
@@ -166,6 +168,11 @@ class JAGPSystem:
                         jb_zeta=np.ascontiguousarray(s.jb_zeta, np.float64),
                         j1_inh=np.ascontiguousarray(s.j1_inh, np.float64),
                         j3=np.ascontiguousarray(s.j3, np.float64))
+        pf = int(getattr(s, "pairing", 0) or 0)
+        k_pf = keep["unpaired"].shape[1] if pf else 0
+        if pf:
+            keep.update(pf_uu=np.ascontiguousarray(s.pf_uu, np.float64), pf_dd=np.ascontiguousarray(s.pf_dd, np.float64),
+                        pf_dn=np.ascontiguousarray(np.asarray(s.unpaired_dn, np.float64).reshape(len(s.lam), -1)))
         Cm = getattr(s, "contraction", None)
         if Cm is not None:
             # CSR of the contraction by orbital: the nonzero C[mu][c] of each column c
@@ -183,7 +190,10 @@ class JAGPSystem:
             j1_form=s.j1_form, j1_b=p(keep["j1_b"]), j2_form=s.j2_form, n_j2=len(s.j2),
             j2=p(keep["j2"]), precision=precision,
             refresh_every=s.refresh_every if refresh_every is None else refresh_every,
-            n_jbasis=LJ, unpaired=p(keep["unpaired"]) if s.n_up > s.n_dn else None,
+            n_jbasis=LJ, unpaired=p(keep["unpaired"]) if (s.n_up > s.n_dn and not pf) or k_pf else None,
+            pairing=pf, pf_k=k_pf,
+            **({} if not pf else dict(pf_uu=p(keep["pf_uu"]), pf_dd=p(keep["pf_dd"]),
+                                      pf_unpaired_dn=p(keep["pf_dn"]) if k_pf else None)),
             **({} if not LJ else dict(jb_center=p(keep["jb_center"]), jb_l=p(keep["jb_l"]), jb_m=p(keep["jb_m"]),
                                       jb_radial=p(keep["jb_radial"]), jb_zeta=p(keep["jb_zeta"]),
                                       j1_inh=p(keep["j1_inh"]), j3=p(keep["j3"]))),
@@ -197,6 +207,8 @@ class JAGPSystem:
         self.n_up, self.n_dn, self.L = s.n_up, s.n_dn, len(s.lam)
         self.n_nuc = len(s.Z)
         self.n_jas = len(s.Z) + len(s.j2)
+        self.pairing = pf
+        self.npf = s.n_up + s.n_dn + k_pf if pf else 0
 
     def set_params(self, R=None, zeta=None, lam=None, jas=None, stream=None):
         """Replace parameters from device tensors (None keeps the current value)."""
@@ -270,8 +282,9 @@ class Walkers:
 
     def read(self, item: int, stream=None) -> torch.Tensor:
         Wk, N, nu, nd, L = self.n, self.sys.n_elec, self.sys.n_up, self.sys.n_dn, self.sys.L
-        shape = {STATE_R: (Wk, N, 3), STATE_LOGABS: (Wk,), STATE_SIGN: (Wk,), STATE_W: (Wk, nu, nu),
-                 STATE_AINV: (Wk, nu, nu), STATE_PHI: (Wk, N, L)}[item]
+        n = self.sys.npf if self.sys.pairing else nu   # G~ (Pfaffian) or W
+        shape = {STATE_R: (Wk, N, 3), STATE_LOGABS: (Wk,), STATE_SIGN: (Wk,), STATE_W: (Wk, n, n),
+                 STATE_AINV: (Wk, n, n), STATE_PHI: (Wk, N, L)}[item]
         dst = torch.empty(shape, dtype=torch.float64, device="cuda")
         _check(load().qmc_walkers_read(self.h, item, _ptr(dst), _stream(stream)))
         return dst

@@ -118,6 +118,16 @@ struct SysDev {
   double* Uph;       // [nk][Lp]
   float* Uph32;      // [nk][Lp] (reduced-precision storage)
   const void* UphS;  // [nk][Lp]
+  // Pfaffian pairing (pairing = 1): G~ is npf x npf (npf = N + pk, pk
+  // unpaired orbitals as fictitious electrons), G~_ij = psi(r_i) . B^{s_i}_j
+  // with the rows B^s_j = psi(r_j)^T K^{s s_j}, K^{s s'} = (A^{s s'})^T; the
+  // walkers keep B^u in P and B^d in Bd.  FP64, npf <= kLuRowMax.
+  int pairing, npf, pk;
+  double* Kuu;       // [Lp][Lp]  (A^{uu})^T
+  double* Kud;       // [Lp][Lp]  (A^{ud})^T
+  double* Kdu;       // [Lp][Lp]  (A^{du})^T = -A^{ud}
+  double* Kdd;       // [Lp][Lp]  (A^{dd})^T
+  double* Upf;       // [2][pk][Lp] unpaired orbitals of up, then down electrons
 };
 
 // Device state of a batch of walkers.
@@ -181,6 +191,8 @@ struct WalkDev {
   double* chi_new;    // [Wk][LJ]
   double* j3e;        // [Wk][N][5] value part, gradient (3), Laplacian
   double* qbuf;       // [Wk][4][Lq] primitive values (and gradients) at r' (contracted orbitals)
+  double* Bd;         // [Wk][N][Lp] B^d rows (Pfaffian pairing; B^u rows are in P)
+  double* pfw;        // [Wk][npf][npf] Parlett-Reid working copy (Pfaffian pairing)
 };
 
 // Workspace of the reverse pass (allocated on the first qmc_forces call).
@@ -440,6 +452,20 @@ hipError_t launch_Y_build(const SysDev& s, const WalkDev& w, hipStream_t st);
 hipError_t launch_lu_inverse(const SysDev& s, const WalkDev& w, hipStream_t st);
 hipError_t launch_lam_mask(const SysDev& s, hipStream_t st);
 hipError_t launch_rowdots(const SysDev& s, const WalkDev& w, hipStream_t st);
+// Gauss-Jordan inverse and log|det| of Wk dense n x n matrices (n <= kLuRowMax)
+hipError_t launch_gj_inverse_n(int Wk, int n, const double* W, double* A, double* logdet, double* detsign,
+                               int* singular, hipStream_t st);
+// Pfaffian pairing: B rows, G~, its Pfaffian (log|Pf|, sign into logdet / detsign)
+// and inverse, cofactor vectors; proposal and accept of a single-electron move
+hipError_t launch_pf_B_build(const SysDev& s, const WalkDev& w, hipStream_t st);
+hipError_t launch_pf_G_build(const SysDev& s, const WalkDev& w, hipStream_t st);
+hipError_t launch_pf_factor(const SysDev& s, const WalkDev& w, hipStream_t st);
+hipError_t launch_pf_Y_build(const SysDev& s, const WalkDev& w, hipStream_t st);
+hipError_t launch_pf_propose(const SysDev& s, const WalkDev& w, int e, const double* r_new, const double* disp,
+                             double* ratio, hipStream_t st);
+hipError_t launch_pf_accept(const SysDev& s, const WalkDev& w, int e, const uint8_t* acc, const double* unif,
+                            int32_t* accept_count, hipStream_t st);
+
 // Jastrow-basis terms of an evaluation (LJ > 0): chi, X -> G, h, per-electron terms
 hipError_t launch_jastrow3_eval(const SysDev& s, const WalkDev& w, hipStream_t st);
 // Estimators (space warp, reweighting factor, stochastic reconfiguration)

@@ -171,13 +171,19 @@ static hipError_t launch_lu_inverse_big(const SysDev& s, const WalkDev& w, hipSt
 hipError_t launch_lu_inverse(const SysDev& s, const WalkDev& w, hipStream_t st) {
   const int n = s.nu;
   if (n > kLuRowMax) return launch_lu_inverse_big(s, w, st);
-  const long wbs = (long)s.nu * s.nu, abs_ = wbs;   // W is n_up x n_up
+  return launch_gj_inverse_n(w.Wk, n, w.W, w.A, w.logdet, w.detsign, w.singular, st);   // W is n_up x n_up
+}
+
+hipError_t launch_gj_inverse_n(int Wk, int n, const double* W, double* A, double* logdet, double* detsign,
+                               int* singular, hipStream_t st) {
+  if (n < 1 || n > kLuRowMax) return hipErrorNotSupported;
+  const long wbs = (long)n * n, abs_ = wbs;
   const dim3 blk(n > 64 ? 128 : 64);
   switch ((n + 7) >> 3) {
 #define QMC_LU_ROW(C)                                                                                   \
     case C:                                                                                             \
-      hipLaunchKernelGGL(gj_inverse_row_kernel<8 * C>, dim3(w.Wk), blk, 0, st, w.W, w.A, w.logdet,      \
-                         w.detsign, w.singular, n, wbs, abs_);                                          \
+      hipLaunchKernelGGL(gj_inverse_row_kernel<8 * C>, dim3(Wk), blk, 0, st, W, A, logdet,              \
+                         detsign, singular, n, wbs, abs_);                                              \
       break;
     QMC_LU_ROW(1) QMC_LU_ROW(2) QMC_LU_ROW(3) QMC_LU_ROW(4) QMC_LU_ROW(5) QMC_LU_ROW(6)
     QMC_LU_ROW(7) QMC_LU_ROW(8) QMC_LU_ROW(9) QMC_LU_ROW(10) QMC_LU_ROW(11) QMC_LU_ROW(12)

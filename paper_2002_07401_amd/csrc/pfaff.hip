@@ -1,0 +1,366 @@
+// Pfaffian wave function (Pfaffian wave function section): Psi = Pf(G~) exp J.
+//
+// G~ is the skew-symmetric (N + k) x (N + k) pairing matrix: for electrons i, j
+// (spins s_i, s_j)  G~_ij = psi(r_i)^T A^{s_i s_j} psi(r_j)  with A^{uu}, A^{dd}
+// skew-symmetric (triplet components +1 / -1), A^{ud} the unlike-spin
+// singlet + triplet-zero coefficients and A^{du} = -(A^{ud})^T (eq:g,
+// agp_expansion); k unpaired orbitals enter as fictitious electrons,
+// G~_{i, N+l} = psi(r_i) . U^{s_i}_l (eq:pfodd).
+//
+// Per electron j two rows are kept, B^s_j = psi(r_j)^T K^{s s_j} with
+// K^{s s'} = (A^{s s'})^T, so that row i of G~ is psi(r_i) . B^{s_i}_j: the
+// rows are four FP64 MFMA products over the walkers, G~ one dot product per
+// entry of its upper triangle (the lower one mirrored, so G~ is exactly
+// skew-symmetric).  Pf(G~) (log|Pf| and sign) comes from a Parlett-Reid
+// reduction with partial pivoting, one workgroup per walker on a working copy;
+// G~^{-1} from the Gauss-Jordan kernel of the determinant path.
+//
+// Pf is linear in row and column i, which alone depend on r_i, and
+// d log Pf = 1/2 tr(G~^{-1} dG~) with G~^{-1} skew-symmetric, so the
+// determinant's cofactor identities hold with Y_i = sum_j (G~^{-1})_ji B^{s_i}_j
+// (+ sum_l (G~^{-1})_{N+l, i} U^{s_i}_l): grad_i Pf / Pf = grad psi(r_i) . Y_i and
+// lap_i Pf / Pf = lap psi(r_i) . Y_i; the row-dot, Jastrow and assembly kernels
+// of the determinant path then apply unchanged, and so do the lattice hops
+// (a hop's ratio is psi(r') . Y_i).
+//
+// A move of electron e replaces row e (and column e, negated) by
+//   g'_j = psi(r') . B^{s_e}_j  (j < N, j != e),  g'_e = 0,  g'_{N+l} = psi(r') . U^{s_e}_l,
+// and Pf(G') / Pf(G) = sum_j g'_j (G^{-1})_je.  With delta = g' - G[e, :],
+// G' = G + e_e delta^T - delta e_e^T, and Woodbury's identity for this skew
+// rank-2 change gives, with p = G^{-1} e_e, q = G^{-1} delta and rho the ratio,
+//   G'^{-1} = G^{-1} + (p q^T - q p^T) / rho.
+// The accept also rewrites electron e's basis row and its two B rows; the
+// inverse is recomputed from the maintained G~ every refresh_every moves.
+#include "move_dev.h"
+
+namespace qmc {
+
+constexpr int kPfMaxN = kLuRowMax;   // G~ dimension (Gauss-Jordan register kernel)
+
+// ---------------------------------------------------------------------------
+// B rows: P (B^u) and Bd (B^d), each as up rows times K^{s u} and down rows
+// times K^{s d}, batched over walkers
+// ---------------------------------------------------------------------------
+hipError_t launch_pf_B_build(const SysDev& s, const WalkDev& w, hipStream_t st) {
+  const long rowst = (long)s.N * s.Lp;
+  struct Part { const double* K; double* out; int row0, nrow; };
+  const Part parts[4] = {{s.Kuu, (double*)w.P, 0, s.nu}, {s.Kud, (double*)w.P, s.nu, s.nd},
+                         {s.Kdu, w.Bd, 0, s.nu}, {s.Kdd, w.Bd, s.nu, s.nd}};
+  for (const Part& x : parts) {
+    if (x.nrow == 0) continue;
+    GemmArgs g = gemm_args(w.Wk * x.nrow, s.Lp, s.Lp);
+    g.A = (const double*)w.phi + (long)x.row0 * s.Lp; g.lda = s.Lp; g.a_grp = x.nrow; g.a_gs = rowst;
+    g.B = x.K; g.ldb = s.Lp;
+    g.C = x.out + (long)x.row0 * s.Lp; g.ldc = s.Lp; g.c_grp = x.nrow; g.c_gs = rowst;
+    const hipError_t e = gemm_f64(g, false, false, true, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// G~: workgroup (i, walker) computes row i's upper-triangle entries and writes
+// them with their negated mirror images; rows of fictitious electrons clear
+// their block
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) pf_G_kernel(SysDev s, WalkDev w) {
+  const int i = blockIdx.x, wk = blockIdx.y;
+  const int n = s.npf, N = s.N, lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  double* G = w.W + (long)wk * n * n;
+  if (i >= N) {
+    for (int j = N + threadIdx.x; j < n; j += blockDim.x) G[(long)i * n + j] = 0.0;
+    return;
+  }
+  const bool up = i < s.nu;
+  const double* ph = (const double*)w.phi + ((long)wk * N + i) * s.Lp;
+  const double* B = (up ? (const double*)w.P : w.Bd) + (long)wk * N * s.Lp;
+  const double* U = s.Upf + (up ? 0L : (long)s.pk * s.Lp);
+  if (threadIdx.x == 0) G[(long)i * n + i] = 0.0;
+  for (int j = i + 1 + wave; j < n; j += nw) {
+    const double* row = j < N ? B + (long)j * s.Lp : U + (long)(j - N) * s.Lp;
+    double v = 0.0;
+    for (int mu = lane; mu < s.Lp; mu += 64) v += ph[mu] * row[mu];
+    v = wave_sum(v);
+    if (lane == 0) {
+      G[(long)i * n + j] = v;
+      G[(long)j * n + i] = -v;
+    }
+  }
+}
+
+hipError_t launch_pf_G_build(const SysDev& s, const WalkDev& w, hipStream_t st) {
+  if (s.npf > kPfMaxN) return hipErrorNotSupported;
+  hipLaunchKernelGGL(pf_G_kernel, dim3(s.npf, w.Wk), dim3(256), 0, st, s, w);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Pfaffian by Parlett-Reid with partial pivoting, one workgroup per walker on
+// the working copy X of G~: for k = 0, 2, ...  exchange row / column k+1 with
+// the one of the largest |X[k][j]|, j > k (lowest index on ties; a sign
+// change), multiply Pf by a = X[k][k+1], and with tau_j = X[k][j] / a update
+//   X[i][j] -= tau_i X[k+1][j] - tau_j X[k+1][i]     (i, j >= k+2),
+// a congruence by a unit lower triangular matrix, which leaves Pf unchanged.
+// Rows k and k+1 are not written by that update, so it reads them in place.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) pf_parlett_reid_kernel(SysDev s, WalkDev w) {
+  __shared__ double pv[4];
+  __shared__ int pj[4];
+  __shared__ int piv;
+  __shared__ double tau[kPfMaxN];
+  const int wk = blockIdx.x, n = s.npf, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nw = blockDim.x >> 6;
+  const double* G = w.W + (long)wk * n * n;
+  double* X = w.pfw + (long)wk * n * n;
+  for (int idx = tid; idx < n * n; idx += blockDim.x) X[idx] = G[idx];
+  __syncthreads();
+  double logabs = 0.0, sgn = 1.0;
+  bool zero = false;
+  for (int k = 0; k + 1 < n; k += 2) {
+    // pivot: argmax_j>k |X[k][j]| (block reduction, lowest index on ties)
+    double best = -1.0;
+    int bj = k + 1;
+    for (int j = k + 1 + tid; j < n; j += blockDim.x) {
+      const double v = fabs(X[(long)k * n + j]);
+      if (v > best) { best = v; bj = j; }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(best, o, 64);
+      const int oj = __shfl_xor(bj, o, 64);
+      if (ov > best || (ov == best && oj < bj)) { best = ov; bj = oj; }
+    }
+    if (lane == 0) { pv[wave] = best; pj[wave] = bj; }
+    __syncthreads();
+    if (tid == 0) {
+      double b = pv[0];
+      int j = pj[0];
+      for (int q = 1; q < nw; ++q)
+        if (pv[q] > b || (pv[q] == b && pj[q] < j)) { b = pv[q]; j = pj[q]; }
+      piv = j;
+    }
+    __syncthreads();
+    const int p = piv;
+    if (p != k + 1) {
+      // exchange rows k+1 and p, then columns k+1 and p
+      for (int c = tid; c < n; c += blockDim.x) {
+        const double a = X[(long)(k + 1) * n + c], b = X[(long)p * n + c];
+        X[(long)(k + 1) * n + c] = b;
+        X[(long)p * n + c] = a;
+      }
+      __syncthreads();
+      for (int r = tid; r < n; r += blockDim.x) {
+        const double a = X[(long)r * n + k + 1], b = X[(long)r * n + p];
+        X[(long)r * n + k + 1] = b;
+        X[(long)r * n + p] = a;
+      }
+      __syncthreads();
+      sgn = -sgn;
+    }
+    const double a = X[(long)k * n + k + 1];
+    if (a == 0.0) { zero = true; break; }   // uniform: every thread reads the same value
+    logabs += log(fabs(a));
+    if (a < 0.0) sgn = -sgn;
+    const int m = n - (k + 2);
+    if (m <= 0) break;
+    for (int j = tid; j < m; j += blockDim.x) tau[j] = X[(long)k * n + k + 2 + j] / a;
+    __syncthreads();
+    const double* r1 = X + (long)(k + 1) * n + k + 2;
+    for (int idx = tid; idx < m * m; idx += blockDim.x) {
+      const int ii = idx / m, jj = idx % m;
+      X[(long)(k + 2 + ii) * n + k + 2 + jj] += -tau[ii] * r1[jj] + tau[jj] * r1[ii];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (zero || (n & 1)) {
+      w.logdet[wk] = -__builtin_inf();
+      w.detsign[wk] = 0.0;
+      w.singular[wk] = 1;
+    } else {
+      w.logdet[wk] = logabs;
+      w.detsign[wk] = sgn;
+    }
+  }
+}
+
+hipError_t launch_pf_factor(const SysDev& s, const WalkDev& w, hipStream_t st) {
+  if (s.npf > kPfMaxN) return hipErrorNotSupported;
+  // G~^{-1} (and a singular flag) by Gauss-Jordan, then Pf overwrites log|det|, sign
+  hipError_t e = launch_gj_inverse_n(w.Wk, s.npf, w.W, w.A, w.logdet, w.detsign, w.singular, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(pf_parlett_reid_kernel, dim3(w.Wk), dim3(256), 0, st, s, w);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Cofactor vectors Y_i = sum_{j<N} (G~^{-1})_ji B^{s_i}_j + sum_l (G~^{-1})_{N+l,i} U^{s_i}_l
+// ---------------------------------------------------------------------------
+hipError_t launch_pf_Y_build(const SysDev& s, const WalkDev& w, hipStream_t st) {
+  const long rowst = (long)s.N * s.Lp, n = s.npf;
+  for (int sp = 0; sp < 2; ++sp) {
+    const int i0 = sp == 0 ? 0 : s.nu, ni = sp == 0 ? s.nu : s.nd;
+    if (ni == 0) continue;
+    GemmArgs g = gemm_args(ni, s.Lp, s.N);
+    g.A = w.A + i0; g.lda = n; g.a_bs = n * n;                  // stored [j][i]: op(A) = A^T
+    g.B = sp == 0 ? (const double*)w.P : w.Bd; g.ldb = s.Lp; g.b_bs = rowst;
+    g.C = w.Yt + (long)i0 * s.Lp; g.ldc = s.Lp; g.c_bs = rowst;
+    g.batch = w.Wk;
+    hipError_t e = gemm_f64(g, true, false, false, st);
+    if (e != hipSuccess) return e;
+    if (s.pk > 0) {
+      GemmArgs u = gemm_args(ni, s.Lp, s.pk);
+      u.A = w.A + (long)s.N * n + i0; u.lda = n; u.a_bs = n * n;
+      u.B = s.Upf + (long)sp * s.pk * s.Lp; u.ldb = s.Lp; u.b_bs = 0;
+      u.C = w.Yt + (long)i0 * s.Lp; u.ldc = s.Lp; u.c_bs = rowst;
+      u.batch = w.Wk;
+      u.accumulate = 1;
+      e = gemm_f64(u, true, false, false, st);
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// Proposal, one workgroup per walker: r', psi(r'), the Jastrow change, the new
+// row g' of G~ (into w_new) and the ratio sum_j g'_j (G~^{-1})_je.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+pf_propose_kernel(SysDev s, WalkDev w, int e, const double* __restrict__ r_new, const double* __restrict__ disp,
+                  double* __restrict__ ratio_o) {
+  __shared__ double red[8];
+  __shared__ double rn[3];
+  __shared__ double part[kPfMaxN];
+  const int wk = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  const int n = s.npf, N = s.N;
+  const double* r = w.r + (long)wk * N * 3;
+  if (tid < 3) {
+    rn[tid] = disp ? r[3 * e + tid] + disp[(long)wk * 3 + tid] : r_new[(long)wk * 3 + tid];
+    w.r_new[3 * wk + tid] = rn[tid];
+  }
+  __syncthreads();
+  const double px = rn[0], py = rn[1], pz = rn[2];
+  double* psi = w.psi_new + (long)wk * s.Lp;
+  for (int mu = tid; mu < s.Lp; mu += blockDim.x) psi[mu] = mu < s.L ? basis_value(s, mu, px, py, pz) : 0.0;
+  double jn, g0, g1, g2, jo, d0, d1, d2;
+  jastrow_one(s, r, e, px, py, pz, false, jn, g0, g1, g2);
+  jastrow_one(s, r, e, r[3 * e], r[3 * e + 1], r[3 * e + 2], false, jo, d0, d1, d2);
+  const double dJ = block_sum_mv(jn - jo, red);   // its barriers also publish psi
+  const bool up = e < s.nu;
+  const double* B = (up ? (const double*)w.P : w.Bd) + (long)wk * N * s.Lp;
+  const double* U = s.Upf + (up ? 0L : (long)s.pk * s.Lp);
+  const double* Ai = w.A + (long)wk * n * n;
+  double* wn = w.w_new + (long)wk * n;
+  for (int j = wave; j < n; j += nw) {
+    double v = 0.0;
+    if (j != e) {
+      const double* row = j < N ? B + (long)j * s.Lp : U + (long)(j - N) * s.Lp;
+      for (int mu = lane; mu < s.Lp; mu += 64) v += psi[mu] * row[mu];
+      v = wave_sum(v);
+    }
+    if (lane == 0) {
+      wn[j] = v;
+      part[j] = v * Ai[(long)j * n + e];
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double rd = 0.0;
+    for (int j = 0; j < n; ++j) rd += part[j];   // fixed order
+    const double ratio = rd * exp(dJ);
+    w.rdet[wk] = rd;
+    w.dJ[wk] = dJ;
+    w.ratio[wk] = ratio;
+    if (ratio_o) ratio_o[wk] = ratio;
+  }
+}
+
+hipError_t launch_pf_propose(const SysDev& s, const WalkDev& w, int e, const double* r_new, const double* disp,
+                             double* ratio, hipStream_t st) {
+  if (s.npf > kPfMaxN) return hipErrorNotSupported;
+  hipLaunchKernelGGL(pf_propose_kernel, dim3(w.Wk), dim3(256), 0, st, s, w, e, r_new, disp, ratio);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Accept (host decisions acc[wk], or the device Metropolis test unif[wk] <
+// ratio^2), one workgroup per walker: the rank-2 inverse update, row and
+// column e of G~, electron e's basis row, B rows and position, the tracked
+// log|Psi|, sign and Jastrow sum.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+pf_accept_kernel(SysDev s, WalkDev w, int e, const uint8_t* __restrict__ acc_in, const double* __restrict__ unif,
+                 int32_t* __restrict__ cnt) {
+  __shared__ double sp_[kPfMaxN], sq[kPfMaxN], sd[kPfMaxN];
+  __shared__ double psi_s[kFuseMaxLp];
+  const int wk = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  const int n = s.npf, N = s.N;
+  const double ratio = w.ratio[wk], rd = w.rdet[wk];
+  const bool acc = unif ? (unif[wk] < ratio * ratio) : (acc_in[wk] != 0);
+  if (tid == 0) w.acc[wk] = acc ? 1 : 0;
+  if (!acc) return;   // uniform over the block
+  double* G = w.W + (long)wk * n * n;
+  double* Ai = w.A + (long)wk * n * n;
+  const double* wn = w.w_new + (long)wk * n;
+  for (int j = tid; j < n; j += blockDim.x) {
+    sd[j] = wn[j] - G[(long)e * n + j];
+    sp_[j] = Ai[(long)j * n + e];
+  }
+  __syncthreads();
+  for (int i = wave; i < n; i += nw) {          // q = G^{-1} delta
+    double v = 0.0;
+    for (int j = lane; j < n; j += 64) v += Ai[(long)i * n + j] * sd[j];
+    v = wave_sum(v);
+    if (lane == 0) sq[i] = v;
+  }
+  __syncthreads();
+  const double ir = 1.0 / rd;
+  for (int idx = tid; idx < n * n; idx += blockDim.x) {
+    const int i = idx / n, j = idx % n;
+    Ai[idx] += (sp_[i] * sq[j] - sq[i] * sp_[j]) * ir;
+  }
+  for (int j = tid; j < n; j += blockDim.x) {
+    G[(long)e * n + j] = wn[j];
+    G[(long)j * n + e] = -wn[j];
+  }
+  // basis row and B rows of electron e: B^s_e = psi(r')^T K^{s s_e}
+  const double* pn = w.psi_new + (long)wk * s.Lp;
+  for (int mu = tid; mu < s.Lp; mu += blockDim.x) psi_s[mu] = pn[mu];
+  __syncthreads();
+  const bool up = e < s.nu;
+  const double* Ku = up ? s.Kuu : s.Kud;
+  const double* Kd = up ? s.Kdu : s.Kdd;
+  double* ph = (double*)w.phi + ((long)wk * N + e) * s.Lp;
+  double* bu = (double*)w.P + ((long)wk * N + e) * s.Lp;
+  double* bd = w.Bd + ((long)wk * N + e) * s.Lp;
+  for (int mu = tid; mu < s.Lp; mu += blockDim.x) {
+    double a = 0.0, b = 0.0;
+    for (int nu = 0; nu < s.L; ++nu) {
+      const double p = psi_s[nu];
+      a += p * Ku[(long)nu * s.Lp + mu];
+      b += p * Kd[(long)nu * s.Lp + mu];
+    }
+    ph[mu] = psi_s[mu];
+    bu[mu] = a;
+    bd[mu] = b;
+  }
+  if (tid == 0) {
+    double* re = w.r + ((long)wk * N + e) * 3;
+    re[0] = w.r_new[3 * wk]; re[1] = w.r_new[3 * wk + 1]; re[2] = w.r_new[3 * wk + 2];
+    const double dJ = w.dJ[wk];
+    w.logabs[wk] += log(fabs(rd)) + dJ;
+    if (rd < 0.0) w.sign[wk] = -w.sign[wk];
+    w.J[wk] += dJ;
+    if (cnt) cnt[wk] += 1;
+  }
+}
+
+hipError_t launch_pf_accept(const SysDev& s, const WalkDev& w, int e, const uint8_t* acc, const double* unif,
+                            int32_t* accept_count, hipStream_t st) {
+  if (s.npf > kPfMaxN || s.Lp > kFuseMaxLp) return hipErrorNotSupported;
+  hipLaunchKernelGGL(pf_accept_kernel, dim3(w.Wk), dim3(256), 0, st, s, w, e, acc, unif, accept_count);
+  return hipGetLastError();
+}
+
+}  // namespace qmc

@@ -161,8 +161,21 @@ extern "C" qmc_status qmc_system_create(const qmc_system_desc* desc, qmc_system*
   if (q.n_basis <= 0 || !q.center || !q.l || !q.m || !q.zeta || !q.lambda)
     return fail(QMC_ERR_ARG, "bad basis");
   if (q.n_up <= 0 || q.n_dn < 0) return fail(QMC_ERR_ARG, "bad electron counts");
-  if (q.n_up < q.n_dn) return fail(QMC_ERR_UNSUPPORTED, "n_up < n_dn: label the majority spin up");
-  if (q.n_up > q.n_dn && !q.unpaired) return fail(QMC_ERR_ARG, "n_up > n_dn needs the unpaired orbitals");
+  const bool pf = q.pairing == 1;
+  if (q.pairing != 0 && !pf) return fail(QMC_ERR_ARG, "pairing must be 0 or 1");
+  if (pf) {
+    if (q.precision != QMC_FP64) return fail(QMC_ERR_UNSUPPORTED, "the Pfaffian is built in FP64 only");
+    if (q.pf_k < 0) return fail(QMC_ERR_ARG, "pf_k must be >= 0");
+    if ((q.n_up + q.n_dn + q.pf_k) % 2) return fail(QMC_ERR_ARG, "N + pf_k must be even");
+    if (q.n_up + q.n_dn + q.pf_k > kLuRowMax) return fail(QMC_ERR_UNSUPPORTED, "Pfaffian of dimension > 96");
+    if (!q.pf_uu || !q.pf_dd) return fail(QMC_ERR_ARG, "Pfaffian same-spin blocks missing");
+    if (q.pf_k > 0 && (!q.unpaired || !q.pf_unpaired_dn)) return fail(QMC_ERR_ARG, "unpaired orbitals missing");
+    if (q.n_jbasis > 0) return fail(QMC_ERR_UNSUPPORTED, "Jastrow basis with the Pfaffian is not built");
+    if (q.n_contracted > 0) return fail(QMC_ERR_UNSUPPORTED, "contracted orbitals with the Pfaffian are not built");
+  } else {
+    if (q.n_up < q.n_dn) return fail(QMC_ERR_UNSUPPORTED, "n_up < n_dn: label the majority spin up");
+    if (q.n_up > q.n_dn && !q.unpaired) return fail(QMC_ERR_ARG, "n_up > n_dn needs the unpaired orbitals");
+  }
   if (q.n_up > kBigMaxN) return fail(QMC_ERR_UNSUPPORTED, "n_up > 1024 is not built");
   if (q.precision < QMC_FP64 || q.precision > QMC_MIXED_BF16)
     return fail(QMC_ERR_UNSUPPORTED, "precision not built");
@@ -205,7 +218,8 @@ extern "C" qmc_status qmc_system_create(const qmc_system_desc* desc, qmc_system*
   SysDev& d = s->d;
   if (hipGetDevice(&s->device) != hipSuccess) s->device = 0;
   d.n_nuc = q.n_nuc; d.L = L; d.Lp = round_up(L, 32);
-  d.nu = q.n_up; d.nd = q.n_dn; d.N = q.n_up + q.n_dn; d.nk = q.n_up - q.n_dn;
+  d.nu = q.n_up; d.nd = q.n_dn; d.N = q.n_up + q.n_dn; d.nk = pf ? 0 : q.n_up - q.n_dn;
+  d.pairing = pf ? 1 : 0; d.pk = pf ? q.pf_k : 0; d.npf = pf ? d.N + q.pf_k : 0;
   d.j1_form = q.j1_form; d.j2_form = q.j2_form;
   for (int k = 0; k < 8; ++k) d.j2[k] = (q.j2 && k < q.n_j2) ? q.j2[k] : 0.0;
   d.precision = q.precision; d.refresh_every = q.refresh_every;
@@ -310,6 +324,40 @@ extern "C" qmc_status qmc_system_create(const qmc_system_desc* desc, qmc_system*
     }
     e = up((void**)&d.bfn, bf.data(), sizeof(double) * bf.size());
   }
+  if (!e && pf) {
+    // K^{s s'} = (A^{s s'})^T, zero padded; unpaired rows per spin
+    const double* Auu = q.pf_uu;
+    const double* Add = q.pf_dd;
+    double mx = 0.0;
+    for (size_t k = 0; k < (size_t)L * L; ++k) mx = std::max(mx, std::max(std::fabs(Auu[k]), std::fabs(Add[k])));
+    for (int a = 0; a < L && !e; ++a)
+      for (int b = 0; b < L; ++b)
+        if (std::fabs(Auu[(size_t)a * L + b] + Auu[(size_t)b * L + a]) > 1e-12 * mx ||
+            std::fabs(Add[(size_t)a * L + b] + Add[(size_t)b * L + a]) > 1e-12 * mx) {
+          delete s;
+          return fail(QMC_ERR_ARG, "Pfaffian same-spin blocks must be skew-symmetric");
+        }
+    std::vector<double> kuu((size_t)Lp * Lp, 0.0), kud(kuu), kdu(kuu), kdd(kuu);
+    for (int a = 0; a < L; ++a)
+      for (int b = 0; b < L; ++b) {
+        kuu[(size_t)b * Lp + a] = Auu[(size_t)a * L + b];
+        kdd[(size_t)b * Lp + a] = Add[(size_t)a * L + b];
+        kud[(size_t)b * Lp + a] = q.lambda[(size_t)a * L + b];
+        kdu[(size_t)a * Lp + b] = -q.lambda[(size_t)a * L + b];
+      }
+    e = up((void**)&d.Kuu, kuu.data(), sizeof(double) * kuu.size());
+    if (!e) e = up((void**)&d.Kud, kud.data(), sizeof(double) * kud.size());
+    if (!e) e = up((void**)&d.Kdu, kdu.data(), sizeof(double) * kdu.size());
+    if (!e) e = up((void**)&d.Kdd, kdd.data(), sizeof(double) * kdd.size());
+    const int k = q.pf_k;
+    std::vector<double> upf(2 * (size_t)(k > 0 ? k : 1) * Lp, 0.0);
+    for (int l = 0; l < k; ++l)
+      for (int mu = 0; mu < L; ++mu) {
+        upf[(size_t)l * Lp + mu] = q.unpaired[(size_t)mu * k + l];
+        upf[((size_t)k + l) * Lp + mu] = q.pf_unpaired_dn[(size_t)mu * k + l];
+      }
+    if (!e) e = up((void**)&d.Upf, upf.data(), sizeof(double) * upf.size());
+  }
   if (!e && d.nk > 0) {
     // unpaired orbital l as a fixed row: Uph[l][mu] = unpaired[mu][l]
     std::vector<double> uph((size_t)d.nk * Lp, 0.0);
@@ -389,8 +437,9 @@ extern "C" qmc_status qmc_walkers_create(qmc_system* sys, int32_t n_walkers, qmc
   al((void**)&d.r, sizeof(double) * Wk * N * 3);
   al(&d.phi, esz * Wk * N * Lp);
   al(&d.P, esz * Wk * N * Lp);
-  al((void**)&d.W, sizeof(double) * Wk * s.nu * s.nu);
-  al((void**)&d.A, sizeof(double) * Wk * s.nu * s.nu);
+  const size_t nsq = s.pairing ? (size_t)s.npf * s.npf : (size_t)s.nu * s.nu;   // G~ or W
+  al((void**)&d.W, sizeof(double) * Wk * nsq);
+  al((void**)&d.A, sizeof(double) * Wk * nsq);
   al((void**)&d.Yt, sizeof(double) * Wk * N * Lp);
   al((void**)&d.D, sizeof(double) * Wk * N * 4);
   al((void**)&d.logdet, sizeof(double) * Wk);
@@ -400,7 +449,7 @@ extern "C" qmc_status qmc_walkers_create(qmc_system* sys, int32_t n_walkers, qmc
   al((void**)&d.sign, sizeof(double) * Wk);
   al((void**)&d.J, sizeof(double) * Wk);
   al((void**)&d.psi_new, sizeof(double) * Wk * Lp);
-  al((void**)&d.w_new, sizeof(double) * Wk * nmax);
+  al((void**)&d.w_new, sizeof(double) * Wk * (s.pairing ? std::max(nmax, (size_t)s.npf) : nmax));
   al((void**)&d.rdet, sizeof(double) * Wk);
   al((void**)&d.dJ, sizeof(double) * Wk);
   al((void**)&d.r_new, sizeof(double) * Wk * 3);
@@ -446,6 +495,10 @@ extern "C" qmc_status qmc_walkers_create(qmc_system* sys, int32_t n_walkers, qmc
     al((void**)&d.j3e, sizeof(double) * Wk * N * 5);
   }
   if (s.Lq > 0) al((void**)&d.qbuf, sizeof(double) * Wk * 4 * s.Lq);
+  if (s.pairing) {
+    al((void**)&d.Bd, sizeof(double) * Wk * N * Lp);
+    al((void**)&d.pfw, sizeof(double) * Wk * s.npf * s.npf);
+  }
   al((void**)&wk->lr.ratio, sizeof(double) * Wk * N * kHops);
   al((void**)&wk->lr.ah, sizeof(double) * Wk * N);
   al((void**)&wk->lr.terms, sizeof(double) * Wk * kLrTerms);
@@ -492,10 +545,17 @@ extern "C" qmc_status qmc_eval_batch(qmc_system* sys, qmc_walkers* wk, const dou
     de.P = d.P64;
   }
   TIMED(wk, QMC_T_BASIS, stream, launch_basis_values(se, de, stream), "basis");
+  if (s.pairing) {
+    TIMED(wk, QMC_T_P_BUILD, stream, launch_pf_B_build(s, d, stream), "Pfaffian B rows");
+    TIMED(wk, QMC_T_W_BUILD, stream, launch_pf_G_build(s, d, stream), "Pfaffian G");
+    TIMED(wk, QMC_T_LU, stream, launch_pf_factor(s, d, stream), "Pfaffian and inverse");
+    TIMED(wk, QMC_T_Y_BUILD, stream, launch_pf_Y_build(s, d, stream), "Pfaffian Y build");
+  } else {
   TIMED(wk, QMC_T_P_BUILD, stream, launch_P_build(se, de, 3, stream), "P build");
   TIMED(wk, QMC_T_W_BUILD, stream, launch_W_build(se, de, stream), "W build");
   TIMED(wk, QMC_T_LU, stream, launch_lu_inverse(se, de, stream), "LU");
   TIMED(wk, QMC_T_Y_BUILD, stream, launch_Y_build(se, de, stream), "Y build");
+  }
   if (refine) {
     const long cnt = (long)d.Wk * s.N * s.Lp;
     TIMED(wk, QMC_T_OTHER, stream, launch_downcast(d.phi64, d.phi, s.bf16(), cnt, stream), "phi copy");
@@ -549,6 +609,14 @@ extern "C" qmc_status qmc_propose_move(qmc_system* sys, qmc_walkers* wk, int32_t
   if (electron < 0 || electron >= s.N) return fail(QMC_ERR_ARG, "electron index out of range");
   if (!r_new) return fail(QMC_ERR_ARG, "null r_new");
   // (a pending proposal is simply replaced)
+  if (s.pairing) {
+    if (drift_new) return fail(QMC_ERR_UNSUPPORTED, "drifts of Pfaffian proposals are not built");
+    wk->yt_valid = wk->lr_ready = false;
+    TIMED(wk, QMC_T_PROPOSE, stream, launch_pf_propose(s, wk->d, electron, r_new, nullptr, ratio, stream),
+          "Pfaffian proposal");
+    wk->pending_e = electron;
+    return QMC_OK;
+  }
   c = before_propose(wk, electron, stream);
   if (c) return c;
   c = ensure_P(wk, electron, stream);
@@ -613,6 +681,20 @@ static qmc_status after_accept(qmc_walkers* wk, int e, int32_t* status, hipStrea
   return QMC_OK;
 }
 
+// Pfaffian moves: the rank-2 updates of G~^{-1} are exact in exact arithmetic;
+// the inverse, log|Psi| and the sign are recomputed from the maintained G~
+// every refresh_every moves.
+static qmc_status pf_after_accept(qmc_walkers* wk, int32_t* status, hipStream_t stream) {
+  const SysDev& s = wk->sys->d;
+  wk->pending_e = -1;
+  wk->attempts += 1;
+  if (++wk->since < s.refresh_every) return QMC_OK;
+  wk->since = 0;
+  TIMED(wk, QMC_T_LU, stream, launch_pf_factor(s, wk->d, stream), "Pfaffian refresh");
+  TIMED(wk, QMC_T_OTHER, stream, launch_refresh_finish(s, wk->d, status, stream), "refresh finish");
+  return QMC_OK;
+}
+
 extern "C" qmc_status qmc_accept_move(qmc_system* sys, qmc_walkers* wk, int32_t electron,
                                       const uint8_t* accept, int32_t* status, hipStream_t stream) {
   qmc_status c = check_pair(sys, wk);
@@ -620,6 +702,11 @@ extern "C" qmc_status qmc_accept_move(qmc_system* sys, qmc_walkers* wk, int32_t 
   if (!accept) return fail(QMC_ERR_ARG, "null accept");
   if (wk->pending_e < 0 || wk->pending_e != electron)
     return fail(QMC_ERR_STATE, "no pending proposal for this electron");
+  if (sys->d.pairing) {
+    TIMED(wk, QMC_T_ACCEPT, stream, launch_pf_accept(sys->d, wk->d, electron, accept, nullptr, nullptr, stream),
+          "Pfaffian accept");
+    return pf_after_accept(wk, status, stream);
+  }
   TIMED(wk, QMC_T_ACCEPT, stream, launch_accept(sys->d, wk->d, electron, accept, stream), "accept");
   return after_accept(wk, electron, status, stream);
 }
@@ -648,6 +735,21 @@ extern "C" qmc_status qmc_vmc_steps(qmc_system* sys, qmc_walkers* wk, int32_t e_
   if (wk->generation != sys->generation) return fail(QMC_ERR_STATE, "parameters changed since the last eval_batch");
   if (!disp || !unif) return fail(QMC_ERR_ARG, "null random arrays");
   if (n_steps < 0 || e_start < 0) return fail(QMC_ERR_ARG, "negative step count or electron");
+  if (s.pairing) {
+    wk->yt_valid = wk->lr_ready = false;
+    for (int t = 0; t < n_steps; ++t) {
+      const int e = (int)((e_start + (long)t) % s.N);
+      TIMED(wk, QMC_T_PROPOSE, stream,
+            launch_pf_propose(s, wk->d, e, nullptr, disp + (long)t * wk->d.Wk * 3, nullptr, stream),
+            "Pfaffian proposal");
+      TIMED(wk, QMC_T_ACCEPT, stream,
+            launch_pf_accept(s, wk->d, e, nullptr, unif + (long)t * wk->d.Wk, accept_count, stream),
+            "Pfaffian Metropolis");
+      c = pf_after_accept(wk, nullptr, stream);
+      if (c) return c;
+    }
+    return QMC_OK;
+  }
   const long Wk = wk->d.Wk;
   bool prepped = false;   // the set-up of step t ran in step t-1's fused accept
   for (int t = 0; t < n_steps; ++t) {
@@ -698,8 +800,12 @@ extern "C" qmc_status qmc_walkers_read(qmc_walkers* wk, int32_t item, double* ds
     case QMC_STATE_R: src = d.r; bytes = sizeof(double) * Wk * s.N * 3; break;
     case QMC_STATE_LOGABS: src = d.logabs; bytes = sizeof(double) * Wk; break;
     case QMC_STATE_SIGN: src = d.sign; bytes = sizeof(double) * Wk; break;
-    case QMC_STATE_W: src = d.W; bytes = sizeof(double) * Wk * s.nu * s.nu; break;
+    case QMC_STATE_W:
+      src = d.W;
+      bytes = sizeof(double) * Wk * (s.pairing ? (size_t)s.npf * s.npf : (size_t)s.nu * s.nu);
+      break;
     case QMC_STATE_AINV:   // A0 combined with the delayed updates
+      if (s.pairing) { src = d.A; bytes = sizeof(double) * Wk * s.npf * s.npf; break; }
       HIP_TRY(launch_materialize_inverse(s, d, wk->buf_spin == 1, wk->rd_scratch, dst, stream), "read inverse");
       return QMC_OK;
     case QMC_STATE_PHI:
@@ -780,6 +886,7 @@ extern "C" qmc_status qmc_forces(qmc_system* sys, qmc_walkers* wk, const double*
   if (s.LJ > 0) return fail(QMC_ERR_UNSUPPORTED, "forces with a Jastrow basis are not built");
   if (s.Lq > 0) return fail(QMC_ERR_UNSUPPORTED, "forces with contracted orbitals are not built");
   if (s.nk > 0) return fail(QMC_ERR_UNSUPPORTED, "forces with unpaired orbitals are not built");
+  if (s.pairing) return fail(QMC_ERR_UNSUPPORTED, "forces of the Pfaffian are not built");
   if (s.N > 2 * kLuMaxN || s.n_nuc > kMaxNucBack)
     return fail(QMC_ERR_UNSUPPORTED, "forces need N <= 256 electrons and <= 256 nuclei");
   hipError_t e = alloc_adjoint(wk);
@@ -859,6 +966,7 @@ extern "C" qmc_status qmc_reweight(qmc_system* sys, qmc_walkers* wk, double thet
   if (!(theta > 0.0) || !(eps >= 0.0)) return fail(QMC_ERR_ARG, "theta > 0 and eps >= 0 required");
   if (!wk->evaluated || !wk->yt_valid)
     return fail(QMC_ERR_STATE, "the reweighting factor needs an evaluation since the last move");
+  if (sys->d.pairing) return fail(QMC_ERR_UNSUPPORTED, "the reweighting factor of the Pfaffian is not built");
   HIP_TRY(launch_reweight(sys->d, wk->d, theta, eps, R, weight, stream), "reweight");
   return QMC_OK;
 }
@@ -886,6 +994,7 @@ extern "C" qmc_status qmc_system_set_params(qmc_system* sys, const double* R, co
   if (!sys) return fail(QMC_ERR_ARG, "null system");
   SysDev& d = sys->d;
   if (R && d.LJ > 0) return fail(QMC_ERR_UNSUPPORTED, "moving nuclei with a Jastrow basis is not built");
+  if (d.pairing) return fail(QMC_ERR_UNSUPPORTED, "parameter changes of the Pfaffian are not built");
   if ((R || zeta) && d.Lq > 0)
     return fail(QMC_ERR_UNSUPPORTED, "changing primitives of a contracted basis is not built");
   if (R) HIP_TRY(hipMemcpyAsync(d.R, R, sizeof(double) * 3 * d.n_nuc, hipMemcpyDeviceToDevice, stream), "set R");
@@ -983,6 +1092,7 @@ extern "C" qmc_status qmc_multi_create(int32_t n_members, qmc_system* const* sys
     if (s.nu != s.nd || s.nu > kLuMaxN) { delete m; return fail(QMC_ERR_UNSUPPORTED, "members need n_up == n_dn <= 128"); }
     if (s.LJ > 0) { delete m; return fail(QMC_ERR_UNSUPPORTED, "members with a Jastrow basis are not built"); }
     if (s.Lq > 0) { delete m; return fail(QMC_ERR_UNSUPPORTED, "members with contracted orbitals are not built"); }
+    if (s.pairing) { delete m; return fail(QMC_ERR_UNSUPPORTED, "Pfaffian members are not built"); }
     m->sys.push_back(systems[k]);
     m->wk.push_back(walkers[k]);
     m->h_sys.push_back(s);

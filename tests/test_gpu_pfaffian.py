@@ -1,0 +1,179 @@
+"""Pfaffian wave function (Pfaffian wave function section) on the GPU path
+against the oracle, at the FP64 bars of the determinant path: relative 1e-10
+on log|Psi|, E_kin, E_loc and move ratios, 1e-8 on drifts; signs equal; chains
+bitwise; the maintained inverse within 1e-9 of the oracle's after a chain.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import need_gpu, rel_err
+from oracle import jagp as O
+from oracle import lrdmc as L
+from oracle import pfaffian as PF
+from workloads import configs as C
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fw():
+    return C.pfaffian_4nuc_20e()
+
+
+def _balanced(s):
+    L_ = len(s.lam)
+    return dataclasses.replace(s, n_up=10, n_dn=10, unpaired=np.zeros((L_, 0)), unpaired_dn=np.zeros((L_, 0)))
+
+
+def _eval(P, s, r0, Wk):
+    sysh = P.JAGPSystem(s)
+    wk = P.Walkers(sysh, Wk)
+    r = torch.tensor(r0[:Wk], device="cuda")
+    out = wk.eval_batch(r)
+    torch.cuda.synchronize()
+    return sysh, wk, r.cpu(), out
+
+
+def _check_eval(out, ref, label):
+    e = {k: rel_err(out[k].cpu(), ref[k]).max().item() for k in ("logabs", "e_kin", "e_loc")}
+    d = out["drift"].cpu()
+    e_dr = ((d - ref["drift"]).abs() / ref["drift"].abs().clamp(min=1.0)).max().item()
+    print(f"[pfaffian eval {label}] {e} drift {e_dr:.3e}")
+    assert max(e.values()) <= 1e-10 and e_dr <= 1e-8
+    assert torch.equal(out["sign"].cpu(), ref["sign"])
+    assert int(out["status"].abs().max()) == 0
+
+
+@pytest.mark.parametrize("case", ["unpaired_k2", "balanced"])
+def test_pfaffian_eval_matches_oracle(fw, case):
+    P = need_gpu()
+    s = fw.system if case == "unpaired_k2" else _balanced(fw.system)
+    r0 = fw.r0 if case == "unpaired_k2" else C.random_positions(41, s, 32)
+    _, wk, r, out = _eval(P, s, r0, 32)
+    sy = O.from_workload_system(s)
+    _check_eval(out, O.evaluate(sy, r), case)
+    G = wk.read(P.STATE_W).cpu()
+    Gref = PF.pairing_matrix(sy, O.agp_basis(sy, r)[0])
+    assert G.shape == Gref.shape
+    assert torch.equal(G, -G.transpose(1, 2))
+    assert ((G - Gref).abs().max() / Gref.abs().max()).item() <= 1e-13
+
+
+def test_singlet_pfaffian_equals_determinant_path():
+    # A^{uu} = A^{dd} = 0: Pf(G~) = (-1)^(n(n-1)/2) det W (the AGP special case)
+    P = need_gpu()
+    for w in (C.tiny_3nuc_10e(n_walkers=16), C.polarized_4nuc_20e(n_walkers=16)):
+        s = w.system
+        L_ = len(s.lam)
+        k = s.n_up - s.n_dn
+        sp = dataclasses.replace(s, pairing=1, pf_uu=np.zeros((L_, L_)), pf_dd=np.zeros((L_, L_)),
+                                 unpaired=np.asarray(s.unpaired).reshape(L_, k), unpaired_dn=np.zeros((L_, k)))
+        a = _eval(P, s, w.r0, 16)[3]
+        b = _eval(P, sp, w.r0, 16)[3]
+        n = s.n_up
+        for key in ("logabs", "e_kin", "e_loc", "drift"):
+            err = rel_err(b[key].cpu(), a[key].cpu()).max().item()
+            assert err <= 1e-10, (s.name, key, err)
+        assert torch.equal(b["sign"].cpu(), a["sign"].cpu() * (-1) ** (n * (n - 1) // 2))
+
+
+def test_pfaffian_propose_ratio(fw):
+    P = need_gpu()
+    _, wk, r, _ = _eval(P, fw.system, fw.r0, 32)
+    sy = O.from_workload_system(fw.system)
+    for e in (0, 10, 11, 19):
+        rn = r[:, e] + torch.tensor(fw.disp[e])
+        ratio = wk.propose(e, rn.cuda().contiguous())
+        torch.cuda.synchronize()
+        err = rel_err(ratio.cpu(), O.move_ratio(sy, r, e, rn)).max().item()
+        print(f"[pfaffian ratio e={e}] {err:.3e}")
+        assert err <= 1e-10
+
+
+def test_pfaffian_chain_matches_oracle(fw):
+    P = need_gpu()
+    Wk, T = 16, 100
+    _, wk, r, _ = _eval(P, fw.system, fw.r0, Wk)
+    disp = torch.tensor(fw.disp[:T, :Wk]).contiguous()
+    unif = torch.tensor(fw.unif[:T, :Wk]).contiguous()
+    cnt = torch.zeros(Wk, dtype=torch.int32, device="cuda")
+    wk.vmc_steps(0, disp.cuda(), unif.cuda(), cnt)
+    rg = wk.read(P.STATE_R).cpu()
+    la = wk.read(P.STATE_LOGABS).cpu()
+    sg = wk.read(P.STATE_SIGN).cpu()
+    Ai = wk.read(P.STATE_AINV).cpu()
+    torch.cuda.synchronize()
+    sy = O.from_workload_system(fw.system)
+    rf, _, accs = O.run_chain(sy, r, disp, unif)
+    print(f"[pfaffian chain] acceptance {accs.double().mean().item():.3f}")
+    assert torch.equal(rg, rf)
+    assert torch.equal(cnt.cpu(), accs.sum(0).to(torch.int32))
+    ref = O.evaluate(sy, rf)
+    assert rel_err(la, ref["logabs"]).max().item() <= 1e-10
+    assert torch.equal(sg, ref["sign"])
+    Gref = PF.pairing_matrix(sy, O.agp_basis(sy, rf)[0])
+    Aref = torch.linalg.inv(Gref)
+    assert ((Ai - Aref).abs().max() / Aref.abs().max()).item() <= 1e-9
+
+
+def test_pfaffian_host_decisions_and_refresh(fw):
+    # propose / accept with host decisions across a refresh (refresh_every = 32)
+    P = need_gpu()
+    Wk = 8
+    _, wk, r, _ = _eval(P, fw.system, fw.r0, Wk)
+    sy = O.from_workload_system(fw.system)
+    rc = r.clone()
+    for t in range(40):
+        e = (3 * t) % 20
+        rn = rc[:, e] + torch.tensor(fw.disp[t, :Wk])
+        ratio = wk.propose(e, rn.cuda().contiguous())
+        acc = (torch.arange(Wk) + t) % 3 != 0
+        wk.accept(e, acc.to(torch.uint8).cuda())
+        torch.cuda.synchronize()
+        if t in (0, 39):
+            assert rel_err(ratio.cpu(), O.move_ratio(sy, rc, e, rn)).max().item() <= 1e-10
+        rc[acc, e] = rn[acc]
+    assert torch.equal(wk.read(P.STATE_R).cpu(), rc)
+    la = wk.read(P.STATE_LOGABS).cpu()
+    assert rel_err(la, O.evaluate(sy, rc)["logabs"]).max().item() <= 1e-10
+
+
+def test_pfaffian_lattice_hops(fw):
+    P = need_gpu()
+    _, wk, r, _ = _eval(P, fw.system, fw.r0, 8)
+    prm = C.LRDMC_DOUBLE
+    g = wk.lrdmc_hops(**prm)
+    torch.cuda.synchronize()
+    sy = O.from_workload_system(fw.system)
+    a_i = L.mesh(sy, r, prm["a"], prm["a_valence"], prm["tf_scale"])
+    assert rel_err(g["ratios"].cpu(), L.lattice_ratios(sy, r, a_i)).max().item() <= 1e-10
+
+
+def test_pfaffian_refusals(fw):
+    P = need_gpu()
+    sysh, wk, r, _ = _eval(P, fw.system, fw.r0, 4)
+    one = torch.ones(4, dtype=torch.float64, device="cuda")
+    with pytest.raises(P.QMCError) as ex:
+        wk.forces(r.cuda(), one, None)
+    assert ex.value.code == -5
+    with pytest.raises(P.QMCError) as ex:
+        P.reweight(wk, 0.375, 0.0)
+    assert ex.value.code == -5
+    with pytest.raises(P.QMCError) as ex:
+        wk.propose(0, r[:, 0].cuda().contiguous(), drift=True)
+    assert ex.value.code == -5
+    s = fw.system
+    with pytest.raises(P.QMCError) as ex:   # N + k odd
+        P.JAGPSystem(dataclasses.replace(s, n_dn=8))
+    assert ex.value.code == -1
+    with pytest.raises(P.QMCError) as ex:
+        P.JAGPSystem(s, precision=P.QMC_MIXED)
+    assert ex.value.code == -5
+    bad = s.pf_uu.copy()
+    bad[0, 1] += 1.0
+    with pytest.raises(P.QMCError) as ex:
+        P.JAGPSystem(dataclasses.replace(s, pf_uu=bad))
+    assert ex.value.code == -1
