@@ -445,6 +445,92 @@ def large_leg(P, C, steps=128, Wk=256):
             "kernel_launches": {k: v[1] for k, v in tim.items() if v[1]}}
 
 
+def pfaffian_leg(P, C, steps=160, Wk=512):
+    """The 80-electron Pfaffian (G~ 80 x 80, triplet blocks, L = 300), 512
+    walkers, FP64: one evaluation and `steps` Metropolis moves (refresh every
+    32 moves); error of the evaluation against the oracle on one walker."""
+    from oracle import jagp as O
+    dev = torch.device("cuda:0")
+    w = C.pfaffian_20nuc_80e(n_walkers=Wk)
+    sysh = P.JAGPSystem(w.system)
+    wk = P.Walkers(sysh, Wk)
+    r = torch.tensor(w.r0, device=dev)
+    d, u = C.chain_arrays(43, steps, Wk)
+    d, u = torch.tensor(d, device=dev), torch.tensor(u, device=dev)
+    cnt = torch.zeros(Wk, dtype=torch.int32, device=dev)
+    wk.eval_batch(r)
+    wk.vmc_steps(0, d[:8].contiguous(), u[:8].contiguous())   # warm-up
+    torch.cuda.synchronize()
+    wk.set_timing(True)
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    e0.record()
+    out = wk.eval_batch(r, drift=True)
+    e1.record()
+    wk.vmc_steps(0, d, u, cnt)
+    e2.record()
+    torch.cuda.synchronize()
+    tim = wk.timing()
+    wk.set_timing(False)
+    t_eval, t_move = e0.elapsed_time(e1) / 1e3, e1.elapsed_time(e2) / 1e3
+    ref = O.evaluate(O.from_workload_system(w.system), torch.tensor(w.r0[:1]))
+    err = {k: float(f"{float(((out[k].cpu()[:1] - ref[k]).abs() / ref[k].abs().clamp(min=1.0)).max()):.3e}")
+           for k in ("logabs", "e_loc")}
+    s = w.system
+    n, Lp = s.n_up + s.n_dn, (len(s.lam) + 31) // 32 * 32
+    prop = tim["propose"]
+    # algorithmic bytes of one proposal launch: the n B rows and the inverse column of every walker
+    prop_bytes = Wk * (n * Lp * 8 + n * 8)
+    prop_us = 1e3 * prop[0] / max(prop[1], 1)
+    wk.close()
+    sysh.close()
+    return {"workload": "pfaffian_20nuc_80e", "walkers": Wk, "precision": "fp64", "pfaffian_dim": n,
+            "eloc_evals_per_s": round(Wk / t_eval, 1), "moves_per_s": round(steps * Wk / t_move, 1),
+            "acceptance": round(cnt.sum().item() / (steps * Wk), 4), "moves": steps,
+            "propose_avg_us": round(prop_us, 2),
+            "propose_GBps": round(prop_bytes / (prop_us * 1e-6) / 1e9, 1),
+            "err_vs_oracle": {"walkers": [0], **err},
+            "kernel_ms": {k: round(v[0], 3) for k, v in tim.items() if v[1]},
+            "kernel_launches": {k: v[1] for k, v in tim.items() if v[1]}}
+
+
+def sr_leg(P, M=4096, Pn=8192, iters=40, eps=1e-3):
+    """Stochastic-reconfiguration step on the device: M samples x Pn
+    parameters of synthetic logarithmic derivatives (correlated Gaussian
+    columns with scales spread over two decades), `iters` conjugate-gradient
+    iterations (tol 0: all run).  Each iteration streams O twice
+    (16 M Pn bytes); the residual |S'delta - f| / |f| is checked with torch
+    products on the device."""
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev).manual_seed(7)
+    base = torch.randn(M, Pn // 16, generator=g, device=dev, dtype=torch.float64)
+    Ok = torch.randn(M, Pn, generator=g, device=dev, dtype=torch.float64)
+    Ok += base.repeat(1, 16)
+    Ok *= torch.logspace(-1, 1, Pn, device=dev, dtype=torch.float64)
+    el = -5.0 + torch.randn(M, generator=g, device=dev, dtype=torch.float64) + 0.5 * Ok[:, 0]
+    work = torch.empty((P.load().qmc_sr_workspace_size(M, Pn) + 7) // 8, dtype=torch.float64, device=dev)
+    P.sr_step(Ok, el, eps, None, max_iter=2, tol=0.0, work=work)   # warm-up
+    torch.cuda.synchronize()
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    e0.record()
+    P.sr_step(Ok, el, eps, None, max_iter=0, tol=0.0, work=work)
+    e1.record()
+    delta, f, res = P.sr_step(Ok, el, eps, None, max_iter=iters, tol=0.0, work=work)
+    e2.record()
+    torch.cuda.synchronize()
+    t0, t1 = e0.elapsed_time(e1) / 1e3, e1.elapsed_time(e2) / 1e3
+    t_iter = (t1 - t0) / iters
+    Ob = Ok.mean(0)
+    Sd = (Ok @ delta) / M
+    Sp = Ok.t() @ Sd - Ob * (Ob @ delta) + eps * ((Ok - Ob) ** 2).mean(0) * delta
+    chk = float((Sp - f).norm() / f.norm())
+    bytes_iter = 16.0 * M * Pn
+    return {"samples": M, "params": Pn, "eps": eps, "iterations": iters, "precision": "fp64",
+            "moments_ms": round(1e3 * t0, 3), "ms_per_iteration": round(1e3 * t_iter, 4),
+            "iteration_GBps": round(bytes_iter / t_iter / 1e9, 1),
+            "iteration_frac_of_hbm_peak": round(bytes_iter / t_iter / 8e12, 3),
+            "residual": float(f"{res.item():.3e}"), "residual_check": float(f"{chk:.3e}")}
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -496,6 +582,8 @@ def main():
         res["multi_system"] = multi_leg(P, C)
         res["large"] = large_leg(P, C)
         res["lrdmc"] = lrdmc_leg(P, C)
+        res["pfaffian"] = pfaffian_leg(P, C)
+        res["sr"] = sr_leg(P)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(res), flush=True)

@@ -9,9 +9,9 @@
 // * Stochastic reconfiguration: (S + eps diag S) delta = f with
 //   S v = O^T (w o (O v)) / sum w - Obar (Obar . v), f = -2 sum_i w_i e_i (O_i - Obar) / sum w,
 //   solved by diagonally preconditioned conjugate gradients on the device
-//   without forming S: per iteration u = O p (and Obar . p), S' p with partial
-//   sums of p . S'p, the x / r update with partial sums of r . z and r . r,
-//   the p update.  Every reduction is a fixed-order sum
+//   without forming S: per iteration u = O p (and Obar . p), O^T (w o u) by
+//   column slices, S' p with partial sums of p . S'p, the x / r update with
+//   partial sums of r . z and r . r, the p update.  Every reduction is a fixed-order sum
 //   of per-block partials; the iteration scalars are double-buffered by parity
 //   so no block reads a value another block of the same launch writes.
 #include "internal.h"
@@ -117,16 +117,24 @@ hipError_t launch_reweight(const SysDev& s, const WalkDev& w, double theta, doub
 // 1 where s_kk = 0): the regularisation is relative to the diagonal, so the
 // diagonally scaled matrix has unit diagonal and a condition number bounded by
 // about (P + eps) / eps whatever the scales of the parameters.
+// The column sums over samples (moments, O^T (w o u)) run on a 2-D grid:
+// blocks of 256 columns times `ms` slices of the samples, each slice writing
+// its partial sums, which a second kernel adds in slice order.
 // Workspace (doubles): Obar, d (= diag S), f, r, p, Sp [P each], u [M],
-// part1, part2, part3 [nblk each], scalars [16]:
+// part1, part2, part3 [nblk each], colpart [2][ms][P], scalars [16]:
 //   sc[0] = sum w, sc[1] = f . f, sc[2 + (it & 1)] = r . z at iteration it,
 //   sc[4] = Obar . p, sc[5] = done, sc[6] = r . r of the last update
 struct SrWork {
-  double *Obar, *d, *f, *r, *p, *Sp, *u, *part1, *part2, *part3, *sc;
+  double *Obar, *d, *f, *r, *p, *Sp, *u, *part1, *part2, *part3, *colpart, *sc;
   long P;
-  int M, nblk;
+  int M, nblk, ms, rows;   // rows: samples per slice
   double eps;
 };
+
+static int sr_slices(int M) {
+  const int ms = (M + 127) / 128;   // about 128 samples per slice, at most 64 slices
+  return ms < 1 ? 1 : (ms > 64 ? 64 : ms);
+}
 
 __device__ inline double sr_precond(const SrWork& q, long k) {
   const double m = (1.0 + q.eps) * q.d[k];
@@ -154,26 +162,56 @@ __global__ void __launch_bounds__(256) sr_wsum_kernel(SrWork q, const double* __
   if (threadIdx.x == 0) q.sc[0] = t;
 }
 
-// Obar, diag S and f; x = 0, r = f, p = z = f / m; partial sums of r . z and r . r
+// Column sums over one slice of samples: pass 0: sum w O; pass 1: sum w (O - Obar)^2
+// and sum w e (O - Obar); pass 2: sum w u O (u = O p).
 __global__ void __launch_bounds__(256)
-sr_moments_kernel(SrWork q, const double* __restrict__ O, const double* __restrict__ el,
-                  const double* __restrict__ wts, double* __restrict__ x) {
+sr_colsum_kernel(SrWork q, const double* __restrict__ O, const double* __restrict__ el,
+                 const double* __restrict__ wts, int pass) {
+  if (pass == 2 && q.sc[5] != 0.0) return;   // converged (uniform)
+  const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int sl = blockIdx.y;
+  if (k >= q.P) return;
+  const int i0 = sl * q.rows, i1 = min(i0 + q.rows, q.M);
+  double a = 0.0, b = 0.0;
+  if (pass == 0) {
+    for (int i = i0; i < i1; ++i) a += (wts ? wts[i] : 1.0) * O[(long)i * q.P + k];
+  } else if (pass == 1) {
+    const double m = q.Obar[k];
+    for (int i = i0; i < i1; ++i) {
+      const double wi = wts ? wts[i] : 1.0, c = O[(long)i * q.P + k] - m;
+      a += wi * c * c;
+      b += wi * el[i] * c;
+    }
+  } else {
+    for (int i = i0; i < i1; ++i) a += (wts ? wts[i] : 1.0) * q.u[i] * O[(long)i * q.P + k];
+  }
+  q.colpart[(long)sl * q.P + k] = a;
+  if (pass == 1) q.colpart[((long)q.ms + sl) * q.P + k] = b;
+}
+
+// Obar = (sum over slices) / sum w
+__global__ void __launch_bounds__(256) sr_mean_kernel(SrWork q) {
+  const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= q.P) return;
+  double a = 0.0;
+  for (int sl = 0; sl < q.ms; ++sl) a += q.colpart[(long)sl * q.P + k];
+  q.Obar[k] = a / q.sc[0];
+}
+
+// diag S and f; x = 0, r = f, p = z = f / m; partial sums of r . z and r . r
+__global__ void __launch_bounds__(256) sr_moments_kernel(SrWork q, double* __restrict__ x) {
   __shared__ double red[4];
   const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
   double rz = 0.0, rr = 0.0;
   if (k < q.P) {
     const double iw = 1.0 / q.sc[0];
-    double m = 0.0;
-    for (int i = 0; i < q.M; ++i) m += (wts ? wts[i] : 1.0) * O[(long)i * q.P + k];
-    m *= iw;
     double s2 = 0.0, fe = 0.0;
-    for (int i = 0; i < q.M; ++i) {
-      const double wi = wts ? wts[i] : 1.0, c = O[(long)i * q.P + k] - m;
-      s2 += wi * c * c;
-      fe += wi * el[i] * c;
+    for (int sl = 0; sl < q.ms; ++sl) {
+      s2 += q.colpart[(long)sl * q.P + k];
+      fe += q.colpart[((long)q.ms + sl) * q.P + k];
     }
     const double f = -2.0 * fe * iw;
-    q.Obar[k] = m; q.d[k] = s2 * iw; q.f[k] = f;
+    q.d[k] = s2 * iw; q.f[k] = f;
     const double z = f / sr_precond(q, k);
     q.r[k] = f; q.p[k] = z; x[k] = 0.0;
     rz = f * z;
@@ -210,16 +248,15 @@ __global__ void __launch_bounds__(256) sr_op_kernel(SrWork q, const double* __re
   }
 }
 
-// S'p and partial sums of p . S'p
-__global__ void __launch_bounds__(256)
-sr_sp_kernel(SrWork q, const double* __restrict__ O, const double* __restrict__ wts) {
+// S'p from the slice sums of O^T (w o u), and partial sums of p . S'p
+__global__ void __launch_bounds__(256) sr_sp_kernel(SrWork q) {
   __shared__ double red[4];
   if (q.sc[5] != 0.0) return;
   const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
   double pp = 0.0;
   if (k < q.P) {
     double t = 0.0;
-    for (int i = 0; i < q.M; ++i) t += (wts ? wts[i] : 1.0) * q.u[i] * O[(long)i * q.P + k];
+    for (int sl = 0; sl < q.ms; ++sl) t += q.colpart[(long)sl * q.P + k];
     const double sp = t / q.sc[0] - q.Obar[k] * q.sc[4] + q.eps * q.d[k] * q.p[k];
     q.Sp[k] = sp;
     pp = q.p[k] * sp;
@@ -289,7 +326,7 @@ __global__ void __launch_bounds__(256) sr_finish_kernel(SrWork q, double* __rest
 
 size_t sr_workspace_doubles(int M, long P) {
   const long nblk = (P + 255) / 256;
-  return (size_t)(6 * P + M + 3 * nblk + 16);
+  return (size_t)(6 * P + M + 3 * nblk + 16 + 2L * sr_slices(M) * P);
 }
 
 hipError_t launch_sr_step(int M, long P, const double* O, const double* el, const double* wts, double eps,
@@ -297,16 +334,22 @@ hipError_t launch_sr_step(int M, long P, const double* O, const double* el, cons
                           hipStream_t st) {
   SrWork q;
   q.P = P; q.M = M; q.nblk = (int)((P + 255) / 256); q.eps = eps;
+  q.ms = sr_slices(M); q.rows = (M + q.ms - 1) / q.ms;
   double* p = work;
   q.Obar = p; p += P; q.d = p; p += P; q.f = p; p += P; q.r = p; p += P; q.p = p; p += P; q.Sp = p; p += P;
-  q.u = p; p += M; q.part1 = p; p += q.nblk; q.part2 = p; p += q.nblk; q.part3 = p; p += q.nblk; q.sc = p;
-  const dim3 gk(q.nblk), blk(256);
+  q.u = p; p += M; q.part1 = p; p += q.nblk; q.part2 = p; p += q.nblk; q.part3 = p; p += q.nblk;
+  q.colpart = p; p += 2L * q.ms * P; q.sc = p;
+  const dim3 gk(q.nblk), g2(q.nblk, q.ms), blk(256);
   hipLaunchKernelGGL(sr_wsum_kernel, dim3(1), blk, 0, st, q, wts);
-  hipLaunchKernelGGL(sr_moments_kernel, gk, blk, 0, st, q, O, el, wts, delta);
+  hipLaunchKernelGGL(sr_colsum_kernel, g2, blk, 0, st, q, O, el, wts, 0);
+  hipLaunchKernelGGL(sr_mean_kernel, gk, blk, 0, st, q);
+  hipLaunchKernelGGL(sr_colsum_kernel, g2, blk, 0, st, q, O, el, wts, 1);
+  hipLaunchKernelGGL(sr_moments_kernel, gk, blk, 0, st, q, delta);
   hipLaunchKernelGGL(sr_init_kernel, dim3(1), dim3(64), 0, st, q);
   for (int it = 0; it < max_iter; ++it) {
     hipLaunchKernelGGL(sr_op_kernel, dim3(M + 1), blk, 0, st, q, O);
-    hipLaunchKernelGGL(sr_sp_kernel, gk, blk, 0, st, q, O, wts);
+    hipLaunchKernelGGL(sr_colsum_kernel, g2, blk, 0, st, q, O, el, wts, 2);
+    hipLaunchKernelGGL(sr_sp_kernel, gk, blk, 0, st, q);
     hipLaunchKernelGGL(sr_update_kernel, gk, blk, 0, st, q, delta, it);
     hipLaunchKernelGGL(sr_dir_kernel, gk, blk, 0, st, q, it);
     hipLaunchKernelGGL(sr_check_kernel, dim3(1), dim3(64), 0, st, q, tol);

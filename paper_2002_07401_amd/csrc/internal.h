@@ -128,6 +128,8 @@ struct SysDev {
   double* Kdu;       // [Lp][Lp]  (A^{du})^T = -A^{ud}
   double* Kdd;       // [Lp][Lp]  (A^{dd})^T
   double* Upf;       // [2][pk][Lp] unpaired orbitals of up, then down electrons
+  double* Kcat_u;    // [Lp][2Lp] [K^{uu} | K^{du}]: the B rows of a moved up electron
+  double* Kcat_d;    // [Lp][2Lp] [K^{ud} | K^{dd}]: the B rows of a moved down electron
 };
 
 // Device state of a batch of walkers.
@@ -192,7 +194,7 @@ struct WalkDev {
   double* j3e;        // [Wk][N][5] value part, gradient (3), Laplacian
   double* qbuf;       // [Wk][4][Lq] primitive values (and gradients) at r' (contracted orbitals)
   double* Bd;         // [Wk][N][Lp] B^d rows (Pfaffian pairing; B^u rows are in P)
-  double* pfw;        // [Wk][npf][npf] Parlett-Reid working copy (Pfaffian pairing)
+  double* pfB;        // [Wk][2][Lp] B^u, B^d rows of the proposal's r' (Pfaffian pairing)
 };
 
 // Workspace of the reverse pass (allocated on the first qmc_forces call).

@@ -12,7 +12,7 @@
 // rows are four FP64 MFMA products over the walkers, G~ one dot product per
 // entry of its upper triangle (the lower one mirrored, so G~ is exactly
 // skew-symmetric).  Pf(G~) (log|Pf| and sign) comes from a Parlett-Reid
-// reduction with partial pivoting, one workgroup per walker on a working copy;
+// reduction with partial pivoting, one workgroup per walker on a copy in LDS;
 // G~^{-1} from the Gauss-Jordan kernel of the determinant path.
 //
 // Pf is linear in row and column i, which alone depend on r_i, and
@@ -29,7 +29,8 @@
 // G' = G + e_e delta^T - delta e_e^T, and Woodbury's identity for this skew
 // rank-2 change gives, with p = G^{-1} e_e, q = G^{-1} delta and rho the ratio,
 //   G'^{-1} = G^{-1} + (p q^T - q p^T) / rho.
-// The accept also rewrites electron e's basis row and its two B rows; the
+// The accept also rewrites electron e's basis row and its two B rows (one
+// MFMA product over all walkers, which move the same electron); the
 // inverse is recomputed from the maintained G~ every refresh_every moves.
 #include "move_dev.h"
 
@@ -59,38 +60,46 @@ hipError_t launch_pf_B_build(const SysDev& s, const WalkDev& w, hipStream_t st) 
 }
 
 // ---------------------------------------------------------------------------
-// G~: workgroup (i, walker) computes row i's upper-triangle entries and writes
-// them with their negated mirror images; rows of fictitious electrons clear
-// their block
+// G~: rows of spin s are Phi_s (B^s)^T over the N electrons and Phi_s (U^s)^T
+// over the fictitious ones (FP64 MFMA products batched over walkers, written
+// into the rows of G~); the mirror kernel then makes G~ exactly skew-symmetric
+// from its upper triangle and clears the fictitious block.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) pf_G_kernel(SysDev s, WalkDev w) {
-  const int i = blockIdx.x, wk = blockIdx.y;
-  const int n = s.npf, N = s.N, lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+__global__ void __launch_bounds__(256) pf_mirror_kernel(SysDev s, WalkDev w) {
+  const int wk = blockIdx.x, n = s.npf, N = s.N;
   double* G = w.W + (long)wk * n * n;
-  if (i >= N) {
-    for (int j = N + threadIdx.x; j < n; j += blockDim.x) G[(long)i * n + j] = 0.0;
-    return;
-  }
-  const bool up = i < s.nu;
-  const double* ph = (const double*)w.phi + ((long)wk * N + i) * s.Lp;
-  const double* B = (up ? (const double*)w.P : w.Bd) + (long)wk * N * s.Lp;
-  const double* U = s.Upf + (up ? 0L : (long)s.pk * s.Lp);
-  if (threadIdx.x == 0) G[(long)i * n + i] = 0.0;
-  for (int j = i + 1 + wave; j < n; j += nw) {
-    const double* row = j < N ? B + (long)j * s.Lp : U + (long)(j - N) * s.Lp;
-    double v = 0.0;
-    for (int mu = lane; mu < s.Lp; mu += 64) v += ph[mu] * row[mu];
-    v = wave_sum(v);
-    if (lane == 0) {
-      G[(long)i * n + j] = v;
-      G[(long)j * n + i] = -v;
-    }
+  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+    const int i = idx / n, j = idx % n;
+    if (i > j) G[idx] = (i >= N && j >= N) ? 0.0 : -G[(long)j * n + i];
+    else if (i == j) G[idx] = 0.0;
+    else if (i >= N) G[idx] = 0.0;   // fictitious-fictitious block
   }
 }
 
 hipError_t launch_pf_G_build(const SysDev& s, const WalkDev& w, hipStream_t st) {
   if (s.npf > kPfMaxN) return hipErrorNotSupported;
-  hipLaunchKernelGGL(pf_G_kernel, dim3(s.npf, w.Wk), dim3(256), 0, st, s, w);
+  const long rowst = (long)s.N * s.Lp, n = s.npf;
+  for (int sp = 0; sp < 2; ++sp) {
+    const int i0 = sp == 0 ? 0 : s.nu, ni = sp == 0 ? s.nu : s.nd;
+    if (ni == 0) continue;
+    GemmArgs g = gemm_args(ni, s.N, s.Lp);
+    g.A = (const double*)w.phi + (long)i0 * s.Lp; g.lda = s.Lp; g.a_bs = rowst;
+    g.B = sp == 0 ? (const double*)w.P : w.Bd; g.ldb = s.Lp; g.b_bs = rowst;   // stored [j][mu]
+    g.C = w.W + (long)i0 * n; g.ldc = n; g.c_bs = n * n;
+    g.batch = w.Wk;
+    hipError_t e = gemm_f64(g, false, true, false, st);
+    if (e != hipSuccess) return e;
+    if (s.pk > 0) {
+      GemmArgs u = gemm_args(ni, s.pk, s.Lp);
+      u.A = (const double*)w.phi + (long)i0 * s.Lp; u.lda = s.Lp; u.a_bs = rowst;
+      u.B = s.Upf + (long)sp * s.pk * s.Lp; u.ldb = s.Lp; u.b_bs = 0;
+      u.C = w.W + (long)i0 * n + s.N; u.ldc = n; u.c_bs = n * n;
+      u.batch = w.Wk;
+      e = gemm_f64(u, false, true, false, st);
+      if (e != hipSuccess) return e;
+    }
+  }
+  hipLaunchKernelGGL(pf_mirror_kernel, dim3(w.Wk), dim3(256), 0, st, s, w);
   return hipGetLastError();
 }
 
@@ -104,6 +113,7 @@ hipError_t launch_pf_G_build(const SysDev& s, const WalkDev& w, hipStream_t st) 
 // Rows k and k+1 are not written by that update, so it reads them in place.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) pf_parlett_reid_kernel(SysDev s, WalkDev w) {
+  __shared__ double X[kPfMaxN * kPfMaxN];   // 72 KB: the working copy stays in LDS
   __shared__ double pv[4];
   __shared__ int pj[4];
   __shared__ int piv;
@@ -111,7 +121,6 @@ __global__ void __launch_bounds__(256) pf_parlett_reid_kernel(SysDev s, WalkDev 
   const int wk = blockIdx.x, n = s.npf, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nw = blockDim.x >> 6;
   const double* G = w.W + (long)wk * n * n;
-  double* X = w.pfw + (long)wk * n * n;
   for (int idx = tid; idx < n * n; idx += blockDim.x) X[idx] = G[idx];
   __syncthreads();
   double logabs = 0.0, sgn = 1.0;
@@ -226,7 +235,7 @@ hipError_t launch_pf_Y_build(const SysDev& s, const WalkDev& w, hipStream_t st) 
 // Proposal, one workgroup per walker: r', psi(r'), the Jastrow change, the new
 // row g' of G~ (into w_new) and the ratio sum_j g'_j (G~^{-1})_je.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(512)
 pf_propose_kernel(SysDev s, WalkDev w, int e, const double* __restrict__ r_new, const double* __restrict__ disp,
                   double* __restrict__ ratio_o) {
   __shared__ double red[8];
@@ -279,7 +288,8 @@ pf_propose_kernel(SysDev s, WalkDev w, int e, const double* __restrict__ r_new, 
 hipError_t launch_pf_propose(const SysDev& s, const WalkDev& w, int e, const double* r_new, const double* disp,
                              double* ratio, hipStream_t st) {
   if (s.npf > kPfMaxN) return hipErrorNotSupported;
-  hipLaunchKernelGGL(pf_propose_kernel, dim3(w.Wk), dim3(256), 0, st, s, w, e, r_new, disp, ratio);
+  // 8 waves per walker (block_sum_mv reduces over at most 8 waves)
+  hipLaunchKernelGGL(pf_propose_kernel, dim3(w.Wk), dim3(512), 0, st, s, w, e, r_new, disp, ratio);
   return hipGetLastError();
 }
 
@@ -293,7 +303,6 @@ __global__ void __launch_bounds__(256)
 pf_accept_kernel(SysDev s, WalkDev w, int e, const uint8_t* __restrict__ acc_in, const double* __restrict__ unif,
                  int32_t* __restrict__ cnt) {
   __shared__ double sp_[kPfMaxN], sq[kPfMaxN], sd[kPfMaxN];
-  __shared__ double psi_s[kFuseMaxLp];
   const int wk = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
   const int n = s.npf, N = s.N;
   const double ratio = w.ratio[wk], rd = w.rdet[wk];
@@ -324,26 +333,17 @@ pf_accept_kernel(SysDev s, WalkDev w, int e, const uint8_t* __restrict__ acc_in,
     G[(long)e * n + j] = wn[j];
     G[(long)j * n + e] = -wn[j];
   }
-  // basis row and B rows of electron e: B^s_e = psi(r')^T K^{s s_e}
+  // basis row and B rows of electron e (B^s_e = psi(r')^T K^{s s_e}, computed for
+  // every walker by the product launched before this kernel)
   const double* pn = w.psi_new + (long)wk * s.Lp;
-  for (int mu = tid; mu < s.Lp; mu += blockDim.x) psi_s[mu] = pn[mu];
-  __syncthreads();
-  const bool up = e < s.nu;
-  const double* Ku = up ? s.Kuu : s.Kud;
-  const double* Kd = up ? s.Kdu : s.Kdd;
+  const double* nb = w.pfB + (long)wk * 2 * s.Lp;
   double* ph = (double*)w.phi + ((long)wk * N + e) * s.Lp;
   double* bu = (double*)w.P + ((long)wk * N + e) * s.Lp;
   double* bd = w.Bd + ((long)wk * N + e) * s.Lp;
   for (int mu = tid; mu < s.Lp; mu += blockDim.x) {
-    double a = 0.0, b = 0.0;
-    for (int nu = 0; nu < s.L; ++nu) {
-      const double p = psi_s[nu];
-      a += p * Ku[(long)nu * s.Lp + mu];
-      b += p * Kd[(long)nu * s.Lp + mu];
-    }
-    ph[mu] = psi_s[mu];
-    bu[mu] = a;
-    bd[mu] = b;
+    ph[mu] = pn[mu];
+    bu[mu] = nb[mu];
+    bd[mu] = nb[s.Lp + mu];
   }
   if (tid == 0) {
     double* re = w.r + ((long)wk * N + e) * 3;
@@ -358,7 +358,18 @@ pf_accept_kernel(SysDev s, WalkDev w, int e, const uint8_t* __restrict__ acc_in,
 
 hipError_t launch_pf_accept(const SysDev& s, const WalkDev& w, int e, const uint8_t* acc, const double* unif,
                             int32_t* accept_count, hipStream_t st) {
-  if (s.npf > kPfMaxN || s.Lp > kFuseMaxLp) return hipErrorNotSupported;
+  if (s.npf > kPfMaxN) return hipErrorNotSupported;
+  // every walker moves electron e, of one spin: its two new B rows for all
+  // walkers are the product psi_new [Wk x Lp] [K^{u s_e} | K^{d s_e}] (FP64 MFMA)
+  // ([K^{u s_e} | K^{d s_e}] side by side: one product, 32 x 32 tiles)
+  {
+    GemmArgs g = gemm_args(w.Wk, 2 * s.Lp, s.Lp);
+    g.A = w.psi_new; g.lda = s.Lp;
+    g.B = e < s.nu ? s.Kcat_u : s.Kcat_d; g.ldb = 2 * s.Lp;
+    g.C = w.pfB; g.ldc = 2 * s.Lp;
+    const hipError_t err = gemm_f64(g, false, false, false, st);
+    if (err != hipSuccess) return err;
+  }
   hipLaunchKernelGGL(pf_accept_kernel, dim3(w.Wk), dim3(256), 0, st, s, w, e, acc, unif, accept_count);
   return hipGetLastError();
 }

@@ -345,7 +345,17 @@ extern "C" qmc_status qmc_system_create(const qmc_system_desc* desc, qmc_system*
         kud[(size_t)b * Lp + a] = q.lambda[(size_t)a * L + b];
         kdu[(size_t)a * Lp + b] = -q.lambda[(size_t)a * L + b];
       }
-    e = up((void**)&d.Kuu, kuu.data(), sizeof(double) * kuu.size());
+    std::vector<double> kcu((size_t)Lp * 2 * Lp), kcd((size_t)Lp * 2 * Lp);
+    for (int r = 0; r < Lp; ++r)
+      for (int c = 0; c < Lp; ++c) {
+        kcu[(size_t)r * 2 * Lp + c] = kuu[(size_t)r * Lp + c];
+        kcu[(size_t)r * 2 * Lp + Lp + c] = kdu[(size_t)r * Lp + c];
+        kcd[(size_t)r * 2 * Lp + c] = kud[(size_t)r * Lp + c];
+        kcd[(size_t)r * 2 * Lp + Lp + c] = kdd[(size_t)r * Lp + c];
+      }
+    e = up((void**)&d.Kcat_u, kcu.data(), sizeof(double) * kcu.size());
+    if (!e) e = up((void**)&d.Kcat_d, kcd.data(), sizeof(double) * kcd.size());
+    if (!e) e = up((void**)&d.Kuu, kuu.data(), sizeof(double) * kuu.size());
     if (!e) e = up((void**)&d.Kud, kud.data(), sizeof(double) * kud.size());
     if (!e) e = up((void**)&d.Kdu, kdu.data(), sizeof(double) * kdu.size());
     if (!e) e = up((void**)&d.Kdd, kdd.data(), sizeof(double) * kdd.size());
@@ -497,7 +507,7 @@ extern "C" qmc_status qmc_walkers_create(qmc_system* sys, int32_t n_walkers, qmc
   if (s.Lq > 0) al((void**)&d.qbuf, sizeof(double) * Wk * 4 * s.Lq);
   if (s.pairing) {
     al((void**)&d.Bd, sizeof(double) * Wk * N * Lp);
-    al((void**)&d.pfw, sizeof(double) * Wk * s.npf * s.npf);
+    al((void**)&d.pfB, sizeof(double) * Wk * 2 * Lp);
   }
   al((void**)&wk->lr.ratio, sizeof(double) * Wk * N * kHops);
   al((void**)&wk->lr.ah, sizeof(double) * Wk * N);

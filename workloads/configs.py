@@ -449,6 +449,24 @@ def forces_20nuc_80e(n_walkers=512, n_steps=0, seed_offset=3) -> Workload:
     return Workload(sysd, r0, disp, unif, 0.3)
 
 
+def pfaffian_20nuc_80e(n_walkers=512, n_steps=0, seed_offset=10) -> Workload:
+    """The 80-electron system of forces_20nuc_80e (20 nuclei, 40/40 electrons,
+    L = 300) as a Pfaffian (G~ 80 x 80): A^{ud} = its singlet Lambda plus a
+    triplet-zero part skew N(0, 0.3^2)/300, A^{uu}, A^{dd} skew N(0, 0.5^2)/300,
+    no unpaired orbitals."""
+    w = forces_20nuc_80e(n_walkers=n_walkers, n_steps=n_steps)
+    rng = np.random.default_rng(SEED_BASE + seed_offset)
+    s = w.system
+    L = len(s.lam)
+    sysd = replace(s, name="pfaffian_20nuc_80e", lam=s.lam + _skew_gaussian(rng, L, 0.3 / L), pairing=1,
+                   pf_uu=_skew_gaussian(rng, L, 0.5 / L), pf_dd=_skew_gaussian(rng, L, 0.5 / L),
+                   unpaired_dn=np.zeros((L, 0)))
+    disp, unif = w.disp, w.unif
+    if n_steps and disp is None:
+        disp, unif = _chain_arrays(rng, n_steps, n_walkers, 0.3)
+    return Workload(sysd, w.r0, disp, unif, 0.3)
+
+
 MULTI_SIZES = (16, 32, 48, 64, 96, 128, 192, 256)
 
 
