@@ -143,8 +143,8 @@ typedef struct {
    * (eq:pfodd): G~_{i, N+l} = phi(r_i) . U^{s_i}[:, l] with U^u = unpaired
    * and U^d = pf_unpaired_dn.  N + pf_k must be even and at most 96; FP64
    * precision only; n_up < n_dn is allowed.  Not supported with it:
-   * qmc_forces, qmc_multi_*, qmc_reweight, qmc_system_set_params, a Jastrow
-   * basis, contracted orbitals, drifts from qmc_propose_move. */
+   * qmc_forces, qmc_multi_*, qmc_system_set_params, a Jastrow basis,
+   * contracted orbitals.  qmc_reweight uses G~ and its inverse. */
   int32_t pairing;            /* 0 AGP determinant, 1 Pfaffian                   */
   const double *pf_uu;        /* [L][L] skew-symmetric                           */
   const double *pf_dd;        /* [L][L] skew-symmetric                           */
@@ -277,7 +277,8 @@ qmc_status qmc_swct(qmc_system *sys, int32_t n_walkers, const double *r, const d
 
 /* Finite-variance reweighting factor (Atomic forces section): for every
  * walker, from the geminal matrix W and its inverse of the last evaluation,
- *     R = (S sum_ij (W^-1)_ij^2)^-theta,   S = min_i sum_j W_ij^2,
+ *     R = (S sum_ij (W^-1)_ij^2)^-theta,   S = min_i sum_j W_ij^2
+ * (W the geminal matrix, or G~ for the Pfaffian),
  *     weight = (R / max(R, eps))^2,
  * the weight that turns averages over the modified sampling back into
  * averages over |Psi|^2 (R is a distance-to-node measure: small near the

@@ -13,7 +13,8 @@ sections of the paper:
       d ln(J^1/2 Psi)/dR_a = dlnPsi/dR_a + sum_i [omega_a(r_i) dlnPsi/dr_i
                                                   + 1/2 grad omega_a(r_i)]
   * finite-variance reweighting: R = (S sum_ij |G^-1_ij|^2)^(-theta),
-    S = min_i sum_j |G_ij|^2 (G the geminal matrix W), R^eps = max(R, eps),
+    S = min_i sum_j |G_ij|^2 (G the geminal matrix W, or the Pfaffian's
+    pairing matrix), R^eps = max(R, eps),
     weight = (R / R^eps)^2
   * stochastic reconfiguration: S_kl = <(O_k - Obar_k)(O_l - Obar_l)>,
     f_k = -2 <e_L (O_k - Obar_k)>, diagonal s_kk (1 + eps), step S'^-1 f
@@ -55,7 +56,12 @@ def swct_total(sy: O.OSystem, r, dR, dr, jacobian=False):
 def reweight(sy: O.OSystem, r, theta, eps):
     """R [Wk] and weight [Wk] from the geminal matrix of the configuration."""
     Phi, _, _ = O.agp_basis(sy, r)
-    W = O.geminal(sy, Phi)
+    if sy.pairing:
+        # the pairing matrix of the Pfaffian, fictitious rows included
+        from oracle import pfaffian as PF
+        W = PF.pairing_matrix(sy, Phi)
+    else:
+        W = O.geminal(sy, Phi)
     A = torch.linalg.inv(W)
     S = (W * W).sum(-1).min(-1).values
     R = (S * (A * A).sum(dim=(1, 2))) ** (-theta)

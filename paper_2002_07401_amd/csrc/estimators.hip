@@ -5,7 +5,8 @@
 //   total derivatives dR_a + sum_i omega_a(r_i) dr_i (+ 1/2 sum_i grad omega_a(r_i)
 //   for ln(J^1/2 Psi)), one workgroup per walker.
 // * Finite-variance reweighting: R = (S sum_ij (W^-1)_ij^2)^(-theta),
-//   S = min_i sum_j W_ij^2, weight = (R / max(R, eps))^2, one workgroup per walker.
+//   S = min_i sum_j W_ij^2, weight = (R / max(R, eps))^2, one workgroup per walker
+//   (W the geminal matrix, or the Pfaffian's pairing matrix G~).
 // * Stochastic reconfiguration: (S + eps diag S) delta = f with
 //   S v = O^T (w o (O v)) / sum w - Obar (Obar . v), f = -2 sum_i w_i e_i (O_i - Obar) / sum w,
 //   solved by diagonally preconditioned conjugate gradients on the device
@@ -79,7 +80,8 @@ __global__ void __launch_bounds__(256)
 reweight_kernel(SysDev s, WalkDev w, double theta, double eps, double* __restrict__ Rout,
                 double* __restrict__ wout) {
   __shared__ double red[4], redm[4];
-  const int wk = blockIdx.x, n = s.nu, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // the pairing matrix: W (n_up x n_up), or G~ of the Pfaffian with its exact inverse
+  const int wk = blockIdx.x, n = s.pairing ? s.npf : s.nu, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const double* W = w.W + (long)wk * n * n;
   const double* A = w.A + (long)wk * n * n;
   double smin = __builtin_inf(), sa = 0.0;

@@ -464,7 +464,7 @@ hipError_t launch_pf_G_build(const SysDev& s, const WalkDev& w, hipStream_t st);
 hipError_t launch_pf_factor(const SysDev& s, const WalkDev& w, hipStream_t st);
 hipError_t launch_pf_Y_build(const SysDev& s, const WalkDev& w, hipStream_t st);
 hipError_t launch_pf_propose(const SysDev& s, const WalkDev& w, int e, const double* r_new, const double* disp,
-                             double* ratio, hipStream_t st);
+                             double* ratio, double* drift, hipStream_t st);
 hipError_t launch_pf_accept(const SysDev& s, const WalkDev& w, int e, const uint8_t* acc, const double* unif,
                             int32_t* accept_count, hipStream_t st);
 

@@ -235,12 +235,17 @@ hipError_t launch_pf_Y_build(const SysDev& s, const WalkDev& w, hipStream_t st) 
 // Proposal, one workgroup per walker: r', psi(r'), the Jastrow change, the new
 // row g' of G~ (into w_new) and the ratio sum_j g'_j (G~^{-1})_je.
 // ---------------------------------------------------------------------------
+// With drift_o, also grad_e log|Psi| at r': column e of the updated inverse is
+// the old one divided by the ratio (p (1 + q_e / rho) with q_e = 1 - rho and
+// (G^{-1})_ee = 0), so grad_e log Pf(G') = sum_j (grad psi(r') . B_j) (G^{-1})_je / rho.
+template <bool DRIFT>
 __global__ void __launch_bounds__(512)
 pf_propose_kernel(SysDev s, WalkDev w, int e, const double* __restrict__ r_new, const double* __restrict__ disp,
-                  double* __restrict__ ratio_o) {
+                  double* __restrict__ ratio_o, double* __restrict__ drift_o) {
   __shared__ double red[8];
   __shared__ double rn[3];
   __shared__ double part[kPfMaxN];
+  __shared__ double gpart[DRIFT ? 3 * kPfMaxN : 1];
   const int wk = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
   const int n = s.npf, N = s.N;
   const double* r = w.r + (long)wk * N * 3;
@@ -251,45 +256,73 @@ pf_propose_kernel(SysDev s, WalkDev w, int e, const double* __restrict__ r_new, 
   __syncthreads();
   const double px = rn[0], py = rn[1], pz = rn[2];
   double* psi = w.psi_new + (long)wk * s.Lp;
-  for (int mu = tid; mu < s.Lp; mu += blockDim.x) psi[mu] = mu < s.L ? basis_value(s, mu, px, py, pz) : 0.0;
+  double* gpsi = w.gpsi_new + (long)wk * 3 * s.Lp;
+  for (int mu = tid; mu < s.Lp; mu += blockDim.x) {
+    if (DRIFT) {
+      double v = 0.0, gx = 0.0, gy = 0.0, gz = 0.0, lp;
+      if (mu < s.L) basis_vgl(s, mu, px, py, pz, v, gx, gy, gz, lp);
+      psi[mu] = v; gpsi[mu] = gx; gpsi[s.Lp + mu] = gy; gpsi[2 * s.Lp + mu] = gz;
+    } else {
+      psi[mu] = mu < s.L ? basis_value(s, mu, px, py, pz) : 0.0;
+    }
+  }
   double jn, g0, g1, g2, jo, d0, d1, d2;
-  jastrow_one(s, r, e, px, py, pz, false, jn, g0, g1, g2);
+  jastrow_one(s, r, e, px, py, pz, DRIFT, jn, g0, g1, g2);
   jastrow_one(s, r, e, r[3 * e], r[3 * e + 1], r[3 * e + 2], false, jo, d0, d1, d2);
   const double dJ = block_sum_mv(jn - jo, red);   // its barriers also publish psi
+  if (DRIFT) { g0 = block_sum_mv(g0, red); g1 = block_sum_mv(g1, red); g2 = block_sum_mv(g2, red); }
   const bool up = e < s.nu;
   const double* B = (up ? (const double*)w.P : w.Bd) + (long)wk * N * s.Lp;
   const double* U = s.Upf + (up ? 0L : (long)s.pk * s.Lp);
   const double* Ai = w.A + (long)wk * n * n;
   double* wn = w.w_new + (long)wk * n;
   for (int j = wave; j < n; j += nw) {
-    double v = 0.0;
+    double v = 0.0, vx = 0.0, vy = 0.0, vz = 0.0;
     if (j != e) {
       const double* row = j < N ? B + (long)j * s.Lp : U + (long)(j - N) * s.Lp;
-      for (int mu = lane; mu < s.Lp; mu += 64) v += psi[mu] * row[mu];
+      for (int mu = lane; mu < s.Lp; mu += 64) {
+        const double b = row[mu];
+        v += psi[mu] * b;
+        if (DRIFT) { vx += gpsi[mu] * b; vy += gpsi[s.Lp + mu] * b; vz += gpsi[2 * s.Lp + mu] * b; }
+      }
       v = wave_sum(v);
+      if (DRIFT) { vx = wave_sum(vx); vy = wave_sum(vy); vz = wave_sum(vz); }
     }
     if (lane == 0) {
+      const double a = Ai[(long)j * n + e];
       wn[j] = v;
-      part[j] = v * Ai[(long)j * n + e];
+      part[j] = v * a;
+      if (DRIFT) { gpart[3 * j] = vx * a; gpart[3 * j + 1] = vy * a; gpart[3 * j + 2] = vz * a; }
     }
   }
   __syncthreads();
   if (tid == 0) {
-    double rd = 0.0;
-    for (int j = 0; j < n; ++j) rd += part[j];   // fixed order
+    double rd = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+    for (int j = 0; j < n; ++j) {   // fixed order
+      rd += part[j];
+      if (DRIFT) { gx += gpart[3 * j]; gy += gpart[3 * j + 1]; gz += gpart[3 * j + 2]; }
+    }
     const double ratio = rd * exp(dJ);
     w.rdet[wk] = rd;
     w.dJ[wk] = dJ;
     w.ratio[wk] = ratio;
     if (ratio_o) ratio_o[wk] = ratio;
+    if (DRIFT) {
+      drift_o[3 * wk] = gx / rd + g0;
+      drift_o[3 * wk + 1] = gy / rd + g1;
+      drift_o[3 * wk + 2] = gz / rd + g2;
+    }
   }
 }
 
 hipError_t launch_pf_propose(const SysDev& s, const WalkDev& w, int e, const double* r_new, const double* disp,
-                             double* ratio, hipStream_t st) {
+                             double* ratio, double* drift, hipStream_t st) {
   if (s.npf > kPfMaxN) return hipErrorNotSupported;
   // 8 waves per walker (block_sum_mv reduces over at most 8 waves)
-  hipLaunchKernelGGL(pf_propose_kernel, dim3(w.Wk), dim3(512), 0, st, s, w, e, r_new, disp, ratio);
+  if (drift)
+    hipLaunchKernelGGL(pf_propose_kernel<true>, dim3(w.Wk), dim3(512), 0, st, s, w, e, r_new, disp, ratio, drift);
+  else
+    hipLaunchKernelGGL(pf_propose_kernel<false>, dim3(w.Wk), dim3(512), 0, st, s, w, e, r_new, disp, ratio, drift);
   return hipGetLastError();
 }
 

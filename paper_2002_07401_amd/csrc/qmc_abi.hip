@@ -620,10 +620,9 @@ extern "C" qmc_status qmc_propose_move(qmc_system* sys, qmc_walkers* wk, int32_t
   if (!r_new) return fail(QMC_ERR_ARG, "null r_new");
   // (a pending proposal is simply replaced)
   if (s.pairing) {
-    if (drift_new) return fail(QMC_ERR_UNSUPPORTED, "drifts of Pfaffian proposals are not built");
     wk->yt_valid = wk->lr_ready = false;
-    TIMED(wk, QMC_T_PROPOSE, stream, launch_pf_propose(s, wk->d, electron, r_new, nullptr, ratio, stream),
-          "Pfaffian proposal");
+    TIMED(wk, QMC_T_PROPOSE, stream,
+          launch_pf_propose(s, wk->d, electron, r_new, nullptr, ratio, drift_new, stream), "Pfaffian proposal");
     wk->pending_e = electron;
     return QMC_OK;
   }
@@ -750,7 +749,7 @@ extern "C" qmc_status qmc_vmc_steps(qmc_system* sys, qmc_walkers* wk, int32_t e_
     for (int t = 0; t < n_steps; ++t) {
       const int e = (int)((e_start + (long)t) % s.N);
       TIMED(wk, QMC_T_PROPOSE, stream,
-            launch_pf_propose(s, wk->d, e, nullptr, disp + (long)t * wk->d.Wk * 3, nullptr, stream),
+            launch_pf_propose(s, wk->d, e, nullptr, disp + (long)t * wk->d.Wk * 3, nullptr, nullptr, stream),
             "Pfaffian proposal");
       TIMED(wk, QMC_T_ACCEPT, stream,
             launch_pf_accept(s, wk->d, e, nullptr, unif + (long)t * wk->d.Wk, accept_count, stream),
@@ -976,7 +975,6 @@ extern "C" qmc_status qmc_reweight(qmc_system* sys, qmc_walkers* wk, double thet
   if (!(theta > 0.0) || !(eps >= 0.0)) return fail(QMC_ERR_ARG, "theta > 0 and eps >= 0 required");
   if (!wk->evaluated || !wk->yt_valid)
     return fail(QMC_ERR_STATE, "the reweighting factor needs an evaluation since the last move");
-  if (sys->d.pairing) return fail(QMC_ERR_UNSUPPORTED, "the reweighting factor of the Pfaffian is not built");
   HIP_TRY(launch_reweight(sys->d, wk->d, theta, eps, R, weight, stream), "reweight");
   return QMC_OK;
 }

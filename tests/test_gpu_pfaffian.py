@@ -80,17 +80,22 @@ def test_singlet_pfaffian_equals_determinant_path():
         assert torch.equal(b["sign"].cpu(), a["sign"].cpu() * (-1) ** (n * (n - 1) // 2))
 
 
-def test_pfaffian_propose_ratio(fw):
+def test_pfaffian_propose_ratio_and_drift(fw):
     P = need_gpu()
     _, wk, r, _ = _eval(P, fw.system, fw.r0, 32)
     sy = O.from_workload_system(fw.system)
     for e in (0, 10, 11, 19):
         rn = r[:, e] + torch.tensor(fw.disp[e])
         ratio = wk.propose(e, rn.cuda().contiguous())
+        ratio2, dn = wk.propose(e, rn.cuda().contiguous(), drift=True)
         torch.cuda.synchronize()
         err = rel_err(ratio.cpu(), O.move_ratio(sy, r, e, rn)).max().item()
         print(f"[pfaffian ratio e={e}] {err:.3e}")
         assert err <= 1e-10
+        assert torch.equal(ratio, ratio2)
+        r2 = r.clone(); r2[:, e] = rn
+        dref = O.evaluate(sy, r2)["drift"][:, e]
+        assert ((dn.cpu() - dref).abs() / dref.abs().clamp(min=1.0)).max().item() <= 1e-8
 
 
 def test_pfaffian_chain_matches_oracle(fw):
@@ -141,6 +146,16 @@ def test_pfaffian_host_decisions_and_refresh(fw):
     assert rel_err(la, O.evaluate(sy, rc)["logabs"]).max().item() <= 1e-10
 
 
+def test_pfaffian_reweight(fw):
+    from oracle import estimators as E
+    P = need_gpu()
+    _, wk, r, _ = _eval(P, fw.system, fw.r0, 16)
+    R, wt = P.reweight(wk, 0.375, 0.0)
+    torch.cuda.synchronize()
+    R_ref, _ = E.reweight(O.from_workload_system(fw.system), r, 0.375, 0.0)
+    assert ((R.cpu() - R_ref).abs() / R_ref.abs()).max().item() <= 1e-10
+
+
 def test_pfaffian_lattice_hops(fw):
     P = need_gpu()
     _, wk, r, _ = _eval(P, fw.system, fw.r0, 8)
@@ -160,10 +175,7 @@ def test_pfaffian_refusals(fw):
         wk.forces(r.cuda(), one, None)
     assert ex.value.code == -5
     with pytest.raises(P.QMCError) as ex:
-        P.reweight(wk, 0.375, 0.0)
-    assert ex.value.code == -5
-    with pytest.raises(P.QMCError) as ex:
-        wk.propose(0, r[:, 0].cuda().contiguous(), drift=True)
+        sysh.set_params(lam=torch.tensor(fw.system.lam, device="cuda"))
     assert ex.value.code == -5
     s = fw.system
     with pytest.raises(P.QMCError) as ex:   # N + k odd
