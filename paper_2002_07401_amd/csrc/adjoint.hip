@@ -419,17 +419,33 @@ static hipError_t sum_rows(const double* in, long n_rows, long len, double* out,
 
 // The reverse pass.  The forward state (Phi rows are recomputed here; P, A,
 // Yt, gJ, drift come from the evaluation that the caller ran just before).
+// Zero fill (the down stacks' rows past n_dn when there are unpaired orbitals).
+__global__ void __launch_bounds__(256) zero_fill_kernel(double* __restrict__ x, long n) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = 0.0;
+}
+
+// With k = n_up - n_dn unpaired orbitals W is n x n (n = n_up) with columns
+// n_dn + l = Phi_U U_l and V's columns n_dn + l = Q_U U_l.  The down stacks hold
+// n_dn real rows and zero rows after them, so every product over the down side
+// sees only the paired columns; the unpaired columns add G_W[:, n_dn:] U to
+// dF/dPhi_U, and their share of dF/dQ_U is already in Yt_U.
 hipError_t launch_forces(const SysDev& s, const WalkDev& w, const AdjWork& aw, const double* ga,
                          const double* gb, int per_walker, double* dR, double* dzeta, double* dlambda,
                          double* djas, double* dr, hipStream_t st) {
-  const int n = s.nu, Wk = w.Wk, Lp = s.Lp, L = s.L, N = s.N;
+  const int n = s.nu, nd = s.nd, Wk = w.Wk, Lp = s.Lp, L = s.L, N = s.N;
   const long rowst = (long)N * Lp, stk = 2L * n * Lp;
   // 1. stacked rows [Phi_U; Q_U], [Phi_D; Q_D]
+  if (s.nk > 0) {
+    const long cnt = (long)Wk * stk;
+    hipLaunchKernelGGL(zero_fill_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, aw.SD, cnt);
+    HT(hipGetLastError());
+  }
   hipLaunchKernelGGL(stack_basis_kernel, dim3((unsigned)((long)Wk * N)), dim3(256), 0, st, s, w, aw.SU, aw.SD);
   HT(hipGetLastError());
-  // 2. V = Q_U P_D^T + P_U Q_D^T   (n x n per walker)
+  // 2. V = Q_U P_D^T + P_U Q_D^T   (paired columns), V[:, n_dn + l] = Q_U U_l
   {
-    GemmArgs g = gemm_args(n, n, Lp);
+    GemmArgs g = gemm_args(n, nd, Lp);
     g.A = aw.SU + (long)n * Lp; g.lda = Lp; g.a_bs = stk;
     g.B = (const double*)w.P + (long)n * Lp; g.ldb = Lp; g.b_bs = rowst;
     g.C = aw.VQ; g.ldc = n; g.c_bs = (long)n * n; g.batch = Wk;
@@ -438,6 +454,13 @@ hipError_t launch_forces(const SysDev& s, const WalkDev& w, const AdjWork& aw, c
     g.B = aw.SD + (long)n * Lp; g.b_bs = stk;
     g.accumulate = 1;
     HT(gemm_f64(g, false, true, false, st));
+    if (s.nk > 0) {
+      GemmArgs u = gemm_args(n, s.nk, Lp);
+      u.A = aw.SU + (long)n * Lp; u.lda = Lp; u.a_bs = stk;
+      u.B = s.Uph; u.ldb = Lp; u.b_bs = 0;
+      u.C = aw.VQ + nd; u.ldc = n; u.c_bs = (long)n * n; u.batch = Wk;
+      HT(gemm_f64(u, false, true, false, st));
+    }
   }
   // 3. M = A V A
   {
@@ -481,11 +504,19 @@ hipError_t launch_forces(const SysDev& s, const WalkDev& w, const AdjWork& aw, c
     g.B = s.lamT; g.ldb = Lp;
     g.C = aw.PB; g.ldc = Lp; g.c_grp = n; g.c_gs = rowst;
     HT(gemm_f64(g, false, false, true, st));
-    GemmArgs h = gemm_args(Wk * n, Lp, Lp);
-    h.A = aw.XD; h.lda = Lp;
+    GemmArgs h = gemm_args(Wk * nd, Lp, Lp);
+    h.A = aw.XD; h.lda = Lp; h.a_grp = nd; h.a_gs = (long)n * Lp;
     h.B = s.lam; h.ldb = Lp;
-    h.C = aw.PB + (long)n * Lp; h.ldc = Lp; h.c_grp = n; h.c_gs = rowst;
+    h.C = aw.PB + (long)n * Lp; h.ldc = Lp; h.c_grp = nd; h.c_gs = rowst;
     HT(gemm_f64(h, false, false, true, st));
+    if (s.nk > 0) {   // dF/dPhi_U += G_W[:, n_dn:] U
+      GemmArgs u = gemm_args(n, Lp, s.nk);
+      u.A = aw.GG + nd; u.lda = 2 * n; u.a_bs = 2L * n * n;
+      u.B = s.Uph; u.ldb = Lp; u.b_bs = 0;
+      u.C = aw.PB; u.ldc = Lp; u.c_bs = rowst; u.batch = Wk;
+      u.accumulate = 1;
+      HT(gemm_f64(u, false, false, false, st));
+    }
   }
   // 7. dF/dLambda = [Phi_U; Q_U]^T [X_U; Z_U]
   if (dlambda) {

@@ -894,7 +894,6 @@ extern "C" qmc_status qmc_forces(qmc_system* sys, qmc_walkers* wk, const double*
   if (s.precision != QMC_FP64) return fail(QMC_ERR_UNSUPPORTED, "forces are built for the FP64 path");
   if (s.LJ > 0) return fail(QMC_ERR_UNSUPPORTED, "forces with a Jastrow basis are not built");
   if (s.Lq > 0) return fail(QMC_ERR_UNSUPPORTED, "forces with contracted orbitals are not built");
-  if (s.nk > 0) return fail(QMC_ERR_UNSUPPORTED, "forces with unpaired orbitals are not built");
   if (s.pairing) return fail(QMC_ERR_UNSUPPORTED, "forces of the Pfaffian are not built");
   if (s.N > 2 * kLuMaxN || s.n_nuc > kMaxNucBack)
     return fail(QMC_ERR_UNSUPPORTED, "forces need N <= 256 electrons and <= 256 nuclei");

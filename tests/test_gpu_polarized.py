@@ -138,12 +138,34 @@ def test_polarized_contracted_and_jastrow_basis():
     assert rel_err(ratio.cpu(), O.move_ratio(sy, r, 4, rn)).max().item() <= 1e-10
 
 
+def test_polarized_forces_match_oracle(pw):
+    # the adjoint with unpaired orbitals: G_W's unpaired columns feed dF/dPhi_up
+    P = need_gpu()
+    Wk = 6
+    _, wk, r, _ = _eval(P, pw.system, pw.r0, Wk)
+    sy = O.from_workload_system(pw.system)
+    rng = np.random.default_rng(5)
+    gl = torch.tensor(rng.normal(size=Wk))
+    ge = torch.tensor(rng.normal(size=Wk))
+    out = wk.forces(r.cuda(), gl.cuda(), ge.cuda())
+    torch.cuda.synchronize()
+    ref = O.forces_vjp(sy, r, gl, ge)
+    for k in ("R", "zeta", "lam", "jas", "r"):
+        a, b = out[k].cpu(), ref[k]
+        err = (a - b).abs().max().item() / max(1.0, b.abs().max().item())
+        print(f"[polarized forces] {k}: {err:.3e}")
+        assert err <= 1e-8, (k, err)
+    one = torch.ones(Wk, dtype=torch.float64, device="cuda")
+    per = wk.forces(r.cuda(), one, None, per_walker=True)
+    pref = O.forces_per_walker(sy, r)
+    for k in ("zeta", "jas"):
+        a, b = per[k].cpu(), pref[k][0]
+        assert (a - b).abs().max().item() / max(1.0, b.abs().max().item()) <= 1e-8, k
+
+
 def test_polarized_refusals(pw):
     P = need_gpu()
     sysh, wk, r, _ = _eval(P, pw.system, pw.r0, 4)
-    with pytest.raises(P.QMCError) as ex:
-        wk.forces(r.cuda(), torch.ones(4, dtype=torch.float64, device="cuda"), None)
-    assert ex.value.code == -5
     swapped = dataclasses.replace(pw.system, n_up=9, n_dn=11, unpaired=np.zeros((44, 0)))
     with pytest.raises(P.QMCError) as ex:
         P.JAGPSystem(swapped)
