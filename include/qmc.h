@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define QMC_ABI_VERSION 8
+#define QMC_ABI_VERSION 9
 
 typedef enum {
   QMC_OK = 0,
@@ -288,6 +288,20 @@ qmc_status qmc_swct(qmc_system *sys, int32_t n_walkers, const double *r, const d
  *   weight [Wk] device, written, may be NULL */
 qmc_status qmc_reweight(qmc_system *sys, qmc_walkers *wk, double theta, double eps, double *R, double *weight,
                         hipStream_t stream);
+
+/* Logarithmic derivatives O_k of the Jastrow-basis coefficients
+ * (onebody_J_inh, threebody_jastrow) for every walker at its current positions
+ * (after qmc_eval_batch and any accepted moves), the SR step's O_k for these
+ * parameters:
+ *   d_j1_inh [Wk][2][LJ]:      d log Psi / d j1_inh[s][k] = sum_{i of spin s} chi_k(r_i)
+ *   d_j3     [Wk][3][LJ][LJ]:  M^{uu}, M^{dd}: 1/2 (X_s X_s^T - sum_{i of s} chi(r_i) chi(r_i)^T)
+ *                              (the gradient with respect to a symmetric matrix,
+ *                              written symmetric: dlog Psi = sum_kl D_kl dM_kl for
+ *                              every symmetric dM); M^{ud}: X_u X_d^T,
+ * X_s = sum_{i of spin s} chi(r_i).  Device pointers, either may be NULL.
+ * QMC_ERR_ARG without a Jastrow basis. */
+qmc_status qmc_jastrow_basis_logderiv(qmc_system *sys, qmc_walkers *wk, double *d_j1_inh, double *d_j3,
+                                      hipStream_t stream);
 
 /* Bytes of device workspace qmc_sr_step needs (0 for non-positive sizes). */
 size_t qmc_sr_workspace_size(int32_t n_samples, int64_t n_params);

@@ -34,7 +34,7 @@ FUNCTIONS = (
     "qmc_walkers_timing", "qmc_forces", "qmc_system_set_params", "qmc_multi_create",
     "qmc_multi_destroy", "qmc_multi_autotune", "qmc_multi_vmc_steps", "qmc_philox_draws",
     "qmc_lrdmc_hops", "qmc_lrdmc_advance", "qmc_walkers_set_timing_mask", "qmc_swct", "qmc_reweight",
-    "qmc_sr_workspace_size", "qmc_sr_step",
+    "qmc_sr_workspace_size", "qmc_sr_step", "qmc_jastrow_basis_logderiv",
 )
 
 TIMER_NAMES = ("basis", "P_build", "W_build", "LU", "Y_build", "rowdot", "assemble", "propose",
@@ -118,6 +118,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.qmc_lrdmc_hops.argtypes = [vp, vp, ctypes.POINTER(LrdmcParams), dp, dp, vp]
     lib.qmc_lrdmc_advance.argtypes = [vp, vp, dp, dp, dp, dp, vp, vp]
     lib.qmc_swct.argtypes = [vp, i32, dp, dp, dp, i32, dp, vp]
+    lib.qmc_jastrow_basis_logderiv.argtypes = [vp, vp, dp, dp, vp]
     lib.qmc_reweight.argtypes = [vp, vp, ctypes.c_double, ctypes.c_double, dp, dp, vp]
     lib.qmc_sr_workspace_size.restype = ctypes.c_size_t
     lib.qmc_sr_workspace_size.argtypes = [i32, ctypes.c_int64]
@@ -207,6 +208,7 @@ class JAGPSystem:
         self.n_up, self.n_dn, self.L = s.n_up, s.n_dn, len(s.lam)
         self.n_nuc = len(s.Z)
         self.n_jas = len(s.Z) + len(s.j2)
+        self.LJ = LJ
         self.pairing = pf
         self.npf = s.n_up + s.n_dn + k_pf if pf else 0
 
@@ -324,6 +326,14 @@ class Walkers:
         _check(load().qmc_forces(S.h, self.h, _ptr(r), 1 if per_walker else 0, _ptr(gbar_logpsi),
                                  _ptr(gbar_eloc), ctypes.byref(g), _stream(stream)))
         return out
+
+    def jastrow_basis_logderiv(self, stream=None):
+        """d log Psi / d (j1_inh [Wk, 2, LJ], j3 [Wk, 3, LJ, LJ]) at the current positions."""
+        LJ = self.sys.LJ
+        f = lambda *sh: torch.empty(*sh, dtype=torch.float64, device="cuda")
+        dm, dM = f(self.n, 2, LJ), f(self.n, 3, LJ, LJ)
+        _check(load().qmc_jastrow_basis_logderiv(self.sys.h, self.h, _ptr(dm), _ptr(dM), _stream(stream)))
+        return dm, dM
 
     def lrdmc_hops(self, a: float, a_valence: float = 0.0, tf_scale: float = 1.0, gamma: float = 0.0,
                    ratios: bool = True, stream=None) -> Dict[str, torch.Tensor]:

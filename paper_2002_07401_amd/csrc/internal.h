@@ -470,6 +470,8 @@ hipError_t launch_pf_accept(const SysDev& s, const WalkDev& w, int e, const uint
 
 // Jastrow-basis terms of an evaluation (LJ > 0): chi, X -> G, h, per-electron terms
 hipError_t launch_jastrow3_eval(const SysDev& s, const WalkDev& w, hipStream_t st);
+// d log Psi / d (one-body inhomogeneous, three/four-body coefficients), per walker
+hipError_t launch_jastrow3_logderiv(const SysDev& s, const WalkDev& w, double* dm, double* dM, hipStream_t st);
 // Estimators (space warp, reweighting factor, stochastic reconfiguration)
 hipError_t launch_swct(const SysDev& s, int Wk, const double* r, const double* dR, const double* dr, int jac,
                        double* out, hipStream_t st);

@@ -102,4 +102,61 @@ hipError_t launch_jastrow3_eval(const SysDev& s, const WalkDev& w, hipStream_t s
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Logarithmic derivatives of the Jastrow-basis coefficients, per walker:
+//   d log Psi / d m_s      = X_s = sum_{i of spin s} chi(r_i)
+//   d log Psi / d M^{ud}   = X_u X_d^T
+//   d log Psi / d M^{ss}   = 1/2 (X_s X_s^T - C_s),  C_s = sum_{i of spin s} chi(r_i) chi(r_i)^T
+// (M^{ss} symmetric: the gradient with respect to a symmetric matrix, each
+// unordered pair once, written as a symmetric matrix so that
+// dlog Psi = sum_kl D_kl dM_kl for every symmetric dM).  chi is the walkers'
+// current state (evaluation, then the accepted moves).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) j3_logderiv_kernel(SysDev s, WalkDev w, double* __restrict__ dm,
+                                                          double* __restrict__ dM) {
+  __shared__ double X[2 * kMaxLJ];
+  const int wk = blockIdx.x, LJ = s.LJ;
+  const double* chi = w.chi + (long)wk * s.N * LJ;
+  for (int k = threadIdx.x; k < LJ; k += blockDim.x) {
+    double xu = 0.0, xd = 0.0;
+    for (int i = 0; i < s.nu; ++i) xu += chi[(long)i * LJ + k];
+    for (int i = s.nu; i < s.N; ++i) xd += chi[(long)i * LJ + k];
+    X[k] = xu;
+    X[LJ + k] = xd;
+    if (dm) { dm[(long)wk * 2 * LJ + k] = xu; dm[(long)wk * 2 * LJ + LJ + k] = xd; }
+  }
+  __syncthreads();
+  if (!dM) return;
+  double* D = dM + (long)wk * 3 * LJ * LJ;
+  const long LL = (long)LJ * LJ;
+  for (long idx = threadIdx.x; idx < LL; idx += blockDim.x) {
+    const int k = (int)(idx / LJ), l = (int)(idx % LJ);
+    const double cu = s.nu > 0 ? D[idx] : 0.0, cd = s.nd > 0 ? D[LL + idx] : 0.0;   // C_s in place
+    D[idx] = 0.5 * (X[k] * X[l] - cu);                           // up-up
+    D[LL + idx] = 0.5 * (X[LJ + k] * X[LJ + l] - cd);            // down-down
+    D[2 * LL + idx] = X[k] * X[LJ + l];                          // up-down
+  }
+}
+
+hipError_t launch_jastrow3_logderiv(const SysDev& s, const WalkDev& w, double* dm, double* dM, hipStream_t st) {
+  if (s.LJ <= 0 || s.LJ > kMaxLJ) return hipErrorNotSupported;
+  const int LJ = s.LJ;
+  if (dM) {
+    // C_s = chi_s^T chi_s into the up-up and down-down slots, batched over walkers
+    for (int sp = 0; sp < 2; ++sp) {
+      const int row0 = sp == 0 ? 0 : s.nu, nrow = sp == 0 ? s.nu : s.nd;
+      GemmArgs g = gemm_args(LJ, LJ, nrow);
+      g.A = w.chi + (long)row0 * LJ; g.lda = LJ; g.a_bs = (long)s.N * LJ;
+      g.B = w.chi + (long)row0 * LJ; g.ldb = LJ; g.b_bs = (long)s.N * LJ;
+      g.C = dM + (long)sp * LJ * LJ; g.ldc = LJ; g.c_bs = 3L * LJ * LJ;
+      g.batch = w.Wk;
+      if (nrow == 0) continue;   // C_s = 0: the kernel does not read the slot
+      const hipError_t e = gemm_f64(g, true, false, false, st);
+      if (e != hipSuccess) return e;
+    }
+  }
+  hipLaunchKernelGGL(j3_logderiv_kernel, dim3(w.Wk), dim3(256), 0, st, s, w, dm, dM);
+  return hipGetLastError();
+}
+
 }  // namespace qmc

@@ -978,6 +978,18 @@ extern "C" qmc_status qmc_reweight(qmc_system* sys, qmc_walkers* wk, double thet
   return QMC_OK;
 }
 
+extern "C" qmc_status qmc_jastrow_basis_logderiv(qmc_system* sys, qmc_walkers* wk, double* d_j1_inh, double* d_j3,
+                                                 hipStream_t stream) {
+  qmc_status c = check_pair(sys, wk);
+  if (c) return c;
+  if (sys->d.LJ <= 0) return fail(QMC_ERR_ARG, "the system has no Jastrow basis");
+  if (!wk->evaluated) return fail(QMC_ERR_STATE, "log-derivatives before eval_batch");
+  if (wk->generation != sys->generation) return fail(QMC_ERR_STATE, "parameters changed since the last eval_batch");
+  if (!d_j1_inh && !d_j3) return QMC_OK;
+  HIP_TRY(launch_jastrow3_logderiv(sys->d, wk->d, d_j1_inh, d_j3, stream), "Jastrow-basis log-derivatives");
+  return QMC_OK;
+}
+
 extern "C" size_t qmc_sr_workspace_size(int32_t n_samples, int64_t n_params) {
   if (n_samples <= 0 || n_params <= 0) return 0;
   return sizeof(double) * sr_workspace_doubles(n_samples, (long)n_params);
