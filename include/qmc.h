@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define QMC_ABI_VERSION 9
+#define QMC_ABI_VERSION 10
 
 typedef enum {
   QMC_OK = 0,
@@ -302,6 +302,18 @@ qmc_status qmc_reweight(qmc_system *sys, qmc_walkers *wk, double theta, double e
  * QMC_ERR_ARG without a Jastrow basis. */
 qmc_status qmc_jastrow_basis_logderiv(qmc_system *sys, qmc_walkers *wk, double *d_j1_inh, double *d_j3,
                                       hipStream_t stream);
+
+/* Logarithmic derivatives O_k of the Pfaffian's pairing coefficients for every
+ * walker at its current state (after qmc_eval_batch and any accepted moves),
+ * from d log Pf = 1/2 tr(G~^{-1} dG~):
+ *   d_uu, d_dd [Wk][L][L]: d / dpf_uu, d / dpf_dd (the gradient with respect to a
+ *                          skew-symmetric matrix, written skew: dlog Psi =
+ *                          sum_kl D_kl dA_kl for every skew dA)
+ *   d_ud       [Wk][L][L]: d / dlambda (every entry independent)
+ *   d_unpaired_up, d_unpaired_dn [Wk][L][pf_k]: d / dunpaired, d / dpf_unpaired_dn
+ * Device pointers, any may be NULL.  QMC_ERR_ARG for a determinant system. */
+qmc_status qmc_pfaffian_logderiv(qmc_system *sys, qmc_walkers *wk, double *d_uu, double *d_dd, double *d_ud,
+                                 double *d_unpaired_up, double *d_unpaired_dn, hipStream_t stream);
 
 /* Bytes of device workspace qmc_sr_step needs (0 for non-positive sizes). */
 size_t qmc_sr_workspace_size(int32_t n_samples, int64_t n_params);

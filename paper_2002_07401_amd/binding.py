@@ -34,7 +34,7 @@ FUNCTIONS = (
     "qmc_walkers_timing", "qmc_forces", "qmc_system_set_params", "qmc_multi_create",
     "qmc_multi_destroy", "qmc_multi_autotune", "qmc_multi_vmc_steps", "qmc_philox_draws",
     "qmc_lrdmc_hops", "qmc_lrdmc_advance", "qmc_walkers_set_timing_mask", "qmc_swct", "qmc_reweight",
-    "qmc_sr_workspace_size", "qmc_sr_step", "qmc_jastrow_basis_logderiv",
+    "qmc_sr_workspace_size", "qmc_sr_step", "qmc_jastrow_basis_logderiv", "qmc_pfaffian_logderiv",
 )
 
 TIMER_NAMES = ("basis", "P_build", "W_build", "LU", "Y_build", "rowdot", "assemble", "propose",
@@ -119,6 +119,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.qmc_lrdmc_advance.argtypes = [vp, vp, dp, dp, dp, dp, vp, vp]
     lib.qmc_swct.argtypes = [vp, i32, dp, dp, dp, i32, dp, vp]
     lib.qmc_jastrow_basis_logderiv.argtypes = [vp, vp, dp, dp, vp]
+    lib.qmc_pfaffian_logderiv.argtypes = [vp, vp, dp, dp, dp, dp, dp, vp]
     lib.qmc_reweight.argtypes = [vp, vp, ctypes.c_double, ctypes.c_double, dp, dp, vp]
     lib.qmc_sr_workspace_size.restype = ctypes.c_size_t
     lib.qmc_sr_workspace_size.argtypes = [i32, ctypes.c_int64]
@@ -334,6 +335,17 @@ class Walkers:
         dm, dM = f(self.n, 2, LJ), f(self.n, 3, LJ, LJ)
         _check(load().qmc_jastrow_basis_logderiv(self.sys.h, self.h, _ptr(dm), _ptr(dM), _stream(stream)))
         return dm, dM
+
+    def pfaffian_logderiv(self, stream=None):
+        """d log Psi / d (pf_uu, pf_dd, lambda [Wk, L, L] each; unpaired, unpaired_dn [Wk, L, k])."""
+        S = self.sys
+        k = S.npf - S.n_elec
+        f = lambda *sh: torch.empty(*sh, dtype=torch.float64, device="cuda")
+        out = dict(uu=f(self.n, S.L, S.L), dd=f(self.n, S.L, S.L), ud=f(self.n, S.L, S.L))
+        out.update(unpaired_up=f(self.n, S.L, k) if k else None, unpaired_dn=f(self.n, S.L, k) if k else None)
+        _check(load().qmc_pfaffian_logderiv(S.h, self.h, _ptr(out["uu"]), _ptr(out["dd"]), _ptr(out["ud"]),
+                                            _ptr(out["unpaired_up"]), _ptr(out["unpaired_dn"]), _stream(stream)))
+        return out
 
     def lrdmc_hops(self, a: float, a_valence: float = 0.0, tf_scale: float = 1.0, gamma: float = 0.0,
                    ratios: bool = True, stream=None) -> Dict[str, torch.Tensor]:

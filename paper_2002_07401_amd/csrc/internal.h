@@ -195,6 +195,7 @@ struct WalkDev {
   double* qbuf;       // [Wk][4][Lq] primitive values (and gradients) at r' (contracted orbitals)
   double* Bd;         // [Wk][N][Lp] B^d rows (Pfaffian pairing; B^u rows are in P)
   double* pfB;        // [Wk][2][Lp] B^u, B^d rows of the proposal's r' (Pfaffian pairing)
+  double* pfT;        // [Wk][N][Lp] work rows of the Pfaffian log-derivatives
 };
 
 // Workspace of the reverse pass (allocated on the first qmc_forces call).
@@ -465,6 +466,8 @@ hipError_t launch_pf_factor(const SysDev& s, const WalkDev& w, hipStream_t st);
 hipError_t launch_pf_Y_build(const SysDev& s, const WalkDev& w, hipStream_t st);
 hipError_t launch_pf_propose(const SysDev& s, const WalkDev& w, int e, const double* r_new, const double* disp,
                              double* ratio, double* drift, hipStream_t st);
+hipError_t launch_pf_logderiv(const SysDev& s, const WalkDev& w, double* d_uu, double* d_dd, double* d_ud,
+                              double* d_uup, double* d_udn, hipStream_t st);
 hipError_t launch_pf_accept(const SysDev& s, const WalkDev& w, int e, const uint8_t* acc, const double* unif,
                             int32_t* accept_count, hipStream_t st);
 

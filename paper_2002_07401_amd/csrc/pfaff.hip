@@ -407,4 +407,71 @@ hipError_t launch_pf_accept(const SysDev& s, const WalkDev& w, int e, const uint
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Logarithmic derivatives of the pairing coefficients, per walker, from
+// d log Pf = 1/2 tr(G~^{-1} dG~) with G~^{-1} skew-symmetric (T = G~^{-1} blocks):
+//   d / dA^{uu} = -1/2 Phi_u^T T_uu Phi_u      (skew: the gradient with respect to
+//   d / dA^{dd} = -1/2 Phi_d^T T_dd Phi_d       a skew-symmetric matrix, written skew)
+//   d / dA^{ud} = -Phi_u^T T_ud Phi_d
+//   d / dU^s[:, l] = sum_{i of spin s} (G~^{-1})_{N+l, i} psi(r_i) = -Phi_s^T T_{s f}[:, l]
+// as two FP64 MFMA products each (T Phi into the walkers' work rows, then Phi^T (T Phi)).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) pf_scale_kernel(double* __restrict__ x, long n, double c) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] *= c;
+}
+
+hipError_t launch_pf_logderiv(const SysDev& s, const WalkDev& w, double* d_uu, double* d_dd, double* d_ud,
+                              double* d_uup, double* d_udn, hipStream_t st) {
+  const long n = s.npf, rowst = (long)s.N * s.Lp, L = s.L;
+  const double* phi = (const double*)w.phi;
+  // (row block rs of T) x Phi (column spin cs) -> pfT rows, then Phi_rs^T pfT -> out [L][L]
+  auto pair = [&](int rs, int cs, double* out, double scale) -> hipError_t {
+    const int r0 = rs == 0 ? 0 : s.nu, nr = rs == 0 ? s.nu : s.nd;
+    const int c0 = cs == 0 ? 0 : s.nu, nc = cs == 0 ? s.nu : s.nd;
+    if (!out) return hipSuccess;
+    if (nr == 0 || nc == 0) return hipMemsetAsync(out, 0, sizeof(double) * L * L * w.Wk, st);
+    GemmArgs g = gemm_args(nr, s.Lp, nc);
+    g.A = w.A + (long)r0 * n + c0; g.lda = n; g.a_bs = n * n;
+    g.B = phi + (long)c0 * s.Lp; g.ldb = s.Lp; g.b_bs = rowst;
+    g.C = w.pfT; g.ldc = s.Lp; g.c_bs = rowst;
+    g.batch = w.Wk;
+    hipError_t e = gemm_f64(g, false, false, false, st);
+    if (e != hipSuccess) return e;
+    GemmArgs h = gemm_args((int)L, (int)L, nr);
+    h.A = phi + (long)r0 * s.Lp; h.lda = s.Lp; h.a_bs = rowst;   // stored [i][mu]: op = A^T
+    h.B = w.pfT; h.ldb = s.Lp; h.b_bs = rowst;
+    h.C = out; h.ldc = L; h.c_bs = L * L;
+    h.batch = w.Wk;
+    e = gemm_f64(h, true, false, false, st);
+    if (e != hipSuccess) return e;
+    const long tot = (long)w.Wk * L * L;
+    hipLaunchKernelGGL(pf_scale_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, out, tot, scale);
+    return hipGetLastError();
+  };
+  hipError_t e = pair(0, 0, d_uu, -0.5);
+  if (e == hipSuccess) e = pair(1, 1, d_dd, -0.5);
+  if (e == hipSuccess) e = pair(0, 1, d_ud, -1.0);
+  if (e != hipSuccess || s.pk == 0) return e;
+  // unpaired orbitals: out_s[mu][l] = sum_{i of s} (G~^{-1})_{N+l, i} psi_mu(r_i)
+  for (int sp = 0; sp < 2; ++sp) {
+    double* out = sp == 0 ? d_uup : d_udn;
+    const int r0 = sp == 0 ? 0 : s.nu, nr = sp == 0 ? s.nu : s.nd;
+    if (!out) continue;
+    if (nr == 0) {
+      e = hipMemsetAsync(out, 0, sizeof(double) * L * s.pk * w.Wk, st);
+      if (e != hipSuccess) return e;
+      continue;
+    }
+    GemmArgs g = gemm_args((int)L, s.pk, nr);
+    g.A = phi + (long)r0 * s.Lp; g.lda = s.Lp; g.a_bs = rowst;   // op = Phi_s^T
+    g.B = w.A + (long)s.N * n + r0; g.ldb = n; g.b_bs = n * n;   // stored [l][i]: op = (.)^T
+    g.C = out; g.ldc = s.pk; g.c_bs = L * s.pk;
+    g.batch = w.Wk;
+    e = gemm_f64(g, true, true, false, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 }  // namespace qmc

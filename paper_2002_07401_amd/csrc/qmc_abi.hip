@@ -508,6 +508,7 @@ extern "C" qmc_status qmc_walkers_create(qmc_system* sys, int32_t n_walkers, qmc
   if (s.pairing) {
     al((void**)&d.Bd, sizeof(double) * Wk * N * Lp);
     al((void**)&d.pfB, sizeof(double) * Wk * 2 * Lp);
+    al((void**)&d.pfT, sizeof(double) * Wk * N * Lp);
   }
   al((void**)&wk->lr.ratio, sizeof(double) * Wk * N * kHops);
   al((void**)&wk->lr.ah, sizeof(double) * Wk * N);
@@ -987,6 +988,19 @@ extern "C" qmc_status qmc_jastrow_basis_logderiv(qmc_system* sys, qmc_walkers* w
   if (wk->generation != sys->generation) return fail(QMC_ERR_STATE, "parameters changed since the last eval_batch");
   if (!d_j1_inh && !d_j3) return QMC_OK;
   HIP_TRY(launch_jastrow3_logderiv(sys->d, wk->d, d_j1_inh, d_j3, stream), "Jastrow-basis log-derivatives");
+  return QMC_OK;
+}
+
+extern "C" qmc_status qmc_pfaffian_logderiv(qmc_system* sys, qmc_walkers* wk, double* d_uu, double* d_dd,
+                                            double* d_ud, double* d_unpaired_up, double* d_unpaired_dn,
+                                            hipStream_t stream) {
+  qmc_status c = check_pair(sys, wk);
+  if (c) return c;
+  if (!sys->d.pairing) return fail(QMC_ERR_ARG, "the system is not a Pfaffian");
+  if (!wk->evaluated) return fail(QMC_ERR_STATE, "log-derivatives before eval_batch");
+  if (wk->generation != sys->generation) return fail(QMC_ERR_STATE, "parameters changed since the last eval_batch");
+  HIP_TRY(launch_pf_logderiv(sys->d, wk->d, d_uu, d_dd, d_ud, d_unpaired_up, d_unpaired_dn, stream),
+          "Pfaffian log-derivatives");
   return QMC_OK;
 }
 

@@ -189,3 +189,46 @@ def test_pfaffian_refusals(fw):
     with pytest.raises(P.QMCError) as ex:
         P.JAGPSystem(dataclasses.replace(s, pf_uu=bad))
     assert ex.value.code == -1
+
+
+def _oracle_pf_logderiv(sy, r):
+    """Per-walker autodiff of log|Psi| with respect to the pairing blocks and
+    unpaired orbitals (same-spin blocks projected on skew-symmetric matrices)."""
+    out = {k: [] for k in ("uu", "dd", "ud", "unpaired_up", "unpaired_dn")}
+    for w in range(r.shape[0]):
+        ps = [sy.pf_uu, sy.pf_dd, sy.lam, sy.unpaired, sy.unpaired_dn]
+        ps = [p.detach().clone().requires_grad_(True) for p in ps]
+        sw = dataclasses.replace(sy, pf_uu=ps[0], pf_dd=ps[1], lam=ps[2], unpaired=ps[3], unpaired_dn=ps[4])
+        # log|Pf| = 1/2 log|det G~| (pinned in the oracle tests), differentiable
+        G = PF.pairing_matrix(sw, O.agp_basis(sw, r[w:w + 1])[0])
+        lp = 0.5 * torch.linalg.slogdet(G)[1]
+        g = torch.autograd.grad(lp.sum(), ps)
+        out["uu"].append(0.5 * (g[0] - g[0].T))
+        out["dd"].append(0.5 * (g[1] - g[1].T))
+        out["ud"].append(g[2])
+        out["unpaired_up"].append(g[3])
+        out["unpaired_dn"].append(g[4])
+    return {k: torch.stack(v) for k, v in out.items()}
+
+
+def test_pfaffian_logderiv_matches_oracle(fw):
+    P = need_gpu()
+    _, wk, r, _ = _eval(P, fw.system, fw.r0, 6)
+    sy = O.from_workload_system(fw.system)
+    got = wk.pfaffian_logderiv()
+    torch.cuda.synchronize()
+    ref = _oracle_pf_logderiv(sy, r)
+    for k, b in ref.items():
+        a = got[k].cpu()
+        err = ((a - b).abs().max() / b.abs().max()).item()
+        print(f"[pfaffian logderiv] {k}: {err:.3e}")
+        assert err <= 1e-10, (k, err)
+    # after moves: the maintained inverse and basis rows
+    disp, unif = torch.tensor(fw.disp[:30, :6]).contiguous(), torch.tensor(fw.unif[:30, :6]).contiguous()
+    wk.vmc_steps(0, disp.cuda(), unif.cuda())
+    got = wk.pfaffian_logderiv()
+    rg = wk.read(P.STATE_R).cpu()
+    torch.cuda.synchronize()
+    ref = _oracle_pf_logderiv(sy, rg)
+    for k, b in ref.items():
+        assert ((got[k].cpu() - b).abs().max() / b.abs().max()).item() <= 1e-8, k
