@@ -163,6 +163,33 @@ def test_polarized_forces_match_oracle(pw):
         assert (a - b).abs().max().item() / max(1.0, b.abs().max().item()) <= 1e-8, k
 
 
+def test_fully_polarized_determinant():
+    # n_dn = 0: W = Phi_up U, a Slater determinant of the k = n_up unpaired orbitals
+    P = need_gpu()
+    w = C.tiny_3nuc_10e(n_walkers=8, n_steps=60)
+    L_ = len(w.system.lam)
+    rng = np.random.default_rng(3)
+    s = dataclasses.replace(w.system, n_up=4, n_dn=0, unpaired=rng.standard_normal((L_, 4)) / np.sqrt(L_))
+    r0 = C.random_positions(5, s, 8)
+    _, wk, r, out = _eval(P, s, r0, 8)
+    sy = O.from_workload_system(s)
+    _check_eval(out, O.evaluate(sy, r), "n_dn = 0")
+    disp = torch.tensor(w.disp[:60, :8, :]).contiguous()
+    unif = torch.tensor(w.unif[:60, :8]).contiguous()
+    wk.vmc_steps(0, disp.cuda(), unif.cuda())
+    rg = wk.read(P.STATE_R).cpu()
+    torch.cuda.synchronize()
+    rf, _, _ = O.run_chain(sy, r, disp, unif)
+    assert torch.equal(rg, rf)
+    one = torch.ones(8, dtype=torch.float64, device="cuda")
+    g = wk.forces(rf.cuda(), one, one)
+    torch.cuda.synchronize()
+    ref = O.forces_vjp(sy, rf, torch.ones(8, dtype=torch.float64), torch.ones(8, dtype=torch.float64))
+    for k in ("R", "zeta", "jas", "r"):
+        a, b = g[k].cpu(), ref[k]
+        assert (a - b).abs().max().item() / max(1.0, b.abs().max().item()) <= 1e-8, k
+
+
 def test_polarized_refusals(pw):
     P = need_gpu()
     sysh, wk, r, _ = _eval(P, pw.system, pw.r0, 4)
