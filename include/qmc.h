@@ -124,8 +124,10 @@ typedef struct {
    * the geminal is built from phi_c = sum_t con_coef[t] psi_{con_idx[t]} over
    * t in [con_ptr[c], con_ptr[c+1]), c < Lc; lambda is then [Lc][Lc] and every
    * [L] of the calls below that refers to orbitals (Phi rows) reads Lc.
-   * L <= 2048 primitives.  Not supported with it: qmc_forces, qmc_multi_*,
-   * exponents or nuclei changed through qmc_system_set_params. */
+   * L <= 2048 primitives.  qmc_forces returns the gradients with respect to the
+   * primitives' exponents and Lambda over the contracted orbitals (not with
+   * respect to con_coef).  Not supported with it: qmc_multi_*, exponents or
+   * nuclei changed through qmc_system_set_params. */
   int32_t n_contracted;       /* Lc (0: the basis functions are the orbitals)    */
   const int32_t *con_ptr;     /* [Lc + 1], con_ptr[0] = 0, non-decreasing        */
   const int32_t *con_idx;     /* [con_ptr[Lc]] primitive index, 0 .. L-1         */
@@ -237,7 +239,7 @@ qmc_status qmc_vmc_steps(qmc_system *sys, qmc_walkers *wk, int32_t e_start, int3
  * n_jas = n_nuc (one-body b per nucleus) + n_j2 (two-body parameters). */
 typedef struct {
   double *dR;       /* [A][3] summed over walkers, or [Wk][A][3] per walker      */
-  double *dzeta;    /* [L] or [Wk][L]                                            */
+  double *dzeta;    /* [n_basis] or [Wk][n_basis] (the primitives' exponents)    */
   double *dlambda;  /* [L][L] or [Wk][L][L]: d/dLambda[mu][nu], every entry
                        independent (the caller applies any symmetry constraint) */
   double *djas;     /* [n_jas] or [Wk][n_jas]                                    */

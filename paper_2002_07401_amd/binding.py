@@ -210,6 +210,7 @@ class JAGPSystem:
         self.n_nuc = len(s.Z)
         self.n_jas = len(s.Z) + len(s.j2)
         self.LJ = LJ
+        self.n_basis = len(s.zeta)
         self.pairing = pf
         self.npf = s.n_up + s.n_dn + k_pf if pf else 0
 
@@ -319,9 +320,9 @@ class Walkers:
         Wk, N, A, L, nj = self.n, S.n_elec, S.n_nuc, S.L, S.n_jas
         f = lambda *sh: torch.empty(*sh, dtype=torch.float64, device=r.device)
         if per_walker:
-            out = dict(R=f(Wk, A, 3), zeta=f(Wk, L), lam=f(Wk, L, L), jas=f(Wk, nj), r=f(Wk, N, 3))
+            out = dict(R=f(Wk, A, 3), zeta=f(Wk, S.n_basis), lam=f(Wk, L, L), jas=f(Wk, nj), r=f(Wk, N, 3))
         else:
-            out = dict(R=f(A, 3), zeta=f(L), lam=f(L, L), jas=f(nj), r=f(Wk, N, 3))
+            out = dict(R=f(A, 3), zeta=f(S.n_basis), lam=f(L, L), jas=f(nj), r=f(Wk, N, 3))
         g = Grads(dR=_ptr(out["R"]), dzeta=_ptr(out["zeta"]), dlambda=_ptr(out["lam"]),
                   djas=_ptr(out["jas"]), dr=_ptr(out["r"]))
         _check(load().qmc_forces(S.h, self.h, _ptr(r), 1 if per_walker else 0, _ptr(gbar_logpsi),

@@ -134,13 +134,33 @@ __global__ void __launch_bounds__(256) stack_basis_kernel(SysDev s, WalkDev w, d
   for (int mu = threadIdx.x; mu < s.Lp; mu += blockDim.x) {
     double v = 0.0, q = 0.0;
     if (mu < s.L) {
-      double bx, by, bz, lp;
-      basis_vgl(s, mu, px, py, pz, v, bx, by, bz, lp);
+      double bx = 0.0, by = 0.0, bz = 0.0, lp = 0.0;
+      if (s.Lq) {   // contracted orbital: the same combination of the primitives' values and derivatives
+        for (int k = s.con_ptr[mu]; k < s.con_ptr[mu + 1]; ++k) {
+          double pv, px_, py_, pz_, pl;
+          basis_vgl(s, s.con_idx[k], px, py, pz, pv, px_, py_, pz_, pl);
+          const double cf = s.con_coef[k];
+          v += cf * pv; bx += cf * px_; by += cf * py_; bz += cf * pz_; lp += cf * pl;
+        }
+      } else {
+        basis_vgl(s, mu, px, py, pz, v, bx, by, bz, lp);
+      }
       q = lp + 2.0 * (bx * gx + by * gy + bz * gz);
     }
     dphi[mu] = v;
     dq[mu] = q;
   }
+}
+
+// Contracted orbitals: rows over the orbitals (dF/dPhi, Yt) as rows over the
+// primitives, out[mu] = sum_c C[mu][c] in[c] (zero past Lq), so that the basis
+// backward runs over the primitives.
+__global__ void __launch_bounds__(256) prim_rows_kernel(SysDev s, const double* __restrict__ in, int lq_pad,
+                                                        double* __restrict__ out) {
+  const long row = blockIdx.x;
+  const double* y = in + row * s.Lp;
+  double* o = out + row * lq_pad;
+  for (int mu = threadIdx.x; mu < lq_pad; mu += blockDim.x) o[mu] = mu < s.Lq ? prim_weight(s, mu, y) : 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -543,10 +563,25 @@ hipError_t launch_forces(const SysDev& s, const WalkDev& w, const AdjWork& aw, c
       HT(sum_rows(aw.lam_part, nfull + (rest ? 1 : 0), (long)L * L, dlambda, st));
     }
   }
-  // 8. basis and Jastrow/Coulomb backward
+  // 8. basis and Jastrow/Coulomb backward (over the primitives of a contracted basis)
   double* drw = dr ? dr : aw.dr;
-  hipLaunchKernelGGL(basis_backward_kernel, dim3(Wk), dim3(256), 0, st, s, w, aw.PB, gb, drw, aw.Rbar,
-                     aw.zbar, aw.tmu);
+  if (s.Lq) {
+    const int lqp = (s.Lq + 31) / 32 * 32;
+    const unsigned rows = (unsigned)((long)Wk * N);
+    hipLaunchKernelGGL(prim_rows_kernel, dim3(rows), dim3(256), 0, st, s, aw.PB, lqp, aw.PBq);
+    HT(hipGetLastError());
+    hipLaunchKernelGGL(prim_rows_kernel, dim3(rows), dim3(256), 0, st, s, w.Yt, lqp, aw.Ytq);
+    HT(hipGetLastError());
+    SysDev sq = s;
+    sq.L = s.Lq; sq.Lp = lqp; sq.Lq = 0;
+    WalkDev wq = w;
+    wq.Yt = aw.Ytq;
+    hipLaunchKernelGGL(basis_backward_kernel, dim3(Wk), dim3(256), 0, st, sq, wq, aw.PBq, gb, drw, aw.Rbar,
+                       aw.zbar, aw.tmu);
+  } else {
+    hipLaunchKernelGGL(basis_backward_kernel, dim3(Wk), dim3(256), 0, st, s, w, aw.PB, gb, drw, aw.Rbar,
+                       aw.zbar, aw.tmu);
+  }
   HT(hipGetLastError());
   hipLaunchKernelGGL(jastrow_backward_kernel, dim3(Wk), dim3(256), 0, st, s, w, ga, gb, drw, aw.Rbar, aw.jbar);
   HT(hipGetLastError());
@@ -554,11 +589,11 @@ hipError_t launch_forces(const SysDev& s, const WalkDev& w, const AdjWork& aw, c
   const int nj = s.n_nuc + (s.j2_form == 1 ? 2 : (s.j2_form == 2 ? 8 : 0));
   if (per_walker) {
     if (dR) HT(hipMemcpyAsync(dR, aw.Rbar, sizeof(double) * Wk * s.n_nuc * 3, hipMemcpyDeviceToDevice, st));
-    if (dzeta) HT(hipMemcpyAsync(dzeta, aw.zbar, sizeof(double) * Wk * L, hipMemcpyDeviceToDevice, st));
+    if (dzeta) HT(hipMemcpyAsync(dzeta, aw.zbar, sizeof(double) * Wk * s.nprim(), hipMemcpyDeviceToDevice, st));
     if (djas) HT(hipMemcpyAsync(djas, aw.jbar, sizeof(double) * Wk * nj, hipMemcpyDeviceToDevice, st));
   } else {
     if (dR) HT(sum_rows(aw.Rbar, Wk, (long)s.n_nuc * 3, dR, st));
-    if (dzeta) HT(sum_rows(aw.zbar, Wk, L, dzeta, st));
+    if (dzeta) HT(sum_rows(aw.zbar, Wk, s.nprim(), dzeta, st));
     if (djas) HT(sum_rows(aw.jbar, Wk, nj, djas, st));
   }
   return hipSuccess;

@@ -210,12 +210,14 @@ struct AdjWork {
   double* XZ;       // [Wk][2n][Lp]  [X_U ; Z_U]
   double* XD;       // [Wk][n][Lp]
   double* PB;       // [Wk][N][Lp]   dF/dPhi
-  double* tmu;      // [Wk][L][3]
+  double* tmu;      // [Wk][L or Lq][3]
   double* Rbar;     // [Wk][A][3]
-  double* zbar;     // [Wk][L]
+  double* zbar;     // [Wk][L or Lq]
   double* jbar;     // [Wk][A + n_j2]
   double* dr;       // [Wk][N][3]    used when the caller passes no dr
   double* lam_part; // [chunks][L][L]
+  double* PBq;      // [Wk][N][Lq pad 32] dF/dPhi over the primitives (contracted orbitals)
+  double* Ytq;      // [Wk][N][Lq pad 32] Yt over the primitives
   int chunk_walkers;
   int chunks;
 };

@@ -875,9 +875,15 @@ static hipError_t alloc_adjoint(qmc_walkers* wk) {
   al(&a.XZ, Wk * 2 * n * Lp);
   al(&a.XD, Wk * n * Lp);
   al(&a.PB, Wk * N * Lp);
-  al(&a.tmu, Wk * L * 3);
+  const size_t Lb = s.Lq ? (size_t)s.Lq : L;   // basis functions (primitives of a contracted basis)
+  al(&a.tmu, Wk * Lb * 3);
   al(&a.Rbar, Wk * A * 3);
-  al(&a.zbar, Wk * L);
+  al(&a.zbar, Wk * Lb);
+  if (s.Lq) {
+    const size_t lqp = (s.Lq + 31) / 32 * 32;
+    al(&a.PBq, Wk * N * lqp);
+    al(&a.Ytq, Wk * N * lqp);
+  }
   al(&a.jbar, Wk * nj);
   al(&a.dr, Wk * N * 3);
   al(&a.lam_part, (size_t)a.chunks * L * L);
@@ -894,7 +900,6 @@ extern "C" qmc_status qmc_forces(qmc_system* sys, qmc_walkers* wk, const double*
   const SysDev& s = sys->d;
   if (s.precision != QMC_FP64) return fail(QMC_ERR_UNSUPPORTED, "forces are built for the FP64 path");
   if (s.LJ > 0) return fail(QMC_ERR_UNSUPPORTED, "forces with a Jastrow basis are not built");
-  if (s.Lq > 0) return fail(QMC_ERR_UNSUPPORTED, "forces with contracted orbitals are not built");
   if (s.pairing) return fail(QMC_ERR_UNSUPPORTED, "forces of the Pfaffian are not built");
   if (s.N > 2 * kLuMaxN || s.n_nuc > kMaxNucBack)
     return fail(QMC_ERR_UNSUPPORTED, "forces need N <= 256 electrons and <= 256 nuclei");

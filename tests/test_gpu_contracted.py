@@ -112,12 +112,30 @@ def test_contracted_lattice_hops(cw):
     assert rel_err(g["ratios"].cpu(), L.lattice_ratios(sy, r, a_i)).max().item() <= 1e-10
 
 
+def test_contracted_forces_match_oracle(cw):
+    # the adjoint over contracted orbitals: orbital-level products, then the
+    # basis backward over the primitives (exponent gradients per primitive)
+    P = need_gpu()
+    Wk = 6
+    _, wk, r, _ = _eval(P, cw.system, cw.r0, Wk)
+    sy = O.from_workload_system(cw.system)
+    rng = np.random.default_rng(9)
+    gl = torch.tensor(rng.normal(size=Wk))
+    ge = torch.tensor(rng.normal(size=Wk))
+    out = wk.forces(r.cuda(), gl.cuda(), ge.cuda())
+    torch.cuda.synchronize()
+    ref = O.forces_vjp(sy, r, gl, ge)
+    assert out["zeta"].shape == (60,) and out["lam"].shape == (28, 28)
+    for k in ("R", "zeta", "lam", "jas", "r"):
+        a, b = out[k].cpu(), ref[k]
+        err = (a - b).abs().max().item() / max(1.0, b.abs().max().item())
+        print(f"[contracted forces] {k}: {err:.3e}")
+        assert err <= 1e-8, (k, err)
+
+
 def test_contracted_refusals(cw):
     P = need_gpu()
     sysh, wk, r, _ = _eval(P, cw.system, cw.r0, 4)
-    with pytest.raises(P.QMCError) as ex:
-        wk.forces(r.cuda(), torch.ones(4, dtype=torch.float64, device="cuda"), None)
-    assert ex.value.code == -5
     with pytest.raises(P.QMCError) as ex:
         P.MultiSystem([wk])
     assert ex.value.code == -5
