@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define QMC_ABI_VERSION 10
+#define QMC_ABI_VERSION 11
 
 typedef enum {
   QMC_OK = 0,
@@ -109,8 +109,8 @@ typedef struct {
    *   J3/4  = sum_{i<j} sum_{k,l} chi_k(r_i) M^{s_i s_j}[k][l] chi_l(r_j)
    * Up electrons come first, so unlike-spin pairs i < j use M^{ud}; the
    * same-spin matrices must be symmetric.  n_jbasis = 0: no such terms.
-   * Not supported with them: qmc_forces, qmc_multi_*, moving nuclei
-   * through qmc_system_set_params. */
+   * Not supported with them: qmc_multi_*, moving nuclei through
+   * qmc_system_set_params. */
   int32_t n_jbasis;           /* LJ <= 1024                                      */
   const int32_t *jb_center;   /* [LJ] nucleus index                              */
   const int32_t *jb_l;        /* [LJ] 0..2                                       */
@@ -244,6 +244,13 @@ typedef struct {
                        independent (the caller applies any symmetry constraint) */
   double *djas;     /* [n_jas] or [Wk][n_jas]                                    */
   double *dr;       /* [Wk][N][3] (always per walker)                            */
+  /* Jastrow basis (n_jbasis = LJ > 0; ignored otherwise): */
+  double *dj1_inh;  /* [2][LJ] or [Wk][2][LJ]                                    */
+  double *dj3;      /* [3][LJ][LJ] or [Wk][3][LJ][LJ]: M^{uu}, M^{dd} as gradients
+                       with respect to symmetric matrices (written symmetric:
+                       dF = sum_kl D_kl dM_kl for every symmetric dM); M^{ud}
+                       every entry independent                                  */
+  double *djb_zeta; /* [LJ] or [Wk][LJ]                                          */
 } qmc_grads;
 
 /* Adjoint of the evaluation (Derivatives of energy section: logarithmic

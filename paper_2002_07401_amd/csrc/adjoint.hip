@@ -211,7 +211,7 @@ __device__ __forceinline__ void hess_P(int kind, double H[6]) {   // xx yy zz xy
 __global__ void __launch_bounds__(256)
 basis_backward_kernel(SysDev s, WalkDev w, const double* __restrict__ phibar, const double* __restrict__ gb,
                       double* __restrict__ dr, double* __restrict__ Rbar_w, double* __restrict__ zbar_w,
-                      double* __restrict__ tmu) {
+                      double* __restrict__ tmu, int acc) {
   __shared__ double rpart[4][kLuMaxN * 2][3];
   const int wk = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const double b = gb ? gb[wk] : 0.0;
@@ -289,7 +289,8 @@ basis_backward_kernel(SysDev s, WalkDev w, const double* __restrict__ phibar, co
     for (int c = 0; c < 3; ++c) {
       double t = 0.0;
       for (int q = 0; q < 4; ++q) t += rpart[q][i][c];
-      dr[((long)wk * s.N + i) * 3 + c] = t;
+      if (acc) dr[((long)wk * s.N + i) * 3 + c] += t;
+      else dr[((long)wk * s.N + i) * 3 + c] = t;
     }
   }
   // nuclear positions: dF/dR_a = - sum over the functions centred on a (CSR order)
@@ -299,7 +300,10 @@ basis_backward_kernel(SysDev s, WalkDev w, const double* __restrict__ phibar, co
       const int mu = s.cmu[k];
       for (int c = 0; c < 3; ++c) t[c] += tm[3 * mu + c];
     }
-    for (int c = 0; c < 3; ++c) Rbar_w[((long)wk * s.n_nuc + a) * 3 + c] = -t[c];
+    for (int c = 0; c < 3; ++c) {
+      if (acc) Rbar_w[((long)wk * s.n_nuc + a) * 3 + c] -= t[c];
+      else Rbar_w[((long)wk * s.n_nuc + a) * 3 + c] = -t[c];
+    }
   }
 }
 
@@ -439,6 +443,167 @@ static hipError_t sum_rows(const double* in, long n_rows, long len, double* out,
 
 // The reverse pass.  The forward state (Phi rows are recomputed here; P, A,
 // Yt, gJ, drift come from the evaluation that the caller ran just before).
+// ---------------------------------------------------------------------------
+// Jastrow-basis terms (onebody_J_inh, threebody_jastrow).  With
+// gvec_i = G_{s_i} - h_i + m_{s_i}, the terms' share of F is
+//   F_3 = sum_i sum_{j != i} u_i^T M^{s_i s_j} chi_j + sum_i (a chi_i + c_i) . m_{s_i},
+//   c_i = gbar_i . grad chi(r_i) + hbar lap chi(r_i),  u_i = a/2 chi_i + c_i,
+// gbar_i = -b drift_i, hbar = -b/2 (dF/dgrad_i J, dF/dlap_i J).  Hence
+//   dF/dchi_j      = [M3 U]_{s_j} - M^{s_j s_j} u_j + a/2 (G_{s_j} - h_j) + a m_{s_j},
+//                    U = [sum_{i up} u_i ; sum_{i down} u_i]
+//   dF/dgrad chi_j = gbar_j gvec_j,  dF/dlap chi_j = hbar gvec_j
+//   dF/dm_s        = sum_{i of s} (a chi_i + c_i)
+//   dF/dM^{ss}     = sym(U_s X_s^T - sum_{i of s} u_i chi_i^T)   (gradient w.r.t. a symmetric matrix)
+//   dF/dM^{ud}     = U_u X_d^T + X_u U_d^T,   X_s = sum_{i of s} chi_i,
+// and the basis backward over chi (with "Yt" = gvec and "g" = drift, so that
+// its gbar = 2 (-b/2 gvec) drift and hbar = -b/2 gvec) gives dF/dr, dF/dR and
+// the exponents' gradients.
+// ---------------------------------------------------------------------------
+// Per (walker, electron), one wave: U rows, gvec rows, (a chi + c) rows, drift4.
+__global__ void __launch_bounds__(256)
+j3_adj_rows_kernel(SysDev s, WalkDev w, AdjWork aw, const double* __restrict__ ga, const double* __restrict__ gb,
+                   int rows) {
+  const int lane = threadIdx.x & 63;
+  const long row = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= rows) return;
+  const int LJ = s.LJ, LJp = aw.LJp;
+  const int wk = (int)(row / s.N), i = (int)(row % s.N);
+  const int sp = i < s.nu ? 0 : 1;
+  const double a = ga ? ga[wk] : 0.0, b = gb ? gb[wk] : 0.0;
+  const double px = w.r[3 * row], py = w.r[3 * row + 1], pz = w.r[3 * row + 2];
+  const double* dft = w.drift + row * 3;
+  const double gbx = -b * dft[0], gby = -b * dft[1], gbz = -b * dft[2], hb = -0.5 * b;
+  const double* G = w.G3 + ((long)wk * 2 + sp) * LJ;
+  const double* h = w.hv + row * LJ;
+  const double* m = s.jm + (long)sp * LJ;
+  for (int k = lane; k < LJp; k += 64) {
+    double u = 0.0, gv = 0.0, ac = 0.0;
+    if (k < LJ) {
+      double v, vx, vy, vz, vl;
+      basis_vgl_tab(s.jbfn, s.jkind, k, px, py, pz, v, vx, vy, vz, vl);
+      const double c = gbx * vx + gby * vy + gbz * vz + hb * vl;
+      u = 0.5 * a * v + c;
+      ac = a * v + c;
+      gv = G[k] - h[k] + m[k];
+    }
+    aw.ju[row * LJp + k] = u;
+    aw.jgv[row * LJp + k] = gv;
+    aw.jac[row * LJp + k] = ac;
+  }
+  if (lane < 4) aw.drift4[row * 4 + lane] = lane < 3 ? dft[lane] : 0.0;
+}
+
+// Per walker: U_s, X_s, dF/dm_s and H = M3 U (LDS), then the dF/dchi rows.
+__global__ void __launch_bounds__(256) j3_adj_sum_kernel(SysDev s, WalkDev w, AdjWork aw, const double* __restrict__ ga) {
+  __shared__ double U[2 * kMaxLJ];
+  const int wk = blockIdx.x, LJ = s.LJ, LJp = aw.LJp;
+  const double a = ga ? ga[wk] : 0.0;
+  const double* u = aw.ju + (long)wk * s.N * LJp;
+  const double* ac = aw.jac + (long)wk * s.N * LJp;
+  const double* chi = w.chi + (long)wk * s.N * LJ;
+  double* X = aw.jX + (long)wk * 4 * LJ;   // X_u, X_d, U_u, U_d
+  for (int k = threadIdx.x; k < LJ; k += blockDim.x) {
+    double uu = 0.0, ud = 0.0, xu = 0.0, xd = 0.0, mu_ = 0.0, md = 0.0;
+    for (int i = 0; i < s.nu; ++i) { uu += u[(long)i * LJp + k]; xu += chi[(long)i * LJ + k]; mu_ += ac[(long)i * LJp + k]; }
+    for (int i = s.nu; i < s.N; ++i) { ud += u[(long)i * LJp + k]; xd += chi[(long)i * LJ + k]; md += ac[(long)i * LJp + k]; }
+    U[k] = uu; U[LJ + k] = ud;
+    X[k] = xu; X[LJ + k] = xd; X[2 * LJ + k] = uu; X[3 * LJ + k] = ud;
+    aw.jdm[(long)wk * 2 * LJ + k] = mu_;
+    aw.jdm[(long)wk * 2 * LJ + LJ + k] = md;
+  }
+  __syncthreads();
+  double* Hs = aw.jH + (long)wk * 2 * LJ;
+  for (int o = threadIdx.x; o < 2 * LJ; o += blockDim.x) {
+    const double* row = s.M3 + (long)o * 2 * LJ;
+    double g = 0.0;
+    for (int c = 0; c < 2 * LJ; ++c) g += row[c] * U[c];
+    Hs[o] = g;
+  }
+  (void)a;
+}
+
+// dF/dchi rows: [M3 U]_s - (M^{ss} u_j) + a/2 (G_s - h_j) + a m_s   (hu holds M^{ss} u_j)
+__global__ void __launch_bounds__(256) j3_adj_chibar_kernel(SysDev s, WalkDev w, AdjWork aw,
+                                                            const double* __restrict__ ga, long total) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int LJ = s.LJ, LJp = aw.LJp;
+  const long row = idx / LJp;
+  const int k = (int)(idx % LJp);
+  if (k >= LJ) { aw.jpb[idx] = 0.0; return; }
+  const int wk = (int)(row / s.N), i = (int)(row % s.N), sp = i < s.nu ? 0 : 1;
+  const double a = ga ? ga[wk] : 0.0;
+  const double H = aw.jH[((long)wk * 2 + sp) * LJ + k];
+  const double G = w.G3[((long)wk * 2 + sp) * LJ + k];
+  const double h = w.hv[row * LJ + k];
+  aw.jpb[idx] = H - aw.jhu[idx] + 0.5 * a * (G - h) + a * s.jm[(long)sp * LJ + k];
+}
+
+// dF/dM: the slots hold sum_{i of s} u_i chi_i^T (same-spin) on entry
+__global__ void __launch_bounds__(256) j3_adj_dM_kernel(SysDev s, AdjWork aw, int Wk) {
+  const int LJ = s.LJ;
+  const long LL = (long)LJ * LJ;
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)Wk * LL) return;
+  const int wk = (int)(idx / LL);
+  const long e = idx % LL;
+  const int k = (int)(e / LJ), l = (int)(e % LJ);
+  const double* X = aw.jX + (long)wk * 4 * LJ;   // X_u, X_d, U_u, U_d
+  const double* Xu = X, *Xd = X + LJ, *Uu = X + 2 * LJ, *Ud = X + 3 * LJ;
+  double* D = aw.jdM + (long)wk * 3 * LL;
+  const double* Cw = aw.jC + (long)wk * 2 * LL;   // sum u chi^T per spin
+  // symmetric parts: 1/2 (raw_kl + raw_lk)
+  D[e] = 0.5 * ((Uu[k] * Xu[l] - Cw[(long)k * LJ + l]) + (Uu[l] * Xu[k] - Cw[(long)l * LJ + k]));
+  D[LL + e] = 0.5 * ((Ud[k] * Xd[l] - Cw[LL + (long)k * LJ + l]) + (Ud[l] * Xd[k] - Cw[LL + (long)l * LJ + k]));
+  D[2 * LL + e] = Uu[k] * Xd[l] + Xu[k] * Ud[l];
+}
+
+static hipError_t launch_jastrow3_backward(const SysDev& s, const WalkDev& w, const AdjWork& aw, const double* ga,
+                                           const double* gb, double* drw, hipStream_t st) {
+  const int LJ = s.LJ, LJp = aw.LJp, Wk = w.Wk;
+  const long rows = (long)Wk * s.N;
+  hipLaunchKernelGGL(j3_adj_rows_kernel, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, s, w, aw, ga, gb,
+                     (int)rows);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(j3_adj_sum_kernel, dim3(Wk), dim3(256), 0, st, s, w, aw, ga);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  for (int sp = 0; sp < 2; ++sp) {
+    const int row0 = sp == 0 ? 0 : s.nu, nrow = sp == 0 ? s.nu : s.nd;
+    if (nrow == 0) continue;
+    // hu = u_j M^{ss} (M^{ss} symmetric) for the electrons of spin s
+    GemmArgs g = gemm_args(nrow, LJ, LJ);
+    g.A = aw.ju + (long)row0 * LJp; g.lda = LJp; g.a_bs = (long)s.N * LJp;
+    g.B = s.M3 + (long)sp * LJ * 2 * LJ + (long)sp * LJ; g.ldb = 2 * LJ; g.b_bs = 0;
+    g.C = aw.jhu + (long)row0 * LJp; g.ldc = LJp; g.c_bs = (long)s.N * LJp;
+    g.batch = Wk;
+    if ((e = gemm_f64(g, false, false, false, st)) != hipSuccess) return e;
+    // C_s = sum_{i of s} u_i chi_i^T  ([LJ][LJ] per walker)
+    GemmArgs c = gemm_args(LJ, LJ, nrow);
+    c.A = aw.ju + (long)row0 * LJp; c.lda = LJp; c.a_bs = (long)s.N * LJp;   // op = A^T
+    c.B = w.chi + (long)row0 * LJ; c.ldb = LJ; c.b_bs = (long)s.N * LJ;
+    c.C = aw.jC + (long)sp * LJ * LJ; c.ldc = LJ; c.c_bs = 2L * LJ * LJ;
+    c.batch = Wk;
+    if ((e = gemm_f64(c, true, false, false, st)) != hipSuccess) return e;
+  }
+  const long tot = rows * LJp;
+  hipLaunchKernelGGL(j3_adj_chibar_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, s, w, aw, ga, tot);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const long tm = (long)Wk * LJ * LJ;
+  hipLaunchKernelGGL(j3_adj_dM_kernel, dim3((unsigned)((tm + 255) / 256)), dim3(256), 0, st, s, aw, Wk);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // the chi basis backward: functions = the Jastrow basis, "Yt" = gvec, "g" = drift
+  SysDev sj = s;
+  sj.L = LJ; sj.Lp = LJp; sj.Lq = 0;
+  sj.bfn = s.jbfn; sj.kind = s.jkind; sj.center = s.jcenter; sj.cptr = s.jcptr; sj.cmu = s.jcmu;
+  WalkDev wj = w;
+  wj.Yt = aw.jgv;
+  wj.gJ = aw.drift4;
+  hipLaunchKernelGGL(basis_backward_kernel, dim3(Wk), dim3(256), 0, st, sj, wj, aw.jpb, gb, drw, aw.Rbar,
+                     aw.jzbar, aw.jtmu, 1);
+  return hipGetLastError();
+}
+
 // Zero fill (the down stacks' rows past n_dn when there are unpaired orbitals).
 __global__ void __launch_bounds__(256) zero_fill_kernel(double* __restrict__ x, long n) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -452,7 +617,8 @@ __global__ void __launch_bounds__(256) zero_fill_kernel(double* __restrict__ x, 
 // dF/dPhi_U, and their share of dF/dQ_U is already in Yt_U.
 hipError_t launch_forces(const SysDev& s, const WalkDev& w, const AdjWork& aw, const double* ga,
                          const double* gb, int per_walker, double* dR, double* dzeta, double* dlambda,
-                         double* djas, double* dr, hipStream_t st) {
+                         double* djas, double* dr, double* dj1_inh, double* dj3, double* djb_zeta,
+                         hipStream_t st) {
   const int n = s.nu, nd = s.nd, Wk = w.Wk, Lp = s.Lp, L = s.L, N = s.N;
   const long rowst = (long)N * Lp, stk = 2L * n * Lp;
   // 1. stacked rows [Phi_U; Q_U], [Phi_D; Q_D]
@@ -577,12 +743,13 @@ hipError_t launch_forces(const SysDev& s, const WalkDev& w, const AdjWork& aw, c
     WalkDev wq = w;
     wq.Yt = aw.Ytq;
     hipLaunchKernelGGL(basis_backward_kernel, dim3(Wk), dim3(256), 0, st, sq, wq, aw.PBq, gb, drw, aw.Rbar,
-                       aw.zbar, aw.tmu);
+                       aw.zbar, aw.tmu, 0);
   } else {
     hipLaunchKernelGGL(basis_backward_kernel, dim3(Wk), dim3(256), 0, st, s, w, aw.PB, gb, drw, aw.Rbar,
-                       aw.zbar, aw.tmu);
+                       aw.zbar, aw.tmu, 0);
   }
   HT(hipGetLastError());
+  if (s.LJ) HT(launch_jastrow3_backward(s, w, aw, ga, gb, drw, st));
   hipLaunchKernelGGL(jastrow_backward_kernel, dim3(Wk), dim3(256), 0, st, s, w, ga, gb, drw, aw.Rbar, aw.jbar);
   HT(hipGetLastError());
   // 9. outputs
@@ -591,10 +758,22 @@ hipError_t launch_forces(const SysDev& s, const WalkDev& w, const AdjWork& aw, c
     if (dR) HT(hipMemcpyAsync(dR, aw.Rbar, sizeof(double) * Wk * s.n_nuc * 3, hipMemcpyDeviceToDevice, st));
     if (dzeta) HT(hipMemcpyAsync(dzeta, aw.zbar, sizeof(double) * Wk * s.nprim(), hipMemcpyDeviceToDevice, st));
     if (djas) HT(hipMemcpyAsync(djas, aw.jbar, sizeof(double) * Wk * nj, hipMemcpyDeviceToDevice, st));
+    if (s.LJ) {
+      const size_t LJ = s.LJ;
+      if (dj1_inh) HT(hipMemcpyAsync(dj1_inh, aw.jdm, sizeof(double) * Wk * 2 * LJ, hipMemcpyDeviceToDevice, st));
+      if (dj3) HT(hipMemcpyAsync(dj3, aw.jdM, sizeof(double) * Wk * 3 * LJ * LJ, hipMemcpyDeviceToDevice, st));
+      if (djb_zeta) HT(hipMemcpyAsync(djb_zeta, aw.jzbar, sizeof(double) * Wk * LJ, hipMemcpyDeviceToDevice, st));
+    }
   } else {
     if (dR) HT(sum_rows(aw.Rbar, Wk, (long)s.n_nuc * 3, dR, st));
     if (dzeta) HT(sum_rows(aw.zbar, Wk, s.nprim(), dzeta, st));
     if (djas) HT(sum_rows(aw.jbar, Wk, nj, djas, st));
+    if (s.LJ) {
+      const long LJ = s.LJ;
+      if (dj1_inh) HT(sum_rows(aw.jdm, Wk, 2 * LJ, dj1_inh, st));
+      if (dj3) HT(sum_rows(aw.jdM, Wk, 3 * LJ * LJ, dj3, st));
+      if (djb_zeta) HT(sum_rows(aw.jzbar, Wk, LJ, djb_zeta, st));
+    }
   }
   return hipSuccess;
 }

@@ -97,6 +97,9 @@ struct SysDev {
   int* jkind;       // [LJ] as kind
   double* jm;       // [2][LJ] one-body inhomogeneous coefficients, up then down
   double* M3;       // [2LJ][2LJ] [[M_uu, M_ud], [M_ud^T, M_dd]] (symmetric)
+  int* jcenter;     // [LJ] nucleus of each Jastrow-basis function
+  int* jcptr;       // [A+1] Jastrow-basis functions of nucleus a: jcmu[jcptr[a] .. jcptr[a+1])
+  int* jcmu;        // [LJ]
   // Contracted orbitals (Lq > 0): center, kind, zeta and bfn then describe Lq
   // primitives and orbital c < L is sum_t con_coef[t] psi_{con_idx[t]},
   // t in [con_ptr[c], con_ptr[c+1]); pri_* hold the same matrix by primitive
@@ -218,6 +221,12 @@ struct AdjWork {
   double* lam_part; // [chunks][L][L]
   double* PBq;      // [Wk][N][Lq pad 32] dF/dPhi over the primitives (contracted orbitals)
   double* Ytq;      // [Wk][N][Lq pad 32] Yt over the primitives
+  // Jastrow basis (LJ > 0): rows [Wk][N][LJp] of u, gvec, a chi + c, dF/dchi and
+  // M^{ss} u; per walker X_s, U_s [4][LJ], M3 U [2][LJ], dF/dm [2][LJ],
+  // sum u chi^T [2][LJ][LJ], dF/dM [3][LJ][LJ], exponent gradients [LJ] and
+  // per-function position sums [LJ][3]; drift as 4-vectors [Wk][N][4]
+  int LJp;
+  double *ju, *jgv, *jac, *jpb, *jhu, *jX, *jH, *jdm, *jC, *jdM, *jzbar, *jtmu, *drift4;
   int chunk_walkers;
   int chunks;
 };
@@ -244,7 +253,8 @@ hipError_t launch_philox_draws(unsigned long long seed, int member, int Wk, unsi
 
 hipError_t launch_forces(const SysDev& s, const WalkDev& w, const AdjWork& aw, const double* ga,
                          const double* gb, int per_walker, double* dR, double* dzeta, double* dlambda,
-                         double* djas, double* dr, hipStream_t st);
+                         double* djas, double* dr, double* dj1_inh, double* dj3, double* djb_zeta,
+                         hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // device helpers

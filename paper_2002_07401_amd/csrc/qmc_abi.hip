@@ -292,6 +292,14 @@ extern "C" qmc_status qmc_system_create(const qmc_system_desc* desc, qmc_system*
     if (!e) e = up((void**)&d.jkind, jkind.data(), sizeof(int) * jkind.size());
     if (!e) e = up((void**)&d.jm, jm.data(), sizeof(double) * jm.size());
     if (!e) e = up((void**)&d.M3, M3.data(), sizeof(double) * M3.size());
+    std::vector<int> jc(LJ), jptr(q.n_nuc + 1, 0), jmu(LJ);
+    for (int k = 0; k < LJ; ++k) { jc[k] = q.jb_center[k]; jptr[jc[k] + 1]++; }
+    for (int a = 0; a < q.n_nuc; ++a) jptr[a + 1] += jptr[a];
+    std::vector<int> fill(jptr.begin(), jptr.end() - 1);
+    for (int k = 0; k < LJ; ++k) jmu[fill[jc[k]]++] = k;
+    if (!e) e = up((void**)&d.jcenter, jc.data(), sizeof(int) * LJ);
+    if (!e) e = up((void**)&d.jcptr, jptr.data(), sizeof(int) * jptr.size());
+    if (!e) e = up((void**)&d.jcmu, jmu.data(), sizeof(int) * LJ);
   }
   d.Lq = Lc > 0 ? Lb : 0;
   if (!e && Lc > 0) {
@@ -884,6 +892,23 @@ static hipError_t alloc_adjoint(qmc_walkers* wk) {
     al(&a.PBq, Wk * N * lqp);
     al(&a.Ytq, Wk * N * lqp);
   }
+  if (s.LJ) {
+    const size_t LJ = s.LJ, LJp = (LJ + 31) / 32 * 32;
+    a.LJp = (int)LJp;
+    al(&a.ju, Wk * N * LJp);
+    al(&a.jgv, Wk * N * LJp);
+    al(&a.jac, Wk * N * LJp);
+    al(&a.jpb, Wk * N * LJp);
+    al(&a.jhu, Wk * N * LJp);
+    al(&a.jX, Wk * 4 * LJ);
+    al(&a.jH, Wk * 2 * LJ);
+    al(&a.jdm, Wk * 2 * LJ);
+    al(&a.jC, Wk * 2 * LJ * LJ);
+    al(&a.jdM, Wk * 3 * LJ * LJ);
+    al(&a.jzbar, Wk * LJ);
+    al(&a.jtmu, Wk * LJ * 3);
+    al(&a.drift4, Wk * N * 4);
+  }
   al(&a.jbar, Wk * nj);
   al(&a.dr, Wk * N * 3);
   al(&a.lam_part, (size_t)a.chunks * L * L);
@@ -899,7 +924,6 @@ extern "C" qmc_status qmc_forces(qmc_system* sys, qmc_walkers* wk, const double*
   if (!r || !out) return fail(QMC_ERR_ARG, "null positions or output block");
   const SysDev& s = sys->d;
   if (s.precision != QMC_FP64) return fail(QMC_ERR_UNSUPPORTED, "forces are built for the FP64 path");
-  if (s.LJ > 0) return fail(QMC_ERR_UNSUPPORTED, "forces with a Jastrow basis are not built");
   if (s.pairing) return fail(QMC_ERR_UNSUPPORTED, "forces of the Pfaffian are not built");
   if (s.N > 2 * kLuMaxN || s.n_nuc > kMaxNucBack)
     return fail(QMC_ERR_UNSUPPORTED, "forces need N <= 256 electrons and <= 256 nuclei");
@@ -909,7 +933,8 @@ extern "C" qmc_status qmc_forces(qmc_system* sys, qmc_walkers* wk, const double*
   c = qmc_eval_batch(sys, wk, r, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, stream);
   if (c) return c;
   HIP_TRY(launch_forces(s, wk->d, wk->aw, gbar_logpsi, gbar_eloc, per_walker, out->dR, out->dzeta,
-                        out->dlambda, out->djas, out->dr, stream), "forces");
+                        out->dlambda, out->djas, out->dr, s.LJ ? out->dj1_inh : nullptr, s.LJ ? out->dj3 : nullptr,
+                        s.LJ ? out->djb_zeta : nullptr, stream), "forces");
   return QMC_OK;
 }
 

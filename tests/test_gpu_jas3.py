@@ -105,12 +105,53 @@ def test_jas3_lattice_hops(jw):
     assert rel_err(g["ratios"].cpu(), L.lattice_ratios(sy, r, a_i)).max().item() <= 1e-10
 
 
+def _oracle_j3_param_grads(sy, r, gl, ge):
+    """Autodiff of sum_w (gl log|Psi| + ge e_L) with respect to the Jastrow-basis
+    coefficients and exponents (same-spin blocks symmetrised)."""
+    j1 = sy.j1_inh.detach().clone().requires_grad_(True)
+    j3 = sy.j3.detach().clone().requires_grad_(True)
+    jz = sy.jb_zeta.detach().clone().requires_grad_(True)
+    sw = dataclasses.replace(sy, j1_inh=j1, j3=j3, jb_zeta=jz)
+    out = O.evaluate(sw, r)
+    F = (gl * out["logabs"] + ge * out["e_loc"]).sum()
+    g1, g3, gz = torch.autograd.grad(F, [j1, j3, jz])
+    g3 = g3.clone()
+    g3[0] = 0.5 * (g3[0] + g3[0].T)
+    g3[1] = 0.5 * (g3[1] + g3[1].T)
+    return g1, g3, gz
+
+
+def test_jas3_forces_match_oracle(jw):
+    # the adjoint through the Jastrow-basis terms (positions, nuclei, coefficients, exponents)
+    P = need_gpu()
+    Wk = 6
+    _, wk, r, _ = _eval(P, jw.system, jw.r0, Wk)
+    sy = O.from_workload_system(jw.system)
+    rng = np.random.default_rng(21)
+    gl = torch.tensor(rng.normal(size=Wk))
+    ge = torch.tensor(rng.normal(size=Wk))
+    out = wk.forces(r.cuda(), gl.cuda(), ge.cuda())
+    torch.cuda.synchronize()
+    ref = O.forces_vjp(sy, r, gl, ge)
+    g1, g3, gz = _oracle_j3_param_grads(sy, r, gl, ge)
+    ref.update(j1_inh=g1, j3=g3, jb_zeta=gz)
+    for k in ("R", "zeta", "lam", "jas", "r", "j1_inh", "j3", "jb_zeta"):
+        a, b = out[k].cpu(), ref[k]
+        err = (a - b).abs().max().item() / max(1.0, b.abs().max().item())
+        print(f"[jas3 forces] {k}: {err:.3e}")
+        assert err <= 1e-8, (k, err)
+    # per walker, log|Psi| only: the coefficients' part equals the closed-form log-derivatives
+    one = torch.ones(Wk, dtype=torch.float64, device="cuda")
+    per = wk.forces(r.cuda(), one, None, per_walker=True)
+    dm, dM = wk.jastrow_basis_logderiv()
+    torch.cuda.synchronize()
+    assert ((per["j1_inh"] - dm).abs().max() / dm.abs().max()).item() <= 1e-12
+    assert ((per["j3"] - dM).abs().max() / dM.abs().max()).item() <= 1e-12
+
+
 def test_jas3_refusals(jw):
     P = need_gpu()
     sysh, wk, r, _ = _eval(P, jw.system, jw.r0, 4)
-    with pytest.raises(P.QMCError) as ex:
-        wk.forces(r.cuda(), torch.ones(4, dtype=torch.float64, device="cuda"), None)
-    assert ex.value.code == -5
     with pytest.raises(P.QMCError) as ex:
         P.MultiSystem([wk])
     assert ex.value.code == -5
