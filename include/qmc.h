@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define QMC_ABI_VERSION 11
+#define QMC_ABI_VERSION 12
 
 typedef enum {
   QMC_OK = 0,
@@ -109,8 +109,8 @@ typedef struct {
    *   J3/4  = sum_{i<j} sum_{k,l} chi_k(r_i) M^{s_i s_j}[k][l] chi_l(r_j)
    * Up electrons come first, so unlike-spin pairs i < j use M^{ud}; the
    * same-spin matrices must be symmetric.  n_jbasis = 0: no such terms.
-   * Not supported with them: qmc_multi_*, moving nuclei through
-   * qmc_system_set_params. */
+   * Not supported with them: qmc_multi_*.  qmc_system_set_jastrow_basis
+   * replaces the coefficients and exponents. */
   int32_t n_jbasis;           /* LJ <= 1024                                      */
   const int32_t *jb_center;   /* [LJ] nucleus index                              */
   const int32_t *jb_l;        /* [LJ] 0..2                                       */
@@ -126,8 +126,7 @@ typedef struct {
    * [L] of the calls below that refers to orbitals (Phi rows) reads Lc.
    * L <= 2048 primitives.  qmc_forces returns the gradients with respect to the
    * primitives' exponents and Lambda over the contracted orbitals (not with
-   * respect to con_coef).  Not supported with it: qmc_multi_*, exponents or
-   * nuclei changed through qmc_system_set_params. */
+   * respect to con_coef).  Not supported with it: qmc_multi_*. */
   int32_t n_contracted;       /* Lc (0: the basis functions are the orbitals)    */
   const int32_t *con_ptr;     /* [Lc + 1], con_ptr[0] = 0, non-decreasing        */
   const int32_t *con_idx;     /* [con_ptr[Lc]] primitive index, 0 .. L-1         */
@@ -135,7 +134,8 @@ typedef struct {
   /* Unpaired orbitals (eq:wfAGPunpaired): with k = n_up - n_dn > 0 the geminal
    * matrix is n_up x n_up, columns n_dn + l holding sum_mu unpaired[mu][l]
    * phi_mu(r_i) (phi the orbitals: the basis functions, or the contracted
-   * orbitals).  Not supported with it: qmc_forces, qmc_multi_*. */
+   * orbitals).  Not supported with it: qmc_multi_*; qmc_forces gives no
+   * gradient with respect to the unpaired coefficients. */
   const double *unpaired;     /* [L or Lc][k]; may be NULL when k = 0            */
   /* Pfaffian pairing (Pfaffian wave function section), pairing = 1: Psi =
    * Pf(G~) exp J with G~_ij = phi(r_i)^T A^{s_i s_j} phi(r_j) (eq:g,
@@ -166,7 +166,7 @@ qmc_status qmc_system_create(const qmc_system_desc *desc, qmc_system **out);
 qmc_status qmc_system_destroy(qmc_system *sys);
 
 /* Replace parameters of a system from DEVICE arrays (any may be NULL to keep
- * the current values): R [A][3], zeta [L], lambda [L][L], jas [A + n_j2]
+ * the current values): R [A][3], zeta [n_basis], lambda [L][L], jas [A + n_j2]
  * (one-body b per nucleus, then the two-body parameters).  Work is enqueued on
  * `stream`; when jas is given the call also waits for that copy (the two-body
  * parameters live in the launch arguments).  Walker sets of this system must be
@@ -174,6 +174,14 @@ qmc_status qmc_system_destroy(qmc_system *sys);
  * QMC_ERR_STATE until then. */
 qmc_status qmc_system_set_params(qmc_system *sys, const double *R, const double *zeta,
                                  const double *lambda, const double *jas, hipStream_t stream);
+
+/* Replace the Jastrow-basis coefficients and exponents from DEVICE arrays (any
+ * may be NULL to keep the current values): j1_inh [2][LJ], j3 [3][LJ][LJ]
+ * (M^{uu}, M^{dd}, M^{ud}; the same-spin blocks must be symmetric, which is not
+ * checked here), jb_zeta [LJ].  Enqueued on `stream`; walker sets must be
+ * re-evaluated before further moves.  QMC_ERR_ARG without a Jastrow basis. */
+qmc_status qmc_system_set_jastrow_basis(qmc_system *sys, const double *j1_inh, const double *j3,
+                                        const double *jb_zeta, hipStream_t stream);
 
 /* Allocate the device state of n_walkers walkers of sys (positions, basis
  * matrix Phi, P = Phi Lambda, W, W^{-1} and move buffers).  The state is

@@ -35,6 +35,7 @@ FUNCTIONS = (
     "qmc_multi_destroy", "qmc_multi_autotune", "qmc_multi_vmc_steps", "qmc_philox_draws",
     "qmc_lrdmc_hops", "qmc_lrdmc_advance", "qmc_walkers_set_timing_mask", "qmc_swct", "qmc_reweight",
     "qmc_sr_workspace_size", "qmc_sr_step", "qmc_jastrow_basis_logderiv", "qmc_pfaffian_logderiv",
+    "qmc_system_set_jastrow_basis",
 )
 
 TIMER_NAMES = ("basis", "P_build", "W_build", "LU", "Y_build", "rowdot", "assemble", "propose",
@@ -121,6 +122,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.qmc_swct.argtypes = [vp, i32, dp, dp, dp, i32, dp, vp]
     lib.qmc_jastrow_basis_logderiv.argtypes = [vp, vp, dp, dp, vp]
     lib.qmc_pfaffian_logderiv.argtypes = [vp, vp, dp, dp, dp, dp, dp, vp]
+    lib.qmc_system_set_jastrow_basis.argtypes = [vp, dp, dp, dp, vp]
     lib.qmc_reweight.argtypes = [vp, vp, ctypes.c_double, ctypes.c_double, dp, dp, vp]
     lib.qmc_sr_workspace_size.restype = ctypes.c_size_t
     lib.qmc_sr_workspace_size.argtypes = [i32, ctypes.c_int64]
@@ -221,6 +223,12 @@ class JAGPSystem:
         R, zeta, lam, jas = c(R), c(zeta), c(lam), c(jas)
         _check(load().qmc_system_set_params(self.h, _ptr(R), _ptr(zeta), _ptr(lam), _ptr(jas),
                                             _stream(stream)))
+
+    def set_jastrow_basis(self, j1_inh=None, j3=None, jb_zeta=None, stream=None):
+        """Replace Jastrow-basis coefficients / exponents from device tensors."""
+        c = lambda t: None if t is None else t.detach().contiguous()
+        j1_inh, j3, jb_zeta = c(j1_inh), c(j3), c(jb_zeta)
+        _check(load().qmc_system_set_jastrow_basis(self.h, _ptr(j1_inh), _ptr(j3), _ptr(jb_zeta), _stream(stream)))
 
     def close(self):
         if getattr(self, "h", None):

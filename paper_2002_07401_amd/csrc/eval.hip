@@ -277,16 +277,54 @@ __global__ void set_lambda_kernel(SysDev s, const double* __restrict__ lam) {
   }
 }
 
-// bfn[mu] = (centre of mu, zeta_mu); rebuilt whenever R or zeta change.
+// bfn[mu] = (centre of mu, zeta_mu) over the basis functions (the primitives
+// of a contracted basis), and the Jastrow basis's centres (its exponents stay);
+// rebuilt whenever R or zeta change.
 __global__ void pack_basis_kernel(SysDev s) {
   const int mu = blockIdx.x * blockDim.x + threadIdx.x;
-  if (mu >= s.L) return;
-  const int c = s.center[mu];
-  s.bfn[mu] = make_double4(s.R[3 * c], s.R[3 * c + 1], s.R[3 * c + 2], s.zeta[mu]);
+  if (mu < s.nprim()) {
+    const int c = s.center[mu];
+    s.bfn[mu] = make_double4(s.R[3 * c], s.R[3 * c + 1], s.R[3 * c + 2], s.zeta[mu]);
+  }
+  if (mu < s.LJ) {
+    const int c = s.jcenter[mu];
+    s.jbfn[mu] = make_double4(s.R[3 * c], s.R[3 * c + 1], s.R[3 * c + 2], s.jbfn[mu].w);
+  }
 }
 
 hipError_t launch_pack_basis(const SysDev& s, hipStream_t st) {
-  hipLaunchKernelGGL(pack_basis_kernel, dim3((s.L + 255) / 256), dim3(256), 0, st, s);
+  const int n = s.nprim() > s.LJ ? s.nprim() : s.LJ;
+  hipLaunchKernelGGL(pack_basis_kernel, dim3((n + 255) / 256), dim3(256), 0, st, s);
+  return hipGetLastError();
+}
+
+// New Jastrow-basis coefficients / exponents from device arrays (any may be null):
+// jm <- j1_inh, M3 <- [[Muu, Mud], [Mud^T, Mdd]], jbfn[k].w <- jb_zeta[k].
+__global__ void set_jastrow_basis_kernel(SysDev s, const double* __restrict__ j1_inh, const double* __restrict__ j3,
+                                         const double* __restrict__ jz) {
+  const int LJ = s.LJ;
+  const long LL = (long)LJ * LJ;
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j3 && idx < LL) {
+    const int a = (int)(idx / LJ), b = (int)(idx % LJ);
+    const long n2 = 2L * LJ;
+    s.M3[a * n2 + b] = j3[idx];
+    s.M3[(LJ + a) * n2 + LJ + b] = j3[LL + idx];
+    s.M3[a * n2 + LJ + b] = j3[2 * LL + idx];
+    s.M3[(LJ + b) * n2 + a] = j3[2 * LL + idx];
+  }
+  if (j1_inh && idx < 2L * LJ) s.jm[idx] = j1_inh[idx];
+  if (jz && idx < LJ) {
+    const double4 f = s.jbfn[idx];
+    s.jbfn[idx] = make_double4(f.x, f.y, f.z, jz[idx]);
+  }
+}
+
+hipError_t launch_set_jastrow_basis(const SysDev& s, const double* j1_inh, const double* j3, const double* jz,
+                                    hipStream_t st) {
+  const long n = (long)s.LJ * s.LJ > 2L * s.LJ ? (long)s.LJ * s.LJ : 2L * s.LJ;
+  hipLaunchKernelGGL(set_jastrow_basis_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s, j1_inh, j3,
+                     jz);
   return hipGetLastError();
 }
 

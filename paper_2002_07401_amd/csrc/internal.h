@@ -522,6 +522,8 @@ inline int wb_cap(const SysDev& s) { return s.refresh_every < kWbMax ? s.refresh
 hipError_t launch_export_phi(const SysDev& s, const WalkDev& w, double* dst, hipStream_t st);
 hipError_t launch_set_lambda(const SysDev& s, const double* lam, hipStream_t st);
 hipError_t launch_pack_basis(const SysDev& s, hipStream_t st);
+hipError_t launch_set_jastrow_basis(const SysDev& s, const double* j1_inh, const double* j3, const double* jz,
+                                    hipStream_t st);
 
 // FP64 MFMA GEMM, exposed for the launchers above.
 struct GemmArgs {

@@ -1052,16 +1052,24 @@ extern "C" qmc_status qmc_sr_step(int32_t n_samples, int64_t n_params, const dou
   return QMC_OK;
 }
 
+extern "C" qmc_status qmc_system_set_jastrow_basis(qmc_system* sys, const double* j1_inh, const double* j3,
+                                                   const double* jb_zeta, hipStream_t stream) {
+  if (!sys) return fail(QMC_ERR_ARG, "null system");
+  const SysDev& d = sys->d;
+  if (d.LJ <= 0) return fail(QMC_ERR_ARG, "the system has no Jastrow basis");
+  HIP_TRY(launch_set_jastrow_basis(d, j1_inh, j3, jb_zeta, stream), "set Jastrow basis");
+  sys->generation += 1;
+  return QMC_OK;
+}
+
 extern "C" qmc_status qmc_system_set_params(qmc_system* sys, const double* R, const double* zeta,
                                             const double* lambda, const double* jas, hipStream_t stream) {
   if (!sys) return fail(QMC_ERR_ARG, "null system");
   SysDev& d = sys->d;
-  if (R && d.LJ > 0) return fail(QMC_ERR_UNSUPPORTED, "moving nuclei with a Jastrow basis is not built");
   if (d.pairing) return fail(QMC_ERR_UNSUPPORTED, "parameter changes of the Pfaffian are not built");
-  if ((R || zeta) && d.Lq > 0)
-    return fail(QMC_ERR_UNSUPPORTED, "changing primitives of a contracted basis is not built");
   if (R) HIP_TRY(hipMemcpyAsync(d.R, R, sizeof(double) * 3 * d.n_nuc, hipMemcpyDeviceToDevice, stream), "set R");
-  if (zeta) HIP_TRY(hipMemcpyAsync(d.zeta, zeta, sizeof(double) * d.L, hipMemcpyDeviceToDevice, stream), "set zeta");
+  if (zeta)   // one exponent per basis function (per primitive of a contracted basis)
+    HIP_TRY(hipMemcpyAsync(d.zeta, zeta, sizeof(double) * d.nprim(), hipMemcpyDeviceToDevice, stream), "set zeta");
   if (lambda) HIP_TRY(launch_set_lambda(d, lambda, stream), "set lambda");
   if (lambda) HIP_TRY(launch_lam_mask(d, stream), "lambda mask");
   if (R || zeta) HIP_TRY(launch_pack_basis(d, stream), "pack basis");

@@ -139,10 +139,15 @@ def test_contracted_refusals(cw):
     with pytest.raises(P.QMCError) as ex:
         P.MultiSystem([wk])
     assert ex.value.code == -5
-    with pytest.raises(P.QMCError) as ex:
-        sysh.set_params(zeta=torch.tensor(cw.system.zeta, device="cuda"))
-    assert ex.value.code == -5
-    # Lambda (acting on the contracted orbitals) may change
+    # primitive exponents, nuclei and Lambda (over the contracted orbitals) may change
+    z2 = cw.system.zeta * 1.05
+    R2 = cw.system.R + 0.03
+    sysh.set_params(zeta=torch.tensor(z2, device="cuda"), R=torch.tensor(R2, device="cuda"))
+    out = wk.eval_batch(r.cuda())
+    torch.cuda.synchronize()
+    ref = O.evaluate(O.from_workload_system(dataclasses.replace(cw.system, zeta=z2, R=R2)), r)
+    assert rel_err(out["e_loc"].cpu(), ref["e_loc"]).max().item() <= 1e-10
+    sysh.set_params(zeta=torch.tensor(cw.system.zeta, device="cuda"), R=torch.tensor(cw.system.R, device="cuda"))
     lam2 = torch.tensor(cw.system.lam * 1.1, device="cuda")
     sysh.set_params(lam=lam2)
     out = wk.eval_batch(r.cuda())

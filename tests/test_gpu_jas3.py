@@ -155,9 +155,6 @@ def test_jas3_refusals(jw):
     with pytest.raises(P.QMCError) as ex:
         P.MultiSystem([wk])
     assert ex.value.code == -5
-    with pytest.raises(P.QMCError) as ex:
-        sysh.set_params(R=torch.tensor(jw.system.R, device="cuda"))
-    assert ex.value.code == -5
     s = jw.system
     bad = s.j3.copy()
     bad[0, 0, 1] += 1.0
@@ -204,3 +201,35 @@ def test_jas3_logderiv_matches_oracle(jw):
     rm, rM = _oracle_logderiv(sy, rg)
     assert ((dm.cpu() - rm).abs().max() / rm.abs().max()).item() <= 1e-10
     assert ((dM.cpu() - rM).abs().max() / rM.abs().max()).item() <= 1e-10
+
+
+def test_jas3_parameter_updates(jw):
+    # moved nuclei carry the Jastrow basis with them; new coefficients and exponents
+    P = need_gpu()
+    sysh, wk, r, _ = _eval(P, jw.system, jw.r0, 8)
+    s = jw.system
+    rng = np.random.default_rng(33)
+    R2 = s.R + 0.05 * rng.standard_normal(s.R.shape)
+    sysh.set_params(R=torch.tensor(R2, device="cuda"))
+    out = wk.eval_batch(r.cuda())
+    torch.cuda.synchronize()
+    s2 = dataclasses.replace(s, R=R2)
+    ref = O.evaluate(O.from_workload_system(s2), r)
+    assert rel_err(out["e_loc"].cpu(), ref["e_loc"]).max().item() <= 1e-10
+    assert rel_err(out["logabs"].cpu(), ref["logabs"]).max().item() <= 1e-10
+    j1 = s.j1_inh * 1.3
+    j3 = s.j3 + 0.02 * np.stack([C._sym_gaussian(rng, len(s.jb_zeta), 1.0), C._sym_gaussian(rng, len(s.jb_zeta), 1.0),
+                                 rng.standard_normal((len(s.jb_zeta),) * 2)])
+    jz = s.jb_zeta * 1.1
+    sysh.set_jastrow_basis(torch.tensor(j1, device="cuda"), torch.tensor(j3, device="cuda"),
+                           torch.tensor(jz, device="cuda"))
+    with pytest.raises(P.QMCError) as ex:      # walkers must re-evaluate after a parameter change
+        wk.propose(0, r[:, 0].cuda().contiguous())
+    assert ex.value.code == -6
+    out = wk.eval_batch(r.cuda())
+    torch.cuda.synchronize()
+    s3 = dataclasses.replace(s2, j1_inh=j1, j3=j3, jb_zeta=jz)
+    ref = O.evaluate(O.from_workload_system(s3), r)
+    assert rel_err(out["e_loc"].cpu(), ref["e_loc"]).max().item() <= 1e-10
+    assert rel_err(out["logabs"].cpu(), ref["logabs"]).max().item() <= 1e-10
+
