@@ -106,17 +106,24 @@ def _blocks(sy):
     return sy.pf_uu, Aud, -Aud.T, sy.pf_dd
 
 
-def _pair_row_matrices(sy):
-    """Per electron pair (i, j) the matrix A^{s_i s_j}: [N, N, L, L]."""
-    N, nu = sy.n_elec, sy.n_up
+def _pair_products(sy, left, right):
+    """X[w, i, j, ...] = left_i^T A^{s_i s_j} right_j over all electron pairs,
+    by spin blocks (left [Wk, N, L] or [Wk, N, L, 3], right [Wk, N, L])."""
+    nu = sy.n_up
     Auu, Aud, Adu, Add = _blocks(sy)
-    L = Aud.shape[0]
-    M = torch.empty(N, N, L, L, dtype=DT)
-    for i in range(N):
-        for j in range(N):
-            ui, uj = i < nu, j < nu
-            M[i, j] = Auu if (ui and uj) else (Aud if ui else (Adu if uj else Add))
-    return M
+    blocks = {(0, 0): Auu, (0, 1): Aud, (1, 0): Adu, (1, 1): Add}
+    vec = left.dim() == 4
+    rows = []
+    for si, I in ((0, slice(0, nu)), (1, slice(nu, None))):
+        cols = []
+        for sj, J in ((0, slice(0, nu)), (1, slice(nu, None))):
+            A = blocks[(si, sj)]
+            if vec:
+                cols.append(torch.einsum('wilx,lm,wjm->wijx', left[:, I], A, right[:, J]))
+            else:
+                cols.append(torch.einsum('wil,lm,wjm->wij', left[:, I], A, right[:, J]))
+        rows.append(torch.cat(cols, dim=2))
+    return torch.cat(rows, dim=1)
 
 
 def unpaired_rows(sy):
@@ -130,8 +137,7 @@ def unpaired_rows(sy):
 def pairing_matrix(sy, Phi):
     """G~ [Wk, N+k, N+k] from orbital values Phi [Wk, N, L]."""
     Wk, N, _ = Phi.shape
-    M = _pair_row_matrices(sy)
-    G = torch.einsum('wil,ijlm,wjm->wij', Phi, M, Phi)
+    G = _pair_products(sy, Phi, Phi)
     G = G * (~torch.eye(N, dtype=torch.bool)).to(DT)
     U = unpaired_rows(sy)
     k = U.shape[2]
@@ -162,11 +168,10 @@ def evaluate(sy, r, with_intermediates=False) -> Dict[str, torch.Tensor]:
     singular = sign == 0
     Gs = torch.where(singular.view(-1, 1, 1), torch.eye(n, dtype=DT).expand_as(Gt), Gt)
     Ginv = torch.linalg.inv(Gs)
-    M = _pair_row_matrices(sy)
     U = unpaired_rows(sy)
     # derivatives of row i of G~ with respect to r_i
-    dG = torch.einsum('wilx,ijlm,wjm->wijx', Gp, M, Phi)        # [Wk, N, N, 3]
-    hG = torch.einsum('wil,ijlm,wjm->wij', Hp, M, Phi)
+    dG = _pair_products(sy, Gp, Phi)                            # [Wk, N, N, 3]
+    hG = _pair_products(sy, Hp, Phi)
     off = (~torch.eye(N, dtype=torch.bool)).to(DT)
     dG = dG * off.view(1, N, N, 1)
     hG = hG * off.view(1, N, N)
