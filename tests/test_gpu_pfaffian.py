@@ -232,3 +232,44 @@ def test_pfaffian_logderiv_matches_oracle(fw):
     ref = _oracle_pf_logderiv(sy, rg)
     for k, b in ref.items():
         assert ((got[k].cpu() - b).abs().max() / b.abs().max()).item() <= 1e-8, k
+
+
+def test_pfaffian_at_the_maximum_dimension():
+    # G~ 96 x 96 (80 electrons + 16 unpaired orbitals): the Gauss-Jordan kernel's
+    # largest size and a 72 KB LDS copy in the Parlett-Reid kernel
+    P = need_gpu()
+    w = C.pfaffian_20nuc_80e(n_walkers=4)
+    L_ = len(w.system.lam)
+    rng = np.random.default_rng(12)
+    s = dataclasses.replace(w.system, unpaired=rng.standard_normal((L_, 16)) / np.sqrt(L_),
+                            unpaired_dn=rng.standard_normal((L_, 16)) / np.sqrt(L_))
+    _, wk, r, out = _eval(P, s, w.r0, 4)
+    sy = O.from_workload_system(s)
+    _check_eval(out, O.evaluate(sy, r), "n = 96")
+    assert wk.read(P.STATE_W).shape == (4, 96, 96)
+    d, u = C.chain_arrays(3, 12, 4)
+    d, u = torch.tensor(d), torch.tensor(u)
+    wk.vmc_steps(0, d.cuda(), u.cuda())
+    rg = wk.read(P.STATE_R).cpu()
+    torch.cuda.synchronize()
+    rf, _, _ = O.run_chain(sy, r, d, u)
+    assert torch.equal(rg, rf)
+    with pytest.raises(P.QMCError) as ex:   # 98 > 96
+        P.JAGPSystem(dataclasses.replace(s, unpaired=np.zeros((L_, 18)), unpaired_dn=np.zeros((L_, 18))))
+    assert ex.value.code == -5
+
+
+def test_pfaffian_two_electrons():
+    # one up and one down electron: G~ is 2 x 2 and Pf = G_12
+    P = need_gpu()
+    w = C.tiny_3nuc_10e(n_walkers=8)
+    L_ = len(w.system.lam)
+    rng = np.random.default_rng(4)
+    s = dataclasses.replace(w.system, n_up=1, n_dn=1, pairing=1, pf_uu=np.zeros((L_, L_)), pf_dd=np.zeros((L_, L_)),
+                            unpaired=np.zeros((L_, 0)), unpaired_dn=np.zeros((L_, 0)))
+    r0 = C.random_positions(9, s, 8)
+    _, wk, r, out = _eval(P, s, r0, 8)
+    sy = O.from_workload_system(s)
+    _check_eval(out, O.evaluate(sy, r), "N = 2")
+    G = wk.read(P.STATE_W).cpu()
+    assert torch.equal(out["sign"].cpu(), torch.sign(G[:, 0, 1]))
