@@ -505,7 +505,8 @@ int propose_splits(const SysDev& s);
 hipError_t launch_propose_prep(const SysDev& s, const WalkDev& w, int e, const double* r_new,
                                const double* disp, bool drift, hipStream_t st);
 hipError_t launch_propose_rows(const SysDev& s, const WalkDev& w, int e, double* ratio,
-                               double* drift_new, bool finalize, hipStream_t st);
+                               double* drift_new, bool finalize, hipStream_t st, hipEvent_t ev_start = nullptr,
+                               hipEvent_t ev_stop = nullptr);
 hipError_t launch_metropolis_accept(const SysDev& s, const WalkDev& w, int e, const double* unif,
                                     int32_t* accept_count, hipStream_t st);
 // Metropolis accept of e fused with the set-up of the next proposal (electron

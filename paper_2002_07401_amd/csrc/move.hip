@@ -19,6 +19,8 @@
 // many blocks are in flight, and every block writes a partial determinant
 // ratio, which the accept kernel (device Metropolis) or the finalize kernel
 // (host-driven moves) sums in a fixed order.
+#include <hip/hip_ext.h>
+
 #include "move_dev.h"
 #include <algorithm>
 
@@ -118,8 +120,11 @@ hipError_t launch_propose_prep(const SysDev& s, const WalkDev& w, int e, const d
   return hipGetLastError();
 }
 
+// ev_start / ev_stop (may be null): events recorded by the streaming kernel's
+// own dispatch (hipExtLaunchKernelGGL), so that they time that kernel alone.
 hipError_t launch_propose_rows(const SysDev& s, const WalkDev& w, int e, double* ratio,
-                               double* drift_new, bool finalize, hipStream_t st) {
+                               double* drift_new, bool finalize, hipStream_t st, hipEvent_t ev_start,
+                               hipEvent_t ev_stop) {
   const bool drift = drift_new != nullptr;
   if (s.prop_rows() < kPropRowsMin) return hipErrorInvalidValue;   // rdet_part would overflow
   const int S = propose_splits(s);
@@ -129,14 +134,14 @@ hipError_t launch_propose_rows(const SysDev& s, const WalkDev& w, int e, double*
   const int vn = store == 0 ? 2 : (store == 1 ? 4 : 8);   // elements per 16-byte load
   const int chunks = (s.Lp + 64 * vn - 1) / (64 * vn);
 #define QMC_GEN(D)                                                                                         \
-  if (store == 2) hipLaunchKernelGGL((propose_rows_generic_kernel<bf16s, D>), grid, dim3(256), 0, st, s, w, e, S); \
-  else if (store == 1) hipLaunchKernelGGL((propose_rows_generic_kernel<float, D>), grid, dim3(256), 0, st, s, w, e, S); \
-  else hipLaunchKernelGGL((propose_rows_generic_kernel<double, D>), grid, dim3(256), 0, st, s, w, e, S);
+  if (store == 2) hipExtLaunchKernelGGL((propose_rows_generic_kernel<bf16s, D>), grid, dim3(256), 0, st, ev_start, ev_stop, 0, s, w, e, S); \
+  else if (store == 1) hipExtLaunchKernelGGL((propose_rows_generic_kernel<float, D>), grid, dim3(256), 0, st, ev_start, ev_stop, 0, s, w, e, S); \
+  else hipExtLaunchKernelGGL((propose_rows_generic_kernel<double, D>), grid, dim3(256), 0, st, ev_start, ev_stop, 0, s, w, e, S);
   if (drift) {
     QMC_GEN(true)
   } else if (chunks <= 8) {
 #define QMC_ROWS(T, NC) \
-    case NC: hipLaunchKernelGGL((propose_rows_kernel<T, NC>), grid, dim3(256), 0, st, s, w, e, S); break;
+    case NC: hipExtLaunchKernelGGL((propose_rows_kernel<T, NC>), grid, dim3(256), 0, st, ev_start, ev_stop, 0, s, w, e, S); break;
     if (store == 2) {
       switch (chunks) { QMC_ROWS(bf16s, 1) QMC_ROWS(bf16s, 2) QMC_ROWS(bf16s, 3) QMC_ROWS(bf16s, 4)
                         QMC_ROWS(bf16s, 5) QMC_ROWS(bf16s, 6) QMC_ROWS(bf16s, 7) QMC_ROWS(bf16s, 8) }

@@ -99,6 +99,33 @@ struct Timers {
     open_id = -1;
     return hipEventRecord(pending.back().b, st);
   }
+  // A pair for a kernel that records it in its own dispatch (hipExtLaunchKernelGGL):
+  // both null when this timer is off.
+  hipError_t begin_ext(int id, hipEvent_t* a, hipEvent_t* b) {
+    *a = *b = nullptr;
+    if (!on || !((mask >> id) & 1u)) return hipSuccess;
+    hipError_t e = begin_pair(id);
+    if (e != hipSuccess) return e;
+    *a = pending.back().a;
+    *b = pending.back().b;
+    return hipSuccess;
+  }
+  hipError_t begin_pair(int id) {
+    if (pending.size() >= 8192) {
+      hipError_t e = fold();
+      if (e != hipSuccess) return e;
+    }
+    Pair p;
+    if (!spare.empty()) { p = spare.back(); spare.pop_back(); }
+    else {
+      hipError_t e = hipEventCreate(&p.a);
+      if (e == hipSuccess) e = hipEventCreate(&p.b);
+      if (e != hipSuccess) return e;
+    }
+    p.id = id;
+    pending.push_back(p);
+    return hipSuccess;
+  }
   void destroy() {
     (void)fold();
     for (auto& p : spare) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
@@ -641,8 +668,11 @@ extern "C" qmc_status qmc_propose_move(qmc_system* sys, qmc_walkers* wk, int32_t
   if (c) return c;
   TIMED(wk, QMC_T_PROPOSE_PREP, stream,
         launch_propose_prep(s, wk->d, electron, r_new, nullptr, drift_new != nullptr, stream), "propose prep");
-  TIMED(wk, QMC_T_PROPOSE, stream, launch_propose_rows(s, wk->d, electron, ratio, drift_new, true, stream),
-        "propose rows");
+{
+    hipEvent_t ea, eb;
+    HIP_TRY(wk->tm.begin_ext(QMC_T_PROPOSE, &ea, &eb), "timer begin");
+    HIP_TRY(launch_propose_rows(s, wk->d, electron, ratio, drift_new, true, stream, ea, eb), "propose rows");
+  }
   wk->pending_e = electron;
   return QMC_OK;
 }
@@ -780,8 +810,11 @@ extern "C" qmc_status qmc_vmc_steps(qmc_system* sys, qmc_walkers* wk, int32_t e_
       TIMED(wk, QMC_T_PROPOSE_PREP, stream,
             launch_propose_prep(s, wk->d, e, nullptr, disp + (long)t * Wk * 3, false, stream), "propose prep");
     }
-    TIMED(wk, QMC_T_PROPOSE, stream, launch_propose_rows(s, wk->d, e, nullptr, nullptr, false, stream),
-          "propose rows");
+{
+      hipEvent_t ea, eb;
+      HIP_TRY(wk->tm.begin_ext(QMC_T_PROPOSE, &ea, &eb), "timer begin");
+      HIP_TRY(launch_propose_rows(s, wk->d, e, nullptr, nullptr, false, stream, ea, eb), "propose rows");
+    }
     const int e2 = (int)((e_start + (long)t + 1) % s.N);
     prepped = t + 1 < n_steps && fusable(wk, e, e2);
     if (prepped) {
