@@ -20,6 +20,25 @@ __device__ double block_sum_mv(double v, double* red) {
   return t;
 }
 
+// out[i] = sum_j M[i*ld + j] x[j] for i < m (m <= kWbMax), x in LDS, out in LDS.
+// Rows are spread over groups of G lanes (G = blockDim / m rounded up to a power
+// of two >= 4, at most 64), so the loads of every row are issued together rather
+// than one row per wave at a time; each group reduces by a fixed xor-shuffle
+// tree.  Called by every thread of the workgroup; the caller synchronises.
+__device__ __forceinline__ void rows_dot_lds(const double* __restrict__ M, long ld, int m, int n,
+                                             const double* x, double* out) {
+  int mp = 4;
+  while (mp < m) mp <<= 1;
+  int G = (int)blockDim.x / mp;
+  if (G > 64) G = 64;
+  const int i = threadIdx.x / G, sub = threadIdx.x % G;
+  double p = 0.0;
+  if (i < m)
+    for (int j = sub; j < n; j += G) p += M[(long)i * ld + j] * x[j];
+  for (int o = G >> 1; o > 0; o >>= 1) p += __shfl_xor(p, o, 64);
+  if (i < m && sub == 0) out[i] = p;
+}
+
 // Jastrow terms of electron e at position p, summed over this thread's share
 // of nuclei and electrons: value and gradient.
 __device__ void jastrow_one(const SysDev& s, const double* r, int e, double px, double py, double pz,
@@ -79,21 +98,14 @@ __device__ void inverse_line_body(const SysDev& s, const WalkDev& w, int wk, int
   const double* V = w.wv + (long)wk * kb * n;
   const double* Si = w.wS + (long)wk * kb * kb;
   double* tz = w.tz + (long)wk * 2 * kb;
-  for (int i = wave; i < m; i += nw) {
-    double p = 0.0;
-    for (int j = lane; j < n; j += 64) p += D[(long)i * n + j] * sv0[j];
-    p = wave_sum(p);
-    if (lane == 0) st[i] = p;
-  }
+  rows_dot_lds(D, n, m, n, sv0, st);          // t = D^T v0
+  __syncthreads();
+  rows_dot_lds(Si, kb, m, m, st, sz);         // z = S^{-1} t
   __syncthreads();
   for (int i = tid; i < m; i += blockDim.x) {
-    double z = 0.0;
-    for (int k = 0; k < m; ++k) z += Si[i * kb + k] * st[k];
-    sz[i] = z;
     tz[i] = st[i];
-    tz[kb + i] = z;
+    tz[kb + i] = sz[i];
   }
-  __syncthreads();
   for (int j = tid; j < n; j += blockDim.x) {
     double c = sv0[j];
     for (int i = 0; i < m; ++i) c -= sz[i] * V[(long)i * n + j];
@@ -469,12 +481,7 @@ __device__ void accept_apply(const SysDev& s, const WalkDev& w, int wk, int e, d
   p0 = wave_sum(p0);
   if (lane == 0) red[wave] = p0;
   __syncthreads();
-  for (int i = wave; i < m; i += nw) {
-    double p = 0.0;
-    for (int j = lane; j < n; j += 64) p += sd[j] * V[(long)i * n + j];
-    p = wave_sum(p);
-    if (lane == 0) sr[i] = p;
-  }
+  rows_dot_lds(V, n, m, n, sd, sr);           // r_i = delta . v_i
   __syncthreads();
   if (tid == 0) {
     double dv = 0.0;
