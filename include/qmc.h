@@ -145,8 +145,8 @@ typedef struct {
    * (eq:pfodd): G~_{i, N+l} = phi(r_i) . U^{s_i}[:, l] with U^u = unpaired
    * and U^d = pf_unpaired_dn.  N + pf_k must be even and at most 96; FP64
    * precision only; n_up < n_dn is allowed.  Not supported with it:
-   * qmc_forces, qmc_multi_*, qmc_system_set_params, a Jastrow basis,
-   * contracted orbitals.  qmc_reweight uses G~ and its inverse. */
+   * qmc_forces, qmc_multi_*, qmc_system_set_params.  qmc_reweight uses G~ and
+   * its inverse. */
   int32_t pairing;            /* 0 AGP determinant, 1 Pfaffian                   */
   const double *pf_uu;        /* [L][L] skew-symmetric                           */
   const double *pf_dd;        /* [L][L] skew-symmetric                           */

@@ -117,24 +117,16 @@ __device__ void inverse_line_body(const SysDev& s, const WalkDev& w, int wk, int
 // values psi(r') (zero-padded to Lp, and their gradients when a drift is
 // requested) and the Jastrow change J(x') - J(x) (and grad J at r').
 // r_new: this walker's new position [3], or disp: its displacement [3].
+// psi(r') (zero-padded to Lp; with their gradients when DRIFT) into this
+// walker's psi_new / gpsi_new: the basis functions, or the contracted orbitals
+// (primitives at r' into the walker's slice of qbuf, then phi_c = sum_t C_t
+// psi_{idx_t}).  Called by every thread of the workgroup.
 template <bool DRIFT>
-__device__ void prep_body(const SysDev& s, const WalkDev& w, int wk, int e, const double* __restrict__ r_new,
-                          const double* __restrict__ disp) {
-  __shared__ double red[8];
-  __shared__ double rn[3];
+__device__ void orbitals_at(const SysDev& s, const WalkDev& w, int wk, double px, double py, double pz) {
   const int tid = threadIdx.x;
-  const double* r = w.r + (long)wk * s.N * 3;
-  if (tid < 3) {
-    rn[tid] = disp ? r[3 * e + tid] + disp[tid] : r_new[tid];
-    w.r_new[3 * wk + tid] = rn[tid];
-  }
-  __syncthreads();
-  const double px = rn[0], py = rn[1], pz = rn[2];
   double* psi = w.psi_new + (long)wk * s.Lp;
   double* gpsi = w.gpsi_new + (long)wk * 3 * s.Lp;
   if (s.Lq) {
-    // contracted orbitals: primitives at r' (values, gradients on request)
-    // into this walker's slice of qbuf, then phi_c = sum_t C_t psi_{idx_t}
     const int Lq = s.Lq;
     double* qb = w.qbuf + (long)wk * 4 * Lq;
     for (int mu = tid; mu < Lq; mu += blockDim.x) {
@@ -159,7 +151,8 @@ __device__ void prep_body(const SysDev& s, const WalkDev& w, int wk, int e, cons
       psi[c] = v;
       if (DRIFT) { gpsi[c] = gx; gpsi[s.Lp + c] = gy; gpsi[2 * s.Lp + c] = gz; }
     }
-  } else
+    return;
+  }
   for (int mu = tid; mu < s.Lp; mu += blockDim.x) {
     if (mu >= s.L) {
       psi[mu] = 0.0;
@@ -172,13 +165,21 @@ __device__ void prep_body(const SysDev& s, const WalkDev& w, int wk, int e, cons
       psi[mu] = basis_value(s, mu, px, py, pz);
     }
   }
-  double jn, gxn, gyn, gzn, jo, d0, d1, d2;
+}
+
+// This thread's share of J(x') - J(x) for electron e moved to p (and of grad J
+// at p when DRIFT): one- and two-body terms, and with a Jastrow basis
+// (chi(r') - chi(r_e)) . (G_s - h_e + m_s), writing chi(r') into chi_new.
+template <bool DRIFT>
+__device__ void jastrow_change(const SysDev& s, const WalkDev& w, int wk, int e, double px, double py, double pz,
+                               double& dj, double& gxn, double& gyn, double& gzn) {
+  const int tid = threadIdx.x;
+  const double* r = w.r + (long)wk * s.N * 3;
+  double jn, jo, d0, d1, d2;
   jastrow_one(s, r, e, px, py, pz, DRIFT, jn, gxn, gyn, gzn);
   jastrow_one(s, r, e, r[3 * e], r[3 * e + 1], r[3 * e + 2], false, jo, d0, d1, d2);
-  double dj = jn - jo;
+  dj = jn - jo;
   if (s.LJ) {
-    // chi(r') and (chi(r') - chi(r_e)) . (G_s - h_e + m_s); drift requests add
-    // grad chi(r') . (G_s - h_e + m_s)
     const int sp = e < s.nu ? 0 : 1, LJ = s.LJ;
     const double* ce = w.chi + ((long)wk * s.N + e) * LJ;
     const double* he = w.hv + ((long)wk * s.N + e) * LJ;
@@ -199,6 +200,24 @@ __device__ void prep_body(const SysDev& s, const WalkDev& w, int wk, int e, cons
       dj += (v - ce[k]) * g;
     }
   }
+}
+
+template <bool DRIFT>
+__device__ void prep_body(const SysDev& s, const WalkDev& w, int wk, int e, const double* __restrict__ r_new,
+                          const double* __restrict__ disp) {
+  __shared__ double red[8];
+  __shared__ double rn[3];
+  const int tid = threadIdx.x;
+  const double* r = w.r + (long)wk * s.N * 3;
+  if (tid < 3) {
+    rn[tid] = disp ? r[3 * e + tid] + disp[tid] : r_new[tid];
+    w.r_new[3 * wk + tid] = rn[tid];
+  }
+  __syncthreads();
+  const double px = rn[0], py = rn[1], pz = rn[2];
+  orbitals_at<DRIFT>(s, w, wk, px, py, pz);
+  double dj, gxn, gyn, gzn;
+  jastrow_change<DRIFT>(s, w, wk, e, px, py, pz, dj, gxn, gyn, gzn);
   const double dJ = block_sum_mv(dj, red);
   if (DRIFT) {
     gxn = block_sum_mv(gxn, red); gyn = block_sum_mv(gyn, red); gzn = block_sum_mv(gzn, red);

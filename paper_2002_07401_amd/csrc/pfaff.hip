@@ -255,21 +255,12 @@ pf_propose_kernel(SysDev s, WalkDev w, int e, const double* __restrict__ r_new, 
   }
   __syncthreads();
   const double px = rn[0], py = rn[1], pz = rn[2];
-  double* psi = w.psi_new + (long)wk * s.Lp;
-  double* gpsi = w.gpsi_new + (long)wk * 3 * s.Lp;
-  for (int mu = tid; mu < s.Lp; mu += blockDim.x) {
-    if (DRIFT) {
-      double v = 0.0, gx = 0.0, gy = 0.0, gz = 0.0, lp;
-      if (mu < s.L) basis_vgl(s, mu, px, py, pz, v, gx, gy, gz, lp);
-      psi[mu] = v; gpsi[mu] = gx; gpsi[s.Lp + mu] = gy; gpsi[2 * s.Lp + mu] = gz;
-    } else {
-      psi[mu] = mu < s.L ? basis_value(s, mu, px, py, pz) : 0.0;
-    }
-  }
-  double jn, g0, g1, g2, jo, d0, d1, d2;
-  jastrow_one(s, r, e, px, py, pz, DRIFT, jn, g0, g1, g2);
-  jastrow_one(s, r, e, r[3 * e], r[3 * e + 1], r[3 * e + 2], false, jo, d0, d1, d2);
-  const double dJ = block_sum_mv(jn - jo, red);   // its barriers also publish psi
+  const double* psi = w.psi_new + (long)wk * s.Lp;
+  const double* gpsi = w.gpsi_new + (long)wk * 3 * s.Lp;
+  orbitals_at<DRIFT>(s, w, wk, px, py, pz);
+  double dj, g0, g1, g2;
+  jastrow_change<DRIFT>(s, w, wk, e, px, py, pz, dj, g0, g1, g2);
+  const double dJ = block_sum_mv(dj, red);   // its barriers also publish psi
   if (DRIFT) { g0 = block_sum_mv(g0, red); g1 = block_sum_mv(g1, red); g2 = block_sum_mv(g2, red); }
   const bool up = e < s.nu;
   const double* B = (up ? (const double*)w.P : w.Bd) + (long)wk * N * s.Lp;
@@ -378,6 +369,7 @@ pf_accept_kernel(SysDev s, WalkDev w, int e, const uint8_t* __restrict__ acc_in,
     bu[mu] = nb[mu];
     bd[mu] = nb[s.Lp + mu];
   }
+  if (s.LJ) jastrow3_accept(s, w, wk, e);   // block-uniform
   if (tid == 0) {
     double* re = w.r + ((long)wk * N + e) * 3;
     re[0] = w.r_new[3 * wk]; re[1] = w.r_new[3 * wk + 1]; re[2] = w.r_new[3 * wk + 2];

@@ -197,8 +197,6 @@ extern "C" qmc_status qmc_system_create(const qmc_system_desc* desc, qmc_system*
     if (q.n_up + q.n_dn + q.pf_k > kLuRowMax) return fail(QMC_ERR_UNSUPPORTED, "Pfaffian of dimension > 96");
     if (!q.pf_uu || !q.pf_dd) return fail(QMC_ERR_ARG, "Pfaffian same-spin blocks missing");
     if (q.pf_k > 0 && (!q.unpaired || !q.pf_unpaired_dn)) return fail(QMC_ERR_ARG, "unpaired orbitals missing");
-    if (q.n_jbasis > 0) return fail(QMC_ERR_UNSUPPORTED, "Jastrow basis with the Pfaffian is not built");
-    if (q.n_contracted > 0) return fail(QMC_ERR_UNSUPPORTED, "contracted orbitals with the Pfaffian are not built");
   } else {
     if (q.n_up < q.n_dn) return fail(QMC_ERR_UNSUPPORTED, "n_up < n_dn: label the majority spin up");
     if (q.n_up > q.n_dn && !q.unpaired) return fail(QMC_ERR_ARG, "n_up > n_dn needs the unpaired orbitals");

@@ -273,3 +273,44 @@ def test_pfaffian_two_electrons():
     _check_eval(out, O.evaluate(sy, r), "N = 2")
     G = wk.read(P.STATE_W).cpu()
     assert torch.equal(out["sign"].cpu(), torch.sign(G[:, 0, 1]))
+
+
+def _pf_variant(kind):
+    rng = np.random.default_rng(51)
+    if kind == "jastrow_basis":
+        w = C.pfaffian_4nuc_20e(n_walkers=16)
+        return w, C.add_jastrow_basis(w.system, rng)
+    w = C.contracted_4nuc_20e(n_walkers=16)
+    L_ = len(w.system.lam)
+    skew = lambda sc: (lambda u: np.triu(u, 1) - np.triu(u, 1).T)(rng.standard_normal((L_, L_)) * sc)
+    s = dataclasses.replace(w.system, pairing=1, pf_uu=skew(0.5 / L_), pf_dd=skew(0.5 / L_),
+                            unpaired_dn=np.zeros((L_, 0)))
+    return w, s
+
+
+@pytest.mark.parametrize("kind", ["jastrow_basis", "contracted"])
+def test_pfaffian_with_jastrow_basis_or_contraction(kind):
+    P = need_gpu()
+    w, s = _pf_variant(kind)
+    r0 = C.random_positions(61, s, 16)
+    _, wk, r, out = _eval(P, s, r0, 16)
+    sy = O.from_workload_system(s)
+    _check_eval(out, O.evaluate(sy, r), kind)
+    for e in (1, 15):
+        rn = r[:, e] + torch.tensor(w.disp[e, :16])
+        ratio, dn = wk.propose(e, rn.cuda().contiguous(), drift=True)
+        torch.cuda.synchronize()
+        assert rel_err(ratio.cpu(), O.move_ratio(sy, r, e, rn)).max().item() <= 1e-10
+        r2 = r.clone(); r2[:, e] = rn
+        dref = O.evaluate(sy, r2)["drift"][:, e]
+        assert ((dn.cpu() - dref).abs() / dref.abs().clamp(min=1.0)).max().item() <= 1e-8
+    d, u = C.chain_arrays(7, 60, 16)
+    d, u = torch.tensor(d), torch.tensor(u)
+    _, wk, r, _ = _eval(P, s, r0, 16)
+    wk.vmc_steps(0, d.cuda(), u.cuda())
+    rg = wk.read(P.STATE_R).cpu()
+    la = wk.read(P.STATE_LOGABS).cpu()
+    torch.cuda.synchronize()
+    rf, _, _ = O.run_chain(sy, r, d, u)
+    assert torch.equal(rg, rf)
+    assert rel_err(la, O.evaluate(sy, rf)["logabs"]).max().item() <= 1e-10
