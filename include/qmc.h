@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define QMC_ABI_VERSION 12
+#define QMC_ABI_VERSION 13
 
 typedef enum {
   QMC_OK = 0,
@@ -145,8 +145,9 @@ typedef struct {
    * (eq:pfodd): G~_{i, N+l} = phi(r_i) . U^{s_i}[:, l] with U^u = unpaired
    * and U^d = pf_unpaired_dn.  N + pf_k must be even and at most 96; FP64
    * precision only; n_up < n_dn is allowed.  Not supported with it:
-   * qmc_forces, qmc_multi_*, qmc_system_set_params.  qmc_reweight uses G~ and
-   * its inverse. */
+   * qmc_forces' local-energy part, qmc_multi_*.  qmc_reweight uses G~ and its inverse;
+   * qmc_system_set_params (lambda = A^{ud}) and qmc_system_set_pfaffian change
+   * the coefficients. */
   int32_t pairing;            /* 0 AGP determinant, 1 Pfaffian                   */
   const double *pf_uu;        /* [L][L] skew-symmetric                           */
   const double *pf_dd;        /* [L][L] skew-symmetric                           */
@@ -182,6 +183,14 @@ qmc_status qmc_system_set_params(qmc_system *sys, const double *R, const double 
  * re-evaluated before further moves.  QMC_ERR_ARG without a Jastrow basis. */
 qmc_status qmc_system_set_jastrow_basis(qmc_system *sys, const double *j1_inh, const double *j3,
                                         const double *jb_zeta, hipStream_t stream);
+
+/* Replace the Pfaffian's same-spin blocks and unpaired orbitals from DEVICE
+ * arrays (any may be NULL): pf_uu, pf_dd [L][L] (skew-symmetric, not checked
+ * here), unpaired, unpaired_dn [L][pf_k].  A^{ud} changes through
+ * qmc_system_set_params' lambda.  Walker sets must be re-evaluated.
+ * QMC_ERR_ARG for a determinant system. */
+qmc_status qmc_system_set_pfaffian(qmc_system *sys, const double *pf_uu, const double *pf_dd,
+                                   const double *unpaired, const double *unpaired_dn, hipStream_t stream);
 
 /* Allocate the device state of n_walkers walkers of sys (positions, basis
  * matrix Phi, P = Phi Lambda, W, W^{-1} and move buffers).  The state is
@@ -271,7 +280,12 @@ typedef struct {
  * them per walker.  r [Wk][N][3] device; gbar_* [Wk] device, NULL means 0.
  * Re-evaluates the walkers at r (their state becomes that of qmc_eval_batch).
  * FP64 systems with N <= 256 electrons and <= 256 nuclei.  The first call on
- * a walker set allocates its workspace. */
+ * a walker set allocates its workspace.
+ * Pfaffian systems: log|Psi| only (d log Pf / d phi(r_i) is the evaluation's
+ * cofactor vector of electron i): gbar_eloc must be NULL (QMC_ERR_UNSUPPORTED)
+ * and dlambda NULL (QMC_ERR_ARG; the pairing coefficients' log-derivatives come
+ * from qmc_pfaffian_logderiv); dR, dzeta, djas, dr and the Jastrow-basis
+ * outputs are as above. */
 qmc_status qmc_forces(qmc_system *sys, qmc_walkers *wk, const double *r, int32_t per_walker,
                       const double *gbar_logpsi, const double *gbar_eloc, const qmc_grads *out,
                       hipStream_t stream);

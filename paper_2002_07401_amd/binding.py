@@ -35,7 +35,7 @@ FUNCTIONS = (
     "qmc_multi_destroy", "qmc_multi_autotune", "qmc_multi_vmc_steps", "qmc_philox_draws",
     "qmc_lrdmc_hops", "qmc_lrdmc_advance", "qmc_walkers_set_timing_mask", "qmc_swct", "qmc_reweight",
     "qmc_sr_workspace_size", "qmc_sr_step", "qmc_jastrow_basis_logderiv", "qmc_pfaffian_logderiv",
-    "qmc_system_set_jastrow_basis",
+    "qmc_system_set_jastrow_basis", "qmc_system_set_pfaffian",
 )
 
 TIMER_NAMES = ("basis", "P_build", "W_build", "LU", "Y_build", "rowdot", "assemble", "propose",
@@ -123,6 +123,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.qmc_jastrow_basis_logderiv.argtypes = [vp, vp, dp, dp, vp]
     lib.qmc_pfaffian_logderiv.argtypes = [vp, vp, dp, dp, dp, dp, dp, vp]
     lib.qmc_system_set_jastrow_basis.argtypes = [vp, dp, dp, dp, vp]
+    lib.qmc_system_set_pfaffian.argtypes = [vp, dp, dp, dp, dp, vp]
     lib.qmc_reweight.argtypes = [vp, vp, ctypes.c_double, ctypes.c_double, dp, dp, vp]
     lib.qmc_sr_workspace_size.restype = ctypes.c_size_t
     lib.qmc_sr_workspace_size.argtypes = [i32, ctypes.c_int64]
@@ -223,6 +224,12 @@ class JAGPSystem:
         R, zeta, lam, jas = c(R), c(zeta), c(lam), c(jas)
         _check(load().qmc_system_set_params(self.h, _ptr(R), _ptr(zeta), _ptr(lam), _ptr(jas),
                                             _stream(stream)))
+
+    def set_pfaffian(self, pf_uu=None, pf_dd=None, unpaired=None, unpaired_dn=None, stream=None):
+        """Replace the Pfaffian's same-spin blocks / unpaired orbitals from device tensors."""
+        c = lambda t: None if t is None else t.detach().contiguous()
+        a, b, u, v = c(pf_uu), c(pf_dd), c(unpaired), c(unpaired_dn)
+        _check(load().qmc_system_set_pfaffian(self.h, _ptr(a), _ptr(b), _ptr(u), _ptr(v), _stream(stream)))
 
     def set_jastrow_basis(self, j1_inh=None, j3=None, jb_zeta=None, stream=None):
         """Replace Jastrow-basis coefficients / exponents from device tensors."""
@@ -332,11 +339,13 @@ class Walkers:
             out = dict(R=f(Wk, A, 3), zeta=f(Wk, S.n_basis), lam=f(Wk, L, L), jas=f(Wk, nj), r=f(Wk, N, 3))
         else:
             out = dict(R=f(A, 3), zeta=f(S.n_basis), lam=f(L, L), jas=f(nj), r=f(Wk, N, 3))
+        if S.pairing:       # pairing-coefficient derivatives: pfaffian_logderiv
+            del out["lam"]
         LJ = S.LJ
         if LJ:
             pre = (Wk,) if per_walker else ()
             out.update(j1_inh=f(*pre, 2, LJ), j3=f(*pre, 3, LJ, LJ), jb_zeta=f(*pre, LJ))
-        g = Grads(dR=_ptr(out["R"]), dzeta=_ptr(out["zeta"]), dlambda=_ptr(out["lam"]),
+        g = Grads(dR=_ptr(out["R"]), dzeta=_ptr(out["zeta"]), dlambda=_ptr(out.get("lam")),
                   djas=_ptr(out["jas"]), dr=_ptr(out["r"]), dj1_inh=_ptr(out.get("j1_inh")),
                   dj3=_ptr(out.get("j3")), djb_zeta=_ptr(out.get("jb_zeta")))
         _check(load().qmc_forces(S.h, self.h, _ptr(r), 1 if per_walker else 0, _ptr(gbar_logpsi),

@@ -615,10 +615,10 @@ __global__ void __launch_bounds__(256) zero_fill_kernel(double* __restrict__ x, 
 // n_dn real rows and zero rows after them, so every product over the down side
 // sees only the paired columns; the unpaired columns add G_W[:, n_dn:] U to
 // dF/dPhi_U, and their share of dF/dQ_U is already in Yt_U.
-hipError_t launch_forces(const SysDev& s, const WalkDev& w, const AdjWork& aw, const double* ga,
-                         const double* gb, int per_walker, double* dR, double* dzeta, double* dlambda,
-                         double* djas, double* dr, double* dj1_inh, double* dj3, double* djb_zeta,
-                         hipStream_t st) {
+// dF/dPhi (aw.PB) and dF/dLambda of the geminal determinant, steps 1 to 7 of
+// the backward pass.
+static hipError_t geminal_backward(const SysDev& s, const WalkDev& w, const AdjWork& aw, const double* ga,
+                                   const double* gb, int per_walker, double* dlambda, hipStream_t st) {
   const int n = s.nu, nd = s.nd, Wk = w.Wk, Lp = s.Lp, L = s.L, N = s.N;
   const long rowst = (long)N * Lp, stk = 2L * n * Lp;
   // 1. stacked rows [Phi_U; Q_U], [Phi_D; Q_D]
@@ -728,6 +728,33 @@ hipError_t launch_forces(const SysDev& s, const WalkDev& w, const AdjWork& aw, c
       }
       HT(sum_rows(aw.lam_part, nfull + (rest ? 1 : 0), (long)L * L, dlambda, st));
     }
+  }
+  return hipSuccess;
+}
+
+// Pfaffian, log|Psi| only: d log Pf / d phi(r_i) is the cofactor vector
+// Y_i = sum_j (G~^{-1})_ji B^{s_i}_j of the evaluation (the same vector whose
+// gradient row dot gives the drift), so dF/dPhi_i = ga_w Y_i.
+__global__ void __launch_bounds__(256)
+pf_phibar_kernel(const double* __restrict__ Yt, const double* __restrict__ ga, long per_w, long tot,
+                 double* __restrict__ PB) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= tot) return;
+  PB[idx] = ga ? ga[idx / per_w] * Yt[idx] : 0.0;
+}
+
+hipError_t launch_forces(const SysDev& s, const WalkDev& w, const AdjWork& aw, const double* ga,
+                         const double* gb, int per_walker, double* dR, double* dzeta, double* dlambda,
+                         double* djas, double* dr, double* dj1_inh, double* dj3, double* djb_zeta,
+                         hipStream_t st) {
+  const int Wk = w.Wk, Lp = s.Lp, N = s.N;
+  if (s.pairing) {
+    const long per_w = (long)N * Lp, tot = per_w * Wk;
+    hipLaunchKernelGGL(pf_phibar_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, w.Yt, ga, per_w,
+                       tot, aw.PB);
+    HT(hipGetLastError());
+  } else {
+    HT(geminal_backward(s, w, aw, ga, gb, per_walker, dlambda, st));
   }
   // 8. basis and Jastrow/Coulomb backward (over the primitives of a contracted basis)
   double* drw = dr ? dr : aw.dr;

@@ -480,6 +480,8 @@ hipError_t launch_pf_propose(const SysDev& s, const WalkDev& w, int e, const dou
                              double* ratio, double* drift, hipStream_t st);
 hipError_t launch_pf_logderiv(const SysDev& s, const WalkDev& w, double* d_uu, double* d_dd, double* d_ud,
                               double* d_uup, double* d_udn, hipStream_t st);
+hipError_t launch_pf_set(const SysDev& s, const double* lam, const double* uu, const double* dd, const double* upu,
+                         const double* upd, hipStream_t st);
 hipError_t launch_pf_accept(const SysDev& s, const WalkDev& w, int e, const uint8_t* acc, const double* unif,
                             int32_t* accept_count, hipStream_t st);
 

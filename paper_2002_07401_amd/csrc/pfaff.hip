@@ -466,4 +466,41 @@ hipError_t launch_pf_logderiv(const SysDev& s, const WalkDev& w, double* d_uu, d
   return hipSuccess;
 }
 
+// ---------------------------------------------------------------------------
+// New pairing coefficients from device arrays (any may be null): A^{ud} (lam,
+// [L][L]) -> K^{ud} = A^{ud T}, K^{du} = -A^{ud}; A^{uu}, A^{dd} -> K^{uu},
+// K^{dd} (transposed); unpaired orbitals -> Upf; and the side-by-side copies
+// [K^{uu} | K^{du}], [K^{ud} | K^{dd}] used by the accept.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+pf_set_kernel(SysDev s, const double* __restrict__ lam, const double* __restrict__ uu, const double* __restrict__ dd,
+              const double* __restrict__ upu, const double* __restrict__ upd) {
+  const long L = s.L, Lp = s.Lp;
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < L * L) {
+    const long a = idx / L, b = idx % L;
+    if (lam) {
+      const double v = lam[idx];
+      s.Kud[b * Lp + a] = v;
+      s.Kdu[a * Lp + b] = -v;
+      s.Kcat_d[b * 2 * Lp + a] = v;
+      s.Kcat_u[a * 2 * Lp + Lp + b] = -v;
+    }
+    if (uu) { s.Kuu[b * Lp + a] = uu[idx]; s.Kcat_u[b * 2 * Lp + a] = uu[idx]; }
+    if (dd) { s.Kdd[b * Lp + a] = dd[idx]; s.Kcat_d[b * 2 * Lp + Lp + a] = dd[idx]; }
+  }
+  if (idx < L * s.pk) {
+    const long mu = idx / s.pk, l = idx % s.pk;
+    if (upu) s.Upf[l * Lp + mu] = upu[idx];
+    if (upd) s.Upf[((long)s.pk + l) * Lp + mu] = upd[idx];
+  }
+}
+
+hipError_t launch_pf_set(const SysDev& s, const double* lam, const double* uu, const double* dd, const double* upu,
+                         const double* upd, hipStream_t st) {
+  const long n = (long)s.L * s.L > (long)s.L * s.pk ? (long)s.L * s.L : (long)s.L * s.pk;
+  hipLaunchKernelGGL(pf_set_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s, lam, uu, dd, upu, upd);
+  return hipGetLastError();
+}
+
 }  // namespace qmc

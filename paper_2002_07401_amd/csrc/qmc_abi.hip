@@ -955,7 +955,10 @@ extern "C" qmc_status qmc_forces(qmc_system* sys, qmc_walkers* wk, const double*
   if (!r || !out) return fail(QMC_ERR_ARG, "null positions or output block");
   const SysDev& s = sys->d;
   if (s.precision != QMC_FP64) return fail(QMC_ERR_UNSUPPORTED, "forces are built for the FP64 path");
-  if (s.pairing) return fail(QMC_ERR_UNSUPPORTED, "forces of the Pfaffian are not built");
+  if (s.pairing && gbar_eloc)
+    return fail(QMC_ERR_UNSUPPORTED, "local-energy derivatives of the Pfaffian are not built (gbar_eloc must be NULL)");
+  if (s.pairing && out->dlambda)
+    return fail(QMC_ERR_ARG, "Pfaffian pairing-coefficient derivatives come from qmc_pfaffian_logderiv (dlambda must be NULL)");
   if (s.N > 2 * kLuMaxN || s.n_nuc > kMaxNucBack)
     return fail(QMC_ERR_UNSUPPORTED, "forces need N <= 256 electrons and <= 256 nuclei");
   hipError_t e = alloc_adjoint(wk);
@@ -1093,16 +1096,26 @@ extern "C" qmc_status qmc_system_set_jastrow_basis(qmc_system* sys, const double
   return QMC_OK;
 }
 
+extern "C" qmc_status qmc_system_set_pfaffian(qmc_system* sys, const double* pf_uu, const double* pf_dd,
+                                               const double* unpaired, const double* unpaired_dn, hipStream_t stream) {
+  if (!sys) return fail(QMC_ERR_ARG, "null system");
+  if (!sys->d.pairing) return fail(QMC_ERR_ARG, "the system is not a Pfaffian");
+  HIP_TRY(launch_pf_set(sys->d, nullptr, pf_uu, pf_dd, sys->d.pk ? unpaired : nullptr,
+                        sys->d.pk ? unpaired_dn : nullptr, stream), "set Pfaffian");
+  sys->generation += 1;
+  return QMC_OK;
+}
+
 extern "C" qmc_status qmc_system_set_params(qmc_system* sys, const double* R, const double* zeta,
                                             const double* lambda, const double* jas, hipStream_t stream) {
   if (!sys) return fail(QMC_ERR_ARG, "null system");
   SysDev& d = sys->d;
-  if (d.pairing) return fail(QMC_ERR_UNSUPPORTED, "parameter changes of the Pfaffian are not built");
   if (R) HIP_TRY(hipMemcpyAsync(d.R, R, sizeof(double) * 3 * d.n_nuc, hipMemcpyDeviceToDevice, stream), "set R");
   if (zeta)   // one exponent per basis function (per primitive of a contracted basis)
     HIP_TRY(hipMemcpyAsync(d.zeta, zeta, sizeof(double) * d.nprim(), hipMemcpyDeviceToDevice, stream), "set zeta");
-  if (lambda) HIP_TRY(launch_set_lambda(d, lambda, stream), "set lambda");
-  if (lambda) HIP_TRY(launch_lam_mask(d, stream), "lambda mask");
+  if (lambda && d.pairing) HIP_TRY(launch_pf_set(d, lambda, nullptr, nullptr, nullptr, nullptr, stream), "set A^ud");
+  if (lambda && !d.pairing) HIP_TRY(launch_set_lambda(d, lambda, stream), "set lambda");
+  if (lambda && !d.pairing) HIP_TRY(launch_lam_mask(d, stream), "lambda mask");
   if (R || zeta) HIP_TRY(launch_pack_basis(d, stream), "pack basis");
   if (jas) {
     HIP_TRY(hipMemcpyAsync(d.j1_b, jas, sizeof(double) * d.n_nuc, hipMemcpyDeviceToDevice, stream), "set j1");

@@ -171,12 +171,13 @@ def test_pfaffian_refusals(fw):
     P = need_gpu()
     sysh, wk, r, _ = _eval(P, fw.system, fw.r0, 4)
     one = torch.ones(4, dtype=torch.float64, device="cuda")
-    with pytest.raises(P.QMCError) as ex:
-        wk.forces(r.cuda(), one, None)
+    with pytest.raises(P.QMCError) as ex:   # local-energy derivatives
+        wk.forces(r.cuda(), one, one)
     assert ex.value.code == -5
-    with pytest.raises(P.QMCError) as ex:
-        sysh.set_params(lam=torch.tensor(fw.system.lam, device="cuda"))
-    assert ex.value.code == -5
+    det = P.JAGPSystem(_balanced(dataclasses.replace(fw.system, pairing=0)))
+    with pytest.raises(P.QMCError) as ex:   # the Pfaffian setter on a determinant system
+        det.set_pfaffian(pf_uu=torch.tensor(fw.system.pf_uu, device="cuda"))
+    assert ex.value.code == -1
     s = fw.system
     with pytest.raises(P.QMCError) as ex:   # N + k odd
         P.JAGPSystem(dataclasses.replace(s, n_dn=8))
@@ -314,3 +315,118 @@ def test_pfaffian_with_jastrow_basis_or_contraction(kind):
     rf, _, _ = O.run_chain(sy, r, d, u)
     assert torch.equal(rg, rf)
     assert rel_err(la, O.evaluate(sy, rf)["logabs"]).max().item() <= 1e-10
+
+
+def test_pfaffian_parameter_updates(fw):
+    # new nuclei, exponents, Jastrow, A^{ud} through set_params; new same-spin
+    # blocks and unpaired orbitals through set_pfaffian; re-evaluated walkers
+    # and a move ratio against the oracle of the changed system
+    P = need_gpu()
+    sysh, wk, r, _ = _eval(P, fw.system, fw.r0, 8)
+    s = fw.system
+    rng = np.random.default_rng(41)
+    L_ = len(s.lam)
+    R2 = s.R + 0.05 * rng.standard_normal(s.R.shape)
+    z2 = s.zeta * (1.0 + 0.05 * rng.standard_normal(s.zeta.shape))
+    lam2 = s.lam + 0.05 * rng.standard_normal(s.lam.shape)
+    a = rng.standard_normal((L_, L_))
+    uu2 = s.pf_uu + 0.03 * (a - a.T)
+    b = rng.standard_normal((L_, L_))
+    dd2 = s.pf_dd + 0.03 * (b - b.T)
+    up2 = s.unpaired + 0.05 * rng.standard_normal(s.unpaired.shape)
+    dn2 = s.unpaired_dn + 0.05 * rng.standard_normal(s.unpaired_dn.shape)
+    T = lambda x: torch.tensor(np.ascontiguousarray(x), device="cuda")
+    sysh.set_params(R=T(R2), zeta=T(z2), lam=T(lam2))
+    sysh.set_pfaffian(pf_uu=T(uu2), pf_dd=T(dd2), unpaired=T(up2), unpaired_dn=T(dn2))
+    with pytest.raises(P.QMCError) as ex:      # walkers must re-evaluate after a parameter change
+        wk.propose(0, r[:, 0].cuda().contiguous())
+    assert ex.value.code == -6
+    out = wk.eval_batch(r.cuda())
+    torch.cuda.synchronize()
+    s2 = dataclasses.replace(s, R=R2, zeta=z2, lam=lam2, pf_uu=uu2, pf_dd=dd2, unpaired=up2, unpaired_dn=dn2)
+    sy2 = O.from_workload_system(s2)
+    _check_eval(out, O.evaluate(sy2, r), "new parameters")
+    for e in (3, 14):
+        rn = r[:, e] + torch.tensor(fw.disp[e, :8])
+        ratio = wk.propose(e, rn.cuda().contiguous())
+        torch.cuda.synchronize()
+        assert rel_err(ratio.cpu(), O.move_ratio(sy2, r, e, rn)).max().item() <= 1e-10, e
+    # a chain through the accepts with the new coefficients
+    wk.eval_batch(r.cuda())
+    disp, unif = torch.tensor(fw.disp[:40, :8]).contiguous(), torch.tensor(fw.unif[:40, :8]).contiguous()
+    wk.vmc_steps(0, disp.cuda(), unif.cuda())
+    rg = wk.read(P.STATE_R).cpu()
+    torch.cuda.synchronize()
+    rf, _, _ = O.run_chain(sy2, r, disp, unif)
+    assert torch.equal(rg, rf)
+
+
+def _oracle_pf_log_grads(sy, r):
+    """Per-walker autodiff of log|Psi| = 1/2 log|det G~| + J (the half log-det
+    is pinned to the Parlett-Reid log|Pf| in the oracle tests) with respect to
+    R, the (primitive) exponents, the Jastrow vector, r and, with a Jastrow
+    basis, its coefficients (same-spin blocks symmetrised) and exponents."""
+    A = sy.R.shape[0]
+    keys = ["R", "zeta", "jas", "r"] + (["j1_inh", "j3", "jb_zeta"] if sy.n_jbasis else [])
+    out = {k: [] for k in keys}
+    for w in range(r.shape[0]):
+        leaf = lambda t: t.detach().clone().requires_grad_(True)
+        R, z, jas, rr = leaf(sy.R), leaf(sy.zeta), leaf(torch.cat([sy.j1_b, sy.j2])), leaf(r[w:w + 1])
+        leaves = [R, z, jas, rr]
+        sw = sy
+        if sy.n_jbasis:
+            j1, j3, jz = leaf(sy.j1_inh), leaf(sy.j3), leaf(sy.jb_zeta)
+            sw = dataclasses.replace(sy, j1_inh=j1, j3=j3, jb_zeta=jz)
+            leaves += [j1, j3, jz]
+        G = PF.pairing_matrix(sw, O.agp_basis(sw, rr, R, z)[0])
+        lp = 0.5 * torch.linalg.slogdet(G)[1] + O.jastrow(sw, rr, R, jas[:A], jas[A:])[0]
+        g = list(torch.autograd.grad(lp.sum(), leaves))
+        g[3] = g[3][0]
+        if sy.n_jbasis:
+            g3 = g[5].clone()
+            g3[0] = 0.5 * (g3[0] + g3[0].T)
+            g3[1] = 0.5 * (g3[1] + g3[1].T)
+            g[5] = g3
+        for k, v in zip(keys, g):
+            out[k].append(v)
+    return {k: torch.stack(v) for k, v in out.items()}
+
+
+@pytest.mark.parametrize("kind", ["plain", "jastrow_basis", "contracted"])
+def test_pfaffian_log_derivative_adjoint(fw, kind):
+    # qmc_forces on a Pfaffian, log|Psi| only: dF/dphi(r_i) = g_w Y_i, then the
+    # basis and Jastrow backward passes of the determinant path
+    P = need_gpu()
+    if kind == "plain":
+        s, r0 = fw.system, fw.r0
+    else:
+        _, s = _pf_variant(kind)
+        r0 = C.random_positions(63, s, 6)
+    Wk = 6
+    _, wk, r, _ = _eval(P, s, r0, Wk)
+    sy = O.from_workload_system(s)
+    ref = _oracle_pf_log_grads(sy, r)
+    one = torch.ones(Wk, dtype=torch.float64, device="cuda")
+    per = wk.forces(r.cuda(), one, None, per_walker=True)
+    torch.cuda.synchronize()
+    assert "lam" not in per
+    for k, b in ref.items():
+        a = per[k].cpu()
+        err = (a - b).abs().max().item() / max(1.0, b.abs().max().item())
+        print(f"[pfaffian log adjoint {kind}] {k}: {err:.3e}")
+        assert err <= 1e-9, (k, err)
+    # d log|Psi| / dr is the drift
+    dref = O.evaluate(sy, r)["drift"]
+    assert ((per["r"].cpu() - dref).abs() / dref.abs().clamp(min=1.0)).max().item() <= 1e-9
+    # summed with weights
+    g = torch.tensor(np.random.default_rng(9).normal(size=Wk))
+    tot = wk.forces(r.cuda(), g.cuda(), None)
+    torch.cuda.synchronize()
+    for k in ("R", "zeta", "jas"):
+        b = (g.view(-1, *([1] * (ref[k].dim() - 1))) * ref[k]).sum(0)
+        err = (tot[k].cpu() - b).abs().max().item() / max(1.0, b.abs().max().item())
+        assert err <= 1e-9, (k, err)
+    # the refusals: local-energy weights, pairing-coefficient output
+    with pytest.raises(P.QMCError) as ex:
+        wk.forces(r.cuda(), one, one)
+    assert ex.value.code == -5
