@@ -145,7 +145,7 @@ typedef struct {
    * (eq:pfodd): G~_{i, N+l} = phi(r_i) . U^{s_i}[:, l] with U^u = unpaired
    * and U^d = pf_unpaired_dn.  N + pf_k must be even and at most 96; FP64
    * precision only; n_up < n_dn is allowed.  Not supported with it:
-   * qmc_forces' local-energy part, qmc_multi_*.  qmc_reweight uses G~ and its inverse;
+   * qmc_forces' pairing-coefficient output, qmc_multi_*.  qmc_reweight uses G~ and its inverse;
    * qmc_system_set_params (lambda = A^{ud}) and qmc_system_set_pfaffian change
    * the coefficients. */
   int32_t pairing;            /* 0 AGP determinant, 1 Pfaffian                   */
@@ -281,11 +281,11 @@ typedef struct {
  * Re-evaluates the walkers at r (their state becomes that of qmc_eval_batch).
  * FP64 systems with N <= 256 electrons and <= 256 nuclei.  The first call on
  * a walker set allocates its workspace.
- * Pfaffian systems: log|Psi| only (d log Pf / d phi(r_i) is the evaluation's
- * cofactor vector of electron i): gbar_eloc must be NULL (QMC_ERR_UNSUPPORTED)
- * and dlambda NULL (QMC_ERR_ARG; the pairing coefficients' log-derivatives come
- * from qmc_pfaffian_logderiv); dR, dzeta, djas, dr and the Jastrow-basis
- * outputs are as above. */
+ * Pfaffian systems: dR, dzeta, djas, dr and the Jastrow-basis outputs as
+ * above (log|Psi| through the cofactor vectors Y_i, e_L through Y, G~^{-1} and
+ * the pairing rows); dlambda must be NULL (QMC_ERR_ARG): the pairing
+ * coefficients' log-derivatives come from qmc_pfaffian_logderiv, their
+ * local-energy derivatives are not built. */
 qmc_status qmc_forces(qmc_system *sys, qmc_walkers *wk, const double *r, int32_t per_walker,
                       const double *gbar_logpsi, const double *gbar_eloc, const qmc_grads *out,
                       hipStream_t stream);

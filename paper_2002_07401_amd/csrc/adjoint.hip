@@ -732,15 +732,113 @@ static hipError_t geminal_backward(const SysDev& s, const WalkDev& w, const AdjW
   return hipSuccess;
 }
 
-// Pfaffian, log|Psi| only: d log Pf / d phi(r_i) is the cofactor vector
-// Y_i = sum_j (G~^{-1})_ji B^{s_i}_j of the evaluation (the same vector whose
-// gradient row dot gives the drift), so dF/dPhi_i = ga_w Y_i.
+// ---------------------------------------------------------------------------
+// Pfaffian: dF/dPhi for F = ga log|Psi| + gb e_L.
+//  * log|Psi|: d log Pf / d phi(r_i) is the cofactor vector Y_i =
+//    sum_j H_ji B^{s_i}_j (H = G~^{-1}), the vector whose gradient row dot is
+//    the drift.
+//  * e_L depends on Phi directly (the basis backward's derivative channels) and
+//    through Y, with dF/dY_i = c Q_i, c = -gb/2, Q_i = lap phi_i + 2 grad J_i .
+//    grad phi_i.  Y depends on H and on the rows B^s_j = A^{s s_j} phi_j:
+//      dF/dH_ji = c T_ij,  T_ij = Q_i . B^{s_i}_j (unpaired j: Q_i . U^{s_i}_l);
+//      dH = -H dG~ H gives dF/dG~ = -c (H T H)^T = -c Z^T, and as G~_ij =
+//      phi_i^T A^{s_i s_j} phi_j with A^{s' s} = -(A^{s s'})^T,
+//      dF/dphi_i = c sum_j (Z^T - Z)_ji B^{s_i}_j (the cofactor products with
+//      X = Z^T - Z in place of H);
+//      dF/dB^s_j = c sum_{i of spin s} H_ji Q_i, and B^s_j = A^{s s_j} phi_j
+//      gives dF/dphi_j += c [H Q_up | H Q_dn]_j [A^{u s_j} ; A^{d s_j}].
+// ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256)
-pf_phibar_kernel(const double* __restrict__ Yt, const double* __restrict__ ga, long per_w, long tot,
-                 double* __restrict__ PB) {
+pf_skew_kernel(const double* __restrict__ Z, long np, long tot, double* __restrict__ X) {
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= tot) return;
-  PB[idx] = ga ? ga[idx / per_w] * Yt[idx] : 0.0;
+  const long w = idx / (np * np), ab = idx % (np * np), a = ab / np, b = ab % np;
+  const double* z = Z + w * np * np;
+  X[idx] = z[b * np + a] - z[a * np + b];
+}
+
+__global__ void __launch_bounds__(256)
+pf_phibar_kernel(const double* __restrict__ Yt, const double* __restrict__ Yb, const double* __restrict__ ga,
+                 const double* __restrict__ gb, long per_w, long tot, double* __restrict__ PB) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= tot) return;
+  const long w = idx / per_w;
+  double v = ga ? ga[w] * Yt[idx] : 0.0;
+  if (gb) v += -0.5 * gb[w] * Yb[idx];
+  PB[idx] = v;
+}
+
+static hipError_t pf_backward(const SysDev& s, const WalkDev& w, const AdjWork& aw, const double* ga,
+                              const double* gb, hipStream_t st) {
+  const int Wk = w.Wk, Lp = s.Lp, N = s.N, n = s.nu, nd = s.nd, np = s.npf, pk = s.pk;
+  const long rowst = (long)N * Lp, stk = 2L * n * Lp, nn = (long)np * np;
+  if (gb) {
+    hipLaunchKernelGGL(stack_basis_kernel, dim3((unsigned)((long)Wk * N)), dim3(256), 0, st, s, w, aw.SU, aw.SD);
+    HT(hipGetLastError());
+    // T rows of the up then the down electrons (rows N.. stay zero)
+    for (int sp = 0; sp < 2; ++sp) {
+      const int i0 = sp ? n : 0, ni = sp ? nd : n;
+      if (ni == 0) continue;
+      const double* Q = (sp ? aw.SD : aw.SU) + (long)n * Lp;
+      GemmArgs g = gemm_args(ni, N, Lp);
+      g.A = Q; g.lda = Lp; g.a_bs = stk;
+      g.B = sp ? w.Bd : (const double*)w.P; g.ldb = Lp; g.b_bs = rowst;
+      g.C = aw.pfT + (long)i0 * np; g.ldc = np; g.c_bs = nn; g.batch = Wk;
+      HT(gemm_f64(g, false, true, false, st));
+      if (pk > 0) {
+        GemmArgs u = gemm_args(ni, pk, Lp);
+        u.A = Q; u.lda = Lp; u.a_bs = stk;
+        u.B = s.Upf + (long)sp * pk * Lp; u.ldb = Lp; u.b_bs = 0;
+        u.C = aw.pfT + (long)i0 * np + N; u.ldc = np; u.c_bs = nn; u.batch = Wk;
+        HT(gemm_f64(u, false, true, false, st));
+      }
+    }
+    // Z = H T H, then X = Z^T - Z (into pfZ1)
+    {
+      GemmArgs g = gemm_args(np, np, np);
+      g.A = w.A; g.lda = np; g.a_bs = nn;
+      g.B = aw.pfT; g.ldb = np; g.b_bs = nn;
+      g.C = aw.pfZ1; g.ldc = np; g.c_bs = nn; g.batch = Wk;
+      HT(gemm_f64(g, false, false, false, st));
+      g.A = aw.pfZ1; g.B = w.A; g.C = aw.pfZ;
+      HT(gemm_f64(g, false, false, false, st));
+      const long tot = nn * Wk;
+      hipLaunchKernelGGL(pf_skew_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, aw.pfZ, (long)np,
+                         tot, aw.pfZ1);
+      HT(hipGetLastError());
+    }
+    HT(launch_pf_Y_products(s, w, aw.pfZ1, aw.pfY, st));
+    // [H Q_up | H Q_dn] rows j < N, then times [A^{u s_j} ; A^{d s_j}] = Kcat_{s_j}^T
+    {
+      GemmArgs g = gemm_args(N, Lp, n);
+      g.A = w.A; g.lda = np; g.a_bs = nn;
+      g.B = aw.SU + (long)n * Lp; g.ldb = Lp; g.b_bs = stk;
+      g.C = aw.pfBb; g.ldc = 2L * Lp; g.c_bs = 2 * rowst; g.batch = Wk;
+      HT(gemm_f64(g, false, false, false, st));
+      if (nd > 0) {
+        g.K = nd;
+        g.A = w.A + n;
+        g.B = aw.SD + (long)n * Lp;
+        g.C = aw.pfBb + Lp;
+        HT(gemm_f64(g, false, false, false, st));
+      }
+      for (int sp = 0; sp < 2; ++sp) {
+        const int j0 = sp ? n : 0, nj = sp ? nd : n;
+        if (nj == 0) continue;
+        // with no down electrons only the H Q_up half exists
+        GemmArgs k = gemm_args(nj, Lp, nd > 0 ? 2 * Lp : Lp);
+        k.A = aw.pfBb + (long)j0 * 2 * Lp; k.lda = 2L * Lp; k.a_bs = 2 * rowst;
+        k.B = sp ? s.Kcat_d : s.Kcat_u; k.ldb = 2L * Lp; k.b_bs = 0;
+        k.C = aw.pfY + (long)j0 * Lp; k.ldc = Lp; k.c_bs = rowst; k.batch = Wk;
+        k.accumulate = 1;
+        HT(gemm_f64(k, false, true, false, st));
+      }
+    }
+  }
+  const long tot = rowst * Wk;
+  hipLaunchKernelGGL(pf_phibar_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, w.Yt, aw.pfY, ga, gb,
+                     rowst, tot, aw.PB);
+  return hipGetLastError();
 }
 
 hipError_t launch_forces(const SysDev& s, const WalkDev& w, const AdjWork& aw, const double* ga,
@@ -749,10 +847,7 @@ hipError_t launch_forces(const SysDev& s, const WalkDev& w, const AdjWork& aw, c
                          hipStream_t st) {
   const int Wk = w.Wk, Lp = s.Lp, N = s.N;
   if (s.pairing) {
-    const long per_w = (long)N * Lp, tot = per_w * Wk;
-    hipLaunchKernelGGL(pf_phibar_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, w.Yt, ga, per_w,
-                       tot, aw.PB);
-    HT(hipGetLastError());
+    HT(pf_backward(s, w, aw, ga, gb, st));
   } else {
     HT(geminal_backward(s, w, aw, ga, gb, per_walker, dlambda, st));
   }

@@ -227,6 +227,10 @@ struct AdjWork {
   // per-function position sums [LJ][3]; drift as 4-vectors [Wk][N][4]
   int LJp;
   double *ju, *jgv, *jac, *jpb, *jhu, *jX, *jH, *jdm, *jC, *jdM, *jzbar, *jtmu, *drift4;
+  // Pfaffian (npf = N + k): T = [Q_i . B^{s_i}_j] and the products H T, H T H
+  // [Wk][npf][npf]; [H Q_up | H Q_dn] rows [Wk][N][2 Lp]; dF/dPhi through G~
+  // and the B rows [Wk][N][Lp]
+  double *pfT, *pfZ1, *pfZ, *pfBb, *pfY;
   int chunk_walkers;
   int chunks;
 };
@@ -475,6 +479,7 @@ hipError_t launch_gj_inverse_n(int Wk, int n, const double* W, double* A, double
 hipError_t launch_pf_B_build(const SysDev& s, const WalkDev& w, hipStream_t st);
 hipError_t launch_pf_G_build(const SysDev& s, const WalkDev& w, hipStream_t st);
 hipError_t launch_pf_factor(const SysDev& s, const WalkDev& w, hipStream_t st);
+hipError_t launch_pf_Y_products(const SysDev& s, const WalkDev& w, const double* X, double* out, hipStream_t st);
 hipError_t launch_pf_Y_build(const SysDev& s, const WalkDev& w, hipStream_t st);
 hipError_t launch_pf_propose(const SysDev& s, const WalkDev& w, int e, const double* r_new, const double* disp,
                              double* ratio, double* drift, hipStream_t st);

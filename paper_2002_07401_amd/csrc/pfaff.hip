@@ -205,23 +205,25 @@ hipError_t launch_pf_factor(const SysDev& s, const WalkDev& w, hipStream_t st) {
 // ---------------------------------------------------------------------------
 // Cofactor vectors Y_i = sum_{j<N} (G~^{-1})_ji B^{s_i}_j + sum_l (G~^{-1})_{N+l,i} U^{s_i}_l
 // ---------------------------------------------------------------------------
-hipError_t launch_pf_Y_build(const SysDev& s, const WalkDev& w, hipStream_t st) {
+// Products sum_j X_ji B^{s_i}_j (+ unpaired rows) for any npf x npf matrix X
+// (X = G~^{-1} gives the cofactor vectors; the adjoint uses other X).
+hipError_t launch_pf_Y_products(const SysDev& s, const WalkDev& w, const double* X, double* out, hipStream_t st) {
   const long rowst = (long)s.N * s.Lp, n = s.npf;
   for (int sp = 0; sp < 2; ++sp) {
     const int i0 = sp == 0 ? 0 : s.nu, ni = sp == 0 ? s.nu : s.nd;
     if (ni == 0) continue;
     GemmArgs g = gemm_args(ni, s.Lp, s.N);
-    g.A = w.A + i0; g.lda = n; g.a_bs = n * n;                  // stored [j][i]: op(A) = A^T
+    g.A = X + i0; g.lda = n; g.a_bs = n * n;                    // stored [j][i]: op(A) = A^T
     g.B = sp == 0 ? (const double*)w.P : w.Bd; g.ldb = s.Lp; g.b_bs = rowst;
-    g.C = w.Yt + (long)i0 * s.Lp; g.ldc = s.Lp; g.c_bs = rowst;
+    g.C = out + (long)i0 * s.Lp; g.ldc = s.Lp; g.c_bs = rowst;
     g.batch = w.Wk;
     hipError_t e = gemm_f64(g, true, false, false, st);
     if (e != hipSuccess) return e;
     if (s.pk > 0) {
       GemmArgs u = gemm_args(ni, s.Lp, s.pk);
-      u.A = w.A + (long)s.N * n + i0; u.lda = n; u.a_bs = n * n;
+      u.A = X + (long)s.N * n + i0; u.lda = n; u.a_bs = n * n;
       u.B = s.Upf + (long)sp * s.pk * s.Lp; u.ldb = s.Lp; u.b_bs = 0;
-      u.C = w.Yt + (long)i0 * s.Lp; u.ldc = s.Lp; u.c_bs = rowst;
+      u.C = out + (long)i0 * s.Lp; u.ldc = s.Lp; u.c_bs = rowst;
       u.batch = w.Wk;
       u.accumulate = 1;
       e = gemm_f64(u, true, false, false, st);
@@ -229,6 +231,10 @@ hipError_t launch_pf_Y_build(const SysDev& s, const WalkDev& w, hipStream_t st) 
     }
   }
   return hipSuccess;
+}
+
+hipError_t launch_pf_Y_build(const SysDev& s, const WalkDev& w, hipStream_t st) {
+  return launch_pf_Y_products(s, w, w.A, w.Yt, st);
 }
 
 // ---------------------------------------------------------------------------

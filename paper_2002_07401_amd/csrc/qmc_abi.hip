@@ -918,6 +918,14 @@ static hipError_t alloc_adjoint(qmc_walkers* wk) {
   al(&a.tmu, Wk * Lb * 3);
   al(&a.Rbar, Wk * A * 3);
   al(&a.zbar, Wk * Lb);
+  if (s.pairing) {
+    const size_t np = s.npf;
+    al(&a.pfT, Wk * np * np);
+    al(&a.pfZ1, Wk * np * np);
+    al(&a.pfZ, Wk * np * np);
+    al(&a.pfBb, Wk * N * 2 * Lp);
+    al(&a.pfY, Wk * N * Lp);
+  }
   if (s.Lq) {
     const size_t lqp = (s.Lq + 31) / 32 * 32;
     al(&a.PBq, Wk * N * lqp);
@@ -955,8 +963,6 @@ extern "C" qmc_status qmc_forces(qmc_system* sys, qmc_walkers* wk, const double*
   if (!r || !out) return fail(QMC_ERR_ARG, "null positions or output block");
   const SysDev& s = sys->d;
   if (s.precision != QMC_FP64) return fail(QMC_ERR_UNSUPPORTED, "forces are built for the FP64 path");
-  if (s.pairing && gbar_eloc)
-    return fail(QMC_ERR_UNSUPPORTED, "local-energy derivatives of the Pfaffian are not built (gbar_eloc must be NULL)");
   if (s.pairing && out->dlambda)
     return fail(QMC_ERR_ARG, "Pfaffian pairing-coefficient derivatives come from qmc_pfaffian_logderiv (dlambda must be NULL)");
   if (s.N > 2 * kLuMaxN || s.n_nuc > kMaxNucBack)

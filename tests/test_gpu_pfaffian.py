@@ -3,6 +3,7 @@ against the oracle, at the FP64 bars of the determinant path: relative 1e-10
 on log|Psi|, E_kin, E_loc and move ratios, 1e-8 on drifts; signs equal; chains
 bitwise; the maintained inverse within 1e-9 of the oracle's after a chain.
 """
+import ctypes
 import dataclasses
 
 import numpy as np
@@ -171,9 +172,12 @@ def test_pfaffian_refusals(fw):
     P = need_gpu()
     sysh, wk, r, _ = _eval(P, fw.system, fw.r0, 4)
     one = torch.ones(4, dtype=torch.float64, device="cuda")
-    with pytest.raises(P.QMCError) as ex:   # local-energy derivatives
-        wk.forces(r.cuda(), one, one)
-    assert ex.value.code == -5
+    from paper_2002_07401_amd import binding as B
+    lam_out = torch.empty(44, 44, dtype=torch.float64, device="cuda")
+    g = B.Grads(dlambda=B._ptr(lam_out))
+    with pytest.raises(P.QMCError) as ex:   # pairing-coefficient gradients: pfaffian_logderiv
+        B._check(B.load().qmc_forces(sysh.h, wk.h, B._ptr(r.cuda()), 0, B._ptr(one), None, ctypes.byref(g), None))
+    assert ex.value.code == -1
     det = P.JAGPSystem(_balanced(dataclasses.replace(fw.system, pairing=0)))
     with pytest.raises(P.QMCError) as ex:   # the Pfaffian setter on a determinant system
         det.set_pfaffian(pf_uu=torch.tensor(fw.system.pf_uu, device="cuda"))
@@ -426,7 +430,74 @@ def test_pfaffian_log_derivative_adjoint(fw, kind):
         b = (g.view(-1, *([1] * (ref[k].dim() - 1))) * ref[k]).sum(0)
         err = (tot[k].cpu() - b).abs().max().item() / max(1.0, b.abs().max().item())
         assert err <= 1e-9, (k, err)
-    # the refusals: local-energy weights, pairing-coefficient output
-    with pytest.raises(P.QMCError) as ex:
-        wk.forces(r.cuda(), one, one)
-    assert ex.value.code == -5
+
+
+def _oracle_pf_forces(sy, r, gl, ge):
+    """Autodiff of sum_w (gl log|Psi| + ge e_L) with respect to R, the
+    exponents, the Jastrow vector, r and the Jastrow-basis parameters; e_L from
+    the oracle's Pfaffian evaluation (G~^{-1} by a library inverse, which
+    autodiff differentiates), log|Psi| as in _oracle_pf_log_grads."""
+    A = sy.R.shape[0]
+    leaf = lambda t: t.detach().clone().requires_grad_(True)
+    R, z, jas, rr = leaf(sy.R), leaf(sy.zeta), leaf(torch.cat([sy.j1_b, sy.j2])), leaf(r)
+    keys, leaves = ["R", "zeta", "jas", "r"], [R, z, jas, rr]
+    repl = dict(R=R, zeta=z, j1_b=jas[:A], j2=jas[A:])
+    if sy.n_jbasis:
+        j1, j3, jz = leaf(sy.j1_inh), leaf(sy.j3), leaf(sy.jb_zeta)
+        repl.update(j1_inh=j1, j3=j3, jb_zeta=jz)
+        keys += ["j1_inh", "j3", "jb_zeta"]
+        leaves += [j1, j3, jz]
+    sw = dataclasses.replace(sy, **repl)
+    G = PF.pairing_matrix(sw, O.agp_basis(sw, rr)[0])
+    lp = 0.5 * torch.linalg.slogdet(G)[1] + O.jastrow(sw, rr)[0]
+    el = O.evaluate(sw, rr)["e_loc"]
+    F = (gl * lp).sum() + (ge * el).sum()
+    g = list(torch.autograd.grad(F, leaves))
+    if sy.n_jbasis:
+        g3 = g[5].clone()
+        g3[0] = 0.5 * (g3[0] + g3[0].T)
+        g3[1] = 0.5 * (g3[1] + g3[1].T)
+        g[5] = g3
+    return dict(zip(keys, g))
+
+
+@pytest.mark.parametrize("kind", ["plain", "jastrow_basis", "contracted"])
+def test_pfaffian_forces_match_oracle(fw, kind):
+    # local-energy derivatives through Y, G~^{-1} and the pairing rows B
+    P = need_gpu()
+    if kind == "plain":
+        s, r0 = fw.system, fw.r0
+    else:
+        _, s = _pf_variant(kind)
+        r0 = C.random_positions(65, s, 6)
+    Wk = 6
+    _, wk, r, _ = _eval(P, s, r0, Wk)
+    sy = O.from_workload_system(s)
+    rng = np.random.default_rng(17)
+    gl = torch.tensor(rng.normal(size=Wk))
+    ge = torch.tensor(rng.normal(size=Wk))
+    out = wk.forces(r.cuda(), gl.cuda(), ge.cuda())
+    torch.cuda.synchronize()
+    ref = _oracle_pf_forces(sy, r, gl, ge)
+    for k, b in ref.items():
+        a = out[k].cpu()
+        err = (a - b).abs().max().item() / max(1.0, b.abs().max().item())
+        print(f"[pfaffian forces {kind}] {k}: {err:.3e}")
+        assert err <= 1e-8, (k, err)
+    if kind != "plain":
+        return
+    # per walker, e_L only, against central differences of the oracle's e_L in R
+    one = torch.ones(Wk, dtype=torch.float64, device="cuda")
+    per = wk.forces(r.cuda(), None, one, per_walker=True)
+    torch.cuda.synchronize()
+    h = 1e-5
+    for a_, c_ in ((0, 0), (2, 1), (3, 2)):
+        Rp, Rm = s.R.copy(), s.R.copy()
+        Rp[a_, c_] += h
+        Rm[a_, c_] -= h
+        ep = O.evaluate(O.from_workload_system(dataclasses.replace(s, R=Rp)), r)["e_loc"]
+        em = O.evaluate(O.from_workload_system(dataclasses.replace(s, R=Rm)), r)["e_loc"]
+        fd = (ep - em) / (2 * h)
+        err = ((per["R"][:, a_, c_].cpu() - fd).abs() / fd.abs().clamp(min=1.0)).max().item()
+        print(f"[pfaffian forces FD] R[{a_},{c_}]: {err:.3e}")
+        assert err <= 1e-6, (a_, c_, err)
