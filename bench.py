@@ -29,7 +29,9 @@ import torch  # noqa: E402
 
 METRIC = "walker-electron moves/s + E_loc evals/s at 160e, mixed vs FP64, err vs oracle"
 HBM_PEAK_GBS = 8000.0
-MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "mixed": 157.3, "bf16": 157.3}
+# the evaluation's P = Phi Lambda product runs on FP64 MFMA in every mode but
+# fp32 (QMC_W_FP32, FP32 operands and accumulation)
+MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "mixed": 78.6, "bf16": 78.6}
 
 
 def parse():
@@ -116,7 +118,9 @@ def kernel_models(s, Wk, esz, acc_rate):
              the buffer restarts at every refresh (after min(refresh_every, 64)
              moves of one spin and at each change of spin) and grows by the
              acceptance rate per move.
-    P_build: 2 L^2 flops per basis row, over the Wk * N/2 rows of one spin.
+    P_build: the evaluation's P = Phi Lambda for both spins, 2 L^2 flops per
+             basis row over Wk * N rows (the one-spin rebuilds before moves
+             have a timer of their own).
     """
     L, N, n = s.n_basis, s.n_up + s.n_dn, s.n_up
     cap = min(s.refresh_every, 64)
@@ -125,7 +129,7 @@ def kernel_models(s, Wk, esz, acc_rate):
     prop = Wk * (esz * n * L + 8 * L + 8 * n + 8 * n)
     acc = Wk * acc_rate * (8 * n * (3 + m) + 8 * m * m + 16 * m + 8 * L
                            + 16 * n + 8 * (m + 1) ** 2 + 8 * n + esz * L)
-    pflops = 2.0 * L * L * Wk * n
+    pflops = 2.0 * L * L * Wk * N
     return {"propose": ("hbm", prop), "accept": ("latency", acc), "P_build": ("mfma", pflops)}
 
 
@@ -237,6 +241,13 @@ def run_precision(P, C, w, args, precision):
         roof = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 2), "peak": peak,
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
                 "flops_per_launch": int(units), "avg_launch_us": round(avg_ms * 1e3, 2)}
+    # MFMA use of the geminal build's dominant product (P = Phi Lambda in the
+    # evaluations of the timed steps)
+    pf_ms = tim["P_build"][0] / max(tim["P_build"][1], 1)
+    pf_tf = models["P_build"][1] / (pf_ms * 1e-3) / 1e12
+    wmfma = {"kernel": "P_build", "achieved": round(pf_tf, 2), "peak": MFMA_PEAK_TFLOPS[precision],
+             "unit": "TFLOP/s", "frac": round(pf_tf / MFMA_PEAK_TFLOPS[precision], 4),
+             "flops_per_launch": int(models["P_build"][1]), "avg_launch_us": round(pf_ms * 1e3, 2)}
     wk.close()
     sysh.close()
     return {
@@ -251,6 +262,7 @@ def run_precision(P, C, w, args, precision):
         "kernel_launches_one_step": {k: v[1] for k, v in one.items() if v[1]},
         "dominant_kernel": dominant,
         "roofline": roof,
+        "w_build_mfma": wmfma,
     }
 
 
@@ -481,9 +493,26 @@ def pfaffian_leg(P, C, steps=160, Wk=512):
     # algorithmic bytes of one proposal launch: the n B rows and the inverse column of every walker
     prop_bytes = Wk * (n * Lp * 8 + n * 8)
     prop_us = 1e3 * prop[0] / max(prop[1], 1)
+    # adjoint (log|Psi| and e_L weights, summed over walkers) against one evaluation
+    one = torch.ones(Wk, dtype=torch.float64, device=dev)
+    rf = wk.read(P.STATE_R)
+    wk.forces(rf, one, one)
+    torch.cuda.synchronize()
+    f0, f1, f2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    reps = 3
+    f0.record()
+    for _ in range(reps):
+        wk.eval_batch(rf)
+    f1.record()
+    for _ in range(reps):
+        wk.forces(rf, one, one)
+    f2.record()
+    torch.cuda.synchronize()
+    t_ev, t_fo = f0.elapsed_time(f1) / reps, f1.elapsed_time(f2) / reps
     wk.close()
     sysh.close()
     return {"workload": "pfaffian_20nuc_80e", "walkers": Wk, "precision": "fp64", "pfaffian_dim": n,
+            "forces_ms": round(t_fo, 3), "eval_ms": round(t_ev, 3), "forces_over_eval": round(t_fo / t_ev, 2),
             "eloc_evals_per_s": round(Wk / t_eval, 1), "moves_per_s": round(steps * Wk / t_move, 1),
             "acceptance": round(cnt.sum().item() / (steps * Wk), 4), "moves": steps,
             "propose_avg_us": round(prop_us, 2),
@@ -570,6 +599,7 @@ def main():
         "kernel_ms_one_step": head["kernel_ms_one_step"],
         "dominant_kernel": head["dominant_kernel"],
         "roofline": head["roofline"],
+        "w_build_mfma": head["w_build_mfma"],
     }
     for p, rec in sides.items():
         res[p] = rec

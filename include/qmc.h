@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define QMC_ABI_VERSION 13
+#define QMC_ABI_VERSION 14
 
 typedef enum {
   QMC_OK = 0,
@@ -501,7 +501,7 @@ qmc_status qmc_walkers_read(qmc_walkers *wk, int32_t item, double *dst, hipStrea
  * call's stream, and the elapsed times are summed per timer. */
 typedef enum {
   QMC_T_BASIS = 0,     /* basis values                                   */
-  QMC_T_P_BUILD = 1,   /* P = Phi Lambda (eval and rebuilds before moves)  */
+  QMC_T_P_BUILD = 1,   /* P = Phi Lambda of an evaluation (both spins)    */
   QMC_T_W_BUILD = 2,   /* W = P_up Phi_dn^T                              */
   QMC_T_LU = 3,        /* FP64 LU inverse / log-det (eval and refresh)   */
   QMC_T_Y_BUILD = 4,   /* cofactor products for the local energy         */
@@ -515,7 +515,8 @@ typedef enum {
                               change                                      */
   QMC_T_LRDMC_HOPS = 11,   /* lattice hop ratios and Green's function terms */
   QMC_T_LRDMC_STEP = 12,   /* continuous-time lattice step                  */
-  QMC_TIMER_COUNT = 13
+  QMC_T_P_REBUILD = 13,    /* one spin's P rows rebuilt before its moves    */
+  QMC_TIMER_COUNT = 14
 } qmc_timer;
 
 /* enable != 0 turns every timer on and clears the sums; 0 turns timing off. */

@@ -631,10 +631,10 @@ static qmc_status ensure_P(qmc_walkers* wk, int e, hipStream_t stream) {
   const SysDev& s = wk->sys->d;
   const bool up = e < s.nu;
   if (up && !wk->P_dn_valid) {
-    TIMED(wk, QMC_T_P_BUILD, stream, launch_P_build(s, wk->d, 2, stream), "P_dn rebuild");
+    TIMED(wk, QMC_T_P_REBUILD, stream, launch_P_build(s, wk->d, 2, stream), "P_dn rebuild");
     wk->P_dn_valid = true;
   } else if (!up && !wk->P_up_valid) {
-    TIMED(wk, QMC_T_P_BUILD, stream, launch_P_build(s, wk->d, 1, stream), "P_up rebuild");
+    TIMED(wk, QMC_T_P_REBUILD, stream, launch_P_build(s, wk->d, 1, stream), "P_up rebuild");
     wk->P_up_valid = true;
   }
   return QMC_OK;
