@@ -241,6 +241,7 @@ def run_precision(P, C, w, args, precision):
         roof = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 2), "peak": peak,
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
                 "flops_per_launch": int(units), "avg_launch_us": round(avg_ms * 1e3, 2)}
+    steps = step_rooflines(s, Wk, precision, one, roof) if roof["kernel"] == "propose" else None
     # MFMA use of the geminal build's dominant product (P = Phi Lambda in the
     # evaluations of the timed steps)
     pf_ms = tim["P_build"][0] / max(tim["P_build"][1], 1)
@@ -263,6 +264,7 @@ def run_precision(P, C, w, args, precision):
         "dominant_kernel": dominant,
         "roofline": roof,
         "w_build_mfma": wmfma,
+        "step_rooflines": steps,
     }
 
 
@@ -560,6 +562,72 @@ def sr_leg(P, M=4096, Pn=8192, iters=40, eps=1e-3):
             "residual": float(f"{res.item():.3e}"), "residual_check": float(f"{chk:.3e}")}
 
 
+def achievable_peaks():
+    """Achievable peaks on this GPU beside the datasheet ones (best of 5): a
+    STREAM-like 1 GiB copy (bytes read + written per second) and an 8192^3
+    FP64 matrix product from the vendor library (flops per second).  These are
+    measurement references only."""
+    dev = torch.device("cuda:0")
+    n = (1 << 30) // 8
+    a = torch.ones(n, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    best = float("inf")
+    for _ in range(6):
+        ev[0].record()
+        b.copy_(a)
+        ev[1].record()
+        torch.cuda.synchronize()
+        best = min(best, ev[0].elapsed_time(ev[1]))
+    copy_gbs = 2 * n * 8 / (best * 1e-3) / 1e9
+    del a, b
+    m = 8192
+    g = torch.Generator(device=dev).manual_seed(3)
+    x = torch.randn(m, m, generator=g, dtype=torch.float64, device=dev)
+    y = torch.randn(m, m, generator=g, dtype=torch.float64, device=dev)
+    z = torch.empty_like(x)
+    best = float("inf")
+    for _ in range(6):
+        ev[0].record()
+        torch.matmul(x, y, out=z)
+        ev[1].record()
+        torch.cuda.synchronize()
+        best = min(best, ev[0].elapsed_time(ev[1]))
+    del x, y, z
+    return {"hbm_copy_GBps": round(copy_gbs, 1), "fp64_gemm_TFLOPs": round(2 * m ** 3 / (best * 1e-3) / 1e12, 2),
+            "datasheet": {"hbm_GBps": HBM_PEAK_GBS, "fp64_TFLOPs": 78.6, "fp32_TFLOPs": 157.3}}
+
+
+def step_rooflines(s, Wk, precision, one, prop_roof):
+    """Roofline of each step of one evaluation (and the proposal) from the
+    one-step timers: algorithmic bytes or flops per launch / average launch.
+      basis:   writes the N x L values of every walker (FP64; FP32 in fp32 mode)
+      P_build: 2 L^2 N flops per walker (MFMA; FP64 but in fp32 mode)
+      W_build: 2 n_up n_dn L flops per walker (FP64 MFMA accumulation)
+      LU:      2 n^3 flops per walker per launch (FP64 vector ALU, latency-bound
+               at n = 80: one workgroup per walker)
+      Y_build: 2 x 2 n^2 L flops per walker (FP64 MFMA)"""
+    L, N, nu, nd = s.n_basis, s.n_up + s.n_dn, s.n_up, s.n_dn
+    models = {
+        "basis": ("hbm", Wk * N * L * (4 if precision == "fp32" else 8), HBM_PEAK_GBS, "GB/s", 1e9),
+        "P_build": ("mfma", 2.0 * L * L * N * Wk, MFMA_PEAK_TFLOPS[precision], "TFLOP/s", 1e12),
+        "W_build": ("mfma", 2.0 * nu * nd * L * Wk, 78.6, "TFLOP/s", 1e12),
+        "LU": ("alu", 2.0 * nu ** 3 * Wk, 78.6, "TFLOP/s", 1e12),
+        "Y_build": ("mfma", 4.0 * nu * nu * L * Wk, 78.6, "TFLOP/s", 1e12),
+    }
+    out = {}
+    for k, (bound, units, peak, unit, scale) in models.items():
+        ms, cnt = one.get(k, (0.0, 0))
+        if not cnt:
+            continue
+        avg = ms / cnt
+        ach = units / (avg * 1e-3) / scale
+        out[k] = {"bound": bound, "achieved": round(ach, 2), "peak": peak, "unit": unit,
+                  "frac": round(ach / peak, 4), "avg_launch_us": round(avg * 1e3, 2)}
+    out["propose"] = {k: prop_roof[k] for k in ("bound", "achieved", "peak", "unit", "frac", "avg_launch_us")}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -600,6 +668,7 @@ def main():
         "dominant_kernel": head["dominant_kernel"],
         "roofline": head["roofline"],
         "w_build_mfma": head["w_build_mfma"],
+        "step_rooflines": head["step_rooflines"],
     }
     for p, rec in sides.items():
         res[p] = rec
@@ -614,6 +683,7 @@ def main():
         res["lrdmc"] = lrdmc_leg(P, C)
         res["pfaffian"] = pfaffian_leg(P, C)
         res["sr"] = sr_leg(P)
+        res["achievable_peaks"] = achievable_peaks()
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(res), flush=True)
