@@ -461,12 +461,18 @@ def _oracle_pf_forces(sy, r, gl, ge):
     return dict(zip(keys, g))
 
 
-@pytest.mark.parametrize("kind", ["plain", "jastrow_basis", "contracted"])
+@pytest.mark.parametrize("kind", ["plain", "jastrow_basis", "contracted", "no_down"])
 def test_pfaffian_forces_match_oracle(fw, kind):
     # local-energy derivatives through Y, G~^{-1} and the pairing rows B
     P = need_gpu()
     if kind == "plain":
         s, r0 = fw.system, fw.r0
+    elif kind == "no_down":   # ten up electrons, k = 2: only A^{uu} and the up unpaired orbitals act
+        L_ = len(fw.system.lam)
+        rng = np.random.default_rng(4)
+        s = dataclasses.replace(fw.system, n_up=10, n_dn=0, unpaired=rng.standard_normal((L_, 2)) / np.sqrt(L_),
+                                unpaired_dn=rng.standard_normal((L_, 2)) / np.sqrt(L_))
+        r0 = C.random_positions(67, s, 6)
     else:
         _, s = _pf_variant(kind)
         r0 = C.random_positions(65, s, 6)
