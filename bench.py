@@ -309,7 +309,7 @@ def multi_leg(P, C, precision="fp32", replays=3):
     graph of 768 steps (the schedule period of all members) replayed.  Beside
     it the same members moved one system at a time with qmc_vmc_steps."""
     dev = torch.device("cuda:0")
-    prec = {"fp64": P.QMC_FP64, "fp32": P.QMC_W_FP32}[precision]
+    prec = {"fp64": P.QMC_FP64, "fp32": P.QMC_W_FP32, "bf16": P.QMC_MIXED_BF16}[precision]
     members = []
     for n in C.MULTI_SIZES:
         w = C.multi_system(n)
@@ -679,6 +679,7 @@ def main():
     if not args.only:
         res["forces"] = forces_leg(P, C)
         res["multi_system"] = multi_leg(P, C)
+        res["multi_system_bf16"] = multi_leg(P, C, precision="bf16")
         res["large"] = large_leg(P, C)
         res["lrdmc"] = lrdmc_leg(P, C)
         res["pfaffian"] = pfaffian_leg(P, C)

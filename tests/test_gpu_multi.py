@@ -133,3 +133,35 @@ def test_multi_autotune_then_steps_stay_correct():
         r = wk.read(P.STATE_R).cpu()
         assert rel_err(wk.read(P.STATE_LOGABS).cpu(), O.log_psi(sy, r)[0]).max().item() <= 1e-10
     m.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "mixed", "mixed_bf16"])
+def test_multi_reduced_precision_members_equal_single_runs(precision):
+    # FP32 / BF16 rows in the persistent launches: each member's chain equals
+    # the single-system run of the same storage type on the same draws
+    P = need_gpu()
+    prec = {"fp32": P.QMC_W_FP32, "mixed": P.QMC_MIXED, "mixed_bf16": P.QMC_MIXED_BF16}[precision]
+    Wk, n_steps = 8, 100
+    grp = _members(P, Wk, prec)
+    solo = _members(P, Wk, prec)
+    draws = [C.chain_arrays(730 + k, n_steps, Wk) for k in range(len(SIZES))]
+    disp = [torch.tensor(d, device="cuda") for d, _ in draws]
+    unif = [torch.tensor(u, device="cuda") for _, u in draws]
+    m = P.MultiSystem([wk for _, _, wk in grp])
+    m.vmc_steps(n_steps, disp, unif)
+    for k, (_, _, wk) in enumerate(solo):
+        wk.vmc_steps(0, disp[k], unif[k])
+    torch.cuda.synchronize()
+    for k, n in enumerate(SIZES):
+        a, b = grp[k][2], solo[k][2]
+        assert torch.equal(a.read(P.STATE_R), b.read(P.STATE_R)), (precision, n)
+        la, lb = a.read(P.STATE_LOGABS).cpu(), b.read(P.STATE_LOGABS).cpu()
+        assert rel_err(la, lb).max().item() <= 1e-12, (precision, n)
+    # the FP64 log|Psi| carried through the chain against the oracle (small members)
+    if precision == "mixed":
+        for k in range(2):
+            w, _, wk = grp[k]
+            sy = O.from_workload_system(w.system)
+            r = wk.read(P.STATE_R).cpu()
+            assert rel_err(wk.read(P.STATE_LOGABS).cpu(), O.log_psi(sy, r)[0]).max().item() <= 1e-6
+    m.close()
