@@ -42,15 +42,17 @@ def test_propose_ratio_and_drift_tiny(e):
     assert derr <= 1e-8
 
 
-@pytest.mark.parametrize("e", [7, 95])
-def test_propose_accept_molecule_160e(e):
+@pytest.mark.parametrize("e,Wk", [(7, 16), (95, 16), (7, 13), (95, 13)])
+def test_propose_accept_molecule_160e(e, Wk):
+    # Wk = 13: a walker count that is not a multiple of the 8 XCDs (the
+    # proposal grid's plain block order)
     P = need_gpu()
-    w = C.mol_40nuc_160e(n_walkers=16)
+    w = C.mol_40nuc_160e(n_walkers=Wk)
     _, wk, sy, r = _setup(P, w)
-    disp = torch.tensor(C.chain_arrays(11, 1, 16)[0][0])
+    disp = torch.tensor(C.chain_arrays(11, 1, Wk)[0][0])
     rn = r[:, e] + disp
     ratio = wk.propose(e, rn.cuda().contiguous())
-    acc = torch.tensor([1, 0] * 8, dtype=torch.uint8)
+    acc = torch.tensor([(k + 1) % 2 for k in range(Wk)], dtype=torch.uint8)
     wk.accept(e, acc.cuda())
     A = wk.read(P.STATE_AINV).cpu()
     la = wk.read(P.STATE_LOGABS).cpu()
