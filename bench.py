@@ -564,7 +564,8 @@ def sr_leg(P, M=4096, Pn=8192, iters=40, eps=1e-3):
 
 def achievable_peaks():
     """Achievable peaks on this GPU beside the datasheet ones (best of 5): a
-    STREAM-like 1 GiB copy (bytes read + written per second) and an 8192^3
+    STREAM-like 1 GiB copy (bytes read + written per second), a 1 GiB sum
+    (read only, the proposal kernel's access pattern) and an 8192^3
     FP64 matrix product from the vendor library (flops per second).  These are
     measurement references only."""
     dev = torch.device("cuda:0")
@@ -580,6 +581,15 @@ def achievable_peaks():
         torch.cuda.synchronize()
         best = min(best, ev[0].elapsed_time(ev[1]))
     copy_gbs = 2 * n * 8 / (best * 1e-3) / 1e9
+    acc = torch.empty((), dtype=torch.float64, device=dev)
+    best = float("inf")
+    for _ in range(6):
+        ev[0].record()
+        torch.sum(a, dim=0, out=acc)
+        ev[1].record()
+        torch.cuda.synchronize()
+        best = min(best, ev[0].elapsed_time(ev[1]))
+    read_gbs = n * 8 / (best * 1e-3) / 1e9
     del a, b
     m = 8192
     g = torch.Generator(device=dev).manual_seed(3)
@@ -594,7 +604,7 @@ def achievable_peaks():
         torch.cuda.synchronize()
         best = min(best, ev[0].elapsed_time(ev[1]))
     del x, y, z
-    return {"hbm_copy_GBps": round(copy_gbs, 1), "fp64_gemm_TFLOPs": round(2 * m ** 3 / (best * 1e-3) / 1e12, 2),
+    return {"hbm_copy_GBps": round(copy_gbs, 1), "hbm_read_GBps": round(read_gbs, 1), "fp64_gemm_TFLOPs": round(2 * m ** 3 / (best * 1e-3) / 1e12, 2),
             "datasheet": {"hbm_GBps": HBM_PEAK_GBS, "fp64_TFLOPs": 78.6, "fp32_TFLOPs": 157.3}}
 
 
