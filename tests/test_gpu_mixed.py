@@ -23,6 +23,9 @@ cofactor products in FP64 and only stores FP32 copies for the moves.  It must
 meet relative 1e-6 on log|Psi| and E_loc against the oracle (it reaches FP64
 accuracy), and its move ratios obey the FP32 bound above.
 """
+import dataclasses
+
+import numpy as np
 import pytest
 import torch
 
@@ -189,3 +192,37 @@ def test_mixed_moves_ratio_within_bound(mode):
         print(f"[{mode} moves e={e}] max |d ratio| {d.max():.3e}, max rel {(d / rr.abs()).max():.3e}, "
               f"bound {bound.min():.3e}..{bound.max():.3e}")
         assert torch.all(d <= bound * (1 + 1e-6) + 1e-12)
+
+
+@pytest.mark.parametrize("precision", ["mixed", "mixed_bf16", "fp32"])
+def test_set_params_equals_fresh_system(precision):
+    # device parameter updates refresh the reduced-precision copies (Lambda's
+    # FP32 copy, the basis packing, the Jastrow scalars): evaluations and a
+    # chain equal those of a system created with the new parameters, bitwise
+    P = need_gpu()
+    prec = {"mixed": P.QMC_MIXED, "mixed_bf16": P.QMC_MIXED_BF16, "fp32": P.QMC_W_FP32}[precision]
+    w = C.tiny_3nuc_10e(n_walkers=16, n_steps=60)
+    s = w.system
+    rng = np.random.default_rng(8)
+    L_ = len(s.lam)
+    a = rng.standard_normal((L_, L_))
+    lam2 = s.lam + 0.01 * (a + a.T) / L_
+    R2 = s.R + 0.03 * rng.standard_normal(s.R.shape)
+    z2 = s.zeta * 1.02
+    jas2 = np.concatenate([np.asarray(s.j1_b) * 1.1, np.asarray(s.j2) * 0.9])
+    T = lambda x: torch.tensor(np.ascontiguousarray(x), device="cuda")
+    upd = P.JAGPSystem(s, precision=prec)
+    upd.set_params(R=T(R2), zeta=T(z2), lam=T(lam2), jas=T(jas2))
+    fresh = P.JAGPSystem(dataclasses.replace(s, R=R2, zeta=z2, lam=lam2, j1_b=jas2[:len(s.Z)],
+                                             j2=jas2[len(s.Z):]), precision=prec)
+    r = torch.tensor(w.r0, device="cuda")
+    wa, wb = P.Walkers(upd, 16), P.Walkers(fresh, 16)
+    oa, ob = wa.eval_batch(r), wb.eval_batch(r)
+    d, u = torch.tensor(w.disp, device="cuda"), torch.tensor(w.unif, device="cuda")
+    wa.vmc_steps(0, d, u)
+    wb.vmc_steps(0, d, u)
+    torch.cuda.synchronize()
+    for k in ("logabs", "e_loc", "drift"):
+        assert torch.equal(oa[k], ob[k]), k
+    assert torch.equal(wa.read(P.STATE_R), wb.read(P.STATE_R))
+    assert torch.equal(wa.read(P.STATE_LOGABS), wb.read(P.STATE_LOGABS))
