@@ -18,6 +18,21 @@ __global__ void __launch_bounds__(256) basis_values_kernel(SysDev s, const doubl
     out[mu] = (T)(mu < s.L ? basis_value(s, mu, px, py, pz) : 0.0);
 }
 
+// FP64 values plus their FP32 or BF16 copy (the rows the moves stream).
+template <typename T2>
+__global__ void __launch_bounds__(256) basis_values_dual_kernel(SysDev s, const double* __restrict__ r,
+                                                                double* __restrict__ phi, T2* __restrict__ lo) {
+  const long row = blockIdx.x;   // w * N + i
+  const double px = r[3 * row], py = r[3 * row + 1], pz = r[3 * row + 2];
+  double* out = phi + row * s.Lp;
+  T2* out2 = lo + row * s.Lp;
+  for (int mu = threadIdx.x; mu < s.Lp; mu += blockDim.x) {
+    const double v = mu < s.L ? basis_value(s, mu, px, py, pz) : 0.0;
+    out[mu] = v;
+    out2[mu] = (T2)v;
+  }
+}
+
 // Contracted orbitals: the row's primitive values are staged in LDS, then
 // phi_c = sum_t C_t psi_{idx_t} (a contraction mixes primitives of one row only).
 template <typename T>
@@ -37,8 +52,15 @@ __global__ void __launch_bounds__(256) contracted_values_kernel(SysDev s, const 
   }
 }
 
-hipError_t launch_basis_values(const SysDev& s, const WalkDev& w, hipStream_t st) {
+hipError_t launch_basis_values(const SysDev& s, const WalkDev& w, hipStream_t st, void* lo, bool lo_bf16) {
   const dim3 grid((unsigned)((long)w.Wk * s.N));
+  if (lo && s.Lq == 0 && !s.bf16() && !s.f32()) {   // FP64 values with a low-precision copy
+    if (lo_bf16)
+      hipLaunchKernelGGL(basis_values_dual_kernel<bf16s>, grid, dim3(256), 0, st, s, w.r, (double*)w.phi, (bf16s*)lo);
+    else
+      hipLaunchKernelGGL(basis_values_dual_kernel<float>, grid, dim3(256), 0, st, s, w.r, (double*)w.phi, (float*)lo);
+    return hipGetLastError();
+  }
   if (s.Lq > 0) {
     if (s.Lq > kMaxLq) return hipErrorNotSupported;
     if (s.bf16())

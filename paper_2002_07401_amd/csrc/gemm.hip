@@ -70,6 +70,8 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g, int gx, int gy) {
   const SA* __restrict__ A = (const SA*)g.A + bz * g.a_bs;
   const SB* __restrict__ B = (const SB*)g.B + bz * g.b_bs;
   TO* __restrict__ C = (TO*)g.C + bz * g.c_bs;
+  float* __restrict__ C2f = (g.C2 && !g.c2_bf16) ? (float*)g.C2 + bz * g.c_bs : nullptr;
+  bf16s* __restrict__ C2h = (g.C2 && g.c2_bf16) ? (bf16s*)g.C2 + bz * g.c_bs : nullptr;
   const int m0 = by * BM, n0 = bx * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
@@ -167,9 +169,16 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g, int gx, int gy) {
         const int gm = m0 + wm * WM + i * 16 + Mfma<TI>::row(lane, r);
         const int gn = n0 + wn * WN + j * 16 + (lane & 15);
         if (gm < g.M && gn < g.N) {
-          TO* cp = C + (long)(gm / g.c_grp) * g.c_gs + (long)(gm % g.c_grp) * g.ldc + gn;
-          if constexpr (sizeof(TO) == 2) *cp = (TO)acc[i][j][r];   // BF16 output: never accumulated
-          else *cp = g.accumulate ? (TO)(*cp + (TO)acc[i][j][r]) : (TO)acc[i][j][r];
+          const long off = (long)(gm / g.c_grp) * g.c_gs + (long)(gm % g.c_grp) * g.ldc + gn;
+          TO* cp = C + off;
+          if constexpr (sizeof(TO) == 2) {
+            *cp = (TO)acc[i][j][r];   // BF16 output: never accumulated
+          } else {
+            const TO v = g.accumulate ? (TO)(*cp + (TO)acc[i][j][r]) : (TO)acc[i][j][r];
+            *cp = v;
+            if (C2f) C2f[off] = (float)v;
+            if (C2h) C2h[off] = bf16s(v);
+          }
         }
       }
 }
@@ -218,9 +227,10 @@ static hipError_t P_gemm(const GemmArgs& g, hipStream_t st) {
 
 // T: storage of Phi and P; TL: storage of Lambda and the MFMA operand type
 // (BF16 rows multiply the FP32 Lambda with FP32 accumulation).
+// lo (FP64 products only): also store P as FP32 / BF16 there (the moves' copy).
 template <typename T, typename TL = T>
 static hipError_t P_build_t(const SysDev& s, const WalkDev& w, int halves, hipStream_t st,
-                            const TL* lam, const TL* lamT) {
+                            const TL* lam, const TL* lamT, void* lo = nullptr, bool lo_bf16 = false) {
   const long rowst = (long)s.N * s.Lp;
   const T* phi = (const T*)w.phi;
   T* P = (T*)w.P;
@@ -232,6 +242,7 @@ static hipError_t P_build_t(const SysDev& s, const WalkDev& w, int halves, hipSt
     g.B = lam; g.ldb = s.Lp;
     g.kmask = s.lam_mask; g.kmask_ld = mask_ld;
     g.C = P; g.ldc = s.Lp; g.c_grp = s.nu; g.c_gs = rowst;
+    g.C2 = lo; g.c2_bf16 = lo_bf16 ? 1 : 0;
     e = P_gemm<T, TL>(g, st);
     if (e != hipSuccess) return e;
   }
@@ -241,15 +252,20 @@ static hipError_t P_build_t(const SysDev& s, const WalkDev& w, int halves, hipSt
     g.B = lamT; g.ldb = s.Lp;
     g.kmask = s.lamT_mask; g.kmask_ld = mask_ld;
     g.C = P + (long)s.nu * s.Lp; g.ldc = s.Lp; g.c_grp = s.nd; g.c_gs = rowst;
+    if (lo) {
+      g.C2 = lo_bf16 ? (void*)((bf16s*)lo + (long)s.nu * s.Lp) : (void*)((float*)lo + (long)s.nu * s.Lp);
+      g.c2_bf16 = lo_bf16 ? 1 : 0;
+    }
     e = P_gemm<T, TL>(g, st);
   }
   return e;
 }
 
-hipError_t launch_P_build(const SysDev& s, const WalkDev& w, int halves, hipStream_t st) {
+hipError_t launch_P_build(const SysDev& s, const WalkDev& w, int halves, hipStream_t st, void* lo,
+                          bool lo_bf16) {
   if (s.bf16()) return P_build_t<bf16s, float>(s, w, halves, st, s.lam32, s.lamT32);
   if (s.f32()) return P_build_t<float>(s, w, halves, st, s.lam32, s.lamT32);
-  return P_build_t<double>(s, w, halves, st, s.lam, s.lamT);
+  return P_build_t<double>(s, w, halves, st, s.lam, s.lamT, lo, lo_bf16);
 }
 
 // W[w] = P_up[w] Phi_dn[w]^T  ->  W[i][j] = sum_nu (Phi_up Lambda)[i][nu] psi_nu(r_j),

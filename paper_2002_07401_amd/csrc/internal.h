@@ -463,9 +463,11 @@ __device__ __forceinline__ float wave_sum(float v) {
 // ---------------------------------------------------------------------------
 // launchers (all asynchronous on `st`)
 // ---------------------------------------------------------------------------
-hipError_t launch_basis_values(const SysDev& s, const WalkDev& w, hipStream_t st);
+hipError_t launch_basis_values(const SysDev& s, const WalkDev& w, hipStream_t st, void* lo = nullptr,
+                               bool lo_bf16 = false);
 hipError_t launch_downcast(const double* src, void* dst, bool to_bf16, long n, hipStream_t st);
-hipError_t launch_P_build(const SysDev& s, const WalkDev& w, int halves, hipStream_t st);
+hipError_t launch_P_build(const SysDev& s, const WalkDev& w, int halves, hipStream_t st,
+                          void* lo = nullptr, bool lo_bf16 = false);
 hipError_t launch_W_build(const SysDev& s, const WalkDev& w, hipStream_t st);
 hipError_t launch_Y_build(const SysDev& s, const WalkDev& w, hipStream_t st);
 hipError_t launch_lu_inverse(const SysDev& s, const WalkDev& w, hipStream_t st);
@@ -541,6 +543,10 @@ struct GemmArgs {
   void* C; long ldc; long c_bs; int c_grp; long c_gs;
   int batch;
   int accumulate;   // 1: C += op(A) op(B); 0: C = op(A) op(B)
+  // optional second output written beside C (same layout, no accumulation):
+  // C2 != null stores each result also as FP32 (c2_bf16 = 0) or BF16 (1)
+  void* C2;
+  int c2_bf16;
   // optional nonzero flags of B's [kLamTileK x kLamTileN] tiles ([K/16][kmask_ld]);
   // honoured by the 64-column-tile kernels, which skip zero tiles
   const uint8_t* kmask;

@@ -588,22 +588,26 @@ extern "C" qmc_status qmc_eval_batch(qmc_system* sys, qmc_walkers* wk, const dou
     de.phi = d.phi64;
     de.P = d.P64;
   }
-  TIMED(wk, QMC_T_BASIS, stream, launch_basis_values(se, de, stream), "basis");
+  // the FP32 / BF16 copies of Phi and P are written by the producing kernels
+  // (contracted orbitals: a separate copy of Phi)
+  const bool phi_fused = refine && s.Lq == 0;
+  TIMED(wk, QMC_T_BASIS, stream,
+        launch_basis_values(se, de, stream, phi_fused ? d.phi : nullptr, s.bf16()), "basis");
   if (s.pairing) {
     TIMED(wk, QMC_T_P_BUILD, stream, launch_pf_B_build(s, d, stream), "Pfaffian B rows");
     TIMED(wk, QMC_T_W_BUILD, stream, launch_pf_G_build(s, d, stream), "Pfaffian G");
     TIMED(wk, QMC_T_LU, stream, launch_pf_factor(s, d, stream), "Pfaffian and inverse");
     TIMED(wk, QMC_T_Y_BUILD, stream, launch_pf_Y_build(s, d, stream), "Pfaffian Y build");
   } else {
-  TIMED(wk, QMC_T_P_BUILD, stream, launch_P_build(se, de, 3, stream), "P build");
+  TIMED(wk, QMC_T_P_BUILD, stream, launch_P_build(se, de, 3, stream, refine ? d.P : nullptr, s.bf16()),
+        "P build");
   TIMED(wk, QMC_T_W_BUILD, stream, launch_W_build(se, de, stream), "W build");
   TIMED(wk, QMC_T_LU, stream, launch_lu_inverse(se, de, stream), "LU");
   TIMED(wk, QMC_T_Y_BUILD, stream, launch_Y_build(se, de, stream), "Y build");
   }
-  if (refine) {
+  if (refine && !phi_fused) {
     const long cnt = (long)d.Wk * s.N * s.Lp;
     TIMED(wk, QMC_T_OTHER, stream, launch_downcast(d.phi64, d.phi, s.bf16(), cnt, stream), "phi copy");
-    TIMED(wk, QMC_T_OTHER, stream, launch_downcast(d.P64, d.P, s.bf16(), cnt, stream), "P copy");
   }
   TIMED(wk, QMC_T_ROWDOT, stream, launch_rowdots(s, d, stream), "row dots");
   if (s.LJ) TIMED(wk, QMC_T_ASSEMBLE, stream, launch_jastrow3_eval(s, d, stream), "Jastrow basis terms");
