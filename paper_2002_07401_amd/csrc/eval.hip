@@ -35,9 +35,10 @@ __global__ void __launch_bounds__(256) basis_values_dual_kernel(SysDev s, const 
 
 // Contracted orbitals: the row's primitive values are staged in LDS, then
 // phi_c = sum_t C_t psi_{idx_t} (a contraction mixes primitives of one row only).
-template <typename T>
+// lo (optional, with T = double): the FP32 or BF16 copy (T2) of the same row.
+template <typename T, typename T2 = float>
 __global__ void __launch_bounds__(256) contracted_values_kernel(SysDev s, const double* __restrict__ r,
-                                                                T* __restrict__ phi) {
+                                                                T* __restrict__ phi, T2* __restrict__ lo) {
   __shared__ double q[kMaxLq];
   const long row = blockIdx.x;   // w * N + i
   const double px = r[3 * row], py = r[3 * row + 1], pz = r[3 * row + 2];
@@ -49,12 +50,14 @@ __global__ void __launch_bounds__(256) contracted_values_kernel(SysDev s, const 
     if (c < s.L)
       for (int k = s.con_ptr[c]; k < s.con_ptr[c + 1]; ++k) v += s.con_coef[k] * q[s.con_idx[k]];
     out[c] = (T)v;
+    if (lo) lo[row * s.Lp + c] = (T2)v;
   }
 }
 
 hipError_t launch_basis_values(const SysDev& s, const WalkDev& w, hipStream_t st, void* lo, bool lo_bf16) {
   const dim3 grid((unsigned)((long)w.Wk * s.N));
-  if (lo && s.Lq == 0 && !s.bf16() && !s.f32()) {   // FP64 values with a low-precision copy
+  const bool dual = lo && !s.bf16() && !s.f32();   // FP64 values with a low-precision copy
+  if (dual && s.Lq == 0) {
     if (lo_bf16)
       hipLaunchKernelGGL(basis_values_dual_kernel<bf16s>, grid, dim3(256), 0, st, s, w.r, (double*)w.phi, (bf16s*)lo);
     else
@@ -63,12 +66,21 @@ hipError_t launch_basis_values(const SysDev& s, const WalkDev& w, hipStream_t st
   }
   if (s.Lq > 0) {
     if (s.Lq > kMaxLq) return hipErrorNotSupported;
-    if (s.bf16())
-      hipLaunchKernelGGL(contracted_values_kernel<bf16s>, grid, dim3(256), 0, st, s, w.r, (bf16s*)w.phi);
+    if (dual && lo_bf16)
+      hipLaunchKernelGGL((contracted_values_kernel<double, bf16s>), grid, dim3(256), 0, st, s, w.r, (double*)w.phi,
+                         (bf16s*)lo);
+    else if (dual)
+      hipLaunchKernelGGL((contracted_values_kernel<double, float>), grid, dim3(256), 0, st, s, w.r, (double*)w.phi,
+                         (float*)lo);
+    else if (s.bf16())
+      hipLaunchKernelGGL((contracted_values_kernel<bf16s>), grid, dim3(256), 0, st, s, w.r, (bf16s*)w.phi,
+                         (float*)nullptr);
     else if (s.f32())
-      hipLaunchKernelGGL(contracted_values_kernel<float>, grid, dim3(256), 0, st, s, w.r, (float*)w.phi);
+      hipLaunchKernelGGL((contracted_values_kernel<float>), grid, dim3(256), 0, st, s, w.r, (float*)w.phi,
+                         (float*)nullptr);
     else
-      hipLaunchKernelGGL(contracted_values_kernel<double>, grid, dim3(256), 0, st, s, w.r, (double*)w.phi);
+      hipLaunchKernelGGL((contracted_values_kernel<double>), grid, dim3(256), 0, st, s, w.r, (double*)w.phi,
+                         (float*)nullptr);
     return hipGetLastError();
   }
   if (s.bf16())

@@ -589,10 +589,7 @@ extern "C" qmc_status qmc_eval_batch(qmc_system* sys, qmc_walkers* wk, const dou
     de.P = d.P64;
   }
   // the FP32 / BF16 copies of Phi and P are written by the producing kernels
-  // (contracted orbitals: a separate copy of Phi)
-  const bool phi_fused = refine && s.Lq == 0;
-  TIMED(wk, QMC_T_BASIS, stream,
-        launch_basis_values(se, de, stream, phi_fused ? d.phi : nullptr, s.bf16()), "basis");
+  TIMED(wk, QMC_T_BASIS, stream, launch_basis_values(se, de, stream, refine ? d.phi : nullptr, s.bf16()), "basis");
   if (s.pairing) {
     TIMED(wk, QMC_T_P_BUILD, stream, launch_pf_B_build(s, d, stream), "Pfaffian B rows");
     TIMED(wk, QMC_T_W_BUILD, stream, launch_pf_G_build(s, d, stream), "Pfaffian G");
@@ -604,10 +601,6 @@ extern "C" qmc_status qmc_eval_batch(qmc_system* sys, qmc_walkers* wk, const dou
   TIMED(wk, QMC_T_W_BUILD, stream, launch_W_build(se, de, stream), "W build");
   TIMED(wk, QMC_T_LU, stream, launch_lu_inverse(se, de, stream), "LU");
   TIMED(wk, QMC_T_Y_BUILD, stream, launch_Y_build(se, de, stream), "Y build");
-  }
-  if (refine && !phi_fused) {
-    const long cnt = (long)d.Wk * s.N * s.Lp;
-    TIMED(wk, QMC_T_OTHER, stream, launch_downcast(d.phi64, d.phi, s.bf16(), cnt, stream), "phi copy");
   }
   TIMED(wk, QMC_T_ROWDOT, stream, launch_rowdots(s, d, stream), "row dots");
   if (s.LJ) TIMED(wk, QMC_T_ASSEMBLE, stream, launch_jastrow3_eval(s, d, stream), "Jastrow basis terms");
