@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define QMC_ABI_VERSION 14
+#define QMC_ABI_VERSION 15
 
 typedef enum {
   QMC_OK = 0,
@@ -268,6 +268,8 @@ typedef struct {
                        dF = sum_kl D_kl dM_kl for every symmetric dM); M^{ud}
                        every entry independent                                  */
   double *djb_zeta; /* [LJ] or [Wk][LJ]                                          */
+  /* Unpaired orbitals (k = n_up - n_dn > 0; ignored otherwise): */
+  double *dunpaired; /* [L][k] or [Wk][L][k]: d/dU[mu][l], U as in the descriptor */
 } qmc_grads;
 
 /* Adjoint of the evaluation (Derivatives of energy section: logarithmic
@@ -283,8 +285,8 @@ typedef struct {
  * a walker set allocates its workspace.
  * Pfaffian systems: dR, dzeta, djas, dr and the Jastrow-basis outputs as
  * above (log|Psi| through the cofactor vectors Y_i, e_L through Y, G~^{-1} and
- * the pairing rows); dlambda must be NULL (QMC_ERR_ARG): the pairing
- * coefficients' log-derivatives come from qmc_pfaffian_logderiv, their
+ * the pairing rows); dlambda and dunpaired must be NULL (QMC_ERR_ARG): the
+ * pairing coefficients' log-derivatives come from qmc_pfaffian_logderiv, their
  * local-energy derivatives are not built. */
 qmc_status qmc_forces(qmc_system *sys, qmc_walkers *wk, const double *r, int32_t per_walker,
                       const double *gbar_logpsi, const double *gbar_eloc, const qmc_grads *out,

@@ -54,7 +54,7 @@ class QMCError(RuntimeError):
 class Grads(ctypes.Structure):
     _fields_ = [("dR", ctypes.c_void_p), ("dzeta", ctypes.c_void_p), ("dlambda", ctypes.c_void_p),
                 ("djas", ctypes.c_void_p), ("dr", ctypes.c_void_p), ("dj1_inh", ctypes.c_void_p),
-                ("dj3", ctypes.c_void_p), ("djb_zeta", ctypes.c_void_p)]
+                ("dj3", ctypes.c_void_p), ("djb_zeta", ctypes.c_void_p), ("dunpaired", ctypes.c_void_p)]
 
 
 class LrdmcParams(ctypes.Structure):
@@ -341,13 +341,17 @@ class Walkers:
             out = dict(R=f(A, 3), zeta=f(S.n_basis), lam=f(L, L), jas=f(nj), r=f(Wk, N, 3))
         if S.pairing:       # pairing-coefficient derivatives: pfaffian_logderiv
             del out["lam"]
+        elif S.n_up > S.n_dn:   # unpaired orbitals U [L][k]
+            k = S.n_up - S.n_dn
+            out["unpaired"] = f(Wk, L, k) if per_walker else f(L, k)
         LJ = S.LJ
         if LJ:
             pre = (Wk,) if per_walker else ()
             out.update(j1_inh=f(*pre, 2, LJ), j3=f(*pre, 3, LJ, LJ), jb_zeta=f(*pre, LJ))
         g = Grads(dR=_ptr(out["R"]), dzeta=_ptr(out["zeta"]), dlambda=_ptr(out.get("lam")),
                   djas=_ptr(out["jas"]), dr=_ptr(out["r"]), dj1_inh=_ptr(out.get("j1_inh")),
-                  dj3=_ptr(out.get("j3")), djb_zeta=_ptr(out.get("jb_zeta")))
+                  dj3=_ptr(out.get("j3")), djb_zeta=_ptr(out.get("jb_zeta")),
+                  dunpaired=_ptr(out.get("unpaired")))
         _check(load().qmc_forces(S.h, self.h, _ptr(r), 1 if per_walker else 0, _ptr(gbar_logpsi),
                                  _ptr(gbar_eloc), ctypes.byref(g), _stream(stream)))
         return out

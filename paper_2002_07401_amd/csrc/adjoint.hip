@@ -618,7 +618,8 @@ __global__ void __launch_bounds__(256) zero_fill_kernel(double* __restrict__ x, 
 // dF/dPhi (aw.PB) and dF/dLambda of the geminal determinant, steps 1 to 7 of
 // the backward pass.
 static hipError_t geminal_backward(const SysDev& s, const WalkDev& w, const AdjWork& aw, const double* ga,
-                                   const double* gb, int per_walker, double* dlambda, hipStream_t st) {
+                                   const double* gb, int per_walker, double* dlambda, double* dunp,
+                                   hipStream_t st) {
   const int n = s.nu, nd = s.nd, Wk = w.Wk, Lp = s.Lp, L = s.L, N = s.N;
   const long rowst = (long)N * Lp, stk = 2L * n * Lp;
   // 1. stacked rows [Phi_U; Q_U], [Phi_D; Q_D]
@@ -727,6 +728,33 @@ static hipError_t geminal_backward(const SysDev& s, const WalkDev& w, const AdjW
         HT(gemm_f64(h, true, false, true, st));
       }
       HT(sum_rows(aw.lam_part, nfull + (rest ? 1 : 0), (long)L * L, dlambda, st));
+    }
+  }
+  // 7b. unpaired orbitals: W[:, n_dn + l] = Phi_U U_l and V[:, n_dn + l] = Q_U U_l give
+  //     dF/dU_l = [Phi_U; Q_U]^T [G_W; G_V][:, n_dn + l]
+  if (dunp && s.nk > 0) {
+    const int k = s.nk;
+    if (per_walker) {
+      GemmArgs g = gemm_args(L, k, 2 * n);
+      g.A = aw.SU; g.lda = Lp; g.a_bs = stk;
+      g.B = aw.GGt + nd; g.ldb = n; g.b_bs = 2L * n * n;
+      g.C = dunp; g.ldc = k; g.c_bs = (long)L * k; g.batch = Wk;
+      HT(gemm_f64(g, true, false, false, st));
+    } else {
+      const int cw = aw.chunk_walkers, nfull = Wk / cw, rest = Wk % cw;
+      GemmArgs g = gemm_args(L, k, 2 * n * cw);
+      g.A = aw.SU; g.lda = Lp; g.a_bs = stk * cw;
+      g.B = aw.GGt + nd; g.ldb = n; g.b_bs = 2L * n * n * cw;
+      g.C = aw.lam_part; g.ldc = k; g.c_bs = (long)L * k; g.batch = nfull;
+      if (nfull) HT(gemm_f64(g, true, false, false, st));
+      if (rest) {
+        GemmArgs h = g;
+        h.K = 2 * n * rest;
+        h.A = aw.SU + stk * cw * nfull; h.B = aw.GGt + nd + 2L * n * n * cw * nfull;
+        h.C = aw.lam_part + (long)nfull * L * k; h.batch = 1;
+        HT(gemm_f64(h, true, false, false, st));
+      }
+      HT(sum_rows(aw.lam_part, nfull + (rest ? 1 : 0), (long)L * k, dunp, st));
     }
   }
   return hipSuccess;
@@ -844,12 +872,12 @@ static hipError_t pf_backward(const SysDev& s, const WalkDev& w, const AdjWork& 
 hipError_t launch_forces(const SysDev& s, const WalkDev& w, const AdjWork& aw, const double* ga,
                          const double* gb, int per_walker, double* dR, double* dzeta, double* dlambda,
                          double* djas, double* dr, double* dj1_inh, double* dj3, double* djb_zeta,
-                         hipStream_t st) {
+                         double* dunpaired, hipStream_t st) {
   const int Wk = w.Wk, Lp = s.Lp, N = s.N;
   if (s.pairing) {
     HT(pf_backward(s, w, aw, ga, gb, st));
   } else {
-    HT(geminal_backward(s, w, aw, ga, gb, per_walker, dlambda, st));
+    HT(geminal_backward(s, w, aw, ga, gb, per_walker, dlambda, dunpaired, st));
   }
   // 8. basis and Jastrow/Coulomb backward (over the primitives of a contracted basis)
   double* drw = dr ? dr : aw.dr;

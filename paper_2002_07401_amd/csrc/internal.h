@@ -258,7 +258,7 @@ hipError_t launch_philox_draws(unsigned long long seed, int member, int Wk, unsi
 hipError_t launch_forces(const SysDev& s, const WalkDev& w, const AdjWork& aw, const double* ga,
                          const double* gb, int per_walker, double* dR, double* dzeta, double* dlambda,
                          double* djas, double* dr, double* dj1_inh, double* dj3, double* djb_zeta,
-                         hipStream_t st);
+                         double* dunpaired, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // device helpers

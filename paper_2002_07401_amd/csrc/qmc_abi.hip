@@ -960,8 +960,9 @@ extern "C" qmc_status qmc_forces(qmc_system* sys, qmc_walkers* wk, const double*
   if (!r || !out) return fail(QMC_ERR_ARG, "null positions or output block");
   const SysDev& s = sys->d;
   if (s.precision != QMC_FP64) return fail(QMC_ERR_UNSUPPORTED, "forces are built for the FP64 path");
-  if (s.pairing && out->dlambda)
-    return fail(QMC_ERR_ARG, "Pfaffian pairing-coefficient derivatives come from qmc_pfaffian_logderiv (dlambda must be NULL)");
+  if (s.pairing && (out->dlambda || out->dunpaired))
+    return fail(QMC_ERR_ARG, "Pfaffian pairing-coefficient derivatives come from qmc_pfaffian_logderiv "
+                             "(dlambda and dunpaired must be NULL)");
   if (s.N > 2 * kLuMaxN || s.n_nuc > kMaxNucBack)
     return fail(QMC_ERR_UNSUPPORTED, "forces need N <= 256 electrons and <= 256 nuclei");
   hipError_t e = alloc_adjoint(wk);
@@ -971,7 +972,7 @@ extern "C" qmc_status qmc_forces(qmc_system* sys, qmc_walkers* wk, const double*
   if (c) return c;
   HIP_TRY(launch_forces(s, wk->d, wk->aw, gbar_logpsi, gbar_eloc, per_walker, out->dR, out->dzeta,
                         out->dlambda, out->djas, out->dr, s.LJ ? out->dj1_inh : nullptr, s.LJ ? out->dj3 : nullptr,
-                        s.LJ ? out->djb_zeta : nullptr, stream), "forces");
+                        s.LJ ? out->djb_zeta : nullptr, s.nk ? out->dunpaired : nullptr, stream), "forces");
   return QMC_OK;
 }
 

@@ -138,6 +138,14 @@ def test_polarized_contracted_and_jastrow_basis():
     assert rel_err(ratio.cpu(), O.move_ratio(sy, r, 4, rn)).max().item() <= 1e-10
 
 
+def _oracle_unpaired_grads(sy, r, gl, ge):
+    """Autodiff of sum_w (gl log|Psi| + ge e_L) with respect to the unpaired orbitals U [L, k]."""
+    U = sy.unpaired.detach().clone().requires_grad_(True)
+    out = O.evaluate(dataclasses.replace(sy, unpaired=U), r)
+    F = (gl * out["logabs"]).sum() + (ge * out["e_loc"]).sum()
+    return torch.autograd.grad(F, U)[0]
+
+
 def test_polarized_forces_match_oracle(pw):
     # the adjoint with unpaired orbitals: G_W's unpaired columns feed dF/dPhi_up
     P = need_gpu()
@@ -150,7 +158,8 @@ def test_polarized_forces_match_oracle(pw):
     out = wk.forces(r.cuda(), gl.cuda(), ge.cuda())
     torch.cuda.synchronize()
     ref = O.forces_vjp(sy, r, gl, ge)
-    for k in ("R", "zeta", "lam", "jas", "r"):
+    ref["unpaired"] = _oracle_unpaired_grads(sy, r, gl, ge)
+    for k in ("R", "zeta", "lam", "jas", "r", "unpaired"):
         a, b = out[k].cpu(), ref[k]
         err = (a - b).abs().max().item() / max(1.0, b.abs().max().item())
         print(f"[polarized forces] {k}: {err:.3e}")
@@ -161,6 +170,12 @@ def test_polarized_forces_match_oracle(pw):
     for k in ("zeta", "jas"):
         a, b = per[k].cpu(), pref[k][0]
         assert (a - b).abs().max().item() / max(1.0, b.abs().max().item()) <= 1e-8, k
+    for w_ in (0, Wk - 1):   # log|Psi| of one walker with respect to U
+        g1 = torch.zeros(Wk, dtype=torch.float64)
+        g1[w_] = 1.0
+        b = _oracle_unpaired_grads(sy, r, g1, torch.zeros(Wk, dtype=torch.float64))
+        a = per["unpaired"][w_].cpu()
+        assert (a - b).abs().max().item() / max(1.0, b.abs().max().item()) <= 1e-8, w_
 
 
 def test_fully_polarized_determinant():
@@ -185,7 +200,9 @@ def test_fully_polarized_determinant():
     g = wk.forces(rf.cuda(), one, one)
     torch.cuda.synchronize()
     ref = O.forces_vjp(sy, rf, torch.ones(8, dtype=torch.float64), torch.ones(8, dtype=torch.float64))
-    for k in ("R", "zeta", "jas", "r"):
+    ref["unpaired"] = _oracle_unpaired_grads(sy, rf, torch.ones(8, dtype=torch.float64),
+                                             torch.ones(8, dtype=torch.float64))
+    for k in ("R", "zeta", "jas", "r", "unpaired"):
         a, b = g[k].cpu(), ref[k]
         assert (a - b).abs().max().item() / max(1.0, b.abs().max().item()) <= 1e-8, k
 
