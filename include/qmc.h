@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define QMC_ABI_VERSION 15
+#define QMC_ABI_VERSION 16
 
 typedef enum {
   QMC_OK = 0,
@@ -125,8 +125,8 @@ typedef struct {
    * t in [con_ptr[c], con_ptr[c+1]), c < Lc; lambda is then [Lc][Lc] and every
    * [L] of the calls below that refers to orbitals (Phi rows) reads Lc.
    * L <= 2048 primitives.  qmc_forces returns the gradients with respect to the
-   * primitives' exponents and Lambda over the contracted orbitals (not with
-   * respect to con_coef).  Not supported with it: qmc_multi_*. */
+   * primitives' exponents, Lambda over the contracted orbitals and con_coef
+   * (qmc_grads.dcon_coef).  Not supported with it: qmc_multi_*. */
   int32_t n_contracted;       /* Lc (0: the basis functions are the orbitals)    */
   const int32_t *con_ptr;     /* [Lc + 1], con_ptr[0] = 0, non-decreasing        */
   const int32_t *con_idx;     /* [con_ptr[Lc]] primitive index, 0 .. L-1         */
@@ -270,6 +270,8 @@ typedef struct {
   double *djb_zeta; /* [LJ] or [Wk][LJ]                                          */
   /* Unpaired orbitals (k = n_up - n_dn > 0; ignored otherwise): */
   double *dunpaired; /* [L][k] or [Wk][L][k]: d/dU[mu][l], U as in the descriptor */
+  /* Contracted orbitals (n_contracted > 0; ignored otherwise): */
+  double *dcon_coef; /* [nnz] or [Wk][nnz], nnz = con_ptr[n_contracted]: d/dcon_coef[t] */
 } qmc_grads;
 
 /* Adjoint of the evaluation (Derivatives of energy section: logarithmic

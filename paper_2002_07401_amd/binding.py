@@ -54,7 +54,8 @@ class QMCError(RuntimeError):
 class Grads(ctypes.Structure):
     _fields_ = [("dR", ctypes.c_void_p), ("dzeta", ctypes.c_void_p), ("dlambda", ctypes.c_void_p),
                 ("djas", ctypes.c_void_p), ("dr", ctypes.c_void_p), ("dj1_inh", ctypes.c_void_p),
-                ("dj3", ctypes.c_void_p), ("djb_zeta", ctypes.c_void_p), ("dunpaired", ctypes.c_void_p)]
+                ("dj3", ctypes.c_void_p), ("djb_zeta", ctypes.c_void_p), ("dunpaired", ctypes.c_void_p),
+                ("dcon_coef", ctypes.c_void_p)]
 
 
 class LrdmcParams(ctypes.Structure):
@@ -215,6 +216,12 @@ class JAGPSystem:
         self.n_jas = len(s.Z) + len(s.j2)
         self.LJ = LJ
         self.n_basis = len(s.zeta)
+        # contraction coefficients in the order passed (CSR by orbital): entry t is
+        # C[con_mu[t], con_orb[t]]
+        self.n_con = 0 if Cm is None else int(keep["con_ptr"][-1])
+        if Cm is not None:
+            self.con_mu = keep["con_idx"].astype(np.int64)
+            self.con_orb = np.repeat(np.arange(Cm.shape[1]), np.diff(keep["con_ptr"]))
         self.pairing = pf
         self.npf = s.n_up + s.n_dn + k_pf if pf else 0
 
@@ -344,6 +351,8 @@ class Walkers:
         elif S.n_up > S.n_dn:   # unpaired orbitals U [L][k]
             k = S.n_up - S.n_dn
             out["unpaired"] = f(Wk, L, k) if per_walker else f(L, k)
+        if S.n_con:             # contraction coefficients, in the CSR order passed
+            out["con_coef"] = f(Wk, S.n_con) if per_walker else f(S.n_con)
         LJ = S.LJ
         if LJ:
             pre = (Wk,) if per_walker else ()
@@ -351,7 +360,7 @@ class Walkers:
         g = Grads(dR=_ptr(out["R"]), dzeta=_ptr(out["zeta"]), dlambda=_ptr(out.get("lam")),
                   djas=_ptr(out["jas"]), dr=_ptr(out["r"]), dj1_inh=_ptr(out.get("j1_inh")),
                   dj3=_ptr(out.get("j3")), djb_zeta=_ptr(out.get("jb_zeta")),
-                  dunpaired=_ptr(out.get("unpaired")))
+                  dunpaired=_ptr(out.get("unpaired")), dcon_coef=_ptr(out.get("con_coef")))
         _check(load().qmc_forces(S.h, self.h, _ptr(r), 1 if per_walker else 0, _ptr(gbar_logpsi),
                                  _ptr(gbar_eloc), ctypes.byref(g), _stream(stream)))
         return out

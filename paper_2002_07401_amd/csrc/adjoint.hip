@@ -869,10 +869,41 @@ static hipError_t pf_backward(const SysDev& s, const WalkDev& w, const AdjWork& 
   return hipGetLastError();
 }
 
+// Contraction coefficients: phi_c = sum_t C_t psi_{mu_t} and its gradient and
+// Laplacian are linear in C, so with dF/dphi (PB), dF/d(lap phi) = c Y and
+// dF/d(grad phi) = 2 c grad J Y (c = -gb/2) over the orbitals
+//   dF/dC_t = sum_i PB[i][c_t] psi_mu(r_i) + c Y[i][c_t] (lap psi_mu + 2 grad J_i . grad psi_mu)(r_i),
+// the primitives' values and derivatives recomputed per electron.  One
+// workgroup per walker, one thread per orbital and its coefficients.
+__global__ void __launch_bounds__(256)
+con_grad_kernel(SysDev s, WalkDev w, const double* __restrict__ PB, const double* __restrict__ gb,
+                double* __restrict__ out) {
+  const int wk = blockIdx.x;
+  const double cq = gb ? -0.5 * gb[wk] : 0.0;
+  const double* r = w.r + (long)wk * s.N * 3;
+  const double* pb = PB + (long)wk * s.N * s.Lp;
+  const double* yt = w.Yt + (long)wk * s.N * s.Lp;
+  const double* gJ = w.gJ + (long)wk * s.N * 4;
+  const int nnz = s.con_ptr[s.L];
+  double* o = out + (long)wk * nnz;
+  for (int c = threadIdx.x; c < s.L; c += blockDim.x)
+    for (int k = s.con_ptr[c]; k < s.con_ptr[c + 1]; ++k) {
+      const int mu = s.con_idx[k];
+      double acc = 0.0;
+      for (int i = 0; i < s.N; ++i) {
+        double v, bx, by, bz, lp;
+        basis_vgl(s, mu, r[3 * i], r[3 * i + 1], r[3 * i + 2], v, bx, by, bz, lp);
+        acc += pb[(long)i * s.Lp + c] * v;
+        if (gb) acc += cq * yt[(long)i * s.Lp + c] * (lp + 2.0 * (bx * gJ[4 * i] + by * gJ[4 * i + 1] + bz * gJ[4 * i + 2]));
+      }
+      o[k] = acc;
+    }
+}
+
 hipError_t launch_forces(const SysDev& s, const WalkDev& w, const AdjWork& aw, const double* ga,
                          const double* gb, int per_walker, double* dR, double* dzeta, double* dlambda,
                          double* djas, double* dr, double* dj1_inh, double* dj3, double* djb_zeta,
-                         double* dunpaired, hipStream_t st) {
+                         double* dunpaired, double* dcon, hipStream_t st) {
   const int Wk = w.Wk, Lp = s.Lp, N = s.N;
   if (s.pairing) {
     HT(pf_backward(s, w, aw, ga, gb, st));
@@ -881,6 +912,10 @@ hipError_t launch_forces(const SysDev& s, const WalkDev& w, const AdjWork& aw, c
   }
   // 8. basis and Jastrow/Coulomb backward (over the primitives of a contracted basis)
   double* drw = dr ? dr : aw.dr;
+  if (s.Lq && dcon) {
+    hipLaunchKernelGGL(con_grad_kernel, dim3(Wk), dim3(256), 0, st, s, w, aw.PB, gb, per_walker ? dcon : aw.dcw);
+    HT(hipGetLastError());
+  }
   if (s.Lq) {
     const int lqp = (s.Lq + 31) / 32 * 32;
     const unsigned rows = (unsigned)((long)Wk * N);
@@ -915,6 +950,7 @@ hipError_t launch_forces(const SysDev& s, const WalkDev& w, const AdjWork& aw, c
       if (djb_zeta) HT(hipMemcpyAsync(djb_zeta, aw.jzbar, sizeof(double) * Wk * LJ, hipMemcpyDeviceToDevice, st));
     }
   } else {
+    if (s.Lq && dcon) HT(sum_rows(aw.dcw, Wk, s.nnz_con, dcon, st));
     if (dR) HT(sum_rows(aw.Rbar, Wk, (long)s.n_nuc * 3, dR, st));
     if (dzeta) HT(sum_rows(aw.zbar, Wk, s.nprim(), dzeta, st));
     if (djas) HT(sum_rows(aw.jbar, Wk, nj, djas, st));

@@ -106,6 +106,7 @@ struct SysDev {
   // (orbitals c with coefficient pri_coef[t] = C[mu][c] for t in
   // [pri_ptr[mu], pri_ptr[mu+1])), so that sum_c C[mu][c] y_c is one short loop.
   int Lq;
+  int nnz_con;       // number of contraction coefficients (con_ptr[L])
   int* con_ptr;      // [L+1]
   int* con_idx;      // [nnz]
   double* con_coef;  // [nnz]
@@ -231,6 +232,8 @@ struct AdjWork {
   // [Wk][npf][npf]; [H Q_up | H Q_dn] rows [Wk][N][2 Lp]; dF/dPhi through G~
   // and the B rows [Wk][N][Lp]
   double *pfT, *pfZ1, *pfZ, *pfBb, *pfY;
+  // contracted orbitals: per-walker gradients of the coefficients [Wk][nnz]
+  double* dcw;
   int chunk_walkers;
   int chunks;
 };
@@ -258,7 +261,7 @@ hipError_t launch_philox_draws(unsigned long long seed, int member, int Wk, unsi
 hipError_t launch_forces(const SysDev& s, const WalkDev& w, const AdjWork& aw, const double* ga,
                          const double* gb, int per_walker, double* dR, double* dzeta, double* dlambda,
                          double* djas, double* dr, double* dj1_inh, double* dj3, double* djb_zeta,
-                         double* dunpaired, hipStream_t st);
+                         double* dunpaired, double* dcon, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // device helpers

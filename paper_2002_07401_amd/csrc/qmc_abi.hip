@@ -327,6 +327,7 @@ extern "C" qmc_status qmc_system_create(const qmc_system_desc* desc, qmc_system*
     if (!e) e = up((void**)&d.jcmu, jmu.data(), sizeof(int) * LJ);
   }
   d.Lq = Lc > 0 ? Lb : 0;
+  d.nnz_con = Lc > 0 ? q.con_ptr[Lc] : 0;
   if (!e && Lc > 0) {
     const int nnz = q.con_ptr[Lc];
     // the same matrix by primitive: pri_* (counting sort of the entries by primitive)
@@ -925,6 +926,7 @@ static hipError_t alloc_adjoint(qmc_walkers* wk) {
   }
   if (s.Lq) {
     const size_t lqp = (s.Lq + 31) / 32 * 32;
+    al(&a.dcw, Wk * (size_t)s.nnz_con);
     al(&a.PBq, Wk * N * lqp);
     al(&a.Ytq, Wk * N * lqp);
   }
@@ -972,7 +974,8 @@ extern "C" qmc_status qmc_forces(qmc_system* sys, qmc_walkers* wk, const double*
   if (c) return c;
   HIP_TRY(launch_forces(s, wk->d, wk->aw, gbar_logpsi, gbar_eloc, per_walker, out->dR, out->dzeta,
                         out->dlambda, out->djas, out->dr, s.LJ ? out->dj1_inh : nullptr, s.LJ ? out->dj3 : nullptr,
-                        s.LJ ? out->djb_zeta : nullptr, s.nk ? out->dunpaired : nullptr, stream), "forces");
+                        s.LJ ? out->djb_zeta : nullptr, s.nk ? out->dunpaired : nullptr,
+                        s.Lq ? out->dcon_coef : nullptr, stream), "forces");
   return QMC_OK;
 }
 

@@ -112,6 +112,14 @@ def test_contracted_lattice_hops(cw):
     assert rel_err(g["ratios"].cpu(), L.lattice_ratios(sy, r, a_i)).max().item() <= 1e-10
 
 
+def _oracle_contraction_grads(sy, r, gl, ge):
+    """Autodiff of sum_w (gl log|Psi| + ge e_L) with respect to the dense contraction matrix."""
+    Cm = sy.contraction.detach().clone().requires_grad_(True)
+    out = O.evaluate(dataclasses.replace(sy, contraction=Cm), r)
+    F = (gl * out["logabs"]).sum() + (ge * out["e_loc"]).sum()
+    return torch.autograd.grad(F, Cm)[0]
+
+
 def test_contracted_forces_match_oracle(cw):
     # the adjoint over contracted orbitals: orbital-level products, then the
     # basis backward over the primitives (exponent gradients per primitive)
@@ -126,11 +134,26 @@ def test_contracted_forces_match_oracle(cw):
     torch.cuda.synchronize()
     ref = O.forces_vjp(sy, r, gl, ge)
     assert out["zeta"].shape == (60,) and out["lam"].shape == (28, 28)
-    for k in ("R", "zeta", "lam", "jas", "r"):
+    # the coefficients C[mu][c] of the pattern, in the CSR order the binding passed
+    sysh = wk.sys
+    Cg = _oracle_contraction_grads(sy, r, gl, ge)
+    ref["con_coef"] = Cg[torch.tensor(sysh.con_mu), torch.tensor(sysh.con_orb)]
+    for k in ("R", "zeta", "lam", "jas", "r", "con_coef"):
         a, b = out[k].cpu(), ref[k]
         err = (a - b).abs().max().item() / max(1.0, b.abs().max().item())
         print(f"[contracted forces] {k}: {err:.3e}")
         assert err <= 1e-8, (k, err)
+    # per walker, log|Psi| only
+    one = torch.ones(Wk, dtype=torch.float64, device="cuda")
+    per = wk.forces(r.cuda(), one, None, per_walker=True)
+    torch.cuda.synchronize()
+    for w_ in (0, Wk - 1):
+        g1 = torch.zeros(Wk, dtype=torch.float64)
+        g1[w_] = 1.0
+        b = _oracle_contraction_grads(sy, r, g1, torch.zeros(Wk, dtype=torch.float64))
+        b = b[torch.tensor(sysh.con_mu), torch.tensor(sysh.con_orb)]
+        a = per["con_coef"][w_].cpu()
+        assert (a - b).abs().max().item() / max(1.0, b.abs().max().item()) <= 1e-8, w_
 
 
 def test_contracted_refusals(cw):

@@ -447,6 +447,11 @@ def _oracle_pf_forces(sy, r, gl, ge):
         repl.update(j1_inh=j1, j3=j3, jb_zeta=jz)
         keys += ["j1_inh", "j3", "jb_zeta"]
         leaves += [j1, j3, jz]
+    if sy.contraction is not None:
+        Cm = leaf(sy.contraction)
+        repl.update(contraction=Cm)
+        keys += ["contraction"]
+        leaves += [Cm]
     sw = dataclasses.replace(sy, **repl)
     G = PF.pairing_matrix(sw, O.agp_basis(sw, rr)[0])
     lp = 0.5 * torch.linalg.slogdet(G)[1] + O.jastrow(sw, rr)[0]
@@ -485,6 +490,9 @@ def test_pfaffian_forces_match_oracle(fw, kind):
     out = wk.forces(r.cuda(), gl.cuda(), ge.cuda())
     torch.cuda.synchronize()
     ref = _oracle_pf_forces(sy, r, gl, ge)
+    if "contraction" in ref:   # the pattern's entries, in the CSR order the binding passed
+        Cg = ref.pop("contraction")
+        ref["con_coef"] = Cg[torch.tensor(wk.sys.con_mu), torch.tensor(wk.sys.con_orb)]
     for k, b in ref.items():
         a = out[k].cpu()
         err = (a - b).abs().max().item() / max(1.0, b.abs().max().item())
