@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define QMC_ABI_VERSION 16
+#define QMC_ABI_VERSION 17
 
 typedef enum {
   QMC_OK = 0,
@@ -145,7 +145,7 @@ typedef struct {
    * (eq:pfodd): G~_{i, N+l} = phi(r_i) . U^{s_i}[:, l] with U^u = unpaired
    * and U^d = pf_unpaired_dn.  N + pf_k must be even and at most 96; FP64
    * precision only; n_up < n_dn is allowed.  Not supported with it:
-   * qmc_forces' pairing-coefficient output, qmc_multi_*.  qmc_reweight uses G~ and its inverse;
+   * qmc_multi_*.  qmc_reweight uses G~ and its inverse;
    * qmc_system_set_params (lambda = A^{ud}) and qmc_system_set_pfaffian change
    * the coefficients. */
   int32_t pairing;            /* 0 AGP determinant, 1 Pfaffian                   */
@@ -272,6 +272,13 @@ typedef struct {
   double *dunpaired; /* [L][k] or [Wk][L][k]: d/dU[mu][l], U as in the descriptor */
   /* Contracted orbitals (n_contracted > 0; ignored otherwise): */
   double *dcon_coef; /* [nnz] or [Wk][nnz], nnz = con_ptr[n_contracted]: d/dcon_coef[t] */
+  /* Pfaffian systems (pairing = 1; must be NULL otherwise): dlambda is A^{ud},
+   * dunpaired the up spin's unpaired orbitals [L][pf_k]; the skew same-spin
+   * blocks as gradients with respect to skew matrices (written skew), and the
+   * down spin's unpaired orbitals: */
+  double *dpf_uu;    /* [L][L] or [Wk][L][L]                                       */
+  double *dpf_dd;    /* [L][L] or [Wk][L][L]                                       */
+  double *dunpaired_dn; /* [L][pf_k] or [Wk][L][pf_k]                              */
 } qmc_grads;
 
 /* Adjoint of the evaluation (Derivatives of energy section: logarithmic
@@ -285,11 +292,12 @@ typedef struct {
  * Re-evaluates the walkers at r (their state becomes that of qmc_eval_batch).
  * FP64 systems with N <= 256 electrons and <= 256 nuclei.  The first call on
  * a walker set allocates its workspace.
- * Pfaffian systems: dR, dzeta, djas, dr and the Jastrow-basis outputs as
- * above (log|Psi| through the cofactor vectors Y_i, e_L through Y, G~^{-1} and
- * the pairing rows); dlambda and dunpaired must be NULL (QMC_ERR_ARG): the
- * pairing coefficients' log-derivatives come from qmc_pfaffian_logderiv, their
- * local-energy derivatives are not built. */
+ * Pfaffian systems: every output above (log|Psi| through the cofactor
+ * vectors Y_i, e_L through Y, G~^{-1} and the pairing rows), the pairing
+ * coefficients in dlambda (A^{ud}), dpf_uu, dpf_dd, dunpaired and dunpaired_dn;
+ * with gbar_eloc NULL these equal qmc_pfaffian_logderiv's weighted by
+ * gbar_logpsi.  dpf_uu, dpf_dd or dunpaired_dn on a determinant system:
+ * QMC_ERR_ARG. */
 qmc_status qmc_forces(qmc_system *sys, qmc_walkers *wk, const double *r, int32_t per_walker,
                       const double *gbar_logpsi, const double *gbar_eloc, const qmc_grads *out,
                       hipStream_t stream);

@@ -55,7 +55,8 @@ class Grads(ctypes.Structure):
     _fields_ = [("dR", ctypes.c_void_p), ("dzeta", ctypes.c_void_p), ("dlambda", ctypes.c_void_p),
                 ("djas", ctypes.c_void_p), ("dr", ctypes.c_void_p), ("dj1_inh", ctypes.c_void_p),
                 ("dj3", ctypes.c_void_p), ("djb_zeta", ctypes.c_void_p), ("dunpaired", ctypes.c_void_p),
-                ("dcon_coef", ctypes.c_void_p)]
+                ("dcon_coef", ctypes.c_void_p), ("dpf_uu", ctypes.c_void_p), ("dpf_dd", ctypes.c_void_p),
+                ("dunpaired_dn", ctypes.c_void_p)]
 
 
 class LrdmcParams(ctypes.Structure):
@@ -346,8 +347,12 @@ class Walkers:
             out = dict(R=f(Wk, A, 3), zeta=f(Wk, S.n_basis), lam=f(Wk, L, L), jas=f(Wk, nj), r=f(Wk, N, 3))
         else:
             out = dict(R=f(A, 3), zeta=f(S.n_basis), lam=f(L, L), jas=f(nj), r=f(Wk, N, 3))
-        if S.pairing:       # pairing-coefficient derivatives: pfaffian_logderiv
-            del out["lam"]
+        if S.pairing:       # "lam" is A^{ud}; the skew blocks and both spins' unpaired orbitals
+            pre = (Wk,) if per_walker else ()
+            out.update(pf_uu=f(*pre, L, L), pf_dd=f(*pre, L, L))
+            k = S.npf - S.n_elec
+            if k:
+                out.update(unpaired=f(*pre, L, k), unpaired_dn=f(*pre, L, k))
         elif S.n_up > S.n_dn:   # unpaired orbitals U [L][k]
             k = S.n_up - S.n_dn
             out["unpaired"] = f(Wk, L, k) if per_walker else f(L, k)
@@ -360,7 +365,9 @@ class Walkers:
         g = Grads(dR=_ptr(out["R"]), dzeta=_ptr(out["zeta"]), dlambda=_ptr(out.get("lam")),
                   djas=_ptr(out["jas"]), dr=_ptr(out["r"]), dj1_inh=_ptr(out.get("j1_inh")),
                   dj3=_ptr(out.get("j3")), djb_zeta=_ptr(out.get("jb_zeta")),
-                  dunpaired=_ptr(out.get("unpaired")), dcon_coef=_ptr(out.get("con_coef")))
+                  dunpaired=_ptr(out.get("unpaired")), dcon_coef=_ptr(out.get("con_coef")),
+                  dpf_uu=_ptr(out.get("pf_uu")), dpf_dd=_ptr(out.get("pf_dd")),
+                  dunpaired_dn=_ptr(out.get("unpaired_dn")))
         _check(load().qmc_forces(S.h, self.h, _ptr(r), 1 if per_walker else 0, _ptr(gbar_logpsi),
                                  _ptr(gbar_eloc), ctypes.byref(g), _stream(stream)))
         return out

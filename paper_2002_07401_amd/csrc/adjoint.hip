@@ -792,17 +792,79 @@ pf_phibar_kernel(const double* __restrict__ Yt, const double* __restrict__ Yb, c
   if (idx >= tot) return;
   const long w = idx / per_w;
   double v = ga ? ga[w] * Yt[idx] : 0.0;
-  if (gb) v += -0.5 * gb[w] * Yb[idx];
+  if (gb) v += Yb[idx];
   PB[idx] = v;
 }
 
+// Q rows of the stacks times c_w = -gb[w]/2 (rows n .. 2n of every walker).
+__global__ void __launch_bounds__(256)
+pf_scale_q_kernel(double* __restrict__ SU, double* __restrict__ SD, const double* __restrict__ gb, int n, int Lp,
+                  long tot) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= tot) return;
+  const long per = (long)n * Lp, w = idx / per, o = w * 2 * per + per + idx % per;
+  const double c = -0.5 * gb[w];
+  SU[o] *= c;
+  SD[o] *= c;
+}
+
+// M = D - D^T for D = dF/dG~ = ga/2 H^T - Z^T (Z = H T' H with the scaled Q rows;
+// omitted without local-energy weights): M[a][b] = ga/2 (H[b][a] - H[a][b]) + Z[a][b] - Z[b][a].
+__global__ void __launch_bounds__(256)
+pf_gbar_kernel(const double* __restrict__ H, const double* __restrict__ Z, const double* __restrict__ ga, long np,
+               long tot, double* __restrict__ M) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= tot) return;
+  const long w = idx / (np * np), ab = idx % (np * np), a = ab / np, b = ab % np;
+  const double* h = H + w * np * np;
+  double v = ga ? 0.5 * ga[w] * (h[b * np + a] - h[a * np + b]) : 0.0;
+  if (Z) {
+    const double* z = Z + w * np * np;
+    v += z[a * np + b] - z[b * np + a];
+  }
+  M[idx] = v;
+}
+
+// E[i][mu] -= Bb[row0 + i][half * Lp + mu] for i < ni (every walker).
+__global__ void __launch_bounds__(256)
+pf_sub_bb_kernel(double* __restrict__ E, const double* __restrict__ Bb, int ni, int Lp, int N, int row0, int half,
+                 long tot) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= tot) return;
+  const long per = (long)ni * Lp, w = idx / per, i = (idx % per) / Lp, mu = idx % Lp;
+  E[w * (long)N * Lp + i * Lp + mu] -= Bb[(w * N + row0 + i) * 2L * Lp + (long)half * Lp + mu];
+}
+
+__global__ void __launch_bounds__(256) pf_half_kernel(double* __restrict__ X, long per, long stride, long tot) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= tot) return;
+  X[(idx / per) * stride + idx % per] *= 0.5;
+}
+
+__global__ void __launch_bounds__(256) pf_zero_kernel(double* __restrict__ X, long per, long stride, long tot) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= tot) return;
+  X[(idx / per) * stride + idx % per] = 0.0;
+}
+
+// dcoef (optional): pairing-coefficient gradients, per walker
+// [Wk][3 L L + 2 L k]: A^{ud}, A^{uu}, A^{dd} (the same-spin ones as gradients
+// with respect to skew matrices), then U^u and U^d [L][k].
 static hipError_t pf_backward(const SysDev& s, const WalkDev& w, const AdjWork& aw, const double* ga,
-                              const double* gb, hipStream_t st) {
-  const int Wk = w.Wk, Lp = s.Lp, N = s.N, n = s.nu, nd = s.nd, np = s.npf, pk = s.pk;
+                              const double* gb, double* dcoef, hipStream_t st) {
+  const int Wk = w.Wk, Lp = s.Lp, N = s.N, n = s.nu, nd = s.nd, np = s.npf, pk = s.pk, L = s.L;
   const long rowst = (long)N * Lp, stk = 2L * n * Lp, nn = (long)np * np;
-  if (gb) {
+  if (gb || dcoef) {   // the stacks [Phi; Q] of both spins
     hipLaunchKernelGGL(stack_basis_kernel, dim3((unsigned)((long)Wk * N)), dim3(256), 0, st, s, w, aw.SU, aw.SD);
     HT(hipGetLastError());
+  }
+  if (gb) {
+    {   // Q rows times c = -gb/2: every product below carries the factor
+      const long tot = (long)Wk * n * Lp;
+      hipLaunchKernelGGL(pf_scale_q_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, aw.SU, aw.SD, gb,
+                         n, Lp, tot);
+      HT(hipGetLastError());
+    }
     // T rows of the up then the down electrons (rows N.. stay zero)
     for (int sp = 0; sp < 2; ++sp) {
       const int i0 = sp ? n : 0, ni = sp ? nd : n;
@@ -866,7 +928,90 @@ static hipError_t pf_backward(const SysDev& s, const WalkDev& w, const AdjWork& 
   const long tot = rowst * Wk;
   hipLaunchKernelGGL(pf_phibar_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, w.Yt, aw.pfY, ga, gb,
                      rowst, tot, aw.PB);
-  return hipGetLastError();
+  HT(hipGetLastError());
+  if (!dcoef) return hipSuccess;
+  // pairing coefficients: G~_ij = phi_i^T A^{s_i s_j} phi_j (A^{du} = -A^{ud T}) and
+  // B^s_j = A^{s s_j} phi_j give, with M = D - D^T and Bb = [H Q'_u | H Q'_d],
+  //   out_{st} = f (Phi_s^T (M_{st} Phi_t - Bb_t[s rows]) + Bb_s[t rows]^T Phi_t)
+  // (f = 1/2 for the skew same-spin blocks, 1 for A^{ud}), and
+  //   dU^s = Phi_s^T M[s rows, N:] + Q'_s^T H[N:, s cols]^T.
+  const long per = 3L * L * L + 2L * L * pk, totm = nn * Wk;
+  hipLaunchKernelGGL(pf_gbar_kernel, dim3((unsigned)((totm + 255) / 256)), dim3(256), 0, st, w.A,
+                     gb ? aw.pfZ : nullptr, ga, (long)np, totm, aw.pfZ1);
+  HT(hipGetLastError());
+  const int blk[3][2] = {{0, 1}, {0, 0}, {1, 1}};   // (s, t): A^{ud}, A^{uu}, A^{dd}
+  for (int q = 0; q < 3; ++q) {
+    const int sg = blk[q][0], tg = blk[q][1];
+    const int s0 = sg ? n : 0, ns = sg ? nd : n, t0 = tg ? n : 0, nt = tg ? nd : n;
+    double* O = dcoef + (long)q * L * L;
+    if (ns == 0 || nt == 0) {
+      const long tz = (long)Wk * L * L;
+      hipLaunchKernelGGL(pf_zero_kernel, dim3((unsigned)((tz + 255) / 256)), dim3(256), 0, st, O, (long)L * L, per,
+                         tz);
+      HT(hipGetLastError());
+      continue;
+    }
+    const double* Phs = sg ? aw.SD : aw.SU;   // Phi rows of spin s (rows 0 .. ns of the stack)
+    const double* Pht = tg ? aw.SD : aw.SU;
+    // E = M[s rows, t cols] Phi_t  (into pfY rows 0 .. ns)
+    GemmArgs g = gemm_args(ns, Lp, nt);
+    g.A = aw.pfZ1 + (long)s0 * np + t0; g.lda = np; g.a_bs = nn;
+    g.B = Pht; g.ldb = Lp; g.b_bs = stk;
+    g.C = aw.pfY; g.ldc = Lp; g.c_bs = rowst; g.batch = Wk;
+    HT(gemm_f64(g, false, false, false, st));
+    if (gb) {
+      const long te = (long)Wk * ns * Lp;
+      hipLaunchKernelGGL(pf_sub_bb_kernel, dim3((unsigned)((te + 255) / 256)), dim3(256), 0, st, aw.pfY, aw.pfBb, ns,
+                         Lp, N, s0, tg, te);
+      HT(hipGetLastError());
+    }
+    // O = Phi_s^T E (+ Bb_s[t rows]^T Phi_t)
+    GemmArgs o = gemm_args(L, L, ns);
+    o.A = Phs; o.lda = Lp; o.a_bs = stk;
+    o.B = aw.pfY; o.ldb = Lp; o.b_bs = rowst;
+    o.C = O; o.ldc = L; o.c_bs = per; o.batch = Wk;
+    HT(gemm_f64(o, true, false, false, st));
+    if (gb) {
+      GemmArgs b = gemm_args(L, L, nt);
+      b.A = aw.pfBb + (long)t0 * 2 * Lp + (long)sg * Lp; b.lda = 2L * Lp; b.a_bs = 2 * rowst;
+      b.B = Pht; b.ldb = Lp; b.b_bs = stk;
+      b.C = O; b.ldc = L; b.c_bs = per; b.batch = Wk;
+      b.accumulate = 1;
+      HT(gemm_f64(b, true, false, false, st));
+    }
+    if (q > 0) {
+      const long th = (long)Wk * L * L;
+      hipLaunchKernelGGL(pf_half_kernel, dim3((unsigned)((th + 255) / 256)), dim3(256), 0, st, O, (long)L * L, per,
+                         th);
+      HT(hipGetLastError());
+    }
+  }
+  for (int sg = 0; sg < 2 && pk > 0; ++sg) {
+    const int s0 = sg ? n : 0, ns = sg ? nd : n;
+    double* O = dcoef + 3L * L * L + (long)sg * L * pk;
+    if (ns == 0) {
+      const long tz = (long)Wk * L * pk;
+      hipLaunchKernelGGL(pf_zero_kernel, dim3((unsigned)((tz + 255) / 256)), dim3(256), 0, st, O, (long)L * pk, per,
+                         tz);
+      HT(hipGetLastError());
+      continue;
+    }
+    const double* S = sg ? aw.SD : aw.SU;
+    GemmArgs u = gemm_args(L, pk, ns);
+    u.A = S; u.lda = Lp; u.a_bs = stk;
+    u.B = aw.pfZ1 + (long)s0 * np + N; u.ldb = np; u.b_bs = nn;
+    u.C = O; u.ldc = pk; u.c_bs = per; u.batch = Wk;
+    HT(gemm_f64(u, true, false, false, st));
+    if (gb) {
+      GemmArgs v = gemm_args(L, pk, ns);
+      v.A = S + (long)n * Lp; v.lda = Lp; v.a_bs = stk;
+      v.B = w.A + (long)N * np + s0; v.ldb = np; v.b_bs = nn;
+      v.C = O; v.ldc = pk; v.c_bs = per; v.batch = Wk;
+      v.accumulate = 1;
+      HT(gemm_f64(v, true, true, false, st));
+    }
+  }
+  return hipSuccess;
 }
 
 // Contraction coefficients: phi_c = sum_t C_t psi_{mu_t} and its gradient and
@@ -903,10 +1048,28 @@ con_grad_kernel(SysDev s, WalkDev w, const double* __restrict__ PB, const double
 hipError_t launch_forces(const SysDev& s, const WalkDev& w, const AdjWork& aw, const double* ga,
                          const double* gb, int per_walker, double* dR, double* dzeta, double* dlambda,
                          double* djas, double* dr, double* dj1_inh, double* dj3, double* djb_zeta,
-                         double* dunpaired, double* dcon, hipStream_t st) {
+                         double* dunpaired, double* dcon, double* dpf_uu, double* dpf_dd,
+                         double* dunpaired_dn, hipStream_t st) {
   const int Wk = w.Wk, Lp = s.Lp, N = s.N;
   if (s.pairing) {
-    HT(pf_backward(s, w, aw, ga, gb, st));
+    const bool coef = dlambda || dunpaired || dpf_uu || dpf_dd || dunpaired_dn;
+    HT(pf_backward(s, w, aw, ga, gb, coef ? aw.pfD : nullptr, st));
+    if (coef) {   // [Wk][A^{ud} | A^{uu} | A^{dd} | U^u | U^d] -> the outputs
+      const long L2 = (long)s.L * s.L, Lk = (long)s.L * s.pk, per = 3 * L2 + 2 * Lk;
+      const double* src = aw.pfD;
+      if (!per_walker) {
+        HT(sum_rows(aw.pfD, Wk, per, aw.pfS, st));
+        src = aw.pfS;
+      }
+      const int rows = per_walker ? Wk : 1;
+      double* dst[5] = {dlambda, dpf_uu, dpf_dd, s.pk ? dunpaired : nullptr, s.pk ? dunpaired_dn : nullptr};
+      const long off[5] = {0, L2, 2 * L2, 3 * L2, 3 * L2 + Lk};
+      const long len[5] = {L2, L2, L2, Lk, Lk};
+      for (int q = 0; q < 5; ++q)
+        if (dst[q] && len[q] > 0)
+          HT(hipMemcpy2DAsync(dst[q], sizeof(double) * len[q], src + off[q], sizeof(double) * per,
+                              sizeof(double) * len[q], rows, hipMemcpyDeviceToDevice, st));
+    }
   } else {
     HT(geminal_backward(s, w, aw, ga, gb, per_walker, dlambda, dunpaired, st));
   }

@@ -232,6 +232,8 @@ struct AdjWork {
   // [Wk][npf][npf]; [H Q_up | H Q_dn] rows [Wk][N][2 Lp]; dF/dPhi through G~
   // and the B rows [Wk][N][Lp]
   double *pfT, *pfZ1, *pfZ, *pfBb, *pfY;
+  // pairing-coefficient gradients per walker [Wk][3 L L + 2 L k] and summed
+  double *pfD, *pfS;
   // contracted orbitals: per-walker gradients of the coefficients [Wk][nnz]
   double* dcw;
   int chunk_walkers;
@@ -261,7 +263,8 @@ hipError_t launch_philox_draws(unsigned long long seed, int member, int Wk, unsi
 hipError_t launch_forces(const SysDev& s, const WalkDev& w, const AdjWork& aw, const double* ga,
                          const double* gb, int per_walker, double* dR, double* dzeta, double* dlambda,
                          double* djas, double* dr, double* dj1_inh, double* dj3, double* djb_zeta,
-                         double* dunpaired, double* dcon, hipStream_t st);
+                         double* dunpaired, double* dcon, double* dpf_uu, double* dpf_dd,
+                         double* dunpaired_dn, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // device helpers

@@ -923,6 +923,9 @@ static hipError_t alloc_adjoint(qmc_walkers* wk) {
     al(&a.pfZ, Wk * np * np);
     al(&a.pfBb, Wk * N * 2 * Lp);
     al(&a.pfY, Wk * N * Lp);
+    const size_t per = 3 * L * L + 2 * L * (size_t)s.pk;
+    al(&a.pfD, Wk * per);
+    al(&a.pfS, per);
   }
   if (s.Lq) {
     const size_t lqp = (s.Lq + 31) / 32 * 32;
@@ -962,9 +965,8 @@ extern "C" qmc_status qmc_forces(qmc_system* sys, qmc_walkers* wk, const double*
   if (!r || !out) return fail(QMC_ERR_ARG, "null positions or output block");
   const SysDev& s = sys->d;
   if (s.precision != QMC_FP64) return fail(QMC_ERR_UNSUPPORTED, "forces are built for the FP64 path");
-  if (s.pairing && (out->dlambda || out->dunpaired))
-    return fail(QMC_ERR_ARG, "Pfaffian pairing-coefficient derivatives come from qmc_pfaffian_logderiv "
-                             "(dlambda and dunpaired must be NULL)");
+  if (!s.pairing && (out->dpf_uu || out->dpf_dd || out->dunpaired_dn))
+    return fail(QMC_ERR_ARG, "dpf_uu, dpf_dd and dunpaired_dn are outputs of Pfaffian systems");
   if (s.N > 2 * kLuMaxN || s.n_nuc > kMaxNucBack)
     return fail(QMC_ERR_UNSUPPORTED, "forces need N <= 256 electrons and <= 256 nuclei");
   hipError_t e = alloc_adjoint(wk);
@@ -974,8 +976,9 @@ extern "C" qmc_status qmc_forces(qmc_system* sys, qmc_walkers* wk, const double*
   if (c) return c;
   HIP_TRY(launch_forces(s, wk->d, wk->aw, gbar_logpsi, gbar_eloc, per_walker, out->dR, out->dzeta,
                         out->dlambda, out->djas, out->dr, s.LJ ? out->dj1_inh : nullptr, s.LJ ? out->dj3 : nullptr,
-                        s.LJ ? out->djb_zeta : nullptr, s.nk ? out->dunpaired : nullptr,
-                        s.Lq ? out->dcon_coef : nullptr, stream), "forces");
+                        s.LJ ? out->djb_zeta : nullptr, (s.nk || s.pk) ? out->dunpaired : nullptr,
+                        s.Lq ? out->dcon_coef : nullptr, out->dpf_uu, out->dpf_dd,
+                        s.pk ? out->dunpaired_dn : nullptr, stream), "forces");
   return QMC_OK;
 }
 

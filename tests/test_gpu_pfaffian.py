@@ -173,12 +173,14 @@ def test_pfaffian_refusals(fw):
     sysh, wk, r, _ = _eval(P, fw.system, fw.r0, 4)
     one = torch.ones(4, dtype=torch.float64, device="cuda")
     from paper_2002_07401_amd import binding as B
-    lam_out = torch.empty(44, 44, dtype=torch.float64, device="cuda")
-    g = B.Grads(dlambda=B._ptr(lam_out))
-    with pytest.raises(P.QMCError) as ex:   # pairing-coefficient gradients: pfaffian_logderiv
-        B._check(B.load().qmc_forces(sysh.h, wk.h, B._ptr(r.cuda()), 0, B._ptr(one), None, ctypes.byref(g), None))
-    assert ex.value.code == -1
     det = P.JAGPSystem(_balanced(dataclasses.replace(fw.system, pairing=0)))
+    uu_out = torch.empty(44, 44, dtype=torch.float64, device="cuda")
+    g = B.Grads(dpf_uu=B._ptr(uu_out))
+    dwk = P.Walkers(det, 4)
+    dwk.eval_batch(r.cuda())
+    with pytest.raises(P.QMCError) as ex:   # Pfaffian outputs on a determinant system
+        B._check(B.load().qmc_forces(det.h, dwk.h, B._ptr(r.cuda()), 0, B._ptr(one), None, ctypes.byref(g), None))
+    assert ex.value.code == -1
     with pytest.raises(P.QMCError) as ex:   # the Pfaffian setter on a determinant system
         det.set_pfaffian(pf_uu=torch.tensor(fw.system.pf_uu, device="cuda"))
     assert ex.value.code == -1
@@ -412,8 +414,15 @@ def test_pfaffian_log_derivative_adjoint(fw, kind):
     ref = _oracle_pf_log_grads(sy, r)
     one = torch.ones(Wk, dtype=torch.float64, device="cuda")
     per = wk.forces(r.cuda(), one, None, per_walker=True)
+    ld = wk.pfaffian_logderiv()
     torch.cuda.synchronize()
-    assert "lam" not in per
+    # the pairing coefficients' log-derivatives equal qmc_pfaffian_logderiv's
+    pairs = [("lam", "ud"), ("pf_uu", "uu"), ("pf_dd", "dd")]
+    if ld["unpaired_up"] is not None:
+        pairs += [("unpaired", "unpaired_up"), ("unpaired_dn", "unpaired_dn")]
+    for a_, b_ in pairs:
+        x, y = per[a_], ld[b_]
+        assert ((x - y).abs().max() / y.abs().max().clamp(min=1.0)).item() <= 1e-11, a_
     for k, b in ref.items():
         a = per[k].cpu()
         err = (a - b).abs().max().item() / max(1.0, b.abs().max().item())
@@ -434,36 +443,43 @@ def test_pfaffian_log_derivative_adjoint(fw, kind):
 
 def _oracle_pf_forces(sy, r, gl, ge):
     """Autodiff of sum_w (gl log|Psi| + ge e_L) with respect to R, the
-    exponents, the Jastrow vector, r and the Jastrow-basis parameters; e_L from
-    the oracle's Pfaffian evaluation (G~^{-1} by a library inverse, which
-    autodiff differentiates), log|Psi| as in _oracle_pf_log_grads."""
+    exponents, the Jastrow vector, r, the Jastrow-basis parameters, the
+    contraction and the pairing coefficients (same-spin blocks of J3 and of
+    the Pfaffian projected on symmetric / skew matrices); e_L from the
+    oracle's Pfaffian evaluation (G~^{-1} by a library inverse, which autodiff
+    differentiates), log|Psi| as in _oracle_pf_log_grads."""
     A = sy.R.shape[0]
     leaf = lambda t: t.detach().clone().requires_grad_(True)
-    R, z, jas, rr = leaf(sy.R), leaf(sy.zeta), leaf(torch.cat([sy.j1_b, sy.j2])), leaf(r)
-    keys, leaves = ["R", "zeta", "jas", "r"], [R, z, jas, rr]
-    repl = dict(R=R, zeta=z, j1_b=jas[:A], j2=jas[A:])
+    L = dict(R=leaf(sy.R), zeta=leaf(sy.zeta), jas=leaf(torch.cat([sy.j1_b, sy.j2])), r=leaf(r),
+             lam=leaf(sy.lam), pf_uu=leaf(sy.pf_uu), pf_dd=leaf(sy.pf_dd))
+    repl = dict(R=L["R"], zeta=L["zeta"], j1_b=L["jas"][:A], j2=L["jas"][A:], lam=L["lam"], pf_uu=L["pf_uu"],
+                pf_dd=L["pf_dd"])
+    if sy.unpaired.shape[-1]:
+        L.update(unpaired=leaf(sy.unpaired), unpaired_dn=leaf(sy.unpaired_dn))
+        repl.update(unpaired=L["unpaired"], unpaired_dn=L["unpaired_dn"])
     if sy.n_jbasis:
-        j1, j3, jz = leaf(sy.j1_inh), leaf(sy.j3), leaf(sy.jb_zeta)
-        repl.update(j1_inh=j1, j3=j3, jb_zeta=jz)
-        keys += ["j1_inh", "j3", "jb_zeta"]
-        leaves += [j1, j3, jz]
+        L.update(j1_inh=leaf(sy.j1_inh), j3=leaf(sy.j3), jb_zeta=leaf(sy.jb_zeta))
+        repl.update(j1_inh=L["j1_inh"], j3=L["j3"], jb_zeta=L["jb_zeta"])
     if sy.contraction is not None:
-        Cm = leaf(sy.contraction)
-        repl.update(contraction=Cm)
-        keys += ["contraction"]
-        leaves += [Cm]
+        L.update(contraction=leaf(sy.contraction))
+        repl.update(contraction=L["contraction"])
     sw = dataclasses.replace(sy, **repl)
+    rr = L["r"]
     G = PF.pairing_matrix(sw, O.agp_basis(sw, rr)[0])
     lp = 0.5 * torch.linalg.slogdet(G)[1] + O.jastrow(sw, rr)[0]
     el = O.evaluate(sw, rr)["e_loc"]
     F = (gl * lp).sum() + (ge * el).sum()
-    g = list(torch.autograd.grad(F, leaves))
-    if sy.n_jbasis:
-        g3 = g[5].clone()
+    keys = list(L)
+    g = dict(zip(keys, torch.autograd.grad(F, [L[k] for k in keys], allow_unused=True)))
+    g = {k: (torch.zeros_like(L[k]) if v is None else v) for k, v in g.items()}
+    for k in ("pf_uu", "pf_dd"):
+        g[k] = 0.5 * (g[k] - g[k].T)
+    if "j3" in g:
+        g3 = g["j3"].clone()
         g3[0] = 0.5 * (g3[0] + g3[0].T)
         g3[1] = 0.5 * (g3[1] + g3[1].T)
-        g[5] = g3
-    return dict(zip(keys, g))
+        g["j3"] = g3
+    return g
 
 
 @pytest.mark.parametrize("kind", ["plain", "jastrow_basis", "contracted", "no_down"])
