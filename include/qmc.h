@@ -134,8 +134,8 @@ typedef struct {
   /* Unpaired orbitals (eq:wfAGPunpaired): with k = n_up - n_dn > 0 the geminal
    * matrix is n_up x n_up, columns n_dn + l holding sum_mu unpaired[mu][l]
    * phi_mu(r_i) (phi the orbitals: the basis functions, or the contracted
-   * orbitals).  Not supported with it: qmc_multi_*; qmc_forces gives no
-   * gradient with respect to the unpaired coefficients. */
+   * orbitals).  Not supported with it: qmc_multi_*; qmc_forces returns the
+   * gradient with respect to them in qmc_grads.dunpaired. */
   const double *unpaired;     /* [L or Lc][k]; may be NULL when k = 0            */
   /* Pfaffian pairing (Pfaffian wave function section), pairing = 1: Psi =
    * Pf(G~) exp J with G~_ij = phi(r_i)^T A^{s_i s_j} phi(r_j) (eq:g,
