@@ -18,7 +18,7 @@ def declared_functions():
 
 def test_header_declares_the_four_calls():
     names = declared_functions()
-    for n in ("qmc_eval_batch", "qmc_propose_move", "qmc_accept_move"):
+    for n in ("qmc_eval_batch", "qmc_propose_move", "qmc_accept_move", "qmc_forces"):
         assert n in names
 
 
