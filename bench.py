@@ -166,7 +166,7 @@ def run_precision(P, C, w, args, precision):
     prec = {"fp64": P.QMC_FP64, "mixed": P.QMC_MIXED, "bf16": P.QMC_MIXED_BF16, "fp32": P.QMC_W_FP32}[precision]
     esz = {"fp64": 8, "bf16": 2}.get(precision, 4)
     sysh = P.JAGPSystem(s, precision=prec)
-    wk = P.Walkers(sysh, Wk)
+    wk = P.Walkers(sysh, Wk, adjoint=False)
     n_tot = args.warmup + args.steps
     # one more step after the timed ones: the per-kernel breakdown
     disp, unif = C.chain_arrays(20020740, (n_tot + 1) * N, Wk)
@@ -314,7 +314,7 @@ def multi_leg(P, C, precision="fp32", replays=3):
     for n in C.MULTI_SIZES:
         w = C.multi_system(n)
         sysh = P.JAGPSystem(w.system, precision=prec)
-        wk = P.Walkers(sysh, w.r0.shape[0])
+        wk = P.Walkers(sysh, w.r0.shape[0], adjoint=False)
         wk.eval_batch(torch.tensor(w.r0, device=dev))
         members.append((w, sysh, wk))
     m = P.MultiSystem([wk for _, _, wk in members])
@@ -363,7 +363,7 @@ def lrdmc_leg(P, C, iters=10):
     Wk, N, Lb = w.r0.shape[0], s.n_up + s.n_dn, s.n_basis
     prm = C.LRDMC_DOUBLE
     sysh = P.JAGPSystem(s)
-    wk = P.Walkers(sysh, Wk)
+    wk = P.Walkers(sysh, Wk, adjoint=False)
     r0 = torch.tensor(w.r0, device=dev)
     xi = torch.tensor(C.lrdmc_draws(17, iters + 1, Wk), device=dev)
     weight = torch.ones(Wk, dtype=torch.float64, device=dev)
@@ -428,7 +428,7 @@ def large_leg(P, C, steps=128, Wk=256):
     dev = torch.device("cuda:0")
     w = C.large_256nuc_1024e(n_walkers=Wk)
     sysh = P.JAGPSystem(w.system)
-    wk = P.Walkers(sysh, Wk)
+    wk = P.Walkers(sysh, Wk, adjoint=False)
     r = torch.tensor(w.r0, device=dev)
     d, u = C.chain_arrays(41, steps, Wk)
     d, u = torch.tensor(d, device=dev), torch.tensor(u, device=dev)

@@ -29,7 +29,12 @@
  *     on the host before anything is enqueued, and qmc_last_error() returns a
  *     thread-local message.  HIP launch errors surface as QMC_ERR_HIP.  Per-walker
  *     numerical problems never fail a call; they are reported in status[w]:
- *        0 ok, 1 singular geminal matrix (det = 0), 2 non-finite result.
+ *        0 ok, 1 singular geminal matrix (det = 0), 2 non-finite result,
+ *        3 refreshed on drift: a periodic refresh replaced an inverse whose
+ *          residual max|W X - I| exceeded the walker set's drift tolerance
+ *          (qmc_walkers_set_drift_tol).  The inverse diverges where det W
+ *          vanishes (the Atomic forces section relates G^{-1} to 1/Pf near
+ *          nodes), so this flags walkers near a node.
  */
 #ifndef QMC_JAGP_H
 #define QMC_JAGP_H
@@ -42,7 +47,7 @@
 extern "C" {
 #endif
 
-#define QMC_ABI_VERSION 17
+#define QMC_ABI_VERSION 18
 
 typedef enum {
   QMC_OK = 0,
@@ -66,10 +71,14 @@ typedef enum {
                       cofactor products in FP64 (log|Psi|, E_loc and drift at
                       FP64 accuracy) and stores the FP32 copies the moves read.
                       Two extra [Wk][N][round_up(L,32)] FP64 work arrays.        */
-  QMC_MIXED_BF16 = 3 /* as QMC_MIXED with the moves' Phi and P rows stored in
+  QMC_MIXED_BF16 = 3, /* as QMC_MIXED with the moves' Phi and P rows stored in
                       BF16 (half the streamed bytes of FP32; the P half rebuilds
                       between evaluations run on MFMA from the BF16 rows with
                       FP32 accumulation); ratios and updates FP64              */
+  QMC_W_BF16 = 4,  /* unrefined geminal build on BF16 matrix instructions with
+                      FP32 accumulation (not built: QMC_ERR_UNSUPPORTED)        */
+  QMC_W_FP8 = 5    /* unrefined geminal build on FP8 matrix instructions (not
+                      built: QMC_ERR_UNSUPPORTED)                              */
 } qmc_precision;
 
 typedef struct qmc_system qmc_system;   /* opaque: nuclei, basis, Lambda, Jastrow */
@@ -169,10 +178,10 @@ qmc_status qmc_system_destroy(qmc_system *sys);
 /* Replace parameters of a system from DEVICE arrays (any may be NULL to keep
  * the current values): R [A][3], zeta [n_basis], lambda [L][L], jas [A + n_j2]
  * (one-body b per nucleus, then the two-body parameters).  Work is enqueued on
- * `stream`; when jas is given the call also waits for that copy (the two-body
- * parameters live in the launch arguments).  Walker sets of this system must be
- * re-evaluated (qmc_eval_batch) before further moves: proposals return
- * QMC_ERR_STATE until then. */
+ * `stream` and the call returns without waiting (every parameter, the two-body
+ * ones included, is read by the kernels from device memory).  Walker sets of
+ * this system must be re-evaluated (qmc_eval_batch) before further moves:
+ * proposals return QMC_ERR_STATE until then. */
 qmc_status qmc_system_set_params(qmc_system *sys, const double *R, const double *zeta,
                                  const double *lambda, const double *jas, hipStream_t stream);
 
@@ -192,11 +201,32 @@ qmc_status qmc_system_set_jastrow_basis(qmc_system *sys, const double *j1_inh, c
 qmc_status qmc_system_set_pfaffian(qmc_system *sys, const double *pf_uu, const double *pf_dd,
                                    const double *unpaired, const double *unpaired_dn, hipStream_t stream);
 
-/* Allocate the device state of n_walkers walkers of sys (positions, basis
- * matrix Phi, P = Phi Lambda, W, W^{-1} and move buffers).  The state is
- * undefined until qmc_eval_batch has run. */
-qmc_status qmc_walkers_create(qmc_system *sys, int32_t n_walkers, qmc_walkers **out);
+/* Flags of a walker set. */
+#define QMC_WALKERS_ADJOINT 1   /* reserve the reverse-pass workspace of qmc_forces */
+
+/* Bytes of device memory a walker set of n_walkers walkers of sys occupies
+ * with these flags: positions, basis matrix Phi, P = Phi Lambda, W, W^{-1},
+ * move buffers and, with QMC_WALKERS_ADJOINT, the reverse-pass workspace.
+ * Every later call on the walker set works inside this memory (no call
+ * other than create allocates). */
+qmc_status qmc_workspace_size(const qmc_system *sys, int32_t n_walkers, int32_t flags, size_t *bytes);
+
+/* Create the device state of n_walkers walkers of sys.  ws: caller-owned
+ * DEVICE memory of at least qmc_workspace_size bytes, 256-byte aligned, that
+ * the walker set uses until it is destroyed (the library never frees it); or
+ * NULL, and the library allocates that much once.  The memory is cleared here
+ * (this call synchronises the device).  The state is undefined until
+ * qmc_eval_batch has run.  QMC_ERR_ARG for a smaller or misaligned ws. */
+qmc_status qmc_walkers_create(qmc_system *sys, int32_t n_walkers, int32_t flags, void *ws, size_t ws_bytes,
+                              qmc_walkers **out);
 qmc_status qmc_walkers_destroy(qmc_walkers *wk);
+
+/* Tolerance of the drift check made by every refresh that qmc_accept_move
+ * triggers with a status array: the inverse about to be replaced, X, is
+ * multiplied by W and status[w] = 3 where max|W X - I| > tol (for walkers the
+ * refresh found non-singular).  tol < 0 turns the check off; the default is
+ * 1e-6.  The last residuals are readable as QMC_STATE_RESIDUAL. */
+qmc_status qmc_walkers_set_drift_tol(qmc_walkers *wk, double tol);
 
 /* Evaluate every walker from scratch at positions r and make that the walkers'
  * state.  (Local energy definition, VMC section; eq:wfAGPs; agp_expansion.)
@@ -238,7 +268,9 @@ qmc_status qmc_propose_move(qmc_system *sys, qmc_walkers *wk, int32_t electron,
  * buffered, W^{-1} and log|det W| are recomputed from W by FP64 elimination.
  * QMC_ERR_STATE if no proposal of this electron is pending.
  *   accept [Wk] device, read (uint8)
- *   status [Wk] device, write, may be NULL (1 when a refresh finds det = 0) */
+ *   status [Wk] device, write, may be NULL: written when this accept triggers
+ *          a refresh (1 when it finds det = 0, 3 when the replaced inverse had
+ *          drifted, see qmc_walkers_set_drift_tol, else 0), untouched otherwise */
 qmc_status qmc_accept_move(qmc_system *sys, qmc_walkers *wk, int32_t electron,
                            const uint8_t *accept, int32_t *status, hipStream_t stream);
 
@@ -290,8 +322,9 @@ typedef struct {
  * parameter gradients over walkers (a vector-Jacobian product); 1 returns
  * them per walker.  r [Wk][N][3] device; gbar_* [Wk] device, NULL means 0.
  * Re-evaluates the walkers at r (their state becomes that of qmc_eval_batch).
- * FP64 systems with N <= 256 electrons and <= 256 nuclei.  The first call on
- * a walker set allocates its workspace.
+ * FP64 systems with N <= 256 electrons and <= 256 nuclei.  Needs a walker set
+ * created with QMC_WALKERS_ADJOINT (QMC_ERR_STATE otherwise); allocates
+ * nothing.
  * Pfaffian systems: every output above (log|Psi| through the cofactor
  * vectors Y_i, e_L through Y, G~^{-1} and the pairing rows), the pairing
  * coefficients in dlambda (A^{ud}), dpf_uu, dpf_dd, dunpaired and dunpaired_dn;
@@ -501,7 +534,9 @@ typedef enum {
   QMC_STATE_W = 3,       /* [Wk][n_up][n_dn] FP64 geminal matrix                 */
   QMC_STATE_AINV = 4,    /* [Wk][n_dn][n_up] FP64 W^{-1} (assembled from the
                             delayed form; uses the walkers' own work arrays)  */
-  QMC_STATE_PHI = 5      /* [Wk][N][L]   FP64 basis values psi_mu(r_i)           */
+  QMC_STATE_PHI = 5,     /* [Wk][N][L]   FP64 basis values psi_mu(r_i)           */
+  QMC_STATE_RESIDUAL = 6 /* [Wk]         max|W X - I| of the last checked refresh
+                            (see qmc_walkers_set_drift_tol)                    */
 } qmc_state_item;
 
 /* Copy one item of the walker state into dst (device memory, the layout given

@@ -21,8 +21,12 @@ QMC_FP64 = 0
 QMC_W_FP32 = 1
 QMC_MIXED = 2
 QMC_MIXED_BF16 = 3
+QMC_W_BF16 = 4
+QMC_W_FP8 = 5
 
-STATE_R, STATE_LOGABS, STATE_SIGN, STATE_W, STATE_AINV, STATE_PHI = range(6)
+WALKERS_ADJOINT = 1
+
+STATE_R, STATE_LOGABS, STATE_SIGN, STATE_W, STATE_AINV, STATE_PHI, STATE_RESIDUAL = range(7)
 
 STATUS_NAMES = {0: "OK", -1: "ERR_ARG", -2: "ERR_SHAPE", -3: "ERR_HIP", -4: "ERR_OOM",
                 -5: "ERR_UNSUPPORTED", -6: "ERR_STATE"}
@@ -35,7 +39,7 @@ FUNCTIONS = (
     "qmc_multi_destroy", "qmc_multi_autotune", "qmc_multi_vmc_steps", "qmc_philox_draws",
     "qmc_lrdmc_hops", "qmc_lrdmc_advance", "qmc_walkers_set_timing_mask", "qmc_swct", "qmc_reweight",
     "qmc_sr_workspace_size", "qmc_sr_step", "qmc_jastrow_basis_logderiv", "qmc_pfaffian_logderiv",
-    "qmc_system_set_jastrow_basis", "qmc_system_set_pfaffian",
+    "qmc_system_set_jastrow_basis", "qmc_system_set_pfaffian", "qmc_workspace_size", "qmc_walkers_set_drift_tol",
 )
 
 TIMER_NAMES = ("basis", "P_build", "W_build", "LU", "Y_build", "rowdot", "assemble", "propose",
@@ -101,7 +105,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         getattr(lib, name).restype = ctypes.c_int
     lib.qmc_system_create.argtypes = [ctypes.POINTER(SystemDesc), ctypes.POINTER(vp)]
     lib.qmc_system_destroy.argtypes = [vp]
-    lib.qmc_walkers_create.argtypes = [vp, i32, ctypes.POINTER(vp)]
+    lib.qmc_walkers_create.argtypes = [vp, i32, i32, vp, ctypes.c_size_t, ctypes.POINTER(vp)]
+    lib.qmc_workspace_size.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_size_t)]
+    lib.qmc_walkers_set_drift_tol.argtypes = [vp, ctypes.c_double]
     lib.qmc_walkers_destroy.argtypes = [vp]
     lib.qmc_eval_batch.argtypes = [vp, vp, dp, dp, dp, dp, dp, dp, vp, vp]
     lib.qmc_propose_move.argtypes = [vp, vp, i32, dp, dp, dp, vp]
@@ -257,15 +263,37 @@ class JAGPSystem:
             pass
 
 
-class Walkers:
-    """Device state of n_walkers walkers of a JAGPSystem."""
+def workspace_size(system: JAGPSystem, n_walkers: int, adjoint: bool = True) -> int:
+    """Bytes of device memory a walker set occupies (qmc_workspace_size)."""
+    n = ctypes.c_size_t()
+    _check(load().qmc_workspace_size(system.h, n_walkers, WALKERS_ADJOINT if adjoint else 0, ctypes.byref(n)))
+    return n.value
 
-    def __init__(self, system: JAGPSystem, n_walkers: int):
+
+class Walkers:
+    """Device state of n_walkers walkers of a JAGPSystem.  adjoint reserves the
+    reverse-pass workspace (needed by forces()); workspace: an optional
+    caller-owned uint8/float64 device tensor of at least workspace_size bytes
+    that the walker set lives in (kept referenced here)."""
+
+    def __init__(self, system: JAGPSystem, n_walkers: int, adjoint: bool = True,
+                 workspace: Optional[torch.Tensor] = None):
         self.sys = system
         self.n = n_walkers
+        self.adjoint = adjoint
+        self.workspace = workspace
         h = ctypes.c_void_p()
-        _check(load().qmc_walkers_create(system.h, n_walkers, ctypes.byref(h)))
+        flags = WALKERS_ADJOINT if adjoint else 0
+        if workspace is None:
+            _check(load().qmc_walkers_create(system.h, n_walkers, flags, None, 0, ctypes.byref(h)))
+        else:
+            nb = workspace.numel() * workspace.element_size()
+            _check(load().qmc_walkers_create(system.h, n_walkers, flags, _ptr(workspace), nb, ctypes.byref(h)))
         self.h = h
+
+    def set_drift_tol(self, tol: float):
+        """Residual tolerance of the refresh drift check (status 3); < 0 turns it off."""
+        _check(load().qmc_walkers_set_drift_tol(self.h, tol))
 
     def close(self):
         if getattr(self, "h", None):
@@ -312,7 +340,7 @@ class Walkers:
         Wk, N, nu, nd, L = self.n, self.sys.n_elec, self.sys.n_up, self.sys.n_dn, self.sys.L
         n = self.sys.npf if self.sys.pairing else nu   # G~ (Pfaffian) or W
         shape = {STATE_R: (Wk, N, 3), STATE_LOGABS: (Wk,), STATE_SIGN: (Wk,), STATE_W: (Wk, n, n),
-                 STATE_AINV: (Wk, n, n), STATE_PHI: (Wk, N, L)}[item]
+                 STATE_AINV: (Wk, n, n), STATE_PHI: (Wk, N, L), STATE_RESIDUAL: (Wk,)}[item]
         dst = torch.empty(shape, dtype=torch.float64, device="cuda")
         _check(load().qmc_walkers_read(self.h, item, _ptr(dst), _stream(stream)))
         return dst

@@ -92,10 +92,10 @@ __device__ __forceinline__ Dl var(double x) { return {x, 1.0}; }
 // Parameters (b, a1, a2, a3) of the two-body channel of a pair.
 __device__ __forceinline__ void j2_params(const SysDev& s, bool same, double p[4]) {
   if (s.j2_form == 1) {
-    p[0] = same ? s.j2[0] : s.j2[1]; p[1] = p[2] = p[3] = 0.0;
+    p[0] = same ? s.j2d[0] : s.j2d[1]; p[1] = p[2] = p[3] = 0.0;
   } else {
     const int o = same ? 0 : 4;
-    p[0] = s.j2[o]; p[1] = s.j2[o + 1]; p[2] = s.j2[o + 2]; p[3] = s.j2[o + 3];
+    p[0] = s.j2d[o]; p[1] = s.j2d[o + 1]; p[2] = s.j2d[o + 2]; p[3] = s.j2d[o + 3];
   }
 }
 

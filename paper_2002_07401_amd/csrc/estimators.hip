@@ -361,3 +361,4 @@ hipError_t launch_sr_step(int M, long P, const double* O, const double* el, cons
 }
 
 }  // namespace qmc
+

@@ -204,7 +204,7 @@ jastrow_assemble_kernel(SysDev s, WalkDev w, double* __restrict__ logabs_o, doub
       Vp += 0.5 / rij;
       if (s.j2_form) {
         double v, v1, v2;
-        j2_radial(s.j2_form, s.j2, up_i == (j < s.nu), rij, v, v1, v2);
+        j2_radial(s.j2_form, s.j2d, up_i == (j < s.nu), rij, v, v1, v2);
         const double q = v1 / rij;
         Jp += 0.5 * v;
         gx += q * dx; gy += q * dy; gz += q * dz;

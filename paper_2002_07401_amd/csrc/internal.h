@@ -35,6 +35,9 @@ constexpr int kLamTileN = 64;     // ... and columns (GEMM N tile)
 
 inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
+// Record msg as this host thread's last error (qmc_last_error) and return st.
+qmc_status set_error(qmc_status st, const char* msg);
+
 // BF16 storage (the bit pattern).  Widening is exact; narrowing rounds to
 // nearest even through FP32 (NaN stays a quiet NaN).
 struct bf16s {
@@ -62,7 +65,9 @@ struct bf16s {
 struct SysDev {
   int n_nuc, L, Lp, nu, nd, N;
   int j1_form, j2_form;
-  double j2[8];
+  double j2[8];      // two-body parameters as created (host copy)
+  const double* j2d; // [8] the same on the device: kernels read these, so that
+                     // qmc_system_set_params can replace them without a host sync
   int precision, refresh_every;
   // reduced-precision storage of Phi and P (the move path): FP32 in QMC_W_FP32
   // and QMC_MIXED, BF16 in QMC_MIXED_BF16
@@ -531,6 +536,9 @@ hipError_t launch_metropolis_accept_prep(const SysDev& s, const WalkDev& w, int 
 hipError_t launch_accept(const SysDev& s, const WalkDev& w, int e, const uint8_t* acc,
                          hipStream_t st);
 hipError_t launch_refresh_finish(const SysDev& s, const WalkDev& w, int32_t* status, hipStream_t st);
+// max |W X - I| per walker (P = W X given) and status 3 where it exceeds tol
+hipError_t launch_refresh_residual(const double* Pm, int n, int Wk, double tol, double* res, int32_t* status,
+                                   hipStream_t st);
 hipError_t launch_materialize_inverse(const SysDev& s, const WalkDev& w, bool down, double* scratch, double* dst,
                                       hipStream_t st);
 // moves that fit the delayed-update buffer between refreshes

@@ -109,13 +109,13 @@ __global__ __launch_bounds__(256) void lrdmc_ratio_kernel(SysDev s, WalkDev w, L
       double v0, v1, v2;
       {
         const double dx = xi - xj, dy = yi - yj, dz = zi - zj;
-        j2_radial(s.j2_form, s.j2, same, sqrt(dx * dx + dy * dy + dz * dz), v0, v1, v2);
+        j2_radial(s.j2_form, s.j2d, same, sqrt(dx * dx + dy * dy + dz * dz), v0, v1, v2);
       }
 #pragma unroll
       for (int k = 0; k < kHops; ++k) {
         const double dx = px[k] - xj, dy = py[k] - yj, dz = pz[k] - zj;
         double u0, u1, u2;
-        j2_radial(s.j2_form, s.j2, same, sqrt(dx * dx + dy * dy + dz * dz), u0, u1, u2);
+        j2_radial(s.j2_form, s.j2d, same, sqrt(dx * dx + dy * dy + dz * dz), u0, u1, u2);
         dj[k] += u0 - v0;
       }
     }

@@ -252,6 +252,47 @@ hipError_t launch_materialize_inverse(const SysDev& s, const WalkDev& w, bool do
   return hipGetLastError();
 }
 
+// Residual of the inverse a refresh replaces: with P = W X (X the inverse
+// before the refresh), res[w] = max_ij |P_ij - delta_ij|; a walker whose
+// refresh found W non-singular (status 0) gets status 3 when the residual
+// exceeds tol (or is not a number).  One workgroup per walker.
+__global__ void __launch_bounds__(256)
+refresh_residual_kernel(const double* __restrict__ Pm, int n, int Wk, double tol, double* __restrict__ res,
+                        int32_t* __restrict__ status) {
+  __shared__ double red[4];
+  const int wk = blockIdx.x, tid = threadIdx.x;
+  const double* p = Pm + (long)wk * n * n;
+  double mx = 0.0;
+  bool bad = false;
+  for (int idx = tid; idx < n * n; idx += blockDim.x) {
+    const double v = fabs(p[idx] - ((idx / n == idx % n) ? 1.0 : 0.0));
+    if (!(v <= mx)) { if (v != v) bad = true; else mx = v; }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    mx = fmax(mx, __shfl_xor(mx, o, 64));
+    bad = bad || __shfl_xor((int)bad, o, 64);
+  }
+  if ((tid & 63) == 0) red[tid >> 6] = bad ? __builtin_nan("") : mx;
+  __syncthreads();
+  if (tid == 0) {
+    double m = 0.0;
+    bool nan = false;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) {
+      if (red[k] != red[k]) nan = true;
+      else m = fmax(m, red[k]);
+    }
+    const double r = nan ? __builtin_nan("") : m;
+    res[wk] = r;
+    if (status && status[wk] == 0 && !(r <= tol)) status[wk] = 3;
+  }
+}
+
+hipError_t launch_refresh_residual(const double* Pm, int n, int Wk, double tol, double* res, int32_t* status,
+                                   hipStream_t st) {
+  hipLaunchKernelGGL(refresh_residual_kernel, dim3(Wk), dim3(256), 0, st, Pm, n, Wk, tol, res, status);
+  return hipGetLastError();
+}
+
 hipError_t launch_refresh_finish(const SysDev& s, const WalkDev& w, int32_t* status, hipStream_t st) {
   (void)s;
   hipLaunchKernelGGL(refresh_finish_kernel, dim3((w.Wk + 255) / 256), dim3(256), 0, st, w, status);

@@ -61,7 +61,7 @@ __device__ void jastrow_one(const SysDev& s, const double* r, int e, double px, 
       const double dx = px - r[3 * j], dy = py - r[3 * j + 1], dz = pz - r[3 * j + 2];
       const double rij = sqrt(dx * dx + dy * dy + dz * dz);
       double v, v1, v2;
-      j2_radial(s.j2_form, s.j2, up_e == (j < s.nu), rij, v, v1, v2);
+      j2_radial(s.j2_form, s.j2d, up_e == (j < s.nu), rij, v, v1, v2);
       val += v;
       if (want_grad) { const double q = v1 / rij; gx += q * dx; gy += q * dy; gz += q * dz; }
     }

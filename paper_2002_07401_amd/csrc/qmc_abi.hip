@@ -142,6 +142,10 @@ struct qmc_walkers {
   int since = 0;        // attempted moves since the last refresh
   int buf_spin = -1;    // spin of the moves in the delayed-update buffer (-1: empty)
   double* rd_scratch = nullptr;   // [Wk][kb][n] state read-out work
+  double* res_x = nullptr;        // [Wk][n][n] refresh check: the inverse being replaced
+  double* res_p = nullptr;        // [Wk][n][n] W times it
+  double* res_v = nullptr;        // [Wk] max |W X - I| of the last checked refresh
+  double drift_tol = 1e-6;        // status 3 when the checked residual exceeds this
   bool evaluated = false;
   bool P_up_valid = false, P_dn_valid = false;
   // lattice-regularised DMC: the cofactor rows Yt hold for the positions of
@@ -175,6 +179,8 @@ struct qmc_walkers {
     HIP_TRY((expr), where);                               \
     HIP_TRY((wk)->tm.end((st)), "timer end");             \
   } while (0)
+
+qmc_status qmc::set_error(qmc_status st, const char* msg) { return fail(st, msg); }
 
 extern "C" int32_t qmc_abi_version(void) { return QMC_ABI_VERSION; }
 
@@ -304,6 +310,7 @@ extern "C" qmc_status qmc_system_create(const qmc_system_desc* desc, qmc_system*
   if (!e) e = up((void**)&d.R, q.R, sizeof(double) * 3 * A);
   if (!e) e = up((void**)&d.Z, q.Z, sizeof(double) * A);
   if (!e) e = up((void**)&d.j1_b, j1b.data(), sizeof(double) * A);
+  if (!e) e = up((void**)&d.j2d, d.j2, sizeof(double) * 8);
   if (!e) e = up((void**)&d.center, q.center, sizeof(int) * Lb);
   if (!e) e = up((void**)&d.kind, kind.data(), sizeof(int) * Lb);
   if (!e) e = up((void**)&d.zeta, q.zeta, sizeof(double) * Lb);
@@ -457,101 +464,214 @@ extern "C" qmc_status qmc_system_destroy(qmc_system* sys) {
   return QMC_OK;
 }
 
-extern "C" qmc_status qmc_walkers_create(qmc_system* sys, int32_t n_walkers, qmc_walkers** out) {
-  if (!sys || !out) return fail(QMC_ERR_ARG, "null argument");
-  if (n_walkers <= 0) return fail(QMC_ERR_ARG, "n_walkers must be positive");
-  *out = nullptr;
-  const SysDev& s = sys->d;
-  auto* wk = new qmc_walkers();
-  wk->sys = sys;
-  WalkDev& d = wk->d;
+// Device layout of one walker set: every array of the evaluation and move
+// state, and (flag QMC_WALKERS_ADJOINT) the reverse-pass workspace, carved out
+// of one buffer at 256-byte boundaries (each array keeps 256 spare bytes past
+// its end, so 16-byte vector loads of a padded row never leave it).  Run once
+// with base == nullptr to size the buffer, then with the buffer to place the
+// arrays.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <typename T>
+  void take(T** p, size_t bytes) {
+    off = (off + 255) / 256 * 256;
+    if (base) *p = reinterpret_cast<T*>(base + off);
+    off += bytes + 256;
+  }
+};
+
+static void walker_layout(const SysDev& s, int n_walkers, bool adjoint, Carver& c, qmc_walkers& wk) {
+  WalkDev& d = wk.d;
   d.Wk = n_walkers;
   const size_t Wk = n_walkers, N = s.N, Lp = s.Lp;
   const size_t nmax = s.nu > s.nd ? s.nu : s.nd;
   const size_t esz = s.bf16() ? sizeof(uint16_t) : (s.f32() ? sizeof(float) : sizeof(double));
-  hipError_t e = hipSuccess;
-  auto al = [&](void** p, size_t bytes) {
-    if (e != hipSuccess) return;
-    e = hipMalloc(p, bytes + 256);
-    if (e == hipSuccess) {
-      wk->allocs.push_back(*p);
-      e = hipMemset(*p, 0, bytes + 256);
-    }
-  };
-  al((void**)&d.r, sizeof(double) * Wk * N * 3);
-  al(&d.phi, esz * Wk * N * Lp);
-  al(&d.P, esz * Wk * N * Lp);
+  c.take(&d.r, sizeof(double) * Wk * N * 3);
+  c.take(&d.phi, esz * Wk * N * Lp);
+  c.take(&d.P, esz * Wk * N * Lp);
   const size_t nsq = s.pairing ? (size_t)s.npf * s.npf : (size_t)s.nu * s.nu;   // G~ or W
-  al((void**)&d.W, sizeof(double) * Wk * nsq);
-  al((void**)&d.A, sizeof(double) * Wk * nsq);
-  al((void**)&d.Yt, sizeof(double) * Wk * N * Lp);
-  al((void**)&d.D, sizeof(double) * Wk * N * 4);
-  al((void**)&d.logdet, sizeof(double) * Wk);
-  al((void**)&d.detsign, sizeof(double) * Wk);
-  al((void**)&d.singular, sizeof(int) * Wk);
-  al((void**)&d.logabs, sizeof(double) * Wk);
-  al((void**)&d.sign, sizeof(double) * Wk);
-  al((void**)&d.J, sizeof(double) * Wk);
-  al((void**)&d.psi_new, sizeof(double) * Wk * Lp);
-  al((void**)&d.w_new, sizeof(double) * Wk * (s.pairing ? std::max(nmax, (size_t)s.npf) : nmax));
-  al((void**)&d.rdet, sizeof(double) * Wk);
-  al((void**)&d.dJ, sizeof(double) * Wk);
-  al((void**)&d.r_new, sizeof(double) * Wk * 3);
-  al((void**)&d.ratio, sizeof(double) * Wk);
-  al((void**)&d.acc, sizeof(uint8_t) * Wk);
+  c.take(&d.W, sizeof(double) * Wk * nsq);
+  c.take(&d.A, sizeof(double) * Wk * nsq);
+  c.take(&d.Yt, sizeof(double) * Wk * N * Lp);
+  c.take(&d.D, sizeof(double) * Wk * N * 4);
+  c.take(&d.logdet, sizeof(double) * Wk);
+  c.take(&d.detsign, sizeof(double) * Wk);
+  c.take(&d.singular, sizeof(int) * Wk);
+  c.take(&d.logabs, sizeof(double) * Wk);
+  c.take(&d.sign, sizeof(double) * Wk);
+  c.take(&d.J, sizeof(double) * Wk);
+  c.take(&d.psi_new, sizeof(double) * Wk * Lp);
+  c.take(&d.w_new, sizeof(double) * Wk * (s.pairing ? std::max(nmax, (size_t)s.npf) : nmax));
+  c.take(&d.rdet, sizeof(double) * Wk);
+  c.take(&d.dJ, sizeof(double) * Wk);
+  c.take(&d.r_new, sizeof(double) * Wk * 3);
+  c.take(&d.ratio, sizeof(double) * Wk);
+  c.take(&d.acc, sizeof(uint8_t) * Wk);
   const size_t S = (nmax + kPropRowsMin - 1) / kPropRowsMin;
-  al((void**)&d.rdet_part, sizeof(double) * Wk * S);
-  al((void**)&d.gdet_part, sizeof(double) * Wk * S * 3);
-  al((void**)&d.gJ_new, sizeof(double) * Wk * 3);
-  al((void**)&d.gpsi_new, sizeof(double) * Wk * 3 * Lp);
-  al((void**)&d.gJ, sizeof(double) * Wk * N * 4);
-  al((void**)&d.drift, sizeof(double) * Wk * N * 3);
+  c.take(&d.rdet_part, sizeof(double) * Wk * S);
+  c.take(&d.gdet_part, sizeof(double) * Wk * S * 3);
+  c.take(&d.gJ_new, sizeof(double) * Wk * 3);
+  c.take(&d.gpsi_new, sizeof(double) * Wk * 3 * Lp);
+  c.take(&d.gJ, sizeof(double) * Wk * N * 4);
+  c.take(&d.drift, sizeof(double) * Wk * N * 3);
   if (s.refined()) {
-    al((void**)&d.phi64, sizeof(double) * Wk * N * s.Lp);
-    al((void**)&d.P64, sizeof(double) * Wk * N * s.Lp);
+    c.take(&d.phi64, sizeof(double) * Wk * N * s.Lp);
+    c.take(&d.P64, sizeof(double) * Wk * N * s.Lp);
   }
   if (s.nu > kLuRowMax) {
     const size_t np = s.np;
-    al((void**)&d.T, sizeof(double) * Wk * np * np);
-    al((void**)&d.Tsave, sizeof(double) * Wk * kGjPanel * np);
-    al((void**)&d.rowk, sizeof(int) * Wk * np);
-    al((void**)&d.prow, sizeof(int) * Wk * np);
-    al((void**)&d.pivv, sizeof(double) * Wk * np);
+    c.take(&d.T, sizeof(double) * Wk * np * np);
+    c.take(&d.Tsave, sizeof(double) * Wk * kGjPanel * np);
+    c.take(&d.rowk, sizeof(int) * Wk * np);
+    c.take(&d.prow, sizeof(int) * Wk * np);
+    c.take(&d.pivv, sizeof(double) * Wk * np);
   }
   d.kb = wb_cap(s);
   {
     const size_t n = s.nu, kb = d.kb;
-    al((void**)&d.wm, sizeof(int) * Wk);
-    al((void**)&d.wv, sizeof(double) * Wk * kb * n);
-    al((void**)&d.wd, sizeof(double) * Wk * kb * n);
-    al((void**)&d.wS, sizeof(double) * Wk * kb * kb);
-    al((void**)&d.cvec, sizeof(double) * Wk * n);
-    al((void**)&d.v0, sizeof(double) * Wk * n);
-    al((void**)&d.tz, sizeof(double) * Wk * 2 * kb);
-    al((void**)&wk->rd_scratch, sizeof(double) * Wk * kb * n);
+    c.take(&d.wm, sizeof(int) * Wk);
+    c.take(&d.wv, sizeof(double) * Wk * kb * n);
+    c.take(&d.wd, sizeof(double) * Wk * kb * n);
+    c.take(&d.wS, sizeof(double) * Wk * kb * kb);
+    c.take(&d.cvec, sizeof(double) * Wk * n);
+    c.take(&d.v0, sizeof(double) * Wk * n);
+    c.take(&d.tz, sizeof(double) * Wk * 2 * kb);
+    c.take(&wk.rd_scratch, sizeof(double) * Wk * kb * n);
+    // refresh residual check: the inverse being replaced and W times it
+    c.take(&wk.res_x, sizeof(double) * Wk * nsq);
+    c.take(&wk.res_p, sizeof(double) * Wk * nsq);
+    c.take(&wk.res_v, sizeof(double) * Wk);
   }
   if (s.LJ > 0) {
     const size_t LJ = s.LJ;
-    al((void**)&d.chi, sizeof(double) * Wk * N * LJ);
-    al((void**)&d.hv, sizeof(double) * Wk * N * LJ);
-    al((void**)&d.G3, sizeof(double) * Wk * 2 * LJ);
-    al((void**)&d.chi_new, sizeof(double) * Wk * LJ);
-    al((void**)&d.j3e, sizeof(double) * Wk * N * 5);
+    c.take(&d.chi, sizeof(double) * Wk * N * LJ);
+    c.take(&d.hv, sizeof(double) * Wk * N * LJ);
+    c.take(&d.G3, sizeof(double) * Wk * 2 * LJ);
+    c.take(&d.chi_new, sizeof(double) * Wk * LJ);
+    c.take(&d.j3e, sizeof(double) * Wk * N * 5);
   }
-  if (s.Lq > 0) al((void**)&d.qbuf, sizeof(double) * Wk * 4 * s.Lq);
+  if (s.Lq > 0) c.take(&d.qbuf, sizeof(double) * Wk * 4 * s.Lq);
   if (s.pairing) {
-    al((void**)&d.Bd, sizeof(double) * Wk * N * Lp);
-    al((void**)&d.pfB, sizeof(double) * Wk * 2 * Lp);
-    al((void**)&d.pfT, sizeof(double) * Wk * N * Lp);
+    c.take(&d.Bd, sizeof(double) * Wk * N * Lp);
+    c.take(&d.pfB, sizeof(double) * Wk * 2 * Lp);
+    c.take(&d.pfT, sizeof(double) * Wk * N * Lp);
   }
-  al((void**)&wk->lr.ratio, sizeof(double) * Wk * N * kHops);
-  al((void**)&wk->lr.ah, sizeof(double) * Wk * N);
-  al((void**)&wk->lr.terms, sizeof(double) * Wk * kLrTerms);
-  al((void**)&wk->lr.ekin, sizeof(double) * Wk);
-  al((void**)&wk->lr.eloc, sizeof(double) * Wk);
+  c.take(&wk.lr.ratio, sizeof(double) * Wk * N * kHops);
+  c.take(&wk.lr.ah, sizeof(double) * Wk * N);
+  c.take(&wk.lr.terms, sizeof(double) * Wk * kLrTerms);
+  c.take(&wk.lr.ekin, sizeof(double) * Wk);
+  c.take(&wk.lr.eloc, sizeof(double) * Wk);
+  if (!adjoint) return;
+  // reverse pass (qmc_forces)
+  const size_t n = s.nu, L = s.L, A = s.n_nuc;
+  const size_t nj = A + (s.j2_form == 1 ? 2 : (s.j2_form == 2 ? 8 : 0));
+  AdjWork& a = wk.aw;
+  a.chunk_walkers = (int)((Wk + 63) / 64);
+  a.chunks = (int)((Wk + a.chunk_walkers - 1) / a.chunk_walkers);
+  const size_t f8 = sizeof(double);
+  c.take(&a.SU, f8 * Wk * 2 * n * Lp);
+  c.take(&a.SD, f8 * Wk * 2 * n * Lp);
+  c.take(&a.VQ, f8 * Wk * n * n);
+  c.take(&a.T1, f8 * Wk * n * n);
+  c.take(&a.M, f8 * Wk * n * n);
+  c.take(&a.GG, f8 * Wk * 2 * n * n);
+  c.take(&a.GGt, f8 * Wk * 2 * n * n);
+  c.take(&a.XZ, f8 * Wk * 2 * n * Lp);
+  c.take(&a.XD, f8 * Wk * n * Lp);
+  c.take(&a.PB, f8 * Wk * N * Lp);
+  const size_t Lb = s.Lq ? (size_t)s.Lq : L;   // basis functions (primitives of a contracted basis)
+  c.take(&a.tmu, f8 * Wk * Lb * 3);
+  c.take(&a.Rbar, f8 * Wk * A * 3);
+  c.take(&a.zbar, f8 * Wk * Lb);
+  if (s.pairing) {
+    const size_t np = s.npf;
+    c.take(&a.pfT, f8 * Wk * np * np);
+    c.take(&a.pfZ1, f8 * Wk * np * np);
+    c.take(&a.pfZ, f8 * Wk * np * np);
+    c.take(&a.pfBb, f8 * Wk * N * 2 * Lp);
+    c.take(&a.pfY, f8 * Wk * N * Lp);
+    const size_t per = 3 * L * L + 2 * L * (size_t)s.pk;
+    c.take(&a.pfD, f8 * Wk * per);
+    c.take(&a.pfS, f8 * per);
+  }
+  if (s.Lq) {
+    const size_t lqp = (s.Lq + 31) / 32 * 32;
+    c.take(&a.dcw, f8 * Wk * (size_t)s.nnz_con);
+    c.take(&a.PBq, f8 * Wk * N * lqp);
+    c.take(&a.Ytq, f8 * Wk * N * lqp);
+  }
+  if (s.LJ) {
+    const size_t LJ = s.LJ, LJp = (LJ + 31) / 32 * 32;
+    a.LJp = (int)LJp;
+    c.take(&a.ju, f8 * Wk * N * LJp);
+    c.take(&a.jgv, f8 * Wk * N * LJp);
+    c.take(&a.jac, f8 * Wk * N * LJp);
+    c.take(&a.jpb, f8 * Wk * N * LJp);
+    c.take(&a.jhu, f8 * Wk * N * LJp);
+    c.take(&a.jX, f8 * Wk * 4 * LJ);
+    c.take(&a.jH, f8 * Wk * 2 * LJ);
+    c.take(&a.jdm, f8 * Wk * 2 * LJ);
+    c.take(&a.jC, f8 * Wk * 2 * LJ * LJ);
+    c.take(&a.jdM, f8 * Wk * 3 * LJ * LJ);
+    c.take(&a.jzbar, f8 * Wk * LJ);
+    c.take(&a.jtmu, f8 * Wk * LJ * 3);
+    c.take(&a.drift4, f8 * Wk * N * 4);
+  }
+  c.take(&a.jbar, f8 * Wk * nj);
+  c.take(&a.dr, f8 * Wk * N * 3);
+  c.take(&a.lam_part, f8 * (size_t)a.chunks * L * L);
+}
+
+static qmc_status check_walker_args(qmc_system* sys, int32_t n_walkers, int32_t flags) {
+  if (!sys) return fail(QMC_ERR_ARG, "null system");
+  if (n_walkers <= 0) return fail(QMC_ERR_ARG, "n_walkers must be positive");
+  if (flags & ~QMC_WALKERS_ADJOINT) return fail(QMC_ERR_ARG, "unknown walker flags");
+  return QMC_OK;
+}
+
+extern "C" qmc_status qmc_workspace_size(const qmc_system* sys, int32_t n_walkers, int32_t flags, size_t* bytes) {
+  if (!bytes) return fail(QMC_ERR_ARG, "null bytes");
+  *bytes = 0;
+  qmc_status c = check_walker_args(const_cast<qmc_system*>(sys), n_walkers, flags);
+  if (c) return c;
+  qmc_walkers probe;
+  Carver cv{nullptr};
+  walker_layout(sys->d, n_walkers, (flags & QMC_WALKERS_ADJOINT) != 0, cv, probe);
+  *bytes = cv.off;
+  return QMC_OK;
+}
+
+extern "C" qmc_status qmc_walkers_create(qmc_system* sys, int32_t n_walkers, int32_t flags, void* ws, size_t ws_bytes,
+                                         qmc_walkers** out) {
+  if (!out) return fail(QMC_ERR_ARG, "null argument");
+  *out = nullptr;
+  qmc_status c = check_walker_args(sys, n_walkers, flags);
+  if (c) return c;
+  const bool adjoint = (flags & QMC_WALKERS_ADJOINT) != 0;
+  size_t need = 0;
+  c = qmc_workspace_size(sys, n_walkers, flags, &need);
+  if (c) return c;
+  if (ws && ((uintptr_t)ws % 256 != 0)) return fail(QMC_ERR_ARG, "workspace must be 256-byte aligned");
+  if (ws && ws_bytes < need) return fail(QMC_ERR_ARG, "workspace smaller than qmc_workspace_size");
+  auto* wk = new qmc_walkers();
+  wk->sys = sys;
+  void* base = ws;
+  if (!base) {
+    hipError_t e = hipMalloc(&base, need);
+    if (e != hipSuccess) {
+      delete wk;
+      return e == hipErrorOutOfMemory ? fail(QMC_ERR_OOM, "device allocation failed") : hip_fail(e, "walkers_create");
+    }
+    wk->allocs.push_back(base);
+  }
+  Carver cv{(char*)base};
+  walker_layout(sys->d, n_walkers, adjoint, cv, *wk);
+  wk->aw_ready = adjoint;
+  hipError_t e = hipMemset(base, 0, need);
   if (e != hipSuccess) {
     delete wk;
-    return e == hipErrorOutOfMemory ? fail(QMC_ERR_OOM, "device allocation failed") : hip_fail(e, "walkers_create");
+    return hip_fail(e, "walkers_create");
   }
   *out = wk;
   return QMC_OK;
@@ -697,9 +817,41 @@ static bool sched_after(const SysDev& s, Sched& q) {           // true: refresh 
   return true;
 }
 
+// With a status array the refresh also measures how far the inverse it
+// replaces had drifted: X = the maintained inverse (delayed form materialised,
+// or the Pfaffian's G~^{-1}), res = max |W X - I|, status 3 above drift_tol.
+static hipError_t residual_before(const SysDev& s, qmc_walkers* wk, hipStream_t stream) {
+  const int n = s.pairing ? s.npf : s.nu;
+  const long nn = (long)n * n;
+  if (s.pairing) {
+    TIMED_E(wk, QMC_T_OTHER, stream,
+            hipMemcpyAsync(wk->res_x, wk->d.A, sizeof(double) * nn * wk->d.Wk, hipMemcpyDeviceToDevice, stream));
+  } else {
+    TIMED_E(wk, QMC_T_OTHER, stream,
+            launch_materialize_inverse(s, wk->d, wk->buf_spin == 1, wk->rd_scratch, wk->res_x, stream));
+  }
+  GemmArgs g = gemm_args(n, n, n);
+  g.A = wk->d.W; g.lda = n; g.a_bs = nn;
+  g.B = wk->res_x; g.ldb = n; g.b_bs = nn;
+  g.C = wk->res_p; g.ldc = n; g.c_bs = nn;
+  g.batch = wk->d.Wk;
+  TIMED_E(wk, QMC_T_OTHER, stream, gemm_f64(g, false, false, false, stream));
+  return hipSuccess;
+}
+
 static hipError_t refresh(const SysDev& s, qmc_walkers* wk, int32_t* status, hipStream_t stream) {
+  const bool check = status && wk->drift_tol >= 0.0;
+  if (check) {
+    hipError_t e = residual_before(s, wk, stream);
+    if (e != hipSuccess) return e;
+  }
   TIMED_E(wk, QMC_T_LU, stream, launch_lu_inverse(s, wk->d, stream));
   TIMED_E(wk, QMC_T_OTHER, stream, launch_refresh_finish(s, wk->d, status, stream));
+  if (check) {
+    const int n = s.pairing ? s.npf : s.nu;
+    TIMED_E(wk, QMC_T_OTHER, stream,
+            launch_refresh_residual(wk->res_p, n, wk->d.Wk, wk->drift_tol, wk->res_v, status, stream));
+  }
   return hipSuccess;
 }
 
@@ -734,8 +886,14 @@ static qmc_status pf_after_accept(qmc_walkers* wk, int32_t* status, hipStream_t 
   wk->attempts += 1;
   if (++wk->since < s.refresh_every) return QMC_OK;
   wk->since = 0;
+  const bool check = status && wk->drift_tol >= 0.0;
+  if (check) HIP_TRY(residual_before(s, wk, stream), "refresh residual");
   TIMED(wk, QMC_T_LU, stream, launch_pf_factor(s, wk->d, stream), "Pfaffian refresh");
   TIMED(wk, QMC_T_OTHER, stream, launch_refresh_finish(s, wk->d, status, stream), "refresh finish");
+  if (check)
+    TIMED(wk, QMC_T_OTHER, stream,
+          launch_refresh_residual(wk->res_p, s.npf, wk->d.Wk, wk->drift_tol, wk->res_v, status, stream),
+          "refresh residual");
   return QMC_OK;
 }
 
@@ -858,9 +1016,17 @@ extern "C" qmc_status qmc_walkers_read(qmc_walkers* wk, int32_t item, double* ds
     case QMC_STATE_PHI:
       HIP_TRY(launch_export_phi(s, d, dst, stream), "export phi");
       return QMC_OK;
+    case QMC_STATE_RESIDUAL: src = wk->res_v; bytes = sizeof(double) * Wk; break;
     default: return fail(QMC_ERR_ARG, "unknown state item");
   }
   HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, stream), "read state");
+  return QMC_OK;
+}
+
+extern "C" qmc_status qmc_walkers_set_drift_tol(qmc_walkers* wk, double tol) {
+  if (!wk) return fail(QMC_ERR_ARG, "null walkers");
+  if (tol != tol) return fail(QMC_ERR_ARG, "tolerance is not a number");
+  wk->drift_tol = tol;
   return QMC_OK;
 }
 
@@ -884,79 +1050,6 @@ extern "C" qmc_status qmc_walkers_timing(qmc_walkers* wk, double* ms, int64_t* l
   return QMC_OK;
 }
 
-// Allocate the reverse-pass workspace of a walker set (first qmc_forces call).
-static hipError_t alloc_adjoint(qmc_walkers* wk) {
-  if (wk->aw_ready) return hipSuccess;
-  const SysDev& s = wk->sys->d;
-  const size_t Wk = wk->d.Wk, n = s.nu, Lp = s.Lp, L = s.L, N = s.N, A = s.n_nuc;
-  const size_t nj = A + (s.j2_form == 1 ? 2 : (s.j2_form == 2 ? 8 : 0));
-  AdjWork& a = wk->aw;
-  a.chunk_walkers = (int)((Wk + 63) / 64);
-  a.chunks = (int)((Wk + a.chunk_walkers - 1) / a.chunk_walkers);
-  hipError_t e = hipSuccess;
-  auto al = [&](double** p, size_t count) {
-    if (e != hipSuccess) return;
-    e = hipMalloc((void**)p, count * sizeof(double) + 256);
-    if (e == hipSuccess) {
-      wk->allocs.push_back(*p);
-      e = hipMemset(*p, 0, count * sizeof(double) + 256);
-    }
-  };
-  al(&a.SU, Wk * 2 * n * Lp);
-  al(&a.SD, Wk * 2 * n * Lp);
-  al(&a.VQ, Wk * n * n);
-  al(&a.T1, Wk * n * n);
-  al(&a.M, Wk * n * n);
-  al(&a.GG, Wk * 2 * n * n);
-  al(&a.GGt, Wk * 2 * n * n);
-  al(&a.XZ, Wk * 2 * n * Lp);
-  al(&a.XD, Wk * n * Lp);
-  al(&a.PB, Wk * N * Lp);
-  const size_t Lb = s.Lq ? (size_t)s.Lq : L;   // basis functions (primitives of a contracted basis)
-  al(&a.tmu, Wk * Lb * 3);
-  al(&a.Rbar, Wk * A * 3);
-  al(&a.zbar, Wk * Lb);
-  if (s.pairing) {
-    const size_t np = s.npf;
-    al(&a.pfT, Wk * np * np);
-    al(&a.pfZ1, Wk * np * np);
-    al(&a.pfZ, Wk * np * np);
-    al(&a.pfBb, Wk * N * 2 * Lp);
-    al(&a.pfY, Wk * N * Lp);
-    const size_t per = 3 * L * L + 2 * L * (size_t)s.pk;
-    al(&a.pfD, Wk * per);
-    al(&a.pfS, per);
-  }
-  if (s.Lq) {
-    const size_t lqp = (s.Lq + 31) / 32 * 32;
-    al(&a.dcw, Wk * (size_t)s.nnz_con);
-    al(&a.PBq, Wk * N * lqp);
-    al(&a.Ytq, Wk * N * lqp);
-  }
-  if (s.LJ) {
-    const size_t LJ = s.LJ, LJp = (LJ + 31) / 32 * 32;
-    a.LJp = (int)LJp;
-    al(&a.ju, Wk * N * LJp);
-    al(&a.jgv, Wk * N * LJp);
-    al(&a.jac, Wk * N * LJp);
-    al(&a.jpb, Wk * N * LJp);
-    al(&a.jhu, Wk * N * LJp);
-    al(&a.jX, Wk * 4 * LJ);
-    al(&a.jH, Wk * 2 * LJ);
-    al(&a.jdm, Wk * 2 * LJ);
-    al(&a.jC, Wk * 2 * LJ * LJ);
-    al(&a.jdM, Wk * 3 * LJ * LJ);
-    al(&a.jzbar, Wk * LJ);
-    al(&a.jtmu, Wk * LJ * 3);
-    al(&a.drift4, Wk * N * 4);
-  }
-  al(&a.jbar, Wk * nj);
-  al(&a.dr, Wk * N * 3);
-  al(&a.lam_part, (size_t)a.chunks * L * L);
-  if (e == hipSuccess) wk->aw_ready = true;
-  return e;
-}
-
 extern "C" qmc_status qmc_forces(qmc_system* sys, qmc_walkers* wk, const double* r, int32_t per_walker,
                                  const double* gbar_logpsi, const double* gbar_eloc, const qmc_grads* out,
                                  hipStream_t stream) {
@@ -969,9 +1062,8 @@ extern "C" qmc_status qmc_forces(qmc_system* sys, qmc_walkers* wk, const double*
     return fail(QMC_ERR_ARG, "dpf_uu, dpf_dd and dunpaired_dn are outputs of Pfaffian systems");
   if (s.N > 2 * kLuMaxN || s.n_nuc > kMaxNucBack)
     return fail(QMC_ERR_UNSUPPORTED, "forces need N <= 256 electrons and <= 256 nuclei");
-  hipError_t e = alloc_adjoint(wk);
-  if (e != hipSuccess)
-    return e == hipErrorOutOfMemory ? fail(QMC_ERR_OOM, "adjoint workspace allocation failed") : hip_fail(e, "forces workspace");
+  if (!wk->aw_ready)
+    return fail(QMC_ERR_STATE, "walkers created without QMC_WALKERS_ADJOINT (no reverse-pass workspace)");
   c = qmc_eval_batch(sys, wk, r, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, stream);
   if (c) return c;
   HIP_TRY(launch_forces(s, wk->d, wk->aw, gbar_logpsi, gbar_eloc, per_walker, out->dR, out->dzeta,
@@ -1130,12 +1222,9 @@ extern "C" qmc_status qmc_system_set_params(qmc_system* sys, const double* R, co
   if (jas) {
     HIP_TRY(hipMemcpyAsync(d.j1_b, jas, sizeof(double) * d.n_nuc, hipMemcpyDeviceToDevice, stream), "set j1");
     const int n2 = d.j2_form == 1 ? 2 : (d.j2_form == 2 ? 8 : 0);
-    if (n2) {
-      double h[8];
-      HIP_TRY(hipMemcpyAsync(h, jas + d.n_nuc, sizeof(double) * n2, hipMemcpyDeviceToHost, stream), "get j2");
-      HIP_TRY(hipStreamSynchronize(stream), "sync j2");
-      for (int k = 0; k < n2; ++k) d.j2[k] = h[k];
-    }
+    if (n2)
+      HIP_TRY(hipMemcpyAsync(const_cast<double*>(d.j2d), jas + d.n_nuc, sizeof(double) * n2, hipMemcpyDeviceToDevice,
+                             stream), "set j2");
   }
   sys->generation += 1;
   return QMC_OK;

@@ -18,7 +18,7 @@ from workloads import configs as C
 
 pytestmark = pytest.mark.gpu
 
-SIZES = (16, 48, 96, 256)
+SIZES = (16, 32, 48, 64, 96, 128, 192, 256)   # every member size of the 8-system workload
 
 
 def _members(P, Wk, precision=None):
@@ -71,7 +71,7 @@ def test_multi_chain_matches_oracle_for_small_members():
     m.vmc_steps(n_steps, [torch.tensor(d, device="cuda") for d, _ in draws],
                 [torch.tensor(u, device="cuda") for _, u in draws])
     torch.cuda.synchronize()
-    for k, n in enumerate(SIZES[:2]):
+    for k, n in enumerate(SIZES[:4]):
         w, _, wk = grp[k]
         sy = O.from_workload_system(w.system)
         rf, _, _ = O.run_chain(sy, torch.tensor(w.r0), torch.tensor(draws[k][0]), torch.tensor(draws[k][1]))
@@ -82,7 +82,7 @@ def test_multi_chain_matches_oracle_for_small_members():
 
 def test_multi_graph_replay_equals_direct_launches():
     P = need_gpu()
-    Wk, n_steps = 8, 96          # 96 = lcm of (N, refresh period) over the members
+    Wk, n_steps = 8, 768         # 768 = lcm of (N, refresh period) over the members: the second call replays
     ga = _members(P, Wk)
     gb = _members(P, Wk)
     ma = P.MultiSystem([wk for _, _, wk in ga])
