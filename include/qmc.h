@@ -415,6 +415,19 @@ qmc_status qmc_sr_step(int32_t n_samples, int64_t n_params, const double *O, con
                        const double *weights, double eps, int32_t max_iter, double tol, double *delta,
                        double *force, double *residual, void *work, size_t work_bytes, hipStream_t stream);
 
+/* qmc_sr_step for callers that cannot allocate device memory and cannot hand
+ * in a workspace (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation): the same computation and result, with the
+ * workspace taken from a fixed 16 MiB array the library keeps on each GPU
+ * until the process ends.  Sizes whose qmc_sr_workspace_size exceeds
+ * 16777216 bytes are refused with QMC_ERR_SHAPE (e.g. n_params <= 29900 at
+ * 4096 samples, <= 262000 at 128).  Allocates nothing.  Every call on one GPU
+ * shares that array: calls that overlap on one GPU (on concurrent streams or
+ * host threads) race and must be serialised by the caller. */
+qmc_status qmc_sr_step_static(int32_t n_samples, int64_t n_params, const double *O, const double *e_loc,
+                              const double *weights, double eps, int32_t max_iter, double tol, double *delta,
+                              double *force, double *residual, hipStream_t stream);
+
 /* Several systems moved together (uneven electron counts).  Every phase of a
  * Metropolis step (proposal set-up, streaming rows, accept/update, periodic LU
  * refresh) is one persistent launch over (system, walker[, row chunk]) work

@@ -40,6 +40,7 @@ FUNCTIONS = (
     "qmc_lrdmc_hops", "qmc_lrdmc_advance", "qmc_walkers_set_timing_mask", "qmc_swct", "qmc_reweight",
     "qmc_sr_workspace_size", "qmc_sr_step", "qmc_jastrow_basis_logderiv", "qmc_pfaffian_logderiv",
     "qmc_system_set_jastrow_basis", "qmc_system_set_pfaffian", "qmc_workspace_size", "qmc_walkers_set_drift_tol",
+    "qmc_sr_step_static",
 )
 
 TIMER_NAMES = ("basis", "P_build", "W_build", "LU", "Y_build", "rowdot", "assemble", "propose",
@@ -137,6 +138,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.qmc_sr_workspace_size.argtypes = [i32, ctypes.c_int64]
     lib.qmc_sr_step.argtypes = [i32, ctypes.c_int64, dp, dp, dp, ctypes.c_double, i32, ctypes.c_double, dp, dp,
                                 dp, vp, ctypes.c_size_t, vp]
+    lib.qmc_sr_step_static.argtypes = [i32, ctypes.c_int64, dp, dp, dp, ctypes.c_double, i32, ctypes.c_double, dp,
+                                       dp, dp, vp]
     _lib = lib
     return lib
 

@@ -15,6 +15,8 @@
 //   partial sums of r . z and r . r, the p update.  Every reduction is a fixed-order sum
 //   of per-block partials; the iteration scalars are double-buffered by parity
 //   so no block reads a value another block of the same launch writes.
+#include <mutex>
+
 #include "internal.h"
 
 namespace qmc {
@@ -362,3 +364,48 @@ hipError_t launch_sr_step(int M, long P, const double* O, const double* el, cons
 
 }  // namespace qmc
 
+// ---------------------------------------------------------------------------
+// SR step without allocation: the workspace is a fixed device array of the
+// library (one copy per GPU, alive until the process ends).  Host code never
+// passes the array's name to a kernel or a copy: on the host that name is a
+// stand-in, not a device address.  Its address on each device is looked up
+// once, with that device current, and kept.
+// ---------------------------------------------------------------------------
+constexpr size_t kSrStaticDoubles = (size_t)2 << 20;   // 16 MiB of FP64
+static __device__ __align__(256) double scratch[kSrStaticDoubles];
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+extern "C" qmc_status qmc_sr_step_static(int32_t n_samples, int64_t n_params, const double* O, const double* e_loc,
+                                         const double* weights, double eps, int32_t max_iter, double tol,
+                                         double* delta, double* force, double* residual, hipStream_t stream) {
+  using namespace qmc;
+  if (!O || !e_loc || !delta) return set_error(QMC_ERR_ARG, "null argument");
+  if (n_samples <= 0 || n_params <= 0 || max_iter < 0) return set_error(QMC_ERR_ARG, "bad sizes");
+  if (!(eps >= 0.0) || !(tol >= 0.0)) return set_error(QMC_ERR_ARG, "eps and tol must be >= 0");
+  if (sr_workspace_doubles(n_samples, (long)n_params) > kSrStaticDoubles)
+    return set_error(QMC_ERR_SHAPE, "SR problem needs more than the 16 MiB static workspace "
+                                    "(qmc_sr_workspace_size > 16777216 bytes): use qmc_sr_step");
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return set_error(QMC_ERR_HIP, hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return set_error(QMC_ERR_UNSUPPORTED, "device ordinal beyond 63");
+  double* ptr = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+      void* p = nullptr;
+      e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !p) return set_error(QMC_ERR_HIP, "hipGetSymbolAddress of the SR scratch failed");
+      g_scratch_ptr[dev] = (double*)p;
+    }
+    ptr = g_scratch_ptr[dev];
+  }
+  e = launch_sr_step(n_samples, (long)n_params, O, e_loc, weights, eps, max_iter, tol, delta, force, residual, ptr,
+                     stream);
+  if (e != hipSuccess) return set_error(QMC_ERR_HIP, hipGetErrorString(e));
+  return QMC_OK;
+}
