@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqmc_jagp.so")
 SOURCES = ["qmc_abi.hip", "gemm.hip", "linalg.hip", "eval.hip", "move.hip", "adjoint.hip", "multi.hip",
-           "lrdmc.hip", "jas3.hip", "estimators.hip", "pfaff.hip"]
+           "lrdmc.hip", "jas3.hip", "estimators.hip", "pfaff.hip", "ozaki.hip"]
 ARCH = os.environ.get("QMC_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -18,18 +18,37 @@ __global__ void __launch_bounds__(256) basis_values_kernel(SysDev s, const doubl
     out[mu] = (T)(mu < s.L ? basis_value(s, mu, px, py, pz) : 0.0);
 }
 
-// FP64 values plus their FP32 or BF16 copy (the rows the moves stream).
+// FP64 values plus their FP32 or BF16 copy (the rows the moves stream).  With
+// ephi, also the exponent floor(log2 max_mu |psi_mu(r_i)|) of the row (0 for a
+// row of zeros), the scale of its int8 digits: up electron i of walker w at
+// ephi[w * n_up + i], down electron j at ephi[Wk * n_up + w * n_dn + j].
 template <typename T2>
 __global__ void __launch_bounds__(256) basis_values_dual_kernel(SysDev s, const double* __restrict__ r,
-                                                                double* __restrict__ phi, T2* __restrict__ lo) {
+                                                                double* __restrict__ phi, T2* __restrict__ lo,
+                                                                int* __restrict__ ephi, int Wk) {
+  __shared__ double red[4];
   const long row = blockIdx.x;   // w * N + i
   const double px = r[3 * row], py = r[3 * row + 1], pz = r[3 * row + 2];
   double* out = phi + row * s.Lp;
   T2* out2 = lo + row * s.Lp;
+  double mx = 0.0;
   for (int mu = threadIdx.x; mu < s.Lp; mu += blockDim.x) {
     const double v = mu < s.L ? basis_value(s, mu, px, py, pz) : 0.0;
     out[mu] = v;
     out2[mu] = (T2)v;
+    mx = fmax(mx, fabs(v));
+  }
+  if (!ephi) return;   // uniform
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = 0.0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) m = fmax(m, red[k]);
+    const long w = row / s.N, i = row % s.N;
+    const long at = i < s.nu ? w * s.nu + i : (long)Wk * s.nu + w * s.nd + (i - s.nu);
+    ephi[at] = m > 0.0 ? ilogb(m) : 0;
   }
 }
 
@@ -54,16 +73,20 @@ __global__ void __launch_bounds__(256) contracted_values_kernel(SysDev s, const 
   }
 }
 
-hipError_t launch_basis_values(const SysDev& s, const WalkDev& w, hipStream_t st, void* lo, bool lo_bf16) {
+hipError_t launch_basis_values(const SysDev& s, const WalkDev& w, hipStream_t st, void* lo, bool lo_bf16,
+                               int* ephi) {
   const dim3 grid((unsigned)((long)w.Wk * s.N));
   const bool dual = lo && !s.bf16() && !s.f32();   // FP64 values with a low-precision copy
   if (dual && s.Lq == 0) {
     if (lo_bf16)
-      hipLaunchKernelGGL(basis_values_dual_kernel<bf16s>, grid, dim3(256), 0, st, s, w.r, (double*)w.phi, (bf16s*)lo);
+      hipLaunchKernelGGL(basis_values_dual_kernel<bf16s>, grid, dim3(256), 0, st, s, w.r, (double*)w.phi, (bf16s*)lo,
+                         ephi, w.Wk);
     else
-      hipLaunchKernelGGL(basis_values_dual_kernel<float>, grid, dim3(256), 0, st, s, w.r, (double*)w.phi, (float*)lo);
+      hipLaunchKernelGGL(basis_values_dual_kernel<float>, grid, dim3(256), 0, st, s, w.r, (double*)w.phi, (float*)lo,
+                         ephi, w.Wk);
     return hipGetLastError();
   }
+  if (ephi) return hipErrorInvalidValue;   // exponents come with the FP64 + copy form only
   if (s.Lq > 0) {
     if (s.Lq > kMaxLq) return hipErrorNotSupported;
     if (dual && lo_bf16)

@@ -32,6 +32,8 @@ constexpr int kWbMax = 64;        // capacity of the delayed-update buffer (move
 constexpr int kGjPanel = 64;      // panel width of the blocked Gauss-Jordan
 constexpr int kLamTileK = 16;     // Lambda tile mask granularity: rows (GEMM K step) ...
 constexpr int kLamTileN = 64;     // ... and columns (GEMM N tile)
+constexpr int kOzMaxSlices = 8;   // int8 digits per FP64 row in the error-free products
+constexpr int kOzSlices = 7;      // digits used by the refined evaluation (error 7e-14 of max|x| max|y| K)
 
 inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
@@ -139,6 +141,12 @@ struct SysDev {
   double* Upf;       // [2][pk][Lp] unpaired orbitals of up, then down electrons
   double* Kcat_u;    // [Lp][2Lp] [K^{uu} | K^{du}]: the B rows of a moved up electron
   double* Kcat_d;    // [Lp][2Lp] [K^{ud} | K^{dd}]: the B rows of a moved down electron
+  // int8 digits of Lambda for the error-free products (refined modes): tiles
+  // [2][oz_s][Lp * Lp] (rows of Lambda^T, then rows of Lambda) and one exponent
+  // per row [2][Lp]
+  int oz_s;
+  int8_t* oz_lam;
+  int* oz_elam;
 };
 
 // Device state of a batch of walkers.
@@ -205,6 +213,11 @@ struct WalkDev {
   double* Bd;         // [Wk][N][Lp] B^d rows (Pfaffian pairing; B^u rows are in P)
   double* pfB;        // [Wk][2][Lp] B^u, B^d rows of the proposal's r' (Pfaffian pairing)
   double* pfT;        // [Wk][N][Lp] work rows of the Pfaffian log-derivatives
+  // int8 digits of the FP64 basis rows (refined modes): tiles of the up rows
+  // [oz_s][Wk * n_up], then of the down rows [oz_s][Wk * n_dn] (rows padded to 32,
+  // Lp digits each), and one exponent per row [Wk * n_up + Wk * n_dn]
+  int8_t* oz_phi;
+  int* oz_ephi;
 };
 
 // Workspace of the reverse pass (allocated on the first qmc_forces call).
@@ -475,11 +488,19 @@ __device__ __forceinline__ float wave_sum(float v) {
 // launchers (all asynchronous on `st`)
 // ---------------------------------------------------------------------------
 hipError_t launch_basis_values(const SysDev& s, const WalkDev& w, hipStream_t st, void* lo = nullptr,
-                               bool lo_bf16 = false);
+                               bool lo_bf16 = false, int* ephi = nullptr);
 hipError_t launch_downcast(const double* src, void* dst, bool to_bf16, long n, hipStream_t st);
 hipError_t launch_P_build(const SysDev& s, const WalkDev& w, int halves, hipStream_t st,
                           void* lo = nullptr, bool lo_bf16 = false);
 hipError_t launch_W_build(const SysDev& s, const WalkDev& w, hipStream_t st);
+// int8 digit tiles of FP64 rows and the error-free products built from them
+long oz_plane_bytes(long rows, int Kp);
+long oz_phi_bytes(const SysDev& s, long Wk);
+hipError_t launch_slice_tiles(const double* X, long rows, int K, int Kp, int grp, long gs, long ld, int S,
+                              int8_t* out, long plane, int* expo, hipStream_t st, bool have_expo = false);
+hipError_t launch_oz_lambda(const SysDev& s, hipStream_t st);
+hipError_t launch_P_build_oz(const SysDev& s, const WalkDev& w, int halves, const double* phi64, double* P64,
+                             void* lo, bool lo_bf16, hipStream_t st, bool have_expo = false);
 hipError_t launch_Y_build(const SysDev& s, const WalkDev& w, hipStream_t st);
 hipError_t launch_lu_inverse(const SysDev& s, const WalkDev& w, hipStream_t st);
 hipError_t launch_lam_mask(const SysDev& s, hipStream_t st);

@@ -449,6 +449,17 @@ extern "C" qmc_status qmc_system_create(const qmc_system_desc* desc, qmc_system*
     if (!e) e = launch_lam_mask(d, nullptr);
     if (!e) e = hipStreamSynchronize(nullptr);
   }
+  if (!e && d.refined() && !pf) {
+    // int8 digits of Lambda for the error-free P products of the evaluation
+    d.oz_s = kOzSlices;
+    const size_t plane = (size_t)oz_plane_bytes(Lp, Lp);
+    std::vector<int8_t> z8(2 * (size_t)d.oz_s * plane, 0);
+    std::vector<int> z4(2 * (size_t)Lp, 0);
+    e = up((void**)&d.oz_lam, z8.data(), z8.size());
+    if (!e) e = up((void**)&d.oz_elam, z4.data(), sizeof(int) * z4.size());
+    if (!e) e = launch_oz_lambda(d, nullptr);
+    if (!e) e = hipStreamSynchronize(nullptr);
+  }
   if (e != hipSuccess) {
     delete s;
     return e == hipErrorOutOfMemory ? fail(QMC_ERR_OOM, "device allocation failed") : hip_fail(e, "system_create");
@@ -518,6 +529,10 @@ static void walker_layout(const SysDev& s, int n_walkers, bool adjoint, Carver& 
   if (s.refined()) {
     c.take(&d.phi64, sizeof(double) * Wk * N * s.Lp);
     c.take(&d.P64, sizeof(double) * Wk * N * s.Lp);
+    if (s.oz_s > 0) {
+      c.take(&d.oz_phi, (size_t)oz_phi_bytes(s, (long)Wk));
+      c.take(&d.oz_ephi, sizeof(int) * Wk * N);
+    }
   }
   if (s.nu > kLuRowMax) {
     const size_t np = s.np;
@@ -710,15 +725,25 @@ extern "C" qmc_status qmc_eval_batch(qmc_system* sys, qmc_walkers* wk, const dou
     de.P = d.P64;
   }
   // the FP32 / BF16 copies of Phi and P are written by the producing kernels
-  TIMED(wk, QMC_T_BASIS, stream, launch_basis_values(se, de, stream, refine ? d.phi : nullptr, s.bf16()), "basis");
+  // the int8 digits of the refined products take their row scales from here
+  int* ephi = (refine && s.oz_s > 0 && s.Lq == 0) ? d.oz_ephi : nullptr;
+  TIMED(wk, QMC_T_BASIS, stream, launch_basis_values(se, de, stream, refine ? d.phi : nullptr, s.bf16(), ephi),
+        "basis");
   if (s.pairing) {
     TIMED(wk, QMC_T_P_BUILD, stream, launch_pf_B_build(s, d, stream), "Pfaffian B rows");
     TIMED(wk, QMC_T_W_BUILD, stream, launch_pf_G_build(s, d, stream), "Pfaffian G");
     TIMED(wk, QMC_T_LU, stream, launch_pf_factor(s, d, stream), "Pfaffian and inverse");
     TIMED(wk, QMC_T_Y_BUILD, stream, launch_pf_Y_build(s, d, stream), "Pfaffian Y build");
   } else {
-  TIMED(wk, QMC_T_P_BUILD, stream, launch_P_build(se, de, 3, stream, refine ? d.P : nullptr, s.bf16()),
-        "P build");
+  if (refine && s.oz_s > 0) {
+    // reduced-precision digits on the int8 matrix cores, refined to the FP64
+    // product (see ozaki.hip); the moves' FP32 / BF16 rows are written beside
+    TIMED(wk, QMC_T_P_BUILD, stream,
+          launch_P_build_oz(s, d, 3, d.phi64, d.P64, d.P, s.bf16(), stream, ephi != nullptr), "P build");
+  } else {
+    TIMED(wk, QMC_T_P_BUILD, stream, launch_P_build(se, de, 3, stream, refine ? d.P : nullptr, s.bf16()),
+          "P build");
+  }
   TIMED(wk, QMC_T_W_BUILD, stream, launch_W_build(se, de, stream), "W build");
   TIMED(wk, QMC_T_LU, stream, launch_lu_inverse(se, de, stream), "LU");
   TIMED(wk, QMC_T_Y_BUILD, stream, launch_Y_build(se, de, stream), "Y build");
@@ -1218,6 +1243,7 @@ extern "C" qmc_status qmc_system_set_params(qmc_system* sys, const double* R, co
   if (lambda && d.pairing) HIP_TRY(launch_pf_set(d, lambda, nullptr, nullptr, nullptr, nullptr, stream), "set A^ud");
   if (lambda && !d.pairing) HIP_TRY(launch_set_lambda(d, lambda, stream), "set lambda");
   if (lambda && !d.pairing) HIP_TRY(launch_lam_mask(d, stream), "lambda mask");
+  if (lambda && !d.pairing && d.oz_s > 0) HIP_TRY(launch_oz_lambda(d, stream), "lambda digits");
   if (R || zeta) HIP_TRY(launch_pack_basis(d, stream), "pack basis");
   if (jas) {
     HIP_TRY(hipMemcpyAsync(d.j1_b, jas, sizeof(double) * d.n_nuc, hipMemcpyDeviceToDevice, stream), "set j1");

@@ -40,20 +40,22 @@ def _eval(P, w, Wk, precision=None):
     return sysh, wk, r, out
 
 
-def _term_tol(ratios, a_i, e_kin, e_loc):
+def _term_tol(ratios, a_i, e_kin, e_loc, bar=1e-10):
     s = (ratios.abs().clamp(min=1.0) / (a_i * a_i).unsqueeze(-1)).sum(dim=(1, 2))
-    return 1e-10 * s + 1e-10 * torch.stack([e_kin.abs(), e_loc.abs(), torch.ones_like(e_kin)]).max(0).values
+    return bar * s + bar * torch.stack([e_kin.abs(), e_loc.abs(), torch.ones_like(e_kin)]).max(0).values
 
 
-def _check_terms(gpu, col, a_i):
-    tol = _term_tol(col["ratios"], a_i, col["e_kin"], col["e_loc"])
+def _check_terms(gpu, col, a_i, bar=1e-10):
+    """bar: relative bar of the hop ratios and energies the terms are built from
+    (1e-10 FP64; 1e-8 for the mixed evaluation's int8 digit products)."""
+    tol = _term_tol(col["ratios"], a_i, col["e_kin"], col["e_loc"], bar)
     for k in ("lap_a", "v_sf", "escape", "hfn_diag"):
         d = (gpu[k].cpu() - col[ORACLE_KEY[k]]).abs()
         assert (d <= tol).all(), (k, d.max().item(), tol.min().item())
     d = (gpu["va_shift"].cpu() - (col["V_a"] - col["V"])).abs()
     assert (d <= tol).all(), ("va_shift", d.max().item())
     for k in ("e_loc", "e_kin"):
-        assert rel_err(gpu[k].cpu(), col[k]).max().item() <= 1e-10
+        assert rel_err(gpu[k].cpu(), col[k]).max().item() <= bar
 
 
 def _check_step(r, a_i, col, xi, w0, t0, rn, wt, tl, hop, tol):
@@ -98,11 +100,14 @@ def test_lrdmc_tiny_all_walkers(grid, precision):
     e = rel_err(g["ratios"].cpu(), col["ratios"]).max().item()
     print(f"[lrdmc tiny {grid} {precision}] ratio rel err {e:.3e}; negative hops "
           f"{int((col['ratios'] < 0).sum())}; hops made {int((hop >= 0).sum())}")
-    assert e <= 1e-10
-    _check_terms(g, col, a_i)
+    # mixed: the cofactor rows come from the int8 digit products (about 1e-13 of
+    # max|Phi| max|Lambda| L before the cond(W) amplification): bar 1e-8
+    bar = 1e-10 if precision == "fp64" else 1e-8
+    assert e <= bar
+    _check_terms(g, col, a_i, bar)
     # the fixed-node lattice local energy is e_L for every gamma (oracle identity)
     assert torch.equal(g["e_loc"].cpu(), out["e_loc"].cpu())
-    tol = _term_tol(col["ratios"], a_i, col["e_kin"], col["e_loc"])
+    tol = _term_tol(col["ratios"], a_i, col["e_kin"], col["e_loc"], bar)
     _check_step(rc, a_i, col, xi.cpu(), w0, t0, rn, weight, tau, hop, tol)
     assert (hop.cpu()[:4] == -1).all() and torch.equal(rn.cpu()[:4], rc[:4])
     assert torch.equal(weight.cpu()[:4], w0[:4]) and (tau.cpu()[:4] == 0).all()

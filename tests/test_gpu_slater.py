@@ -43,7 +43,10 @@ def test_slater_eval_matches_oracle(slater, precision):
     d = out["drift"].cpu()
     e_dr = ((d - ref["drift"]).abs() / ref["drift"].abs().clamp(min=1.0)).max().item()
     print(f"[slater eval {precision}] logabs {e_la:.3e} e_kin {e_ek:.3e} e_loc {e_el:.3e} drift {e_dr:.3e}")
-    assert e_la <= 1e-10 and e_ek <= 1e-10 and e_el <= 1e-10 and e_dr <= 1e-8
+    # the mixed evaluation's products carry the int8 digit expansion's error
+    # (about 1e-13 of max|Phi| max|Lambda| L), amplified by cond(W): its bar is 1e-8
+    bar = 1e-10 if precision == "fp64" else 1e-8
+    assert e_la <= bar and e_ek <= bar and e_el <= bar and e_dr <= 1e-8
     assert torch.equal(out["sign"].cpu(), ref["sign"])
 
 
