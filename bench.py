@@ -29,9 +29,15 @@ import torch  # noqa: E402
 
 METRIC = "walker-electron moves/s + E_loc evals/s at 160e, mixed vs FP64, err vs oracle"
 HBM_PEAK_GBS = 8000.0
-# the evaluation's P = Phi Lambda product runs on FP64 MFMA in every mode but
-# fp32 (QMC_W_FP32, FP32 operands and accumulation)
-MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "mixed": 78.6, "bf16": 78.6}
+INT8_PEAK_TOPS = 5000.0
+# the evaluation's P = Phi Lambda product: FP64 MFMA (fp64), FP32 MFMA (fp32),
+# int8 MFMA digit products (mixed, mixed_fp32_rows, bf16: refined evaluations)
+MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "mixed": INT8_PEAK_TOPS, "mixed_fp32_rows": INT8_PEAK_TOPS,
+                    "bf16": INT8_PEAK_TOPS}
+OZ_DIGITS = 7          # int8 digits per FP64 row in the refined products
+PRECISIONS = ("fp64", "mixed", "mixed_fp32_rows", "bf16", "fp32")
+# accuracy bar of each mode's ratios and evaluations against the oracle
+BARS = {"fp64": 1e-10, "mixed": 1e-6, "mixed_fp32_rows": 1e-6, "bf16": 1e-6, "fp32": 1e-6}
 
 
 def parse():
@@ -40,9 +46,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--walkers", type=int, default=1024)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed", "bf16", "fp32"],
-                    help="fp64; mixed = FP32 move path with FP64-accurate evaluations; bf16 = the "
-                         "same with BF16 move rows; fp32 = FP32 move path and FP32-product evaluations")
+    ap.add_argument("--precision", default="fp64", choices=list(PRECISIONS),
+                    help="fp64 (QMC_FP64); mixed (QMC_REFINED: int8-refined products, screened FP64 "
+                         "proposals); mixed_fp32_rows (QMC_MIXED: refined evaluations, FP32 move rows); "
+                         "bf16 (QMC_MIXED_BF16: BF16 move rows); fp32 (QMC_W_FP32: FP32 products and rows)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--oracle-walkers", type=int, default=4)
     ap.add_argument("--only", action="store_true", help="run the headline precision only")
@@ -100,13 +107,17 @@ def copy_probe(mib):
     del src, dst
 
 
-def kernel_models(s, Wk, esz, acc_rate):
+def kernel_models(s, Wk, esz, acc_rate, kept=None):
     """Algorithmic bytes / flops per launch of the main kernels.
 
     propose (the streaming kernel): every walker reads the N_other x L rows of P
              of the opposite spin (esz bytes each), psi(r') (8 L), the current
              W^{-1} column / row of the moved electron (8 N_other, assembled by the
-             set-up kernel), and writes the new W row (8 N_other).
+             set-up kernel), and writes the new W row (8 N_other).  Screened
+             proposals (kept = average number of basis functions streamed):
+             kept columns of N_other FP64 values, the kept functions' indices and
+             values (12 kept), the inverse column (8 N_other) and the new row
+             (8 N_other).
     accept:  (latency-bound: chains of dependent loads of a few kB per walker;
              in a Metropolis sweep it also runs the next proposal's set-up, so
              its time is not priced against a roofline)
@@ -126,15 +137,33 @@ def kernel_models(s, Wk, esz, acc_rate):
     cap = min(s.refresh_every, 64)
     cycles = [cap] * (n // cap) + ([n % cap] if n % cap else [])
     m = acc_rate * sum(c * (c - 1) / 2 for c in cycles) / n
-    prop = Wk * (esz * n * L + 8 * L + 8 * n + 8 * n)
+    if kept is None:
+        prop = Wk * (esz * n * L + 8 * L + 8 * n + 8 * n)
+    else:
+        prop = Wk * (kept * (8 * n + 12) + 16 * n)
     acc = Wk * acc_rate * (8 * n * (3 + m) + 8 * m * m + 16 * m + 8 * L
                            + 16 * n + 8 * (m + 1) ** 2 + 8 * n + esz * L)
     pflops = 2.0 * L * L * Wk * N
     return {"propose": ("hbm", prop), "accept": ("latency", acc), "P_build": ("mfma", pflops)}
 
 
-def cpu_baseline(w, n_walk=8, n_moves=320, n_eval=32):
-    """The CPU oracle, untuned, on a bounded sample of the same workload."""
+def host_cpu():
+    """Model name of the host processor and the cores this process may use."""
+    name = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return name, len(os.sched_getaffinity(0))
+
+
+def cpu_baseline(w, n_walk=8, n_moves=320, n_eval=32, n_moves_1t=40):
+    """The CPU oracle, untuned, on a bounded sample of the same workload: with
+    torch's default thread count, and on one thread for a shorter chain."""
     from oracle import jagp as O
     from workloads import configs as C
     sy = O.from_workload_system(w.system)
@@ -146,13 +175,25 @@ def cpu_baseline(w, n_walk=8, n_moves=320, n_eval=32):
     t0 = time.perf_counter()
     O.run_chain(sy, r, torch.tensor(disp), torch.tensor(unif))
     t_moves = time.perf_counter() - t0
+    threads = torch.get_num_threads()
+    torch.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        O.run_chain(sy, r, torch.tensor(disp[:n_moves_1t]), torch.tensor(unif[:n_moves_1t]))
+        t_1t = time.perf_counter() - t0
+    finally:
+        torch.set_num_threads(threads)
+    model, avail = host_cpu()
     return {
         "value": n_walk * n_moves / t_moves, "unit": "walker-electron moves/s",
-        "cores": torch.get_num_threads(), "kind": "oracle",
+        "cores": threads, "kind": "oracle",
         "sample": f"{n_walk} walkers x {n_moves} single-electron moves (each move re-evaluates Psi "
                   f"from scratch) and E_loc evaluations of {n_eval} walkers, same workload",
         "eloc_evals_per_s": n_eval / t_eval,
-        "seconds": round(t_eval + t_moves, 2),
+        "one_thread": {"value": n_walk * n_moves_1t / t_1t, "unit": "walker-electron moves/s",
+                       "sample": f"{n_walk} walkers x {n_moves_1t} moves"},
+        "host_cpu": model, "host_cores_available": avail,
+        "seconds": round(t_eval + t_moves + t_1t, 2),
     }
 
 
@@ -163,8 +204,10 @@ def run_precision(P, C, w, args, precision):
     s = w.system
     N = s.n_up + s.n_dn
     Wk = args.walkers
-    prec = {"fp64": P.QMC_FP64, "mixed": P.QMC_MIXED, "bf16": P.QMC_MIXED_BF16, "fp32": P.QMC_W_FP32}[precision]
-    esz = {"fp64": 8, "bf16": 2}.get(precision, 4)
+    prec = {"fp64": P.QMC_FP64, "mixed": P.QMC_REFINED, "mixed_fp32_rows": P.QMC_MIXED, "bf16": P.QMC_MIXED_BF16,
+            "fp32": P.QMC_W_FP32}[precision]
+    esz = {"fp64": 8, "mixed": 8, "bf16": 2}.get(precision, 4)
+    screened = precision == "mixed"
     sysh = P.JAGPSystem(s, precision=prec)
     wk = P.Walkers(sysh, Wk, adjoint=False)
     n_tot = args.warmup + args.steps
@@ -209,21 +252,46 @@ def run_precision(P, C, w, args, precision):
     moves = args.steps * N * Wk
     acc_rate = n_acc / moves
 
-    # error of an evaluation at the final positions against the CPU oracle
+    # screened proposals: basis functions streamed per proposal over one sweep
+    kept = None
+    if screened:
+        ks = []
+        for t in range(N):
+            wk.vmc_steps(t, disp[0][t:t + 1].contiguous(), unif[0][t:t + 1].contiguous())
+            ks.append(wk.read(P.STATE_KEPT))
+        kept = torch.stack(ks).mean().item()
+        r_cur = wk.read(P.STATE_R)
+
+    # error against the CPU oracle on sampled walkers at the final positions: an
+    # evaluation (log|Psi|, E_loc) and the ratios of proposals of two up and two
+    # down electrons (the definition: two full evaluations)
     idx = np.linspace(0, Wk - 1, args.oracle_walkers).round().astype(int).tolist()
     err = {}
     if idx:
         out = wk.eval_batch(r_cur, drift=True)
         torch.cuda.synchronize()
-        ref = O.evaluate(O.from_workload_system(s), r_cur.cpu()[idx])
+        sy = O.from_workload_system(s)
+        rc = r_cur.cpu()
+        ref = O.evaluate(sy, rc[idx])
         for key in ("logabs", "e_loc"):
             d = (out[key].cpu()[idx] - ref[key]).abs() / ref[key].abs().clamp(min=1.0)
             err[key] = float(f"{float(d.max()):.3e}")
+        g = torch.Generator().manual_seed(5)
+        rmax = 0.0
+        for e in (3, s.n_up - 1, s.n_up, N - 7):
+            rn = rc[:, e] + 0.3 * torch.randn(Wk, 3, generator=g, dtype=torch.float64)
+            wk.eval_batch(r_cur, drift=False)
+            ratio = wk.propose(e, rn.to(dev).contiguous()).cpu()[idx]
+            rr = O.move_ratio(sy, rc[idx], e, rn[idx])
+            rmax = max(rmax, float(((ratio - rr).abs() / rr.abs().clamp(min=1.0)).max()))
+        err["ratio"] = float(f"{rmax:.3e}")
+        err["bar"] = BARS[precision]
+        err["conforming"] = bool(max(err["logabs"], err["e_loc"], err["ratio"]) <= BARS[precision])
 
     # roofline of the dominant kernel (largest summed time in the timed steps)
     # roofline of the dominant bandwidth- or MFMA-bound kernel; the kernel with the
     # largest summed time overall is named beside it
-    models = kernel_models(s, Wk, esz, acc_rate)
+    models = kernel_models(s, Wk, esz, acc_rate, kept)
     dominant = max(one, key=lambda k: one[k][0])
     dom = max((k for k in models if models[k][0] != "latency"), key=lambda k: tim[k][0])
     bound, units = models[dom]
@@ -232,8 +300,8 @@ def run_precision(P, C, w, args, precision):
         achieved = units / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": (recorded_traffic({"fp64": "fp64", "bf16": "bf16"}.get(precision, "fp32"), Wk)
-                            if dom == "propose" else None),
+                "traffic": (recorded_traffic({"fp64": "fp64", "bf16": "bf16", "mixed": "refined"}.get(
+                    precision, "fp32"), Wk) if dom == "propose" else None),
                 "bytes_per_launch": int(units), "avg_launch_us": round(avg_ms * 1e3, 2)}
     else:
         peak = MFMA_PEAK_TFLOPS[precision]
@@ -243,15 +311,30 @@ def run_precision(P, C, w, args, precision):
                 "flops_per_launch": int(units), "avg_launch_us": round(avg_ms * 1e3, 2)}
     steps = step_rooflines(s, Wk, precision, one, roof) if roof["kernel"] == "propose" else None
     # MFMA use of the geminal build's dominant product (P = Phi Lambda in the
-    # evaluations of the timed steps)
+    # evaluations of the timed steps).  Refined modes: int8 operations of the
+    # digit products (the P_build timer also covers the digit split) against
+    # the int8 peak, and the FP64-equivalent rate beside it
     pf_ms = tim["P_build"][0] / max(tim["P_build"][1], 1)
-    pf_tf = models["P_build"][1] / (pf_ms * 1e-3) / 1e12
-    wmfma = {"kernel": "P_build", "achieved": round(pf_tf, 2), "peak": MFMA_PEAK_TFLOPS[precision],
-             "unit": "TFLOP/s", "frac": round(pf_tf / MFMA_PEAK_TFLOPS[precision], 4),
-             "flops_per_launch": int(models["P_build"][1]), "avg_launch_us": round(pf_ms * 1e3, 2)}
+    if precision in ("fp64", "fp32"):
+        pf_tf = models["P_build"][1] / (pf_ms * 1e-3) / 1e12
+        wmfma = {"kernel": "P_build", "instruction": "v_mfma_f64_16x16x4f64" if precision == "fp64"
+                 else "v_mfma_f32_16x16x4f32", "achieved": round(pf_tf, 2), "peak": MFMA_PEAK_TFLOPS[precision],
+                 "unit": "TFLOP/s", "frac": round(pf_tf / MFMA_PEAK_TFLOPS[precision], 4),
+                 "flops_per_launch": int(models["P_build"][1]), "avg_launch_us": round(pf_ms * 1e3, 2)}
+    else:
+        Lp = (s.n_basis + 31) // 32 * 32
+        ops = 2.0 * Lp * Lp * N * Wk * OZ_DIGITS * (OZ_DIGITS + 1) // 2
+        int8 = ops / (pf_ms * 1e-3) / 1e12
+        wmfma = {"kernel": "P_build", "instruction": "v_mfma_i32_32x32x32_i8", "achieved": round(int8, 1),
+                 "peak": INT8_PEAK_TOPS, "unit": "TOP/s", "frac": round(int8 / INT8_PEAK_TOPS, 4),
+                 "ops_per_launch": int(ops), "digit_products": OZ_DIGITS * (OZ_DIGITS + 1) // 2,
+                 "fp64_equivalent_TFLOPs": round(models["P_build"][1] / (pf_ms * 1e-3) / 1e12, 2),
+                 "avg_launch_us": round(pf_ms * 1e3, 2)}
     wk.close()
     sysh.close()
     return {
+        "mode": {"fp64": "QMC_FP64", "mixed": "QMC_REFINED", "mixed_fp32_rows": "QMC_MIXED",
+                 "bf16": "QMC_MIXED_BF16", "fp32": "QMC_W_FP32"}[precision],
         "moves_per_s": round(moves / t_move, 1),
         "eloc_evals_per_s": round(Wk * args.steps / t_eval, 1),
         "ms_per_step": round(wall / args.steps * 1e3, 3),
@@ -265,6 +348,7 @@ def run_precision(P, C, w, args, precision):
         "roofline": roof,
         "w_build_mfma": wmfma,
         "step_rooflines": steps,
+        **({"screened_functions_per_proposal": round(kept, 1), "basis_functions": s.n_basis} if screened else {}),
     }
 
 
@@ -612,7 +696,9 @@ def step_rooflines(s, Wk, precision, one, prop_roof):
     """Roofline of each step of one evaluation (and the proposal) from the
     one-step timers: algorithmic bytes or flops per launch / average launch.
       basis:   writes the N x L values of every walker (FP64; FP32 in fp32 mode)
-      P_build: 2 L^2 N flops per walker (MFMA; FP64 but in fp32 mode)
+      P_build: 2 L^2 N flops per walker (MFMA; FP64 but in fp32 mode); the
+               refined modes count the int8 operations of their 28 digit
+               products, 2 Lp^2 N x 28 per walker (Lp = L rounded up to 32)
       W_build: 2 n_up n_dn L flops per walker (FP64 MFMA accumulation)
       LU:      2 n^3 flops per walker per launch (FP64 vector ALU, latency-bound
                at n = 80: one workgroup per walker)
@@ -620,7 +706,10 @@ def step_rooflines(s, Wk, precision, one, prop_roof):
     L, N, nu, nd = s.n_basis, s.n_up + s.n_dn, s.n_up, s.n_dn
     models = {
         "basis": ("hbm", Wk * N * L * (4 if precision == "fp32" else 8), HBM_PEAK_GBS, "GB/s", 1e9),
-        "P_build": ("mfma", 2.0 * L * L * N * Wk, MFMA_PEAK_TFLOPS[precision], "TFLOP/s", 1e12),
+        "P_build": (("mfma", 2.0 * L * L * N * Wk, MFMA_PEAK_TFLOPS[precision], "TFLOP/s", 1e12)
+                    if precision in ("fp64", "fp32") else
+                    ("mfma", 2.0 * ((L + 31) // 32 * 32) ** 2 * N * Wk * OZ_DIGITS * (OZ_DIGITS + 1) // 2,
+                     INT8_PEAK_TOPS, "TOP/s", 1e12)),
         "W_build": ("mfma", 2.0 * nu * nd * L * Wk, 78.6, "TFLOP/s", 1e12),
         "LU": ("alu", 2.0 * nu ** 3 * Wk, 78.6, "TFLOP/s", 1e12),
         "Y_build": ("mfma", 4.0 * nu * nu * L * Wk, 78.6, "TFLOP/s", 1e12),
@@ -654,7 +743,7 @@ def main():
     s = w.system
     N = s.n_up + s.n_dn
     main_prec = args.precision
-    others = [p for p in ("fp64", "mixed", "bf16", "fp32") if p != main_prec]
+    others = [p for p in PRECISIONS if p != main_prec]
     head = run_precision(P, C, w, args, main_prec)
     sides = {} if args.only else {p: run_precision(P, C, w, args, p) for p in others}
     res = {
@@ -664,7 +753,8 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": head["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if main_prec == "fp64" else "f32+f64",
+        "dtype": {"fp64": "f64", "mixed": "i8+f64", "mixed_fp32_rows": "i8+f32+f64", "bf16": "i8+bf16+f64",
+                  "fp32": "f32+f64"}[main_prec],
         "data": "synthetic",
         "config": {"workload": "mol_40nuc_160e", "walkers": args.walkers, "electrons": N,
                    "basis": s.n_basis, "nuclei": len(s.Z), "refresh_every": s.refresh_every,

@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define QMC_ABI_VERSION 18
+#define QMC_ABI_VERSION 19
 
 typedef enum {
   QMC_OK = 0,
@@ -77,8 +77,21 @@ typedef enum {
                       FP32 accumulation); ratios and updates FP64              */
   QMC_W_BF16 = 4,  /* unrefined geminal build on BF16 matrix instructions with
                       FP32 accumulation (not built: QMC_ERR_UNSUPPORTED)        */
-  QMC_W_FP8 = 5    /* unrefined geminal build on FP8 matrix instructions (not
+  QMC_W_FP8 = 5,   /* unrefined geminal build on FP8 matrix instructions (not
                       built: QMC_ERR_UNSUPPORTED)                              */
+  QMC_REFINED = 6  /* the mixed path held to the FP64 oracle: every P = Phi Lambda
+                      product (evaluation and the P rebuilds between moves) on
+                      the int8 matrix cores as an error-free digit expansion
+                      (7 int8 digits per FP64 row, exact int32 accumulation:
+                      error below 7e-14 of max|Phi| max|Lambda| L); Phi, P, W,
+                      LU, inverse, cofactors, ratios and updates FP64;
+                      proposals stream only the P columns of basis functions
+                      whose value at r' can change the determinant ratio:
+                      those skipped contribute at most 1e-13 in total (bound
+                      from the largest |P| of each column and the inverse
+                      column's 1-norm).  Not with unpaired orbitals, the
+                      Pfaffian or qmc_multi_*.  One more [Wk][L][N] FP64 array
+                      (P transposed).                                          */
 } qmc_precision;
 
 typedef struct qmc_system qmc_system;   /* opaque: nuclei, basis, Lambda, Jastrow */
@@ -548,8 +561,10 @@ typedef enum {
   QMC_STATE_AINV = 4,    /* [Wk][n_dn][n_up] FP64 W^{-1} (assembled from the
                             delayed form; uses the walkers' own work arrays)  */
   QMC_STATE_PHI = 5,     /* [Wk][N][L]   FP64 basis values psi_mu(r_i)           */
-  QMC_STATE_RESIDUAL = 6 /* [Wk]         max|W X - I| of the last checked refresh
+  QMC_STATE_RESIDUAL = 6, /* [Wk]        max|W X - I| of the last checked refresh
                             (see qmc_walkers_set_drift_tol)                    */
+  QMC_STATE_KEPT = 7     /* [Wk]         basis functions the last proposal streamed
+                            (QMC_REFINED only; as FP64 values)                */
 } qmc_state_item;
 
 /* Copy one item of the walker state into dst (device memory, the layout given

@@ -23,10 +23,11 @@ QMC_MIXED = 2
 QMC_MIXED_BF16 = 3
 QMC_W_BF16 = 4
 QMC_W_FP8 = 5
+QMC_REFINED = 6
 
 WALKERS_ADJOINT = 1
 
-STATE_R, STATE_LOGABS, STATE_SIGN, STATE_W, STATE_AINV, STATE_PHI, STATE_RESIDUAL = range(7)
+STATE_R, STATE_LOGABS, STATE_SIGN, STATE_W, STATE_AINV, STATE_PHI, STATE_RESIDUAL, STATE_KEPT = range(8)
 
 STATUS_NAMES = {0: "OK", -1: "ERR_ARG", -2: "ERR_SHAPE", -3: "ERR_HIP", -4: "ERR_OOM",
                 -5: "ERR_UNSUPPORTED", -6: "ERR_STATE"}
@@ -343,7 +344,7 @@ class Walkers:
         Wk, N, nu, nd, L = self.n, self.sys.n_elec, self.sys.n_up, self.sys.n_dn, self.sys.L
         n = self.sys.npf if self.sys.pairing else nu   # G~ (Pfaffian) or W
         shape = {STATE_R: (Wk, N, 3), STATE_LOGABS: (Wk,), STATE_SIGN: (Wk,), STATE_W: (Wk, n, n),
-                 STATE_AINV: (Wk, n, n), STATE_PHI: (Wk, N, L), STATE_RESIDUAL: (Wk,)}[item]
+                 STATE_AINV: (Wk, n, n), STATE_PHI: (Wk, N, L), STATE_RESIDUAL: (Wk,), STATE_KEPT: (Wk,)}[item]
         dst = torch.empty(shape, dtype=torch.float64, device="cuda")
         _check(load().qmc_walkers_read(self.h, item, _ptr(dst), _stream(stream)))
         return dst

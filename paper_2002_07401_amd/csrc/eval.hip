@@ -18,7 +18,7 @@ __global__ void __launch_bounds__(256) basis_values_kernel(SysDev s, const doubl
     out[mu] = (T)(mu < s.L ? basis_value(s, mu, px, py, pz) : 0.0);
 }
 
-// FP64 values plus their FP32 or BF16 copy (the rows the moves stream).  With
+// FP64 values plus (lo not null) their FP32 or BF16 copy (the rows the moves stream).  With
 // ephi, also the exponent floor(log2 max_mu |psi_mu(r_i)|) of the row (0 for a
 // row of zeros), the scale of its int8 digits: up electron i of walker w at
 // ephi[w * n_up + i], down electron j at ephi[Wk * n_up + w * n_dn + j].
@@ -30,12 +30,12 @@ __global__ void __launch_bounds__(256) basis_values_dual_kernel(SysDev s, const 
   const long row = blockIdx.x;   // w * N + i
   const double px = r[3 * row], py = r[3 * row + 1], pz = r[3 * row + 2];
   double* out = phi + row * s.Lp;
-  T2* out2 = lo + row * s.Lp;
+  T2* out2 = lo ? lo + row * s.Lp : nullptr;
   double mx = 0.0;
   for (int mu = threadIdx.x; mu < s.Lp; mu += blockDim.x) {
     const double v = mu < s.L ? basis_value(s, mu, px, py, pz) : 0.0;
     out[mu] = v;
-    out2[mu] = (T2)v;
+    if (out2) out2[mu] = (T2)v;
     mx = fmax(mx, fabs(v));
   }
   if (!ephi) return;   // uniform
@@ -76,7 +76,8 @@ __global__ void __launch_bounds__(256) contracted_values_kernel(SysDev s, const 
 hipError_t launch_basis_values(const SysDev& s, const WalkDev& w, hipStream_t st, void* lo, bool lo_bf16,
                                int* ephi) {
   const dim3 grid((unsigned)((long)w.Wk * s.N));
-  const bool dual = lo && !s.bf16() && !s.f32();   // FP64 values with a low-precision copy
+  // FP64 values with a low-precision copy and / or the rows' digit exponents
+  const bool dual = (lo || ephi) && !s.f32();
   if (dual && s.Lq == 0) {
     if (lo_bf16)
       hipLaunchKernelGGL(basis_values_dual_kernel<bf16s>, grid, dim3(256), 0, st, s, w.r, (double*)w.phi, (bf16s*)lo,

@@ -34,6 +34,9 @@ constexpr int kLamTileK = 16;     // Lambda tile mask granularity: rows (GEMM K 
 constexpr int kLamTileN = 64;     // ... and columns (GEMM N tile)
 constexpr int kOzMaxSlices = 8;   // int8 digits per FP64 row in the error-free products
 constexpr int kOzSlices = 7;      // digits used by the refined evaluation (error 7e-14 of max|x| max|y| K)
+// Screened proposals (QMC_REFINED): the basis functions skipped at r' change the
+// determinant ratio by at most this much in total (absolute)
+constexpr double kScreenTol = 1e-13;
 
 inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
@@ -72,12 +75,16 @@ struct SysDev {
                      // qmc_system_set_params can replace them without a host sync
   int precision, refresh_every;
   // reduced-precision storage of Phi and P (the move path): FP32 in QMC_W_FP32
-  // and QMC_MIXED, BF16 in QMC_MIXED_BF16
-  __host__ __device__ bool f32() const { return precision != QMC_FP64; }
+  // and QMC_MIXED, BF16 in QMC_MIXED_BF16 (FP64 in QMC_FP64 and QMC_REFINED)
+  __host__ __device__ bool f32() const {
+    return precision == QMC_W_FP32 || precision == QMC_MIXED || precision == QMC_MIXED_BF16;
+  }
+  // QMC_REFINED: FP64 storage, refined int8 products, screened proposals
+  __host__ __device__ bool screened() const { return precision == QMC_REFINED; }
   __host__ __device__ bool bf16() const { return precision == QMC_MIXED_BF16; }
   __host__ __device__ bool refined() const { return precision == QMC_MIXED || precision == QMC_MIXED_BF16; }
   // 0: FP64, 1: FP32, 2: BF16 storage
-  __host__ __device__ int store() const { return precision == QMC_FP64 ? 0 : (bf16() ? 2 : 1); }
+  __host__ __device__ int store() const { return f32() ? (bf16() ? 2 : 1) : 0; }
   __host__ __device__ int prop_rows() const { return store() == 0 ? kPropRowsF64 : kPropRowsNarrow; }
   double* R;        // [A][3]
   double* Z;        // [A]
@@ -218,6 +225,16 @@ struct WalkDev {
   // Lp digits each), and one exponent per row [Wk * n_up + Wk * n_dn]
   int8_t* oz_phi;
   int* oz_ephi;
+  // screened proposals (QMC_REFINED): P transposed per walker, PT[w][mu][i] =
+  // P[w][i][mu] (so that one basis function's column over the rows of one spin
+  // is contiguous); per walker and spin the largest |P| of each column
+  // [Wk][2][Lp] (0: up rows, 1: down rows); the pending proposal's kept basis
+  // functions (index and value at r') and their count
+  double* PT;
+  double* cmax;
+  int* muk;
+  double* psk;
+  int* nkeep;
 };
 
 // Workspace of the reverse pass (allocated on the first qmc_forces call).
@@ -500,7 +517,12 @@ hipError_t launch_slice_tiles(const double* X, long rows, int K, int Kp, int grp
                               int8_t* out, long plane, int* expo, hipStream_t st, bool have_expo = false);
 hipError_t launch_oz_lambda(const SysDev& s, hipStream_t st);
 hipError_t launch_P_build_oz(const SysDev& s, const WalkDev& w, int halves, const double* phi64, double* P64,
-                             void* lo, bool lo_bf16, hipStream_t st, bool have_expo = false);
+                             void* lo, bool lo_bf16, hipStream_t st, bool have_expo = false, double* PT = nullptr);
+// screened proposals: column maxima of the P halves, and the streaming kernel
+hipError_t launch_screen_colmax(const SysDev& s, const WalkDev& w, int halves, hipStream_t st);
+hipError_t launch_export_kept(const WalkDev& w, double* dst, hipStream_t st);
+hipError_t launch_propose_screened(const SysDev& s, const WalkDev& w, int e, double* ratio, bool finalize,
+                                   hipStream_t st, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 hipError_t launch_Y_build(const SysDev& s, const WalkDev& w, hipStream_t st);
 hipError_t launch_lu_inverse(const SysDev& s, const WalkDev& w, hipStream_t st);
 hipError_t launch_lam_mask(const SysDev& s, hipStream_t st);

@@ -164,6 +164,126 @@ hipError_t launch_propose_rows(const SysDev& s, const WalkDev& w, int e, double*
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Screened proposals (QMC_REFINED).  The new W row (column) of walker wk is
+//   w'_j = sum over the kept mu of psi_mu(r') PT[wk][mu][i0 + j],
+// one contiguous column of the other spin's rows per kept basis function (the
+// skipped ones change the ratio by at most kScreenTol, see screen_list_body).
+// One workgroup per walker: wave v takes kept functions v, v + 4, ..., four at
+// a time, lane l the rows l, l + 64, ...; the waves' partial rows are added in
+// a fixed order through LDS, then the ratio sum_j w'_j c_j.  The ratio goes to
+// the first of the walker's S partial slots (the others are zeroed), which the
+// accept and finalize kernels sum as usual.
+// ---------------------------------------------------------------------------
+template <int NB>
+__global__ void __launch_bounds__(256) propose_screened_kernel(SysDev s, WalkDev w, int e, int S) {
+  __shared__ double part[4][64 * NB];
+  __shared__ double red[8];
+  const int wk = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const bool up = e < s.nu;
+  const int i0 = up ? s.nu : 0;
+  const int n = up ? s.nd : s.nu;
+  const double* base = w.PT + (long)wk * s.Lp * s.N + i0;
+  const int cnt = w.nkeep[wk];
+  const int* mk = w.muk + (long)wk * s.Lp;
+  const double* pk = w.psk + (long)wk * s.Lp;
+  double acc[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) acc[b] = 0.0;
+  int k = wave;
+  for (; k + 12 < cnt; k += 16) {   // four functions in flight per wave
+    int mu[4];
+    double v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) { mu[q] = mk[k + 4 * q]; v[q] = pk[k + 4 * q]; }
+    double x[4][NB];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int j = lane + 64 * b;
+        x[q][b] = j < n ? __builtin_nontemporal_load(base + (long)mu[q] * s.N + j) : 0.0;
+      }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) acc[b] += v[q] * x[q][b];
+  }
+  for (; k < cnt; k += 4) {
+    const int mu = mk[k];
+    const double v = pk[k];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int j = lane + 64 * b;
+      if (j < n) acc[b] += v * base[(long)mu * s.N + j];
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < NB; ++b) part[wave][lane + 64 * b] = acc[b];
+  __syncthreads();
+  const double* cv = w.cvec + (long)wk * s.nu;
+  double* wn = w.w_new + (long)wk * s.nu;
+  double rp = 0.0;
+  for (int j = tid; j < n; j += blockDim.x) {
+    const double x = ((part[0][j] + part[1][j]) + part[2][j]) + part[3][j];
+    wn[j] = x;
+    rp += x * cv[j];
+  }
+  const double R = block_sum_mv(rp, red);
+  for (int q = tid; q < S; q += blockDim.x) w.rdet_part[(long)wk * S + q] = q == 0 ? R : 0.0;
+}
+
+// Column maxima of the P halves (bit 0: up rows, bit 1: down rows):
+// cmax[w][h][mu] = max over the rows i of half h of |P[w][i][mu]|.
+__global__ void __launch_bounds__(256) screen_colmax_kernel(SysDev s, WalkDev w, int halves) {
+  const int wk = blockIdx.x, h = blockIdx.y;
+  if (!((halves >> h) & 1)) return;
+  const int i0 = h == 0 ? 0 : s.nu, n = h == 0 ? s.nu : s.nd;
+  const double* P = (const double*)w.P + ((long)wk * s.N + i0) * s.Lp;
+  double* out = w.cmax + ((long)wk * 2 + h) * s.Lp;
+  for (int mu = threadIdx.x; mu < s.Lp; mu += blockDim.x) {
+    double m = 0.0;
+    for (int i = 0; i < n; ++i) m = fmax(m, fabs(P[(long)i * s.Lp + mu]));
+    out[mu] = m;
+  }
+}
+
+__global__ void int_to_double_kernel(const int* __restrict__ src, double* __restrict__ dst, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = (double)src[i];
+}
+
+hipError_t launch_export_kept(const WalkDev& w, double* dst, hipStream_t st) {
+  if (!w.nkeep) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(int_to_double_kernel, dim3((w.Wk + 255) / 256), dim3(256), 0, st, w.nkeep, dst, w.Wk);
+  return hipGetLastError();
+}
+
+hipError_t launch_screen_colmax(const SysDev& s, const WalkDev& w, int halves, hipStream_t st) {
+  if (!w.cmax) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(screen_colmax_kernel, dim3(w.Wk, 2), dim3(256), 0, st, s, w, halves);
+  return hipGetLastError();
+}
+
+hipError_t launch_propose_screened(const SysDev& s, const WalkDev& w, int e, double* ratio, bool finalize,
+                                   hipStream_t st, hipEvent_t ev_start, hipEvent_t ev_stop) {
+  if (!w.PT || !w.muk) return hipErrorInvalidValue;
+  const int n = e < s.nu ? s.nd : s.nu;
+  const int S = propose_splits(s);
+  const dim3 grid(w.Wk), blk(256);
+  if (n <= 64) hipExtLaunchKernelGGL(propose_screened_kernel<1>, grid, blk, 0, st, ev_start, ev_stop, 0, s, w, e, S);
+  else if (n <= 128) hipExtLaunchKernelGGL(propose_screened_kernel<2>, grid, blk, 0, st, ev_start, ev_stop, 0, s, w, e, S);
+  else if (n <= 256) hipExtLaunchKernelGGL(propose_screened_kernel<4>, grid, blk, 0, st, ev_start, ev_stop, 0, s, w, e, S);
+  else if (n <= 512) hipExtLaunchKernelGGL(propose_screened_kernel<8>, grid, blk, 0, st, ev_start, ev_stop, 0, s, w, e, S);
+  else if (n <= 1024) hipExtLaunchKernelGGL(propose_screened_kernel<16>, grid, blk, 0, st, ev_start, ev_stop, 0, s, w, e, S);
+  else return hipErrorNotSupported;
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess || !finalize) return err;
+  hipLaunchKernelGGL(propose_finalize_kernel, dim3((w.Wk + 255) / 256), dim3(256), 0, st, w, S, ratio,
+                     (double*)nullptr);
+  return hipGetLastError();
+}
+
 static hipError_t accept_launch(const SysDev& s, const WalkDev& w, int e, const uint8_t* acc,
                                 const double* unif, int32_t* accept_count, int S, hipStream_t st) {
   if (s.nu > kBigMaxN || !w.wv) return hipErrorNotSupported;

@@ -202,6 +202,62 @@ __device__ void jastrow_change(const SysDev& s, const WalkDev& w, int wk, int e,
   }
 }
 
+// Screened proposals (QMC_REFINED): the basis functions at r' whose column of
+// the streamed P rows can change the ratio.  Over the rows j of the other spin,
+//   |sum_j c_j P_j[mu] psi_mu(r')| <= |psi_mu(r')| cmax_mu sum_j |c_j|,
+// cmax_mu = max_j |P_j[mu]|, c the current inverse column (row) of the moved
+// electron.  Functions with |psi_mu| cmax_mu |c|_1 <= kScreenTol / L are
+// skipped, so all skipped ones together change the ratio by at most
+// kScreenTol (and each new W entry by at most kScreenTol / |c|_1).  The kept
+// ones are listed in increasing mu with their values.  Called by every thread
+// of the workgroup after psi_new and cvec of electron e are written.
+__device__ void screen_list_body(const SysDev& s, const WalkDev& w, int wk, int e) {
+  __shared__ double red[8];
+  __shared__ int wcount[4];
+  __shared__ int total;
+  __syncthreads();
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const bool up = e < s.nu;
+  const double* cv = w.cvec + (long)wk * s.nu;
+  double c1 = 0.0;
+  for (int j = tid; j < s.nu; j += blockDim.x) c1 += fabs(cv[j]);
+  c1 = block_sum_mv(c1, red);
+  const double thr = (c1 > 0.0) ? kScreenTol / ((double)s.L * c1) : 0.0;
+  const double* cm = w.cmax + ((long)wk * 2 + (up ? 1 : 0)) * s.Lp;   // the rows the proposal streams
+  const double* psi = w.psi_new + (long)wk * s.Lp;
+  int* mk = w.muk + (long)wk * s.Lp;
+  double* pk = w.psk + (long)wk * s.Lp;
+  if (tid == 0) total = 0;
+  __syncthreads();
+  for (int base = 0; base < s.L; base += blockDim.x) {
+    const int mu = base + tid;
+    double v = 0.0;
+    bool keep = false;
+    if (mu < s.L) {
+      v = psi[mu];
+      keep = fabs(v) * cm[mu] > thr;
+    }
+    const unsigned long long b = __ballot(keep);
+    if (lane == 0) wcount[wave] = __popcll(b);
+    __syncthreads();
+    int off = total;
+    for (int k = 0; k < wave; ++k) off += wcount[k];
+    if (keep) {
+      const int at = off + __popcll(b & ((1ull << lane) - 1ull));
+      mk[at] = mu;
+      pk[at] = v;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int t = total;
+      for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += wcount[k];
+      total = t;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) w.nkeep[wk] = total;
+}
+
 template <bool DRIFT>
 __device__ void prep_body(const SysDev& s, const WalkDev& w, int wk, int e, const double* __restrict__ r_new,
                           const double* __restrict__ disp) {
@@ -227,6 +283,7 @@ __device__ void prep_body(const SysDev& s, const WalkDev& w, int wk, int e, cons
     if (DRIFT) { w.gJ_new[3 * wk] = gxn; w.gJ_new[3 * wk + 1] = gyn; w.gJ_new[3 * wk + 2] = gzn; }
   }
   inverse_line_body(s, w, wk, e);
+  if (s.screened()) screen_list_body(s, w, wk, e);
 }
 
 template <typename T> struct Vec16;
@@ -575,6 +632,7 @@ __device__ void accept_prep_body(const SysDev& s, const WalkDev& w, int wk, int 
   const double dJ = block_sum_mv(jn - jo, red);
   if (tid == 0) w.dJ[wk] = dJ;
   inverse_line_body(s, w, wk, e2);
+  if (s.screened()) screen_list_body(s, w, wk, e2);
 }
 
 }  // namespace qmc

@@ -133,6 +133,8 @@ struct OzArgs {
   const int8_t* B; long b_plane; const int* eb;                       // B tiles, exponents [N]
   double* C; int c_grp; long c_gs; long ldc;                          // C row m at (m/grp)*gs + (m%grp)*ldc
   void* C2; int c2_bf16;                                              // optional FP32 / BF16 copy
+  double* CT; long ct_gs; long ct_ld;                                 // optional transposed FP64 copy:
+                                                                      // C[m][n] at (m/grp)*ct_gs + n*ct_ld + m%grp
   const uint8_t* kmask; int kmask_ld;                                 // nonzero 16 x 64 tiles of B^T
 };
 
@@ -301,6 +303,7 @@ __global__ void __launch_bounds__(256) ozaki_gemm_kernel(OzArgs g, int gx, int g
           if (g.c2_bf16) ((bf16s*)g.C2)[off] = bf16s(v);
           else ((float*)g.C2)[off] = (float)v;
         }
+        if (g.CT) g.CT[(long)(gm / g.c_grp) * g.ct_gs + (long)gn * g.ct_ld + (gm % g.c_grp)] = v;
       }
     }
   }
@@ -345,10 +348,10 @@ long oz_phi_bytes(const SysDev& s, long Wk) {
 // P halves (bit 0: up rows, bit 1: down rows) from the FP64 basis rows in
 // phi64: digits of those rows first (oz_phi: up tiles, then down tiles; with
 // have_expo the rows' exponents in oz_ephi are already set), then the
-// products; P64 gets the FP64 result and, when lo is given, its FP32 / BF16
-// copy.
+// products; P64 gets the FP64 result, lo (if given) its FP32 / BF16 copy and PT
+// (if given) its transpose per walker, PT[w][mu][i].
 hipError_t launch_P_build_oz(const SysDev& s, const WalkDev& w, int halves, const double* phi64, double* P64,
-                             void* lo, bool lo_bf16, hipStream_t st, bool have_expo) {
+                             void* lo, bool lo_bf16, hipStream_t st, bool have_expo, double* PT) {
   const long rowst = (long)s.N * s.Lp;
   const long planeB = oz_plane_bytes(s.Lp, s.Lp);
   const int mask_ld = (s.Lp + kLamTileN - 1) / kLamTileN;
@@ -374,6 +377,11 @@ hipError_t launch_P_build_oz(const SysDev& s, const WalkDev& w, int halves, cons
     if (lo) {
       g.C2 = lo_bf16 ? (void*)((bf16s*)lo + r0) : (void*)((float*)lo + r0);
       g.c2_bf16 = lo_bf16 ? 1 : 0;
+    }
+    if (PT) {   // PT[w][mu][i] for every electron i of walker w (this half: i = i0 + m % n)
+      g.CT = PT + (h == 0 ? 0 : s.nu);
+      g.ct_gs = (long)s.Lp * s.N;
+      g.ct_ld = s.N;
     }
     g.kmask = h == 0 ? s.lam_mask : s.lamT_mask;
     g.kmask_ld = mask_ld;

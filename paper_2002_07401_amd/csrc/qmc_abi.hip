@@ -208,8 +208,11 @@ extern "C" qmc_status qmc_system_create(const qmc_system_desc* desc, qmc_system*
     if (q.n_up > q.n_dn && !q.unpaired) return fail(QMC_ERR_ARG, "n_up > n_dn needs the unpaired orbitals");
   }
   if (q.n_up > kBigMaxN) return fail(QMC_ERR_UNSUPPORTED, "n_up > 1024 is not built");
-  if (q.precision < QMC_FP64 || q.precision > QMC_MIXED_BF16)
+  if (q.precision < QMC_FP64 || q.precision > QMC_REFINED || q.precision == QMC_W_BF16 ||
+      q.precision == QMC_W_FP8)
     return fail(QMC_ERR_UNSUPPORTED, "precision not built");
+  if (q.precision == QMC_REFINED && (pf || q.n_up != q.n_dn))
+    return fail(QMC_ERR_UNSUPPORTED, "QMC_REFINED is built for paired determinant systems (n_up == n_dn)");
   if (q.refresh_every < 1) return fail(QMC_ERR_ARG, "refresh_every must be >= 1");
   if (q.j1_form < 0 || q.j1_form > 2 || (q.j1_form && !q.j1_b)) return fail(QMC_ERR_ARG, "bad j1");
   if (q.j2_form < 0 || q.j2_form > 2) return fail(QMC_ERR_ARG, "bad j2 form");
@@ -415,12 +418,12 @@ extern "C" qmc_status qmc_system_create(const qmc_system_desc* desc, qmc_system*
     for (int l = 0; l < d.nk; ++l)
       for (int mu = 0; mu < L; ++mu) uph[(size_t)l * Lp + mu] = q.unpaired[(size_t)mu * d.nk + l];
     e = up((void**)&d.Uph, uph.data(), sizeof(double) * uph.size());
-    if (!e && q.precision != QMC_FP64) {
+    if (!e && d.f32()) {
       std::vector<float> u32(uph.begin(), uph.end());
       e = up((void**)&d.Uph32, u32.data(), sizeof(float) * u32.size());
     }
     if (!e) {
-      if (q.precision == QMC_FP64) {
+      if (!d.f32()) {
         d.UphS = d.Uph;
       } else if (q.precision == QMC_MIXED_BF16) {
         void* u16 = nullptr;
@@ -436,7 +439,7 @@ extern "C" qmc_status qmc_system_create(const qmc_system_desc* desc, qmc_system*
       }
     }
   }
-  if (!e && q.precision != QMC_FP64) {
+  if (!e && d.f32()) {
     std::vector<float> l32(lam.begin(), lam.end()), lT32(lamT.begin(), lamT.end());
     e = up((void**)&d.lam32, l32.data(), sizeof(float) * l32.size());
     if (!e) e = up((void**)&d.lamT32, lT32.data(), sizeof(float) * lT32.size());
@@ -449,7 +452,7 @@ extern "C" qmc_status qmc_system_create(const qmc_system_desc* desc, qmc_system*
     if (!e) e = launch_lam_mask(d, nullptr);
     if (!e) e = hipStreamSynchronize(nullptr);
   }
-  if (!e && d.refined() && !pf) {
+  if (!e && (d.refined() || d.screened()) && !pf) {
     // int8 digits of Lambda for the error-free P products of the evaluation
     d.oz_s = kOzSlices;
     const size_t plane = (size_t)oz_plane_bytes(Lp, Lp);
@@ -529,10 +532,17 @@ static void walker_layout(const SysDev& s, int n_walkers, bool adjoint, Carver& 
   if (s.refined()) {
     c.take(&d.phi64, sizeof(double) * Wk * N * s.Lp);
     c.take(&d.P64, sizeof(double) * Wk * N * s.Lp);
-    if (s.oz_s > 0) {
-      c.take(&d.oz_phi, (size_t)oz_phi_bytes(s, (long)Wk));
-      c.take(&d.oz_ephi, sizeof(int) * Wk * N);
-    }
+  }
+  if ((s.refined() || s.screened()) && s.oz_s > 0) {
+    c.take(&d.oz_phi, (size_t)oz_phi_bytes(s, (long)Wk));
+    c.take(&d.oz_ephi, sizeof(int) * Wk * N);
+  }
+  if (s.screened()) {
+    c.take(&d.PT, sizeof(double) * Wk * N * s.Lp);
+    c.take(&d.cmax, sizeof(double) * Wk * 2 * s.Lp);
+    c.take(&d.muk, sizeof(int) * Wk * s.Lp);
+    c.take(&d.psk, sizeof(double) * Wk * s.Lp);
+    c.take(&d.nkeep, sizeof(int) * Wk);
   }
   if (s.nu > kLuRowMax) {
     const size_t np = s.np;
@@ -726,7 +736,8 @@ extern "C" qmc_status qmc_eval_batch(qmc_system* sys, qmc_walkers* wk, const dou
   }
   // the FP32 / BF16 copies of Phi and P are written by the producing kernels
   // the int8 digits of the refined products take their row scales from here
-  int* ephi = (refine && s.oz_s > 0 && s.Lq == 0) ? d.oz_ephi : nullptr;
+  const bool oz = (refine || s.screened()) && s.oz_s > 0;
+  int* ephi = (oz && s.Lq == 0) ? d.oz_ephi : nullptr;
   TIMED(wk, QMC_T_BASIS, stream, launch_basis_values(se, de, stream, refine ? d.phi : nullptr, s.bf16(), ephi),
         "basis");
   if (s.pairing) {
@@ -735,11 +746,16 @@ extern "C" qmc_status qmc_eval_batch(qmc_system* sys, qmc_walkers* wk, const dou
     TIMED(wk, QMC_T_LU, stream, launch_pf_factor(s, d, stream), "Pfaffian and inverse");
     TIMED(wk, QMC_T_Y_BUILD, stream, launch_pf_Y_build(s, d, stream), "Pfaffian Y build");
   } else {
-  if (refine && s.oz_s > 0) {
+  if (oz) {
     // reduced-precision digits on the int8 matrix cores, refined to the FP64
-    // product (see ozaki.hip); the moves' FP32 / BF16 rows are written beside
+    // product (see ozaki.hip); the moves' FP32 / BF16 rows (refined modes) or
+    // the transposed rows of the screened proposals are written beside
     TIMED(wk, QMC_T_P_BUILD, stream,
-          launch_P_build_oz(s, d, 3, d.phi64, d.P64, d.P, s.bf16(), stream, ephi != nullptr), "P build");
+          launch_P_build_oz(s, d, 3, de.phi == d.phi64 ? d.phi64 : (const double*)d.phi,
+                            refine ? d.P64 : (double*)d.P, refine ? d.P : nullptr, s.bf16(), stream,
+                            ephi != nullptr, s.screened() ? d.PT : nullptr),
+          "P build");
+    if (s.screened()) TIMED(wk, QMC_T_OTHER, stream, launch_screen_colmax(s, d, 3, stream), "column maxima");
   } else {
     TIMED(wk, QMC_T_P_BUILD, stream, launch_P_build(se, de, 3, stream, refine ? d.P : nullptr, s.bf16()),
           "P build");
@@ -770,14 +786,24 @@ extern "C" qmc_status qmc_eval_batch(qmc_system* sys, qmc_walkers* wk, const dou
 }
 
 // P rows of the spin opposite to electron e must match the current basis rows.
+static hipError_t rebuild_P(const SysDev& s, const WalkDev& d, int halves, hipStream_t stream) {
+  if (!s.screened()) return launch_P_build(s, d, halves, stream);
+  // refined int8 products from the FP64 rows the accepts maintain, with the
+  // transposed rows and column maxima of the screened proposals
+  hipError_t e = launch_P_build_oz(s, d, halves, (const double*)d.phi, (double*)d.P, nullptr, false, stream, false,
+                                   d.PT);
+  if (e == hipSuccess) e = launch_screen_colmax(s, d, halves, stream);
+  return e;
+}
+
 static qmc_status ensure_P(qmc_walkers* wk, int e, hipStream_t stream) {
   const SysDev& s = wk->sys->d;
   const bool up = e < s.nu;
   if (up && !wk->P_dn_valid) {
-    TIMED(wk, QMC_T_P_REBUILD, stream, launch_P_build(s, wk->d, 2, stream), "P_dn rebuild");
+    TIMED(wk, QMC_T_P_REBUILD, stream, rebuild_P(s, wk->d, 2, stream), "P_dn rebuild");
     wk->P_dn_valid = true;
   } else if (!up && !wk->P_up_valid) {
-    TIMED(wk, QMC_T_P_REBUILD, stream, launch_P_build(s, wk->d, 1, stream), "P_up rebuild");
+    TIMED(wk, QMC_T_P_REBUILD, stream, rebuild_P(s, wk->d, 1, stream), "P_up rebuild");
     wk->P_up_valid = true;
   }
   return QMC_OK;
@@ -812,7 +838,10 @@ extern "C" qmc_status qmc_propose_move(qmc_system* sys, qmc_walkers* wk, int32_t
 {
     hipEvent_t ea, eb;
     HIP_TRY(wk->tm.begin_ext(QMC_T_PROPOSE, &ea, &eb), "timer begin");
-    HIP_TRY(launch_propose_rows(s, wk->d, electron, ratio, drift_new, true, stream, ea, eb), "propose rows");
+    if (s.screened() && !drift_new)
+      HIP_TRY(launch_propose_screened(s, wk->d, electron, ratio, true, stream, ea, eb), "screened proposal");
+    else
+      HIP_TRY(launch_propose_rows(s, wk->d, electron, ratio, drift_new, true, stream, ea, eb), "propose rows");
   }
   wk->pending_e = electron;
   return QMC_OK;
@@ -992,7 +1021,10 @@ extern "C" qmc_status qmc_vmc_steps(qmc_system* sys, qmc_walkers* wk, int32_t e_
 {
       hipEvent_t ea, eb;
       HIP_TRY(wk->tm.begin_ext(QMC_T_PROPOSE, &ea, &eb), "timer begin");
-      HIP_TRY(launch_propose_rows(s, wk->d, e, nullptr, nullptr, false, stream, ea, eb), "propose rows");
+      if (s.screened())
+        HIP_TRY(launch_propose_screened(s, wk->d, e, nullptr, false, stream, ea, eb), "screened proposal");
+      else
+        HIP_TRY(launch_propose_rows(s, wk->d, e, nullptr, nullptr, false, stream, ea, eb), "propose rows");
     }
     const int e2 = (int)((e_start + (long)t + 1) % s.N);
     prepped = t + 1 < n_steps && fusable(wk, e, e2);
@@ -1042,6 +1074,10 @@ extern "C" qmc_status qmc_walkers_read(qmc_walkers* wk, int32_t item, double* ds
       HIP_TRY(launch_export_phi(s, d, dst, stream), "export phi");
       return QMC_OK;
     case QMC_STATE_RESIDUAL: src = wk->res_v; bytes = sizeof(double) * Wk; break;
+    case QMC_STATE_KEPT:
+      if (!s.screened()) return fail(QMC_ERR_ARG, "QMC_STATE_KEPT needs a QMC_REFINED system");
+      HIP_TRY(launch_export_kept(d, dst, stream), "export kept counts");
+      return QMC_OK;
     default: return fail(QMC_ERR_ARG, "unknown state item");
   }
   HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, stream), "read state");
@@ -1333,6 +1369,7 @@ extern "C" qmc_status qmc_multi_create(int32_t n_members, qmc_system* const* sys
     if (s.LJ > 0) { delete m; return fail(QMC_ERR_UNSUPPORTED, "members with a Jastrow basis are not built"); }
     if (s.Lq > 0) { delete m; return fail(QMC_ERR_UNSUPPORTED, "members with contracted orbitals are not built"); }
     if (s.pairing) { delete m; return fail(QMC_ERR_UNSUPPORTED, "Pfaffian members are not built"); }
+    if (s.screened()) { delete m; return fail(QMC_ERR_UNSUPPORTED, "QMC_REFINED members are not built"); }
     m->sys.push_back(systems[k]);
     m->wk.push_back(walkers[k]);
     m->h_sys.push_back(s);

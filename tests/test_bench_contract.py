@@ -48,3 +48,21 @@ def test_step_rooflines_arithmetic():
     assert abs(r["P_build"]["achieved"] - 2.0 * L * L * N * 1024 / 3.0e-3 / 1e12) < 0.01
     assert abs(r["LU"]["achieved"] - 2.0 * n ** 3 * 1024 / 0.3e-3 / 1e12) < 0.01
     assert r["propose"]["frac"] == 0.75
+
+
+def test_screened_and_refined_counts_160e():
+    """Screened proposals (QMC_REFINED) stream only the kept basis functions:
+    kept columns of n FP64 values plus their index and value (12 bytes each),
+    the inverse column and the new row (16 n).  The refined products count the
+    int8 operations of the 28 digit products (7 digits per FP64 row, pairs
+    a + b < 7) over L rounded up to 32 (608 at L = 600)."""
+    s = C.mol_40nuc_160e(n_walkers=4).system
+    Wk, L, n, N = 1024, 600, 80, 160
+    m = bench.kernel_models(s, Wk, 8, 0.74, kept=144.0)
+    assert m["propose"] == ("hbm", Wk * (144.0 * (8 * n + 12) + 16 * n))
+    one = {"P_build": (2.0, 1)}
+    prop = {"bound": "hbm", "achieved": 1.0, "peak": 8000.0, "unit": "GB/s", "frac": 0.0, "avg_launch_us": 1.0}
+    r = bench.step_rooflines(s, Wk, "mixed", one, prop)
+    ops = 2.0 * 608 * 608 * N * Wk * 28
+    assert r["P_build"]["unit"] == "TOP/s" and r["P_build"]["peak"] == 5000.0
+    assert abs(r["P_build"]["achieved"] - ops / 2.0e-3 / 1e12) < 0.01
