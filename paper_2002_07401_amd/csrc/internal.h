@@ -390,13 +390,16 @@ __device__ __forceinline__ double angular_value(int kind, double x, double y, do
 
 // Function mu of a basis table (packed centre + zeta, kind) at point
 // (px,py,pz): value only.  One packed record per function (one round trip).
-__device__ __forceinline__ double basis_value_tab(const double4* __restrict__ bfn, const int* __restrict__ kinds,
-                                                  int mu, double px, double py, double pz) {
-  const double4 f = bfn[mu];
+// The value from the function's record f and kind k (already loaded).
+__device__ __forceinline__ double basis_value_rec(const double4& f, int k, double px, double py, double pz) {
   const double x = px - f.x, y = py - f.y, z = pz - f.z;
   const double r2 = x * x + y * y + z * z;
-  const int k = kinds[mu];
   return angular_value(kind_ang(k), x, y, z) * radial_e(k, f.w, r2);
+}
+
+__device__ __forceinline__ double basis_value_tab(const double4* __restrict__ bfn, const int* __restrict__ kinds,
+                                                  int mu, double px, double py, double pz) {
+  return basis_value_rec(bfn[mu], kinds[mu], px, py, pz);
 }
 
 __device__ __forceinline__ double basis_value(const SysDev& s, int mu, double px, double py, double pz) {
@@ -573,9 +576,11 @@ hipError_t launch_propose_rows(const SysDev& s, const WalkDev& w, int e, double*
 hipError_t launch_metropolis_accept(const SysDev& s, const WalkDev& w, int e, const double* unif,
                                     int32_t* accept_count, hipStream_t st);
 // Metropolis accept of e fused with the set-up of the next proposal (electron
-// e2, displacements disp2 [Wk][3]); needs s.Lp <= kFuseMaxLp.
+// e2, displacements disp2 [Wk][3]); needs s.Lp <= kFuseMaxLp.  since: the
+// attempted moves since the last refresh (a bound on the buffered updates).
 hipError_t launch_metropolis_accept_prep(const SysDev& s, const WalkDev& w, int e, const double* unif,
-                                         int32_t* accept_count, int e2, const double* disp2, hipStream_t st);
+                                         int32_t* accept_count, int e2, const double* disp2, int since,
+                                         hipStream_t st);
 hipError_t launch_accept(const SysDev& s, const WalkDev& w, int e, const uint8_t* acc,
                          hipStream_t st);
 hipError_t launch_refresh_finish(const SysDev& s, const WalkDev& w, int32_t* status, hipStream_t st);

@@ -284,6 +284,395 @@ hipError_t launch_propose_screened(const SysDev& s, const WalkDev& w, int e, dou
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Metropolis accept of e fused with the set-up of e2, staged through LDS.
+// The same arithmetic in the same order as accept_prep_body (so chains are
+// bitwise those of the unstaged kernel and of the multi-system launches), but
+// every input the workgroup reads is requested at once at the start: the
+// delayed-update buffers V and D (rows below mc), S^{-1} and the positions go
+// global -> LDS by direct copies (no registers held), while the basis records
+// of psi(r'), the nuclei of the one-body Jastrow, the new and old W line, v0
+// and z of the pending proposal, A0's line of e2, psi(r') of the pending
+// proposal and the column maxima of the screened proposals go to registers.
+// psi(r') of e2 is computed while the copies are in flight.  The unstaged
+// kernel walks a chain of some fifteen dependent global round trips per
+// walker; this one, one.
+// mc bounds the buffered moves: at the accept of an attempt, wm <= the
+// attempts since the last refresh (both restart together, wm grows by at
+// most one per attempt), which the host passes.  A walker with more (not
+// reachable through the move calls) reads the buffers from global memory.
+// LDS: V, D [(mc+1) n], S^{-1} [(mc+1) kb], r [3 N] (each padded to 1 KiB,
+// the copy granule), psi(r') of e2 [Lp], three n-vectors, five kb-vectors.
+// ---------------------------------------------------------------------------
+constexpr int kStageMaxN = 128;    // n <= 128 (one W entry per thread)
+constexpr int kStageMaxNe = 256;   // electrons
+constexpr int kStageMaxNuc = 256;  // nuclei (one per thread)
+constexpr int kStageQL = (kFuseMaxLp + 255) / 256;
+constexpr int kStageMaxSplits = (kStageMaxN + kPropRowsMin - 1) / kPropRowsMin;   // partial ratios
+constexpr size_t kStageMaxLds = 63 * 1024;   // dynamic LDS (the static arrays take the rest of 64 KiB)
+
+__host__ __device__ inline size_t pad1k(size_t b) { return (b + 1023) & ~(size_t)1023; }
+
+struct StageLayout {
+  size_t V, D, S, r, psi, vec, total;   // byte offsets of the regions and the size
+};
+__host__ __device__ inline StageLayout stage_layout(int n, int kb, int N, int Lp, int mc) {
+  StageLayout o;
+  o.V = 0;
+  o.D = o.V + pad1k(sizeof(double) * (size_t)(mc + 1) * n);
+  o.S = o.D + pad1k(sizeof(double) * (size_t)(mc + 1) * n);
+  o.r = o.S + pad1k(sizeof(double) * (size_t)(mc + 1) * kb);
+  o.psi = o.r + pad1k(sizeof(double) * 3 * (size_t)N);
+  o.vec = o.psi + sizeof(double) * (size_t)Lp;
+  o.total = o.vec + sizeof(double) * (3 * (size_t)n + 5 * (size_t)kb);
+  return o;
+}
+
+// bytes (a multiple of 8) from global src to LDS dst in 1 KiB granules, 16
+// bytes per lane (global_load_lds): granule j by wave j mod the wave count.
+// Lanes past the end re-read src's first 16 bytes into dst's padding.
+__device__ __forceinline__ void lds_copy_async(void* dst, const void* src, int bytes) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const char* s = (const char*)src;
+  char* d = (char*)dst;
+  const int nch = (bytes + 1023) >> 10;
+  for (int j = wave; j < nch; j += nw) {
+    const int off = (j << 10) + 16 * lane;
+    const char* p = off < bytes ? s + off : s;
+    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)p,
+                                     (__attribute__((address_space(3))) void*)(d + (j << 10)), 16, 0, 0);
+  }
+}
+
+// Prefetched per-thread inputs of the staged kernel.
+struct StagePre {
+  double4 bf[kStageQL];   // basis records of mu = tid + 256 q
+  int bk[kStageQL];
+  double xp[kStageQL];    // psi(r') of the pending proposal (the accepted row)
+  double xc[kStageQL];    // column maxima of the rows e2's proposal streams (screened)
+  double nx, ny, nz, nZ, nb;   // nucleus tid (one-body Jastrow)
+  double wn, Wo, v0, a0, z;    // new W entry, old one, v0, A0's line of e2, z (thread = index)
+};
+
+// jastrow_one with nucleus tid's record prefetched, the positions and the
+// two-body parameters (j2p, the eight of s.j2d) in LDS.
+__device__ __forceinline__ double jastrow_staged(const SysDev& s, const double* r, int e, double px, double py,
+                                                 double pz, const StagePre& q, const double* j2p) {
+  double val = 0.0;
+  const int tid = threadIdx.x;
+  if (s.j1_form) {
+    if (tid < s.n_nuc) {
+      const double dx = px - q.nx, dy = py - q.ny, dz = pz - q.nz;
+      const double ria = sqrt(dx * dx + dy * dy + dz * dz);
+      double f, f1, f2;
+      j1_radial(s.j1_form, q.nZ, q.nb, ria, f, f1, f2);
+      val += f;
+    }
+  }
+  if (s.j2_form) {
+    const bool up_e = e < s.nu;
+    for (int j = tid; j < s.N; j += blockDim.x) {
+      if (j == e) continue;
+      const double dx = px - r[3 * j], dy = py - r[3 * j + 1], dz = pz - r[3 * j + 2];
+      const double rij = sqrt(dx * dx + dy * dy + dz * dz);
+      double v, v1, v2;
+      j2_radial(s.j2_form, j2p, up_e == (j < s.nu), rij, v, v1, v2);
+      val += v;
+    }
+  }
+  return val;
+}
+
+template <typename T, bool STAGED, int QL>
+__device__ void accept_prep_staged_body(const SysDev& s, const WalkDev& w, int wk, int e, double u,
+                                        int32_t* __restrict__ cnt, int cnt0, int S, int e2, double px, double py,
+                                        double pz, double R, double dJ, int m, int mc, char* lds, const StagePre& q,
+                                        const double* j2p, double la, double sg, double jv, double rx, double ry,
+                                        double rz) {
+  __shared__ double red[16];
+  __shared__ double gam_s;
+  __shared__ int wcount[4];
+  __shared__ int total;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  const int n = s.nu, kb = w.kb, N = s.N, L = s.L, Lp = s.Lp;
+  const bool up = e < n;
+  const int ie = up ? e : e - n;
+  const StageLayout ly = stage_layout(n, kb, N, Lp, mc);
+  double* Vl = (double*)(lds + ly.V);
+  double* Dl = (double*)(lds + ly.D);
+  double* Sl = (double*)(lds + ly.S);
+  double* rl = (double*)(lds + ly.r);
+  double* sps = (double*)(lds + ly.psi);
+  double* sd = (double*)(lds + ly.vec);
+  double* sv0 = sd + n;
+  double* cvl = sv0 + n;
+  double* zo = cvl + n;
+  double* sr = zo + kb;
+  double* sy = sr + kb;
+  double* st = sy + kb;
+  double* sz = st + kb;
+  double* Vg = w.wv + (long)wk * kb * n;
+  double* Dg = w.wd + (long)wk * kb * n;
+  double* Sg = w.wS + (long)wk * kb * kb;
+  const double* Vr = STAGED ? Vl : Vg;
+  const double* Dr = STAGED ? Dl : Dg;
+  double* Sr = STAGED ? Sl : Sg;
+
+  // the accept of e (accept_body, Metropolis mode)
+  const double ratio = R * exp(dJ);
+  const bool acc = m < kb && u < ratio * ratio;
+  if (tid == 0) {
+    w.rdet[wk] = R;
+    w.ratio[wk] = ratio;
+    w.acc[wk] = acc ? 1 : 0;
+  }
+  if (acc) {
+    double p0 = 0.0;
+    if (tid < n) {
+      const double d = q.wn - q.Wo;
+      sd[tid] = d;
+      p0 += d * q.v0;
+      Dg[(long)m * n + tid] = d;
+      Vg[(long)m * n + tid] = q.v0;
+      if (STAGED) { Dl[(long)m * n + tid] = d; Vl[(long)m * n + tid] = q.v0; }
+    }
+    p0 = wave_sum(p0);
+    if (lane == 0) red[wave] = p0;
+    __syncthreads();
+    rows_dot_lds(Vr, n, m, n, sd, sr);           // r_i = delta . v_i
+    __syncthreads();
+    if (tid == 0) {
+      double dv = 0.0;
+      for (int k = 0; k < nw; ++k) dv += red[k];
+      double rzs = 0.0;
+      for (int i = 0; i < m; ++i) rzs += sr[i] * zo[i];
+      gam_s = 1.0 + dv - rzs;
+    }
+    for (int k = tid; k < m; k += blockDim.x) {
+      double y = 0.0;
+      for (int i = 0; i < m; ++i) y += Sr[i * kb + k] * sr[i];
+      sy[k] = y;
+    }
+    __syncthreads();
+    const double ig = 1.0 / gam_s;
+    for (int idx = tid; idx < (m + 1) * (m + 1); idx += blockDim.x) {
+      const int i = idx / (m + 1), k = idx % (m + 1);
+      double v;
+      if (i < m && k < m) v = Sr[i * kb + k] + zo[i] * sy[k] * ig;
+      else if (i < m) v = -zo[i] * ig;
+      else if (k < m) v = -sy[k] * ig;
+      else v = ig;
+      Sr[i * kb + k] = v;
+      if (STAGED) Sg[i * kb + k] = v;
+    }
+    if (tid < n) {
+      double* Ww = w.W + (long)wk * n * n;
+      if (up) Ww[(long)ie * n + tid] = q.wn;
+      else Ww[(long)tid * n + ie] = q.wn;
+    }
+    T* prow = (T*)w.phi + ((long)wk * N + e) * Lp;
+#pragma unroll
+    for (int k = 0; k < QL; ++k) {
+      const int mu = tid + 256 * k;
+      if (mu < L) prow[mu] = (T)q.xp[k];
+    }
+    if (tid == 0) {
+      w.wm[wk] = m + 1;
+      double* re = w.r + ((long)wk * N + e) * 3;
+      re[0] = rx; re[1] = ry; re[2] = rz;
+      rl[3 * e] = rx; rl[3 * e + 1] = ry; rl[3 * e + 2] = rz;
+      w.logabs[wk] = la + (log(fabs(R)) + dJ);
+      if (R < 0.0) w.sign[wk] = -sg;
+      w.J[wk] = jv + dJ;
+      if (cnt) cnt[0] = cnt0 + 1;
+    }
+  }
+  __syncthreads();
+
+  // the set-up of e2: psi(r'), r', the Jastrow change
+  double* psi = w.psi_new + (long)wk * Lp;
+  for (int mu = tid; mu < Lp; mu += blockDim.x) psi[mu] = mu < L ? sps[mu] : 0.0;
+  if (tid < 3) w.r_new[3 * wk + tid] = tid == 0 ? px : (tid == 1 ? py : pz);
+  const double jn = jastrow_staged(s, rl, e2, px, py, pz, q, j2p);
+  const double jo = jastrow_staged(s, rl, e2, rl[3 * e2], rl[3 * e2 + 1], rl[3 * e2 + 2], q, j2p);
+  const double dJ2 = block_sum_mv(jn - jo, red);
+  if (tid == 0) w.dJ[wk] = dJ2;
+
+  // the current inverse's line of e2 (inverse_line_body)
+  double* v0g = w.v0 + (long)wk * n;
+  double* cv = w.cvec + (long)wk * n;
+  if (tid < n) v0g[tid] = sv0[tid];
+  const int m2 = acc ? m + 1 : m;
+  if (m2 == 0) {
+    if (tid < n) { cv[tid] = sv0[tid]; cvl[tid] = sv0[tid]; }
+  } else {
+    double* tz = w.tz + (long)wk * 2 * kb;
+    rows_dot_lds(Dr, n, m2, n, sv0, st);        // t = D^T v0
+    __syncthreads();
+    rows_dot_lds(Sr, kb, m2, m2, st, sz);       // z = S^{-1} t
+    __syncthreads();
+    for (int i = tid; i < m2; i += blockDim.x) {
+      tz[i] = st[i];
+      tz[kb + i] = sz[i];
+    }
+    if (tid < n) {
+      double c = sv0[tid];
+      for (int i = 0; i < m2; ++i) c -= sz[i] * Vr[(long)i * n + tid];
+      cv[tid] = c;
+      cvl[tid] = c;
+    }
+  }
+  if (!s.screened()) return;
+
+  // screened proposals of e2 (screen_list_body)
+  __syncthreads();
+  double c1 = 0.0;
+  for (int j = tid; j < n; j += blockDim.x) c1 += fabs(cvl[j]);
+  c1 = block_sum_mv(c1, red);
+  const double thr = (c1 > 0.0) ? kScreenTol / ((double)L * c1) : 0.0;
+  int* mk = w.muk + (long)wk * Lp;
+  double* pk = w.psk + (long)wk * Lp;
+  if (tid == 0) total = 0;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < QL; ++k) {
+    const int base = 256 * k;
+    if (base >= L) break;
+    const int mu = base + tid;
+    double v = 0.0;
+    bool keep = false;
+    if (mu < L) {
+      v = sps[mu];
+      keep = fabs(v) * q.xc[k] > thr;
+    }
+    const unsigned long long b = __ballot(keep);
+    if (lane == 0) wcount[wave] = __popcll(b);
+    __syncthreads();
+    int off = total;
+    for (int k2 = 0; k2 < wave; ++k2) off += wcount[k2];
+    if (keep) {
+      const int at = off + __popcll(b & ((1ull << lane) - 1ull));
+      mk[at] = mu;
+      pk[at] = v;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int t = total;
+      for (int k2 = 0; k2 < nw; ++k2) t += wcount[k2];
+      total = t;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) w.nkeep[wk] = total;
+}
+
+template <typename T, int QL>
+__global__ void __launch_bounds__(256)
+accept_prep_staged_kernel(SysDev s, WalkDev w, int e, const double* __restrict__ unif,
+                          int32_t* __restrict__ accept_count, int S, int e2, const double* __restrict__ disp2,
+                          int mc) {
+  extern __shared__ __align__(16) char lds[];
+  __shared__ double scal[kStageMaxSplits + 22];
+  __shared__ int ints_s[2];
+  const int wk = blockIdx.x, tid = threadIdx.x;
+  const int n = s.nu, kb = w.kb, N = s.N, L = s.L, Lp = s.Lp;
+  const bool up = e < n, up2 = e2 < n;
+  const int ie = up ? e : e - n, ie2 = up2 ? e2 : e2 - n;
+  const StageLayout ly = stage_layout(n, kb, N, Lp, mc);
+  // bulk copies first
+  lds_copy_async(lds + ly.V, w.wv + (long)wk * kb * n, 8 * mc * n);
+  lds_copy_async(lds + ly.D, w.wd + (long)wk * kb * n, 8 * mc * n);
+  lds_copy_async(lds + ly.S, w.wS + (long)wk * kb * kb, 8 * mc * kb);
+  lds_copy_async(lds + ly.r, w.r + (long)wk * N * 3, 8 * 3 * N);
+  // per-thread loads, every address valid (indices past the ends read element 0)
+  StagePre q;
+#pragma unroll
+  for (int k = 0; k < QL; ++k) {
+    const int mu = tid + 256 * k, mc0 = mu < L ? mu : 0;
+    q.bf[k] = s.bfn[mc0];
+    q.bk[k] = s.kind[mc0];
+  }
+  {
+    const int a = tid < s.n_nuc ? tid : 0;
+    q.nx = s.R[3 * a]; q.ny = s.R[3 * a + 1]; q.nz = s.R[3 * a + 2];
+    q.nZ = s.Z[a];
+    q.nb = s.j1_b[a];
+  }
+  {
+    const int j = tid < n ? tid : 0;
+    const double* Ww = w.W + (long)wk * n * n;
+    const double* A0 = w.A + (long)wk * n * n;
+    q.wn = w.w_new[(long)wk * n + j];
+    q.Wo = up ? Ww[(long)ie * n + j] : Ww[(long)j * n + ie];
+    q.v0 = w.v0[(long)wk * n + j];
+    q.a0 = up2 ? A0[(long)j * n + ie2] : A0[(long)ie2 * n + j];
+    q.z = w.tz[(long)wk * 2 * kb + kb + (tid < kb ? tid : 0)];
+  }
+  const double* pn = w.psi_new + (long)wk * Lp;
+  const double* cm = s.screened() ? w.cmax + ((long)wk * 2 + (up2 ? 1 : 0)) * Lp : pn;
+#pragma unroll
+  for (int k = 0; k < QL; ++k) {
+    const int mu = tid + 256 * k, mc0 = mu < L ? mu : 0;
+    q.xp[k] = pn[mc0];
+    q.xc[k] = cm[mc0];
+  }
+  // the walker's scalars, one per thread, through LDS: the S partial ratios
+  // (threads 0..S-1), then dJ, log|Psi|, sign, J, u, the displacement of e2,
+  // r' of e and r of e2 and the eight two-body parameters (wave 1), the
+  // buffered-move and accept counts.  Loads first, unconditionally (every
+  // address valid), stores after.
+  const double pv = w.rdet_part[(long)wk * S + (tid < S ? tid : 0)];
+  const int t2 = tid - 64;
+  const double* sp;
+  switch (t2) {
+    case 0: sp = w.dJ + wk; break;
+    case 1: sp = w.logabs + wk; break;
+    case 2: sp = w.sign + wk; break;
+    case 3: sp = w.J + wk; break;
+    case 4: sp = unif + wk; break;
+    case 5: case 6: case 7: sp = disp2 + 3 * (long)wk + (t2 - 5); break;
+    case 8: case 9: case 10: sp = w.r_new + 3 * (long)wk + (t2 - 8); break;
+    case 11: case 12: case 13: sp = w.r + ((long)wk * N + e2) * 3 + (t2 - 11); break;
+    case 14: case 15: case 16: case 17: case 18: case 19: case 20: case 21: sp = s.j2d + (t2 - 14); break;
+    default: sp = w.dJ + wk; break;
+  }
+  const double sv_ = *sp;
+  const int mv = w.wm[wk];
+  const int cv_ = accept_count ? accept_count[wk] : 0;
+  if (tid < S) scal[tid] = pv;
+  if (t2 >= 0 && t2 < 22) scal[kStageMaxSplits + t2] = sv_;
+  if (tid == 128) { ints_s[0] = mv; ints_s[1] = cv_; }
+  __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this wave's copies landed
+  __syncthreads();
+  double R = 0.0;
+  for (int k = 0; k < S; ++k) R += scal[k];
+  const double* sc = scal + kStageMaxSplits;
+  const double dJ = sc[0], la = sc[1], sg = sc[2], jv = sc[3], u = sc[4];
+  const double rx = sc[8], ry = sc[9], rz = sc[10];
+  const double px = sc[11] + sc[5], py = sc[12] + sc[6], pz = sc[13] + sc[7];
+  const int m = ints_s[0];
+  double* sps = (double*)(lds + ly.psi);
+  double* sv0 = (double*)(lds + ly.vec) + n;
+  double* zo = sv0 + 2 * n;
+  // psi(r') of e2
+#pragma unroll
+  for (int k = 0; k < QL; ++k) {
+    const int mu = tid + 256 * k;
+    const double v = basis_value_rec(q.bf[k], q.bk[k], px, py, pz);
+    if (mu < L) sps[mu] = v;
+  }
+  if (tid < n) sv0[tid] = q.a0;
+  if (tid < kb) zo[tid] = q.z;
+  __syncthreads();
+  int32_t* cnt = accept_count ? accept_count + wk : nullptr;
+  if (m <= mc)
+    accept_prep_staged_body<T, true, QL>(s, w, wk, e, u, cnt, ints_s[1], S, e2, px, py, pz, R, dJ, m, mc, lds, q,
+                                         sc + 14, la, sg, jv, rx, ry, rz);
+  else
+    accept_prep_staged_body<T, false, QL>(s, w, wk, e, u, cnt, ints_s[1], S, e2, px, py, pz, R, dJ, m, mc, lds, q,
+                                          sc + 14, la, sg, jv, rx, ry, rz);
+}
+
 static hipError_t accept_launch(const SysDev& s, const WalkDev& w, int e, const uint8_t* acc,
                                 const double* unif, int32_t* accept_count, int S, hipStream_t st) {
   if (s.nu > kBigMaxN || !w.wv) return hipErrorNotSupported;
@@ -304,10 +693,35 @@ hipError_t launch_metropolis_accept(const SysDev& s, const WalkDev& w, int e, co
 }
 
 hipError_t launch_metropolis_accept_prep(const SysDev& s, const WalkDev& w, int e, const double* unif,
-                                         int32_t* accept_count, int e2, const double* disp2, hipStream_t st) {
+                                         int32_t* accept_count, int e2, const double* disp2, int since,
+                                         hipStream_t st) {
   if (s.nu > kBigMaxN || !w.wv || s.Lp > kFuseMaxLp || e2 == e || s.LJ > 0) return hipErrorNotSupported;
   const int S = propose_splits(s);
   const dim3 grid(w.Wk), blk(256);
+  const int mc = std::max(0, std::min(since, w.kb - 1));
+  const StageLayout ly = stage_layout(s.nu, w.kb, s.N, s.Lp, mc);
+  // the direct copies move 16-byte granules: every walker's V, D, S^{-1} and
+  // positions start 16-byte aligned
+  const bool aligned = ((uintptr_t)w.wv | (uintptr_t)w.wd | (uintptr_t)w.wS | (uintptr_t)w.r) % 16 == 0 &&
+                       ((long)w.kb * s.nu) % 2 == 0 && w.kb % 2 == 0 && s.N % 2 == 0;
+  if (s.nu <= kStageMaxN && s.N <= kStageMaxNe && s.n_nuc <= kStageMaxNuc && S > 0 && S <= kStageMaxSplits &&
+      aligned &&
+      ly.total <= kStageMaxLds) {
+    const int QL = (s.L + 255) / 256;
+#define QMC_STAGED(T, Q) hipLaunchKernelGGL((accept_prep_staged_kernel<T, Q>), grid, blk, ly.total, st, s, w, e, \
+                                            unif, accept_count, S, e2, disp2, mc)
+#define QMC_STAGED_QL(T)                                                                                   \
+  if (QL <= 1) QMC_STAGED(T, 1);                                                                           \
+  else if (QL == 2) QMC_STAGED(T, 2);                                                                      \
+  else if (QL == 3) QMC_STAGED(T, 3);                                                                      \
+  else QMC_STAGED(T, 4);
+    if (s.bf16()) { QMC_STAGED_QL(bf16s) }
+    else if (s.f32()) { QMC_STAGED_QL(float) }
+    else { QMC_STAGED_QL(double) }
+#undef QMC_STAGED_QL
+#undef QMC_STAGED
+    return hipGetLastError();
+  }
   if (s.bf16())
     hipLaunchKernelGGL(accept_prep_kernel<bf16s>, grid, blk, 0, st, s, w, e, unif, accept_count, S, e2, disp2);
   else if (s.f32())

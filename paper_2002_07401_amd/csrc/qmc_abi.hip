@@ -1033,7 +1033,7 @@ extern "C" qmc_status qmc_vmc_steps(qmc_system* sys, qmc_walkers* wk, int32_t e_
       // after_accept, before_propose and ensure_P below launches nothing
       TIMED(wk, QMC_T_ACCEPT, stream,
             launch_metropolis_accept_prep(s, wk->d, e, unif + (long)t * Wk, accept_count, e2,
-                                          disp + (long)(t + 1) * Wk * 3, stream),
+                                          disp + (long)(t + 1) * Wk * 3, wk->since, stream),
             "metropolis + next set-up");
       c = after_accept(wk, e, nullptr, stream);
       if (c) return c;
