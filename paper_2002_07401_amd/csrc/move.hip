@@ -26,6 +26,10 @@
 
 namespace qmc {
 
+constexpr int kStageQL = (kFuseMaxLp + 255) / 256;   // per-thread slots over Lp <= kFuseMaxLp
+__host__ __device__ inline size_t pad1k(size_t b) { return (b + 1023) & ~(size_t)1023; }
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+
 template <bool DRIFT>
 __global__ void __launch_bounds__(256)
 propose_prep_kernel(SysDev s, WalkDev w, int e, const double* __restrict__ r_new_in,
@@ -233,6 +237,98 @@ __global__ void __launch_bounds__(256) propose_screened_kernel(SysDev s, WalkDev
   for (int q = tid; q < S; q += blockDim.x) w.rdet_part[(long)wk * S + q] = q == 0 ? R : 0.0;
 }
 
+// Blocked form of the same sum, for an even row count n: the kept functions
+// are taken FB at a time (FB n a multiple of 128, IPB = FB n / 128 <= 8), and
+// a wave reads a block's FB columns (FB n doubles) with IPB 16-byte loads of
+// all 64 lanes: lane l of load i holds the two rows j, j + 1 of function f
+// with 2 (64 i + l) = f n + j, fixed over the blocks.  The kept list and the
+// inverse line come first (one round), then every wave issues about eight
+// loads at once (8 / IPB blocks), some 32 KiB in flight per walker.  The
+// per-lane sums go to LDS and row j adds its FB x 4 partial sums in a fixed
+// order (waves outer, functions inner).
+template <int IPB>
+__global__ void __launch_bounds__(256) propose_screened_blk_kernel(SysDev s, WalkDev w, int e, int S, int FB) {
+  extern __shared__ __align__(16) char lds[];
+  __shared__ double red[8];
+  const int wk = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const bool up = e < s.nu;
+  const int i0 = up ? s.nu : 0;
+  const int n = up ? s.nd : s.nu;
+  const int Lp = s.Lp;
+  const double* base = w.PT + (long)wk * Lp * s.N + i0;
+  int* lmu = (int*)lds;
+  double* lv = (double*)(lds + pad1k(sizeof(int) * (size_t)Lp));
+  dbl2* part = (dbl2*)((char*)lv + pad1k(sizeof(double) * (size_t)Lp));
+  // the kept list (the whole Lp-long arrays: no wait on the count), c
+  const int* mk = w.muk + (long)wk * Lp;
+  const double* pk = w.psk + (long)wk * Lp;
+  int xm[kStageQL];
+  double xv[kStageQL];
+#pragma unroll
+  for (int k = 0; k < kStageQL; ++k) {
+    const int q = tid + 256 * k, qc = q < Lp ? q : 0;
+    xm[k] = mk[qc];
+    xv[k] = pk[qc];
+  }
+  const int cnt = w.nkeep[wk];
+  const double cj = w.cvec[(long)wk * s.nu + (tid < n ? tid : 0)];
+#pragma unroll
+  for (int k = 0; k < kStageQL; ++k) {
+    const int q = tid + 256 * k;
+    if (q < Lp) { lmu[q] = xm[k]; lv[q] = xv[k]; }
+  }
+  __syncthreads();
+  // this lane's (function, row) of each of its IPB loads
+  int fi[IPB], ji[IPB];
+#pragma unroll
+  for (int i = 0; i < IPB; ++i) {
+    const int el = 2 * (64 * i + lane);
+    fi[i] = el / n;
+    ji[i] = el - fi[i] * n;
+  }
+  dbl2 acc[IPB];
+#pragma unroll
+  for (int i = 0; i < IPB; ++i) acc[i] = dbl2{0.0, 0.0};
+  const int nblk = (cnt + FB - 1) / FB;
+  constexpr int UB = 8 / IPB > 1 ? 8 / IPB : 1;   // blocks per wave in flight (8 loads)
+  for (int b0 = wave; b0 < nblk; b0 += 4 * UB) {
+    dbl2 x[UB][IPB];
+    double vv[UB][IPB];
+#pragma unroll
+    for (int u = 0; u < UB; ++u)
+#pragma unroll
+      for (int i = 0; i < IPB; ++i) {
+        const int kk = (b0 + 4 * u) * FB + fi[i];
+        const bool ok = kk < cnt;
+        const int mu = lmu[ok ? kk : 0];
+        vv[u][i] = ok ? lv[kk] : 0.0;
+        x[u][i] = __builtin_nontemporal_load((const dbl2*)(base + (long)mu * s.N + ji[i]));
+      }
+#pragma unroll
+    for (int u = 0; u < UB; ++u)
+#pragma unroll
+      for (int i = 0; i < IPB; ++i) {
+        acc[i].x += vv[u][i] * x[u][i].x;
+        acc[i].y += vv[u][i] * x[u][i].y;
+      }
+  }
+#pragma unroll
+  for (int i = 0; i < IPB; ++i) part[wave * 64 * IPB + 64 * i + lane] = acc[i];
+  __syncthreads();
+  const double* pd = (const double*)part;
+  double* wn = w.w_new + (long)wk * s.nu;
+  double rp = 0.0;
+  if (tid < n) {
+    double t = 0.0;
+    for (int v = 0; v < 4; ++v)
+      for (int f = 0; f < FB; ++f) t += pd[v * 128 * IPB + f * n + tid];
+    wn[tid] = t;
+    rp = t * cj;
+  }
+  const double R = block_sum_mv(rp, red);
+  for (int q = tid; q < S; q += blockDim.x) w.rdet_part[(long)wk * S + q] = q == 0 ? R : 0.0;
+}
+
 // Column maxima of the P halves (bit 0: up rows, bit 1: down rows):
 // cmax[w][h][mu] = max over the rows i of half h of |P[w][i][mu]|.
 __global__ void __launch_bounds__(256) screen_colmax_kernel(SysDev s, WalkDev w, int halves) {
@@ -271,7 +367,20 @@ hipError_t launch_propose_screened(const SysDev& s, const WalkDev& w, int e, dou
   const int n = e < s.nu ? s.nd : s.nu;
   const int S = propose_splits(s);
   const dim3 grid(w.Wk), blk(256);
-  if (n <= 64) hipExtLaunchKernelGGL(propose_screened_kernel<1>, grid, blk, 0, st, ev_start, ev_stop, 0, s, w, e, S);
+  // blocked kernel: n even, FB = 128 / gcd(n, 128) functions per block, IPB
+  // = FB n / 128 loads per lane and block, at most 8; n <= 256 (one row per
+  // thread in the final sums), Lp <= kFuseMaxLp (the kept list in LDS)
+  int g = 128;
+  while (n % g) g >>= 1;
+  const int FB = 128 / g, IPB = FB * n / 128;
+  if (n % 2 == 0 && n <= 256 && IPB <= 8 && s.Lp <= kFuseMaxLp && (uintptr_t)w.PT % 16 == 0 && s.N % 2 == 0 &&
+      (e < s.nu ? s.nu : 0) % 2 == 0) {
+    const size_t lds = pad1k(sizeof(int) * (size_t)s.Lp) + pad1k(sizeof(double) * (size_t)s.Lp) +
+                       sizeof(dbl2) * 4 * 64 * (size_t)IPB;
+#define QMC_SBLK(I) case I: hipExtLaunchKernelGGL(propose_screened_blk_kernel<I>, grid, blk, lds, st, ev_start, ev_stop, 0, s, w, e, S, FB); break;
+    switch (IPB) { QMC_SBLK(1) QMC_SBLK(2) QMC_SBLK(3) QMC_SBLK(4) QMC_SBLK(5) QMC_SBLK(6) QMC_SBLK(7) QMC_SBLK(8) }
+#undef QMC_SBLK
+  } else if (n <= 64) hipExtLaunchKernelGGL(propose_screened_kernel<1>, grid, blk, 0, st, ev_start, ev_stop, 0, s, w, e, S);
   else if (n <= 128) hipExtLaunchKernelGGL(propose_screened_kernel<2>, grid, blk, 0, st, ev_start, ev_stop, 0, s, w, e, S);
   else if (n <= 256) hipExtLaunchKernelGGL(propose_screened_kernel<4>, grid, blk, 0, st, ev_start, ev_stop, 0, s, w, e, S);
   else if (n <= 512) hipExtLaunchKernelGGL(propose_screened_kernel<8>, grid, blk, 0, st, ev_start, ev_stop, 0, s, w, e, S);
@@ -307,11 +416,8 @@ hipError_t launch_propose_screened(const SysDev& s, const WalkDev& w, int e, dou
 constexpr int kStageMaxN = 128;    // n <= 128 (one W entry per thread)
 constexpr int kStageMaxNe = 256;   // electrons
 constexpr int kStageMaxNuc = 256;  // nuclei (one per thread)
-constexpr int kStageQL = (kFuseMaxLp + 255) / 256;
 constexpr int kStageMaxSplits = (kStageMaxN + kPropRowsMin - 1) / kPropRowsMin;   // partial ratios
 constexpr size_t kStageMaxLds = 63 * 1024;   // dynamic LDS (the static arrays take the rest of 64 KiB)
-
-__host__ __device__ inline size_t pad1k(size_t b) { return (b + 1023) & ~(size_t)1023; }
 
 struct StageLayout {
   size_t V, D, S, r, psi, vec, total;   // byte offsets of the regions and the size
