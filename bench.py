@@ -502,12 +502,12 @@ def lrdmc_leg(P, C, iters=10):
             "ratio_err_vs_oracle": float(f"{err:.3e}")}
 
 
-def large_leg(P, C, steps=128, Wk=256):
+def large_leg(P, C, steps=128, Wk=256, fw=32):
     """The 1024-electron workload (256 nuclei, L = 4096, Lambda banded at 8
     bohr; n = 512 per spin, so the blocked Gauss-Jordan refresh), 256 walkers,
     FP64: one evaluation and `steps` Metropolis moves (refresh after 64 moves
-    of one spin); error of the evaluation against
-    the oracle on one walker."""
+    of one spin); error of the evaluation against the oracle on one walker;
+    forces through the adjoint on fw walkers."""
     from oracle import jagp as O
     dev = torch.device("cuda:0")
     w = C.large_256nuc_1024e(n_walkers=Wk)
@@ -534,13 +534,36 @@ def large_leg(P, C, steps=128, Wk=256):
     err = {k: float(f"{float(((out[k].cpu()[:1] - ref[k]).abs() / ref[k].abs().clamp(min=1.0)).max()):.3e}")
            for k in ("logabs", "e_loc")}
     wk.close()
+    # forces via the adjoint on `fw` walkers (the reverse-pass workspace is
+    # some 0.2 GB per walker at this size): one evaluation against one call
+    # of qmc_forces (which re-evaluates), walker-summed gradients, median of 3
+    wf = P.Walkers(sysh, fw)
+    rf = r[:fw].contiguous()
+    gl = torch.ones(fw, dtype=torch.float64, device=dev)
+    wf.forces(rf, gl, gl)
+    torch.cuda.synchronize()
+    te, tf = [], []
+    for _ in range(3):
+        f0, f1, f2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        f0.record()
+        wf.eval_batch(rf)
+        f1.record()
+        wf.forces(rf, gl, gl)
+        f2.record()
+        torch.cuda.synchronize()
+        te.append(f0.elapsed_time(f1))
+        tf.append(f1.elapsed_time(f2))
+    te, tf = float(np.median(te)), float(np.median(tf))
+    wf.close()
     sysh.close()
     return {"workload": "large_256nuc_1024e", "walkers": Wk, "precision": "fp64",
             "eloc_evals_per_s": round(Wk / t_eval, 1), "moves_per_s": round(steps * Wk / t_move, 1),
             "acceptance": round(cnt.sum().item() / (steps * Wk), 4), "moves": steps,
             "err_vs_oracle": {"walkers": [0], **err},
             "kernel_ms": {k: round(v[0], 3) for k, v in tim.items() if v[1]},
-            "kernel_launches": {k: v[1] for k, v in tim.items() if v[1]}}
+            "kernel_launches": {k: v[1] for k, v in tim.items() if v[1]},
+            "forces": {"walkers": fw, "eval_ms": round(te, 3), "forces_ms": round(tf, 3),
+                       "forces_over_eval": round(tf / te, 2), "grad_evals_per_s": round(fw / (tf * 1e-3), 1)}}
 
 
 def pfaffian_leg(P, C, steps=160, Wk=512):

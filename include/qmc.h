@@ -335,7 +335,8 @@ typedef struct {
  * parameter gradients over walkers (a vector-Jacobian product); 1 returns
  * them per walker.  r [Wk][N][3] device; gbar_* [Wk] device, NULL means 0.
  * Re-evaluates the walkers at r (their state becomes that of qmc_eval_batch).
- * FP64 systems with N <= 256 electrons and <= 256 nuclei.  Needs a walker set
+ * FP64 systems with <= 256 nuclei (any electron count the evaluation takes,
+ * up to 2048).  Needs a walker set
  * created with QMC_WALKERS_ADJOINT (QMC_ERR_STATE otherwise); allocates
  * nothing.
  * Pfaffian systems: every output above (log|Psi| through the cofactor

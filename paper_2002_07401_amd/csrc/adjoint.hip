@@ -212,7 +212,8 @@ __global__ void __launch_bounds__(256)
 basis_backward_kernel(SysDev s, WalkDev w, const double* __restrict__ phibar, const double* __restrict__ gb,
                       double* __restrict__ dr, double* __restrict__ Rbar_w, double* __restrict__ zbar_w,
                       double* __restrict__ tmu, int acc) {
-  __shared__ double rpart[4][kLuMaxN * 2][3];
+  constexpr int NC = kLuMaxN * 2;   // electrons per chunk (rows of rpart)
+  __shared__ double rpart[4][NC][3];
   const int wk = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const double b = gb ? gb[wk] : 0.0;
   const double* r = w.r + (long)wk * s.N * 3;
@@ -220,78 +221,88 @@ basis_backward_kernel(SysDev s, WalkDev w, const double* __restrict__ phibar, co
   const double* PB = phibar + (long)wk * s.N * s.Lp;
   const double* gJ = w.gJ + (long)wk * s.N * 4;
   double* tm = tmu + (long)wk * s.L * 3;
+  double* zw = zbar_w + (long)wk * s.L;
   const int nmu = (s.L + blockDim.x - 1) / blockDim.x;
-  for (int k = 0; k < nmu; ++k) {
-    const int mu = tid + k * blockDim.x;
-    const bool act = mu < s.L;
-    int c = 0, kind = 0;
-    double zt = 0.0, Rx = 0.0, Ry = 0.0, Rz = 0.0, HP[6];
-    if (act) {
-      const double4 f = s.bfn[mu];
-      c = s.center[mu]; kind = s.kind[mu]; zt = f.w;
-      Rx = f.x; Ry = f.y; Rz = f.z;
-    }
-    hess_P(kind_ang(kind), HP);
-    double zacc = 0.0, tx = 0.0, ty = 0.0, tz = 0.0;
-    for (int i = 0; i < s.N; ++i) {
-      double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+  // electrons in chunks of NC: a function's sums over the electrons continue
+  // from the previous chunk's (its own thread stored them), so every sum runs
+  // over i in increasing order whatever the chunking
+  for (int c0 = 0; c0 < s.N; c0 += NC) {
+    const int c1 = min(s.N, c0 + NC);
+    for (int k = 0; k < nmu; ++k) {
+      const int mu = tid + k * blockDim.x;
+      const bool act = mu < s.L;
+      int kind = 0;
+      double zt = 0.0, Rx = 0.0, Ry = 0.0, Rz = 0.0, HP[6];
       if (act) {
-        const double pb = PB[(long)i * s.Lp + mu];
-        const double qb = -0.5 * b * Yt[(long)i * s.Lp + mu];
-        const double gbx = 2.0 * qb * gJ[4 * i], gby = 2.0 * qb * gJ[4 * i + 1], gbz = 2.0 * qb * gJ[4 * i + 2];
-        const double hb = qb;
-        const double d[3] = {r[3 * i] - Rx, r[3 * i + 1] - Ry, r[3 * i + 2] - Rz};
-        const double sq = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-        double P, Pg[3];
-        angular(kind_ang(kind), d[0], d[1], d[2], P, Pg[0], Pg[1], Pg[2]);
-        const Radial rd = radial_all(kind, zt, sq);
-        const double e = rd.e;
-        const double psi = P * e;
-        double gpsi[3];
-        for (int a = 0; a < 3; ++a) gpsi[a] = (Pg[a] + rd.h1 * d[a] * P) * e;
-        // Hessian of psi
-        const int ia[6] = {0, 1, 2, 0, 1, 2}, ib[6] = {0, 1, 2, 1, 2, 0};
-        double Hs[3][3];
-        for (int q = 0; q < 6; ++q) {
-          const int a = ia[q], bb = ib[q];
-          const double v = (HP[q] + rd.h1 * (d[a] * Pg[bb] + d[bb] * Pg[a]) +
-                            (a == bb ? rd.h1 * P : 0.0) + rd.h2 * d[a] * d[bb] * P) * e;
-          Hs[a][bb] = v; Hs[bb][a] = v;
+        const double4 f = s.bfn[mu];
+        kind = s.kind[mu]; zt = f.w;
+        Rx = f.x; Ry = f.y; Rz = f.z;
+      }
+      hess_P(kind_ang(kind), HP);
+      double zacc = 0.0, tx = 0.0, ty = 0.0, tz = 0.0;
+      if (c0 > 0 && act) { zacc = zw[mu]; tx = tm[3 * mu]; ty = tm[3 * mu + 1]; tz = tm[3 * mu + 2]; }
+      for (int i = c0; i < c1; ++i) {
+        double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+        if (act) {
+          const double pb = PB[(long)i * s.Lp + mu];
+          const double qb = -0.5 * b * Yt[(long)i * s.Lp + mu];
+          const double gbx = 2.0 * qb * gJ[4 * i], gby = 2.0 * qb * gJ[4 * i + 1], gbz = 2.0 * qb * gJ[4 * i + 2];
+          const double hb = qb;
+          const double d[3] = {r[3 * i] - Rx, r[3 * i + 1] - Ry, r[3 * i + 2] - Rz};
+          const double sq = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+          double P, Pg[3];
+          angular(kind_ang(kind), d[0], d[1], d[2], P, Pg[0], Pg[1], Pg[2]);
+          const Radial rd = radial_all(kind, zt, sq);
+          const double e = rd.e;
+          const double psi = P * e;
+          double gpsi[3];
+          for (int a = 0; a < 3; ++a) gpsi[a] = (Pg[a] + rd.h1 * d[a] * P) * e;
+          // Hessian of psi
+          const int ia[6] = {0, 1, 2, 0, 1, 2}, ib[6] = {0, 1, 2, 1, 2, 0};
+          double Hs[3][3];
+          for (int q = 0; q < 6; ++q) {
+            const int a = ia[q], bb = ib[q];
+            const double v = (HP[q] + rd.h1 * (d[a] * Pg[bb] + d[bb] * Pg[a]) +
+                              (a == bb ? rd.h1 * P : 0.0) + rd.h2 * d[a] * d[bb] * P) * e;
+            Hs[a][bb] = v; Hs[bb][a] = v;
+          }
+          const double cl = rd.cl;   // lap psi = cl psi
+          double glap[3];
+          for (int a = 0; a < 3; ++a) glap[a] = rd.gl * d[a] * psi + cl * gpsi[a];
+          const double gbv[3] = {gbx, gby, gbz};
+          t0 = pb * gpsi[0] + Hs[0][0] * gbv[0] + Hs[0][1] * gbv[1] + Hs[0][2] * gbv[2] + hb * glap[0];
+          t1 = pb * gpsi[1] + Hs[1][0] * gbv[0] + Hs[1][1] * gbv[1] + Hs[1][2] * gbv[2] + hb * glap[1];
+          t2 = pb * gpsi[2] + Hs[2][0] * gbv[0] + Hs[2][1] * gbv[1] + Hs[2][2] * gbv[2] + hb * glap[2];
+          // exponent derivatives
+          const double zpsi = -rd.zp * psi;
+          double zg = 0.0;
+          for (int a = 0; a < 3; ++a) zg += gbv[a] * (-rd.zq * d[a] * psi - rd.zp * gpsi[a]);
+          const double zlap = rd.dcl * psi - rd.zp * cl * psi;
+          zacc += pb * zpsi + zg + hb * zlap;
+          tx += t0; ty += t1; tz += t2;
         }
-        const double cl = rd.cl;   // lap psi = cl psi
-        double glap[3];
-        for (int a = 0; a < 3; ++a) glap[a] = rd.gl * d[a] * psi + cl * gpsi[a];
-        const double gbv[3] = {gbx, gby, gbz};
-        t0 = pb * gpsi[0] + Hs[0][0] * gbv[0] + Hs[0][1] * gbv[1] + Hs[0][2] * gbv[2] + hb * glap[0];
-        t1 = pb * gpsi[1] + Hs[1][0] * gbv[0] + Hs[1][1] * gbv[1] + Hs[1][2] * gbv[2] + hb * glap[1];
-        t2 = pb * gpsi[2] + Hs[2][0] * gbv[0] + Hs[2][1] * gbv[1] + Hs[2][2] * gbv[2] + hb * glap[2];
-        // exponent derivatives
-        const double zpsi = -rd.zp * psi;
-        double zg = 0.0;
-        for (int a = 0; a < 3; ++a) zg += gbv[a] * (-rd.zq * d[a] * psi - rd.zp * gpsi[a]);
-        const double zlap = rd.dcl * psi - rd.zp * cl * psi;
-        zacc += pb * zpsi + zg + hb * zlap;
-        tx += t0; ty += t1; tz += t2;
+        const double s0 = wave_sum(t0), s1 = wave_sum(t1), s2 = wave_sum(t2);
+        if (lane == 0) {
+          double* rp = rpart[wave][i - c0];
+          if (k == 0) { rp[0] = s0; rp[1] = s1; rp[2] = s2; }
+          else { rp[0] += s0; rp[1] += s1; rp[2] += s2; }
+        }
       }
-      const double s0 = wave_sum(t0), s1 = wave_sum(t1), s2 = wave_sum(t2);
-      if (lane == 0) {
-        if (k == 0) { rpart[wave][i][0] = s0; rpart[wave][i][1] = s1; rpart[wave][i][2] = s2; }
-        else { rpart[wave][i][0] += s0; rpart[wave][i][1] += s1; rpart[wave][i][2] += s2; }
+      if (act) {
+        zw[mu] = zacc;
+        tm[3 * mu] = tx; tm[3 * mu + 1] = ty; tm[3 * mu + 2] = tz;
       }
     }
-    if (act) {
-      zbar_w[(long)wk * s.L + mu] = zacc;
-      tm[3 * mu] = tx; tm[3 * mu + 1] = ty; tm[3 * mu + 2] = tz;
+    __syncthreads();
+    for (int i = c0 + tid; i < c1; i += blockDim.x) {
+      for (int c = 0; c < 3; ++c) {
+        double t = 0.0;
+        for (int q = 0; q < 4; ++q) t += rpart[q][i - c0][c];
+        if (acc) dr[((long)wk * s.N + i) * 3 + c] += t;
+        else dr[((long)wk * s.N + i) * 3 + c] = t;
+      }
     }
-  }
-  __syncthreads();
-  for (int i = tid; i < s.N; i += blockDim.x) {
-    for (int c = 0; c < 3; ++c) {
-      double t = 0.0;
-      for (int q = 0; q < 4; ++q) t += rpart[q][i][c];
-      if (acc) dr[((long)wk * s.N + i) * 3 + c] += t;
-      else dr[((long)wk * s.N + i) * 3 + c] = t;
-    }
+    __syncthreads();   // rpart is refilled by the next chunk; tm complete for the nuclei below
   }
   // nuclear positions: dF/dR_a = - sum over the functions centred on a (CSR order)
   for (int a = tid; a < s.n_nuc; a += blockDim.x) {
@@ -308,7 +319,8 @@ basis_backward_kernel(SysDev s, WalkDev w, const double* __restrict__ phibar, co
 }
 
 // ---------------------------------------------------------------------------
-// 4. Jastrow and Coulomb backward, one workgroup per walker, thread i = electron i.
+// 4. Jastrow and Coulomb backward, one workgroup per walker, thread = electron
+//    (in chunks of the block size).
 //    Pair terms of F: a_w J + sum_i gbar_i . grad_i J - b_w/2 sum_i lap_i J + b_w V,
 //    gbar_i = -b_w drift_i.  Accumulates into dr, Rbar_w and writes jbar_w.
 // ---------------------------------------------------------------------------
@@ -321,74 +333,80 @@ jastrow_backward_kernel(SysDev s, WalkDev w, const double* __restrict__ ga, cons
   const double av = ga ? ga[wk] : 0.0, bv = gbw ? gbw[wk] : 0.0;
   const double* r = w.r + (long)wk * s.N * 3;
   const double* drift = w.drift + (long)wk * s.N * 3;
-  const int i = tid;
-  const bool act = i < s.N;
-  double xi[3] = {0.0, 0.0, 0.0}, gi[3] = {0.0, 0.0, 0.0};
-  if (act) {
-    for (int c = 0; c < 3; ++c) { xi[c] = r[3 * i + c]; gi[c] = -bv * drift[3 * i + c]; }
-  }
-  double rb[3] = {0.0, 0.0, 0.0};
-  // one-body terms and electron-nucleus attraction, nucleus by nucleus
-  for (int a = 0; a < s.n_nuc; ++a) {
-    double cR[3] = {0.0, 0.0, 0.0}, cb = 0.0;
-    if (act) {
-      const double d[3] = {xi[0] - s.R[3 * a], xi[1] - s.R[3 * a + 1], xi[2] - s.R[3 * a + 2]};
-      const double ria = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-      const double Z = s.Z[a];
-      double t[3] = {0.0, 0.0, 0.0};
-      if (s.j1_form) {
-        Dl f, f1, f2;
-        j1_radial_t<Dl>(s.j1_form, Z, cst(s.j1_b[a]), var(ria), f, f1, f2);
-        pair_term_grad(av, -0.5 * bv, gi, d, ria, f1.v, f2.v, f2.d, t);
-        Dl pf, pf1, pf2;
-        j1_radial_t<Dl>(s.j1_form, Z, var(s.j1_b[a]), cst(ria), pf, pf1, pf2);
-        const double gd = (gi[0] * d[0] + gi[1] * d[1] + gi[2] * d[2]) / ria;
-        cb = av * pf.d + gd * pf1.d - 0.5 * bv * (pf2.d + 2.0 * pf1.d / ria);
-      }
-      // b_w * (-Z / r_ia): d/dr_i = b Z d / r^3
-      const double ir3 = 1.0 / (ria * ria * ria);
-      for (int c = 0; c < 3; ++c) t[c] += bv * Z * d[c] * ir3;
-      for (int c = 0; c < 3; ++c) { rb[c] += t[c]; cR[c] = -t[c]; }
-    }
-    const double s0 = wave_sum(cR[0]), s1 = wave_sum(cR[1]), s2 = wave_sum(cR[2]), s3 = wave_sum(cb);
-    if (lane == 0 && a < kMaxNucBack) {
-      rbin[wave][a][0] = s0; rbin[wave][a][1] = s1; rbin[wave][a][2] = s2; rbin[wave][a][3] = s3;
-    }
-  }
-  // two-body terms and electron-electron repulsion
   double th[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // jas slots after the one-body b's
-  if (act) {
-    for (int j = 0; j < s.N; ++j) {
-      if (j == i) continue;
-      const double d[3] = {xi[0] - r[3 * j], xi[1] - r[3 * j + 1], xi[2] - r[3 * j + 2]};
-      const double rij = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-      const double ir3 = 1.0 / (rij * rij * rij);
-      for (int c = 0; c < 3; ++c) rb[c] += -bv * d[c] * ir3;    // b_w * 1/r_ij
-      if (!s.j2_form) continue;
-      const bool same = (i < s.nu) == (j < s.nu);
-      double p[4];
-      j2_params(s, same, p);
-      const double cc = same ? 0.25 : 0.5;
-      double dg[3];
-      for (int c = 0; c < 3; ++c) dg[c] = gi[c] + bv * drift[3 * j + c];    // gbar_i - gbar_j
-      Dl v, v1, v2;
-      j2_radial_t<Dl>(cc, cst(p[0]), cst(p[1]), cst(p[2]), cst(p[3]), var(rij), v, v1, v2);
-      double t[3];
-      pair_term_grad(av, -bv, dg, d, rij, v1.v, v2.v, v2.d, t);
-      for (int c = 0; c < 3; ++c) rb[c] += t[c];
-      const double gd = (dg[0] * d[0] + dg[1] * d[1] + dg[2] * d[2]) / rij;
-      const int np = s.j2_form == 1 ? 1 : 4;
-      const int slot0 = s.j2_form == 1 ? (same ? 0 : 1) : (same ? 0 : 4);
-      for (int k = 0; k < np; ++k) {
-        Dl q[4] = {cst(p[0]), cst(p[1]), cst(p[2]), cst(p[3])};
-        q[k].d = 1.0;
-        Dl pv, pv1, pv2;
-        j2_radial_t<Dl>(cc, q[0], q[1], q[2], q[3], cst(rij), pv, pv1, pv2);
-        // each pair is visited from both electrons: half weight
-        th[slot0 + k] += 0.5 * (av * pv.d + gd * pv1.d - bv * (pv2.d + 2.0 * pv1.d / rij));
+  // electrons in chunks of the block size (thread = electron c0 + tid); the
+  // per-nucleus sums continue over the chunks in order
+  for (int c0 = 0; c0 < s.N; c0 += blockDim.x) {
+    const int i = c0 + tid;
+    const bool act = i < s.N;
+    double xi[3] = {0.0, 0.0, 0.0}, gi[3] = {0.0, 0.0, 0.0};
+    if (act) {
+      for (int c = 0; c < 3; ++c) { xi[c] = r[3 * i + c]; gi[c] = -bv * drift[3 * i + c]; }
+    }
+    double rb[3] = {0.0, 0.0, 0.0};
+    // one-body terms and electron-nucleus attraction, nucleus by nucleus
+    for (int a = 0; a < s.n_nuc; ++a) {
+      double cR[3] = {0.0, 0.0, 0.0}, cb = 0.0;
+      if (act) {
+        const double d[3] = {xi[0] - s.R[3 * a], xi[1] - s.R[3 * a + 1], xi[2] - s.R[3 * a + 2]};
+        const double ria = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        const double Z = s.Z[a];
+        double t[3] = {0.0, 0.0, 0.0};
+        if (s.j1_form) {
+          Dl f, f1, f2;
+          j1_radial_t<Dl>(s.j1_form, Z, cst(s.j1_b[a]), var(ria), f, f1, f2);
+          pair_term_grad(av, -0.5 * bv, gi, d, ria, f1.v, f2.v, f2.d, t);
+          Dl pf, pf1, pf2;
+          j1_radial_t<Dl>(s.j1_form, Z, var(s.j1_b[a]), cst(ria), pf, pf1, pf2);
+          const double gd = (gi[0] * d[0] + gi[1] * d[1] + gi[2] * d[2]) / ria;
+          cb = av * pf.d + gd * pf1.d - 0.5 * bv * (pf2.d + 2.0 * pf1.d / ria);
+        }
+        // b_w * (-Z / r_ia): d/dr_i = b Z d / r^3
+        const double ir3 = 1.0 / (ria * ria * ria);
+        for (int c = 0; c < 3; ++c) t[c] += bv * Z * d[c] * ir3;
+        for (int c = 0; c < 3; ++c) { rb[c] += t[c]; cR[c] = -t[c]; }
+      }
+      const double s0 = wave_sum(cR[0]), s1 = wave_sum(cR[1]), s2 = wave_sum(cR[2]), s3 = wave_sum(cb);
+      if (lane == 0 && a < kMaxNucBack) {
+        double* rbw = rbin[wave][a];
+        if (c0 == 0) { rbw[0] = s0; rbw[1] = s1; rbw[2] = s2; rbw[3] = s3; }
+        else { rbw[0] += s0; rbw[1] += s1; rbw[2] += s2; rbw[3] += s3; }
       }
     }
-    for (int c = 0; c < 3; ++c) dr[((long)wk * s.N + i) * 3 + c] += rb[c];
+    // two-body terms and electron-electron repulsion
+    if (act) {
+      for (int j = 0; j < s.N; ++j) {
+        if (j == i) continue;
+        const double d[3] = {xi[0] - r[3 * j], xi[1] - r[3 * j + 1], xi[2] - r[3 * j + 2]};
+        const double rij = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        const double ir3 = 1.0 / (rij * rij * rij);
+        for (int c = 0; c < 3; ++c) rb[c] += -bv * d[c] * ir3;    // b_w * 1/r_ij
+        if (!s.j2_form) continue;
+        const bool same = (i < s.nu) == (j < s.nu);
+        double p[4];
+        j2_params(s, same, p);
+        const double cc = same ? 0.25 : 0.5;
+        double dg[3];
+        for (int c = 0; c < 3; ++c) dg[c] = gi[c] + bv * drift[3 * j + c];    // gbar_i - gbar_j
+        Dl v, v1, v2;
+        j2_radial_t<Dl>(cc, cst(p[0]), cst(p[1]), cst(p[2]), cst(p[3]), var(rij), v, v1, v2);
+        double t[3];
+        pair_term_grad(av, -bv, dg, d, rij, v1.v, v2.v, v2.d, t);
+        for (int c = 0; c < 3; ++c) rb[c] += t[c];
+        const double gd = (dg[0] * d[0] + dg[1] * d[1] + dg[2] * d[2]) / rij;
+        const int np = s.j2_form == 1 ? 1 : 4;
+        const int slot0 = s.j2_form == 1 ? (same ? 0 : 1) : (same ? 0 : 4);
+        for (int k = 0; k < np; ++k) {
+          Dl q[4] = {cst(p[0]), cst(p[1]), cst(p[2]), cst(p[3])};
+          q[k].d = 1.0;
+          Dl pv, pv1, pv2;
+          j2_radial_t<Dl>(cc, q[0], q[1], q[2], q[3], cst(rij), pv, pv1, pv2);
+          // each pair is visited from both electrons: half weight
+          th[slot0 + k] += 0.5 * (av * pv.d + gd * pv1.d - bv * (pv2.d + 2.0 * pv1.d / rij));
+        }
+      }
+      for (int c = 0; c < 3; ++c) dr[((long)wk * s.N + i) * 3 + c] += rb[c];
+    }
   }
   for (int k = 0; k < 8; ++k) {
     const double t = wave_sum(th[k]);

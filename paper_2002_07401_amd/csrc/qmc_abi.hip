@@ -1121,8 +1121,7 @@ extern "C" qmc_status qmc_forces(qmc_system* sys, qmc_walkers* wk, const double*
   if (s.precision != QMC_FP64) return fail(QMC_ERR_UNSUPPORTED, "forces are built for the FP64 path");
   if (!s.pairing && (out->dpf_uu || out->dpf_dd || out->dunpaired_dn))
     return fail(QMC_ERR_ARG, "dpf_uu, dpf_dd and dunpaired_dn are outputs of Pfaffian systems");
-  if (s.N > 2 * kLuMaxN || s.n_nuc > kMaxNucBack)
-    return fail(QMC_ERR_UNSUPPORTED, "forces need N <= 256 electrons and <= 256 nuclei");
+  if (s.n_nuc > kMaxNucBack) return fail(QMC_ERR_UNSUPPORTED, "forces need <= 256 nuclei");
   if (!wk->aw_ready)
     return fail(QMC_ERR_STATE, "walkers created without QMC_WALKERS_ADJOINT (no reverse-pass workspace)");
   c = qmc_eval_batch(sys, wk, r, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, stream);
