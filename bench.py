@@ -58,8 +58,8 @@ def parse():
     return ap.parse_args()
 
 
-# Sources of the streaming proposal kernel: a recorded counter measurement is
-# reported only while these files are unchanged.
+# Sources of the move kernels: a recorded counter measurement is reported only
+# while these files are unchanged.
 ROWS_SOURCES = ("paper_2002_07401_amd/csrc/move.hip", "paper_2002_07401_amd/csrc/move_dev.h",
                 "paper_2002_07401_amd/csrc/internal.h")
 
@@ -73,12 +73,13 @@ def rows_source_hash():
     return h.hexdigest()
 
 
-def recorded_traffic(precision, walkers):
-    """HBM bytes per launch of the proposal kernel from the committed counter
-    summary (FETCH_SIZE and WRITE_SIZE passes, each scaled by the same counter
-    over a plain copy of known size), or None when the summary is missing, was
-    taken on another configuration, or the kernel sources changed since."""
-    path = os.path.join(ROOT, "profiles", f"propose_rows_mol160e_{precision}_pmc.txt")
+def recorded_traffic(tag, precision, walkers):
+    """HBM bytes per launch of a move kernel (tag: propose_rows,
+    propose_screened or accept_prep) from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE passes, each scaled by the same counter over a
+    plain copy of known size), or None when the summary is missing, was taken
+    on another configuration, or the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", f"{tag}_mol160e_{precision}_pmc.txt")
     if not os.path.exists(path):
         return None
     rec = {}
@@ -118,16 +119,19 @@ def kernel_models(s, Wk, esz, acc_rate, kept=None):
              kept columns of N_other FP64 values, the kept functions' indices and
              values (12 kept), the inverse column (8 N_other) and the new row
              (8 N_other).
-    accept:  (latency-bound: chains of dependent loads of a few kB per walker;
-             in a Metropolis sweep it also runs the next proposal's set-up, so
-             its time is not priced against a roofline)
-             an accepted walker with m buffered moves reads the new W row, the
-             old one, v0 and the m buffered vectors v_j (8 n (3 + m)), S^{-1} and
-             t, z (8 m^2 + 16 m), psi(r') (8 L); it writes d and v (16 n), the
-             bordered S^{-1} (8 (m+1)^2), the W row (8 n) and the basis row
-             (esz L); rejected walkers move no data.  m is averaged over a sweep:
-             the buffer restarts at every refresh (after min(refresh_every, 64)
-             moves of one spin and at each change of spin) and grows by the
+    accept:  the Metropolis accept fused with the next proposal's set-up (the
+             kernel of 150 of the 160 steps of a sweep), per walker with m
+             buffered moves: reads the m rows of V and D and S^{-1}
+             (8 (2 m n + m^2)), the new and old W line, v0 and the next
+             electron's A0 line (32 n), z (8 m) and the positions (24 N); an
+             accepted walker also reads psi(r') (8 L) and writes d and v
+             (16 n), the bordered S^{-1} (8 (m+1)^2), the W line (8 n) and the
+             basis row (esz L); every walker writes psi(r') of the next
+             electron (8 Lp), v0 and the inverse line (16 n) and t, z
+             (16 m); screened proposals add the column maxima (8 L) and the
+             kept list (12 kept).  m is averaged over a sweep: the buffer
+             restarts at every refresh (after min(refresh_every, 64) moves of
+             one spin and at each change of spin) and grows by the
              acceptance rate per move.
     P_build: the evaluation's P = Phi Lambda for both spins, 2 L^2 flops per
              basis row over Wk * N rows (the one-spin rebuilds before moves
@@ -141,10 +145,13 @@ def kernel_models(s, Wk, esz, acc_rate, kept=None):
         prop = Wk * (esz * n * L + 8 * L + 8 * n + 8 * n)
     else:
         prop = Wk * (kept * (8 * n + 12) + 16 * n)
-    acc = Wk * acc_rate * (8 * n * (3 + m) + 8 * m * m + 16 * m + 8 * L
-                           + 16 * n + 8 * (m + 1) ** 2 + 8 * n + esz * L)
+    Lp = (L + 31) // 32 * 32
+    acc = Wk * (8 * (2 * m * n + m * m) + 32 * n + 8 * m + 24 * N
+                + acc_rate * (8 * L + 16 * n + 8 * (m + 1) ** 2 + 8 * n + esz * L)
+                + 8 * Lp + 16 * n + 16 * m
+                + (8 * L + 12 * kept if kept is not None else 0))
     pflops = 2.0 * L * L * Wk * N
-    return {"propose": ("hbm", prop), "accept": ("latency", acc), "P_build": ("mfma", pflops)}
+    return {"propose": ("hbm", prop), "accept": ("hbm", acc), "P_build": ("mfma", pflops)}
 
 
 def host_cpu():
@@ -159,6 +166,15 @@ def host_cpu():
     except OSError:
         pass
     return name, len(os.sched_getaffinity(0))
+
+
+def prop_roofline(models, tim):
+    """Roofline fields of the proposal stream from the timed steps."""
+    ms, cnt = tim["propose"]
+    avg = ms / max(cnt, 1)
+    ach = models["propose"][1] / (avg * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "avg_launch_us": round(avg * 1e3, 2)}
 
 
 def cpu_baseline(w, n_walk=8, n_moves=320, n_eval=32, n_moves_1t=40):
@@ -233,7 +249,7 @@ def run_precision(P, C, w, args, precision):
     cnt.zero_()
     # the timed steps record events only around the kernels a roofline is
     # reported for (every timed launch adds two event records to the stream)
-    wk.set_timing(True, timers=("propose", "P_build"))
+    wk.set_timing(True, timers=("propose", "accept", "P_build"))
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -288,20 +304,20 @@ def run_precision(P, C, w, args, precision):
         err["bar"] = BARS[precision]
         err["conforming"] = bool(max(err["logabs"], err["e_loc"], err["ratio"]) <= BARS[precision])
 
-    # roofline of the dominant kernel (largest summed time in the timed steps)
-    # roofline of the dominant bandwidth- or MFMA-bound kernel; the kernel with the
-    # largest summed time overall is named beside it
+    # roofline of the dominant kernel among those with a model (proposal
+    # stream, fused accept, P product: largest summed time in the timed
+    # steps); the kernel with the largest summed time overall is named beside it
     models = kernel_models(s, Wk, esz, acc_rate, kept)
     dominant = max(one, key=lambda k: one[k][0])
-    dom = max((k for k in models if models[k][0] != "latency"), key=lambda k: tim[k][0])
+    dom = max((k for k in models if tim.get(k, (0.0, 0))[1]), key=lambda k: tim[k][0])
     bound, units = models[dom]
     avg_ms = tim[dom][0] / max(tim[dom][1], 1)
     if bound == "hbm":
         achieved = units / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": (recorded_traffic({"fp64": "fp64", "bf16": "bf16", "mixed": "refined"}.get(
-                    precision, "fp32"), Wk) if dom == "propose" else None),
+                "traffic": recorded_traffic({"propose": "propose_screened" if screened else "propose_rows",
+                                             "accept": "accept_prep"}[dom], precision, Wk),
                 "bytes_per_launch": int(units), "avg_launch_us": round(avg_ms * 1e3, 2)}
     else:
         peak = MFMA_PEAK_TFLOPS[precision]
@@ -309,7 +325,8 @@ def run_precision(P, C, w, args, precision):
         roof = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 2), "peak": peak,
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
                 "flops_per_launch": int(units), "avg_launch_us": round(avg_ms * 1e3, 2)}
-    steps = step_rooflines(s, Wk, precision, one, roof) if roof["kernel"] == "propose" else None
+    steps = step_rooflines(s, Wk, precision, one, roof if roof["kernel"] == "propose" else
+                           prop_roofline(models, tim), models["accept"][1])
     # MFMA use of the geminal build's dominant product (P = Phi Lambda in the
     # evaluations of the timed steps).  Refined modes: int8 operations of the
     # digit products (the P_build timer also covers the digit split) against
@@ -715,7 +732,7 @@ def achievable_peaks():
             "datasheet": {"hbm_GBps": HBM_PEAK_GBS, "fp64_TFLOPs": 78.6, "fp32_TFLOPs": 157.3}}
 
 
-def step_rooflines(s, Wk, precision, one, prop_roof):
+def step_rooflines(s, Wk, precision, one, prop_roof, acc_model=None):
     """Roofline of each step of one evaluation (and the proposal) from the
     one-step timers: algorithmic bytes or flops per launch / average launch.
       basis:   writes the N x L values of every walker (FP64; FP32 in fp32 mode)
@@ -747,6 +764,13 @@ def step_rooflines(s, Wk, precision, one, prop_roof):
         out[k] = {"bound": bound, "achieved": round(ach, 2), "peak": peak, "unit": unit,
                   "frac": round(ach / peak, 4), "avg_launch_us": round(avg * 1e3, 2)}
     out["propose"] = {k: prop_roof[k] for k in ("bound", "achieved", "peak", "unit", "frac", "avg_launch_us")}
+    if acc_model is not None and one.get("accept", (0.0, 0))[1]:
+        ms, cnt = one["accept"]
+        avg = ms / cnt
+        ach = acc_model / (avg * 1e-3) / 1e9
+        out["accept"] = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(ach / HBM_PEAK_GBS, 4), "avg_launch_us": round(avg * 1e3, 2),
+                         "bytes_per_launch": int(acc_model)}
     return out
 
 

@@ -121,8 +121,9 @@ __global__ void __launch_bounds__(256) multi_accept_kernel(MultiArgs a, const in
     const int e = (int)(a.steps[k] % s.N);
     double d[3], u;
     member_draw(a, k, w, wd.Wk, d, &u);
-    const int nrow = e < s.nu ? s.nd : s.nu;
-    accept_body<T>(s, wd, w, e, 1, nullptr, u, nullptr, (nrow + a.rows[k] - 1) / a.rows[k]);
+    // the rows phase wrote ceil(n_up / rows) partial ratios for every walker
+    // (the count the rows table was built with), whichever spin moved
+    accept_body<T>(s, wd, w, e, 1, nullptr, u, nullptr, (s.nu + a.rows[k] - 1) / a.rows[k]);
   }
 }
 
