@@ -420,16 +420,14 @@ constexpr int kStageMaxSplits = (kStageMaxN + kPropRowsMin - 1) / kPropRowsMin; 
 constexpr size_t kStageMaxLds = 63 * 1024;   // dynamic LDS (the static arrays take the rest of 64 KiB)
 
 struct StageLayout {
-  size_t V, D, S, r, psi, vec, total;   // byte offsets of the regions and the size
+  size_t V, D, S, vec, total;   // byte offsets of the regions and the size
 };
-__host__ __device__ inline StageLayout stage_layout(int n, int kb, int N, int Lp, int mc) {
+__host__ __device__ inline StageLayout stage_layout(int n, int kb, int mc) {
   StageLayout o;
   o.V = 0;
   o.D = o.V + pad1k(sizeof(double) * (size_t)(mc + 1) * n);
   o.S = o.D + pad1k(sizeof(double) * (size_t)(mc + 1) * n);
-  o.r = o.S + pad1k(sizeof(double) * (size_t)(mc + 1) * kb);
-  o.psi = o.r + pad1k(sizeof(double) * 3 * (size_t)N);
-  o.vec = o.psi + sizeof(double) * (size_t)Lp;
+  o.vec = o.S + pad1k(sizeof(double) * (size_t)(mc + 1) * kb);
   o.total = o.vec + sizeof(double) * (3 * (size_t)n + 5 * (size_t)kb);
   return o;
 }
@@ -456,14 +454,18 @@ struct StagePre {
   int bk[kStageQL];
   double xp[kStageQL];    // psi(r') of the pending proposal (the accepted row)
   double xc[kStageQL];    // column maxima of the rows e2's proposal streams (screened)
+  double sv[kStageQL];    // psi(r') of e2 (computed)
   double nx, ny, nz, nZ, nb;   // nucleus tid (one-body Jastrow)
+  double ex, ey, ez;           // electron tid's position (two-body Jastrow)
   double wn, Wo, v0, a0, z;    // new W entry, old one, v0, A0's line of e2, z (thread = index)
 };
 
-// jastrow_one with nucleus tid's record prefetched, the positions and the
-// two-body parameters (j2p, the eight of s.j2d) in LDS.
-__device__ __forceinline__ double jastrow_staged(const SysDev& s, const double* r, int e, double px, double py,
-                                                 double pz, const StagePre& q, const double* j2p) {
+// jastrow_one for N <= the block size: nucleus tid's record and electron
+// tid's position (xj, yj, zj) in registers, the two-body parameters (j2p, the
+// eight of s.j2d) in LDS.
+__device__ __forceinline__ double jastrow_staged(const SysDev& s, int e, double px, double py, double pz,
+                                                 const StagePre& q, double xj, double yj, double zj,
+                                                 const double* j2p) {
   double val = 0.0;
   const int tid = threadIdx.x;
   if (s.j1_form) {
@@ -477,9 +479,9 @@ __device__ __forceinline__ double jastrow_staged(const SysDev& s, const double* 
   }
   if (s.j2_form) {
     const bool up_e = e < s.nu;
-    for (int j = tid; j < s.N; j += blockDim.x) {
-      if (j == e) continue;
-      const double dx = px - r[3 * j], dy = py - r[3 * j + 1], dz = pz - r[3 * j + 2];
+    const int j = tid;
+    if (j < s.N && j != e) {
+      const double dx = px - xj, dy = py - yj, dz = pz - zj;
       const double rij = sqrt(dx * dx + dy * dy + dz * dz);
       double v, v1, v2;
       j2_radial(s.j2_form, j2p, up_e == (j < s.nu), rij, v, v1, v2);
@@ -494,7 +496,7 @@ __device__ void accept_prep_staged_body(const SysDev& s, const WalkDev& w, int w
                                         int32_t* __restrict__ cnt, int cnt0, int S, int e2, double px, double py,
                                         double pz, double R, double dJ, int m, int mc, char* lds, const StagePre& q,
                                         const double* j2p, double la, double sg, double jv, double rx, double ry,
-                                        double rz) {
+                                        double rz, double ox, double oy, double oz) {
   __shared__ double red[16];
   __shared__ double gam_s;
   __shared__ int wcount[4];
@@ -503,12 +505,10 @@ __device__ void accept_prep_staged_body(const SysDev& s, const WalkDev& w, int w
   const int n = s.nu, kb = w.kb, N = s.N, L = s.L, Lp = s.Lp;
   const bool up = e < n;
   const int ie = up ? e : e - n;
-  const StageLayout ly = stage_layout(n, kb, N, Lp, mc);
+  const StageLayout ly = stage_layout(n, kb, mc);
   double* Vl = (double*)(lds + ly.V);
   double* Dl = (double*)(lds + ly.D);
   double* Sl = (double*)(lds + ly.S);
-  double* rl = (double*)(lds + ly.r);
-  double* sps = (double*)(lds + ly.psi);
   double* sd = (double*)(lds + ly.vec);
   double* sv0 = sd + n;
   double* cvl = sv0 + n;
@@ -586,7 +586,6 @@ __device__ void accept_prep_staged_body(const SysDev& s, const WalkDev& w, int w
       w.wm[wk] = m + 1;
       double* re = w.r + ((long)wk * N + e) * 3;
       re[0] = rx; re[1] = ry; re[2] = rz;
-      rl[3 * e] = rx; rl[3 * e + 1] = ry; rl[3 * e + 2] = rz;
       w.logabs[wk] = la + (log(fabs(R)) + dJ);
       if (R < 0.0) w.sign[wk] = -sg;
       w.J[wk] = jv + dJ;
@@ -595,12 +594,19 @@ __device__ void accept_prep_staged_body(const SysDev& s, const WalkDev& w, int w
   }
   __syncthreads();
 
-  // the set-up of e2: psi(r'), r', the Jastrow change
+  // the set-up of e2: psi(r'), r', the Jastrow change (with e at its new
+  // position when accepted)
   double* psi = w.psi_new + (long)wk * Lp;
-  for (int mu = tid; mu < Lp; mu += blockDim.x) psi[mu] = mu < L ? sps[mu] : 0.0;
+#pragma unroll
+  for (int k = 0; k < QL; ++k) {
+    const int mu = tid + 256 * k;
+    if (mu < Lp) psi[mu] = mu < L ? q.sv[k] : 0.0;
+  }
   if (tid < 3) w.r_new[3 * wk + tid] = tid == 0 ? px : (tid == 1 ? py : pz);
-  const double jn = jastrow_staged(s, rl, e2, px, py, pz, q, j2p);
-  const double jo = jastrow_staged(s, rl, e2, rl[3 * e2], rl[3 * e2 + 1], rl[3 * e2 + 2], q, j2p);
+  const bool me = acc && tid == e;
+  const double xj = me ? rx : q.ex, yj = me ? ry : q.ey, zj = me ? rz : q.ez;
+  const double jn = jastrow_staged(s, e2, px, py, pz, q, xj, yj, zj, j2p);
+  const double jo = jastrow_staged(s, e2, ox, oy, oz, q, xj, yj, zj, j2p);
   const double dJ2 = block_sum_mv(jn - jo, red);
   if (tid == 0) w.dJ[wk] = dJ2;
 
@@ -648,7 +654,7 @@ __device__ void accept_prep_staged_body(const SysDev& s, const WalkDev& w, int w
     double v = 0.0;
     bool keep = false;
     if (mu < L) {
-      v = sps[mu];
+      v = q.sv[k];
       keep = fabs(v) * q.xc[k] > thr;
     }
     const unsigned long long b = __ballot(keep);
@@ -684,12 +690,11 @@ accept_prep_staged_kernel(SysDev s, WalkDev w, int e, const double* __restrict__
   const int n = s.nu, kb = w.kb, N = s.N, L = s.L, Lp = s.Lp;
   const bool up = e < n, up2 = e2 < n;
   const int ie = up ? e : e - n, ie2 = up2 ? e2 : e2 - n;
-  const StageLayout ly = stage_layout(n, kb, N, Lp, mc);
+  const StageLayout ly = stage_layout(n, kb, mc);
   // bulk copies first
   lds_copy_async(lds + ly.V, w.wv + (long)wk * kb * n, 8 * mc * n);
   lds_copy_async(lds + ly.D, w.wd + (long)wk * kb * n, 8 * mc * n);
   lds_copy_async(lds + ly.S, w.wS + (long)wk * kb * kb, 8 * mc * kb);
-  lds_copy_async(lds + ly.r, w.r + (long)wk * N * 3, 8 * 3 * N);
   // per-thread loads, every address valid (indices past the ends read element 0)
   StagePre q;
 #pragma unroll
@@ -703,6 +708,8 @@ accept_prep_staged_kernel(SysDev s, WalkDev w, int e, const double* __restrict__
     q.nx = s.R[3 * a]; q.ny = s.R[3 * a + 1]; q.nz = s.R[3 * a + 2];
     q.nZ = s.Z[a];
     q.nb = s.j1_b[a];
+    const double* rj = w.r + ((long)wk * N + (tid < N ? tid : 0)) * 3;
+    q.ex = rj[0]; q.ey = rj[1]; q.ez = rj[2];
   }
   {
     const int j = tid < n ? tid : 0;
@@ -757,26 +764,21 @@ accept_prep_staged_kernel(SysDev s, WalkDev w, int e, const double* __restrict__
   const double rx = sc[8], ry = sc[9], rz = sc[10];
   const double px = sc[11] + sc[5], py = sc[12] + sc[6], pz = sc[13] + sc[7];
   const int m = ints_s[0];
-  double* sps = (double*)(lds + ly.psi);
   double* sv0 = (double*)(lds + ly.vec) + n;
   double* zo = sv0 + 2 * n;
   // psi(r') of e2
 #pragma unroll
-  for (int k = 0; k < QL; ++k) {
-    const int mu = tid + 256 * k;
-    const double v = basis_value_rec(q.bf[k], q.bk[k], px, py, pz);
-    if (mu < L) sps[mu] = v;
-  }
+  for (int k = 0; k < QL; ++k) q.sv[k] = basis_value_rec(q.bf[k], q.bk[k], px, py, pz);
   if (tid < n) sv0[tid] = q.a0;
   if (tid < kb) zo[tid] = q.z;
   __syncthreads();
   int32_t* cnt = accept_count ? accept_count + wk : nullptr;
   if (m <= mc)
     accept_prep_staged_body<T, true, QL>(s, w, wk, e, u, cnt, ints_s[1], S, e2, px, py, pz, R, dJ, m, mc, lds, q,
-                                         sc + 14, la, sg, jv, rx, ry, rz);
+                                         sc + 14, la, sg, jv, rx, ry, rz, sc[11], sc[12], sc[13]);
   else
     accept_prep_staged_body<T, false, QL>(s, w, wk, e, u, cnt, ints_s[1], S, e2, px, py, pz, R, dJ, m, mc, lds, q,
-                                          sc + 14, la, sg, jv, rx, ry, rz);
+                                          sc + 14, la, sg, jv, rx, ry, rz, sc[11], sc[12], sc[13]);
 }
 
 static hipError_t accept_launch(const SysDev& s, const WalkDev& w, int e, const uint8_t* acc,
@@ -805,11 +807,11 @@ hipError_t launch_metropolis_accept_prep(const SysDev& s, const WalkDev& w, int 
   const int S = propose_splits(s);
   const dim3 grid(w.Wk), blk(256);
   const int mc = std::max(0, std::min(since, w.kb - 1));
-  const StageLayout ly = stage_layout(s.nu, w.kb, s.N, s.Lp, mc);
+  const StageLayout ly = stage_layout(s.nu, w.kb, mc);
   // the direct copies move 16-byte granules: every walker's V, D, S^{-1} and
   // positions start 16-byte aligned
-  const bool aligned = ((uintptr_t)w.wv | (uintptr_t)w.wd | (uintptr_t)w.wS | (uintptr_t)w.r) % 16 == 0 &&
-                       ((long)w.kb * s.nu) % 2 == 0 && w.kb % 2 == 0 && s.N % 2 == 0;
+  const bool aligned = ((uintptr_t)w.wv | (uintptr_t)w.wd | (uintptr_t)w.wS) % 16 == 0 &&
+                       ((long)w.kb * s.nu) % 2 == 0 && w.kb % 2 == 0;
   if (s.nu <= kStageMaxN && s.N <= kStageMaxNe && s.n_nuc <= kStageMaxNuc && S > 0 && S <= kStageMaxSplits &&
       aligned &&
       ly.total <= kStageMaxLds) {
