@@ -499,8 +499,7 @@ __device__ void accept_prep_staged_body(const SysDev& s, const WalkDev& w, int w
                                         double rz, double ox, double oy, double oz) {
   __shared__ double red[16];
   __shared__ double gam_s;
-  __shared__ int wcount[4];
-  __shared__ int total;
+  __shared__ int wcnt[QL][4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
   const int n = s.nu, kb = w.kb, N = s.N, L = s.L, Lp = s.Lp;
   const bool up = e < n;
@@ -644,38 +643,30 @@ __device__ void accept_prep_staged_body(const SysDev& s, const WalkDev& w, int w
   const double thr = (c1 > 0.0) ? kScreenTol / ((double)L * c1) : 0.0;
   int* mk = w.muk + (long)wk * Lp;
   double* pk = w.psk + (long)wk * Lp;
-  if (tid == 0) total = 0;
-  __syncthreads();
+  // the kept functions in increasing mu: every slot's ballot first, one
+  // barrier, then each kept lane's place from the counts before it
+  unsigned long long bal[QL];
 #pragma unroll
   for (int k = 0; k < QL; ++k) {
-    const int base = 256 * k;
-    if (base >= L) break;
-    const int mu = base + tid;
-    double v = 0.0;
-    bool keep = false;
-    if (mu < L) {
-      v = q.sv[k];
-      keep = fabs(v) * q.xc[k] > thr;
-    }
-    const unsigned long long b = __ballot(keep);
-    if (lane == 0) wcount[wave] = __popcll(b);
-    __syncthreads();
-    int off = total;
-    for (int k2 = 0; k2 < wave; ++k2) off += wcount[k2];
-    if (keep) {
-      const int at = off + __popcll(b & ((1ull << lane) - 1ull));
-      mk[at] = mu;
-      pk[at] = v;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      int t = total;
-      for (int k2 = 0; k2 < nw; ++k2) t += wcount[k2];
-      total = t;
-    }
-    __syncthreads();
+    const int mu = 256 * k + tid;
+    const bool keep = mu < L && fabs(q.sv[k]) * q.xc[k] > thr;
+    bal[k] = __ballot(keep);
+    if (lane == 0) wcnt[k][wave] = __popcll(bal[k]);
   }
-  if (tid == 0) w.nkeep[wk] = total;
+  __syncthreads();
+  int off = 0;
+#pragma unroll
+  for (int k = 0; k < QL; ++k) {
+    int before = off;   // kept in earlier slots, then earlier waves of this slot
+    for (int k2 = 0; k2 < wave; ++k2) before += wcnt[k][k2];
+    if ((bal[k] >> lane) & 1ull) {
+      const int at = before + __popcll(bal[k] & ((1ull << lane) - 1ull));
+      mk[at] = 256 * k + tid;
+      pk[at] = q.sv[k];
+    }
+    for (int k2 = 0; k2 < nw; ++k2) off += wcnt[k][k2];
+  }
+  if (tid == 0) w.nkeep[wk] = off;
 }
 
 template <typename T, int QL>
