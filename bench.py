@@ -519,16 +519,18 @@ def lrdmc_leg(P, C, iters=10):
             "ratio_err_vs_oracle": float(f"{err:.3e}")}
 
 
-def large_leg(P, C, steps=128, Wk=256, fw=32):
+def large_leg(P, C, steps=128, Wk=256, fw=32, refined=False):
     """The 1024-electron workload (256 nuclei, L = 4096, Lambda banded at 8
-    bohr; n = 512 per spin, so the blocked Gauss-Jordan refresh), 256 walkers,
-    FP64: one evaluation and `steps` Metropolis moves (refresh after 64 moves
-    of one spin); error of the evaluation against the oracle on one walker;
-    forces through the adjoint on fw walkers."""
+    bohr; n = 512 per spin, so the blocked Gauss-Jordan refresh), 256 walkers:
+    one evaluation and `steps` Metropolis moves (refresh after 64 moves of one
+    spin); error of the evaluation against the oracle on one walker.  FP64:
+    forces through the adjoint on fw walkers.  refined: QMC_REFINED (int8
+    digit products skipping Lambda's zero tiles, screened proposals), with
+    the basis functions streamed per proposal."""
     from oracle import jagp as O
     dev = torch.device("cuda:0")
     w = C.large_256nuc_1024e(n_walkers=Wk)
-    sysh = P.JAGPSystem(w.system)
+    sysh = P.JAGPSystem(w.system, precision=P.QMC_REFINED if refined else P.QMC_FP64)
     wk = P.Walkers(sysh, Wk, adjoint=False)
     r = torch.tensor(w.r0, device=dev)
     d, u = C.chain_arrays(41, steps, Wk)
@@ -550,6 +552,18 @@ def large_leg(P, C, steps=128, Wk=256, fw=32):
     ref = O.evaluate(O.from_workload_system(w.system), torch.tensor(w.r0[:1]))
     err = {k: float(f"{float(((out[k].cpu()[:1] - ref[k]).abs() / ref[k].abs().clamp(min=1.0)).max()):.3e}")
            for k in ("logabs", "e_loc")}
+    rec = {"workload": "large_256nuc_1024e", "walkers": Wk, "precision": "refined" if refined else "fp64",
+           "eloc_evals_per_s": round(Wk / t_eval, 1), "moves_per_s": round(steps * Wk / t_move, 1),
+           "acceptance": round(cnt.sum().item() / (steps * Wk), 4), "moves": steps,
+           "err_vs_oracle": {"walkers": [0], **err},
+           "kernel_ms": {k: round(v[0], 3) for k, v in tim.items() if v[1]},
+           "kernel_launches": {k: v[1] for k, v in tim.items() if v[1]}}
+    if refined:
+        rec["screened_functions_per_proposal"] = round(wk.read(P.STATE_KEPT).mean().item(), 1)
+        rec["basis_functions"] = w.system.n_basis
+        wk.close()
+        sysh.close()
+        return rec
     wk.close()
     # forces via the adjoint on `fw` walkers (the reverse-pass workspace is
     # some 0.2 GB per walker at this size): one evaluation against one call
@@ -573,14 +587,9 @@ def large_leg(P, C, steps=128, Wk=256, fw=32):
     te, tf = float(np.median(te)), float(np.median(tf))
     wf.close()
     sysh.close()
-    return {"workload": "large_256nuc_1024e", "walkers": Wk, "precision": "fp64",
-            "eloc_evals_per_s": round(Wk / t_eval, 1), "moves_per_s": round(steps * Wk / t_move, 1),
-            "acceptance": round(cnt.sum().item() / (steps * Wk), 4), "moves": steps,
-            "err_vs_oracle": {"walkers": [0], **err},
-            "kernel_ms": {k: round(v[0], 3) for k, v in tim.items() if v[1]},
-            "kernel_launches": {k: v[1] for k, v in tim.items() if v[1]},
-            "forces": {"walkers": fw, "eval_ms": round(te, 3), "forces_ms": round(tf, 3),
-                       "forces_over_eval": round(tf / te, 2), "grad_evals_per_s": round(fw / (tf * 1e-3), 1)}}
+    rec["forces"] = {"walkers": fw, "eval_ms": round(te, 3), "forces_ms": round(tf, 3),
+                     "forces_over_eval": round(tf / te, 2), "grad_evals_per_s": round(fw / (tf * 1e-3), 1)}
+    return rec
 
 
 def pfaffian_leg(P, C, steps=160, Wk=512):
@@ -828,6 +837,11 @@ def main():
         res["multi_system"] = multi_leg(P, C)
         res["multi_system_bf16"] = multi_leg(P, C, precision="bf16")
         res["large"] = large_leg(P, C)
+        res["large_refined"] = large_leg(P, C, refined=True)
+        res["large_refined_over_fp64_moves"] = round(res["large_refined"]["moves_per_s"] /
+                                                     res["large"]["moves_per_s"], 3)
+        res["large_refined_over_fp64_evals"] = round(res["large_refined"]["eloc_evals_per_s"] /
+                                                     res["large"]["eloc_evals_per_s"], 3)
         res["lrdmc"] = lrdmc_leg(P, C)
         res["pfaffian"] = pfaffian_leg(P, C)
         res["sr"] = sr_leg(P)
