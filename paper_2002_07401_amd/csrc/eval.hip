@@ -333,6 +333,15 @@ __global__ void set_lambda_kernel(SysDev s, const double* __restrict__ lam) {
     s.lam32[(long)i * s.Lp + j] = (float)v;
     s.lamT32[(long)j * s.Lp + i] = (float)v;
   }
+  if (s.lamB) {   // hi / lo BF16 pair of v at (j, i) of Lambda^T's copy and (i, j) of Lambda's
+    const long pl = (long)s.Lp * s.Lp;
+    const bf16s hi(v);
+    const bf16s lo(v - (double)hi);
+    s.lamB[(long)j * s.Lp + i] = hi.x;
+    s.lamB[pl + (long)j * s.Lp + i] = lo.x;
+    s.lamB[2 * pl + (long)i * s.Lp + j] = hi.x;
+    s.lamB[3 * pl + (long)i * s.Lp + j] = lo.x;
+  }
 }
 
 // bfn[mu] = (centre of mu, zeta_mu) over the basis functions (the primitives

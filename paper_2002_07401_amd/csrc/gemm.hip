@@ -261,9 +261,121 @@ static hipError_t P_build_t(const SysDev& s, const WalkDev& w, int halves, hipSt
   return e;
 }
 
+// ---------------------------------------------------------------------------
+// BF16 rows (QMC_MIXED_BF16): P = Phi Lambda on the BF16 matrix cores.  Phi is
+// stored in BF16 (exact operand); Lambda enters as an unevaluated pair
+// hi + lo of BF16 values (lo = bf16(Lambda - hi), Lambda to about 16
+// significant bits), two v_mfma_f32_16x16x32_bf16 per block and K step, FP32
+// accumulation, and the result rounded once to the BF16 rows.  The operand
+// split keeps Lambda's share of the error far below the rows' own BF16
+// rounding.  256 threads as 2 x 2 waves over a 64 x 64 tile, 32 x 32 per wave
+// as 2 x 2 blocks of 16 x 16; K steps of 32 staged through LDS (rows of 32
+// BF16 values, padded to 40), the next step loaded into registers while the
+// current one multiplies.  Operand layout of the instruction: lane l holds row
+// (column) l % 16 of A (B), k = 8 (l / 16) .. 8 (l / 16) + 7; accumulator
+// register r of lane l is row 4 (l / 16) + r, column l % 16.
+// ---------------------------------------------------------------------------
+typedef __bf16 bfx8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+struct PBf16Args {
+  const uint16_t* A; long lda; int a_grp; long a_gs;   // rows m: (m / a_grp) a_gs + (m % a_grp) lda
+  const uint16_t* Bh; const uint16_t* Bl; long ldb;    // [N][K] hi and lo
+  uint16_t* C; long ldc; int c_grp; long c_gs;
+  int M, N, K;
+};
+
+__global__ void __launch_bounds__(256) p_bf16_kernel(PBf16Args g, int gx) {
+  constexpr int BK = 32, LD = 40;
+  __shared__ __align__(16) uint16_t As[64][LD];
+  __shared__ __align__(16) uint16_t Bh[64][LD];
+  __shared__ __align__(16) uint16_t Bl[64][LD];
+  const long L = xcd_remap(blockIdx.x, (long)gridDim.x);
+  const int bx = (int)(L % gx), by = (int)(L / gx);
+  const int m0 = 64 * by, n0 = 64 * bx;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  // staging: thread t moves 8 values (16 bytes) of row / column t / 4, k = 8 (t % 4)
+  const int sr = tid >> 2, sk = 8 * (tid & 3);
+  const int gm = m0 + sr, gn = n0 + sr;
+  const bool aok = gm < g.M, bok = gn < g.N;
+  const uint16_t* ap = g.A + (aok ? (long)(gm / g.a_grp) * g.a_gs + (long)(gm % g.a_grp) * g.lda : 0) + sk;
+  const uint16_t* bhp = g.Bh + (bok ? (long)gn * g.ldb : 0) + sk;
+  const uint16_t* blp = g.Bl + (bok ? (long)gn * g.ldb : 0) + sk;
+  const u16x8 zero = {0, 0, 0, 0, 0, 0, 0, 0};
+  u16x8 ra, rh, rl;
+  auto load = [&](int k0) {
+    ra = aok ? *(const u16x8*)(ap + k0) : zero;
+    rh = bok ? *(const u16x8*)(bhp + k0) : zero;
+    rl = bok ? *(const u16x8*)(blp + k0) : zero;
+  };
+  fx4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = fx4{0.f, 0.f, 0.f, 0.f};
+  load(0);
+  const int fr = lane & 15, fk = 8 * (lane >> 4);
+  for (int k0 = 0; k0 < g.K; k0 += BK) {
+    __syncthreads();   // the previous step's reads are done
+    *(u16x8*)&As[sr][sk] = ra;
+    *(u16x8*)&Bh[sr][sk] = rh;
+    *(u16x8*)&Bl[sr][sk] = rl;
+    __syncthreads();
+    if (k0 + BK < g.K) load(k0 + BK);
+    bfx8 a[2], bh[2], bl[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      a[i] = __builtin_bit_cast(bfx8, *(const u16x8*)&As[32 * wm + 16 * i + fr][fk]);
+      bh[i] = __builtin_bit_cast(bfx8, *(const u16x8*)&Bh[32 * wn + 16 * i + fr][fk]);
+      bl[i] = __builtin_bit_cast(bfx8, *(const u16x8*)&Bl[32 * wn + 16 * i + fr][fk]);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bh[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bl[j], acc[i][j], 0, 0, 0);
+      }
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + 32 * wm + 16 * i + 4 * (lane >> 4) + r;
+        const int n = n0 + 32 * wn + 16 * j + fr;
+        if (m < g.M && n < g.N)
+          g.C[(long)(m / g.c_grp) * g.c_gs + (long)(m % g.c_grp) * g.ldc + n] = bf16s(acc[i][j][r]).x;
+      }
+}
+
+static hipError_t P_build_bf16(const SysDev& s, const WalkDev& w, int halves, hipStream_t st) {
+  if (!s.lamB || s.Lp % 32 != 0) return hipErrorInvalidValue;
+  const long rowst = (long)s.N * s.Lp, pl = (long)s.Lp * s.Lp;
+  const uint16_t* phi = (const uint16_t*)w.phi;
+  uint16_t* P = (uint16_t*)w.P;
+  for (int h = 0; h < 2; ++h) {
+    if (!((halves >> h) & 1)) continue;
+    const int rows = h == 0 ? s.nu : s.nd;
+    if (rows == 0) continue;
+    PBf16Args g;
+    g.A = phi + (h == 0 ? 0 : (long)s.nu * s.Lp); g.lda = s.Lp; g.a_grp = rows; g.a_gs = rowst;
+    g.Bh = s.lamB + 2 * h * pl; g.Bl = s.lamB + (2 * h + 1) * pl; g.ldb = s.Lp;
+    g.C = P + (h == 0 ? 0 : (long)s.nu * s.Lp); g.ldc = s.Lp; g.c_grp = rows; g.c_gs = rowst;
+    g.M = w.Wk * rows; g.N = s.Lp; g.K = s.Lp;
+    const int gx = (g.N + 63) / 64, gy = (g.M + 63) / 64;
+    hipLaunchKernelGGL(p_bf16_kernel, dim3((unsigned)((long)gx * gy)), dim3(256), 0, st, g, gx);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_P_build(const SysDev& s, const WalkDev& w, int halves, hipStream_t st, void* lo,
                           bool lo_bf16) {
-  if (s.bf16()) return P_build_t<bf16s, float>(s, w, halves, st, s.lam32, s.lamT32);
+  if (s.bf16()) return P_build_bf16(s, w, halves, st);
   if (s.f32()) return P_build_t<float>(s, w, halves, st, s.lam32, s.lamT32);
   return P_build_t<double>(s, w, halves, st, s.lam, s.lamT, lo, lo_bf16);
 }

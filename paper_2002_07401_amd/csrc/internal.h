@@ -97,6 +97,9 @@ struct SysDev {
   double* lamT;     // [Lp][Lp]  Lambda^T
   float* lam32;     // [Lp][Lp]  FP32 copies (precision QMC_W_FP32)
   float* lamT32;
+  uint16_t* lamB;   // QMC_MIXED_BF16: [2][2][Lp][Lp] BF16, half h (0: Lambda^T, the
+                    // transposed operand of P_up = Phi_up Lambda; 1: Lambda, of
+                    // P_dn = Phi_dn Lambda^T), hi then lo = bf16(x - hi)
   int* cptr;        // [A+1] basis functions of nucleus a: cmu[cptr[a] .. cptr[a+1])
   int* cmu;         // [L]
   double4* bfn;     // [L] packed (x, y, z) of the function's centre and its zeta

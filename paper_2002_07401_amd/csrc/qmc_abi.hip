@@ -444,6 +444,22 @@ extern "C" qmc_status qmc_system_create(const qmc_system_desc* desc, qmc_system*
     e = up((void**)&d.lam32, l32.data(), sizeof(float) * l32.size());
     if (!e) e = up((void**)&d.lamT32, lT32.data(), sizeof(float) * lT32.size());
   }
+  if (!e && d.bf16()) {
+    // BF16 hi / lo pairs of Lambda^T and Lambda, [n][k] with k contiguous:
+    // the operands of the BF16 matrix-core P rebuilds
+    const size_t pl = (size_t)Lp * Lp;
+    std::vector<uint16_t> b(4 * pl);
+    for (size_t h = 0; h < 2; ++h) {
+      const std::vector<double>& src = h == 0 ? lamT : lam;
+      for (size_t k = 0; k < pl; ++k) {
+        const bf16s hi(src[k]);
+        const bf16s lo(src[k] - (double)hi);
+        b[(2 * h) * pl + k] = hi.x;
+        b[(2 * h + 1) * pl + k] = lo.x;
+      }
+    }
+    e = up((void**)&d.lamB, b.data(), sizeof(uint16_t) * b.size());
+  }
   if (!e) {
     const size_t mb = (size_t)((Lp + kLamTileK - 1) / kLamTileK) * ((Lp + kLamTileN - 1) / kLamTileN);
     std::vector<uint8_t> ones(mb, 1);
