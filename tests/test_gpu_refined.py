@@ -121,3 +121,45 @@ def test_refined_refusals():
     with pytest.raises(P.QMCError) as ei:
         P.MultiSystem([wk])
     assert ei.value.code == -5
+
+
+def test_refined_far_proposal_keeps_nothing_and_ratio_is_zero():
+    # A proposal 1000 bohr from every nucleus: every basis value at r' is 0 in
+    # FP64 (e^{-zeta r^2} underflows), so the screening keeps no function and
+    # the determinant ratio is exactly 0, as the oracle's (the Jastrow factor
+    # stays finite); the device Metropolis rejects it.
+    P = need_gpu()
+    w = C.mol_40nuc_160e(n_walkers=4)
+    _, wk = _walkers(P, w, 4)
+    r = torch.tensor(w.r0)
+    wk.eval_batch(r.cuda())
+    rn = r[:, 11].clone()
+    rn[:, 0] += 1000.0
+    ratio = wk.propose(11, rn.cuda().contiguous())
+    kept = wk.read(P.STATE_KEPT).cpu()
+    torch.cuda.synchronize()
+    ref = O.move_ratio(O.from_workload_system(w.system), r, 11, rn)
+    print(f"[refined far proposal] kept {kept.tolist()} ratio {ratio.cpu().tolist()} oracle {ref.tolist()}")
+    assert (kept == 0).all()
+    assert (ratio.cpu() == 0.0).all() and (ref == 0.0).all()
+
+
+@pytest.mark.parametrize("Wk", [1, 13])
+def test_refined_ragged_walker_counts(Wk):
+    # one walker, and 13 walkers (1040 rows of the int8 products: a partial
+    # 128-row tile; walker count not a multiple of the 8 XCDs): evaluation and
+    # a 40-step chain against the oracle
+    P = need_gpu()
+    w = C.mol_40nuc_160e(n_walkers=Wk)
+    _, wk = _walkers(P, w, Wk)
+    r = torch.tensor(w.r0[:Wk])
+    out = wk.eval_batch(r.cuda())
+    d, u = C.chain_arrays(91, 40, Wk)
+    wk.vmc_steps(70, torch.tensor(d, device="cuda"), torch.tensor(u, device="cuda"))
+    rg = wk.read(P.STATE_R).cpu()
+    torch.cuda.synchronize()
+    sy = O.from_workload_system(w.system)
+    ref = O.evaluate(sy, r)
+    assert rel_err(out["e_loc"].cpu(), ref["e_loc"]).max().item() <= 1e-8
+    rf, _, _ = O.run_chain(sy, r, torch.tensor(d), torch.tensor(u), e_start=70)
+    assert torch.equal(rg, rf)
