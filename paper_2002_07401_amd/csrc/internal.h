@@ -590,6 +590,7 @@ hipError_t launch_refresh_finish(const SysDev& s, const WalkDev& w, int32_t* sta
 // max |W X - I| per walker (P = W X given) and status 3 where it exceeds tol
 hipError_t launch_refresh_residual(const double* Pm, int n, int Wk, double tol, double* res, int32_t* status,
                                    hipStream_t st);
+// scratch: [Wk][2][kb][n]
 hipError_t launch_materialize_inverse(const SysDev& s, const WalkDev& w, bool down, double* scratch, double* dst,
                                       hipStream_t st);
 // moves that fit the delayed-update buffer between refreshes

@@ -842,8 +842,12 @@ __global__ void refresh_finish_kernel(WalkDev w, int32_t* __restrict__ status) {
 }
 
 // W^{-1} of every walker from the refresh inverse A0 and the delayed updates
-// (state read-out).  up: A0 - V S^{-1} (D^T A0); down: A0 - (A0 D) S^{-T} V^T.
-// G = D^T A0 (up, [m][n]) or (A0 D)^T (down, [m][n]) goes through `scratch`.
+// (state read-out and the drift check before a refresh).  up: A0 - V^T S^{-1} (D A0);
+// down: A0 - (D A0^T)^T S^{-T} V, with V, D [m][n] the buffered rows.  Three
+// passes over one workgroup per walker, through `scratch` ([Wk][2][kb][n]):
+//   G = D A0 (up) or D A0^T (down)                      [m][n]
+//   H = S^{-1} G (up) or S^{-T} V (down)               [m][n]
+//   X = A0 - V^T H (up) or A0 - G^T H (down)            [n][n]
 __global__ void __launch_bounds__(256)
 materialize_inverse_kernel(SysDev s, WalkDev w, int down, double* __restrict__ scratch, double* __restrict__ dst) {
   const int wk = blockIdx.x, tid = threadIdx.x;
@@ -852,30 +856,31 @@ materialize_inverse_kernel(SysDev s, WalkDev w, int down, double* __restrict__ s
   const double* D = w.wd + (long)wk * kb * n;
   const double* V = w.wv + (long)wk * kb * n;
   const double* Si = w.wS + (long)wk * kb * kb;
-  double* G = scratch + (long)wk * kb * n;
+  double* G = scratch + (long)wk * 2 * kb * n;
+  double* H = G + (long)kb * n;
   double* out = dst + (long)wk * n * n;
   for (int idx = tid; idx < m * n; idx += blockDim.x) {
     const int l = idx / n, j = idx % n;
     double g = 0.0;
     if (!down) for (int i = 0; i < n; ++i) g += D[(long)l * n + i] * A0[(long)i * n + j];
-    else for (int i = 0; i < n; ++i) g += A0[(long)j * n + i] * D[(long)l * n + i];
-    G[(long)l * n + j] = g;
+    else for (int i = 0; i < n; ++i) g += D[(long)l * n + i] * A0[(long)j * n + i];
+    G[idx] = g;
   }
   __syncthreads();
+  for (int idx = tid; idx < m * n; idx += blockDim.x) {
+    const int k = idx / n, j = idx % n;
+    double h = 0.0;
+    if (!down) for (int l = 0; l < m; ++l) h += Si[k * kb + l] * G[(long)l * n + j];
+    else for (int l = 0; l < m; ++l) h += Si[l * kb + k] * V[(long)l * n + j];
+    H[idx] = h;
+  }
+  __syncthreads();
+  const double* Lf = down ? G : V;   // left factor, read as its transpose
   for (int idx = tid; idx < n * n; idx += blockDim.x) {
     const int i = idx / n, j = idx % n;
-    double corr = 0.0;
-    for (int k = 0; k < m; ++k) {
-      double h = 0.0;
-      if (!down) {   // (V S^{-1} G)[i][j]
-        for (int l = 0; l < m; ++l) h += Si[k * kb + l] * G[(long)l * n + j];
-        corr += V[(long)k * n + i] * h;
-      } else {       // (G^T S^{-T} V)[i][j]
-        for (int l = 0; l < m; ++l) h += Si[l * kb + k] * V[(long)l * n + j];
-        corr += G[(long)k * n + i] * h;
-      }
-    }
-    out[idx] = A0[idx] - corr;
+    double c = 0.0;
+    for (int k = 0; k < m; ++k) c += Lf[(long)k * n + i] * H[(long)k * n + j];
+    out[idx] = A0[idx] - c;
   }
 }
 

@@ -141,7 +141,7 @@ struct qmc_walkers {
   long attempts = 0;
   int since = 0;        // attempted moves since the last refresh
   int buf_spin = -1;    // spin of the moves in the delayed-update buffer (-1: empty)
-  double* rd_scratch = nullptr;   // [Wk][kb][n] state read-out work
+  double* rd_scratch = nullptr;   // [Wk][2][kb][n] materialised-inverse work (read-out, drift check)
   double* res_x = nullptr;        // [Wk][n][n] refresh check: the inverse being replaced
   double* res_p = nullptr;        // [Wk][n][n] W times it
   double* res_v = nullptr;        // [Wk] max |W X - I| of the last checked refresh
@@ -578,7 +578,7 @@ static void walker_layout(const SysDev& s, int n_walkers, bool adjoint, Carver& 
     c.take(&d.cvec, sizeof(double) * Wk * n);
     c.take(&d.v0, sizeof(double) * Wk * n);
     c.take(&d.tz, sizeof(double) * Wk * 2 * kb);
-    c.take(&wk.rd_scratch, sizeof(double) * Wk * kb * n);
+    c.take(&wk.rd_scratch, sizeof(double) * Wk * 2 * kb * n);
     // refresh residual check: the inverse being replaced and W times it
     c.take(&wk.res_x, sizeof(double) * Wk * nsq);
     c.take(&wk.res_p, sizeof(double) * Wk * nsq);
