@@ -331,16 +331,40 @@ __global__ void __launch_bounds__(256) propose_screened_blk_kernel(SysDev s, Wal
 
 // Column maxima of the P halves (bit 0: up rows, bit 1: down rows):
 // cmax[w][h][mu] = max over the rows i of half h of |P[w][i][mu]|.
+// One workgroup per (walker, half), columns in chunks of 512: wave v takes the
+// rows v, v + 4, ..., each lane the columns lane + 64 c of the chunk (all
+// eight loaded per row together), and the four waves' maxima meet in LDS (a
+// maximum does not depend on the order).
 __global__ void __launch_bounds__(256) screen_colmax_kernel(SysDev s, WalkDev w, int halves) {
+  constexpr int CM = 8;
+  __shared__ double part[4][64 * CM];
   const int wk = blockIdx.x, h = blockIdx.y;
   if (!((halves >> h) & 1)) return;
-  const int i0 = h == 0 ? 0 : s.nu, n = h == 0 ? s.nu : s.nd;
-  const double* P = (const double*)w.P + ((long)wk * s.N + i0) * s.Lp;
-  double* out = w.cmax + ((long)wk * 2 + h) * s.Lp;
-  for (int mu = threadIdx.x; mu < s.Lp; mu += blockDim.x) {
-    double m = 0.0;
-    for (int i = 0; i < n; ++i) m = fmax(m, fabs(P[(long)i * s.Lp + mu]));
-    out[mu] = m;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i0 = h == 0 ? 0 : s.nu, n = h == 0 ? s.nu : s.nd, Lp = s.Lp;
+  const double* P = (const double*)w.P + ((long)wk * s.N + i0) * Lp;
+  double* out = w.cmax + ((long)wk * 2 + h) * Lp;
+  for (int c0 = 0; c0 < Lp; c0 += 64 * CM) {
+    double m[CM];
+#pragma unroll
+    for (int c = 0; c < CM; ++c) m[c] = 0.0;
+    for (int i = wave; i < n; i += 4) {
+      const double* row = P + (long)i * Lp + c0;
+      double v[CM];
+#pragma unroll
+      for (int c = 0; c < CM; ++c) {
+        const int mu = lane + 64 * c;
+        v[c] = c0 + mu < Lp ? __builtin_nontemporal_load(row + mu) : 0.0;
+      }
+#pragma unroll
+      for (int c = 0; c < CM; ++c) m[c] = fmax(m[c], fabs(v[c]));
+    }
+    __syncthreads();   // the previous chunk's maxima are written out
+#pragma unroll
+    for (int c = 0; c < CM; ++c) part[wave][lane + 64 * c] = m[c];
+    __syncthreads();
+    for (int mu = tid; mu < 64 * CM && c0 + mu < Lp; mu += blockDim.x)
+      out[c0 + mu] = fmax(fmax(part[0][mu], part[1][mu]), fmax(part[2][mu], part[3][mu]));
   }
 }
 
