@@ -787,7 +787,7 @@ def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU: the walker batch of one MI355X is the unit measured here; "
-              "multi-GPU runs are not part of this build.", file=sys.stderr)
+              "multi-GPU runs are not supported.", file=sys.stderr)
         sys.exit(2)
     import paper_2002_07401_amd as P
     from workloads import configs as C

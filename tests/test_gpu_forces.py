@@ -5,7 +5,7 @@ differences of the GPU's own evaluation.
 Bars: against the oracle, |g_gpu - g_ref| <= 1e-8 * max(1, max|g_ref|) per
 output array (FP64 on both sides; the tolerance leaves room for the condition
 of W, which enters through W^{-1} twice in the local-energy gradient).  Against
-central differences with h = 1e-5: 1e-6 * max(1, |g_fd|) (spec bar).
+central differences with h = 1e-5: 1e-6 * max(1, |g_fd|) (the gradient bar).
 """
 import numpy as np
 import pytest

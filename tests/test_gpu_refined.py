@@ -3,7 +3,7 @@ products (evaluation and the P rebuilds between moves) and screened FP64
 proposals.
 
 * Evaluation: log|Psi|, E_kin, E_loc within 1e-8 (the mixed bar of these tests;
-  the spec bar is 1e-6) and drift within 1e-8 of the oracle.
+  the mixed path's bar is 1e-6) and drift within 1e-8 of the oracle.
 * Proposals: ratios of host-driven proposals against the oracle's full
   re-evaluations (1e-8), with and without the drift at r' (the drift request
   takes the dense FP64 rows); the screening really skips functions and keeps

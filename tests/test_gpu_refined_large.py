@@ -5,7 +5,7 @@ inverse, refresh after 64 moves of one spin, the unstaged set-up and the
 wide screened proposal kernel).
 
 * Evaluation against the oracle at the mixed bar used by every refined test
-  (1e-8 relative on log|Psi| and E_loc; the spec bar is 1e-6).
+  (1e-8 relative on log|Psi| and E_loc; the mixed path's bar is 1e-6).
 * Proposal ratios of up and down electrons against the oracle's ratio of two
   full evaluations (1e-8), with the screened kept count strictly inside (0, L).
 * 24 Metropolis steps of two walkers: positions equal to the oracle's chain on
