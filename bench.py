@@ -108,7 +108,7 @@ def copy_probe(mib):
     del src, dst
 
 
-def kernel_models(s, Wk, esz, acc_rate, kept=None):
+def kernel_models(s, Wk, esz, acc_rate, kept=None, p_rows=None):
     """Algorithmic bytes / flops per launch of the main kernels.
 
     propose (the streaming kernel): every walker reads the N_other x L rows of P
@@ -133,9 +133,11 @@ def kernel_models(s, Wk, esz, acc_rate, kept=None):
              restarts at every refresh (after min(refresh_every, 64) moves of
              one spin and at each change of spin) and grows by the
              acceptance rate per move.
-    P_build: the evaluation's P = Phi Lambda for both spins, 2 L^2 flops per
-             basis row over Wk * N rows (the one-spin rebuilds before moves
-             have a timer of their own).
+    P_build: the evaluation's P = Phi Lambda, 2 L^2 flops per basis row over
+             Wk * p_rows rows: p_rows = N when both spins are built, n_dn
+             when the evaluation at the chain's current positions finds the up
+             rows current (the one-spin rebuilds before moves have a timer of
+             their own).
     """
     L, N, n = s.n_basis, s.n_up + s.n_dn, s.n_up
     cap = min(s.refresh_every, 64)
@@ -150,7 +152,7 @@ def kernel_models(s, Wk, esz, acc_rate, kept=None):
                 + acc_rate * (8 * L + 16 * n + 8 * (m + 1) ** 2 + 8 * n + esz * L)
                 + 8 * Lp + 16 * n + 16 * m
                 + (8 * L + 12 * kept if kept is not None else 0))
-    pflops = 2.0 * L * L * Wk * N
+    pflops = 2.0 * L * L * Wk * (N if p_rows is None else p_rows)
     return {"propose": ("hbm", prop), "accept": ("hbm", acc), "P_build": ("mfma", pflops)}
 
 
@@ -232,16 +234,15 @@ def run_precision(P, C, w, args, precision):
     disp = torch.tensor(disp, device=dev).view(n_tot + 1, N, Wk, 3)
     unif = torch.tensor(unif, device=dev).view(n_tot + 1, N, Wk)
     cnt = torch.zeros(Wk, dtype=torch.int32, device=dev)
-    r_cur = torch.tensor(w.r0, device=dev)
+    wk.eval_batch(torch.tensor(w.r0, device=dev), drift=True)   # the starting positions
 
     def step(k, ev=None):
-        nonlocal r_cur
+        # E_loc at the chain's current positions, then one sweep of moves
         if ev: ev[0].record()
-        wk.eval_batch(r_cur, drift=True)
+        wk.eval_batch(None, drift=True)
         if ev: ev[1].record()
         wk.vmc_steps(0, disp[k], unif[k], cnt)
         if ev: ev[2].record()
-        r_cur = wk.read(P.STATE_R)
 
     for k in range(args.warmup):
         step(k)
@@ -269,6 +270,7 @@ def run_precision(P, C, w, args, precision):
     acc_rate = n_acc / moves
 
     # screened proposals: basis functions streamed per proposal over one sweep
+    r_cur = wk.read(P.STATE_R)
     kept = None
     if screened:
         ks = []
@@ -307,7 +309,12 @@ def run_precision(P, C, w, args, precision):
     # roofline of the dominant kernel among those with a model (proposal
     # stream, fused accept, P product: largest summed time in the timed
     # steps); the kernel with the largest summed time overall is named beside it
-    models = kernel_models(s, Wk, esz, acc_rate, kept)
+    # the timed evaluations run at the chain's positions after full sweeps: in
+    # FP64, FP32 and the refined mode the up rows of P are current from the
+    # rebuild between the halves of the sweep, and their P_build builds the
+    # down rows only (the other modes rebuild their FP64 P for both spins)
+    p_rows = s.n_dn if precision in ("fp64", "fp32", "mixed") else N
+    models = kernel_models(s, Wk, esz, acc_rate, kept, p_rows)
     dominant = max(one, key=lambda k: one[k][0])
     dom = max((k for k in models if tim.get(k, (0.0, 0))[1]), key=lambda k: tim[k][0])
     bound, units = models[dom]
@@ -326,7 +333,7 @@ def run_precision(P, C, w, args, precision):
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
                 "flops_per_launch": int(units), "avg_launch_us": round(avg_ms * 1e3, 2)}
     steps = step_rooflines(s, Wk, precision, one, roof if roof["kernel"] == "propose" else
-                           prop_roofline(models, tim), models["accept"][1])
+                           prop_roofline(models, tim), models["accept"][1], p_rows)
     # MFMA use of the geminal build's dominant product (P = Phi Lambda in the
     # evaluations of the timed steps).  Refined modes: int8 operations of the
     # digit products (the P_build timer also covers the digit split) against
@@ -337,16 +344,17 @@ def run_precision(P, C, w, args, precision):
         wmfma = {"kernel": "P_build", "instruction": "v_mfma_f64_16x16x4f64" if precision == "fp64"
                  else "v_mfma_f32_16x16x4f32", "achieved": round(pf_tf, 2), "peak": MFMA_PEAK_TFLOPS[precision],
                  "unit": "TFLOP/s", "frac": round(pf_tf / MFMA_PEAK_TFLOPS[precision], 4),
-                 "flops_per_launch": int(models["P_build"][1]), "avg_launch_us": round(pf_ms * 1e3, 2)}
+                 "flops_per_launch": int(models["P_build"][1]), "rows_per_walker": p_rows,
+                 "avg_launch_us": round(pf_ms * 1e3, 2)}
     else:
         Lp = (s.n_basis + 31) // 32 * 32
-        ops = 2.0 * Lp * Lp * N * Wk * OZ_DIGITS * (OZ_DIGITS + 1) // 2
+        ops = 2.0 * Lp * Lp * p_rows * Wk * OZ_DIGITS * (OZ_DIGITS + 1) // 2
         int8 = ops / (pf_ms * 1e-3) / 1e12
         wmfma = {"kernel": "P_build", "instruction": "v_mfma_i32_32x32x32_i8", "achieved": round(int8, 1),
                  "peak": INT8_PEAK_TOPS, "unit": "TOP/s", "frac": round(int8 / INT8_PEAK_TOPS, 4),
                  "ops_per_launch": int(ops), "digit_products": OZ_DIGITS * (OZ_DIGITS + 1) // 2,
                  "fp64_equivalent_TFLOPs": round(models["P_build"][1] / (pf_ms * 1e-3) / 1e12, 2),
-                 "avg_launch_us": round(pf_ms * 1e3, 2)}
+                 "rows_per_walker": p_rows, "avg_launch_us": round(pf_ms * 1e3, 2)}
     wk.close()
     sysh.close()
     return {
@@ -741,28 +749,37 @@ def achievable_peaks():
             "datasheet": {"hbm_GBps": HBM_PEAK_GBS, "fp64_TFLOPs": 78.6, "fp32_TFLOPs": 157.3}}
 
 
-def step_rooflines(s, Wk, precision, one, prop_roof, acc_model=None):
+def step_rooflines(s, Wk, precision, one, prop_roof, acc_model=None, p_rows=None):
     """Roofline of each step of one evaluation (and the proposal) from the
     one-step timers: algorithmic bytes or flops per launch / average launch.
       basis:   writes the N x L values of every walker (FP64; FP32 in fp32 mode)
-      P_build: 2 L^2 N flops per walker (MFMA; FP64 but in fp32 mode); the
-               refined modes count the int8 operations of their 28 digit
-               products, 2 Lp^2 N x 28 per walker (Lp = L rounded up to 32)
+      P_build: 2 L^2 flops per basis row built, p_rows rows per walker (N,
+               or n_dn when the up rows are reused; MFMA; FP64 but in fp32
+               mode); the refined modes count the int8 operations of their 28
+               digit products, 2 Lp^2 x 28 per row (Lp = L rounded up to 32)
+      P_rebuild (fp64, fp32, mixed): the same per row over the n_up rows
+               rebuilt before the down electrons move
       W_build: 2 n_up n_dn L flops per walker (FP64 MFMA accumulation)
       LU:      2 n^3 flops per walker per launch (FP64 vector ALU, latency-bound
                at n = 80: one workgroup per walker)
       Y_build: 2 x 2 n^2 L flops per walker (FP64 MFMA)"""
     L, N, nu, nd = s.n_basis, s.n_up + s.n_dn, s.n_up, s.n_dn
+    pr = N if p_rows is None else p_rows
+
+    def p_model(rows):
+        if precision in ("fp64", "fp32"):
+            return ("mfma", 2.0 * L * L * rows * Wk, MFMA_PEAK_TFLOPS[precision], "TFLOP/s", 1e12)
+        return ("mfma", 2.0 * ((L + 31) // 32 * 32) ** 2 * rows * Wk * OZ_DIGITS * (OZ_DIGITS + 1) // 2,
+                INT8_PEAK_TOPS, "TOP/s", 1e12)
     models = {
         "basis": ("hbm", Wk * N * L * (4 if precision == "fp32" else 8), HBM_PEAK_GBS, "GB/s", 1e9),
-        "P_build": (("mfma", 2.0 * L * L * N * Wk, MFMA_PEAK_TFLOPS[precision], "TFLOP/s", 1e12)
-                    if precision in ("fp64", "fp32") else
-                    ("mfma", 2.0 * ((L + 31) // 32 * 32) ** 2 * N * Wk * OZ_DIGITS * (OZ_DIGITS + 1) // 2,
-                     INT8_PEAK_TOPS, "TOP/s", 1e12)),
+        "P_build": p_model(pr),
         "W_build": ("mfma", 2.0 * nu * nd * L * Wk, 78.6, "TFLOP/s", 1e12),
         "LU": ("alu", 2.0 * nu ** 3 * Wk, 78.6, "TFLOP/s", 1e12),
         "Y_build": ("mfma", 4.0 * nu * nu * L * Wk, 78.6, "TFLOP/s", 1e12),
     }
+    if precision in ("fp64", "fp32", "mixed"):
+        models["P_rebuild"] = p_model(nu)
     out = {}
     for k, (bound, units, peak, unit, scale) in models.items():
         ms, cnt = one.get(k, (0.0, 0))

@@ -243,7 +243,14 @@ qmc_status qmc_walkers_set_drift_tol(qmc_walkers *wk, double tol);
 
 /* Evaluate every walker from scratch at positions r and make that the walkers'
  * state.  (Local energy definition, VMC section; eq:wfAGPs; agp_expansion.)
- *   r      [Wk][N][3]  device, read
+ *   r      [Wk][N][3]  device, read; or NULL: the walkers' current positions
+ *                      (those of the last evaluation with the moves accepted
+ *                      since).  Then, in QMC_FP64, QMC_W_FP32 and QMC_REFINED,
+ *                      the P rows of a spin none of whose electrons has been
+ *                      proposed since the rows were last built are reused (the
+ *                      rebuild between the halves of a sweep leaves the up rows
+ *                      current for the next evaluation); QMC_ERR_STATE before
+ *                      the first evaluation.
  *   logabs [Wk]        device, write: log|Psi|
  *   sign   [Wk]        device, write: sign(Psi) = sign(det W); 0 when singular
  *   drift  [Wk][N][3]  device, write, may be NULL: grad_i log|Psi|

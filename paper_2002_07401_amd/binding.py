@@ -310,10 +310,11 @@ class Walkers:
         except Exception:
             pass
 
-    def eval_batch(self, r: torch.Tensor, drift=True, stream=None) -> Dict[str, torch.Tensor]:
-        dev = r.device
+    def eval_batch(self, r: Optional[torch.Tensor], drift=True, stream=None) -> Dict[str, torch.Tensor]:
+        """Evaluate at positions r, or (r None) at the walkers' current positions."""
+        dev = r.device if r is not None else torch.device("cuda")
         Wk, N = self.n, self.sys.n_elec
-        assert r.shape == (Wk, N, 3) and r.dtype == torch.float64
+        assert r is None or (r.shape == (Wk, N, 3) and r.dtype == torch.float64)
         f = lambda *sh: torch.empty(*sh, dtype=torch.float64, device=dev)
         out = dict(logabs=f(Wk), sign=f(Wk), drift=f(Wk, N, 3) if drift else None,
                    e_kin=f(Wk), e_loc=f(Wk), status=torch.empty(Wk, dtype=torch.int32, device=dev))

@@ -736,10 +736,19 @@ extern "C" qmc_status qmc_eval_batch(qmc_system* sys, qmc_walkers* wk, const dou
                                      int32_t* status, hipStream_t stream) {
   qmc_status c = check_pair(sys, wk);
   if (c) return c;
-  if (!r) return fail(QMC_ERR_ARG, "null positions");
+  if (!r && !wk->evaluated) return fail(QMC_ERR_STATE, "no current positions: evaluate at given positions first");
   const SysDev& s = sys->d;
   WalkDev& d = wk->d;
-  HIP_TRY(hipMemcpyAsync(d.r, r, sizeof(double) * d.Wk * s.N * 3, hipMemcpyDeviceToDevice, stream), "copy r");
+  if (r) HIP_TRY(hipMemcpyAsync(d.r, r, sizeof(double) * d.Wk * s.N * 3, hipMemcpyDeviceToDevice, stream), "copy r");
+  // At the current positions, the P rows of a spin none of whose electrons
+  // has moved since they were built (the rebuild between the two halves of a
+  // sweep) are still Phi Lambda: the FP64, FP32 and int8-refined builds skip
+  // them (the rebuilds between moves compute exactly what this build would).
+  int halves = 3;
+  if (!r && wk->generation == sys->generation && !s.refined() && !s.pairing) {
+    if (wk->P_up_valid) halves &= ~1;
+    if (wk->P_dn_valid) halves &= ~2;
+  }
   // QMC_MIXED evaluates through the FP64 kernels on the FP64 work arrays, then
   // stores the FP32 basis and P rows the moves stream.
   const bool refine = s.refined();
@@ -766,14 +775,17 @@ extern "C" qmc_status qmc_eval_batch(qmc_system* sys, qmc_walkers* wk, const dou
     // reduced-precision digits on the int8 matrix cores, refined to the FP64
     // product (see ozaki.hip); the moves' FP32 / BF16 rows (refined modes) or
     // the transposed rows of the screened proposals are written beside
-    TIMED(wk, QMC_T_P_BUILD, stream,
-          launch_P_build_oz(s, d, 3, de.phi == d.phi64 ? d.phi64 : (const double*)d.phi,
-                            refine ? d.P64 : (double*)d.P, refine ? d.P : nullptr, s.bf16(), stream,
-                            ephi != nullptr, s.screened() ? d.PT : nullptr),
-          "P build");
-    if (s.screened()) TIMED(wk, QMC_T_OTHER, stream, launch_screen_colmax(s, d, 3, stream), "column maxima");
-  } else {
-    TIMED(wk, QMC_T_P_BUILD, stream, launch_P_build(se, de, 3, stream, refine ? d.P : nullptr, s.bf16()),
+    if (halves) {
+      TIMED(wk, QMC_T_P_BUILD, stream,
+            launch_P_build_oz(s, d, halves, de.phi == d.phi64 ? d.phi64 : (const double*)d.phi,
+                              refine ? d.P64 : (double*)d.P, refine ? d.P : nullptr, s.bf16(), stream,
+                              ephi != nullptr, s.screened() ? d.PT : nullptr),
+            "P build");
+      if (s.screened())
+        TIMED(wk, QMC_T_OTHER, stream, launch_screen_colmax(s, d, halves, stream), "column maxima");
+    }
+  } else if (halves) {
+    TIMED(wk, QMC_T_P_BUILD, stream, launch_P_build(se, de, halves, stream, refine ? d.P : nullptr, s.bf16()),
           "P build");
   }
   TIMED(wk, QMC_T_W_BUILD, stream, launch_W_build(se, de, stream), "W build");

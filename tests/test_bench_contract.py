@@ -66,3 +66,19 @@ def test_screened_and_refined_counts_160e():
     ops = 2.0 * 608 * 608 * N * Wk * 28
     assert r["P_build"]["unit"] == "TOP/s" and r["P_build"]["peak"] == 5000.0
     assert abs(r["P_build"]["achieved"] - ops / 2.0e-3 / 1e12) < 0.01
+
+
+def test_p_rows_of_evaluations_at_current_positions_160e():
+    """After a full sweep the up rows of P are current (rebuilt before the down
+    electrons moved): the evaluation's P_build is priced on the n_dn = 80 rows
+    per walker it builds, the rebuild on the n_up = 80 rows."""
+    s = C.mol_40nuc_160e(n_walkers=4).system
+    Wk, L, n = 1024, 600, 80
+    assert bench.kernel_models(s, Wk, 8, 0.74, p_rows=n)["P_build"] == ("mfma", 2.0 * L * L * Wk * n)
+    one = {"P_build": (1.5, 1), "P_rebuild": (1.5, 1)}
+    prop = {"bound": "hbm", "achieved": 1.0, "peak": 8000.0, "unit": "GB/s", "frac": 0.0, "avg_launch_us": 1.0}
+    r = bench.step_rooflines(s, Wk, "fp64", one, prop, p_rows=n)
+    assert abs(r["P_build"]["achieved"] - 2.0 * L * L * n * Wk / 1.5e-3 / 1e12) < 0.01
+    assert abs(r["P_rebuild"]["achieved"] - r["P_build"]["achieved"]) < 1e-9
+    r = bench.step_rooflines(s, Wk, "mixed", one, prop, p_rows=n)
+    assert abs(r["P_build"]["achieved"] - 2.0 * 608 * 608 * n * Wk * 28 / 1.5e-3 / 1e12) < 0.01
