@@ -61,6 +61,7 @@ def parse():
 # Sources of the move kernels: a recorded counter measurement is reported only
 # while these files are unchanged.
 ROWS_SOURCES = ("paper_2002_07401_amd/csrc/move.hip", "paper_2002_07401_amd/csrc/move_dev.h",
+                "paper_2002_07401_amd/csrc/move_staged.h", "paper_2002_07401_amd/csrc/sweep.hip",
                 "paper_2002_07401_amd/csrc/internal.h")
 
 
@@ -74,7 +75,7 @@ def rows_source_hash():
 
 
 def recorded_traffic(tag, precision, walkers):
-    """HBM bytes per launch of a move kernel (tag: propose_rows,
+    """HBM bytes per launch of a move kernel (tag: sweep, propose_rows,
     propose_screened or accept_prep) from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE passes, each scaled by the same counter over a
     plain copy of known size), or None when the summary is missing, was taken
@@ -171,12 +172,29 @@ def host_cpu():
 
 
 def prop_roofline(models, tim):
-    """Roofline fields of the proposal stream from the timed steps."""
+    """Roofline fields of the proposal stream from the timed steps (None when
+    every proposal ran inside the persistent sweep)."""
     ms, cnt = tim["propose"]
-    avg = ms / max(cnt, 1)
+    if not cnt:
+        return None
+    avg = ms / cnt
     ach = models["propose"][1] / (avg * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 4), "avg_launch_us": round(avg * 1e3, 2)}
+
+
+def sweep_bytes(models, tim, moves):
+    """Algorithmic bytes per launch of the persistent sweep over the timed
+    steps: every proposal not launched on its own ran inside a sweep, and every
+    sweep launch ends with a proposal whose accept is a launch of its own, so a
+    sweep of k proposals holds k - 1 fused accepts (each priced as the fused
+    accept kernel: propose and accept bytes per walker from kernel_models)."""
+    launches = tim["sweep"][1]
+    if not launches:
+        return None
+    props = moves - tim["propose"][1]
+    accs = props - launches
+    return (props * models["propose"][1] + accs * models["accept"][1]) / launches
 
 
 def cpu_baseline(w, n_walk=8, n_moves=320, n_eval=32, n_moves_1t=40):
@@ -250,7 +268,7 @@ def run_precision(P, C, w, args, precision):
     cnt.zero_()
     # the timed steps record events only around the kernels a roofline is
     # reported for (every timed launch adds two event records to the stream)
-    wk.set_timing(True, timers=("propose", "accept", "P_build"))
+    wk.set_timing(True, timers=("sweep", "propose", "accept", "P_build"))
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -315,6 +333,9 @@ def run_precision(P, C, w, args, precision):
     # down rows only (the other modes rebuild their FP64 P for both spins)
     p_rows = s.n_dn if precision in ("fp64", "fp32", "mixed") else N
     models = kernel_models(s, Wk, esz, acc_rate, kept, p_rows)
+    sw = sweep_bytes(models, tim, args.steps * N)
+    if sw is not None:
+        models["sweep"] = ("hbm", sw)
     dominant = max(one, key=lambda k: one[k][0])
     dom = max((k for k in models if tim.get(k, (0.0, 0))[1]), key=lambda k: tim[k][0])
     bound, units = models[dom]
@@ -324,7 +345,7 @@ def run_precision(P, C, w, args, precision):
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": recorded_traffic({"propose": "propose_screened" if screened else "propose_rows",
-                                             "accept": "accept_prep"}[dom], precision, Wk),
+                                             "accept": "accept_prep", "sweep": "sweep"}[dom], precision, Wk),
                 "bytes_per_launch": int(units), "avg_launch_us": round(avg_ms * 1e3, 2)}
     else:
         peak = MFMA_PEAK_TFLOPS[precision]
@@ -333,7 +354,8 @@ def run_precision(P, C, w, args, precision):
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
                 "flops_per_launch": int(units), "avg_launch_us": round(avg_ms * 1e3, 2)}
     steps = step_rooflines(s, Wk, precision, one, roof if roof["kernel"] == "propose" else
-                           prop_roofline(models, tim), models["accept"][1], p_rows)
+                           prop_roofline(models, tim), models["accept"][1], p_rows,
+                           roof if roof["kernel"] == "sweep" else None)
     # MFMA use of the geminal build's dominant product (P = Phi Lambda in the
     # evaluations of the timed steps).  Refined modes: int8 operations of the
     # digit products (the P_build timer also covers the digit split) against
@@ -749,7 +771,7 @@ def achievable_peaks():
             "datasheet": {"hbm_GBps": HBM_PEAK_GBS, "fp64_TFLOPs": 78.6, "fp32_TFLOPs": 157.3}}
 
 
-def step_rooflines(s, Wk, precision, one, prop_roof, acc_model=None, p_rows=None):
+def step_rooflines(s, Wk, precision, one, prop_roof, acc_model=None, p_rows=None, sweep_roof=None):
     """Roofline of each step of one evaluation (and the proposal) from the
     one-step timers: algorithmic bytes or flops per launch / average launch.
       basis:   writes the N x L values of every walker (FP64; FP32 in fp32 mode)
@@ -762,7 +784,11 @@ def step_rooflines(s, Wk, precision, one, prop_roof, acc_model=None, p_rows=None
       W_build: 2 n_up n_dn L flops per walker (FP64 MFMA accumulation)
       LU:      2 n^3 flops per walker per launch (FP64 vector ALU, latency-bound
                at n = 80: one workgroup per walker)
-      Y_build: 2 x 2 n^2 L flops per walker (FP64 MFMA)"""
+      Y_build: 2 x 2 n^2 L flops per walker (FP64 MFMA)
+      sweep:   the persistent launch of a run of moves (FP64 and refined
+               modes): the proposals' and fused accepts' algorithmic bytes
+               (sweep_bytes) over its average launch; the proposal and accept
+               entries then cover only the launches made on their own"""
     L, N, nu, nd = s.n_basis, s.n_up + s.n_dn, s.n_up, s.n_dn
     pr = N if p_rows is None else p_rows
 
@@ -789,8 +815,12 @@ def step_rooflines(s, Wk, precision, one, prop_roof, acc_model=None, p_rows=None
         ach = units / (avg * 1e-3) / scale
         out[k] = {"bound": bound, "achieved": round(ach, 2), "peak": peak, "unit": unit,
                   "frac": round(ach / peak, 4), "avg_launch_us": round(avg * 1e3, 2)}
-    out["propose"] = {k: prop_roof[k] for k in ("bound", "achieved", "peak", "unit", "frac", "avg_launch_us")}
-    if acc_model is not None and one.get("accept", (0.0, 0))[1]:
+    keys = ("bound", "achieved", "peak", "unit", "frac", "avg_launch_us")
+    if prop_roof is not None:
+        out["propose"] = {k: prop_roof[k] for k in keys}
+    if sweep_roof is not None:
+        out["sweep"] = {k: sweep_roof[k] for k in keys + ("bytes_per_launch",)}
+    if acc_model is not None and one.get("accept", (0.0, 0))[1] and sweep_roof is None:
         ms, cnt = one["accept"]
         avg = ms / cnt
         ach = acc_model / (avg * 1e-3) / 1e9

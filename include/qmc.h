@@ -599,7 +599,10 @@ typedef enum {
   QMC_T_LRDMC_HOPS = 11,   /* lattice hop ratios and Green's function terms */
   QMC_T_LRDMC_STEP = 12,   /* continuous-time lattice step                  */
   QMC_T_P_REBUILD = 13,    /* one spin's P rows rebuilt before its moves    */
-  QMC_TIMER_COUNT = 14
+  QMC_T_SWEEP = 14,        /* a run of moves in one persistent launch: the
+                              proposals and the accepts fused with the next
+                              set-up, between two refreshes               */
+  QMC_TIMER_COUNT = 15
 } qmc_timer;
 
 /* enable != 0 turns every timer on and clears the sums; 0 turns timing off. */

@@ -45,7 +45,7 @@ FUNCTIONS = (
 )
 
 TIMER_NAMES = ("basis", "P_build", "W_build", "LU", "Y_build", "rowdot", "assemble", "propose",
-               "accept", "other", "propose_prep", "lrdmc_hops", "lrdmc_step", "P_rebuild")
+               "accept", "other", "propose_prep", "lrdmc_hops", "lrdmc_step", "P_rebuild", "sweep")
 
 # per-walker terms of qmc_lrdmc_hops
 LR_TERMS = ("e_loc", "e_kin", "lap_a", "va_shift", "v_sf", "escape", "hfn_diag")

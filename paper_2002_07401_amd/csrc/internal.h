@@ -586,6 +586,17 @@ hipError_t launch_metropolis_accept_prep(const SysDev& s, const WalkDev& w, int 
                                          hipStream_t st);
 hipError_t launch_accept(const SysDev& s, const WalkDev& w, int e, const uint8_t* acc,
                          hipStream_t st);
+// Persistent sweep of k >= 2 moves e0, e0 + 1, ... (mod N): the k proposals and
+// the k - 1 accepts between them fused with the next set-up, in one launch
+// (one workgroup per walker); the set-up of e0 must have run, and the last
+// proposal is left for a plain accept.  No refresh, change of spin or P
+// rebuild may fall inside.  since0: the attempts since the last refresh at the
+// first accept.  sweep_segment_ok: whether the kernel is built for the system
+// and the spin of e0 (hipErrorNotSupported from the launch otherwise).
+bool sweep_segment_ok(const SysDev& s, const WalkDev& w, int e0);
+hipError_t launch_sweep_segment(const SysDev& s, const WalkDev& w, int e0, int k, const double* disp,
+                                const double* unif, int32_t* accept_count, int since0, hipStream_t st,
+                                hipEvent_t ev_start, hipEvent_t ev_stop);
 hipError_t launch_refresh_finish(const SysDev& s, const WalkDev& w, int32_t* status, hipStream_t st);
 // max |W X - I| per walker (P = W X given) and status 3 where it exceeds tol
 hipError_t launch_refresh_residual(const double* Pm, int n, int Wk, double tol, double* res, int32_t* status,

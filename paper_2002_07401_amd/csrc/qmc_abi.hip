@@ -998,15 +998,39 @@ extern "C" qmc_status qmc_accept_move(qmc_system* sys, qmc_walkers* wk, int32_t 
 // The accept of e can run fused with the set-up of the next proposal e2 when
 // neither a refresh (after the accept, or before proposing e2) nor a P rebuild
 // (for e2) falls between them, and psi(r') fits the kernel's LDS stage.
-static bool fusable(const qmc_walkers* wk, int e, int e2) {
+// The host's move bookkeeping (refresh schedule and P validity), stepped
+// without launching anything.
+struct MoveState {
+  Sched q;
+  bool up_ok, dn_ok;
+};
+// fusable on state m; on success m becomes the state after the accept of e,
+// the refresh check before e2 and its P check (none of which then launches).
+static bool fuse_step(const qmc_walkers* wk, MoveState& m, int e, int e2) {
   const SysDev& s = wk->sys->d;
   if (s.Lp > kFuseMaxLp || s.nu > kBigMaxN || !wk->d.wv || e2 == e || s.LJ > 0 || s.Lq > 0) return false;
-  Sched q{wk->attempts, wk->since, wk->buf_spin};
-  if (sched_after(s, q)) return false;
-  if (sched_before(s, q, e2)) return false;
-  bool up_ok = wk->P_up_valid, dn_ok = wk->P_dn_valid;
-  if (e < s.nu) up_ok = false; else dn_ok = false;
-  return e2 < s.nu ? dn_ok : up_ok;
+  MoveState t = m;
+  if (sched_after(s, t.q)) return false;
+  if (sched_before(s, t.q, e2)) return false;
+  if (e < s.nu) t.up_ok = false; else t.dn_ok = false;
+  if (!(e2 < s.nu ? t.dn_ok : t.up_ok)) return false;
+  m = t;
+  return true;
+}
+static bool fusable(const qmc_walkers* wk, int e, int e2) {
+  MoveState m{Sched{wk->attempts, wk->since, wk->buf_spin}, wk->P_up_valid, wk->P_dn_valid};
+  return fuse_step(wk, m, e, e2);
+}
+// Moves t, t + 1, ..., t + k - 1 of a vmc_steps call whose accepts, all but
+// the last, are fusable with the next set-up: the k of the run starting at t.
+static int fused_run(const qmc_walkers* wk, int e_start, int t, int n_steps) {
+  const int N = wk->sys->d.N;
+  MoveState m{Sched{wk->attempts, wk->since, wk->buf_spin}, wk->P_up_valid, wk->P_dn_valid};
+  int k = 1;
+  while (t + k < n_steps &&
+         fuse_step(wk, m, (int)((e_start + (long)t + k - 1) % N), (int)((e_start + (long)t + k) % N)))
+    ++k;
+  return k;
 }
 
 extern "C" qmc_status qmc_vmc_steps(qmc_system* sys, qmc_walkers* wk, int32_t e_start, int32_t n_steps,
@@ -1045,6 +1069,34 @@ extern "C" qmc_status qmc_vmc_steps(qmc_system* sys, qmc_walkers* wk, int32_t e_
       if (c) return c;
       TIMED(wk, QMC_T_PROPOSE_PREP, stream,
             launch_propose_prep(s, wk->d, e, nullptr, disp + (long)t * Wk * 3, false, stream), "propose prep");
+      // a run of fusable moves from here: one persistent launch, then the
+      // bookkeeping of its fused steps (which launches nothing) and a plain
+      // accept of its last proposal
+      const int k = sweep_segment_ok(s, wk->d, e) ? fused_run(wk, e_start, t, n_steps) : 1;
+      if (k >= 2) {
+        hipEvent_t ea, eb;
+        HIP_TRY(wk->tm.begin_ext(QMC_T_SWEEP, &ea, &eb), "timer begin");
+        HIP_TRY(launch_sweep_segment(s, wk->d, e, k, disp + (long)t * Wk * 3, unif + (long)t * Wk, accept_count,
+                                     wk->since, stream, ea, eb),
+                "persistent sweep");
+        for (int j = 0; j + 1 < k; ++j) {
+          const int ej = (int)((e_start + (long)t + j) % s.N), ej2 = (int)((e_start + (long)t + j + 1) % s.N);
+          c = after_accept(wk, ej, nullptr, stream);
+          if (c) return c;
+          c = before_propose(wk, ej2, stream);
+          if (c) return c;
+          c = ensure_P(wk, ej2, stream);
+          if (c) return c;
+        }
+        const long tl = t + k - 1;
+        TIMED(wk, QMC_T_ACCEPT, stream,
+              launch_metropolis_accept(s, wk->d, (int)((e_start + tl) % s.N), unif + tl * Wk, accept_count, stream),
+              "metropolis");
+        c = after_accept(wk, (int)((e_start + tl) % s.N), nullptr, stream);
+        if (c) return c;
+        t += k - 1;
+        continue;
+      }
     }
 {
       hipEvent_t ea, eb;

@@ -158,3 +158,38 @@ def test_device_sweep_equals_host_driven_moves():
         torch.cuda.synchronize()
         assert torch.equal(a.cpu(), b.cpu()), item
     assert 0 < int(cnt.sum()) < 16 * n
+
+
+@pytest.mark.parametrize("prec", ["QMC_FP64", "QMC_REFINED"])
+def test_vmc_steps_split_into_calls_equals_one_call(prec):
+    # Runs of moves with no refresh, change of spin or P rebuild inside go to
+    # one persistent launch; a call boundary ends a run with a plain accept
+    # and the next call starts with a separate set-up.  A sweep and a half in
+    # one call and in calls of 1, 7, 13 and 32 moves: positions, log|Psi| and
+    # the accept counts agree bitwise (the same arithmetic in the same order).
+    P = need_gpu()
+    w = C.mol_40nuc_160e(n_walkers=16)
+    N = w.system.n_up + w.system.n_dn
+    n = 240
+    disp, unif = C.chain_arrays(77, n, 16)
+    disp, unif = torch.tensor(disp, device="cuda"), torch.tensor(unif, device="cuda")
+    r0 = torch.tensor(w.r0[:16], device="cuda")
+    sysh = P.JAGPSystem(w.system, precision=getattr(P, prec))
+    out = []
+    for sizes in ([n], [1] * 20 + [7] * 10 + [13] * 6 + [32] * 2 + [n - 20 - 70 - 78 - 64]):
+        wk = P.Walkers(sysh, 16, adjoint=False)
+        wk.eval_batch(r0)
+        cnt = torch.zeros(16, dtype=torch.int32, device="cuda")
+        t = 0
+        for m in sizes:
+            wk.vmc_steps(t % N, disp[t:t + m].contiguous(), unif[t:t + m].contiguous(), cnt)
+            t += m
+        assert t == n
+        out.append((wk.read(P.STATE_R).cpu(), wk.read(P.STATE_LOGABS).cpu(), cnt.cpu()))
+        torch.cuda.synchronize()
+        wk.close()
+    (ra, la, ca), (rb, lb, cb) = out
+    assert torch.equal(ra, rb)
+    assert torch.equal(ca, cb)
+    assert torch.equal(la, lb)
+    sysh.close()
