@@ -361,7 +361,9 @@ def run_precision(P, C, w, args, precision):
     # digit products (the P_build timer also covers the digit split) against
     # the int8 peak, and the FP64-equivalent rate beside it
     pf_ms = tim["P_build"][0] / max(tim["P_build"][1], 1)
-    if precision in ("fp64", "fp32"):
+    if not tim["P_build"][1]:
+        wmfma = None   # (no evaluation of the timed steps built P)
+    elif precision in ("fp64", "fp32"):
         pf_tf = models["P_build"][1] / (pf_ms * 1e-3) / 1e12
         wmfma = {"kernel": "P_build", "instruction": "v_mfma_f64_16x16x4f64" if precision == "fp64"
                  else "v_mfma_f32_16x16x4f32", "achieved": round(pf_tf, 2), "peak": MFMA_PEAK_TFLOPS[precision],
