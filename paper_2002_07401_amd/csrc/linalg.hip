@@ -15,6 +15,8 @@
 // reverse order, leaving W^{-1}.  A zero pivot marks the walker singular.
 #include "internal.h"
 
+#include <type_traits>
+
 namespace qmc {
 
 // Row-per-thread variant (the default for n <= kLuRowMax).  The matrix is
@@ -189,6 +191,185 @@ gj_inverse_row_kernel(const double* __restrict__ Wg, double* __restrict__ Ag, do
   gj_row_body<NMAX>(Wg + b * w_bs, Ag + b * a_bs, logdet + b, detsign + b, singular + b, n, sm);
 }
 
+// Column-split variant for 64 < n <= 88 (NMAX = round_up(n, 8), two waves): wave w keeps columns [w H, w H + H) (H = NMAX / 2) of every row,
+// lane l rows l and 64 + l.  Steps 0..H-1 pivot on wave 0's columns (its
+// window of H columns rotates as in gj_row_body, the other wave's stays in
+// place), steps H..2H-1 on wave 1's.  Each wave takes the pivot row's values
+// in its own columns from lane p mod 64 of its own registers (readlane), so
+// the row is never copied through LDS (that copy, 80 values written by one
+// lane every step, was the row kernel's largest cost); only the pivot column
+// crosses the waves, two values per lane.  Pivot choice, multipliers and
+// updates are those of gj_row_body, so W^{-1} is bitwise the row kernel's;
+// log|det| adds the same logarithms in another order.
+struct GjSplitShared {
+  double fcol[2][128];   // per parity: the pivot column's entries, row-indexed
+  double piv[2];
+  int p[2];
+  int prow[kLuRowMax];
+  int kof[kLuRowMax];
+};
+
+template <int NMAX>
+__global__ void __launch_bounds__(128)
+gj_split_kernel(const double* __restrict__ Wg, double* __restrict__ Ag, double* __restrict__ logdet,
+                double* __restrict__ detsign, int* __restrict__ singular, int n, long w_bs, long a_bs) {
+  static_assert(NMAX > 64 && NMAX <= 128 && NMAX % 8 == 0, "two waves, two rows per lane");
+  constexpr int H = NMAX / 2;
+  __shared__ GjSplitShared sm;
+  const long bb = blockIdx.x;
+  const double* W = Wg + bb * w_bs;
+  double* A = Ag + bb * a_bs;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r0 = lane, r1 = 64 + lane;
+  const bool live1 = r1 < NMAX;
+  const bool real0 = r0 < n, real1 = r1 < n;
+  const int c0 = wave * H;
+  double x0[H], x1[H];
+#pragma unroll
+  for (int j = 0; j < H; ++j) {
+    const int c = c0 + j;
+    x0[j] = real0 ? (c < n ? W[(long)r0 * n + c] : 0.0) : (c == r0 ? 1.0 : 0.0);
+    x1[j] = real1 ? (c < n ? W[(long)r1 * n + c] : 0.0) : (c == r1 ? 1.0 : 0.0);
+  }
+  bool used0 = false, used1 = !live1;
+  double piv0 = 1.0, piv1 = 1.0;
+  int k0 = r0, k1 = r1;
+  int sing = 0;
+  auto phase = [&](auto own_tag, int ph) {
+    constexpr bool own = decltype(own_tag)::value;
+    for (int kk = 0; kk < H; ++kk) {
+      const int k = ph * H + kk, b = k & 1;
+      if (own) {
+        // pivot: the largest |entry| of column k among rows not yet pivoted
+        // (real rows only in the first n steps), lowest row on ties
+        const double f0 = x0[0], f1 = x1[0];
+        const bool e0 = !used0 && (real0 || k >= n), e1 = !used1 && (real1 || k >= n);
+        const unsigned long long q0 =
+            e0 ? ((__double_as_longlong(fabs(f0)) & ~0xFFull) | (unsigned long long)(255 - r0)) : 0ull;
+        const unsigned long long q1 =
+            e1 ? ((__double_as_longlong(fabs(f1)) & ~0xFFull) | (unsigned long long)(255 - r1)) : 0ull;
+        const unsigned long long wk = wave_max_u64(q0 > q1 ? q0 : q1);
+        const int p = 255 - (int)(wk & 0xFFull);
+        const int wl = p & 63;
+        const double fp = p < 64 ? f0 : f1;   // uniform choice of register, lane wl's value below
+        const double pv = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(fp), wl),
+                                           __builtin_amdgcn_readlane(__double2loint(fp), wl));
+        sm.fcol[b][lane] = f0;
+        sm.fcol[b][64 + lane] = f1;
+        if (lane == 0) {
+          sm.piv[b] = wk != 0ull ? pv : 0.0;
+          sm.p[b] = p;
+          sm.prow[k] = p;
+        }
+      }
+      __syncthreads();
+      const double piv = sm.piv[b];
+      if (!(piv != 0.0)) { sing = 1; return; }   // uniform across the block
+      const int p = sm.p[b];
+      const int wl = p & 63;
+      const bool isp0 = r0 == p, isp1 = r1 == p;
+      const double f0 = own ? x0[0] : sm.fcol[b][lane];
+      const double f1 = own ? x1[0] : sm.fcol[b][64 + lane];
+      if (isp0) { used0 = true; piv0 = piv; k0 = k; }
+      if (isp1) { used1 = true; piv1 = piv; k1 = k; }
+      const double g0 = isp0 ? 0.0 : f0 * (1.0 / piv);
+      const double g1 = isp1 ? 0.0 : f1 * (1.0 / piv);
+      const bool hi_row = p >= 64;
+      // the pivot row's entries in this wave's columns (window order) from lane
+      // wl, eight at a time, each used at once
+#pragma unroll
+      for (int c = 0; c < H; c += 8) {
+        double pr[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int j = c + q + (own ? 1 : 0);
+          double v = 0.0;
+          if (j < H) {
+            const double xs = hi_row ? x1[j] : x0[j];
+            v = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(xs), wl),
+                                 __builtin_amdgcn_readlane(__double2loint(xs), wl));
+          }
+          pr[q] = v;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int j = c + q;
+          if (own) {
+            if (j < H - 1) {
+              x0[j] = fma(-g0, pr[q], x0[j + 1]);
+              x1[j] = fma(-g1, pr[q], x1[j + 1]);
+            }
+          } else if (j < H) {
+            x0[j] = fma(-g0, pr[q], x0[j]);
+            x1[j] = fma(-g1, pr[q], x1[j]);
+          }
+        }
+      }
+      if (own) {
+        x0[H - 1] = isp0 ? 1.0 : -g0;
+        x1[H - 1] = isp1 ? 1.0 : -g1;
+      }
+    }
+  };
+  if (wave == 0) {
+    phase(std::true_type{}, 0);
+    if (!sing) phase(std::false_type{}, 1);
+  } else {
+    phase(std::false_type{}, 0);
+    if (!sing) phase(std::true_type{}, 1);
+  }
+  if (sing) {
+    const double nanv = __longlong_as_double(0x7ff8000000000000LL);
+    for (int idx = tid; idx < n * n; idx += blockDim.x) A[idx] = nanv;
+    if (tid == 0) { logdet[bb] = -__builtin_inf(); detsign[bb] = 0.0; singular[bb] = 1; }
+    return;
+  }
+  if (wave == 0) {
+    sm.kof[r0] = k0;
+    if (live1) sm.kof[r1] = k1;
+  }
+  __syncthreads();
+  // log|det| and the sign as in gj_row_body (wave 0 holds every row once)
+  double ls = 0.0;
+  int odd = 0;
+  if (wave == 0) {
+    if (real0) {
+      ls += log(fabs(piv0));
+      odd += piv0 < 0.0;
+      for (int i2 = r0 + 1; i2 < n; ++i2) odd += sm.kof[i2] < k0;
+    }
+    if (real1) {
+      ls += log(fabs(piv1));
+      odd += piv1 < 0.0;
+      for (int i2 = r1 + 1; i2 < n; ++i2) odd += sm.kof[i2] < k1;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      ls += __shfl_xor(ls, o, 64);
+      odd += __shfl_xor(odd, o, 64);
+    }
+  }
+  if (real0) {
+    const double inv = 1.0 / piv0;
+    double* out = A + (long)k0 * n;
+#pragma unroll
+    for (int j = 0; j < H; ++j)
+      if (c0 + j < n) out[sm.prow[c0 + j]] = x0[j] * inv;
+  }
+  if (real1) {
+    const double inv = 1.0 / piv1;
+    double* out = A + (long)k1 * n;
+#pragma unroll
+    for (int j = 0; j < H; ++j)
+      if (c0 + j < n) out[sm.prow[c0 + j]] = x1[j] * inv;
+  }
+  if (tid == 0) {
+    logdet[bb] = ls;
+    detsign[bb] = (odd & 1) ? -1.0 : 1.0;
+    singular[bb] = 0;
+  }
+}
+
 static hipError_t launch_lu_inverse_big(const SysDev& s, const WalkDev& w, hipStream_t st);
 
 hipError_t launch_lu_inverse(const SysDev& s, const WalkDev& w, hipStream_t st) {
@@ -202,6 +383,19 @@ hipError_t launch_gj_inverse_n(int Wk, int n, const double* W, double* A, double
   if (n < 1 || n > kLuRowMax) return hipErrorNotSupported;
   const long wbs = (long)n * n, abs_ = wbs;
   const dim3 blk(n > 64 ? 128 : 64);
+  if (n > 64 && n <= 88) {   // two waves, columns split between them (at 96, one wave per SIMD: the row kernel)
+    switch ((n + 7) >> 3) {
+#define QMC_LU_SPLIT(C)                                                                                 \
+      case C:                                                                                           \
+        hipLaunchKernelGGL(gj_split_kernel<8 * C>, dim3(Wk), blk, 0, st, W, A, logdet, detsign, singular, \
+                           n, wbs, abs_);                                                               \
+        break;
+      QMC_LU_SPLIT(9) QMC_LU_SPLIT(10) QMC_LU_SPLIT(11)
+#undef QMC_LU_SPLIT
+      default: return hipErrorNotSupported;
+    }
+    return hipGetLastError();
+  }
   switch ((n + 7) >> 3) {
 #define QMC_LU_ROW(C)                                                                                   \
     case C:                                                                                             \
