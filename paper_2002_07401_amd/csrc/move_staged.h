@@ -29,8 +29,49 @@ __device__ __forceinline__ int phase_tid() {
 // loads at once (8 / IPB blocks), some 32 KiB in flight per walker.  The
 // per-lane sums go to LDS and row j adds its FB x 4 partial sums in a fixed
 // order (waves outer, functions inner).
-template <int IPB>
-__device__ void screened_stream_walker(const SysDev& s, const WalkDev& w, int wk, int e, int S, int FB, char* lds) {
+constexpr int kStageMaxN = 128;    // n <= 128 (one W entry per thread)
+constexpr int kStageMaxNe = 256;   // electrons
+constexpr int kStageMaxNuc = 256;  // nuclei (one per thread)
+constexpr int kStageMaxSplits = (kStageMaxN + kPropRowsMin - 1) / kPropRowsMin;   // partial ratios
+constexpr size_t kStageMaxLds = 63 * 1024;   // dynamic LDS (the static arrays take the rest of 64 KiB)
+
+struct StageLayout {
+  size_t V, D, S, vec, total;   // byte offsets of the regions and the size
+};
+// vec_min: the vector area starts at vec_min or later (the persistent sweep
+// keeps its hand-off arrays below it)
+__host__ __device__ inline StageLayout stage_layout(int n, int kb, int mc, size_t vec_min = 0) {
+  StageLayout o;
+  o.V = 0;
+  o.D = o.V + pad1k(sizeof(double) * (size_t)(mc + 1) * n);
+  o.S = o.D + pad1k(sizeof(double) * (size_t)(mc + 1) * n);
+  o.vec = o.S + pad1k(sizeof(double) * (size_t)(mc + 1) * kb);
+  if (o.vec < vec_min) o.vec = vec_min;
+  o.total = o.vec + sizeof(double) * (3 * (size_t)n + 5 * (size_t)kb);
+  return o;
+}
+
+// The persistent sweep hands values from one phase of a move to the next
+// through LDS rather than global memory (a load of a value the workgroup has
+// just stored waits for the store): the new W line and the partial ratios of a
+// proposal (to the accept), the kept count of a screened set-up (to the next
+// proposal; the kept list itself and psi(r') go to the bottom of the dynamic
+// LDS, the inverse line stays in the vector area).
+struct SweepHand {
+  double wn[kStageMaxN];
+  double part[kStageMaxSplits];
+  int cnt;
+};
+
+
+// HAND (persistent sweep): with from_lds the kept list is already at the
+// bottom of lds, its count in hand->cnt and the inverse line in cvl (the set-up
+// ran in the same workgroup); the new W line and the partial ratios also go to
+// hand.
+template <int IPB, bool HAND = false>
+__device__ void screened_stream_walker(const SysDev& s, const WalkDev& w, int wk, int e, int S, int FB, char* lds,
+                                       SweepHand* hand = nullptr, const double* cvl = nullptr,
+                                       bool from_lds = false) {
   __shared__ double red[8];
   const int tid = phase_tid(), lane = tid & 63, wave = tid >> 6;
   const bool up = e < s.nu;
@@ -41,23 +82,30 @@ __device__ void screened_stream_walker(const SysDev& s, const WalkDev& w, int wk
   int* lmu = (int*)lds;
   double* lv = (double*)(lds + pad1k(sizeof(int) * (size_t)Lp));
   dbl2* part = (dbl2*)((char*)lv + pad1k(sizeof(double) * (size_t)Lp));
-  // the kept list (the whole Lp-long arrays: no wait on the count), c
-  const int* mk = w.muk + (long)wk * Lp;
-  const double* pk = w.psk + (long)wk * Lp;
-  int xm[kStageQL];
-  double xv[kStageQL];
+  int cnt;
+  double cj;
+  if (HAND && from_lds) {
+    cnt = hand->cnt;
+    cj = cvl[tid < n ? tid : 0];
+  } else {
+    // the kept list (the whole Lp-long arrays: no wait on the count), c
+    const int* mk = w.muk + (long)wk * Lp;
+    const double* pk = w.psk + (long)wk * Lp;
+    int xm[kStageQL];
+    double xv[kStageQL];
 #pragma unroll
-  for (int k = 0; k < kStageQL; ++k) {
-    const int q = tid + 256 * k, qc = q < Lp ? q : 0;
-    xm[k] = mk[qc];
-    xv[k] = pk[qc];
-  }
-  const int cnt = w.nkeep[wk];
-  const double cj = w.cvec[(long)wk * s.nu + (tid < n ? tid : 0)];
+    for (int k = 0; k < kStageQL; ++k) {
+      const int q = tid + 256 * k, qc = q < Lp ? q : 0;
+      xm[k] = mk[qc];
+      xv[k] = pk[qc];
+    }
+    cnt = w.nkeep[wk];
+    cj = w.cvec[(long)wk * s.nu + (tid < n ? tid : 0)];
 #pragma unroll
-  for (int k = 0; k < kStageQL; ++k) {
-    const int q = tid + 256 * k;
-    if (q < Lp) { lmu[q] = xm[k]; lv[q] = xv[k]; }
+    for (int k = 0; k < kStageQL; ++k) {
+      const int q = tid + 256 * k;
+      if (q < Lp) { lmu[q] = xm[k]; lv[q] = xv[k]; }
+    }
   }
   __syncthreads();
   // this lane's (function, row) of each of its IPB loads
@@ -105,10 +153,14 @@ __device__ void screened_stream_walker(const SysDev& s, const WalkDev& w, int wk
     for (int v = 0; v < 4; ++v)
       for (int f = 0; f < FB; ++f) t += pd[v * 128 * IPB + f * n + tid];
     wn[tid] = t;
+    if (HAND) hand->wn[tid] = t;
     rp = t * cj;
   }
   const double R = block_sum_mv(rp, red);
-  for (int q = tid; q < S; q += blockDim.x) w.rdet_part[(long)wk * S + q] = q == 0 ? R : 0.0;
+  for (int q = tid; q < S; q += blockDim.x) {
+    w.rdet_part[(long)wk * S + q] = q == 0 ? R : 0.0;
+    if (HAND) hand->part[q] = q == 0 ? R : 0.0;
+  }
 }
 
 // The blocked screened stream for proposals of e: n even, FB = 128 /
@@ -147,25 +199,6 @@ inline bool screened_blk_config(const SysDev& s, const WalkDev& w, int e, int& I
 // LDS: V, D [(mc+1) n], S^{-1} [(mc+1) kb], r [3 N] (each padded to 1 KiB,
 // the copy granule), psi(r') of e2 [Lp], three n-vectors, five kb-vectors.
 // ---------------------------------------------------------------------------
-constexpr int kStageMaxN = 128;    // n <= 128 (one W entry per thread)
-constexpr int kStageMaxNe = 256;   // electrons
-constexpr int kStageMaxNuc = 256;  // nuclei (one per thread)
-constexpr int kStageMaxSplits = (kStageMaxN + kPropRowsMin - 1) / kPropRowsMin;   // partial ratios
-constexpr size_t kStageMaxLds = 63 * 1024;   // dynamic LDS (the static arrays take the rest of 64 KiB)
-
-struct StageLayout {
-  size_t V, D, S, vec, total;   // byte offsets of the regions and the size
-};
-__host__ __device__ inline StageLayout stage_layout(int n, int kb, int mc) {
-  StageLayout o;
-  o.V = 0;
-  o.D = o.V + pad1k(sizeof(double) * (size_t)(mc + 1) * n);
-  o.S = o.D + pad1k(sizeof(double) * (size_t)(mc + 1) * n);
-  o.vec = o.S + pad1k(sizeof(double) * (size_t)(mc + 1) * kb);
-  o.total = o.vec + sizeof(double) * (3 * (size_t)n + 5 * (size_t)kb);
-  return o;
-}
-
 // bytes (a multiple of 8) from global src to LDS dst in 1 KiB granules, 16
 // bytes per lane (global_load_lds): granule j by wave j mod the wave count.
 // Lanes past the end re-read src's first 16 bytes into dst's padding.
@@ -225,12 +258,13 @@ __device__ __forceinline__ double jastrow_staged(const SysDev& s, int e, double 
   return val;
 }
 
-template <typename T, bool STAGED, int QL>
+template <typename T, bool STAGED, int QL, bool HAND = false>
 __device__ void accept_prep_staged_body(const SysDev& s, const WalkDev& w, int wk, int e, double u,
                                         int32_t* __restrict__ cnt, int cnt0, int S, int e2, double px, double py,
                                         double pz, double R, double dJ, int m, int mc, char* lds, const StagePre& q,
                                         const double* j2p, double la, double sg, double jv, double rx, double ry,
-                                        double rz, double ox, double oy, double oz) {
+                                        double rz, double ox, double oy, double oz, SweepHand* hand = nullptr,
+                                        size_t vec_min = 0) {
   __shared__ double red[16];
   __shared__ double gam_s;
   __shared__ int wcnt[QL][4];
@@ -238,7 +272,7 @@ __device__ void accept_prep_staged_body(const SysDev& s, const WalkDev& w, int w
   const int n = s.nu, kb = w.kb, N = s.N, L = s.L, Lp = s.Lp;
   const bool up = e < n;
   const int ie = up ? e : e - n;
-  const StageLayout ly = stage_layout(n, kb, mc);
+  const StageLayout ly = stage_layout(n, kb, mc, vec_min);
   double* Vl = (double*)(lds + ly.V);
   double* Dl = (double*)(lds + ly.D);
   double* Sl = (double*)(lds + ly.S);
@@ -367,7 +401,20 @@ __device__ void accept_prep_staged_body(const SysDev& s, const WalkDev& w, int w
       cvl[tid] = c;
     }
   }
-  if (!s.screened()) return;
+  if (!s.screened()) {
+    if (HAND) {
+      // psi(r') of e2 for the next proposal's stream, at the bottom of the LDS
+      // (the staged rows there are no longer read)
+      __syncthreads();
+      double* psl = (double*)lds;
+#pragma unroll
+      for (int k = 0; k < QL; ++k) {
+        const int mu = tid + 256 * k;
+        if (mu < Lp) psl[mu] = mu < L ? q.sv[k] : 0.0;
+      }
+    }
+    return;
+  }
 
   // screened proposals of e2 (screen_list_body)
   __syncthreads();
@@ -395,29 +442,37 @@ __device__ void accept_prep_staged_body(const SysDev& s, const WalkDev& w, int w
     for (int k2 = 0; k2 < wave; ++k2) before += wcnt[k][k2];
     if ((bal[k] >> lane) & 1ull) {
       const int at = before + __popcll(bal[k] & ((1ull << lane) - 1ull));
-      mk[at] = 256 * k + tid;
-      pk[at] = q.sv[k];
+      if (HAND) {   // the list where the screened stream keeps it (the staged rows are no longer read)
+        ((int*)lds)[at] = 256 * k + tid;
+        ((double*)(lds + pad1k(sizeof(int) * (size_t)Lp)))[at] = q.sv[k];
+      } else {
+        mk[at] = 256 * k + tid;
+        pk[at] = q.sv[k];
+      }
     }
     for (int k2 = 0; k2 < nw; ++k2) off += wcnt[k][k2];
   }
-  if (tid == 0) w.nkeep[wk] = off;
+  if (tid == 0) {
+    w.nkeep[wk] = off;
+    if (HAND) hand->cnt = off;
+  }
 }
 
 // One walker's fused accept and set-up (the staged kernel's work for walker
 // wk): rows below mc of V and D are staged; the LDS regions are laid out for
 // mcl >= mc rows (the persistent sweep keeps one layout for all its moves).
-template <typename T, int QL>
+template <typename T, int QL, bool HAND = false>
 __device__ void accept_prep_staged_phase(const SysDev& s, const WalkDev& w, int wk, int e,
                                          const double* __restrict__ unif, int32_t* __restrict__ accept_count,
                                          int S, int e2, const double* __restrict__ disp2, int mc, int mcl,
-                                         char* lds) {
+                                         char* lds, SweepHand* hand = nullptr, size_t vec_min = 0) {
   __shared__ double scal[kStageMaxSplits + 22];
   __shared__ int ints_s[2];
   const int tid = phase_tid();
   const int n = s.nu, kb = w.kb, N = s.N, L = s.L, Lp = s.Lp;
   const bool up = e < n, up2 = e2 < n;
   const int ie = up ? e : e - n, ie2 = up2 ? e2 : e2 - n;
-  const StageLayout ly = stage_layout(n, kb, mcl);
+  const StageLayout ly = stage_layout(n, kb, mcl, vec_min);
   // bulk copies first
   lds_copy_async(lds + ly.V, w.wv + (long)wk * kb * n, 8 * mc * n);
   lds_copy_async(lds + ly.D, w.wd + (long)wk * kb * n, 8 * mc * n);
@@ -442,7 +497,7 @@ __device__ void accept_prep_staged_phase(const SysDev& s, const WalkDev& w, int 
     const int j = tid < n ? tid : 0;
     const double* Ww = w.W + (long)wk * n * n;
     const double* A0 = w.A + (long)wk * n * n;
-    q.wn = w.w_new[(long)wk * n + j];
+    q.wn = HAND ? hand->wn[j] : w.w_new[(long)wk * n + j];
     q.Wo = up ? Ww[(long)ie * n + j] : Ww[(long)j * n + ie];
     q.v0 = w.v0[(long)wk * n + j];
     q.a0 = up2 ? A0[(long)j * n + ie2] : A0[(long)ie2 * n + j];
@@ -461,7 +516,7 @@ __device__ void accept_prep_staged_phase(const SysDev& s, const WalkDev& w, int 
   // r' of e and r of e2 and the eight two-body parameters (wave 1), the
   // buffered-move and accept counts.  Loads first, unconditionally (every
   // address valid), stores after.
-  const double pv = w.rdet_part[(long)wk * S + (tid < S ? tid : 0)];
+  const double pv = HAND ? hand->part[tid < S ? tid : 0] : w.rdet_part[(long)wk * S + (tid < S ? tid : 0)];
   const int t2 = tid - 64;
   const double* sp;
   switch (t2) {
@@ -501,11 +556,13 @@ __device__ void accept_prep_staged_phase(const SysDev& s, const WalkDev& w, int 
   __syncthreads();
   int32_t* cnt = accept_count ? accept_count + wk : nullptr;
   if (m <= mc)
-    accept_prep_staged_body<T, true, QL>(s, w, wk, e, u, cnt, ints_s[1], S, e2, px, py, pz, R, dJ, m, mcl, lds, q,
-                                         sc + 14, la, sg, jv, rx, ry, rz, sc[11], sc[12], sc[13]);
+    accept_prep_staged_body<T, true, QL, HAND>(s, w, wk, e, u, cnt, ints_s[1], S, e2, px, py, pz, R, dJ, m, mcl,
+                                               lds, q, sc + 14, la, sg, jv, rx, ry, rz, sc[11], sc[12], sc[13],
+                                               hand, vec_min);
   else
-    accept_prep_staged_body<T, false, QL>(s, w, wk, e, u, cnt, ints_s[1], S, e2, px, py, pz, R, dJ, m, mcl, lds, q,
-                                          sc + 14, la, sg, jv, rx, ry, rz, sc[11], sc[12], sc[13]);
+    accept_prep_staged_body<T, false, QL, HAND>(s, w, wk, e, u, cnt, ints_s[1], S, e2, px, py, pz, R, dJ, m, mcl,
+                                                lds, q, sc + 14, la, sg, jv, rx, ry, rz, sc[11], sc[12], sc[13],
+                                                hand, vec_min);
 }
 
 }  // namespace qmc

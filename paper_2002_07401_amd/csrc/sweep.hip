@@ -24,16 +24,19 @@ namespace qmc {
 // 38 KiB: four workgroups per compute unit hold the 1024 walkers of a large
 // batch at once).
 // ---------------------------------------------------------------------------
-constexpr size_t kSweepMaxLds = 38 * 1024;
+constexpr size_t kSweepMaxLds = 37 * 1024;
 
 // All S row blocks of walker wk's proposal in one workgroup, FP64 rows, two
 // rows per wave and block (R = 8 = 2 x 4 waves): block sb's rows j0 + v and
 // j0 + v + 4 go to wave v as in rows_body.  Every sum runs in rows_body's
 // order and each block's partial ratio adds the waves' sums in wave order as
 // block_partial does, so the new W line and the S partial ratios equal the
-// proposal kernel's bit for bit.
+// proposal kernel's bit for bit.  With from_lds, psi(r') and the inverse
+// line are taken from the LDS (psl, cvl: the set-up ran in the same
+// workgroup); the new W line and the partial ratios also go to hand.
 template <int NC>
-__device__ void rows_stream_walker(const SysDev& s, const WalkDev& w, int wk, int e, int S) {
+__device__ void rows_stream_walker(const SysDev& s, const WalkDev& w, int wk, int e, int S, SweepHand* hand,
+                                   const double* psl, const double* cvl, bool from_lds) {
   __shared__ double red2[kStageMaxSplits * 4];
   constexpr int VN = 2, STEP = 64 * VN, NW = 4, R = 2 * NW;
   const int tid = phase_tid(), lane = tid & 63, wave = tid >> 6;
@@ -44,9 +47,9 @@ __device__ void rows_stream_walker(const SysDev& s, const WalkDev& w, int wk, in
   auto rowp = [&](int j) -> const double* {
     return (up && j >= s.nd) ? (const double*)s.UphS + (long)(j - s.nd) * s.Lp : Pw + (long)j * s.Lp;
   };
-  const double* cv = w.cvec + (long)wk * s.nu;
+  const double* cv = from_lds ? cvl : w.cvec + (long)wk * s.nu;
   double* wn_g = w.w_new + (long)wk * s.nu;
-  const double* psi = w.psi_new + (long)wk * s.Lp;
+  const double* psi = from_lds ? psl : w.psi_new + (long)wk * s.Lp;
   double ps[NC][VN];
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
@@ -81,9 +84,11 @@ __device__ void rows_stream_walker(const SysDev& s, const WalkDev& w, int wk, in
       double part = 0.0;
       if (oka) {
         wn_g[ja] = xa;
+        hand->wn[ja] = xa;
         part += xa * aa;
         if (okb) {
           wn_g[jb] = xb;
+          hand->wn[jb] = xb;
           part += xb * ab;
         }
       }
@@ -95,6 +100,7 @@ __device__ void rows_stream_walker(const SysDev& s, const WalkDev& w, int wk, in
     double t = 0.0;
     for (int k = 0; k < NW; ++k) t += red2[tid * NW + k];
     w.rdet_part[(long)wk * S + tid] = t;
+    hand->part[tid] = t;
   }
 }
 
@@ -102,8 +108,11 @@ template <int QL, int NC, int IPB>
 __global__ void __launch_bounds__(256, 4)   // four waves per SIMD: 128 VGPRs
 sweep_segment_kernel(SysDev s, WalkDev w, int e0, int k, const double* __restrict__ disp,
                      const double* __restrict__ unif, int32_t* __restrict__ accept_count, int S, int FB, int since0,
-                     int mcl) {
+                     int mcl, int vec_min) {
   extern __shared__ __align__(16) char lds[];
+  __shared__ SweepHand hand;
+  // the inverse line the set-up leaves in the vector area (after d and v0)
+  const double* cvl = (const double*)(lds + stage_layout(s.nu, w.kb, mcl, vec_min).vec) + 2 * s.nu;
   const int N = s.N;
   const long Wk = w.Wk;
   for (int j = 0; j < k; ++j) {
@@ -113,13 +122,14 @@ sweep_segment_kernel(SysDev s, WalkDev w, int e0, int k, const double* __restric
     // held in registers across the loop
     int wk;
     asm volatile("s_mov_b32 %0, %1" : "=s"(wk) : "s"(blockIdx.x));
-    if constexpr (IPB > 0) screened_stream_walker<IPB>(s, w, wk, e, S, FB, lds);
-    else rows_stream_walker<NC>(s, w, wk, e, S);
+    if constexpr (IPB > 0) screened_stream_walker<IPB, true>(s, w, wk, e, S, FB, lds, &hand, cvl, j > 0);
+    else rows_stream_walker<NC>(s, w, wk, e, S, &hand, (const double*)lds, cvl, j > 0);
     if (j + 1 == k) break;
     __syncthreads();
     const int mc = min(since0 + j, mcl);
-    accept_prep_staged_phase<double, QL>(s, w, wk, e, unif + (long)j * Wk, accept_count, S, (e0 + j + 1) % N,
-                                         disp + (long)(j + 1) * Wk * 3, mc, mcl, lds);
+    accept_prep_staged_phase<double, QL, true>(s, w, wk, e, unif + (long)j * Wk, accept_count, S,
+                                               (e0 + j + 1) % N, disp + (long)(j + 1) * Wk * 3, mc, mcl, lds, &hand,
+                                               (size_t)vec_min);
     __syncthreads();
   }
 }
@@ -128,7 +138,7 @@ sweep_segment_kernel(SysDev s, WalkDev w, int e0, int k, const double* __restric
 // persistent kernel is not built for the system (the per-move launches run).
 struct SweepShape {
   int S, QL, NC, IPB, FB;
-  size_t lds_stream;
+  size_t lds_stream, vec_min;
 };
 static bool sweep_shape(const SysDev& s, const WalkDev& w, int e0, SweepShape& o) {
   if (s.store() != 0 || s.pairing || s.LJ > 0 || s.Lq > 0 || s.Lp > kFuseMaxLp || !w.wv || s.nu > kStageMaxN ||
@@ -148,7 +158,11 @@ static bool sweep_shape(const SysDev& s, const WalkDev& w, int e0, SweepShape& o
     o.NC = (s.Lp + 127) / 128;
     if (s.prop_rows() != 8 || (o.NC != 2 * o.QL && o.NC != 2 * o.QL - 1)) return false;
   }
-  return std::max(stage_layout(n, kb, 0).total, o.lds_stream) <= kSweepMaxLds;
+  // the hand-off region at the bottom of the LDS: the screened stream's kept
+  // list and partial sums, or psi(r') for the row stream; the set-up's vectors
+  // above it
+  o.vec_min = s.screened() ? o.lds_stream : pad1k(sizeof(double) * (size_t)s.Lp);
+  return stage_layout(n, kb, 0, o.vec_min).total <= kSweepMaxLds;
 }
 
 bool sweep_segment_ok(const SysDev& s, const WalkDev& w, int e0) {
@@ -166,10 +180,10 @@ hipError_t launch_sweep_segment(const SysDev& s, const WalkDev& w, int e0, int k
   const int n = s.nu, kb = w.kb;
   // staged rows: the most any move of the run can hold that the LDS allows
   int mcl = std::max(0, std::min(since0 + k - 2, kb - 1));
-  while (mcl > 0 && std::max(stage_layout(n, kb, mcl).total, o.lds_stream) > kSweepMaxLds) --mcl;
-  const size_t lds = std::max(stage_layout(n, kb, mcl).total, o.lds_stream);
+  while (mcl > 0 && stage_layout(n, kb, mcl, o.vec_min).total > kSweepMaxLds) --mcl;
+  const size_t lds = stage_layout(n, kb, mcl, o.vec_min).total;   // >= vec_min >= the stream's region
   const dim3 grid(w.Wk), blk(256);
-#define QMC_SWEEP(Q, C, I)                                                                                      hipExtLaunchKernelGGL((sweep_segment_kernel<Q, C, I>), grid, blk, lds, st, ev_start, ev_stop, 0, s, w, e0, k,                         disp, unif, accept_count, S, FB, since0, mcl)
+#define QMC_SWEEP(Q, C, I)                                                                                      hipExtLaunchKernelGGL((sweep_segment_kernel<Q, C, I>), grid, blk, lds, st, ev_start, ev_stop, 0, s, w, e0, k,                         disp, unif, accept_count, S, FB, since0, mcl, (int)o.vec_min)
 #define QMC_SWEEP_IPB(Q)                                                                switch (IPB) {                                                                          case 1: QMC_SWEEP(Q, 0, 1); break; case 2: QMC_SWEEP(Q, 0, 2); break;                 case 3: QMC_SWEEP(Q, 0, 3); break; case 4: QMC_SWEEP(Q, 0, 4); break;                 case 5: QMC_SWEEP(Q, 0, 5); break; case 6: QMC_SWEEP(Q, 0, 6); break;                 case 7: QMC_SWEEP(Q, 0, 7); break; default: QMC_SWEEP(Q, 0, 8); break;             }
   if (IPB > 0) {
     switch (QL) {
