@@ -238,6 +238,15 @@ struct WalkDev {
   int* muk;
   double* psk;
   int* nkeep;
+  // (QMC_REFINED) the positions at which each electron's P row was last built
+  // [Wk][N][3]; the rows of a P half whose electron has moved since, as
+  // indices into the half's row order (walker * n + i), and their count per
+  // half; the int8 row exponents in that compacted order
+  double* rpos_P;
+  int* dirty_idx;
+  int* dirty_cnt;
+  int* dirty_blk;   // per block of 256 rows: count, then offset [Wk * N / 256 + 1]
+  int* oz_ephi_c;
 };
 
 // Workspace of the reverse pass (allocated on the first qmc_forces call).
@@ -520,10 +529,15 @@ hipError_t launch_W_build(const SysDev& s, const WalkDev& w, hipStream_t st);
 long oz_plane_bytes(long rows, int Kp);
 long oz_phi_bytes(const SysDev& s, long Wk);
 hipError_t launch_slice_tiles(const double* X, long rows, int K, int Kp, int grp, long gs, long ld, int S,
-                              int8_t* out, long plane, int* expo, hipStream_t st, bool have_expo = false);
+                              int8_t* out, long plane, int* expo, hipStream_t st, bool have_expo = false,
+                              const int* ridx = nullptr, const int* rcnt = nullptr, int* expo_c = nullptr);
 hipError_t launch_oz_lambda(const SysDev& s, hipStream_t st);
+// dirty (QMC_REFINED, bit h for half h): build only the rows whose electron
+// has moved since its row was last built (the other rows of P, PT stand); every
+// half built records its positions for the next such build.
 hipError_t launch_P_build_oz(const SysDev& s, const WalkDev& w, int halves, const double* phi64, double* P64,
-                             void* lo, bool lo_bf16, hipStream_t st, bool have_expo = false, double* PT = nullptr);
+                             void* lo, bool lo_bf16, hipStream_t st, bool have_expo = false, double* PT = nullptr,
+                             int dirty = 0);
 // screened proposals: column maxima of the P halves, and the streaming kernel
 hipError_t launch_screen_colmax(const SysDev& s, const WalkDev& w, int halves, hipStream_t st);
 hipError_t launch_export_kept(const WalkDev& w, double* dst, hipStream_t st);

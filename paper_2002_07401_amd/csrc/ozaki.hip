@@ -41,21 +41,33 @@ constexpr int kOzMaxKSteps = 256;   // K <= 8192
 // read in chunks of 64 values, 8 threads per row reading 64 contiguous bytes
 // each; the chunk passes through LDS so that each thread then turns 8 values
 // of one row into digits and the 32 rows' pieces of a tile go out together.
+// With ridx, row m of the tiles is row ridx[m] of X (m < *rcnt; the rest of
+// the rows up to `rows` are not written) and the exponents go to expo_c in
+// that order (copied from expo[ridx[m]] with have_expo).
 __global__ void __launch_bounds__(256)
 slice_tiles_kernel(const double* __restrict__ X, long rows, int K, int Kp, int grp, long gs, long ld, int S,
-                   int8_t* __restrict__ out, long plane, int* __restrict__ expo, int have_expo) {
+                   int8_t* __restrict__ out, long plane, int* __restrict__ expo, int have_expo,
+                   const int* __restrict__ ridx, const int* __restrict__ rcnt, int* __restrict__ expo_c) {
   __shared__ double xs[32][65];
   __shared__ double red[32][9];
   __shared__ int se[32];
   const long g = blockIdx.x;
   const int tid = threadIdx.x;
   const int J = Kp / 32;
+  const long nrow = ridx ? min(rows, (long)*rcnt) : rows;
+  if (32 * g >= nrow) return;   // (uniform) tiles past the compacted rows are not read
   const int lr = tid >> 3, lc = tid & 7;          // load mapping: row, 8-value piece
   const long lm = 32 * g + lr;
-  const double* xrow = lm < rows ? X + (lm / grp) * gs + (lm % grp) * ld : nullptr;
+  const long src = lm < nrow ? (ridx ? (long)ridx[lm] : lm) : -1;
+  const double* xrow = src >= 0 ? X + (src / grp) * gs + (src % grp) * ld : nullptr;
+  int* eout = ridx ? expo_c : expo;
   // pass 1: row maxima (unless the producer of X gave the exponents)
   if (have_expo) {
-    if (tid < 32) se[tid] = 32 * g + tid < rows ? expo[32 * g + tid] : 0;
+    if (tid < 32) {
+      const long m = 32 * g + tid;
+      se[tid] = m < nrow ? expo[ridx ? (long)ridx[m] : m] : 0;
+      if (ridx && m < nrow) expo_c[m] = se[tid];
+    }
   } else {
     double mx = 0.0;
     if (xrow)
@@ -70,7 +82,7 @@ slice_tiles_kernel(const double* __restrict__ X, long rows, int K, int Kp, int g
       for (int c = 0; c < 8; ++c) m = fmax(m, red[tid][c]);
       const int E = m > 0.0 ? ilogb(m) : 0;
       se[tid] = E;
-      if (32 * g + tid < rows) expo[32 * g + tid] = E;
+      if (32 * g + tid < nrow) eout[32 * g + tid] = E;
     }
   }
   __syncthreads();
@@ -112,13 +124,15 @@ long oz_plane_bytes(long rows, int Kp) { return (rows + 31) / 32 * 32 * (long)Kp
 
 // Digits of `rows` rows into fragment tiles (plane: bytes per digit plane).
 hipError_t launch_slice_tiles(const double* X, long rows, int K, int Kp, int grp, long gs, long ld, int S, int8_t* out,
-                              long plane, int* expo, hipStream_t st, bool have_expo) {
+                              long plane, int* expo, hipStream_t st, bool have_expo, const int* ridx, const int* rcnt,
+                              int* expo_c) {
   if (rows <= 0) return hipSuccess;
   if (Kp % 32 != 0 || K > Kp || S < 1 || S > kOzMaxSlices) return hipErrorInvalidValue;
   if (plane < oz_plane_bytes(rows, Kp)) return hipErrorInvalidValue;
   const long G = (rows + 31) / 32;
+  if (ridx && (!rcnt || !expo_c)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(slice_tiles_kernel, dim3((unsigned)G), dim3(256), 0, st, X, rows, K, Kp, grp, gs, ld, S, out,
-                     plane, expo, have_expo ? 1 : 0);
+                     plane, expo, have_expo ? 1 : 0, ridx, rcnt, expo_c);
   return hipGetLastError();
 }
 
@@ -136,6 +150,7 @@ struct OzArgs {
   double* CT; long ct_gs; long ct_ld;                                 // optional transposed FP64 copy:
                                                                       // C[m][n] at (m/grp)*ct_gs + n*ct_ld + m%grp
   const uint8_t* kmask; int kmask_ld;                                 // nonzero 16 x 64 tiles of B^T
+  const int* ridx; const int* rcnt;   // optional: output row m is row ridx[m] of C (and CT), m < *rcnt
 };
 
 __device__ __forceinline__ long oz_xcd_remap(long id, long total) {
@@ -171,7 +186,12 @@ __global__ void __launch_bounds__(256) ozaki_gemm_kernel(OzArgs g, int gx, int g
   __shared__ __attribute__((aligned(16))) int8_t spare[1024];
   __shared__ short steps[kOzMaxKSteps];          // K steps with a nonzero B^T tile, in order
   __shared__ int nsteps;
-  const long Lb = oz_xcd_remap(blockIdx.x, (long)gridDim.x);
+  // with a row list, only its tiles are spread over the XCDs (the grid is
+  // sized for every row; the workgroups past the list's tiles leave at once)
+  const int Mr = g.ridx ? min(g.M, *g.rcnt) : g.M;   // rows with an output
+  const long nt = g.ridx ? (long)((Mr + 127) / 128) * gx : (long)gridDim.x;
+  if ((long)blockIdx.x >= nt) return;                  // (uniform, before any copy or barrier)
+  const long Lb = oz_xcd_remap(blockIdx.x, nt);
   const int bx = (int)(Lb % gx);
   const int by = (int)((Lb / gx) % gy);
   const int m0 = by * 128, n0 = bx * 64;
@@ -292,18 +312,19 @@ __global__ void __launch_bounds__(256) ozaki_gemm_kernel(OzArgs g, int gx, int g
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int gm = m0 + wave * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-      if (gm < g.M) {
+      if (gm < Mr) {
         double v = 0.0;
 #pragma unroll
         for (int q = S - 1; q >= 0; --q) v = v * (1.0 / 128.0) + (double)acc[q][c][r];
         v = ldexp(v, g.ea[gm] + en - 10);
-        const long off = (long)(gm / g.c_grp) * g.c_gs + (long)(gm % g.c_grp) * g.ldc + gn;
+        const int gr = g.ridx ? g.ridx[gm] : gm;   // the row of C
+        const long off = (long)(gr / g.c_grp) * g.c_gs + (long)(gr % g.c_grp) * g.ldc + gn;
         g.C[off] = v;
         if (g.C2) {
           if (g.c2_bf16) ((bf16s*)g.C2)[off] = bf16s(v);
           else ((float*)g.C2)[off] = (float)v;
         }
-        if (g.CT) g.CT[(long)(gm / g.c_grp) * g.ct_gs + (long)gn * g.ct_ld + (gm % g.c_grp)] = v;
+        if (g.CT) g.CT[(long)(gr / g.c_grp) * g.ct_gs + (long)gn * g.ct_ld + (gr % g.c_grp)] = v;
       }
     }
   }
@@ -345,13 +366,79 @@ long oz_phi_bytes(const SysDev& s, long Wk) {
   return (long)s.oz_s * (oz_plane_bytes(Wk * s.nu, s.Lp) + oz_plane_bytes(Wk * s.nd, s.Lp));
 }
 
+// The rows of one P half (rows i0 .. i0 + n - 1 of every walker) whose
+// electron has moved since its row was last built, listed in increasing order
+// of their index walker * n + i (so that a block of compacted rows still
+// writes P and its transpose in nearly contiguous runs): per block of 256 rows
+// the count of moved ones, an exclusive scan of the counts, then the list,
+// with the positions recorded.  ALL (a full build): positions only.
+__device__ __forceinline__ bool row_moved(const double* __restrict__ r, const double* __restrict__ rP, long o) {
+  return !(r[o] == rP[o] && r[o + 1] == rP[o + 1] && r[o + 2] == rP[o + 2]);
+}
+
+__global__ void __launch_bounds__(256)
+p_dirty_count_kernel(const double* __restrict__ r, const double* __restrict__ rP, int Wk, int N, int i0, int n,
+                     int* __restrict__ bcnt) {
+  __shared__ int wc[4];
+  const long t = (long)blockIdx.x * 256 + threadIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const bool moved = t < (long)Wk * n && row_moved(r, rP, ((t / n) * N + i0 + t % n) * 3);
+  const unsigned long long b = __ballot(moved);
+  if (lane == 0) wc[wave] = __popcll(b);
+  __syncthreads();
+  if (threadIdx.x == 0) bcnt[blockIdx.x] = wc[0] + wc[1] + wc[2] + wc[3];
+}
+
+// one workgroup of 1024 threads: bcnt[0 .. nb) -> exclusive offsets in place,
+// the total to *cnt
+__global__ void __launch_bounds__(1024) p_dirty_scan_kernel(int* __restrict__ bcnt, int nb, int* __restrict__ cnt) {
+  __shared__ int part[1024];
+  int carry = 0;
+  for (int c0 = 0; c0 < nb; c0 += 1024) {
+    const int i = c0 + (int)threadIdx.x;
+    const int v = i < nb ? bcnt[i] : 0;
+    part[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {   // inclusive Hillis-Steele scan
+      const int x = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0;
+      __syncthreads();
+      part[threadIdx.x] += x;
+      __syncthreads();
+    }
+    if (i < nb) bcnt[i] = carry + part[threadIdx.x] - v;
+    carry += part[1023];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *cnt = carry;
+}
+
+template <bool ALL>
+__global__ void __launch_bounds__(256)
+p_dirty_write_kernel(const double* __restrict__ r, double* __restrict__ rP, int Wk, int N, int i0, int n,
+                     const int* __restrict__ boff, int* __restrict__ idx) {
+  __shared__ int wc[4];
+  const long t = (long)blockIdx.x * 256 + threadIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const long o = ((t / n) * N + i0 + t % n) * 3;
+  const bool moved = t < (long)Wk * n && (ALL || row_moved(r, rP, o));
+  if (!ALL) {
+    const unsigned long long b = __ballot(moved);
+    if (lane == 0) wc[wave] = __popcll(b);
+    __syncthreads();
+    int at = boff[blockIdx.x] + __popcll(b & ((1ull << lane) - 1ull));
+    for (int k = 0; k < wave; ++k) at += wc[k];
+    if (moved) idx[at] = (int)t;
+  }
+  if (moved) { rP[o] = r[o]; rP[o + 1] = r[o + 1]; rP[o + 2] = r[o + 2]; }
+}
+
 // P halves (bit 0: up rows, bit 1: down rows) from the FP64 basis rows in
 // phi64: digits of those rows first (oz_phi: up tiles, then down tiles; with
 // have_expo the rows' exponents in oz_ephi are already set), then the
 // products; P64 gets the FP64 result, lo (if given) its FP32 / BF16 copy and PT
 // (if given) its transpose per walker, PT[w][mu][i].
 hipError_t launch_P_build_oz(const SysDev& s, const WalkDev& w, int halves, const double* phi64, double* P64,
-                             void* lo, bool lo_bf16, hipStream_t st, bool have_expo, double* PT) {
+                             void* lo, bool lo_bf16, hipStream_t st, bool have_expo, double* PT, int dirty) {
   const long rowst = (long)s.N * s.Lp;
   const long planeB = oz_plane_bytes(s.Lp, s.Lp);
   const int mask_ld = (s.Lp + kLamTileN - 1) / kLamTileN;
@@ -365,13 +452,42 @@ hipError_t launch_P_build_oz(const SysDev& s, const WalkDev& w, int halves, cons
     const long planeA = oz_plane_bytes(rows, s.Lp);
     int8_t* tiles = w.oz_phi + (h == 0 ? 0 : up_bytes);
     int* ex = w.oz_ephi + (h == 0 ? 0 : (long)w.Wk * s.nu);
+    // rows of this half that need a product (all, or those whose electron has
+    // moved: the positions of the rows built are recorded either way)
+    const bool dirt = (dirty >> h) & 1;
+    int* ridx = nullptr;
+    int* rcnt = nullptr;
+    int* exc = nullptr;
+    hipError_t e = hipSuccess;
+    if (w.rpos_P) {
+      const int i0 = h == 0 ? 0 : s.nu;
+      const int nb = (int)((rows + 255) / 256);
+      if (dirt) {
+        ridx = w.dirty_idx + (h == 0 ? 0 : (long)w.Wk * s.nu);
+        rcnt = w.dirty_cnt + h;
+        exc = w.oz_ephi_c + (h == 0 ? 0 : (long)w.Wk * s.nu);
+        int* boff = w.dirty_blk;
+        hipLaunchKernelGGL(p_dirty_count_kernel, dim3(nb), dim3(256), 0, st, w.r, w.rpos_P, w.Wk, s.N, i0, n, boff);
+        hipLaunchKernelGGL(p_dirty_scan_kernel, dim3(1), dim3(1024), 0, st, boff, nb, rcnt);
+        hipLaunchKernelGGL(p_dirty_write_kernel<false>, dim3(nb), dim3(256), 0, st, w.r, w.rpos_P, w.Wk, s.N, i0, n,
+                           boff, ridx);
+      } else {
+        hipLaunchKernelGGL(p_dirty_write_kernel<true>, dim3(nb), dim3(256), 0, st, w.r, w.rpos_P, w.Wk, s.N, i0, n,
+                           nullptr, nullptr);
+      }
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    } else if (dirt) {
+      return hipErrorInvalidValue;
+    }
     // rows m of this half: walker m / n, electron m % n of the spin
-    hipError_t e =
-        launch_slice_tiles(phi64 + r0, rows, s.L, s.Lp, n, rowst, s.Lp, s.oz_s, tiles, planeA, ex, st, have_expo);
+    e = launch_slice_tiles(phi64 + r0, rows, s.L, s.Lp, n, rowst, s.Lp, s.oz_s, tiles, planeA, ex, st, have_expo,
+                           ridx, rcnt, exc);
     if (e != hipSuccess) return e;
     OzArgs g{};
     g.M = (int)rows; g.N = s.Lp; g.Kp = s.Lp;
-    g.A = tiles; g.a_plane = planeA; g.ea = ex;
+    g.A = tiles; g.a_plane = planeA; g.ea = ridx ? exc : ex;
+    g.ridx = ridx; g.rcnt = rcnt;
     g.B = s.oz_lam + (long)h * s.oz_s * planeB; g.b_plane = planeB; g.eb = s.oz_elam + (long)h * s.Lp;
     g.C = P64 + r0; g.c_grp = n; g.c_gs = rowst; g.ldc = s.Lp;
     if (lo) {

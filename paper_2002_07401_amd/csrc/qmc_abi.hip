@@ -148,6 +148,10 @@ struct qmc_walkers {
   double drift_tol = 1e-6;        // status 3 when the checked residual exceeds this
   bool evaluated = false;
   bool P_up_valid = false, P_dn_valid = false;
+  // (QMC_REFINED) parameter generation at which each P half's rows were last
+  // built with their positions recorded (-1: never): a later build of that
+  // half may take only the rows whose electron has moved
+  long P_gen[2] = {-1, -1};
   // lattice-regularised DMC: the cofactor rows Yt hold for the positions of
   // the last evaluation until a move; hops computed for them (lr_ready)
   LrdmcDev lr{};
@@ -559,6 +563,11 @@ static void walker_layout(const SysDev& s, int n_walkers, bool adjoint, Carver& 
     c.take(&d.muk, sizeof(int) * Wk * s.Lp);
     c.take(&d.psk, sizeof(double) * Wk * s.Lp);
     c.take(&d.nkeep, sizeof(int) * Wk);
+    c.take(&d.rpos_P, sizeof(double) * Wk * N * 3);
+    c.take(&d.dirty_idx, sizeof(int) * Wk * N);
+    c.take(&d.dirty_cnt, sizeof(int) * 2);
+    c.take(&d.dirty_blk, sizeof(int) * ((size_t)Wk * N / 256 + 2));
+    c.take(&d.oz_ephi_c, sizeof(int) * Wk * N);
   }
   if (s.nu > kLuRowMax) {
     const size_t np = s.np;
@@ -776,11 +785,20 @@ extern "C" qmc_status qmc_eval_batch(qmc_system* sys, qmc_walkers* wk, const dou
     // product (see ozaki.hip); the moves' FP32 / BF16 rows (refined modes) or
     // the transposed rows of the screened proposals are written beside
     if (halves) {
+      // (QMC_REFINED) a half built before at these parameters: only the rows
+      // whose electron has moved since
+      int dirty = 0;
+      if (s.screened())
+        for (int h = 0; h < 2; ++h)
+          if (wk->P_gen[h] == sys->generation) dirty |= 1 << h;
       TIMED(wk, QMC_T_P_BUILD, stream,
             launch_P_build_oz(s, d, halves, de.phi == d.phi64 ? d.phi64 : (const double*)d.phi,
                               refine ? d.P64 : (double*)d.P, refine ? d.P : nullptr, s.bf16(), stream,
-                              ephi != nullptr, s.screened() ? d.PT : nullptr),
+                              ephi != nullptr, s.screened() ? d.PT : nullptr, dirty & halves),
             "P build");
+      if (s.screened())
+        for (int h = 0; h < 2; ++h)
+          if ((halves >> h) & 1) wk->P_gen[h] = sys->generation;
       if (s.screened())
         TIMED(wk, QMC_T_OTHER, stream, launch_screen_colmax(s, d, halves, stream), "column maxima");
     }
@@ -814,13 +832,22 @@ extern "C" qmc_status qmc_eval_batch(qmc_system* sys, qmc_walkers* wk, const dou
 }
 
 // P rows of the spin opposite to electron e must match the current basis rows.
-static hipError_t rebuild_P(const SysDev& s, const WalkDev& d, int halves, hipStream_t stream) {
+static hipError_t rebuild_P(qmc_walkers* wk, int halves, hipStream_t stream) {
+  const SysDev& s = wk->sys->d;
+  const WalkDev& d = wk->d;
   if (!s.screened()) return launch_P_build(s, d, halves, stream);
-  // refined int8 products from the FP64 rows the accepts maintain, with the
+  // refined int8 products from the FP64 rows the accepts maintain (only the
+  // rows whose electron has moved since the half was last built), with the
   // transposed rows and column maxima of the screened proposals
+  int dirty = 0;
+  for (int h = 0; h < 2; ++h)
+    if (((halves >> h) & 1) && wk->P_gen[h] == wk->sys->generation) dirty |= 1 << h;
   hipError_t e = launch_P_build_oz(s, d, halves, (const double*)d.phi, (double*)d.P, nullptr, false, stream, false,
-                                   d.PT);
+                                   d.PT, dirty);
   if (e == hipSuccess) e = launch_screen_colmax(s, d, halves, stream);
+  if (e == hipSuccess)
+    for (int h = 0; h < 2; ++h)
+      if ((halves >> h) & 1) wk->P_gen[h] = wk->sys->generation;
   return e;
 }
 
@@ -828,10 +855,10 @@ static qmc_status ensure_P(qmc_walkers* wk, int e, hipStream_t stream) {
   const SysDev& s = wk->sys->d;
   const bool up = e < s.nu;
   if (up && !wk->P_dn_valid) {
-    TIMED(wk, QMC_T_P_REBUILD, stream, rebuild_P(s, wk->d, 2, stream), "P_dn rebuild");
+    TIMED(wk, QMC_T_P_REBUILD, stream, rebuild_P(wk, 2, stream), "P_dn rebuild");
     wk->P_dn_valid = true;
   } else if (!up && !wk->P_up_valid) {
-    TIMED(wk, QMC_T_P_REBUILD, stream, rebuild_P(s, wk->d, 1, stream), "P_up rebuild");
+    TIMED(wk, QMC_T_P_REBUILD, stream, rebuild_P(wk, 1, stream), "P_up rebuild");
     wk->P_up_valid = true;
   }
   return QMC_OK;

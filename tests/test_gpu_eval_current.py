@@ -14,6 +14,9 @@ explicitly gives:
   explicit build from the evaluation's own, which agree to rounding), and the
   FP64 and refined results within the bars of the evaluation parity tests
   against the oracle;
+* the same against a fresh walker set evaluated at those positions (every P
+  row built anew; in QMC_REFINED a build otherwise takes only the rows whose
+  electron has moved since the row was last built);
 * moves after it: a sweep on both walker sets gives bitwise equal positions;
 * refusal before the first evaluation; after a parameter change both halves are
   built again (results as the explicit evaluation of the changed system).
@@ -85,6 +88,13 @@ def test_eval_at_current_positions(name, prec):
             ref = O.evaluate(sy, ra.cpu())
             for k in KEYS:
                 assert rel_err(oa[k].cpu(), ref[k]).max().item() <= oracle_bar, (label, k)
+    # a fresh walker set (every row built from scratch) at the same positions
+    c = P.Walkers(sysh, Wk, adjoint=False)
+    oc = c.eval_batch(a.read(P.STATE_R))
+    oa = a.eval_batch(None)
+    torch.cuda.synchronize()
+    _close(oa, oc, 1e-12)
+    c.close()
     # moves after the evaluation at the current positions
     _moves(a, 0, N, 999)
     _moves(b, 0, N, 999)
