@@ -62,11 +62,17 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g, int gx, int gy) {
   __shared__ TI Bs[BK][BN + 1];
   typedef typename Mfma<TI>::acc_t acc_t;
 
-  const long L = xcd_remap(blockIdx.x, (long)gridDim.x);
+  // with a row list, only its tiles are dealt out (the grid is sized for M
+  // rows; the workgroups past the list's tiles leave at once)
+  const int Mr = g.ridx ? min(g.M, *g.rcnt) : g.M;
+  const int gyr = g.ridx ? (Mr + BM - 1) / BM : gy;
+  const long nt = g.ridx ? (long)gx * gyr * g.batch : (long)gridDim.x;
+  if ((long)blockIdx.x >= nt) return;   // (uniform, before any barrier)
+  const long L = xcd_remap(blockIdx.x, nt);
   const int bx = (int)(L % gx);
   const long rest = L / gx;
-  const int by = (int)(rest % gy);
-  const long bz = rest / gy;
+  const int by = (int)(rest % gyr);
+  const long bz = rest / gyr;
   const SA* __restrict__ A = (const SA*)g.A + bz * g.a_bs;
   const SB* __restrict__ B = (const SB*)g.B + bz * g.b_bs;
   TO* __restrict__ C = (TO*)g.C + bz * g.c_bs;
@@ -86,9 +92,10 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g, int gx, int gy) {
     int mm, kk;
     if (TA) { kk = idx / BM; mm = idx % BM; } else { mm = idx / BK; kk = idx % BK; }
     const int gm = m0 + mm;
-    akk[q] = kk; amm[q] = mm; aok[q] = gm < g.M;
+    akk[q] = kk; amm[q] = mm; aok[q] = gm < Mr;
+    const int gr = (g.ridx && gm < Mr) ? g.ridx[gm] : gm;   // the row of A
     aoff[q] = TA ? (long)kk * g.lda + gm
-                 : (long)(gm / g.a_grp) * g.a_gs + (long)(gm % g.a_grp) * g.lda + kk;
+                 : (long)(gr / g.a_grp) * g.a_gs + (long)(gr % g.a_grp) * g.lda + kk;
   }
 #pragma unroll
   for (int q = 0; q < EB; ++q) {
@@ -168,8 +175,9 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g, int gx, int gy) {
       for (int r = 0; r < 4; ++r) {
         const int gm = m0 + wm * WM + i * 16 + Mfma<TI>::row(lane, r);
         const int gn = n0 + wn * WN + j * 16 + (lane & 15);
-        if (gm < g.M && gn < g.N) {
-          const long off = (long)(gm / g.c_grp) * g.c_gs + (long)(gm % g.c_grp) * g.ldc + gn;
+        if (gm < Mr && gn < g.N) {
+          const int gr = g.ridx ? g.ridx[gm] : gm;   // the row of C
+          const long off = (long)(gr / g.c_grp) * g.c_gs + (long)(gr % g.c_grp) * g.ldc + gn;
           TO* cp = C + off;
           if constexpr (sizeof(TO) == 2) {
             *cp = (TO)acc[i][j][r];   // BF16 output: never accumulated
@@ -230,14 +238,22 @@ static hipError_t P_gemm(const GemmArgs& g, hipStream_t st) {
 // lo (FP64 products only): also store P as FP32 / BF16 there (the moves' copy).
 template <typename T, typename TL = T>
 static hipError_t P_build_t(const SysDev& s, const WalkDev& w, int halves, hipStream_t st,
-                            const TL* lam, const TL* lamT, void* lo = nullptr, bool lo_bf16 = false) {
+                            const TL* lam, const TL* lamT, void* lo = nullptr, bool lo_bf16 = false, int dirty = 0) {
   const long rowst = (long)s.N * s.Lp;
   const T* phi = (const T*)w.phi;
   T* P = (T*)w.P;
   hipError_t e = hipSuccess;
   const int mask_ld = (s.Lp + kLamTileN - 1) / kLamTileN;
+  int* ridx[2] = {nullptr, nullptr};
+  int* rcnt[2] = {nullptr, nullptr};
+  for (int h = 0; h < 2; ++h)
+    if ((halves >> h) & 1) {
+      e = launch_moved_rows(s, w, h, (dirty >> h) & 1, &ridx[h], &rcnt[h], st);
+      if (e != hipSuccess) return e;
+    }
   if (halves & 1) {   // P_up = Phi_up Lambda  (rows 0..nu-1 of every walker)
     GemmArgs g = plain(w.Wk * s.nu, s.Lp, s.Lp);
+    g.ridx = ridx[0]; g.rcnt = rcnt[0];
     g.A = phi; g.lda = s.Lp; g.a_grp = s.nu; g.a_gs = rowst;
     g.B = lam; g.ldb = s.Lp;
     g.kmask = s.lam_mask; g.kmask_ld = mask_ld;
@@ -248,6 +264,7 @@ static hipError_t P_build_t(const SysDev& s, const WalkDev& w, int halves, hipSt
   }
   if (halves & 2) {   // P_dn = Phi_dn Lambda^T (rows nu..N-1)
     GemmArgs g = plain(w.Wk * s.nd, s.Lp, s.Lp);
+    g.ridx = ridx[1]; g.rcnt = rcnt[1];
     g.A = phi + (long)s.nu * s.Lp; g.lda = s.Lp; g.a_grp = s.nd; g.a_gs = rowst;
     g.B = lamT; g.ldb = s.Lp;
     g.kmask = s.lamT_mask; g.kmask_ld = mask_ld;
@@ -374,10 +391,10 @@ static hipError_t P_build_bf16(const SysDev& s, const WalkDev& w, int halves, hi
 }
 
 hipError_t launch_P_build(const SysDev& s, const WalkDev& w, int halves, hipStream_t st, void* lo,
-                          bool lo_bf16) {
-  if (s.bf16()) return P_build_bf16(s, w, halves, st);
-  if (s.f32()) return P_build_t<float>(s, w, halves, st, s.lam32, s.lamT32);
-  return P_build_t<double>(s, w, halves, st, s.lam, s.lamT, lo, lo_bf16);
+                          bool lo_bf16, int dirty) {
+  if (s.bf16()) return dirty ? hipErrorInvalidValue : P_build_bf16(s, w, halves, st);
+  if (s.f32()) return P_build_t<float>(s, w, halves, st, s.lam32, s.lamT32, nullptr, false, dirty);
+  return P_build_t<double>(s, w, halves, st, s.lam, s.lamT, lo, lo_bf16, dirty);
 }
 
 // W[w] = P_up[w] Phi_dn[w]^T  ->  W[i][j] = sum_nu (Phi_up Lambda)[i][nu] psi_nu(r_j),

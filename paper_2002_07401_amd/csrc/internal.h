@@ -522,8 +522,16 @@ __device__ __forceinline__ float wave_sum(float v) {
 hipError_t launch_basis_values(const SysDev& s, const WalkDev& w, hipStream_t st, void* lo = nullptr,
                                bool lo_bf16 = false, int* ephi = nullptr);
 hipError_t launch_downcast(const double* src, void* dst, bool to_bf16, long n, hipStream_t st);
+// dirty (FP64 and FP32 products, bit h for half h): only the rows whose
+// electron has moved since the row was last built (launch_moved_rows)
 hipError_t launch_P_build(const SysDev& s, const WalkDev& w, int halves, hipStream_t st,
-                          void* lo = nullptr, bool lo_bf16 = false);
+                          void* lo = nullptr, bool lo_bf16 = false, int dirty = 0);
+// The rows of P half h (0: up, 1: down) whose electron has moved since the row
+// was last built, in increasing order (*ridx, count at *rcnt on the device),
+// recording the positions; moved_only = false: every row (positions only, no
+// list).  Nothing to do (and no list) when the walker set keeps no positions.
+hipError_t launch_moved_rows(const SysDev& s, const WalkDev& w, int h, bool moved_only, int** ridx, int** rcnt,
+                             hipStream_t st);
 hipError_t launch_W_build(const SysDev& s, const WalkDev& w, hipStream_t st);
 // int8 digit tiles of FP64 rows and the error-free products built from them
 long oz_plane_bytes(long rows, int Kp);
@@ -642,6 +650,10 @@ struct GemmArgs {
   // honoured by the 64-column-tile kernels, which skip zero tiles
   const uint8_t* kmask;
   int kmask_ld;
+  // optional row list (row-major A, not TA): output row m is row ridx[m] of A
+  // and of C, for m < *rcnt (the grid is sized for M rows)
+  const int* ridx;
+  const int* rcnt;
 };
 
 // Plain (ungathered) argument block for an M x N x K product.

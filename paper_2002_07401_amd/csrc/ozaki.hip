@@ -432,6 +432,30 @@ p_dirty_write_kernel(const double* __restrict__ r, double* __restrict__ rP, int 
   if (moved) { rP[o] = r[o]; rP[o + 1] = r[o + 1]; rP[o + 2] = r[o + 2]; }
 }
 
+hipError_t launch_moved_rows(const SysDev& s, const WalkDev& w, int h, bool moved_only, int** ridx, int** rcnt,
+                             hipStream_t st) {
+  *ridx = nullptr;
+  *rcnt = nullptr;
+  if (!w.rpos_P) return moved_only ? hipErrorInvalidValue : hipSuccess;
+  const int n = h == 0 ? s.nu : s.nd, i0 = h == 0 ? 0 : s.nu;
+  const long rows = (long)w.Wk * n;
+  if (rows <= 0) return hipSuccess;
+  const int nb = (int)((rows + 255) / 256);
+  if (moved_only) {
+    *ridx = w.dirty_idx + (h == 0 ? 0 : (long)w.Wk * s.nu);
+    *rcnt = w.dirty_cnt + h;
+    int* boff = w.dirty_blk;
+    hipLaunchKernelGGL(p_dirty_count_kernel, dim3(nb), dim3(256), 0, st, w.r, w.rpos_P, w.Wk, s.N, i0, n, boff);
+    hipLaunchKernelGGL(p_dirty_scan_kernel, dim3(1), dim3(1024), 0, st, boff, nb, *rcnt);
+    hipLaunchKernelGGL(p_dirty_write_kernel<false>, dim3(nb), dim3(256), 0, st, w.r, w.rpos_P, w.Wk, s.N, i0, n,
+                       boff, *ridx);
+  } else {
+    hipLaunchKernelGGL(p_dirty_write_kernel<true>, dim3(nb), dim3(256), 0, st, w.r, w.rpos_P, w.Wk, s.N, i0, n,
+                       nullptr, nullptr);
+  }
+  return hipGetLastError();
+}
+
 // P halves (bit 0: up rows, bit 1: down rows) from the FP64 basis rows in
 // phi64: digits of those rows first (oz_phi: up tiles, then down tiles; with
 // have_expo the rows' exponents in oz_ephi are already set), then the
@@ -458,28 +482,9 @@ hipError_t launch_P_build_oz(const SysDev& s, const WalkDev& w, int halves, cons
     int* ridx = nullptr;
     int* rcnt = nullptr;
     int* exc = nullptr;
-    hipError_t e = hipSuccess;
-    if (w.rpos_P) {
-      const int i0 = h == 0 ? 0 : s.nu;
-      const int nb = (int)((rows + 255) / 256);
-      if (dirt) {
-        ridx = w.dirty_idx + (h == 0 ? 0 : (long)w.Wk * s.nu);
-        rcnt = w.dirty_cnt + h;
-        exc = w.oz_ephi_c + (h == 0 ? 0 : (long)w.Wk * s.nu);
-        int* boff = w.dirty_blk;
-        hipLaunchKernelGGL(p_dirty_count_kernel, dim3(nb), dim3(256), 0, st, w.r, w.rpos_P, w.Wk, s.N, i0, n, boff);
-        hipLaunchKernelGGL(p_dirty_scan_kernel, dim3(1), dim3(1024), 0, st, boff, nb, rcnt);
-        hipLaunchKernelGGL(p_dirty_write_kernel<false>, dim3(nb), dim3(256), 0, st, w.r, w.rpos_P, w.Wk, s.N, i0, n,
-                           boff, ridx);
-      } else {
-        hipLaunchKernelGGL(p_dirty_write_kernel<true>, dim3(nb), dim3(256), 0, st, w.r, w.rpos_P, w.Wk, s.N, i0, n,
-                           nullptr, nullptr);
-      }
-      e = hipGetLastError();
-      if (e != hipSuccess) return e;
-    } else if (dirt) {
-      return hipErrorInvalidValue;
-    }
+    hipError_t e = launch_moved_rows(s, w, h, dirt, &ridx, &rcnt, st);
+    if (e != hipSuccess) return e;
+    if (ridx) exc = w.oz_ephi_c + (h == 0 ? 0 : (long)w.Wk * s.nu);
     // rows m of this half: walker m / n, electron m % n of the spin
     e = launch_slice_tiles(phi64 + r0, rows, s.L, s.Lp, n, rowst, s.Lp, s.oz_s, tiles, planeA, ex, st, have_expo,
                            ridx, rcnt, exc);

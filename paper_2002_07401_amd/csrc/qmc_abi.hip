@@ -563,11 +563,13 @@ static void walker_layout(const SysDev& s, int n_walkers, bool adjoint, Carver& 
     c.take(&d.muk, sizeof(int) * Wk * s.Lp);
     c.take(&d.psk, sizeof(double) * Wk * s.Lp);
     c.take(&d.nkeep, sizeof(int) * Wk);
+    c.take(&d.oz_ephi_c, sizeof(int) * Wk * N);
+  }
+  if (!s.refined() && !s.pairing) {   // P builds of the moved rows only (FP64, FP32, QMC_REFINED)
     c.take(&d.rpos_P, sizeof(double) * Wk * N * 3);
     c.take(&d.dirty_idx, sizeof(int) * Wk * N);
     c.take(&d.dirty_cnt, sizeof(int) * 2);
     c.take(&d.dirty_blk, sizeof(int) * ((size_t)Wk * N / 256 + 2));
-    c.take(&d.oz_ephi_c, sizeof(int) * Wk * N);
   }
   if (s.nu > kLuRowMax) {
     const size_t np = s.np;
@@ -788,7 +790,7 @@ extern "C" qmc_status qmc_eval_batch(qmc_system* sys, qmc_walkers* wk, const dou
       // (QMC_REFINED) a half built before at these parameters: only the rows
       // whose electron has moved since
       int dirty = 0;
-      if (s.screened())
+      if (s.screened() && d.rpos_P)
         for (int h = 0; h < 2; ++h)
           if (wk->P_gen[h] == sys->generation) dirty |= 1 << h;
       TIMED(wk, QMC_T_P_BUILD, stream,
@@ -803,8 +805,17 @@ extern "C" qmc_status qmc_eval_batch(qmc_system* sys, qmc_walkers* wk, const dou
         TIMED(wk, QMC_T_OTHER, stream, launch_screen_colmax(s, d, halves, stream), "column maxima");
     }
   } else if (halves) {
-    TIMED(wk, QMC_T_P_BUILD, stream, launch_P_build(se, de, halves, stream, refine ? d.P : nullptr, s.bf16()),
-          "P build");
+    // (FP64, FP32) a half built before at these parameters: only the rows
+    // whose electron has moved since
+    int dirty = 0;
+    if (d.rpos_P)
+      for (int h = 0; h < 2; ++h)
+        if (((halves >> h) & 1) && wk->P_gen[h] == sys->generation) dirty |= 1 << h;
+    TIMED(wk, QMC_T_P_BUILD, stream,
+          launch_P_build(se, de, halves, stream, refine ? d.P : nullptr, s.bf16(), dirty), "P build");
+    if (d.rpos_P)
+      for (int h = 0; h < 2; ++h)
+        if ((halves >> h) & 1) wk->P_gen[h] = sys->generation;
   }
   TIMED(wk, QMC_T_W_BUILD, stream, launch_W_build(se, de, stream), "W build");
   TIMED(wk, QMC_T_LU, stream, launch_lu_inverse(se, de, stream), "LU");
@@ -835,7 +846,17 @@ extern "C" qmc_status qmc_eval_batch(qmc_system* sys, qmc_walkers* wk, const dou
 static hipError_t rebuild_P(qmc_walkers* wk, int halves, hipStream_t stream) {
   const SysDev& s = wk->sys->d;
   const WalkDev& d = wk->d;
-  if (!s.screened()) return launch_P_build(s, d, halves, stream);
+  if (!s.screened()) {
+    int dirty = 0;
+    if (d.rpos_P)
+      for (int h = 0; h < 2; ++h)
+        if (((halves >> h) & 1) && wk->P_gen[h] == wk->sys->generation) dirty |= 1 << h;
+    hipError_t e = launch_P_build(s, d, halves, stream, nullptr, false, dirty);
+    if (e == hipSuccess && d.rpos_P)
+      for (int h = 0; h < 2; ++h)
+        if ((halves >> h) & 1) wk->P_gen[h] = wk->sys->generation;
+    return e;
+  }
   // refined int8 products from the FP64 rows the accepts maintain (only the
   // rows whose electron has moved since the half was last built), with the
   // transposed rows and column maxima of the screened proposals
