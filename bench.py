@@ -135,10 +135,10 @@ def kernel_models(s, Wk, esz, acc_rate, kept=None, p_rows=None):
              one spin and at each change of spin) and grows by the
              acceptance rate per move.
     P_build: the evaluation's P = Phi Lambda, 2 L^2 flops per basis row over
-             Wk * p_rows rows: p_rows = N when both spins are built, n_dn
-             when the evaluation at the chain's current positions finds the up
-             rows current (the one-spin rebuilds before moves have a timer of
-             their own).
+             Wk * p_rows rows: p_rows = N when both spins are built; after a
+             sweep the up rows are current and only the rows of the down
+             electrons that moved are built (n_dn times the share that moved;
+             the one-spin rebuilds before moves have a timer of their own).
     """
     L, N, n = s.n_basis, s.n_up + s.n_dn, s.n_up
     cap = min(s.refresh_every, 64)
@@ -279,9 +279,15 @@ def run_precision(P, C, w, args, precision):
     tim = wk.timing()
     n_acc = cnt.sum().item()
     wk.set_timing(True)
+    r_a = wk.read(P.STATE_R)
     step(n_tot)
     one = wk.timing()
     wk.set_timing(False)
+    # the share of each spin's electrons that moved in a sweep (measured on
+    # this step): FP64, FP32 and the refined mode build only those P rows
+    moved = (wk.read(P.STATE_R) != r_a).any(-1)
+    f_up = moved[:, :s.n_up].double().mean().item()
+    f_dn = moved[:, s.n_up:].double().mean().item()
     t_eval = sum(e[0].elapsed_time(e[1]) for e in evs) / 1e3
     t_move = sum(e[1].elapsed_time(e[2]) for e in evs) / 1e3
     moves = args.steps * N * Wk
@@ -330,8 +336,11 @@ def run_precision(P, C, w, args, precision):
     # the timed evaluations run at the chain's positions after full sweeps: in
     # FP64, FP32 and the refined mode the up rows of P are current from the
     # rebuild between the halves of the sweep, and their P_build builds the
-    # down rows only (the other modes rebuild their FP64 P for both spins)
-    p_rows = s.n_dn if precision in ("fp64", "fp32", "mixed") else N
+    # rows of the down electrons that moved in the sweep (the rebuild, those of
+    # the up electrons); the other modes rebuild their FP64 P for both spins
+    part = precision in ("fp64", "fp32", "mixed")
+    p_rows = s.n_dn * f_dn if part else N
+    rb_rows = s.n_up * f_up if part else s.n_up
     models = kernel_models(s, Wk, esz, acc_rate, kept, p_rows)
     sw = sweep_bytes(models, tim, args.steps * N)
     if sw is not None:
@@ -355,7 +364,7 @@ def run_precision(P, C, w, args, precision):
                 "flops_per_launch": int(units), "avg_launch_us": round(avg_ms * 1e3, 2)}
     steps = step_rooflines(s, Wk, precision, one, roof if roof["kernel"] == "propose" else
                            prop_roofline(models, tim), models["accept"][1], p_rows,
-                           roof if roof["kernel"] == "sweep" else None)
+                           roof if roof["kernel"] == "sweep" else None, rb_rows)
     # MFMA use of the geminal build's dominant product (P = Phi Lambda in the
     # evaluations of the timed steps).  Refined modes: int8 operations of the
     # digit products (the P_build timer also covers the digit split) against
@@ -368,7 +377,7 @@ def run_precision(P, C, w, args, precision):
         wmfma = {"kernel": "P_build", "instruction": "v_mfma_f64_16x16x4f64" if precision == "fp64"
                  else "v_mfma_f32_16x16x4f32", "achieved": round(pf_tf, 2), "peak": MFMA_PEAK_TFLOPS[precision],
                  "unit": "TFLOP/s", "frac": round(pf_tf / MFMA_PEAK_TFLOPS[precision], 4),
-                 "flops_per_launch": int(models["P_build"][1]), "rows_per_walker": p_rows,
+                 "flops_per_launch": int(models["P_build"][1]), "rows_per_walker": round(p_rows, 2),
                  "avg_launch_us": round(pf_ms * 1e3, 2)}
     else:
         Lp = (s.n_basis + 31) // 32 * 32
@@ -378,7 +387,7 @@ def run_precision(P, C, w, args, precision):
                  "peak": INT8_PEAK_TOPS, "unit": "TOP/s", "frac": round(int8 / INT8_PEAK_TOPS, 4),
                  "ops_per_launch": int(ops), "digit_products": OZ_DIGITS * (OZ_DIGITS + 1) // 2,
                  "fp64_equivalent_TFLOPs": round(models["P_build"][1] / (pf_ms * 1e-3) / 1e12, 2),
-                 "rows_per_walker": p_rows, "avg_launch_us": round(pf_ms * 1e3, 2)}
+                 "rows_per_walker": round(p_rows, 2), "avg_launch_us": round(pf_ms * 1e3, 2)}
     wk.close()
     sysh.close()
     return {
@@ -773,7 +782,7 @@ def achievable_peaks():
             "datasheet": {"hbm_GBps": HBM_PEAK_GBS, "fp64_TFLOPs": 78.6, "fp32_TFLOPs": 157.3}}
 
 
-def step_rooflines(s, Wk, precision, one, prop_roof, acc_model=None, p_rows=None, sweep_roof=None):
+def step_rooflines(s, Wk, precision, one, prop_roof, acc_model=None, p_rows=None, sweep_roof=None, rb_rows=None):
     """Roofline of each step of one evaluation (and the proposal) from the
     one-step timers: algorithmic bytes or flops per launch / average launch.
       basis:   writes the N x L values of every walker (FP64; FP32 in fp32 mode)
@@ -781,8 +790,9 @@ def step_rooflines(s, Wk, precision, one, prop_roof, acc_model=None, p_rows=None
                or n_dn when the up rows are reused; MFMA; FP64 but in fp32
                mode); the refined modes count the int8 operations of their 28
                digit products, 2 Lp^2 x 28 per row (Lp = L rounded up to 32)
-      P_rebuild (fp64, fp32, mixed): the same per row over the n_up rows
-               rebuilt before the down electrons move
+      P_rebuild (fp64, fp32, mixed): the same per row over the rb_rows rows
+               per walker rebuilt before the down electrons move (those of
+               the up electrons that moved; n_up when not given)
       W_build: 2 n_up n_dn L flops per walker (FP64 MFMA accumulation)
       LU:      2 n^3 flops per walker per launch (FP64 vector ALU, latency-bound
                at n = 80: one workgroup per walker)
@@ -807,7 +817,7 @@ def step_rooflines(s, Wk, precision, one, prop_roof, acc_model=None, p_rows=None
         "Y_build": ("mfma", 4.0 * nu * nu * L * Wk, 78.6, "TFLOP/s", 1e12),
     }
     if precision in ("fp64", "fp32", "mixed"):
-        models["P_rebuild"] = p_model(nu)
+        models["P_rebuild"] = p_model(nu if rb_rows is None else rb_rows)
     out = {}
     for k, (bound, units, peak, unit, scale) in models.items():
         ms, cnt = one.get(k, (0.0, 0))
