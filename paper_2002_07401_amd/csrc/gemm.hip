@@ -400,9 +400,104 @@ hipError_t launch_P_build(const SysDev& s, const WalkDev& w, int halves, hipStre
 // W[w] = P_up[w] Phi_dn[w]^T  ->  W[i][j] = sum_nu (Phi_up Lambda)[i][nu] psi_nu(r_j),
 // and with unpaired orbitals (eq:wfAGPunpaired) the last nk columns
 // W[i][n_dn + l] = psi(r_i) . U[:, l] = (Phi_up Uph^T)[i][l].  W is n_up x n_up.
+// The geminal matrix of one walker per workgroup, W = P_up Phi_dn^T (n x n,
+// K = Lp), for n = n_up = n_dn = 16 RB <= 80, Lp a multiple of 32 and no
+// unpaired orbitals.  The batched product reads 16 n Lp bytes per walker for
+// 2 n^2 Lp flops, about the FP64 matrix cores' ratio of flops to HBM bytes, so
+// the kernel keeps both busy: K advances in chunks of 16 whose rows are read
+// with 16-byte loads into registers while the previous chunk's MFMAs run from
+// LDS, where both operands sit in fragment order (each K step's 64 lane values
+// of a 16-row block contiguous).  Wave rb owns output rows 16 rb .. 16 rb + 15.
+// Products accumulate in k order in steps of 4 with the generic kernel's
+// instruction, so W is bitwise the same.
+template <typename T, int RB>
+__global__ void __launch_bounds__(64 * RB, RB == 5 ? 5 : 4) wgem_kernel(const T* __restrict__ Pg, const T* __restrict__ Fg,
+                                                          double* __restrict__ Wg, int N, int Lp) {
+  constexpr int n = 16 * RB, KC = 16, SC = KC / 4;   // K per chunk, K steps per chunk
+  constexpr int HC = KC / 2, PQ = KC / 8;             // column pairs per row, pieces per thread and operand
+  __shared__ double La[RB * SC * 64], Lb[RB * SC * 64];   // [row block][K step in chunk][lane]
+  const long wk = xcd_remap(blockIdx.x, gridDim.x);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const T* Pa = Pg + wk * N * (long)Lp;             // P_up rows
+  const T* Fb = Fg + (wk * N + n) * (long)Lp;       // Phi_dn rows
+  // each thread copies PQ pieces of 16 bytes (2 columns) of each operand per
+  // chunk: piece q is row tid / HC + (64 RB / HC) q, columns 2 (tid % HC) + {0, 1}
+  // (a uniform base per piece and one lane offset)
+  const int loff = (tid / HC) * Lp + 2 * (tid % HC);
+  double2 ra[PQ], rb[PQ];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < PQ; ++q) {
+      const long ub = (long)(64 * RB / HC * q) * Lp + k0;
+      if constexpr (sizeof(T) == 8) {
+        ra[q] = *(const double2*)((Pa + ub) + loff);
+        rb[q] = *(const double2*)((Fb + ub) + loff);
+      } else {
+        const float2 x = *(const float2*)((Pa + ub) + loff);
+        const float2 y = *(const float2*)((Fb + ub) + loff);
+        ra[q] = double2{(double)x.x, (double)x.y};
+        rb[q] = double2{(double)y.x, (double)y.y};
+      }
+    }
+  };
+  // fragment order: column k of the chunk goes to K step k / 4, lane (k % 4) 16 + row % 16
+  auto store = [&]() {
+#pragma unroll
+    for (int q = 0; q < PQ; ++q) {
+      const int row = tid / HC + 64 * RB / HC * q, k = 2 * (tid % HC);
+      const int o = ((row >> 4) * SC + (k >> 2)) * 64 + (k & 3) * 16 + (row & 15);
+      La[o] = ra[q].x; La[o + 16] = ra[q].y;
+      Lb[o] = rb[q].x; Lb[o + 16] = rb[q].y;
+    }
+  };
+  dx4 acc[RB];
+#pragma unroll
+  for (int cb = 0; cb < RB; ++cb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[cb][r] = 0.0;
+  load(0);
+  for (int k0 = 0; k0 < Lp; k0 += KC) {
+    store();
+    __syncthreads();
+    if (k0 + KC < Lp) load(k0 + KC);
+#pragma unroll
+    for (int st = 0; st < SC; ++st) {
+      const double a = La[(wave * SC + st) * 64 + lane];
+#pragma unroll
+      for (int cb = 0; cb < RB; ++cb)
+        acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Lb[(cb * SC + st) * 64 + lane], acc[cb], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // 16 x 16 block layout: lane holds column lane % 16 and rows 4 r + lane / 16
+  double* W = Wg + wk * (long)n * n;
+#pragma unroll
+  for (int cb = 0; cb < RB; ++cb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) W[(long)(wave * 16 + 4 * r + (lane >> 4)) * n + cb * 16 + (lane & 15)] = acc[cb][r];
+}
+
+template <typename T>
+static hipError_t launch_wgem(const SysDev& s, const WalkDev& w, hipStream_t st) {
+#define QMC_WG(R)                                                                                               \
+  hipLaunchKernelGGL((wgem_kernel<T, R>), dim3((unsigned)w.Wk), dim3(64 * R), 0, st, (const T*)w.P, (const T*)w.phi, \
+                     w.W, s.N, s.Lp)
+  switch (s.nu / 16) {
+    case 1: QMC_WG(1); break;
+    case 2: QMC_WG(2); break;
+    case 3: QMC_WG(3); break;
+    case 4: QMC_WG(4); break;
+    default: QMC_WG(5); break;
+  }
+#undef QMC_WG
+  return hipGetLastError();
+}
+
 template <typename T>
 static hipError_t W_build_t(const SysDev& s, const WalkDev& w, const T* Uph, hipStream_t st) {
   const long rowst = (long)s.N * s.Lp, n = s.nu;
+  if (s.nk == 0 && s.nu == s.nd && s.nu % 16 == 0 && s.nu >= 16 && s.nu <= 80 && s.Lp % 32 == 0)
+    return launch_wgem<T>(s, w, st);
   GemmArgs g = plain(s.nu, s.nd, s.Lp);
   g.A = (const T*)w.P; g.lda = s.Lp; g.a_bs = rowst;
   g.B = (const T*)w.phi + (long)s.nu * s.Lp; g.ldb = s.Lp; g.b_bs = rowst;
@@ -434,9 +529,117 @@ hipError_t launch_W_build(const SysDev& s, const WalkDev& w, hipStream_t st) {
 // FP64 arithmetic: A is FP64 and P (FP64 or FP32 storage) is promoted exactly.
 // With unpaired orbitals the up electrons' vectors also collect the unpaired
 // columns: Yt_up[i] += sum_l A[n_dn + l][i] U[:, l].
+// Both spins' cofactor products of one walker per set of workgroups, for
+// n_up = n_dn = n = 16 RB <= 96, Lp a multiple of 32 and no unpaired orbitals:
+//   Yt_up[i][mu] = sum_j A[j][i] P_dn[j][mu],  Yt_dn[j][mu] = sum_i A[j][i] P_up[i][mu].
+// The product is bound by its HBM traffic (P in, Yt out: 16 n Lp bytes per
+// spin and walker) as much as by the FP64 matrix rate (K = n is short), and
+// the generic tiled kernel spends most of its time staging K through LDS in
+// short steps with M = n rounded up to 32-row tiles.  Here a workgroup owns 64
+// columns of one spin of one walker: the n x 64 slab of P goes to LDS once, and
+// wave rb computes output rows 16 rb .. 16 rb + 15 for the 64 columns as four
+// 16 x 16 blocks, taking its A fragments straight from global memory (the
+// walker's A is read by all its slabs from L2).  Products accumulate in k order
+// in steps of 4 with the same MFMA instruction as the generic kernel, so Yt is
+// bitwise the same.
+template <typename T, int RB>
+__global__ void __launch_bounds__(64 * RB) yt_kernel(const double* __restrict__ Ag, const T* __restrict__ Pg,
+                                                     double* __restrict__ Yg, int n, int N, int Lp, int nslab) {
+  extern __shared__ double Ps[];   // [n][64]
+  // the slabs of one walker on one XCD (they share its A in that L2)
+  const long b = xcd_remap(blockIdx.x, gridDim.x);
+  const int slab = (int)(b % nslab);
+  const int spin = (int)((b / nslab) & 1);   // 0: up rows of Yt (from P_dn), 1: down rows (from P_up)
+  const long wk = b / nslab / 2;
+  const int c0 = slab * 64;
+  const int cw = min(64, Lp - c0);           // columns in this slab: 64, or 32 in the last one
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const double* A = Ag + wk * (long)n * n;
+  const T* P = Pg + (wk * N + (spin == 0 ? n : 0)) * (long)Lp + c0;
+  double* Y = Yg + (wk * N + (spin == 0 ? 0 : n)) * (long)Lp + c0;
+  // this wave's A fragments for every K step, requested first (n is a multiple
+  // of 16: no row or k past n).  op(A)[row][k] is A^T for the up rows (A[k][row])
+  // and A for the down rows (A[row][k]); each step's loads take a uniform base
+  // and one lane offset
+  const int row = wave * 16 + (lane & 15), g = lane >> 4;
+  const int tstride = spin == 0 ? 4 * n : 4;
+  const int loff = spin == 0 ? g * n + row : row * n + g;
+  constexpr int KS = 24;   // K steps of 4 for n <= 96
+  double af[KS];
+#pragma unroll
+  for (int t = 0; t < KS; ++t)
+    if (4 * t < n) af[t] = (A + (long)t * tstride)[loff];
+  // the slab of P, two columns per load, all eight loads of a thread in
+  // flight together (n x 32 pairs over 64 RB = 4 n threads; FP32 storage
+  // promotes exactly)
+  const int h = cw / 2;   // pairs of columns per row
+  double2 pv[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int idx = tid + 64 * RB * q, k = idx >> 5, cp = idx & 31;
+    pv[q] = double2{};
+    if (cp < h) {
+      if constexpr (sizeof(T) == 8) {
+        pv[q] = *(const double2*)(P + (long)k * Lp + 2 * cp);
+      } else {
+        const float2 v = *(const float2*)(P + (long)k * Lp + 2 * cp);
+        pv[q] = double2{(double)v.x, (double)v.y};
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) *(double2*)(Ps + 2 * (tid + 64 * RB * q)) = pv[q];
+  __syncthreads();
+  dx4 acc[4];
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[cb][r] = 0.0;
+#pragma unroll
+  for (int t = 0; t < KS; ++t) {
+    if (4 * t < n) {
+      const double* pr = Ps + (4 * t + g) * 64 + (lane & 15);
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[t], pr[16 * cb], acc[cb], 0, 0, 0);
+    }
+  }
+  // 16 x 16 block layout: lane holds column lane % 16 and rows 4 r + lane / 16
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) {
+    const int c = cb * 16 + (lane & 15);
+    if (c < cw) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Y[(long)(wave * 16 + 4 * r + g) * Lp + c] = acc[cb][r];
+    }
+  }
+}
+
+template <typename T>
+static hipError_t launch_yt(const SysDev& s, const WalkDev& w, hipStream_t st) {
+  const int n = s.nu, nslab = (s.Lp + 63) / 64;
+  const long total = (long)w.Wk * 2 * nslab;
+  if (total > 0x7fffffffL) return hipErrorInvalidValue;
+  const size_t lds = sizeof(double) * (size_t)n * 64;
+#define QMC_YT(R)                                                                                         \
+  hipLaunchKernelGGL((yt_kernel<T, R>), dim3((unsigned)total), dim3(64 * R), lds, st, w.A, (const T*)w.P, w.Yt, n, \
+                     s.N, s.Lp, nslab)
+  switch (n / 16) {
+    case 1: QMC_YT(1); break;
+    case 2: QMC_YT(2); break;
+    case 3: QMC_YT(3); break;
+    case 4: QMC_YT(4); break;
+    case 5: QMC_YT(5); break;
+    default: QMC_YT(6); break;
+  }
+#undef QMC_YT
+  return hipGetLastError();
+}
+
 template <typename T>
 static hipError_t Y_build_t(const SysDev& s, const WalkDev& w, const T* Uph, hipStream_t st) {
   const long rowst = (long)s.N * s.Lp, n = s.nu;
+  if (s.nk == 0 && s.nu == s.nd && s.nu % 16 == 0 && s.nu >= 16 && s.nu <= 96 && s.Lp % 32 == 0)
+    return launch_yt<T>(s, w, st);
   hipError_t e;
   {
     GemmArgs g = plain(s.nu, s.Lp, s.nd);
