@@ -30,7 +30,8 @@ namespace qmc {
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
-constexpr int kOzMaxKSteps = 256;   // K <= 8192
+constexpr int kOzMaxKSteps = 256;   // K <= 8192 (one K step per thread of a workgroup)
+constexpr int kNoRow = -2147483647 - 1;   // exponent of a row or column with no output
 
 // ---------------------------------------------------------------------------
 // digits
@@ -167,11 +168,16 @@ __device__ __forceinline__ long oz_xcd_remap(long id, long total) {
 // into LDS (global_load_lds, no register staging) through a ring of three
 // stages, and each wave reads its fragments one step ahead into a second set of
 // registers, so that LDS reads, copies and products of neighbouring steps
-// overlap.  Every wave issues the same number of copies per step (slots past
-// the last block copy into `spare`, steps past the end repeat the last one), so
+// overlap; within a step the copies and fragment reads are spread between the
+// products (scheduling groups), so that neither queue holds the matrix core
+// back.  Every wave issues the same number of copies per step (slots past the
+// last block copy into `spare`, steps past the end repeat the last one), so
 // the count of copies in flight is the same on every path and a fixed vmcnt
 // tells when a step has landed.  Rows past M or N read the last tile group
-// (their products land in outputs that are not stored).
+// (their products land in outputs that are not stored).  The exponents and
+// output offsets of the tile's rows and columns are loaded once, ahead of the
+// first copies, and kept in LDS for the epilogue, which then needs no global
+// load and no division per output.
 template <int S>
 __global__ void __launch_bounds__(256) ozaki_gemm_kernel(OzArgs g, int gx, int gy) {
   constexpr int NA = S * 4, NB = S * 2;          // fragment blocks per stage: A (4 row groups), B (2)
@@ -185,7 +191,9 @@ __global__ void __launch_bounds__(256) ozaki_gemm_kernel(OzArgs g, int gx, int g
   __shared__ __attribute__((aligned(16))) int8_t st2[NBLK][1024];
   __shared__ __attribute__((aligned(16))) int8_t spare[1024];
   __shared__ short steps[kOzMaxKSteps];          // K steps with a nonzero B^T tile, in order
-  __shared__ int nsteps;
+  __shared__ int nsteps, wcnt[4];
+  __shared__ long rows_c[128], rows_t[128];      // offsets of the tile's output rows in C and CT
+  __shared__ int rows_e[128], cols_e[64];        // exponents of its rows and columns (kNoRow: no output)
   // with a row list, only its tiles are spread over the XCDs (the grid is
   // sized for every row; the workgroups past the list's tiles leave at once)
   const int Mr = g.ridx ? min(g.M, *g.rcnt) : g.M;   // rows with an output
@@ -199,23 +207,23 @@ __global__ void __launch_bounds__(256) ozaki_gemm_kernel(OzArgs g, int gx, int g
   const int J = g.Kp / 32;
   const int GA = (g.M + 31) / 32, GB = (g.N + 31) / 32;
 
-  // step list, before any copy is in flight
-  for (int t = tid; t < J; t += 256) {
-    bool nz = true;
-    if (g.kmask) {
+  // step list, before any copy is in flight: thread t < J flags K step t,
+  // the flagged steps are compacted in order by wave ballots (J <= 256)
+  {
+    bool nz = tid < J;
+    if (nz && g.kmask) {
       const int nt = n0 / kLamTileN;
-      nz = g.kmask[(long)(2 * t) * g.kmask_ld + nt] || g.kmask[(long)(2 * t + 1) * g.kmask_ld + nt];
+      nz = g.kmask[(long)(2 * tid) * g.kmask_ld + nt] || g.kmask[(long)(2 * tid + 1) * g.kmask_ld + nt];
     }
-    steps[t] = nz ? 1 : 0;
+    const unsigned long long bal = __ballot(nz);
+    if (lane == 0) wcnt[wave] = __popcll(bal);
+    __syncthreads();
+    int pos = __popcll(bal & ((1ull << lane) - 1ull));
+    for (int k = 0; k < wave; ++k) pos += wcnt[k];
+    if (nz) steps[pos] = (short)tid;
+    if (tid == 0) nsteps = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+    __syncthreads();
   }
-  __syncthreads();
-  if (tid == 0) {
-    int c = 0;
-    for (int t = 0; t < J; ++t)
-      if (steps[t]) steps[c++] = (short)t;
-    nsteps = c;
-  }
-  __syncthreads();
   const int ns = nsteps;
 
   // this wave's PW slots: tile base of lane l's 16 bytes at K step 0, and the
@@ -236,8 +244,7 @@ __global__ void __launch_bounds__(256) ozaki_gemm_kernel(OzArgs g, int gx, int g
       src[j] = g.B + 16 * lane;   // any valid address: the copy lands in `spare`
     }
   }
-  auto issue = [&](int t, int8_t (&buf)[NBLK][1024]) {
-    const long k = ns > 0 ? 1024L * steps[min(t, ns - 1)] : 0;
+  auto issue_k = [&](long k, int8_t (&buf)[NBLK][1024]) {
 #pragma unroll
     for (int j = 0; j < PW; ++j) {
       int8_t* d = dst[j] >= 0 ? &buf[dst[j]][0] : &spare[0];
@@ -245,6 +252,7 @@ __global__ void __launch_bounds__(256) ozaki_gemm_kernel(OzArgs g, int gx, int g
                                        (__attribute__((address_space(3))) void*)d, 16, 0, 0);
     }
   };
+  auto koff = [&](int t) -> long { return ns > 0 ? 1024L * steps[min(t, ns - 1)] : 0; };
   v16i acc[S][2];
 #pragma unroll
   for (int q = 0; q < S; ++q)
@@ -279,19 +287,55 @@ __global__ void __launch_bounds__(256) ozaki_gemm_kernel(OzArgs g, int gx, int g
         for (int c = 0; c < 2; ++c)
           acc[a + b][c] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a], fb[b][c], acc[a + b][c], 0, 0, 0);
   };
+  // (past the last step the fragment reads fetch a repeated stage; unused)
   auto step = [&](int t, int8_t (&cur)[NBLK][1024], int8_t (&nx1)[NBLK][1024], const v4i (&fa)[S],
                   const v4i (&fb)[S][2], v4i (&na)[S], v4i (&nb)[S][2]) {
+    const long k3 = koff(t + 3);
     __builtin_amdgcn_s_waitcnt(0x0070 | PW);   // vmcnt(PW), lgkmcnt(0); expcnt: no wait
     __builtin_amdgcn_s_barrier();
-    issue(t + 3, cur);
-    if (t + 1 < ns) frags(nx1, na, nb);
+    issue_k(k3, cur);
+    frags(nx1, na, nb);
     mma(fa, fb);
+    // order within the step: each copy, then each fragment read, followed by
+    // one product; the remaining products last
+    constexpr int NR = 3 * S, NM = S * (S + 1);
+    static_assert(NM >= NR + PW, "fewer products than memory operations to spread");
+#pragma unroll
+    for (int i = 0; i < PW; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x0020, 1, 0);   // one VMEM read (the copy)
+      __builtin_amdgcn_sched_group_barrier(0x0008, 1, 0);   // one MFMA
+    }
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x0100, 1, 0);   // one DS read
+      __builtin_amdgcn_sched_group_barrier(0x0008, 1, 0);
+    }
+    __builtin_amdgcn_sched_group_barrier(0x0008, NM - NR - PW, 0);
   };
-  issue(0, st0);
-  issue(1, st1);
-  issue(2, st2);
+  // the exponents and row indices of the tile's rows (threads 0..127) and
+  // columns (128..191), loaded before the first copies: they complete before
+  // those, so the copy counts below still hold
+  int ld_e = kNoRow, ld_r = 0;
+  if (tid < 128) {
+    const int gm = m0 + tid;
+    if (gm < Mr) { ld_e = g.ea[gm]; ld_r = g.ridx ? g.ridx[gm] : gm; }
+  } else if (tid < 192) {
+    const int gn = n0 + tid - 128;
+    if (gn < g.N) ld_e = g.eb[gn];
+  }
+  issue_k(koff(0), st0);
+  issue_k(koff(1), st1);
+  issue_k(koff(2), st2);
   __builtin_amdgcn_s_waitcnt(0x0F70 | (2 * PW));   // vmcnt(2 PW): step 0 landed
   __builtin_amdgcn_s_barrier();
+  if (tid < 128) {   // row r of C sits at (r / grp) gs + (r % grp) ldc, of CT at (r / grp) ct_gs + r % grp
+    rows_e[tid] = ld_e;
+    const long q = ld_r / g.c_grp, rm = ld_r - q * g.c_grp;
+    rows_c[tid] = q * g.c_gs + rm * g.ldc;
+    rows_t[tid] = q * g.ct_gs + rm;
+  } else if (tid < 192) {
+    cols_e[tid - 128] = ld_e;
+  }
   frags(st0, fa0, fb0);
   for (int t = 0; t < ns; t += 6) {
     step(t, st0, st1, fa0, fb0, fa1, fb1);
@@ -302,29 +346,32 @@ __global__ void __launch_bounds__(256) ozaki_gemm_kernel(OzArgs g, int gx, int g
     if (t + 5 < ns) step(t + 5, st2, st0, fa1, fb1, fa0, fb0);
   }
   __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): no copy outlives the workgroup
+  __syncthreads();   // the row and column data are visible (also when no K step ran)
   // 32 x 32 accumulator layout: lane holds column lane % 32 and, in register
   // r, row 8 (r / 4) + 4 (lane / 32) + r % 4
+  const bool full = m0 + 128 <= Mr && n0 + 64 <= g.N;
+  int en[2];
 #pragma unroll
-  for (int c = 0; c < 2; ++c) {
-    const int gn = n0 + 32 * c + (lane & 31);
-    if (gn >= g.N) continue;
-    const int en = g.eb[gn];
+  for (int c = 0; c < 2; ++c) en[c] = cols_e[32 * c + (lane & 31)];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int gm = m0 + wave * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-      if (gm < Mr) {
+  for (int r = 0; r < 16; ++r) {
+    const int lr = wave * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+    const int er = rows_e[lr];
+    const long oc = rows_c[lr], ot = rows_t[lr];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int gn = n0 + 32 * c + (lane & 31);
+      if (full || (er != kNoRow && gn < g.N)) {
         double v = 0.0;
 #pragma unroll
         for (int q = S - 1; q >= 0; --q) v = v * (1.0 / 128.0) + (double)acc[q][c][r];
-        v = ldexp(v, g.ea[gm] + en - 10);
-        const int gr = g.ridx ? g.ridx[gm] : gm;   // the row of C
-        const long off = (long)(gr / g.c_grp) * g.c_gs + (long)(gr % g.c_grp) * g.ldc + gn;
-        g.C[off] = v;
+        v = ldexp(v, er + en[c] - 10);
+        g.C[oc + gn] = v;
         if (g.C2) {
-          if (g.c2_bf16) ((bf16s*)g.C2)[off] = bf16s(v);
-          else ((float*)g.C2)[off] = (float)v;
+          if (g.c2_bf16) ((bf16s*)g.C2)[oc + gn] = bf16s(v);
+          else ((float*)g.C2)[oc + gn] = (float)v;
         }
-        if (g.CT) g.CT[(long)(gr / g.c_grp) * g.ct_gs + (long)gn * g.ct_ld + (gr % g.c_grp)] = v;
+        if (g.CT) g.CT[ot + (long)gn * g.ct_ld] = v;
       }
     }
   }
