@@ -454,8 +454,10 @@ qmc_status qmc_sr_step_static(int32_t n_samples, int64_t n_params, const double 
  * refresh) is one persistent launch over (system, walker[, row chunk]) work
  * items ordered by decreasing cost; each member evolves exactly as it would
  * with qmc_vmc_steps alone given the same random numbers.  Members must have
- * the same precision and n_up == n_dn <= 128; at most 32 members.  The handles
- * stay owned by the caller and must outlive the group. */
+ * the same precision and n_up <= 128 (unpaired orbitals, a Jastrow basis and
+ * contracted orbitals are allowed); Pfaffian and QMC_REFINED members are
+ * refused (QMC_ERR_UNSUPPORTED); at most 32 members.  The handles stay owned
+ * by the caller and must outlive the group. */
 typedef struct qmc_multi qmc_multi;
 qmc_status qmc_multi_create(int32_t n_members, qmc_system *const *systems, qmc_walkers *const *walkers,
                             qmc_multi **out);

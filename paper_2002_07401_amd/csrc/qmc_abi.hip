@@ -1492,9 +1492,9 @@ extern "C" qmc_status qmc_multi_create(int32_t n_members, qmc_system* const* sys
     if (check_pair(systems[k], walkers[k])) { delete m; return QMC_ERR_ARG; }
     const SysDev& s = systems[k]->d;
     if (s.precision != systems[0]->d.precision) { delete m; return fail(QMC_ERR_ARG, "members differ in precision"); }
-    if (s.nu != s.nd || s.nu > kLuMaxN) { delete m; return fail(QMC_ERR_UNSUPPORTED, "members need n_up == n_dn <= 128"); }
-    if (s.LJ > 0) { delete m; return fail(QMC_ERR_UNSUPPORTED, "members with a Jastrow basis are not built"); }
-    if (s.Lq > 0) { delete m; return fail(QMC_ERR_UNSUPPORTED, "members with contracted orbitals are not built"); }
+    // unpaired orbitals, a Jastrow basis and contracted orbitals run in the
+    // per-item bodies every member shares with the one-system kernels
+    if (s.nu > kLuMaxN) { delete m; return fail(QMC_ERR_UNSUPPORTED, "members need n_up <= 128"); }
     if (s.pairing) { delete m; return fail(QMC_ERR_UNSUPPORTED, "Pfaffian members are not built"); }
     if (s.screened()) { delete m; return fail(QMC_ERR_UNSUPPORTED, "QMC_REFINED members are not built"); }
     m->sys.push_back(systems[k]);

@@ -151,10 +151,6 @@ def test_jas3_forces_match_oracle(jw):
 
 def test_jas3_refusals(jw):
     P = need_gpu()
-    sysh, wk, r, _ = _eval(P, jw.system, jw.r0, 4)
-    with pytest.raises(P.QMCError) as ex:
-        P.MultiSystem([wk])
-    assert ex.value.code == -5
     s = jw.system
     bad = s.j3.copy()
     bad[0, 0, 1] += 1.0
