@@ -241,39 +241,52 @@ __global__ void __launch_bounds__(256) propose_screened_blk_kernel(SysDev s, Wal
 
 // Column maxima of the P halves (bit 0: up rows, bit 1: down rows):
 // cmax[w][h][mu] = max over the rows i of half h of |P[w][i][mu]|.
-// One workgroup per (walker, half), columns in chunks of 512: wave v takes the
-// rows v, v + 4, ..., each lane the columns lane + 64 c of the chunk (all
-// eight loaded per row together), and the four waves' maxima meet in LDS (a
-// maximum does not depend on the order).
+// One workgroup per (walker, half), columns in passes of 128 CC: each lane
+// takes the column pairs 2 lane + 128 c (16-byte loads), wave v the rows v,
+// v + 4, ..., four rows at a time (4 CC independent loads in flight per
+// lane), and the four waves' maxima meet in LDS (a maximum does not depend on
+// the order, so any split gives the same values).
+template <int CC>
 __global__ void __launch_bounds__(256) screen_colmax_kernel(SysDev s, WalkDev w, int halves) {
-  constexpr int CM = 8;
-  __shared__ double part[4][64 * CM];
+  __shared__ double part[4][128 * CC];
   const int wk = blockIdx.x, h = blockIdx.y;
   if (!((halves >> h) & 1)) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int i0 = h == 0 ? 0 : s.nu, n = h == 0 ? s.nu : s.nd, Lp = s.Lp;
+  const int i0 = h == 0 ? 0 : s.nu, n = h == 0 ? s.nu : s.nd, Lp = s.Lp;   // Lp even
   const double* P = (const double*)w.P + ((long)wk * s.N + i0) * Lp;
   double* out = w.cmax + ((long)wk * 2 + h) * Lp;
-  for (int c0 = 0; c0 < Lp; c0 += 64 * CM) {
-    double m[CM];
+  for (int c0 = 0; c0 < Lp; c0 += 128 * CC) {
+    double2 m[CC];
 #pragma unroll
-    for (int c = 0; c < CM; ++c) m[c] = 0.0;
-    for (int i = wave; i < n; i += 4) {
-      const double* row = P + (long)i * Lp + c0;
-      double v[CM];
+    for (int c = 0; c < CC; ++c) m[c] = double2{0.0, 0.0};
+    for (int i = wave; i < n; i += 16) {
+      double2 v[4][CC];
 #pragma unroll
-      for (int c = 0; c < CM; ++c) {
-        const int mu = lane + 64 * c;
-        v[c] = c0 + mu < Lp ? __builtin_nontemporal_load(row + mu) : 0.0;
+      for (int u = 0; u < 4; ++u) {
+        const bool ok = i + 4 * u < n;
+        const double* row = P + (long)(i + 4 * u) * Lp + c0;
+#pragma unroll
+        for (int c = 0; c < CC; ++c) {
+          const int mu = 2 * lane + 128 * c;
+          v[u][c] = ok && c0 + mu < Lp ? load16_nt<double2>(row + mu) : double2{0.0, 0.0};
+        }
       }
 #pragma unroll
-      for (int c = 0; c < CM; ++c) m[c] = fmax(m[c], fabs(v[c]));
-    }
-    __syncthreads();   // the previous chunk's maxima are written out
+      for (int u = 0; u < 4; ++u)
 #pragma unroll
-    for (int c = 0; c < CM; ++c) part[wave][lane + 64 * c] = m[c];
+        for (int c = 0; c < CC; ++c) {
+          m[c].x = fmax(m[c].x, fabs(v[u][c].x));
+          m[c].y = fmax(m[c].y, fabs(v[u][c].y));
+        }
+    }
+    __syncthreads();   // the previous pass's maxima are written out
+#pragma unroll
+    for (int c = 0; c < CC; ++c) {
+      part[wave][2 * lane + 128 * c] = m[c].x;
+      part[wave][2 * lane + 128 * c + 1] = m[c].y;
+    }
     __syncthreads();
-    for (int mu = tid; mu < 64 * CM && c0 + mu < Lp; mu += blockDim.x)
+    for (int mu = tid; mu < 128 * CC && c0 + mu < Lp; mu += blockDim.x)
       out[c0 + mu] = fmax(fmax(part[0][mu], part[1][mu]), fmax(part[2][mu], part[3][mu]));
   }
 }
@@ -291,7 +304,18 @@ hipError_t launch_export_kept(const WalkDev& w, double* dst, hipStream_t st) {
 
 hipError_t launch_screen_colmax(const SysDev& s, const WalkDev& w, int halves, hipStream_t st) {
   if (!w.cmax) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(screen_colmax_kernel, dim3(w.Wk, 2), dim3(256), 0, st, s, w, halves);
+  if (s.Lp % 2) return hipErrorInvalidValue;
+  const dim3 grid(w.Wk, 2), blk(256);
+  switch (std::min(8, (s.Lp + 127) / 128)) {
+    case 1: hipLaunchKernelGGL(screen_colmax_kernel<1>, grid, blk, 0, st, s, w, halves); break;
+    case 2: hipLaunchKernelGGL(screen_colmax_kernel<2>, grid, blk, 0, st, s, w, halves); break;
+    case 3: hipLaunchKernelGGL(screen_colmax_kernel<3>, grid, blk, 0, st, s, w, halves); break;
+    case 4: hipLaunchKernelGGL(screen_colmax_kernel<4>, grid, blk, 0, st, s, w, halves); break;
+    case 5: hipLaunchKernelGGL(screen_colmax_kernel<5>, grid, blk, 0, st, s, w, halves); break;
+    case 6: hipLaunchKernelGGL(screen_colmax_kernel<6>, grid, blk, 0, st, s, w, halves); break;
+    case 7: hipLaunchKernelGGL(screen_colmax_kernel<7>, grid, blk, 0, st, s, w, halves); break;
+    default: hipLaunchKernelGGL(screen_colmax_kernel<8>, grid, blk, 0, st, s, w, halves); break;
+  }
   return hipGetLastError();
 }
 

@@ -197,69 +197,29 @@ __global__ void __launch_bounds__(256) ozaki_gemm_kernel(OzArgs g, int gx, int g
   // with a row list, only its tiles are spread over the XCDs (the grid is
   // sized for every row; the workgroups past the list's tiles leave at once)
   const int Mr = g.ridx ? min(g.M, *g.rcnt) : g.M;   // rows with an output
-  const long nt = g.ridx ? (long)((Mr + 127) / 128) * gx : (long)gridDim.x;
+  const long nt = g.ridx ? (long)((Mr + 127) / 128) * gx : (long)gx * gy;
   if ((long)blockIdx.x >= nt) return;                  // (uniform, before any copy or barrier)
-  const long Lb = oz_xcd_remap(blockIdx.x, nt);
-  const int bx = (int)(Lb % gx);
-  const int by = (int)((Lb / gx) % gy);
-  const int m0 = by * 128, n0 = bx * 64;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int J = g.Kp / 32;
   const int GA = (g.M + 31) / 32, GB = (g.N + 31) / 32;
-
-  // step list, before any copy is in flight: thread t < J flags K step t,
-  // the flagged steps are compacted in order by wave ballots (J <= 256)
-  {
-    bool nz = tid < J;
-    if (nz && g.kmask) {
-      const int nt = n0 / kLamTileN;
-      nz = g.kmask[(long)(2 * tid) * g.kmask_ld + nt] || g.kmask[(long)(2 * tid + 1) * g.kmask_ld + nt];
-    }
-    const unsigned long long bal = __ballot(nz);
-    if (lane == 0) wcnt[wave] = __popcll(bal);
-    __syncthreads();
-    int pos = __popcll(bal & ((1ull << lane) - 1ull));
-    for (int k = 0; k < wave; ++k) pos += wcnt[k];
-    if (nz) steps[pos] = (short)tid;
-    if (tid == 0) nsteps = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
-    __syncthreads();
-  }
-  const int ns = nsteps;
-
-  // this wave's PW slots: tile base of lane l's 16 bytes at K step 0, and the
-  // block of the stage they fill (-1: the spare block)
+  int m0 = 0, n0 = 0, ns = J;
+  // per copy slot: the tile's base address (uniform over the wave: scalar
+  // registers) and the stage block it fills (-1: the spare block)
+  const int wvs = __builtin_amdgcn_readfirstlane(wave);
   const int8_t* src[PW];
   int dst[PW];
-#pragma unroll
-  for (int j = 0; j < PW; ++j) {
-    const int b = wave * PW + j;
-    dst[j] = b < NBLK ? b : -1;
-    if (b < NA) {
-      const int q = b / 4, grp = min(m0 / 32 + b % 4, GA - 1);
-      src[j] = g.A + (long)q * g.a_plane + (long)grp * J * 1024 + 16 * lane;
-    } else if (b < NBLK) {
-      const int q = (b - NA) / 2, grp = min(n0 / 32 + (b - NA) % 2, GB - 1);
-      src[j] = g.B + (long)q * g.b_plane + (long)grp * J * 1024 + 16 * lane;
-    } else {
-      src[j] = g.B + 16 * lane;   // any valid address: the copy lands in `spare`
-    }
-  }
+  int ld_e = kNoRow, ld_r = 0;
+  // K offset of step t (the step list's entries; past the end the last one)
+  auto koff = [&](int t) -> long { return ns > 0 ? 1024L * steps[min(t, ns - 1)] : 0; };
   auto issue_k = [&](long k, int8_t (&buf)[NBLK][1024]) {
 #pragma unroll
     for (int j = 0; j < PW; ++j) {
       int8_t* d = dst[j] >= 0 ? &buf[dst[j]][0] : &spare[0];
-      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(src[j] + k),
+      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(src[j] + (k + 16 * lane)),
                                        (__attribute__((address_space(3))) void*)d, 16, 0, 0);
     }
   };
-  auto koff = [&](int t) -> long { return ns > 0 ? 1024L * steps[min(t, ns - 1)] : 0; };
   v16i acc[S][2];
-#pragma unroll
-  for (int q = 0; q < S; ++q)
-#pragma unroll
-    for (int c = 0; c < 2; ++c)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) acc[q][c][r] = 0;
 
   // Fragments of step t sit in registers (set 0 / set 1 by parity) while step
   // t + 1's are read from LDS, and the copies of steps t + 2 and t + 3 are in
@@ -312,10 +272,79 @@ __global__ void __launch_bounds__(256) ozaki_gemm_kernel(OzArgs g, int gx, int g
     }
     __builtin_amdgcn_sched_group_barrier(0x0008, NM - NR - PW, 0);
   };
-  // the exponents and row indices of the tile's rows (threads 0..127) and
-  // columns (128..191), loaded before the first copies: they complete before
-  // those, so the copy counts below still hold
-  int ld_e = kNoRow, ld_r = 0;
+  // The epilogue.  32 x 32 accumulator layout: lane holds column lane % 32
+  // and, in register r, row 8 (r / 4) + 4 (lane / 32) + r % 4.
+  auto epilogue = [&]() {
+    const bool full = m0 + 128 <= Mr && n0 + 64 <= g.N;
+    int en[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) en[c] = cols_e[32 * c + (lane & 31)];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int lr = wave * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      const int er = rows_e[lr];
+      const long oc = rows_c[lr], ot = rows_t[lr];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const int gn = n0 + 32 * c + (lane & 31);
+        if (full || (er != kNoRow && gn < g.N)) {
+          double v = 0.0;
+#pragma unroll
+          for (int q = S - 1; q >= 0; --q) v = v * (1.0 / 128.0) + (double)acc[q][c][r];
+          v = ldexp(v, er + en[c] - 10);
+          g.C[oc + gn] = v;
+          if (g.C2) {
+            if (g.c2_bf16) ((bf16s*)g.C2)[oc + gn] = bf16s(v);
+            else ((float*)g.C2)[oc + gn] = (float)v;
+          }
+          if (g.CT) g.CT[ot + (long)gn * g.ct_ld] = v;
+        }
+      }
+    }
+  };
+
+  // the tile's place, its step list, the copy sources of this wave's PW
+  // slots (lane l copies the 16 bytes at 16 l of a block), the exponents and
+  // row indices of its rows (threads 0..127) and columns (128..191), then the
+  // copies of its first three steps.  The exponent loads go out before the
+  // copies: they complete first, so the copy counts of the main loop hold.
+  {
+    const long Lb = oz_xcd_remap(blockIdx.x, nt);
+    m0 = (int)((Lb / gx) % gy) * 128;
+    n0 = (int)(Lb % gx) * 64;
+  }
+  {
+    // thread t < J flags K step t (a nonzero B^T tile); the flagged steps are
+    // compacted in order by wave ballots (J <= 256)
+    bool nz = tid < J;
+    if (nz && g.kmask) {
+      const int nb = n0 / kLamTileN;
+      nz = g.kmask[(long)(2 * tid) * g.kmask_ld + nb] || g.kmask[(long)(2 * tid + 1) * g.kmask_ld + nb];
+    }
+    const unsigned long long bal = __ballot(nz);
+    if (lane == 0) wcnt[wave] = __popcll(bal);
+    __syncthreads();
+    int pos = __popcll(bal & ((1ull << lane) - 1ull));
+    for (int k = 0; k < wave; ++k) pos += wcnt[k];
+    if (nz) steps[pos] = (short)tid;
+    if (tid == 0) nsteps = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+    __syncthreads();
+    ns = nsteps;
+  }
+#pragma unroll
+  for (int j = 0; j < PW; ++j) {
+    const int b = wvs * PW + j;
+    dst[j] = b < NBLK ? b : -1;
+    if (b < NA) {
+      const int q = b / 4, grp = min(m0 / 32 + b % 4, GA - 1);
+      src[j] = g.A + (long)q * g.a_plane + (long)grp * J * 1024;
+    } else if (b < NBLK) {
+      const int q = (b - NA) / 2, grp = min(n0 / 32 + (b - NA) % 2, GB - 1);
+      src[j] = g.B + (long)q * g.b_plane + (long)grp * J * 1024;
+    } else {
+      src[j] = g.B;   // any valid address: the copy lands in `spare`
+    }
+  }
   if (tid < 128) {
     const int gm = m0 + tid;
     if (gm < Mr) { ld_e = g.ea[gm]; ld_r = g.ridx ? g.ridx[gm] : gm; }
@@ -336,6 +365,12 @@ __global__ void __launch_bounds__(256) ozaki_gemm_kernel(OzArgs g, int gx, int g
   } else if (tid < 192) {
     cols_e[tid - 128] = ld_e;
   }
+#pragma unroll
+  for (int q = 0; q < S; ++q)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[q][c][r] = 0;
   frags(st0, fa0, fb0);
   for (int t = 0; t < ns; t += 6) {
     step(t, st0, st1, fa0, fb0, fa1, fb1);
@@ -346,35 +381,8 @@ __global__ void __launch_bounds__(256) ozaki_gemm_kernel(OzArgs g, int gx, int g
     if (t + 5 < ns) step(t + 5, st2, st0, fa1, fb1, fa0, fb0);
   }
   __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): no copy outlives the workgroup
-  __syncthreads();   // the row and column data are visible (also when no K step ran)
-  // 32 x 32 accumulator layout: lane holds column lane % 32 and, in register
-  // r, row 8 (r / 4) + 4 (lane / 32) + r % 4
-  const bool full = m0 + 128 <= Mr && n0 + 64 <= g.N;
-  int en[2];
-#pragma unroll
-  for (int c = 0; c < 2; ++c) en[c] = cols_e[32 * c + (lane & 31)];
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int lr = wave * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-    const int er = rows_e[lr];
-    const long oc = rows_c[lr], ot = rows_t[lr];
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      const int gn = n0 + 32 * c + (lane & 31);
-      if (full || (er != kNoRow && gn < g.N)) {
-        double v = 0.0;
-#pragma unroll
-        for (int q = S - 1; q >= 0; --q) v = v * (1.0 / 128.0) + (double)acc[q][c][r];
-        v = ldexp(v, er + en[c] - 10);
-        g.C[oc + gn] = v;
-        if (g.C2) {
-          if (g.c2_bf16) ((bf16s*)g.C2)[oc + gn] = bf16s(v);
-          else ((float*)g.C2)[oc + gn] = (float)v;
-        }
-        if (g.CT) g.CT[ot + (long)gn * g.ct_ld] = v;
-      }
-    }
-  }
+  __syncthreads();                       // the row and column data are visible (also when no K step ran)
+  epilogue();
 }
 
 template <int S>
@@ -384,7 +392,7 @@ static hipError_t run_ozaki(const OzArgs& g, hipStream_t st) {
   const int gx = (g.N + 63) / 64, gy = (g.M + 127) / 128;
   const long total = (long)gx * gy;
   if (total > 0x7fffffffL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(ozaki_gemm_kernel<S>, dim3((unsigned)total), dim3(256), 0, st, g, gx, gy);
+  hipLaunchKernelGGL((ozaki_gemm_kernel<S>), dim3((unsigned)total), dim3(256), 0, st, g, gx, gy);
   return hipGetLastError();
 }
 
