@@ -166,18 +166,32 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g, int gx, int gy) {
     __syncthreads();
     k0 = k1;
   }
-  // 16x16 block layout: lane holds column lane%16 and the rows given by Mfma::row
+  // 16x16 block layout: lane holds column lane%16 and the rows given by
+  // Mfma::row.  The output rows' offsets (their row-list entries loaded, the
+  // row index split into group and row) are formed for all of this lane's
+  // rows before any store: a load issued after a store of C would wait for it
+  // (the two may alias as far as the compiler knows).
+  long roff[FM][4];
+  bool rok[FM][4];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int gm = m0 + wm * WM + i * 16 + Mfma<TI>::row(lane, r);
+      rok[i][r] = gm < Mr;
+      const int gr = rok[i][r] ? (g.ridx ? g.ridx[gm] : gm) : 0;   // the row of C
+      const int q = gr / g.c_grp;
+      roff[i][r] = (long)q * g.c_gs + (long)(gr - q * g.c_grp) * g.ldc;
+    }
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int j = 0; j < FN; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int gm = m0 + wm * WM + i * 16 + Mfma<TI>::row(lane, r);
         const int gn = n0 + wn * WN + j * 16 + (lane & 15);
-        if (gm < Mr && gn < g.N) {
-          const int gr = g.ridx ? g.ridx[gm] : gm;   // the row of C
-          const long off = (long)(gr / g.c_grp) * g.c_gs + (long)(gr % g.c_grp) * g.ldc + gn;
+        if (rok[i][r] && gn < g.N) {
+          const long off = roff[i][r] + gn;
           TO* cp = C + off;
           if constexpr (sizeof(TO) == 2) {
             *cp = (TO)acc[i][j][r];   // BF16 output: never accumulated
