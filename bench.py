@@ -636,7 +636,9 @@ def large_leg(P, C, steps=128, Wk=256, fw=32, refined=False):
 def pfaffian_leg(P, C, steps=160, Wk=512):
     """The 80-electron Pfaffian (G~ 80 x 80, triplet blocks, L = 300), 512
     walkers, FP64: one evaluation and `steps` Metropolis moves (refresh every
-    32 moves); error of the evaluation against the oracle on one walker."""
+    32 moves); error of the evaluation against the oracle on one walker; the
+    adjoint's cost against an evaluation; and QMC_REFINED evaluations (B rows
+    from int8 digit products) against the FP64 ones, with their error."""
     from oracle import jagp as O
     dev = torch.device("cuda:0")
     w = C.pfaffian_20nuc_80e(n_walkers=Wk)
@@ -685,9 +687,40 @@ def pfaffian_leg(P, C, steps=160, Wk=512):
     f2.record()
     torch.cuda.synchronize()
     t_ev, t_fo = f0.elapsed_time(f1) / reps, f1.elapsed_time(f2) / reps
+    wk.set_timing(True)
+    wk.eval_batch(rf)
+    torch.cuda.synchronize()
+    b_fp64 = wk.timing()["P_build"][0]
+    wk.set_timing(False)
+    # QMC_REFINED: the B rows of the evaluation from the int8 digit products
+    # (G~, Pf, the inverse and the moves FP64), at the chain's final positions
+    sr = P.JAGPSystem(w.system, precision=P.QMC_REFINED)
+    wr = P.Walkers(sr, Wk, adjoint=False)
+    wr.eval_batch(rf)
+    torch.cuda.synchronize()
+    g0, g1 = (torch.cuda.Event(enable_timing=True) for _ in range(2))
+    g0.record()
+    for _ in range(reps):
+        outr = wr.eval_batch(rf)
+    g1.record()
+    torch.cuda.synchronize()
+    t_evr = g0.elapsed_time(g1) / reps
+    wr.set_timing(True)
+    wr.eval_batch(rf)
+    torch.cuda.synchronize()
+    b_ref = wr.timing()["P_build"][0]
+    wr.close()
+    sr.close()
+    refr = O.evaluate(O.from_workload_system(w.system), rf[:1].cpu())
+    errr = {k: float(f"{float(((outr[k].cpu()[:1] - refr[k]).abs() / refr[k].abs().clamp(min=1.0)).max()):.3e}")
+            for k in ("logabs", "e_loc")}
+    refined = {"mode": "QMC_REFINED", "eval_ms": round(t_evr, 3), "eval_over_fp64": round(t_ev / t_evr, 3),
+               "B_rows_ms": round(b_ref, 3), "B_rows_fp64_ms": round(b_fp64, 3),
+               "err_vs_oracle": {"walkers": [0], **errr}}
     wk.close()
     sysh.close()
     return {"workload": "pfaffian_20nuc_80e", "walkers": Wk, "precision": "fp64", "pfaffian_dim": n,
+            "refined": refined,
             "forces_ms": round(t_fo, 3), "eval_ms": round(t_ev, 3), "forces_over_eval": round(t_fo / t_ev, 2),
             "eloc_evals_per_s": round(Wk / t_eval, 1), "moves_per_s": round(steps * Wk / t_move, 1),
             "acceptance": round(cnt.sum().item() / (steps * Wk), 4), "moves": steps,

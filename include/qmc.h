@@ -89,9 +89,12 @@ typedef enum {
                       whose value at r' can change the determinant ratio:
                       those skipped contribute at most 1e-13 in total (bound
                       from the largest |P| of each column and the inverse
-                      column's 1-norm).  Not with unpaired orbitals, the
-                      Pfaffian or qmc_multi_*.  One more [Wk][L][N] FP64 array
-                      (P transposed).                                          */
+                      column's 1-norm).  Determinant systems with n_up ==
+                      n_dn; not with qmc_multi_*.  One more [Wk][L][N] FP64
+                      array (P transposed).  For a Pfaffian (pairing = 1) the
+                      evaluation's B rows phi(r_j)^T K^{s s_j} are the same
+                      error-free int8 digit products; G~, Pf, its inverse and
+                      the moves are those of the FP64 path.                    */
 } qmc_precision;
 
 typedef struct qmc_system qmc_system;   /* opaque: nuclei, basis, Lambda, Jastrow */
@@ -165,8 +168,8 @@ typedef struct {
    * matrix), A^{du} = -lambda^T, A^{uu} = pf_uu and A^{dd} = pf_dd
    * skew-symmetric; pf_k unpaired orbitals as fictitious electrons
    * (eq:pfodd): G~_{i, N+l} = phi(r_i) . U^{s_i}[:, l] with U^u = unpaired
-   * and U^d = pf_unpaired_dn.  N + pf_k must be even and at most 96; FP64
-   * precision only; n_up < n_dn is allowed.  Not supported with it:
+   * and U^d = pf_unpaired_dn.  N + pf_k must be even and at most 96;
+   * precision QMC_FP64 or QMC_REFINED; n_up < n_dn is allowed.  Not supported with it:
    * qmc_multi_*.  qmc_reweight uses G~ and its inverse;
    * qmc_system_set_params (lambda = A^{ud}) and qmc_system_set_pfaffian change
    * the coefficients. */

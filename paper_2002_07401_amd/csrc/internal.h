@@ -80,7 +80,10 @@ struct SysDev {
     return precision == QMC_W_FP32 || precision == QMC_MIXED || precision == QMC_MIXED_BF16;
   }
   // QMC_REFINED: FP64 storage, refined int8 products, screened proposals
-  __host__ __device__ bool screened() const { return precision == QMC_REFINED; }
+  // (determinant systems)
+  __host__ __device__ bool screened() const { return precision == QMC_REFINED && !pairing; }
+  // QMC_REFINED Pfaffian: the B rows from int8 digit products, FP64 otherwise
+  __host__ __device__ bool pf_refined() const { return precision == QMC_REFINED && pairing; }
   __host__ __device__ bool bf16() const { return precision == QMC_MIXED_BF16; }
   __host__ __device__ bool refined() const { return precision == QMC_MIXED || precision == QMC_MIXED_BF16; }
   // 0: FP64, 1: FP32, 2: BF16 storage
@@ -142,7 +145,8 @@ struct SysDev {
   // Pfaffian pairing (pairing = 1): G~ is npf x npf (npf = N + pk, pk
   // unpaired orbitals as fictitious electrons), G~_ij = psi(r_i) . B^{s_i}_j
   // with the rows B^s_j = psi(r_j)^T K^{s s_j}, K^{s s'} = (A^{s s'})^T; the
-  // walkers keep B^u in P and B^d in Bd.  FP64, npf <= kLuRowMax.
+  // walkers keep B^u in P and B^d in Bd.  FP64 (QMC_REFINED: the evaluation's
+  // B rows from int8 digit products), npf <= kLuRowMax.
   int pairing, npf, pk;
   double* Kuu;       // [Lp][Lp]  (A^{uu})^T
   double* Kud;       // [Lp][Lp]  (A^{ud})^T
@@ -153,10 +157,13 @@ struct SysDev {
   double* Kcat_d;    // [Lp][2Lp] [K^{ud} | K^{dd}]: the B rows of a moved down electron
   // int8 digits of Lambda for the error-free products (refined modes): tiles
   // [2][oz_s][Lp * Lp] (rows of Lambda^T, then rows of Lambda) and one exponent
-  // per row [2][Lp]
+  // per row [2][Lp]; for a QMC_REFINED Pfaffian the rows of the four K^T
+  // (uu, ud, du, dd): [4][oz_s][Lp * Lp] and [4][Lp], with an Lp x Lp FP64
+  // work array for the transposes
   int oz_s;
   int8_t* oz_lam;
   int* oz_elam;
+  double* oz_tmp;
 };
 
 // Device state of a batch of walkers.
@@ -540,6 +547,10 @@ hipError_t launch_slice_tiles(const double* X, long rows, int K, int Kp, int grp
                               int8_t* out, long plane, int* expo, hipStream_t st, bool have_expo = false,
                               const int* ridx = nullptr, const int* rcnt = nullptr, int* expo_c = nullptr);
 hipError_t launch_oz_lambda(const SysDev& s, hipStream_t st);
+// QMC_REFINED Pfaffian: digits of the rows of the four K^T, and the B rows
+// (P = B^u, Bd = B^d) of the evaluation from the walkers' FP64 basis rows
+hipError_t launch_oz_pf_K(const SysDev& s, hipStream_t st);
+hipError_t launch_pf_B_build_oz(const SysDev& s, const WalkDev& w, hipStream_t st);
 // dirty (QMC_REFINED, bit h for half h): build only the rows whose electron
 // has moved since its row was last built (the other rows of P, PT stand); every
 // half built records its positions for the next such build.

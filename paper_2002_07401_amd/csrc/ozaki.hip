@@ -567,4 +567,71 @@ hipError_t launch_P_build_oz(const SysDev& s, const WalkDev& w, int halves, cons
   return hipSuccess;
 }
 
+// ---------------------------------------------------------------------------
+// Pfaffian B rows (QMC_REFINED): B^s_j = psi(r_j)^T K^{s s_j} as the same
+// error-free digit products, B operand = the rows of K^T.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) oz_transpose_kernel(const double* __restrict__ K, double* __restrict__ T,
+                                                           int Lp) {
+  __shared__ double t[32][33];
+  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8 threads
+  for (int r = ty; r < 32; r += 8)
+    t[r][tx] = (by + r < Lp && bx + tx < Lp) ? K[(long)(by + r) * Lp + bx + tx] : 0.0;
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8)
+    if (bx + r < Lp && by + tx < Lp) T[(long)(bx + r) * Lp + by + tx] = t[tx][r];
+}
+
+hipError_t launch_oz_pf_K(const SysDev& s, hipStream_t st) {
+  if (!s.pf_refined() || !s.oz_lam || !s.oz_tmp) return hipErrorInvalidValue;
+  const long plane = oz_plane_bytes(s.Lp, s.Lp);
+  const double* K[4] = {s.Kuu, s.Kud, s.Kdu, s.Kdd};
+  const dim3 grid((s.Lp + 31) / 32, (s.Lp + 31) / 32);
+  for (int q = 0; q < 4; ++q) {
+    hipLaunchKernelGGL(oz_transpose_kernel, grid, dim3(256), 0, st, K[q], s.oz_tmp, s.Lp);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess)
+      e = launch_slice_tiles(s.oz_tmp, s.Lp, s.Lp, s.Lp, 1 << 30, 0, s.Lp, s.oz_s, s.oz_lam + (long)q * s.oz_s * plane,
+                             plane, s.oz_elam + (long)q * s.Lp, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_pf_B_build_oz(const SysDev& s, const WalkDev& w, hipStream_t st) {
+  if (!s.pf_refined() || !w.oz_phi || !w.oz_ephi) return hipErrorInvalidValue;
+  const long rowst = (long)s.N * s.Lp;
+  const long planeB = oz_plane_bytes(s.Lp, s.Lp);
+  const long up_bytes = (long)s.oz_s * oz_plane_bytes((long)w.Wk * s.nu, s.Lp);
+  const double* phi = (const double*)w.phi;   // FP64 rows in this mode
+  // digits of the up rows, then the down rows (rows m: walker m / n, electron m % n of the spin)
+  for (int h = 0; h < 2; ++h) {
+    const int n = h == 0 ? s.nu : s.nd;
+    if (n == 0) continue;
+    const long rows = (long)w.Wk * n;
+    hipError_t e = launch_slice_tiles(phi + (h == 0 ? 0 : (long)s.nu * s.Lp), rows, s.L, s.Lp, n, rowst, s.Lp,
+                                      s.oz_s, w.oz_phi + (h == 0 ? 0 : up_bytes), oz_plane_bytes(rows, s.Lp),
+                                      w.oz_ephi + (h == 0 ? 0 : (long)w.Wk * s.nu), st);
+    if (e != hipSuccess) return e;
+  }
+  // B^u = [Phi_u K^{uu}; Phi_d K^{ud}] in P, B^d = [Phi_u K^{du}; Phi_d K^{dd}] in Bd
+  struct Part { int q, h; double* out; };
+  const Part parts[4] = {{0, 0, (double*)w.P}, {1, 1, (double*)w.P}, {2, 0, w.Bd}, {3, 1, w.Bd}};
+  for (const Part& x : parts) {
+    const int n = x.h == 0 ? s.nu : s.nd;
+    if (n == 0) continue;
+    const long rows = (long)w.Wk * n;
+    OzArgs g{};
+    g.M = (int)rows; g.N = s.Lp; g.Kp = s.Lp;
+    g.A = w.oz_phi + (x.h == 0 ? 0 : up_bytes); g.a_plane = oz_plane_bytes(rows, s.Lp);
+    g.ea = w.oz_ephi + (x.h == 0 ? 0 : (long)w.Wk * s.nu);
+    g.B = s.oz_lam + (long)x.q * s.oz_s * planeB; g.b_plane = planeB; g.eb = s.oz_elam + (long)x.q * s.Lp;
+    g.C = x.out + (x.h == 0 ? 0 : (long)s.nu * s.Lp); g.c_grp = n; g.c_gs = rowst; g.ldc = s.Lp;
+    const hipError_t e = run_ozaki_s(s.oz_s, g, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 }  // namespace qmc

@@ -201,7 +201,8 @@ extern "C" qmc_status qmc_system_create(const qmc_system_desc* desc, qmc_system*
   const bool pf = q.pairing == 1;
   if (q.pairing != 0 && !pf) return fail(QMC_ERR_ARG, "pairing must be 0 or 1");
   if (pf) {
-    if (q.precision != QMC_FP64) return fail(QMC_ERR_UNSUPPORTED, "the Pfaffian is built in FP64 only");
+    if (q.precision != QMC_FP64 && q.precision != QMC_REFINED)
+      return fail(QMC_ERR_UNSUPPORTED, "the Pfaffian is built in FP64 and QMC_REFINED only");
     if (q.pf_k < 0) return fail(QMC_ERR_ARG, "pf_k must be >= 0");
     if ((q.n_up + q.n_dn + q.pf_k) % 2) return fail(QMC_ERR_ARG, "N + pf_k must be even");
     if (q.n_up + q.n_dn + q.pf_k > kLuRowMax) return fail(QMC_ERR_UNSUPPORTED, "Pfaffian of dimension > 96");
@@ -215,8 +216,8 @@ extern "C" qmc_status qmc_system_create(const qmc_system_desc* desc, qmc_system*
   if (q.precision < QMC_FP64 || q.precision > QMC_REFINED || q.precision == QMC_W_BF16 ||
       q.precision == QMC_W_FP8)
     return fail(QMC_ERR_UNSUPPORTED, "precision not built");
-  if (q.precision == QMC_REFINED && (pf || q.n_up != q.n_dn))
-    return fail(QMC_ERR_UNSUPPORTED, "QMC_REFINED is built for paired determinant systems (n_up == n_dn)");
+  if (q.precision == QMC_REFINED && !pf && q.n_up != q.n_dn)
+    return fail(QMC_ERR_UNSUPPORTED, "QMC_REFINED is built for paired determinants (n_up == n_dn) and Pfaffians");
   if (q.refresh_every < 1) return fail(QMC_ERR_ARG, "refresh_every must be >= 1");
   if (q.j1_form < 0 || q.j1_form > 2 || (q.j1_form && !q.j1_b)) return fail(QMC_ERR_ARG, "bad j1");
   if (q.j2_form < 0 || q.j2_form > 2) return fail(QMC_ERR_ARG, "bad j2 form");
@@ -483,6 +484,19 @@ extern "C" qmc_status qmc_system_create(const qmc_system_desc* desc, qmc_system*
     if (!e) e = launch_oz_lambda(d, nullptr);
     if (!e) e = hipStreamSynchronize(nullptr);
   }
+  if (!e && d.pf_refined()) {
+    // int8 digits of the four K^T for the error-free B rows of the evaluation
+    d.oz_s = kOzSlices;
+    const size_t plane = (size_t)oz_plane_bytes(Lp, Lp);
+    std::vector<int8_t> z8(4 * (size_t)d.oz_s * plane, 0);
+    std::vector<int> z4(4 * (size_t)Lp, 0);
+    std::vector<double> zt((size_t)Lp * Lp, 0.0);
+    e = up((void**)&d.oz_lam, z8.data(), z8.size());
+    if (!e) e = up((void**)&d.oz_elam, z4.data(), sizeof(int) * z4.size());
+    if (!e) e = up((void**)&d.oz_tmp, zt.data(), sizeof(double) * zt.size());
+    if (!e) e = launch_oz_pf_K(d, nullptr);
+    if (!e) e = hipStreamSynchronize(nullptr);
+  }
   if (e != hipSuccess) {
     delete s;
     return e == hipErrorOutOfMemory ? fail(QMC_ERR_OOM, "device allocation failed") : hip_fail(e, "system_create");
@@ -553,7 +567,7 @@ static void walker_layout(const SysDev& s, int n_walkers, bool adjoint, Carver& 
     c.take(&d.phi64, sizeof(double) * Wk * N * s.Lp);
     c.take(&d.P64, sizeof(double) * Wk * N * s.Lp);
   }
-  if ((s.refined() || s.screened()) && s.oz_s > 0) {
+  if ((s.refined() || s.screened() || s.pf_refined()) && s.oz_s > 0) {
     c.take(&d.oz_phi, (size_t)oz_phi_bytes(s, (long)Wk));
     c.take(&d.oz_ephi, sizeof(int) * Wk * N);
   }
@@ -777,7 +791,8 @@ extern "C" qmc_status qmc_eval_batch(qmc_system* sys, qmc_walkers* wk, const dou
   TIMED(wk, QMC_T_BASIS, stream, launch_basis_values(se, de, stream, refine ? d.phi : nullptr, s.bf16(), ephi),
         "basis");
   if (s.pairing) {
-    TIMED(wk, QMC_T_P_BUILD, stream, launch_pf_B_build(s, d, stream), "Pfaffian B rows");
+    TIMED(wk, QMC_T_P_BUILD, stream, s.pf_refined() ? launch_pf_B_build_oz(s, d, stream) : launch_pf_B_build(s, d, stream),
+          "Pfaffian B rows");
     TIMED(wk, QMC_T_W_BUILD, stream, launch_pf_G_build(s, d, stream), "Pfaffian G");
     TIMED(wk, QMC_T_LU, stream, launch_pf_factor(s, d, stream), "Pfaffian and inverse");
     TIMED(wk, QMC_T_Y_BUILD, stream, launch_pf_Y_build(s, d, stream), "Pfaffian Y build");
@@ -1392,6 +1407,7 @@ extern "C" qmc_status qmc_system_set_pfaffian(qmc_system* sys, const double* pf_
   if (!sys->d.pairing) return fail(QMC_ERR_ARG, "the system is not a Pfaffian");
   HIP_TRY(launch_pf_set(sys->d, nullptr, pf_uu, pf_dd, sys->d.pk ? unpaired : nullptr,
                         sys->d.pk ? unpaired_dn : nullptr, stream), "set Pfaffian");
+  if ((pf_uu || pf_dd) && sys->d.pf_refined()) HIP_TRY(launch_oz_pf_K(sys->d, stream), "K digits");
   sys->generation += 1;
   return QMC_OK;
 }
@@ -1404,6 +1420,7 @@ extern "C" qmc_status qmc_system_set_params(qmc_system* sys, const double* R, co
   if (zeta)   // one exponent per basis function (per primitive of a contracted basis)
     HIP_TRY(hipMemcpyAsync(d.zeta, zeta, sizeof(double) * d.nprim(), hipMemcpyDeviceToDevice, stream), "set zeta");
   if (lambda && d.pairing) HIP_TRY(launch_pf_set(d, lambda, nullptr, nullptr, nullptr, nullptr, stream), "set A^ud");
+  if (lambda && d.pf_refined()) HIP_TRY(launch_oz_pf_K(d, stream), "K digits");
   if (lambda && !d.pairing) HIP_TRY(launch_set_lambda(d, lambda, stream), "set lambda");
   if (lambda && !d.pairing) HIP_TRY(launch_lam_mask(d, stream), "lambda mask");
   if (lambda && !d.pairing && d.oz_s > 0) HIP_TRY(launch_oz_lambda(d, stream), "lambda digits");

@@ -110,7 +110,7 @@ def test_refined_chain_matches_oracle(name):
 
 def test_refined_refusals():
     P = need_gpu()
-    for w in (C.polarized_4nuc_20e(n_walkers=2), C.pfaffian_4nuc_20e(n_walkers=2)):
+    for w in (C.polarized_4nuc_20e(n_walkers=2),):   # (a QMC_REFINED Pfaffian is built)
         with pytest.raises(P.QMCError) as ei:
             P.JAGPSystem(w.system, precision=P.QMC_REFINED)
         assert ei.value.code == -5
