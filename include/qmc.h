@@ -89,8 +89,9 @@ typedef enum {
                       whose value at r' can change the determinant ratio:
                       those skipped contribute at most 1e-13 in total (bound
                       from the largest |P| of each column and the inverse
-                      column's 1-norm).  Determinant systems with n_up ==
-                      n_dn; not with qmc_multi_*.  One more [Wk][L][N] FP64
+                      column's 1-norm; an up move of a polarized system also
+                      streams the unpaired orbitals' values).  Not with
+                      qmc_multi_*.  One more [Wk][L][N + n_up - n_dn] FP64
                       array (P transposed).  For a Pfaffian (pairing = 1) the
                       evaluation's B rows phi(r_j)^T K^{s s_j} are the same
                       error-free int8 digit products; G~, Pf, its inverse and

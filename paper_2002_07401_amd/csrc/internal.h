@@ -89,6 +89,9 @@ struct SysDev {
   // 0: FP64, 1: FP32, 2: BF16 storage
   __host__ __device__ int store() const { return f32() ? (bf16() ? 2 : 1) : 0; }
   __host__ __device__ int prop_rows() const { return store() == 0 ? kPropRowsF64 : kPropRowsNarrow; }
+  // entries per basis function of the transposed rows of the screened
+  // proposals: the N electrons, then the nk unpaired orbitals' values
+  __host__ __device__ int pt_ld() const { return N + nk; }
   double* R;        // [A][3]
   double* Z;        // [A]
   double* j1_b;     // [A]
@@ -236,10 +239,13 @@ struct WalkDev {
   int8_t* oz_phi;
   int* oz_ephi;
   // screened proposals (QMC_REFINED): P transposed per walker, PT[w][mu][i] =
-  // P[w][i][mu] (so that one basis function's column over the rows of one spin
-  // is contiguous); per walker and spin the largest |P| of each column
-  // [Wk][2][Lp] (0: up rows, 1: down rows); the pending proposal's kept basis
-  // functions (index and value at r') and their count
+  // P[w][i][mu] for the N electrons and PT[w][mu][N + l] = U[mu][l] for the
+  // nk unpaired orbitals ([Wk][Lp][N + nk]: one basis function's column over
+  // the rows an up move streams, the down electrons and the unpaired
+  // orbitals, and over the up rows a down move streams is contiguous); per
+  // walker and spin the largest |value| of each column over those rows
+  // [Wk][2][Lp] (0: up rows, 1: down rows and unpaired orbitals); the pending
+  // proposal's kept basis functions (index and value at r') and their count
   double* PT;
   double* cmax;
   int* muk;
@@ -559,6 +565,8 @@ hipError_t launch_P_build_oz(const SysDev& s, const WalkDev& w, int halves, cons
                              int dirty = 0);
 // screened proposals: column maxima of the P halves, and the streaming kernel
 hipError_t launch_screen_colmax(const SysDev& s, const WalkDev& w, int halves, hipStream_t st);
+// the unpaired orbitals' entries of every walker's transposed rows
+hipError_t launch_pt_unpaired(const SysDev& s, const WalkDev& w, hipStream_t st);
 hipError_t launch_export_kept(const WalkDev& w, double* dst, hipStream_t st);
 hipError_t launch_propose_screened(const SysDev& s, const WalkDev& w, int e, double* ratio, bool finalize,
                                    hipStream_t st, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);

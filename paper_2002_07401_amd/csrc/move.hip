@@ -166,8 +166,9 @@ hipError_t launch_propose_rows(const SysDev& s, const WalkDev& w, int e, double*
 
 // ---------------------------------------------------------------------------
 // Screened proposals (QMC_REFINED).  The new W row (column) of walker wk is
-//   w'_j = sum over the kept mu of psi_mu(r') PT[wk][mu][i0 + j],
-// one contiguous column of the other spin's rows per kept basis function (the
+//   w'_j = sum over the kept mu of psi_mu(r') PT[wk][mu][i0 + j],  j < n_up,
+// one contiguous column of the rows the move streams per kept basis function
+// (for an up move the down electrons' rows and the unpaired orbitals; the
 // skipped ones change the ratio by at most kScreenTol, see screen_list_body).
 // One workgroup per walker: wave v takes kept functions v, v + 4, ..., four at
 // a time, lane l the rows l, l + 64, ...; the waves' partial rows are added in
@@ -182,8 +183,9 @@ __global__ void __launch_bounds__(256) propose_screened_kernel(SysDev s, WalkDev
   const int wk = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const bool up = e < s.nu;
   const int i0 = up ? s.nu : 0;
-  const int n = up ? s.nd : s.nu;
-  const double* base = w.PT + (long)wk * s.Lp * s.N + i0;
+  const int n = up ? s.nd + s.nk : s.nu;   // = n_up either way
+  const int ld = s.pt_ld();
+  const double* base = w.PT + (long)wk * s.Lp * ld + i0;
   const int cnt = w.nkeep[wk];
   const int* mk = w.muk + (long)wk * s.Lp;
   const double* pk = w.psk + (long)wk * s.Lp;
@@ -202,7 +204,7 @@ __global__ void __launch_bounds__(256) propose_screened_kernel(SysDev s, WalkDev
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         const int j = lane + 64 * b;
-        x[q][b] = j < n ? __builtin_nontemporal_load(base + (long)mu[q] * s.N + j) : 0.0;
+        x[q][b] = j < n ? __builtin_nontemporal_load(base + (long)mu[q] * ld + j) : 0.0;
       }
 #pragma unroll
     for (int q = 0; q < 4; ++q)
@@ -215,7 +217,7 @@ __global__ void __launch_bounds__(256) propose_screened_kernel(SysDev s, WalkDev
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       const int j = lane + 64 * b;
-      if (j < n) acc[b] += v * base[(long)mu * s.N + j];
+      if (j < n) acc[b] += v * base[(long)mu * ld + j];
     }
   }
 #pragma unroll
@@ -286,9 +288,30 @@ __global__ void __launch_bounds__(256) screen_colmax_kernel(SysDev s, WalkDev w,
       part[wave][2 * lane + 128 * c + 1] = m[c].y;
     }
     __syncthreads();
-    for (int mu = tid; mu < 128 * CC && c0 + mu < Lp; mu += blockDim.x)
-      out[c0 + mu] = fmax(fmax(part[0][mu], part[1][mu]), fmax(part[2][mu], part[3][mu]));
+    for (int mu = tid; mu < 128 * CC && c0 + mu < Lp; mu += blockDim.x) {
+      double m = fmax(fmax(part[0][mu], part[1][mu]), fmax(part[2][mu], part[3][mu]));
+      if (h == 1)   // an up move also streams the unpaired orbitals' values
+        for (int l = 0; l < s.nk; ++l) m = fmax(m, fabs(s.Uph[(long)l * Lp + c0 + mu]));
+      out[c0 + mu] = m;
+    }
   }
+}
+
+// PT[w][mu][N + l] = U[mu][l] for every walker (constant: written once)
+__global__ void __launch_bounds__(256) pt_unpaired_kernel(SysDev s, WalkDev w) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long per = (long)s.Lp * s.nk;
+  if (t >= per * w.Wk) return;
+  const long wk = t / per, q = t % per, mu = q / s.nk, l = q % s.nk;
+  w.PT[(wk * s.Lp + mu) * s.pt_ld() + s.N + l] = s.Uph[l * s.Lp + mu];
+}
+
+hipError_t launch_pt_unpaired(const SysDev& s, const WalkDev& w, hipStream_t st) {
+  if (s.nk == 0) return hipSuccess;
+  if (!w.PT || !s.Uph) return hipErrorInvalidValue;
+  const long n = (long)s.Lp * s.nk * w.Wk;
+  hipLaunchKernelGGL(pt_unpaired_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s, w);
+  return hipGetLastError();
 }
 
 __global__ void int_to_double_kernel(const int* __restrict__ src, double* __restrict__ dst, int n) {

@@ -76,9 +76,9 @@ __device__ void screened_stream_walker(const SysDev& s, const WalkDev& w, int wk
   const int tid = phase_tid(), lane = tid & 63, wave = tid >> 6;
   const bool up = e < s.nu;
   const int i0 = up ? s.nu : 0;
-  const int n = up ? s.nd : s.nu;
-  const int Lp = s.Lp;
-  const double* base = w.PT + (long)wk * Lp * s.N + i0;
+  const int n = up ? s.nd + s.nk : s.nu;   // = n_up either way (unpaired orbitals after the down rows)
+  const int Lp = s.Lp, ld = s.pt_ld();
+  const double* base = w.PT + (long)wk * Lp * ld + i0;
   int* lmu = (int*)lds;
   double* lv = (double*)(lds + pad1k(sizeof(int) * (size_t)Lp));
   dbl2* part = (dbl2*)((char*)lv + pad1k(sizeof(double) * (size_t)Lp));
@@ -132,7 +132,7 @@ __device__ void screened_stream_walker(const SysDev& s, const WalkDev& w, int wk
         const bool ok = kk < cnt;
         const int mu = lmu[ok ? kk : 0];
         vv[u][i] = ok ? lv[kk] : 0.0;
-        x[u][i] = __builtin_nontemporal_load((const dbl2*)(base + (long)mu * s.N + ji[i]));
+        x[u][i] = __builtin_nontemporal_load((const dbl2*)(base + (long)mu * ld + ji[i]));
       }
 #pragma unroll
     for (int u = 0; u < UB; ++u)
@@ -168,7 +168,7 @@ __device__ void screened_stream_walker(const SysDev& s, const WalkDev& w, int wk
 // at most 8; n <= 256 (one row per thread in the final sums), Lp <=
 // kFuseMaxLp (the kept list in LDS).  False: the plain screened kernel.
 inline bool screened_blk_config(const SysDev& s, const WalkDev& w, int e, int& IPB, int& FB, size_t& lds) {
-  const int n = e < s.nu ? s.nd : s.nu;
+  const int n = e < s.nu ? s.nd + s.nk : s.nu;
   int g = 128;
   while (n % g) g >>= 1;
   FB = 128 / g;
@@ -176,7 +176,7 @@ inline bool screened_blk_config(const SysDev& s, const WalkDev& w, int e, int& I
   lds = pad1k(sizeof(int) * (size_t)s.Lp) + pad1k(sizeof(double) * (size_t)s.Lp) +
         sizeof(dbl2) * 4 * 64 * (size_t)IPB;
   return n % 2 == 0 && n <= 256 && IPB >= 1 && IPB <= 8 && s.Lp <= kFuseMaxLp && (uintptr_t)w.PT % 16 == 0 &&
-         s.N % 2 == 0 && (e < s.nu ? s.nu : 0) % 2 == 0;
+         s.pt_ld() % 2 == 0 && (e < s.nu ? s.nu : 0) % 2 == 0;
 }
 
 // ---------------------------------------------------------------------------

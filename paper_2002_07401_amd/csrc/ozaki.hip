@@ -556,8 +556,8 @@ hipError_t launch_P_build_oz(const SysDev& s, const WalkDev& w, int halves, cons
     }
     if (PT) {   // PT[w][mu][i] for every electron i of walker w (this half: i = i0 + m % n)
       g.CT = PT + (h == 0 ? 0 : s.nu);
-      g.ct_gs = (long)s.Lp * s.N;
-      g.ct_ld = s.N;
+      g.ct_gs = (long)s.Lp * s.pt_ld();
+      g.ct_ld = s.pt_ld();
     }
     g.kmask = h == 0 ? s.lam_mask : s.lamT_mask;
     g.kmask_ld = mask_ld;

@@ -216,8 +216,6 @@ extern "C" qmc_status qmc_system_create(const qmc_system_desc* desc, qmc_system*
   if (q.precision < QMC_FP64 || q.precision > QMC_REFINED || q.precision == QMC_W_BF16 ||
       q.precision == QMC_W_FP8)
     return fail(QMC_ERR_UNSUPPORTED, "precision not built");
-  if (q.precision == QMC_REFINED && !pf && q.n_up != q.n_dn)
-    return fail(QMC_ERR_UNSUPPORTED, "QMC_REFINED is built for paired determinants (n_up == n_dn) and Pfaffians");
   if (q.refresh_every < 1) return fail(QMC_ERR_ARG, "refresh_every must be >= 1");
   if (q.j1_form < 0 || q.j1_form > 2 || (q.j1_form && !q.j1_b)) return fail(QMC_ERR_ARG, "bad j1");
   if (q.j2_form < 0 || q.j2_form > 2) return fail(QMC_ERR_ARG, "bad j2 form");
@@ -572,7 +570,7 @@ static void walker_layout(const SysDev& s, int n_walkers, bool adjoint, Carver& 
     c.take(&d.oz_ephi, sizeof(int) * Wk * N);
   }
   if (s.screened()) {
-    c.take(&d.PT, sizeof(double) * Wk * N * s.Lp);
+    c.take(&d.PT, sizeof(double) * Wk * s.pt_ld() * s.Lp);
     c.take(&d.cmax, sizeof(double) * Wk * 2 * s.Lp);
     c.take(&d.muk, sizeof(int) * Wk * s.Lp);
     c.take(&d.psk, sizeof(double) * Wk * s.Lp);
@@ -735,6 +733,10 @@ extern "C" qmc_status qmc_walkers_create(qmc_system* sys, int32_t n_walkers, int
   walker_layout(sys->d, n_walkers, adjoint, cv, *wk);
   wk->aw_ready = adjoint;
   hipError_t e = hipMemset(base, 0, need);
+  if (e == hipSuccess && sys->d.screened() && sys->d.nk > 0) {   // the unpaired orbitals' transposed rows
+    e = launch_pt_unpaired(sys->d, wk->d, nullptr);
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+  }
   if (e != hipSuccess) {
     delete wk;
     return hip_fail(e, "walkers_create");
