@@ -238,12 +238,14 @@ hipError_t gemm_f64(const GemmArgs& g, bool ta, bool tb, bool big, hipStream_t s
 #undef QMC_G
 }
 
-// Tile shapes from a sweep on MI355X (1024 walkers x 80 rows, L = 608): FP64
-// 64 x 32 with K steps of 16 (65 % of the FP64 matrix peak); FP32 / BF16 rows
-// 64 x 64 with K steps of 32.
+// Tile shapes from sweeps on MI355X (1024 walkers x 80 rows, L = 608, all
+// rows or a list of 60 per walker): FP64 64 x 64 with K steps of 16 (61-63 %
+// of the FP64 matrix peak, against 51-57 % for 64 x 32, 57-58 % for 128 x 32
+// and 32 x 64, 49-51 % for 128 x 128); FP32 / BF16 rows 64 x 64 with K steps
+// of 32.
 template <typename T, typename TL>
 static hipError_t P_gemm(const GemmArgs& g, hipStream_t st) {
-  if constexpr (sizeof(TL) == 8) return run_gemm<64, 32, false, false, T, TL, TL, T, 16>(g, st);
+  if constexpr (sizeof(TL) == 8) return run_gemm<64, 64, false, false, T, TL, TL, T, 16>(g, st);
   else return run_gemm<64, 64, false, false, T, TL, TL, T, 32>(g, st);
 }
 
