@@ -630,9 +630,127 @@ __global__ void __launch_bounds__(64 * RB) yt_kernel(const double* __restrict__ 
   }
 }
 
+// The same products for n = 80 or 96 (RB = 5 or 6 row blocks of 16): one
+// workgroup of four waves per (walker, spin) walks all column slabs of P.
+// With RB > 4 the per-slab kernel above puts RB waves on the four SIMDs, two
+// of them on one, which then takes twice as long; here wave w computes row
+// block w for all four 16-column blocks of a slab and row blocks 4 .. RB - 1
+// for column block w, so that every SIMD runs the same number of MFMA chains
+// (RB of the 4 RB of a slab).  The wave's A fragments
+// (its row blocks, every K step) are loaded once per walker; the next slab's
+// values are loaded into registers while the current slab multiplies out of
+// LDS.  Same instruction, same k order: bitwise the per-slab kernel's Yt.
+template <typename T, int RB>
+__global__ void __launch_bounds__(256) yt_walker_kernel(const double* __restrict__ Ag, const T* __restrict__ Pg,
+                                                        double* __restrict__ Yg, int N, int Lp) {
+  static_assert(RB == 5 || RB == 6, "n = 80 or 96");
+  constexpr int n = 16 * RB, KS = n / 4, NX = RB - 4;   // K steps; extra row blocks per wave
+  constexpr int PAIRS = n * 32 / 256;                    // column pairs of a slab per thread
+  __shared__ double Ps[n * 64];
+  const long b = xcd_remap(blockIdx.x, gridDim.x);
+  const int spin = (int)(b & 1);   // 0: up rows of Yt (from P_dn), 1: down rows (from P_up)
+  const long wk = b >> 1;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nslab = (Lp + 63) / 64;
+  const double* A = Ag + wk * (long)n * n;
+  const T* P = Pg + (wk * N + (spin == 0 ? n : 0)) * (long)Lp;
+  double* Y = Yg + (wk * N + (spin == 0 ? 0 : n)) * (long)Lp;
+  // A fragments of row blocks wave and 4 .. RB - 1: op(A)[row][k] is A^T
+  // (A[k][row]) for the up rows and A (A[row][k]) for the down rows
+  const int g = lane >> 4;
+  const int tstride = spin == 0 ? 4 * n : 4;
+  double am[KS], ax[NX > 0 ? NX : 1][KS];
+  {
+    const int row = wave * 16 + (lane & 15);
+    const int loff = spin == 0 ? g * n + row : row * n + g;
+#pragma unroll
+    for (int t = 0; t < KS; ++t) am[t] = (A + (long)t * tstride)[loff];
+  }
+#pragma unroll
+  for (int j = 0; j < NX; ++j) {
+    const int row = (4 + j) * 16 + (lane & 15);
+    const int loff = spin == 0 ? g * n + row : row * n + g;
+#pragma unroll
+    for (int t = 0; t < KS; ++t) ax[j][t] = (A + (long)t * tstride)[loff];
+  }
+  // slab staging: thread tid moves column pairs idx = tid + 256 q (row idx / 32, pair idx % 32)
+  double2 pv[PAIRS];
+  auto load = [&](int c0) {
+    const int h = min(64, Lp - c0) / 2;
+#pragma unroll
+    for (int q = 0; q < PAIRS; ++q) {
+      const int idx = tid + 256 * q, k = idx >> 5, cp = idx & 31;
+      pv[q] = double2{};
+      if (cp < h) {
+        if constexpr (sizeof(T) == 8) {
+          pv[q] = *(const double2*)(P + (long)k * Lp + c0 + 2 * cp);
+        } else {
+          const float2 v = *(const float2*)(P + (long)k * Lp + c0 + 2 * cp);
+          pv[q] = double2{(double)v.x, (double)v.y};
+        }
+      }
+    }
+  };
+  load(0);
+  for (int sl = 0; sl < nslab; ++sl) {
+    const int c0 = sl * 64, cw = min(64, Lp - c0);
+#pragma unroll
+    for (int q = 0; q < PAIRS; ++q) *(double2*)(Ps + 2 * (tid + 256 * q)) = pv[q];
+    __syncthreads();
+    if (sl + 1 < nslab) load(c0 + 64);
+    dx4 acc[4], accx[NX > 0 ? NX : 1];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[cb][r] = 0.0;
+#pragma unroll
+    for (int j = 0; j < NX; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) accx[j][r] = 0.0;
+#pragma unroll
+    for (int t = 0; t < KS; ++t) {
+      const double* pr = Ps + (4 * t + g) * 64 + (lane & 15);
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(am[t], pr[16 * cb], acc[cb], 0, 0, 0);
+#pragma unroll
+      for (int j = 0; j < NX; ++j)
+        accx[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ax[j][t], pr[16 * wave], accx[j], 0, 0, 0);
+    }
+    // 16 x 16 block layout: lane holds column lane % 16 and rows 4 r + lane / 16
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+      const int c = cb * 16 + (lane & 15);
+      if (c < cw) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Y[(long)(wave * 16 + 4 * r + g) * Lp + c0 + c] = acc[cb][r];
+      }
+    }
+    {
+      const int c = wave * 16 + (lane & 15);
+      if (c < cw) {
+#pragma unroll
+        for (int j = 0; j < NX; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) Y[(long)((4 + j) * 16 + 4 * r + g) * Lp + c0 + c] = accx[j][r];
+      }
+    }
+    __syncthreads();   // every wave has read the slab before the next one is written
+  }
+}
+
 template <typename T>
 static hipError_t launch_yt(const SysDev& s, const WalkDev& w, hipStream_t st) {
   const int n = s.nu, nslab = (s.Lp + 63) / 64;
+  if (n == 80 || n == 96) {   // four balanced waves per walker and spin
+    if ((long)w.Wk * 2 > 0x7fffffffL) return hipErrorInvalidValue;
+    if (n == 80)
+      hipLaunchKernelGGL((yt_walker_kernel<T, 5>), dim3((unsigned)(w.Wk * 2)), dim3(256), 0, st, w.A, (const T*)w.P,
+                         w.Yt, s.N, s.Lp);
+    else
+      hipLaunchKernelGGL((yt_walker_kernel<T, 6>), dim3((unsigned)(w.Wk * 2)), dim3(256), 0, st, w.A, (const T*)w.P,
+                         w.Yt, s.N, s.Lp);
+    return hipGetLastError();
+  }
   const long total = (long)w.Wk * 2 * nslab;
   if (total > 0x7fffffffL) return hipErrorInvalidValue;
   const size_t lds = sizeof(double) * (size_t)n * 64;
