@@ -208,12 +208,15 @@ __device__ __forceinline__ void hess_P(int kind, double H[6]) {   // xx yy zz xy
   }
 }
 
-__global__ void __launch_bounds__(256)
+// Launched with kBackThreads threads (five waves: 300 functions in one pass at
+// L = 300, 600 in two).
+constexpr int kBackThreads = 320;
+__global__ void __launch_bounds__(kBackThreads)
 basis_backward_kernel(SysDev s, WalkDev w, const double* __restrict__ phibar, const double* __restrict__ gb,
                       double* __restrict__ dr, double* __restrict__ Rbar_w, double* __restrict__ zbar_w,
                       double* __restrict__ tmu, int acc) {
   constexpr int NC = kLuMaxN * 2;   // electrons per chunk (rows of rpart)
-  __shared__ double rpart[4][NC][3];
+  __shared__ double rpart[kBackThreads / 64][NC][3];
   const int wk = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const double b = gb ? gb[wk] : 0.0;
   const double* r = w.r + (long)wk * s.N * 3;
@@ -297,7 +300,7 @@ basis_backward_kernel(SysDev s, WalkDev w, const double* __restrict__ phibar, co
     for (int i = c0 + tid; i < c1; i += blockDim.x) {
       for (int c = 0; c < 3; ++c) {
         double t = 0.0;
-        for (int q = 0; q < 4; ++q) t += rpart[q][i - c0][c];
+        for (int q = 0; q < (int)(blockDim.x >> 6); ++q) t += rpart[q][i - c0][c];
         if (acc) dr[((long)wk * s.N + i) * 3 + c] += t;
         else dr[((long)wk * s.N + i) * 3 + c] = t;
       }
@@ -329,6 +332,7 @@ jastrow_backward_kernel(SysDev s, WalkDev w, const double* __restrict__ ga, cons
                         double* __restrict__ dr, double* __restrict__ Rbar_w, double* __restrict__ jbar_w) {
   __shared__ double rbin[4][kMaxNucBack][4];   // per wave: dR (3) and d b_a
   __shared__ double red[4][8];
+  __shared__ double rpair[256][3];              // per thread: its partners' share of dF/dr_i
   const int wk = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const double av = ga ? ga[wk] : 0.0, bv = gbw ? gbw[wk] : 0.0;
   const double* r = w.r + (long)wk * s.N * 3;
@@ -373,26 +377,35 @@ jastrow_backward_kernel(SysDev s, WalkDev w, const double* __restrict__ ga, cons
         else { rbw[0] += s0; rbw[1] += s1; rbw[2] += s2; rbw[3] += s3; }
       }
     }
-    // two-body terms and electron-electron repulsion
-    if (act) {
-      for (int j = 0; j < s.N; ++j) {
-        if (j == i) continue;
-        const double d[3] = {xi[0] - r[3 * j], xi[1] - r[3 * j + 1], xi[2] - r[3 * j + 2]};
+    // two-body terms and electron-electron repulsion: the chunk's nc electrons
+    // times G groups of partners (thread = electron c0 + tid % nc, partners
+    // j = g, g + G, ... for g = tid / nc), so that short chunks keep most
+    // threads busy; the groups' sums for an electron meet in LDS in order of g
+    const int nc = min(s.N - c0, (int)blockDim.x);
+    const int G = max(1, (int)blockDim.x / nc);
+    const int ip = c0 + tid % nc, gp = tid / nc;
+    double rp[3] = {0.0, 0.0, 0.0};
+    if (gp < G) {
+      double xp[3], gq[3];
+      for (int c = 0; c < 3; ++c) { xp[c] = r[3 * ip + c]; gq[c] = -bv * drift[3 * ip + c]; }
+      for (int j = gp; j < s.N; j += G) {
+        if (j == ip) continue;
+        const double d[3] = {xp[0] - r[3 * j], xp[1] - r[3 * j + 1], xp[2] - r[3 * j + 2]};
         const double rij = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
         const double ir3 = 1.0 / (rij * rij * rij);
-        for (int c = 0; c < 3; ++c) rb[c] += -bv * d[c] * ir3;    // b_w * 1/r_ij
+        for (int c = 0; c < 3; ++c) rp[c] += -bv * d[c] * ir3;    // b_w * 1/r_ij
         if (!s.j2_form) continue;
-        const bool same = (i < s.nu) == (j < s.nu);
+        const bool same = (ip < s.nu) == (j < s.nu);
         double p[4];
         j2_params(s, same, p);
         const double cc = same ? 0.25 : 0.5;
         double dg[3];
-        for (int c = 0; c < 3; ++c) dg[c] = gi[c] + bv * drift[3 * j + c];    // gbar_i - gbar_j
+        for (int c = 0; c < 3; ++c) dg[c] = gq[c] + bv * drift[3 * j + c];    // gbar_i - gbar_j
         Dl v, v1, v2;
         j2_radial_t<Dl>(cc, cst(p[0]), cst(p[1]), cst(p[2]), cst(p[3]), var(rij), v, v1, v2);
         double t[3];
         pair_term_grad(av, -bv, dg, d, rij, v1.v, v2.v, v2.d, t);
-        for (int c = 0; c < 3; ++c) rb[c] += t[c];
+        for (int c = 0; c < 3; ++c) rp[c] += t[c];
         const double gd = (dg[0] * d[0] + dg[1] * d[1] + dg[2] * d[2]) / rij;
         const int np = s.j2_form == 1 ? 1 : 4;
         const int slot0 = s.j2_form == 1 ? (same ? 0 : 1) : (same ? 0 : 4);
@@ -405,6 +418,14 @@ jastrow_backward_kernel(SysDev s, WalkDev w, const double* __restrict__ ga, cons
           th[slot0 + k] += 0.5 * (av * pv.d + gd * pv1.d - bv * (pv2.d + 2.0 * pv1.d / rij));
         }
       }
+    }
+    __syncthreads();   // the previous chunk's partner sums are read
+    if (gp < G)
+      for (int c = 0; c < 3; ++c) rpair[tid][c] = rp[c];
+    __syncthreads();
+    if (act) {
+      for (int g = 0; g < G; ++g)
+        for (int c = 0; c < 3; ++c) rb[c] += rpair[g * nc + tid][c];
       for (int c = 0; c < 3; ++c) dr[((long)wk * s.N + i) * 3 + c] += rb[c];
     }
   }
@@ -440,11 +461,23 @@ jastrow_backward_kernel(SysDev s, WalkDev w, const double* __restrict__ ga, cons
 }
 
 // Sum per-walker (or per-chunk) rows: out[k] = sum_w in[w][k], fixed order.
+// The rows are added in order; their values are loaded sixteen at a time (a
+// short output, such as dF/dR over 512 walkers, is otherwise one dependent
+// load per row).
 __global__ void sum_rows_kernel(const double* __restrict__ in, long n_rows, long len, double* __restrict__ out) {
   const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= len) return;
+  constexpr int U = 16;
   double t = 0.0;
-  for (long w = 0; w < n_rows; ++w) t += in[w * len + k];
+  long w = 0;
+  for (; w + U <= n_rows; w += U) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = in[(w + u) * len + k];
+#pragma unroll
+    for (int u = 0; u < U; ++u) t += v[u];
+  }
+  for (; w < n_rows; ++w) t += in[w * len + k];
   out[k] = t;
 }
 
@@ -617,7 +650,7 @@ static hipError_t launch_jastrow3_backward(const SysDev& s, const WalkDev& w, co
   WalkDev wj = w;
   wj.Yt = aw.jgv;
   wj.gJ = aw.drift4;
-  hipLaunchKernelGGL(basis_backward_kernel, dim3(Wk), dim3(256), 0, st, sj, wj, aw.jpb, gb, drw, aw.Rbar,
+  hipLaunchKernelGGL(basis_backward_kernel, dim3(Wk), dim3(kBackThreads), 0, st, sj, wj, aw.jpb, gb, drw, aw.Rbar,
                      aw.jzbar, aw.jtmu, 1);
   return hipGetLastError();
 }
@@ -1108,10 +1141,10 @@ hipError_t launch_forces(const SysDev& s, const WalkDev& w, const AdjWork& aw, c
     sq.L = s.Lq; sq.Lp = lqp; sq.Lq = 0;
     WalkDev wq = w;
     wq.Yt = aw.Ytq;
-    hipLaunchKernelGGL(basis_backward_kernel, dim3(Wk), dim3(256), 0, st, sq, wq, aw.PBq, gb, drw, aw.Rbar,
+    hipLaunchKernelGGL(basis_backward_kernel, dim3(Wk), dim3(kBackThreads), 0, st, sq, wq, aw.PBq, gb, drw, aw.Rbar,
                        aw.zbar, aw.tmu, 0);
   } else {
-    hipLaunchKernelGGL(basis_backward_kernel, dim3(Wk), dim3(256), 0, st, s, w, aw.PB, gb, drw, aw.Rbar,
+    hipLaunchKernelGGL(basis_backward_kernel, dim3(Wk), dim3(kBackThreads), 0, st, s, w, aw.PB, gb, drw, aw.Rbar,
                        aw.zbar, aw.tmu, 0);
   }
   HT(hipGetLastError());

@@ -228,7 +228,7 @@ GemmArgs gemm_args(int M, int N, int K) {
 static GemmArgs plain(int M, int N, int K) { return gemm_args(M, N, K); }
 
 hipError_t gemm_f64(const GemmArgs& g, bool ta, bool tb, bool big, hipStream_t st) {
-#define QMC_G(BM, BN, TA_, TB_) run_gemm<BM, BN, TA_, TB_, double, double, double, double>(g, st)
+#define QMC_G(BM, BN, TA_, TB_) run_gemm<BM, BN, TA_, TB_, double, double, double, double, 16>(g, st)
   if (big) {
     if (ta) return tb ? QMC_G(64, 64, true, true) : QMC_G(64, 64, true, false);
     return tb ? QMC_G(64, 64, false, true) : QMC_G(64, 64, false, false);
