@@ -447,11 +447,13 @@ def forces_leg(P, C, reps=5):
 
 def multi_leg(P, C, precision="fp32", replays=3):
     """Eight systems with 16..256 electrons, 256 walkers each (2048 walkers),
-    moved together by the persistent multi-system launches: autotuned, one
+    with FP32 rows, BF16 rows or in QMC_REFINED ("mixed": int8-refined
+    products, screened FP64 proposals), moved together by the persistent
+    multi-system launches: autotuned, one
     graph of 768 steps (the schedule period of all members) replayed.  Beside
     it the same members moved one system at a time with qmc_vmc_steps."""
     dev = torch.device("cuda:0")
-    prec = {"fp64": P.QMC_FP64, "fp32": P.QMC_W_FP32, "bf16": P.QMC_MIXED_BF16}[precision]
+    prec = {"fp64": P.QMC_FP64, "fp32": P.QMC_W_FP32, "bf16": P.QMC_MIXED_BF16, "mixed": P.QMC_REFINED}[precision]
     members = []
     for n in C.MULTI_SIZES:
         w = C.multi_system(n)
@@ -928,6 +930,7 @@ def main():
         res["forces"] = forces_leg(P, C)
         res["multi_system"] = multi_leg(P, C)
         res["multi_system_bf16"] = multi_leg(P, C, precision="bf16")
+        res["multi_system_refined"] = multi_leg(P, C, precision="mixed")
         res["large"] = large_leg(P, C)
         res["large_refined"] = large_leg(P, C, refined=True)
         res["large_refined_over_fp64_moves"] = round(res["large_refined"]["moves_per_s"] /

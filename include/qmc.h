@@ -90,8 +90,8 @@ typedef enum {
                       those skipped contribute at most 1e-13 in total (bound
                       from the largest |P| of each column and the inverse
                       column's 1-norm; an up move of a polarized system also
-                      streams the unpaired orbitals' values).  Not with
-                      qmc_multi_*.  One more [Wk][L][N + n_up - n_dn] FP64
+                      streams the unpaired orbitals' values).  One more
+                      [Wk][L][N + n_up - n_dn] FP64
                       array (P transposed).  For a Pfaffian (pairing = 1) the
                       evaluation's B rows phi(r_j)^T K^{s s_j} are the same
                       error-free int8 digit products; G~, Pf, its inverse and
@@ -459,8 +459,8 @@ qmc_status qmc_sr_step_static(int32_t n_samples, int64_t n_params, const double 
  * items ordered by decreasing cost; each member evolves exactly as it would
  * with qmc_vmc_steps alone given the same random numbers.  Members must have
  * the same precision and n_up <= 128 (unpaired orbitals, a Jastrow basis and
- * contracted orbitals are allowed); Pfaffian and QMC_REFINED members are
- * refused (QMC_ERR_UNSUPPORTED); at most 32 members.  The handles stay owned
+ * contracted orbitals are allowed, and QMC_REFINED members); Pfaffian members
+ * are refused (QMC_ERR_UNSUPPORTED); at most 32 members.  The handles stay owned
  * by the caller and must outlive the group. */
 typedef struct qmc_multi qmc_multi;
 qmc_status qmc_multi_create(int32_t n_members, qmc_system *const *systems, qmc_walkers *const *walkers,

@@ -312,8 +312,10 @@ struct MultiArgs {
   double sigma;                   // displacement width
 };
 hipError_t launch_multi_prep(const MultiArgs& a, const int2* items, int n_items, int grid, hipStream_t st);
+// screened_lds > 0: QMC_REFINED members (the screened streams, with that much
+// dynamic LDS)
 hipError_t launch_multi_rows(const MultiArgs& a, int store, int nc, const int4* items, int n_items, int grid,
-                             hipStream_t st);
+                             hipStream_t st, size_t screened_lds = 0);
 hipError_t launch_multi_accept(const MultiArgs& a, int store, const int2* items, int n_items, int grid,
                                hipStream_t st);
 hipError_t launch_multi_advance(long long* steps, int n, hipStream_t st);
@@ -565,6 +567,8 @@ hipError_t launch_P_build_oz(const SysDev& s, const WalkDev& w, int halves, cons
                              int dirty = 0);
 // screened proposals: column maxima of the P halves, and the streaming kernel
 hipError_t launch_screen_colmax(const SysDev& s, const WalkDev& w, int halves, hipStream_t st);
+// dynamic LDS of the blocked screened stream for a proposal of e (0: the plain one runs)
+size_t screened_stream_lds(const SysDev& s, const WalkDev& w, int e);
 // the unpaired orbitals' entries of every walker's transposed rows
 hipError_t launch_pt_unpaired(const SysDev& s, const WalkDev& w, hipStream_t st);
 hipError_t launch_export_kept(const WalkDev& w, double* dst, hipStream_t st);

@@ -178,61 +178,7 @@ hipError_t launch_propose_rows(const SysDev& s, const WalkDev& w, int e, double*
 // ---------------------------------------------------------------------------
 template <int NB>
 __global__ void __launch_bounds__(256) propose_screened_kernel(SysDev s, WalkDev w, int e, int S) {
-  __shared__ double part[4][64 * NB];
-  __shared__ double red[8];
-  const int wk = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const bool up = e < s.nu;
-  const int i0 = up ? s.nu : 0;
-  const int n = up ? s.nd + s.nk : s.nu;   // = n_up either way
-  const int ld = s.pt_ld();
-  const double* base = w.PT + (long)wk * s.Lp * ld + i0;
-  const int cnt = w.nkeep[wk];
-  const int* mk = w.muk + (long)wk * s.Lp;
-  const double* pk = w.psk + (long)wk * s.Lp;
-  double acc[NB];
-#pragma unroll
-  for (int b = 0; b < NB; ++b) acc[b] = 0.0;
-  int k = wave;
-  for (; k + 12 < cnt; k += 16) {   // four functions in flight per wave
-    int mu[4];
-    double v[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) { mu[q] = mk[k + 4 * q]; v[q] = pk[k + 4 * q]; }
-    double x[4][NB];
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        const int j = lane + 64 * b;
-        x[q][b] = j < n ? __builtin_nontemporal_load(base + (long)mu[q] * ld + j) : 0.0;
-      }
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-      for (int b = 0; b < NB; ++b) acc[b] += v[q] * x[q][b];
-  }
-  for (; k < cnt; k += 4) {
-    const int mu = mk[k];
-    const double v = pk[k];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const int j = lane + 64 * b;
-      if (j < n) acc[b] += v * base[(long)mu * ld + j];
-    }
-  }
-#pragma unroll
-  for (int b = 0; b < NB; ++b) part[wave][lane + 64 * b] = acc[b];
-  __syncthreads();
-  const double* cv = w.cvec + (long)wk * s.nu;
-  double* wn = w.w_new + (long)wk * s.nu;
-  double rp = 0.0;
-  for (int j = tid; j < n; j += blockDim.x) {
-    const double x = ((part[0][j] + part[1][j]) + part[2][j]) + part[3][j];
-    wn[j] = x;
-    rp += x * cv[j];
-  }
-  const double R = block_sum_mv(rp, red);
-  for (int q = tid; q < S; q += blockDim.x) w.rdet_part[(long)wk * S + q] = q == 0 ? R : 0.0;
+  screened_rows_walker<NB>(s, w, blockIdx.x, e, S);
 }
 
 template <int IPB>
@@ -342,10 +288,16 @@ hipError_t launch_screen_colmax(const SysDev& s, const WalkDev& w, int halves, h
   return hipGetLastError();
 }
 
+size_t screened_stream_lds(const SysDev& s, const WalkDev& w, int e) {
+  int IPB = 0, FB = 0;
+  size_t lds = 0;
+  return screened_blk_config(s, w, e, IPB, FB, lds) ? lds : 0;
+}
+
 hipError_t launch_propose_screened(const SysDev& s, const WalkDev& w, int e, double* ratio, bool finalize,
                                    hipStream_t st, hipEvent_t ev_start, hipEvent_t ev_stop) {
   if (!w.PT || !w.muk) return hipErrorInvalidValue;
-  const int n = e < s.nu ? s.nd : s.nu;
+  const int n = e < s.nu ? s.nd + s.nk : s.nu;   // rows streamed (= n_up)
   const int S = propose_splits(s);
   const dim3 grid(w.Wk), blk(256);
   int IPB, FB;

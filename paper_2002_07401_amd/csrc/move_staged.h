@@ -163,11 +163,76 @@ __device__ void screened_stream_walker(const SysDev& s, const WalkDev& w, int wk
   }
 }
 
+// The plain screened stream of one walker (any row count), one workgroup of
+// 256 threads: wave v takes kept functions v, v + 4, ..., four at a time, lane
+// l the rows l, l + 64, ...; the waves' partial rows are added in a fixed order
+// through LDS, then the ratio sum_j w'_j c_j, which goes to the first of the
+// walker's S partial slots (the others are zeroed).
+template <int NB>
+__device__ void screened_rows_walker(const SysDev& s, const WalkDev& w, int wk, int e, int S) {
+  __shared__ double part[4][64 * NB];
+  __shared__ double red[8];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const bool up = e < s.nu;
+  const int i0 = up ? s.nu : 0;
+  const int n = up ? s.nd + s.nk : s.nu;   // = n_up either way
+  const int ld = s.pt_ld();
+  const double* base = w.PT + (long)wk * s.Lp * ld + i0;
+  const int cnt = w.nkeep[wk];
+  const int* mk = w.muk + (long)wk * s.Lp;
+  const double* pk = w.psk + (long)wk * s.Lp;
+  double acc[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) acc[b] = 0.0;
+  int k = wave;
+  for (; k + 12 < cnt; k += 16) {   // four functions in flight per wave
+    int mu[4];
+    double v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) { mu[q] = mk[k + 4 * q]; v[q] = pk[k + 4 * q]; }
+    double x[4][NB];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int j = lane + 64 * b;
+        x[q][b] = j < n ? __builtin_nontemporal_load(base + (long)mu[q] * ld + j) : 0.0;
+      }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) acc[b] += v[q] * x[q][b];
+  }
+  for (; k < cnt; k += 4) {
+    const int mu = mk[k];
+    const double v = pk[k];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int j = lane + 64 * b;
+      if (j < n) acc[b] += v * base[(long)mu * ld + j];
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < NB; ++b) part[wave][lane + 64 * b] = acc[b];
+  __syncthreads();
+  const double* cv = w.cvec + (long)wk * s.nu;
+  double* wn = w.w_new + (long)wk * s.nu;
+  double rp = 0.0;
+  for (int j = tid; j < n; j += blockDim.x) {
+    const double x = ((part[0][j] + part[1][j]) + part[2][j]) + part[3][j];
+    wn[j] = x;
+    rp += x * cv[j];
+  }
+  const double R = block_sum_mv(rp, red);
+  for (int q = tid; q < S; q += blockDim.x) w.rdet_part[(long)wk * S + q] = q == 0 ? R : 0.0;
+}
+
 // The blocked screened stream for proposals of e: n even, FB = 128 /
 // gcd(n, 128) functions per block, IPB = FB n / 128 loads per lane and block,
 // at most 8; n <= 256 (one row per thread in the final sums), Lp <=
 // kFuseMaxLp (the kept list in LDS).  False: the plain screened kernel.
-inline bool screened_blk_config(const SysDev& s, const WalkDev& w, int e, int& IPB, int& FB, size_t& lds) {
+__host__ __device__ inline bool screened_blk_config(const SysDev& s, const WalkDev& w, int e, int& IPB, int& FB,
+                                                   size_t& lds) {
   const int n = e < s.nu ? s.nd + s.nk : s.nu;
   int g = 128;
   while (n % g) g >>= 1;

@@ -6,7 +6,7 @@
 // exactly as it would alone.  Random numbers come from Philox4x32-10 (counter =
 // the member's move count, the walker and the member; key = the seed), which
 // lets a captured graph of many steps be replayed without host involvement.
-#include "move_dev.h"
+#include "move_staged.h"
 
 namespace qmc {
 
@@ -127,6 +127,40 @@ __global__ void __launch_bounds__(256) multi_accept_kernel(MultiArgs a, const in
   }
 }
 
+// QMC_REFINED members: one item per walker, the screened stream the lone
+// proposal would run (blocked with its LDS where screened_blk_config allows,
+// else the plain one), writing the S partial slots the accept sums.
+__global__ void __launch_bounds__(256) multi_screened_rows_kernel(MultiArgs a, const int4* __restrict__ items,
+                                                                  int n_items) {
+  extern __shared__ __align__(16) char dyn[];
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    __syncthreads();
+    const int4 q = items[it];   // member, walker, 0, 1
+    const SysDev& s = a.sysv[q.x];
+    const WalkDev& wd = a.wkv[q.x];
+    const int e = (int)(a.steps[q.x] % s.N);
+    const int S = (s.nu + a.rows[q.x] - 1) / a.rows[q.x];
+    int IPB = 0, FB = 0;
+    size_t lds = 0;
+    if (screened_blk_config(s, wd, e, IPB, FB, lds)) {
+      switch (IPB) {
+        case 1: screened_stream_walker<1>(s, wd, q.y, e, S, FB, dyn); break;
+        case 2: screened_stream_walker<2>(s, wd, q.y, e, S, FB, dyn); break;
+        case 3: screened_stream_walker<3>(s, wd, q.y, e, S, FB, dyn); break;
+        case 4: screened_stream_walker<4>(s, wd, q.y, e, S, FB, dyn); break;
+        case 5: screened_stream_walker<5>(s, wd, q.y, e, S, FB, dyn); break;
+        case 6: screened_stream_walker<6>(s, wd, q.y, e, S, FB, dyn); break;
+        case 7: screened_stream_walker<7>(s, wd, q.y, e, S, FB, dyn); break;
+        default: screened_stream_walker<8>(s, wd, q.y, e, S, FB, dyn); break;
+      }
+    } else if (s.nu <= 64) {
+      screened_rows_walker<1>(s, wd, q.y, e, S);
+    } else {
+      screened_rows_walker<2>(s, wd, q.y, e, S);   // members have n_up <= 128
+    }
+  }
+}
+
 __global__ void multi_advance_kernel(long long* steps, int n) {
   const int k = threadIdx.x;
   if (k < n) steps[k] += 1;
@@ -144,7 +178,11 @@ hipError_t launch_multi_prep(const MultiArgs& a, const int2* items, int n_items,
 }
 
 hipError_t launch_multi_rows(const MultiArgs& a, int store, int nc, const int4* items, int n_items, int grid,
-                             hipStream_t st) {
+                             hipStream_t st, size_t screened_lds) {
+  if (screened_lds > 0) {
+    hipLaunchKernelGGL(multi_screened_rows_kernel, dim3(grid), dim3(256), screened_lds, st, a, items, n_items);
+    return hipGetLastError();
+  }
 #define QMC_MR(T, NC) case NC: return rows_launch<T, NC>(a, items, n_items, grid, st);
   if (store == 2) {
     switch (nc) { QMC_MR(bf16s, 1) QMC_MR(bf16s, 2) QMC_MR(bf16s, 3) QMC_MR(bf16s, 4)

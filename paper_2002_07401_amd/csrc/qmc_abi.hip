@@ -1464,6 +1464,7 @@ struct qmc_multi {
   int grid_rows = 2048, grid_items = 1024;
   int nc = 1;
   int store = 0;        // 0 FP64, 1 FP32, 2 BF16 rows
+  size_t scr_lds = 0;   // QMC_REFINED members: dynamic LDS of the screened streams (0: other modes)
   hipStream_t own = nullptr;
   hipEvent_t ev_a = nullptr, ev_b = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -1482,7 +1483,8 @@ static hipError_t multi_build_rows(qmc_multi* m) {
   std::vector<int4> items;
   for (int k : m->order) {
     const SysDev& s = m->h_sys[k];
-    const int S = (s.nu + m->rows[k] - 1) / m->rows[k];
+    // (QMC_REFINED: one screened stream per walker)
+    const int S = s.screened() ? 1 : (s.nu + m->rows[k] - 1) / m->rows[k];
     for (int w = 0; w < m->h_wk[k].Wk; ++w)
       for (int sb = 0; sb < S; ++sb) items.push_back(make_int4(k, w, sb, S));
   }
@@ -1515,7 +1517,6 @@ extern "C" qmc_status qmc_multi_create(int32_t n_members, qmc_system* const* sys
     // per-item bodies every member shares with the one-system kernels
     if (s.nu > kLuMaxN) { delete m; return fail(QMC_ERR_UNSUPPORTED, "members need n_up <= 128"); }
     if (s.pairing) { delete m; return fail(QMC_ERR_UNSUPPORTED, "Pfaffian members are not built"); }
-    if (s.screened()) { delete m; return fail(QMC_ERR_UNSUPPORTED, "QMC_REFINED members are not built"); }
     m->sys.push_back(systems[k]);
     m->wk.push_back(walkers[k]);
     m->h_sys.push_back(s);
@@ -1523,6 +1524,15 @@ extern "C" qmc_status qmc_multi_create(int32_t n_members, qmc_system* const* sys
     m->rows.push_back(s.prop_rows());
   }
   m->store = systems[0]->d.store();
+  if (systems[0]->d.screened()) {
+    // the largest LDS any member's blocked screened stream needs (both spins);
+    // at least the 1 KiB granule, so that the screened kernel is chosen
+    m->scr_lds = 1024;
+    for (int k = 0; k < n_members; ++k) {
+      const SysDev& s = m->h_sys[k];
+      for (int e : {0, s.N - 1}) m->scr_lds = std::max(m->scr_lds, screened_stream_lds(s, m->h_wk[k], e));
+    }
+  }
   m->order.resize(n_members);
   std::iota(m->order.begin(), m->order.end(), 0);
   std::stable_sort(m->order.begin(), m->order.end(), [&](int a, int b) {
@@ -1628,7 +1638,16 @@ static hipError_t multi_enqueue(qmc_multi* m, int n_steps, bool explicit_draws, 
       bool pre, post;
       plan_member(m->h_sys[k], st[k], pb, pre, post);
       if (pb) {
-        hipError_t r = launch_P_build(m->h_sys[k], m->h_wk[k], pb, m->own);
+        const SysDev& sk = m->h_sys[k];
+        const WalkDev& wkd = m->h_wk[k];
+        hipError_t r;
+        if (sk.screened()) {   // the refined rows with their transposes and column maxima
+          r = launch_P_build_oz(sk, wkd, pb, (const double*)wkd.phi, (double*)wkd.P, nullptr, false, m->own, false,
+                                wkd.PT, 0);
+          if (r == hipSuccess) r = launch_screen_colmax(sk, wkd, pb, m->own);
+        } else {
+          r = launch_P_build(sk, wkd, pb, m->own);
+        }
         if (r != hipSuccess) return r;
       }
       if (pre) pre_mask |= 1u << k;
@@ -1637,7 +1656,8 @@ static hipError_t multi_enqueue(qmc_multi* m, int n_steps, bool explicit_draws, 
     // refreshes: the one-system LU per member, so results match a lone run bitwise
     hipError_t r = multi_refresh(m, pre_mask);
     if (r == hipSuccess) r = launch_multi_prep(a, m->d_items, m->n_items, m->grid_items, m->own);
-    if (r == hipSuccess) r = launch_multi_rows(a, m->store, m->nc, m->d_rows_items, m->n_rows_items, m->grid_rows, m->own);
+    if (r == hipSuccess)
+      r = launch_multi_rows(a, m->store, m->nc, m->d_rows_items, m->n_rows_items, m->grid_rows, m->own, m->scr_lds);
     if (r == hipSuccess) r = launch_multi_accept(a, m->store, m->d_items, m->n_items, m->grid_items, m->own);
     if (r == hipSuccess) r = multi_refresh(m, post_mask);
     if (r == hipSuccess) r = launch_multi_advance(m->d_steps, m->n, m->own);
@@ -1751,10 +1771,10 @@ extern "C" qmc_status qmc_multi_autotune(qmc_multi* m, int32_t* rows_out, int32_
     if (err != hipSuccess) break;
     for (int g : cand_grid) {
       const int grid = std::min(g, m->n_rows_items);
-      err = launch_multi_rows(a, m->store, m->nc, m->d_rows_items, m->n_rows_items, grid, m->own);
+      err = launch_multi_rows(a, m->store, m->nc, m->d_rows_items, m->n_rows_items, grid, m->own, m->scr_lds);
       if (err == hipSuccess) err = hipEventRecord(e0, m->own);
       for (int rep = 0; rep < 5 && err == hipSuccess; ++rep)
-        err = launch_multi_rows(a, m->store, m->nc, m->d_rows_items, m->n_rows_items, grid, m->own);
+        err = launch_multi_rows(a, m->store, m->nc, m->d_rows_items, m->n_rows_items, grid, m->own, m->scr_lds);
       if (err == hipSuccess) err = hipEventRecord(e1, m->own);
       if (err == hipSuccess) err = hipEventSynchronize(e1);
       float ms = 0.f;

@@ -10,8 +10,8 @@ proposals.
   some.
 * Chains: Metropolis chains (device accept) equal the oracle's chain on the
   same draws: positions bitwise, the tracked log|Psi| within 1e-8.
-* Refusals: the multi-system launches (polarized systems and the Pfaffian are
-  built: their own test files).
+* Refusals: a Pfaffian member of a multi-system group (polarized systems, the
+  Pfaffian and multi-system groups are built: their own test files).
 """
 import dataclasses
 
@@ -110,11 +110,12 @@ def test_refined_chain_matches_oracle(name):
 
 
 def test_refined_refusals():
+    # a QMC_REFINED Pfaffian is built, but not as a member of a multi-system group
     P = need_gpu()
-    w = C.multi_system(16, n_walkers=4)
+    w = C.pfaffian_4nuc_20e(n_walkers=4)
     sysh = P.JAGPSystem(w.system, precision=P.QMC_REFINED)
     wk = P.Walkers(sysh, 4, adjoint=False)
-    wk.eval_batch(torch.tensor(w.r0, device="cuda"))
+    wk.eval_batch(torch.tensor(w.r0[:4], device="cuda"))
     with pytest.raises(P.QMCError) as ei:
         P.MultiSystem([wk])
     assert ei.value.code == -5
