@@ -84,7 +84,7 @@ def test_eval_forces_workload_pade_series():
     _compare(out, ref, idx, "forces80")
 
 
-@pytest.mark.parametrize("n_elec", [16, 48, 96, 256])
+@pytest.mark.parametrize("n_elec", [16, 48, 96, 160, 192, 256])   # n_up 80 and 96: the walker-level cofactor kernel
 def test_eval_multi_system_members(n_elec):
     P = need_gpu()
     w = C.multi_system(n_elec, n_walkers=32)
