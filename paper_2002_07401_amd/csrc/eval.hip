@@ -193,66 +193,88 @@ __device__ double block_sum(double v, double* red) {
 //   e_kin   = -1/2 sum_i [ lap_i det/det + 2 grad_i det/det . grad_i J
 //                          + lap_i J + |grad_i J|^2 ]
 //   e_loc   = e_kin + V     (local energy, VMC section)
-// One workgroup per walker, threads over electrons.
+// One workgroup of kAssembleThreads per walker.  The electrons go in chunks
+// of at most the block size; a chunk of nc electrons is spread over G =
+// blockDim / nc groups of threads, group g taking the nuclei and partners a,
+// j = g, g + G, ... of every electron (so that short chunks keep most threads
+// busy), and each electron's gradient and Laplacian of J add the groups'
+// partial sums in order of g.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256)
+constexpr int kAssembleThreads = 512;
+__global__ void __launch_bounds__(kAssembleThreads)
 jastrow_assemble_kernel(SysDev s, WalkDev w, double* __restrict__ logabs_o, double* __restrict__ sign_o,
                         double* __restrict__ drift_o, double* __restrict__ ekin_o,
                         double* __restrict__ eloc_o, int32_t* __restrict__ status_o) {
-  __shared__ double red[16];
-  const int wk = blockIdx.x;
+  __shared__ double red[3 * (kAssembleThreads / 64)];
+  __shared__ double part[kAssembleThreads][4];
+  const int wk = blockIdx.x, tid = threadIdx.x, T = blockDim.x;
   const double* r = w.r + (long)wk * s.N * 3;
   double Jp = 0.0, Vp = 0.0, Kp = 0.0;
   bool bad = false;
-  for (int i = threadIdx.x; i < s.N; i += blockDim.x) {
-    const double xi = r[3 * i], yi = r[3 * i + 1], zi = r[3 * i + 2];
-    double gx = 0.0, gy = 0.0, gz = 0.0, h = 0.0;
-    for (int a = 0; a < s.n_nuc; ++a) {
-      const double dx = xi - s.R[3 * a], dy = yi - s.R[3 * a + 1], dz = zi - s.R[3 * a + 2];
-      const double ria = sqrt(dx * dx + dy * dy + dz * dz);
-      Vp -= s.Z[a] / ria;
-      if (s.j1_form) {
-        double f, f1, f2;
-        j1_radial(s.j1_form, s.Z[a], s.j1_b[a], ria, f, f1, f2);
-        const double q = f1 / ria;
-        Jp += f;
-        gx += q * dx; gy += q * dy; gz += q * dz;
-        h += f2 + 2.0 * q;
+  for (int c0 = 0; c0 < s.N; c0 += T) {
+    const int nc = min(s.N - c0, T);
+    const int G = max(1, T / nc);
+    const int g = tid / nc, i = c0 + tid % nc;
+    if (g < G) {
+      const double xi = r[3 * i], yi = r[3 * i + 1], zi = r[3 * i + 2];
+      double gx = 0.0, gy = 0.0, gz = 0.0, h = 0.0;
+      for (int a = g; a < s.n_nuc; a += G) {
+        const double dx = xi - s.R[3 * a], dy = yi - s.R[3 * a + 1], dz = zi - s.R[3 * a + 2];
+        const double ria = sqrt(dx * dx + dy * dy + dz * dz);
+        Vp -= s.Z[a] / ria;
+        if (s.j1_form) {
+          double f, f1, f2;
+          j1_radial(s.j1_form, s.Z[a], s.j1_b[a], ria, f, f1, f2);
+          const double q = f1 / ria;
+          Jp += f;
+          gx += q * dx; gy += q * dy; gz += q * dz;
+          h += f2 + 2.0 * q;
+        }
+      }
+      const bool up_i = i < s.nu;
+      for (int j = g; j < s.N; j += G) {
+        if (j == i) continue;
+        const double dx = xi - r[3 * j], dy = yi - r[3 * j + 1], dz = zi - r[3 * j + 2];
+        const double rij = sqrt(dx * dx + dy * dy + dz * dz);
+        Vp += 0.5 / rij;
+        if (s.j2_form) {
+          double v, v1, v2;
+          j2_radial(s.j2_form, s.j2d, up_i == (j < s.nu), rij, v, v1, v2);
+          const double q = v1 / rij;
+          Jp += 0.5 * v;
+          gx += q * dx; gy += q * dy; gz += q * dz;
+          h += v2 + 2.0 * q;
+        }
+      }
+      part[tid][0] = gx; part[tid][1] = gy; part[tid][2] = gz; part[tid][3] = h;
+    }
+    __syncthreads();
+    if (tid < nc) {   // electron i = c0 + tid
+      double gx = 0.0, gy = 0.0, gz = 0.0, h = 0.0;
+      for (int q = 0; q < G; ++q) {
+        const double* pq = part[q * nc + tid];
+        gx += pq[0]; gy += pq[1]; gz += pq[2]; h += pq[3];
+      }
+      if (s.LJ) {   // Jastrow-basis terms (one-body inhomogeneous, three/four-body)
+        const double* e3 = w.j3e + ((long)wk * s.N + i) * 5;
+        Jp += e3[0];
+        gx += e3[1]; gy += e3[2]; gz += e3[3];
+        h += e3[4];
+      }
+      const double* Di = w.D + ((long)wk * s.N + i) * 4;
+      const double ddx = Di[0], ddy = Di[1], ddz = Di[2], dl = Di[3];
+      Kp += dl + 2.0 * (ddx * gx + ddy * gy + ddz * gz) + h + gx * gx + gy * gy + gz * gz;
+      double* gj = w.gJ + ((long)wk * s.N + i) * 4;
+      gj[0] = gx; gj[1] = gy; gj[2] = gz; gj[3] = h;
+      double* dd = w.drift + ((long)wk * s.N + i) * 3;
+      dd[0] = ddx + gx; dd[1] = ddy + gy; dd[2] = ddz + gz;
+      if (drift_o) {
+        double* o = drift_o + ((long)wk * s.N + i) * 3;
+        o[0] = ddx + gx; o[1] = ddy + gy; o[2] = ddz + gz;
+        bad |= !isfinite(o[0]) || !isfinite(o[1]) || !isfinite(o[2]);
       }
     }
-    const bool up_i = i < s.nu;
-    for (int j = 0; j < s.N; ++j) {
-      if (j == i) continue;
-      const double dx = xi - r[3 * j], dy = yi - r[3 * j + 1], dz = zi - r[3 * j + 2];
-      const double rij = sqrt(dx * dx + dy * dy + dz * dz);
-      Vp += 0.5 / rij;
-      if (s.j2_form) {
-        double v, v1, v2;
-        j2_radial(s.j2_form, s.j2d, up_i == (j < s.nu), rij, v, v1, v2);
-        const double q = v1 / rij;
-        Jp += 0.5 * v;
-        gx += q * dx; gy += q * dy; gz += q * dz;
-        h += v2 + 2.0 * q;
-      }
-    }
-    if (s.LJ) {   // Jastrow-basis terms (one-body inhomogeneous, three/four-body)
-      const double* e3 = w.j3e + ((long)wk * s.N + i) * 5;
-      Jp += e3[0];
-      gx += e3[1]; gy += e3[2]; gz += e3[3];
-      h += e3[4];
-    }
-    const double* Di = w.D + ((long)wk * s.N + i) * 4;
-    const double ddx = Di[0], ddy = Di[1], ddz = Di[2], dl = Di[3];
-    Kp += dl + 2.0 * (ddx * gx + ddy * gy + ddz * gz) + h + gx * gx + gy * gy + gz * gz;
-    double* gj = w.gJ + ((long)wk * s.N + i) * 4;
-    gj[0] = gx; gj[1] = gy; gj[2] = gz; gj[3] = h;
-    double* dd = w.drift + ((long)wk * s.N + i) * 3;
-    dd[0] = ddx + gx; dd[1] = ddy + gy; dd[2] = ddz + gz;
-    if (drift_o) {
-      double* o = drift_o + ((long)wk * s.N + i) * 3;
-      o[0] = ddx + gx; o[1] = ddy + gy; o[2] = ddz + gz;
-      bad |= !isfinite(o[0]) || !isfinite(o[1]) || !isfinite(o[2]);
-    }
+    __syncthreads();   // the chunk's partial sums are read before the next chunk writes them
   }
   // nucleus-nucleus repulsion
   for (int p = threadIdx.x; p < s.n_nuc * s.n_nuc; p += blockDim.x) {
@@ -262,9 +284,10 @@ jastrow_assemble_kernel(SysDev s, WalkDev w, double* __restrict__ logabs_o, doub
                  dz = s.R[3 * a + 2] - s.R[3 * b + 2];
     Vp += s.Z[a] * s.Z[b] / sqrt(dx * dx + dy * dy + dz * dz);
   }
+  constexpr int NW = kAssembleThreads / 64;
   const double J = block_sum(Jp, red);
-  const double V = block_sum(Vp, red + 4);
-  const double K = block_sum(Kp, red + 8);
+  const double V = block_sum(Vp, red + NW);
+  const double K = block_sum(Kp, red + 2 * NW);
   __shared__ int bad_s;
   if (threadIdx.x == 0) bad_s = 0;
   __syncthreads();
@@ -294,7 +317,7 @@ jastrow_assemble_kernel(SysDev s, WalkDev w, double* __restrict__ logabs_o, doub
 hipError_t launch_jastrow_assemble(const SysDev& s, const WalkDev& w, double* logabs, double* sign,
                                    double* drift, double* e_kin, double* e_loc, int32_t* status,
                                    hipStream_t st) {
-  hipLaunchKernelGGL(jastrow_assemble_kernel, dim3(w.Wk), dim3(256), 0, st, s, w, logabs, sign, drift,
+  hipLaunchKernelGGL(jastrow_assemble_kernel, dim3(w.Wk), dim3(kAssembleThreads), 0, st, s, w, logabs, sign, drift,
                      e_kin, e_loc, status);
   return hipGetLastError();
 }
