@@ -423,7 +423,7 @@ hipError_t launch_gj_inverse_n(int Wk, int n, const double* W, double* A, double
 // Gauss-Jordan leaves exactly those columns of E in the panel.  The update
 // kernel then applies E to every other column:
 //   T[:, O] <- D T[:, O] + T'[:, C] T_old[P, O]      (D zeroes the rows P),
-// a product with K = NB.  The finish kernel writes W^{-1}[k][p_k'] = T[p_k][k']
+// a product with K = NB on the FP64 matrix cores.  The finish kernel writes W^{-1}[k][p_k'] = T[p_k][k']
 // and log|det W| = sum log|pivot_k|, sign = sgn(p) prod sign(pivot_k).
 // ---------------------------------------------------------------------------
 __global__ void gj_big_init_kernel(const double* __restrict__ W, double* __restrict__ T, int* __restrict__ rowk,
@@ -507,71 +507,37 @@ gj_panel_kernel(double* __restrict__ T, double* __restrict__ Tsave, int* __restr
     *reinterpret_cast<double2*>(Tw + (long)i * np + c0 + j) = make_double2(a[j], a[j + 1]);
   rkw[i] = my_k;
   __syncthreads();
-  // the panel's pivot rows outside the panel, before the update kernel changes them
+  // the panel's pivot rows outside the panel move to Tsave (the update's right
+  // operand) and are cleared in T (the D of the update)
   double* Sw = Tsave + wk * NB * np;
   for (int kk = 0; kk < NB; ++kk) {
-    const double* src = Tw + (long)pr_s[kk] * np;
-    for (int o = i; o < np; o += blockDim.x)
-      Sw[(long)kk * np + o] = (o >= c0 && o < c0 + NB) ? 0.0 : src[o];
+    double* src = Tw + (long)pr_s[kk] * np;
+    for (int o = i; o < np; o += blockDim.x) {
+      const bool in_panel = o >= c0 && o < c0 + NB;
+      Sw[(long)kk * np + o] = in_panel ? 0.0 : src[o];
+      if (!in_panel) src[o] = 0.0;
+    }
   }
 }
 
-// T[r][o] <- (rowk[r] in panel ? 0 : T[r][o]) + sum_kk T[r][c0+kk] Tsave[kk][o]
-// for o outside the panel; 64 x 64 tiles, 4 x 4 outputs per thread.
-template <int NB>
-__global__ void __launch_bounds__(256)
-gj_update_kernel(double* __restrict__ T, const double* __restrict__ Tsave, const int* __restrict__ rowk,
-                 const int* __restrict__ singular, int np, int c0) {
-  __shared__ double Fp[64][NB + 1];
-  __shared__ double Sv[NB][64 + 1];
-  __shared__ int zr[64];
-  const long wk = blockIdx.z;
-  const int o0 = blockIdx.x * 64, r0 = blockIdx.y * 64;
-  if (singular[wk]) return;
-  if (o0 >= c0 && o0 + 64 <= c0 + NB) return;   // tile inside the panel
-  double* Tw = T + wk * np * np;
-  const double* Sw = Tsave + wk * NB * np;
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  for (int idx = tid; idx < 64 * NB; idx += 256) {
-    const int r = idx / NB, kk = idx % NB;
-    Fp[r][kk] = Tw[(long)(r0 + r) * np + c0 + kk];
+// T[:, O] += T[:, panel] Tsave[:, O] for the column ranges O left and right of
+// the panel: batched FP64 MFMA products (the panel kernel has cleared the
+// pivot rows of T[:, O]).  Walkers found singular are updated with whatever
+// Tsave holds; their outputs are overwritten by the finish kernels.
+static hipError_t gj_update_mfma(const WalkDev& w, int np, int c0, int NB, hipStream_t st) {
+  for (int side = 0; side < 2; ++side) {
+    const int o0 = side ? c0 + NB : 0, no = side ? np - c0 - NB : c0;
+    if (no <= 0) continue;
+    GemmArgs g = gemm_args(np, no, NB);
+    g.A = w.T + c0; g.lda = np; g.a_bs = (long)np * np;
+    g.B = w.Tsave + o0; g.ldb = np; g.b_bs = (long)NB * np;
+    g.C = w.T + o0; g.ldc = np; g.c_bs = (long)np * np;
+    g.batch = w.Wk;
+    g.accumulate = 1;
+    const hipError_t e = gemm_f64(g, false, false, true, st);
+    if (e != hipSuccess) return e;
   }
-  for (int idx = tid; idx < NB * 64; idx += 256) {
-    const int kk = idx / 64, o = idx % 64;
-    Sv[kk][o] = Sw[(long)kk * np + o0 + o];
-  }
-  if (tid < 64) {
-    const int k = rowk[wk * np + r0 + tid];
-    zr[tid] = (k >= c0 && k < c0 + NB) ? 1 : 0;
-  }
-  __syncthreads();
-  double acc[4][4];
-#pragma unroll
-  for (int ri = 0; ri < 4; ++ri)
-#pragma unroll
-    for (int cj = 0; cj < 4; ++cj) {
-      const int r = ty + 16 * ri, o = tx + 16 * cj;
-      acc[ri][cj] = zr[r] ? 0.0 : Tw[(long)(r0 + r) * np + o0 + o];
-    }
-#pragma unroll 8
-  for (int kk = 0; kk < NB; ++kk) {
-    double fr[4], sc[4];
-#pragma unroll
-    for (int ri = 0; ri < 4; ++ri) fr[ri] = Fp[ty + 16 * ri][kk];
-#pragma unroll
-    for (int cj = 0; cj < 4; ++cj) sc[cj] = Sv[kk][tx + 16 * cj];
-#pragma unroll
-    for (int ri = 0; ri < 4; ++ri)
-#pragma unroll
-      for (int cj = 0; cj < 4; ++cj) acc[ri][cj] = fma(fr[ri], sc[cj], acc[ri][cj]);
-  }
-#pragma unroll
-  for (int ri = 0; ri < 4; ++ri)
-#pragma unroll
-    for (int cj = 0; cj < 4; ++cj) {
-      const int r = ty + 16 * ri, o = o0 + tx + 16 * cj;
-      if (o < c0 || o >= c0 + NB) Tw[(long)(r0 + r) * np + o] = acc[ri][cj];
-    }
+  return hipSuccess;
 }
 
 // A[k][m] = T[prow[k]][rowk[m]] for k, m < n (4 rows of A per block).
@@ -638,19 +604,16 @@ static hipError_t launch_lu_inverse_big(const SysDev& s, const WalkDev& w, hipSt
   const long nn = (long)np * np;
   hipLaunchKernelGGL(gj_big_init_kernel, dim3((unsigned)((nn + 255) / 256), w.Wk), dim3(256), 0, st, w.W, w.T,
                      w.rowk, w.singular, n, np);
-  const dim3 ug(np / 64, np / 64, w.Wk);
-  if (np <= 512) {
-    for (int c0 = 0; c0 < np; c0 += 64) {
+  const int NB = np <= 512 ? 64 : 32;
+  for (int c0 = 0; c0 < np; c0 += NB) {
+    if (NB == 64)
       hipLaunchKernelGGL(gj_panel_kernel<64>, dim3(w.Wk), dim3(np), 0, st, w.T, w.Tsave, w.rowk, w.prow, w.pivv,
                          w.singular, n, np, c0);
-      hipLaunchKernelGGL(gj_update_kernel<64>, ug, dim3(256), 0, st, w.T, w.Tsave, w.rowk, w.singular, np, c0);
-    }
-  } else {
-    for (int c0 = 0; c0 < np; c0 += 32) {
+    else
       hipLaunchKernelGGL(gj_panel_kernel<32>, dim3(w.Wk), dim3(np), 0, st, w.T, w.Tsave, w.rowk, w.prow, w.pivv,
                          w.singular, n, np, c0);
-      hipLaunchKernelGGL(gj_update_kernel<32>, ug, dim3(256), 0, st, w.T, w.Tsave, w.rowk, w.singular, np, c0);
-    }
+    const hipError_t e = gj_update_mfma(w, np, c0, NB, st);
+    if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(gj_big_output_kernel, dim3((n + 3) / 4, w.Wk), dim3(256), 0, st, w.T, w.rowk, w.prow,
                      w.singular, w.A, n, np);

@@ -76,6 +76,25 @@ def test_blocked_eval_and_refresh(n_elec):
     assert ((A - A2).abs().max() / A2.abs().max()).item() <= 1e-8
 
 
+def test_blocked_inverse_narrow_panels():
+    # n = 550 (np = 576 > 512): 32-column panels, each followed by the two
+    # batched MFMA products left and right of the panel
+    P = need_gpu()
+    w = C.multi_system(1100, n_walkers=2)
+    sysh = P.JAGPSystem(w.system)
+    wk = P.Walkers(sysh, 2)
+    out = wk.eval_batch(torch.tensor(w.r0[:2], device="cuda"))
+    torch.cuda.synchronize()
+    assert int(out["status"].abs().max()) == 0
+    W, A = wk.read(P.STATE_W).cpu(), wk.read(P.STATE_AINV).cpu()
+    Ainv = torch.linalg.inv(W)
+    err = ((A - Ainv).abs().max() / Ainv.abs().max()).item()
+    print(f"[blocked inverse n=550] W^-1 against LAPACK {err:.3e}")
+    assert err <= 1e-8
+    sg, _ = torch.linalg.slogdet(W)
+    assert torch.equal(out["sign"].cpu(), sg)
+
+
 def test_large_ratios_and_update(large):
     P = need_gpu()
     w = large
